@@ -1,0 +1,165 @@
+"""Lattice models standing in for the paper's mean-field inputs.
+
+The method consumes band energies, Bloch states, a position (dipole) matrix
+and a velocity operator (Eq. tdagw and Appendix A.1 of the paper); the paper
+takes them from DFT + GW.  Here they come from two small tight-binding models:
+
+* a two-band massive Dirac lattice model  H(k) = D sz + t (sin kx a sx + sin ky a sy);
+* a seeded random Hermitian four-band nearest-neighbour model
+  H(k) = H0 + sum_a (T_a exp(i k_a a) + h.c.),  H0 = diag(D, D, -D, -D).
+
+Hartree atomic units throughout (energies in Ha, lengths in bohr).
+Layouts (all C-contiguous):
+  kpts  [nk][2]        float64, k index = i1 * nk2 + i2
+  eps   [nk][nb]       float64, ascending
+  evec  [nk][nb][nb]   complex128, evec[k][alpha, n] = <alpha | n k>
+  vel   [2][nk][nb][nb] complex128, v^a_nm = <n k| dH/dk_a |m k>
+  dip   [2][nk][nb][nb] complex128, interband Berry connection
+"""
+
+from __future__ import annotations
+
+import json
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HARTREE_EV = 27.211386245988          # eV per hartree
+FS_AU = 41.341373335                  # atomic time units per femtosecond
+BOHR_NM = 0.0529177210903             # nm per bohr
+EFIELD_AU_V_PER_CM = 5.14220674763e9  # V/cm per atomic unit of field
+
+_DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+@dataclass
+class Model:
+    name: str
+    nk1: int
+    nk2: int
+    shift: float
+    a: float
+    nb: int
+    nv: int
+    kpts: np.ndarray
+    eps: np.ndarray
+    evec: np.ndarray
+    vel: np.ndarray
+    dip: np.ndarray
+    hk: np.ndarray
+
+    @property
+    def nk(self) -> int:
+        return self.nk1 * self.nk2
+
+    @property
+    def nc(self) -> int:
+        return self.nb - self.nv
+
+
+def mp_grid(nk1: int, nk2: int, a: float, shift: float = 0.5) -> np.ndarray:
+    """Uniform grid k_i = (2 pi / a) ((i + shift) / N - 1/2), i = 0..N-1.
+
+    shift = 0.5 is the Monkhorst-Pack grid for even N (Gamma excluded);
+    shift = 0 is Gamma-centred for even N.
+    """
+    g1 = (2.0 * np.pi / a) * ((np.arange(nk1) + shift) / nk1 - 0.5)
+    g2 = (2.0 * np.pi / a) * ((np.arange(nk2) + shift) / nk2 - 0.5)
+    kx, ky = np.meshgrid(g1, g2, indexing="ij")
+    return np.stack([kx.ravel(), ky.ravel()], axis=1)
+
+
+_SX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+_SY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+_SZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+
+def _canonical_phase(evec: np.ndarray) -> np.ndarray:
+    """Fix each eigenvector's phase: its largest-magnitude component is made
+    real and positive (the lowest orbital index among components within 1e-9
+    of the maximum)."""
+    mag = np.abs(evec)                                 # [nk][alpha][n]
+    mx = mag.max(axis=1, keepdims=True)
+    first = np.argmax(mag >= mx * (1.0 - 1e-9), axis=1)  # [nk][n]
+    comp = np.take_along_axis(evec, first[:, None, :], axis=1)[:, 0, :]
+    phase = comp / np.abs(comp)
+    return evec / phase[:, None, :]
+
+
+def _bands(hk: np.ndarray, dh: np.ndarray, nv: int):
+    """Diagonalise H(k) and express dH/dk and the Berry connection in the band basis."""
+    eps, evec = np.linalg.eigh(hk)
+    evec = _canonical_phase(evec)
+    vel = np.einsum("kan,xkab,kbm->xknm", evec.conj(), dh, evec)
+    nb = hk.shape[-1]
+    de = eps[:, None, :] - eps[:, :, None]             # de[k, n, m] = e_m - e_n
+    inter = np.zeros((nb, nb), dtype=bool)
+    inter[:nv, nv:] = True
+    inter[nv:, :nv] = True
+    dip = np.zeros_like(vel)
+    safe = np.where(inter[None], de, 1.0)
+    dip[:, :, inter] = (1j * vel / safe[None])[:, :, inter]
+    return eps, evec, vel, dip
+
+
+def dirac_model(nk: int = 12, delta_ev: float = 1.0, t_ev: float = 1.5,
+                a: float = 6.0, shift: float = 0.5) -> Model:
+    """Two-band massive Dirac lattice model, one valence and one conduction band."""
+    kpts = mp_grid(nk, nk, a, shift)
+    d = delta_ev / HARTREE_EV
+    t = t_ev / HARTREE_EV
+    sx = np.sin(kpts[:, 0] * a)[:, None, None]
+    sy = np.sin(kpts[:, 1] * a)[:, None, None]
+    cx = np.cos(kpts[:, 0] * a)[:, None, None]
+    cy = np.cos(kpts[:, 1] * a)[:, None, None]
+    hk = d * _SZ[None] + t * (sx * _SX[None] + sy * _SY[None])
+    dh = np.stack([t * a * cx * _SX[None], t * a * cy * _SY[None]])
+    eps, evec, vel, dip = _bands(hk, dh, 1)
+    return Model("dirac", nk, nk, shift, a, 2, 1, kpts, eps, evec, vel, dip, hk)
+
+
+def draw_tb4_hoppings(seed: int):
+    """Seeded draw of the two 4x4 hopping matrices (eV): magnitudes U[0.2, 1.0],
+    phases U[0, 2 pi); draw order |Tx|, arg Tx, |Ty|, arg Ty (PCG64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(2):
+        mag = rng.uniform(0.2, 1.0, size=(4, 4))
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=(4, 4))
+        out.append(mag * np.exp(1j * ph))
+    return out[0], out[1]
+
+
+def tb4_hamiltonian(kpts: np.ndarray, a: float, tx: np.ndarray, ty: np.ndarray,
+                    delta: float):
+    """H(k) and dH/dk for the four-band model; tx, ty, delta in hartree."""
+    h0 = np.diag([delta, delta, -delta, -delta]).astype(np.complex128)
+    ex = np.exp(1j * kpts[:, 0] * a)[:, None, None]
+    ey = np.exp(1j * kpts[:, 1] * a)[:, None, None]
+    txh = tx.conj().T
+    tyh = ty.conj().T
+    hk = h0[None] + tx[None] * ex + txh[None] * ex.conj() + ty[None] * ey + tyh[None] * ey.conj()
+    dhx = 1j * a * (tx[None] * ex - txh[None] * ex.conj())
+    dhy = 1j * a * (ty[None] * ey - tyh[None] * ey.conj())
+    return hk, np.stack([dhx, dhy])
+
+
+def load_tb4_table(path: str | None = None) -> dict:
+    """The stored four-band model (seed, hoppings, on-site splitting)."""
+    path = path or os.path.join(_DATA, "tb4_model.json")
+    with open(path) as f:
+        tab = json.load(f)
+    tab["tx"] = np.array(tab["tx_re"]) + 1j * np.array(tab["tx_im"])
+    tab["ty"] = np.array(tab["ty_re"]) + 1j * np.array(tab["ty_im"])
+    return tab
+
+
+def tb4_model(nk: int, a: float = 6.0, shift: float = 0.5, table: dict | None = None) -> Model:
+    """Seeded random 4-band model (2 valence + 2 conduction bands) on an nk x nk grid."""
+    tab = table or load_tb4_table()
+    kpts = mp_grid(nk, nk, a, shift)
+    hk, dh = tb4_hamiltonian(kpts, a, tab["tx"] / HARTREE_EV, tab["ty"] / HARTREE_EV,
+                             tab["delta_ev"] / HARTREE_EV)
+    eps, evec, vel, dip = _bands(hk, dh, 2)
+    return Model("tb4", nk, nk, shift, a, 4, 2, kpts, eps, evec, vel, dip, hk)
