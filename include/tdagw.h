@@ -1,0 +1,229 @@
+/*
+ * tdagw.h -- C ABI of the MI355X (gfx950) TD-aGW propagation library.
+ *
+ * The library integrates the time-dependent adiabatic GW equation of motion
+ * for the one-particle density matrix in the Bloch basis (paper Eq. tdagw):
+ *
+ *     i d rho_k/dt = [ H^QP_k + dSigma_k(t) - E(t) e.d_k , rho_k ],
+ *     dSigma_{nm k} = sum_{n'm'k'} K_{(nmk),(n'm'k')} drho_{n'm'k'}   (Eq. sigma-from-k)
+ *
+ * with drho = rho - rho_eq, either with the dense kernel K or with the
+ * compressed kernel K ~ K_diag + S V^H, S = U M (Eq. svd_diag_offdiag and
+ * Eq. svd_acc), applied as K_diag o x + S (V^H x).
+ *
+ * Conventions shared by every call
+ *   - Complex numbers are interleaved (re, im): c128 = 2 x double, c64 = 2 x float.
+ *   - Matrices are row-major; "ld" is the row stride in elements.
+ *   - Pair index: block ALL uses p = n*nb + m for every band pair (n, m);
+ *     block EH uses p = (c - nv)*nv + v for conduction c >= nv and valence
+ *     v < nv (the conduction-valence block).  Kernel index i = k*P + p,
+ *     k = i1*nk2 + i2.  P = nb*nb (ALL) or (nb-nv)*nv (EH).
+ *   - Every array argument is DEVICE memory owned by the caller, unless its
+ *     comment says "host".  The library never frees caller memory; it owns
+ *     only the workspace inside a context.
+ *   - Calls enqueue work on the context's stream and return; results are
+ *     valid after that stream is synchronised.  tdg_kernel_compress and
+ *     tdg_check_numeric synchronise the stream themselves.
+ *   - Every call returns TDG_OK (0) or a negative TDG_E_* code and never
+ *     aborts or throws; tdg_last_error() describes the last failure.
+ *     Arguments are validated on the host before any device work is queued.
+ */
+#ifndef TDAGW_H
+#define TDAGW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDG_OK 0
+#define TDG_E_INVAL (-1)       /* bad argument: null pointer, shape, dtype, alignment */
+#define TDG_E_HIP (-2)         /* a HIP runtime call or kernel launch failed */
+#define TDG_E_NOMEM (-3)       /* workspace allocation failed */
+#define TDG_E_UNSUPPORTED (-4) /* valid request this build does not implement */
+#define TDG_E_NUMERIC (-5)     /* NaN / trace / Hermiticity drift found by tdg_check_numeric */
+#define TDG_E_SOLVER (-6)      /* the eigensolver used by compression reported failure */
+
+#define TDG_C128 0 /* complex double storage, FP64 arithmetic */
+#define TDG_C64 1  /* complex float storage, FP32 arithmetic with FP32 accumulation */
+
+#define TDG_BLOCK_ALL 0 /* every band pair (n, m) */
+#define TDG_BLOCK_EH 1  /* conduction-valence block; dSigma_vc = conj(dSigma_cv) */
+
+#define TDG_NB_MAX 8 /* largest number of bands per k point */
+
+typedef struct tdg_ctx_s* tdg_ctx;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int tdg_version(void);
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the device's default stream).  *out receives the
+ * handle.  The context owns all library workspace on that device. */
+int tdg_create(tdg_ctx* out, int device, void* hip_stream);
+/* Release the context and its workspace (waits for its stream first). */
+int tdg_destroy(tdg_ctx ctx);
+/* Rebind the context to another stream of the same device. */
+int tdg_set_stream(tdg_ctx ctx, void* hip_stream);
+/* Message describing the last failed call on ctx ("" if none); owned by ctx,
+ * valid until the next call on ctx.  ctx may be NULL for tdg_create failures. */
+const char* tdg_last_error(tdg_ctx ctx);
+
+/* Band-structure input: quasiparticle energies, Bloch states, position and
+ * velocity operators (paper Appendix A.1: H^QP and the dipole matrix r in a
+ * smooth gauge; the velocity operator of the HHG current).  Device arrays:
+ *   eps  double [nk][nb]          band energies (Ha), ascending per k
+ *   evec c128   [nk][nb][nb]      evec[k][alpha][n] = <alpha | n k>
+ *   dip  c128   [2][nk][nb][nb]   d^a_{nm k} (bohr), a = x, y
+ *   vel  c128   [2][nk][nb][nb]   v^a_{nm k} (Ha bohr)
+ * nk = nk1*nk2 points of the uniform grid k = (2pi/a)((i + shift)/N - 1/2);
+ * the lowest nv bands are occupied in rho_eq. */
+typedef struct {
+  int32_t nk1, nk2, nb, nv;
+  double shift, a_bohr;
+  const double* eps;
+  const void* evec;
+  const void* dip;
+  const void* vel;
+} tdg_model;
+
+/* Screened interaction for the kernel build: 2D Rytova-Keldysh
+ * W(q) = 2pi / (q (1 + r0 q)); at q = 0 the average of W over the grid cell
+ * [-h, h]^2, h = pi/(nk1 a), by nquad-point Gauss-Legendre (0 = 64). */
+typedef struct {
+  double r0_bohr;
+  int32_t block; /* TDG_BLOCK_ALL or TDG_BLOCK_EH */
+  int32_t nquad;
+} tdg_coulomb;
+
+/* Kernel dimension N = nk * P for a model and block (host call, no device work). */
+int tdg_kernel_dim(const tdg_model* model, int32_t block, int64_t* n_out);
+
+/* Build the direct electron-hole kernel of the lattice model (paper
+ * Eq. sigma-from-k with the single-G limit of Eq. bse-direct-def):
+ *   K_{(n m k),(n' m' k')} = -W(|fold(k - k')|) / (nk a^2) <n k|n' k'> <m' k'|m k>
+ * into K (dtype TDG_C128 or TDG_C64, row-major [N][ld], ld >= N; for C64
+ * K must be 16-byte aligned and ld even).  Overwrites the N x N block only. */
+int tdg_kernel_build(tdg_ctx ctx, const tdg_model* model, const tdg_coulomb* coulomb,
+                     int32_t dtype, void* K, int64_t ld);
+
+/* Rank rules for compression (paper Sec. SVD analysis): */
+#define TDG_TRUNC_REL_CUT 0  /* keep singular values s_i > value * s_max */
+#define TDG_TRUNC_FRACTION 1 /* keep round(value * N) singular values (at least 1) */
+#define TDG_TRUNC_RANK 2     /* keep exactly value singular values */
+#define TDG_TRUNC_R2 3       /* smallest rank with reconstruction R^2 >= value */
+typedef struct {
+  int32_t mode;
+  int32_t pad;
+  double value;
+} tdg_trunc;
+/* A rank never splits a group of singular values equal to within 1e-9 s_max:
+ * it is raised to the end of the group, so the truncated kernel is unique. */
+
+/* Output of compression.  The caller sets n, max_rank, dtype and the
+ * pointers; the library fills rank and the norms.
+ *   kdiag  device [n]               diagonal of K (dtype)
+ *   us     device, n*max_rank elts  S = U diag(s), row-major [n][rank] (dtype)
+ *   w      device, max_rank*n elts  V^H, row-major [rank][n] (dtype)
+ *   sigma  HOST double [n] or NULL  all singular values of K_off, descending */
+typedef struct {
+  int64_t n, max_rank;
+  int32_t dtype, pad;
+  void* kdiag;
+  void* us;
+  void* w;
+  double* sigma;
+  int64_t rank;
+  double tail_fro;  /* sqrt(sum_{i >= rank} s_i^2) = ||K_off - U S V^H||_F */
+  double tail_spec; /* s_rank, the spectral norm of the discarded part */
+} tdg_lowrank;
+
+/* Split K = K_diag + K_off (K_diag the literal matrix diagonal) and replace
+ * K_off by its rank-r truncated SVD (paper Eq. svd_diag_offdiag).  K is the
+ * Hermitian kernel (dtype, [n][ld]); the SVD is computed in FP64 through the
+ * Hermitian eigendecomposition K_off = Q L Q^H (s = |l|, U = Q sign(l),
+ * V = Q).  Synchronises the stream.  Fails with TDG_E_INVAL if the chosen
+ * rank exceeds max_rank (rank is still reported). */
+int tdg_kernel_compress(tdg_ctx ctx, const void* K, int64_t ld, int32_t dtype,
+                        const tdg_trunc* trunc, tdg_lowrank* out);
+
+/* One driving-field instance (atomic units): a Gaussian-enveloped carrier
+ * E(t) = e0 exp(-(t - t0)^2 / (2 tau^2)) cos(omega t) along (ex, ey), run for
+ * nsteps RK4 steps.  64 bytes; arrays of it are HOST memory. */
+typedef struct {
+  double e0, omega, tau, t0, ex, ey;
+  double nsteps; /* integral value stored as double */
+  double pad;
+} tdg_field;
+
+#define TDG_OP_DENSE 0
+#define TDG_OP_LOWRANK 1
+
+/* The kernel operator applied each RK4 stage.  dtype selects arithmetic:
+ * TDG_C128 -> FP64 contraction, TDG_C64 -> FP32 contraction with FP32
+ * accumulation (drho is formed in FP64 and rounded; dSigma is widened back
+ * to FP64 before the commutator).  Dense: K [n][ld].  Low rank: kdiag [n],
+ * us [n][rank], w [rank][n] as written by tdg_kernel_compress. */
+typedef struct {
+  int32_t kind, dtype, block, pad;
+  int64_t n;
+  const void* K;
+  int64_t ld;
+  const void* kdiag;
+  const void* us;
+  const void* w;
+  int64_t rank;
+} tdg_operator;
+
+/* Observable time series, device double arrays [batch][stride] (stride >=
+ * max nsteps + 1); entry [b][n] is taken at t_n = n dt for n = 0..nsteps_b:
+ *   P    (1/nk) sum_k Re Tr(e.d_k rho_k)        polarisation along e
+ *   J    (1/nk) sum_k Re Tr(e.v_k rho_k)        current along e
+ *   occ  (1/nk) sum_k Re rho_{c1 c1 k}          first conduction band
+ *   tr   max_k |Tr rho_k - nv|                  diagnostic (may be NULL)
+ *   herm max_k max_nm |rho_nm - conj rho_mn|    diagnostic (may be NULL) */
+typedef struct {
+  double* P;
+  double* J;
+  double* occ;
+  double* tr;
+  double* herm;
+  int64_t stride;
+} tdg_obs;
+
+/* Integrate `batch` field instances with classical RK4 (fields evaluated at
+ * t_n, t_n + dt/2 twice, t_n + dt; t_n = n dt), each for its own nsteps.
+ * rho: device c128 [batch][nk][nb][nb], row n column m; on entry rho(0)
+ * (ignored and replaced by rho_eq when init_eq != 0), on exit rho(T_b).
+ * Every step of the path runs on the device; nothing is copied back. */
+int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
+                  const tdg_field* fields, int32_t batch, double dt, void* rho,
+                  int32_t init_eq, const tdg_obs* obs);
+
+/* Observables of a given state: out device double [batch][5] =
+ * (P, J, occ, tr, herm) as defined for tdg_obs, with e taken from fields
+ * (host, batch entries). */
+int tdg_observables(tdg_ctx ctx, const tdg_model* model, const void* rho, int32_t batch,
+                    const tdg_field* fields, double* out);
+
+/* Scan observable series for NaN/Inf and for trace or Hermiticity drift
+ * beyond the given thresholds.  Synchronises; returns TDG_E_NUMERIC with the
+ * first offending (instance, step) in tdg_last_error, else TDG_OK. */
+int tdg_check_numeric(tdg_ctx ctx, const tdg_obs* obs, int32_t batch, const tdg_field* fields,
+                      double tr_tol, double herm_tol);
+
+/* Per-kernel timing with HIP events on the context stream, for measurement
+ * only.  While enabled, every launch of the timed kernel classes is bracketed
+ * by events; tdg_profile_read synchronises and returns the summed duration
+ * (ms) and launch count of a class since the last reset. */
+#define TDG_KCLASS_STAGE 0   /* fused contraction + commutator + RK4 stage kernel */
+#define TDG_KCLASS_PROJECT 1 /* low-rank projection z = V^H x */
+int tdg_profile_enable(tdg_ctx ctx, int32_t on);
+int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDAGW_H */

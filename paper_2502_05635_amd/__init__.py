@@ -1,0 +1,236 @@
+"""Python binding of libtdagw (MI355X TD-aGW propagation with dense or
+SVD-compressed electron-hole kernels).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream, every computation runs in the library's HIP kernels.  There is no CPU
+fallback; loading fails loudly when the library is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch  # must precede the library load: it binds to torch's HIP runtime
+
+from . import _abi as abi
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdagw.so")
+_LIB = None
+
+
+class TdgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tdagw error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_05635_amd.build`")
+        handle = C.CDLL(LIB_PATH)
+        for name, (args, res) in abi.SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = handle
+    return _LIB
+
+
+def _ptr(t: torch.Tensor | None):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _cdtype(dtype: str):
+    if dtype == "c128":
+        return abi.TDG_C128, torch.complex128
+    if dtype == "c64":
+        return abi.TDG_C64, torch.complex64
+    raise ValueError(dtype)
+
+
+def _block(block: str) -> int:
+    return {"all": abi.TDG_BLOCK_ALL, "eh": abi.TDG_BLOCK_EH}[block]
+
+
+def field_array(fields) -> C.Array:
+    """tdg_field[B] (host) from a FieldTable or a [B][8] float64 array."""
+    rec = fields.as_records() if hasattr(fields, "as_records") else np.asarray(fields, dtype=np.float64)
+    arr = (abi.Field * rec.shape[0])()
+    C.memmove(arr, np.ascontiguousarray(rec, dtype=np.float64).ctypes.data, rec.nbytes)
+    return arr
+
+
+@dataclass
+class DeviceModel:
+    """Band-structure input resident on the device (caller-owned tensors)."""
+    nk1: int
+    nk2: int
+    nb: int
+    nv: int
+    shift: float
+    a: float
+    eps: torch.Tensor
+    evec: torch.Tensor
+    dip: torch.Tensor
+    vel: torch.Tensor
+
+    @staticmethod
+    def from_model(m, device="cuda") -> "DeviceModel":
+        as_t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)  # noqa: E731
+        return DeviceModel(m.nk1, m.nk2, m.nb, m.nv, m.shift, m.a,
+                           as_t(m.eps, torch.float64), as_t(m.evec, torch.complex128),
+                           as_t(m.dip, torch.complex128), as_t(m.vel, torch.complex128))
+
+    @property
+    def nk(self) -> int:
+        return self.nk1 * self.nk2
+
+    def struct(self) -> abi.Model:
+        return abi.Model(self.nk1, self.nk2, self.nb, self.nv, self.shift, self.a,
+                         self.eps.data_ptr(), self.evec.data_ptr(), self.dip.data_ptr(), self.vel.data_ptr())
+
+
+@dataclass
+class LowRankFactors:
+    kdiag: torch.Tensor
+    us: torch.Tensor        # [N][rank]
+    w: torch.Tensor         # [rank][N]  (= V^H)
+    sigma: np.ndarray       # all singular values of K_off, descending
+    rank: int
+    tail_fro: float
+    tail_spec: float
+    dtype: str
+
+
+class Context:
+    """A library context bound to one device and the current torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self._lib = lib()
+        self.device = device
+        stream = stream or torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        self._check(self._lib.tdg_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)), None)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.tdg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, h=...):
+        if rc != abi.TDG_OK:
+            handle = self.h if h is ... else h
+            msg = self._lib.tdg_last_error(handle).decode()
+            raise TdgError(rc, msg)
+
+    # --- kernel build / compression -------------------------------------
+    def kernel_dim(self, model: DeviceModel, block: str) -> int:
+        n = C.c_int64()
+        ms = model.struct()
+        self._check(self._lib.tdg_kernel_dim(C.byref(ms), _block(block), C.byref(n)))
+        return n.value
+
+    def kernel_build(self, model: DeviceModel, r0: float, block: str, dtype: str = "c128",
+                     nquad: int = 64, out: torch.Tensor | None = None) -> torch.Tensor:
+        code, tdt = _cdtype(dtype)
+        n = self.kernel_dim(model, block)
+        if out is None:
+            out = torch.empty((n, n), dtype=tdt, device=f"cuda:{self.device}")
+        ms = model.struct()
+        cs = abi.Coulomb(r0, _block(block), nquad)
+        self._check(self._lib.tdg_kernel_build(self.h, C.byref(ms), C.byref(cs), code, _ptr(out), out.stride(0)))
+        return out
+
+    def kernel_compress(self, K: torch.Tensor, rule: str = "rel_cut", value: float = 1e-3,
+                        max_rank: int | None = None) -> LowRankFactors:
+        dtype = "c128" if K.dtype == torch.complex128 else "c64"
+        code, tdt = _cdtype(dtype)
+        n = K.shape[0]
+        max_rank = n if max_rank is None else int(max_rank)
+        dev = K.device
+        kdiag = torch.empty(n, dtype=tdt, device=dev)
+        us = torch.empty(n * max_rank, dtype=tdt, device=dev)
+        w = torch.empty(n * max_rank, dtype=tdt, device=dev)
+        sigma = np.zeros(n, dtype=np.float64)
+        lr = abi.LowRank(n, max_rank, code, 0, kdiag.data_ptr(), us.data_ptr(), w.data_ptr(),
+                         sigma.ctypes.data, 0, 0.0, 0.0)
+        tr = abi.Trunc(abi.TDG_TRUNC[rule], 0, float(value))
+        self._check(self._lib.tdg_kernel_compress(self.h, _ptr(K), K.stride(0), code, C.byref(tr), C.byref(lr)))
+        r = int(lr.rank)
+        return LowRankFactors(kdiag, us[: n * r].view(n, r), w[: n * r].view(r, n), sigma, r,
+                              lr.tail_fro, lr.tail_spec, dtype)
+
+    # --- propagation --------------------------------------------------------
+    def _operator(self, op, block: str, n: int) -> abi.Operator:
+        if isinstance(op, LowRankFactors):
+            code, _ = _cdtype(op.dtype)
+            return abi.Operator(abi.TDG_OP_LOWRANK, code, _block(block), 0, n, None, 0,
+                                op.kdiag.data_ptr(), op.us.data_ptr(), op.w.data_ptr(), op.rank)
+        code, _ = _cdtype("c128" if op.dtype == torch.complex128 else "c64")
+        return abi.Operator(abi.TDG_OP_DENSE, code, _block(block), 0, n, op.data_ptr(), op.stride(0),
+                            None, None, None, 0)
+
+    def propagate(self, op, model: DeviceModel, block: str, fields, dt: float,
+                  rho: torch.Tensor | None = None, init_eq: bool | None = None,
+                  diagnostics: bool = True) -> dict:
+        """Integrate every instance of `fields`; returns device tensors
+        P, J, occ (and tr, herm) of shape [B][max nsteps + 1] and rho(T)."""
+        fa = field_array(fields)
+        batch = len(fa)
+        maxn = max(int(f.nsteps) for f in fa)
+        dev = f"cuda:{self.device}"
+        if rho is None:
+            rho = torch.empty((batch, model.nk, model.nb, model.nb), dtype=torch.complex128, device=dev)
+            init_eq = True if init_eq is None else init_eq
+        init_eq = bool(init_eq)
+        stride = maxn + 1
+        arrs = {k: torch.zeros((batch, stride), dtype=torch.float64, device=dev)
+                for k in (("P", "J", "occ", "tr", "herm") if diagnostics else ("P", "J", "occ"))}
+        obs = abi.Obs(arrs["P"].data_ptr(), arrs["J"].data_ptr(), arrs["occ"].data_ptr(),
+                      arrs["tr"].data_ptr() if diagnostics else None,
+                      arrs["herm"].data_ptr() if diagnostics else None, stride)
+        n = self.kernel_dim(model, block)
+        opr = self._operator(op, block, n)
+        ms = model.struct()
+        self._check(self._lib.tdg_propagate(self.h, C.byref(opr), C.byref(ms), fa, batch, float(dt), _ptr(rho),
+                                            int(init_eq), C.byref(obs)))
+        arrs["rho"] = rho
+        arrs["_obs_struct"] = obs
+        return arrs
+
+    def observables(self, model: DeviceModel, rho: torch.Tensor, fields) -> torch.Tensor:
+        fa = field_array(fields)
+        out = torch.zeros((len(fa), 5), dtype=torch.float64, device=rho.device)
+        ms = model.struct()
+        self._check(self._lib.tdg_observables(self.h, C.byref(ms), _ptr(rho), len(fa), fa, _ptr(out)))
+        return out
+
+    def check_numeric(self, result: dict, fields, tr_tol: float = 1e-10, herm_tol: float = 1e-10) -> None:
+        fa = field_array(fields)
+        self._check(self._lib.tdg_check_numeric(self.h, C.byref(result["_obs_struct"]), len(fa), fa,
+                                                tr_tol, herm_tol))
+
+    # --- measurement ------------------------------------------------------
+    def profile_enable(self, on: bool = True) -> None:
+        self._check(self._lib.tdg_profile_enable(self.h, int(on)))
+
+    def profile_read(self, kclass: int = abi.TDG_KCLASS_STAGE):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        self._check(self._lib.tdg_profile_read(self.h, kclass, C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value

@@ -1,0 +1,76 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tdagw.h"
+
+namespace tdg {
+
+// Workspace slots owned by a context (grow-only device allocations).
+enum WsSlot {
+  WS_RHO_S = 0,  // stage state          c128 [B][nk][nb][nb]
+  WS_ACC,        // RK4 accumulator      c128 [B][nk][nb][nb]
+  WS_X0,         // drho gather, ping    [B][N] (operator dtype)
+  WS_X1,         // drho gather, pong
+  WS_Z,          // low-rank projection  [B][r]
+  WS_OBS_PART,   // per-k observables    double [chunk][B][nk][5]
+  WS_FIELDS,     // field records        tdg_field [B]
+  WS_WTAB,       // W(q) by index difference, double [nk1][nk2]
+  WS_SOLVER_A,   // compression: K_off column-major, c128 [n][n]
+  WS_SOLVER_D,   // eigenvalues / off-diagonal, double [2n]
+  WS_SOLVER_I,   // info, permutation, kept eigenvalues
+  WS_MISC,       // small scratch (row sums, flags)
+  WS_COUNT
+};
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace tdg
+
+struct tdg_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  tdg::Buf ws[tdg::WS_COUNT];
+  void* blas = nullptr;  // rocblas_handle, created on first compression
+  bool prof = false;
+  std::vector<tdg::EventPair> events[2];
+  size_t used[2] = {0, 0};
+};
+
+namespace tdg {
+
+int fail(tdg_ctx ctx, int code, const char* fmt, ...);
+// Ensure workspace slot holds at least `bytes`; returns TDG_OK or an error.
+int ws_reserve(tdg_ctx ctx, WsSlot slot, size_t bytes, void** out);
+// Check the last launch / HIP status and convert to a library error.
+int hip_check(tdg_ctx ctx, hipError_t e, const char* what);
+int launch_check(tdg_ctx ctx, const char* what);
+// Profiling brackets (no-ops unless profiling is on).
+void prof_begin(tdg_ctx ctx, int kclass);
+void prof_end(tdg_ctx ctx, int kclass);
+int validate_model(tdg_ctx ctx, const tdg_model* m);
+int pairs_per_k(const tdg_model* m, int block);
+// Destroy the context's rocBLAS handle if compression created one.
+void release_blas(tdg_ctx ctx);
+
+}  // namespace tdg
+
+#define TDG_TRY(expr)              \
+  do {                             \
+    int _rc = (expr);              \
+    if (_rc != TDG_OK) return _rc; \
+  } while (0)

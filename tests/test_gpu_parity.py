@@ -1,0 +1,250 @@
+"""HIP library vs the FP64 oracle on the same seeded inputs (GPU only).
+
+Tolerances: the FP64 path must agree to 1e-10 and the FP32 paths to 1e-4 in
+err_X = max_n |X_gpu(t_n) - X_ref(t_n)| / max_n |X_ref(t_n)| for the
+polarisation P and current J; kernel elements compare to 1e-14 (FP64) or
+1e-7 (FP32 storage) of the largest element.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from workloads import FS_AU, HARTREE_EV, FieldTable, dirac_model, get_config, tb4_model
+from workloads.configs import R0_STABLE
+
+pytestmark = pytest.mark.gpu
+
+A = 6.0
+DT = 0.05 * FS_AU
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2502_05635_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def err_rel(x, ref):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+def strong(nsteps, e0=5e-3, omega_ev=1.5):
+    t = nsteps * DT
+    return FieldTable.single(e0, omega_ev / HARTREE_EV, t / 10.0, t / 2.0, nsteps)
+
+
+@pytest.fixture(scope="module")
+def tb4_6():
+    return tb4_model(6, A, 0.5)
+
+
+@pytest.fixture(scope="module")
+def k_tb4_6(tb4_6):
+    return O.build_kernel(tb4_6, R0_STABLE, "eh")
+
+
+def _dev(P, m):
+    return P.DeviceModel.from_model(m)
+
+
+# --- kernel build -----------------------------------------------------------
+
+def test_kernel_build_dirac_c128(P, ctx):
+    m = dirac_model(6, 1.0, 1.5, A, 0.5)
+    _log("kernel build dirac 6x6 all-pairs c128")
+    kg = ctx.kernel_build(_dev(P, m), R0_STABLE, "all", "c128").cpu().numpy()
+    ko = O.build_kernel(m, R0_STABLE, "all")
+    assert np.abs(kg - ko).max() <= 1e-14 * np.abs(ko).max()
+
+
+def test_kernel_build_tb4_c64(P, ctx, tb4_6, k_tb4_6):
+    _log("kernel build tb4 6x6 eh c64")
+    kg = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", "c64").cpu().numpy()
+    assert np.abs(kg - k_tb4_6).max() <= 1e-7 * np.abs(k_tb4_6).max()
+
+
+def test_kernel_build_full_size_sampled(P, ctx):
+    cfg = get_config(1)
+    m = cfg.model()
+    _log(f"kernel build {cfg.name} N={cfg.n} c64, sampled elements")
+    kg = ctx.kernel_build(_dev(P, m), cfg.r0, "eh", "c64")
+    n = kg.shape[0]
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, n, size=(300, 2))
+    idx = np.vstack([idx, [[0, 0], [n - 1, n - 1], [0, n - 1], [n - 1, 0], [5, 5]]])
+    vals = kg[torch.from_numpy(idx[:, 0]).cuda(), torch.from_numpy(idx[:, 1]).cuda()].cpu().numpy()
+    ref = np.array([O.kernel_element(m, cfg.r0, "eh", i, j) for i, j in idx])
+    scale = abs(O.kernel_element(m, cfg.r0, "eh", 0, 0))
+    assert np.abs(vals - ref).max() <= 1e-7 * scale
+
+
+# --- compression ------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_compress_matches_oracle(P, ctx, tb4_6, k_tb4_6, dtype):
+    _log(f"compress tb4 6x6 eh {dtype}")
+    kg = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", dtype)
+    f = ctx.kernel_compress(kg, "fraction", 0.2)
+    ref = O.compress(k_tb4_6, "fraction", 0.2)
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    assert f.rank == ref["r"]
+    np.testing.assert_allclose(f.sigma, ref["s"], rtol=0, atol=tol * ref["s"][0])
+    rec = f.us.cpu().numpy().astype(np.complex128) @ f.w.cpu().numpy().astype(np.complex128)
+    rec_ref = ref["US"] @ ref["Vh"]
+    assert np.abs(rec - rec_ref).max() <= tol * 10 * np.abs(rec_ref).max()
+    np.testing.assert_allclose(f.kdiag.cpu().numpy(), ref["kdiag"], rtol=tol)
+    np.testing.assert_allclose(f.tail_fro, ref["tail_fro"], rtol=1e-6 if dtype == "c64" else 1e-10)
+
+
+def test_compress_rank_rules(P, ctx, tb4_6, k_tb4_6):
+    kg = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", "c128")
+    for rule, val in (("rel_cut", 1e-2), ("rank", 17), ("r2", 0.9), ("fraction", 1.0)):
+        f = ctx.kernel_compress(kg, rule, val)
+        assert f.rank == O.compress(k_tb4_6, rule, val)["r"], rule
+
+
+# --- propagation ------------------------------------------------------------
+
+def test_dense_fp64_dirac_full_config(P, ctx):
+    """The two-band all-pairs workload (12x12, 576 x 576 complex128, 2000 steps)."""
+    cfg = get_config(0)
+    m = cfg.model()
+    _log(f"propagate {cfg.name} dense FP64 2000 steps")
+    k = O.build_kernel(m, cfg.r0, "all")
+    ref = O.propagate(m, O.DenseOp(k), "all", cfg.fields, cfg.dt)
+    dm = _dev(P, m)
+    kg = ctx.kernel_build(dm, cfg.r0, "all", "c128")
+    res = ctx.propagate(kg, dm, "all", cfg.fields, cfg.dt)
+    torch.cuda.synchronize()
+    for key in ("P", "J", "occ"):
+        e = err_rel(res[key][0].cpu().numpy(), ref[key])
+        _log(f"  err_{key} = {e:.3e}")
+        assert e <= 1e-10, key
+    assert res["tr"].max().item() < 1e-12
+    assert res["herm"].max().item() < 1e-13
+    ctx.check_numeric(res, cfg.fields, 1e-10, 1e-10)
+    np.testing.assert_allclose(res["rho"][0].cpu().numpy(), ref["rho"], rtol=0, atol=1e-12)
+
+
+def test_lowrank_fp64_parity(P, ctx, tb4_6, k_tb4_6):
+    f = strong(600)
+    ref_fac = O.compress(k_tb4_6, "fraction", 0.3)
+    _log(f"propagate tb4 6x6 low rank r={ref_fac['r']} FP64 600 steps")
+    ref = O.propagate(tb4_6, O.LowRankOp.from_factors(ref_fac), "eh", f, DT)
+    dm = _dev(P, tb4_6)
+    fac = ctx.kernel_compress(ctx.kernel_build(dm, R0_STABLE, "eh", "c128"), "fraction", 0.3)
+    assert fac.rank == ref_fac["r"]
+    res = ctx.propagate(fac, dm, "eh", f, DT)
+    for key in ("P", "J", "occ"):
+        assert err_rel(res[key][0].cpu().numpy(), ref[key]) <= 1e-10, key
+
+
+def test_dense_fp32_parity(P, ctx, tb4_6, k_tb4_6):
+    f = strong(800)
+    _log("propagate tb4 6x6 dense FP32 800 steps")
+    ref = O.propagate(tb4_6, O.DenseOp(k_tb4_6), "eh", f, DT)
+    dm = _dev(P, tb4_6)
+    res = ctx.propagate(ctx.kernel_build(dm, R0_STABLE, "eh", "c64"), dm, "eh", f, DT)
+    for key in ("P", "J"):
+        e = err_rel(res[key][0].cpu().numpy(), ref[key])
+        _log(f"  err_{key} = {e:.3e}")
+        assert e <= 1e-4, key
+
+
+def test_lowrank_fp32_parity_odd_rank(P, ctx, tb4_6, k_tb4_6):
+    """An odd rank exercises the unaligned (one complex per load) row path."""
+    f = strong(800)
+    r = 37
+    ref_fac = O.compress(k_tb4_6, "rank", r)
+    assert ref_fac["r"] % 2 == 1
+    ref = O.propagate(tb4_6, O.LowRankOp.from_factors(ref_fac), "eh", f, DT)
+    dm = _dev(P, tb4_6)
+    fac = ctx.kernel_compress(ctx.kernel_build(dm, R0_STABLE, "eh", "c64"), "rank", r)
+    assert fac.rank == ref_fac["r"]
+    res = ctx.propagate(fac, dm, "eh", f, DT)
+    for key in ("P", "J"):
+        assert err_rel(res[key][0].cpu().numpy(), ref[key]) <= 1e-4, key
+
+
+def test_batched_uneven_instances(P, ctx):
+    m = tb4_model(4, A, 0.5)
+    k = O.build_kernel(m, R0_STABLE, "eh")
+    fields = FieldTable.stack([strong(200, 5e-3, 1.5), strong(350, 1e-3, 0.9),
+                               FieldTable.single(1e-2, 2.0 / HARTREE_EV, 1.0 * FS_AU, 2.0 * FS_AU, 0),
+                               strong(1, 2e-3, 1.1)])
+    _log("propagate tb4 4x4 batched uneven lengths (200, 350, 0, 1)")
+    dm = _dev(P, m)
+    res = ctx.propagate(ctx.kernel_build(dm, R0_STABLE, "eh", "c128"), dm, "eh", fields, DT)
+    for b in range(fields.batch):
+        ref = O.propagate(m, O.DenseOp(k), "eh", fields, DT, instance=b)
+        n = int(fields.nsteps[b])
+        for key in ("P", "J", "occ"):
+            got = res[key][b, : n + 1].cpu().numpy()
+            if n == 0 or np.abs(ref[key]).max() == 0.0:
+                assert np.abs(got - ref[key]).max() <= 1e-14
+            else:
+                assert err_rel(got, ref[key]) <= 1e-10, (b, key)
+        np.testing.assert_allclose(res["rho"][b].cpu().numpy(), ref["rho"], rtol=0, atol=1e-12)
+
+
+def test_stationary_zero_field_bitwise(P, ctx, tb4_6):
+    f = FieldTable.single(0.0, 0.05, 100.0, 200.0, 50)
+    dm = _dev(P, tb4_6)
+    for dtype in ("c128", "c64"):
+        res = ctx.propagate(ctx.kernel_build(dm, R0_STABLE, "eh", dtype), dm, "eh", f, DT)
+        rho = res["rho"][0].cpu().numpy()
+        assert np.array_equal(rho, O.rho_equilibrium(tb4_6))
+        assert torch.count_nonzero(res["P"]).item() == 0
+
+
+def test_observables_entry_point(P, ctx, tb4_6):
+    rng = np.random.default_rng(3)
+    nb = tb4_6.nb
+    x = rng.standard_normal((tb4_6.nk, nb, nb)) + 1j * rng.standard_normal((tb4_6.nk, nb, nb))
+    rho = 0.5 * (x + x.conj().transpose(0, 2, 1))
+    f = FieldTable.single(1e-3, 0.05, 100.0, 200.0, 10, ex=0.6, ey=0.8)
+    out = ctx.observables(_dev(P, tb4_6), torch.from_numpy(rho[None]).cuda(), f).cpu().numpy()[0]
+    ref = O.observables(tb4_6, rho, 0.6, 0.8)
+    for i, key in enumerate(("P", "J", "occ", "tr", "herm")):
+        assert abs(out[i] - ref[key]) <= 1e-13 * max(1.0, abs(ref[key])), key
+
+
+def test_invalid_arguments_rejected(P, ctx, tb4_6):
+    dm = _dev(P, tb4_6)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c128")
+    with pytest.raises(P.TdgError) as e:
+        ctx.propagate(kg, dm, "all", strong(10), DT)          # N mismatch for the all-pairs block
+    assert e.value.code == -1
+    with pytest.raises(P.TdgError):
+        ctx.propagate(kg, dm, "eh", strong(10), -1.0)          # negative dt
+    with pytest.raises(P.TdgError):
+        ctx.kernel_compress(kg, "rank", 50, max_rank=10)       # rank above capacity
+
+
+def test_check_numeric_reports_nan(P, ctx, tb4_6):
+    """A NaN planted in the initial state (host-forced) is reported with its step."""
+    dm = _dev(P, tb4_6)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c128")
+    rho = torch.from_numpy(O.rho_equilibrium(tb4_6)[None]).cuda()
+    rho[0, 3, 1, 1] = float("nan")
+    f = strong(5)
+    res = ctx.propagate(kg, dm, "eh", f, DT, rho=rho, init_eq=False)
+    with pytest.raises(P.TdgError) as e:
+        ctx.check_numeric(res, f)
+    assert e.value.code == -5 and "step 0" in str(e.value)
