@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of TD-aGW propagation on one MI355X: instance.RK4-steps/s with
+the SVD-compressed (low-rank) electron-hole kernel against the dense kernel,
+at fixed error vs the FP64 oracle.
+
+Workload: the seeded four-band lattice model on a 36x36 grid, conduction-valence
+kernel block N = 5184 (complex64), one field instance E0 = 5e-3 a.u.,
+omega = 1.5 eV, 4000 RK4 steps of 0.05 fs.  The low-rank operator keeps the
+fraction of singular values chosen by the fixed-error criterion (stored with
+the oracle results under tests/golden/).  One step = one full RK4 step of the
+hot path: field, drho gather, contraction, per-k commutator, RK4 combine and
+observables, all on the device.
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+GOLDEN_JSON = os.path.join(ROOT, "tests", "golden", "tb4_36x36_fixed_error.json")
+GOLDEN_NPZ = os.path.join(ROOT, "tests", "golden", "tb4_36x36_oracle_series.npz")
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000, help="timed RK4 steps per path")
+    ap.add_argument("--warmup", type=int, default=400, help="untimed RK4 steps per path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
+    ap.add_argument("--fraction", type=float, default=None, help="override the kept fraction of singular values")
+    return ap.parse_args()
+
+
+def err_rel(x, ref):
+    import numpy as np
+    return float(np.abs(np.asarray(x) - ref).max() / np.abs(ref).max())
+
+
+def state_bytes(nk, nb):
+    """Per-stage traffic of the per-k part (FP64 state): rho_s read + write,
+    rho_n read (+ write in one stage of four), acc read + write (written only in
+    the first stage), both dipole planes, band energies."""
+    blk = nk * nb * nb * 16
+    return blk * (2 + 1.25 + 1.75) + 2 * blk + nk * nb * 8
+
+
+def algorithmic_bytes(kind, n, r, nk, nb, elt=8):
+    """Bytes one launch must move at minimum (stated per kernel)."""
+    if kind == "dense_stage":      # K rows, drho in, drho out, state
+        return n * n * elt + 2 * n * elt + state_bytes(nk, nb)
+    if kind == "lowrank_stage":    # S rows, z, K_diag, drho in, drho out, state
+        return n * r * elt + r * elt + 3 * n * elt + state_bytes(nk, nb)
+    if kind == "project":          # V^H rows, drho in, z out
+        return r * n * elt + n * elt + r * elt
+    raise ValueError(kind)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(instances or k-blocks would shard across GPUs; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_05635_amd as P
+    from paper_2502_05635_amd import _abi as abi
+    from workloads import FieldTable, get_config
+
+    cfg = get_config(1)
+    model = cfg.model()
+    f = cfg.fields
+    golden = json.load(open(GOLDEN_JSON)) if os.path.exists(GOLDEN_JSON) else None
+    frac = args.fraction if args.fraction is not None else (golden["chosen"]["fraction"] if golden else 0.05)
+
+    def fields_for(nsteps):
+        return FieldTable(f.e0, f.omega, f.tau, f.t0, f.ex, f.ey, np.array([nsteps], dtype=np.int64))
+
+    ctx = P.Context(0)
+    dm = P.DeviceModel.from_model(model)
+    K = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
+    t0 = time.perf_counter()
+    fac = ctx.kernel_compress(K, "fraction", frac)
+    torch.cuda.synchronize()
+    compress_s = time.perf_counter() - t0
+    n, r, nk, nb = K.shape[0], fac.rank, model.nk, model.nb
+
+    def timed(op, steps, warmup, profile):
+        ctx.propagate(op, dm, "eh", fields_for(warmup), cfg.dt)
+        ctx.profile_enable(profile)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        res = ctx.propagate(op, dm, "eh", fields_for(steps), cfg.dt)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        prof = {}
+        if profile:
+            for name, cls in (("stage", abi.TDG_KCLASS_STAGE), ("project", abi.TDG_KCLASS_PROJECT)):
+                ms, cnt = ctx.profile_read(cls)
+                prof[name] = (ms, cnt)
+        ctx.profile_enable(False)
+        return res, t_b - t_a, prof
+
+    out = {}
+    for name, op in (("dense", K), ("lowrank", fac)):
+        res, secs, _ = timed(op, args.steps, args.warmup, False)
+        _, _, prof = timed(op, args.steps, args.warmup, True)
+        out[name] = {"secs": secs, "res": res, "prof": prof}
+
+    # errors against the stored FP64 oracle series (same operator, same steps)
+    errs = {}
+    if os.path.exists(GOLDEN_NPZ) and golden and abs(golden["chosen"]["fraction"] - frac) < 1e-12:
+        g = np.load(GOLDEN_NPZ)
+        m_ = min(args.steps, cfg.fields.nsteps[0]) + 1
+        for name, pre in (("dense", "dense"), ("lowrank", "low")):
+            res = out[name]["res"]
+            errs[name] = {k: err_rel(res[k][0, :m_].cpu().numpy(), g[f"{pre}_{k}"][:m_]) for k in ("P", "J")}
+        low = out["lowrank"]["res"]
+        errs["lowrank_vs_dense_oracle_P_l2"] = float(
+            np.linalg.norm(low["P"][0, :m_].cpu().numpy() - g["dense_P"][:m_]) / np.linalg.norm(g["dense_P"][:m_]))
+
+    # dominant kernel of the low-rank path and the dense stage kernel
+    lp = out["lowrank"]["prof"]
+    dom = "stage" if lp["stage"][0] >= lp["project"][0] else "project"
+    dom_kind = "lowrank_stage" if dom == "stage" else "project"
+    dom_avg_s = lp[dom][0] / lp[dom][1] * 1e-3
+    dom_bytes = algorithmic_bytes(dom_kind, n, r, nk, nb)
+    dense_avg_s = out["dense"]["prof"]["stage"][0] / out["dense"]["prof"]["stage"][1] * 1e-3
+    dense_bytes = algorithmic_bytes("dense_stage", n, r, nk, nb)
+
+    value = args.steps / out["lowrank"]["secs"]
+    dense_value = args.steps / out["dense"]["secs"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, frac, args.cpu_seconds)
+
+    line = {
+        "metric": "instance*RK4-steps/s, low-rank vs dense K, at fixed error vs FP64 oracle",
+        "value": value,
+        "unit": "instance*RK4-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 / value,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: seeded 4-band lattice model, 36x36 k-grid, conduction-valence kernel "
+                        f"N={n} complex64, 1 field instance, dt=0.05 fs; FP32 contraction, FP64 state",
+            "operator": "low-rank K_diag + S V^H",
+            "kept_fraction": frac, "rank": r, "rank_rel_cut_1e-3": int(np.count_nonzero(fac.sigma > 1e-3 * fac.sigma[0])),
+            "batch": 1, "parallelism": "none",
+        },
+        "dense": {"value": dense_value, "ms_per_step": 1e3 / dense_value,
+                  "stage_kernel_us": dense_avg_s * 1e6,
+                  "stage_kernel_GBps": dense_bytes / dense_avg_s / 1e9,
+                  "stage_kernel_hbm_frac": dense_bytes / dense_avg_s / 1e9 / HBM_PEAK_GBS},
+        "speedup_lowrank_vs_dense": value / dense_value,
+        "errors_vs_fp64_oracle": errs or None,
+        "compress_seconds": compress_s,
+        "roofline": {
+            "bound": "hbm", "kernel": f"stage_kernel<float,true>" if dom == "stage" else "project_kernel<float>",
+            "achieved": dom_bytes / dom_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dom_bytes / dom_avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_us": dom_avg_s * 1e6, "bytes_per_launch": dom_bytes,
+        },
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(cfg, frac, seconds):
+    """The FP64 oracle on the host cores: the same workload and kept fraction,
+    a bounded prefix of the 4000 steps (about `seconds` of CPU time)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle as O
+
+    model = cfg.model()
+    k = O.build_kernel(model, cfg.r0, "eh")
+    fac = O.compress(k, "fraction", frac, method="eigh")
+    op = O.LowRankOp.from_factors(fac)
+    probe = 20
+    t0 = time.perf_counter()
+    O.propagate(model, op, "eh", cfg.fields, cfg.dt, nsteps=probe)
+    per = (time.perf_counter() - t0) / probe
+    nsamp = int(max(probe, min(int(cfg.fields.nsteps[0]), seconds / per)))
+    t0 = time.perf_counter()
+    O.propagate(model, op, "eh", cfg.fields, cfg.dt, nsteps=nsamp)
+    secs = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {"value": nsamp / secs, "unit": "instance*RK4-steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {nsamp} of {int(cfg.fields.nsteps[0])} RK4 steps of the same workload, FP64 numpy "
+                      f"oracle, low-rank operator at rank {fac['r']} (kernel build and SVD untimed)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -222,6 +222,19 @@ int tdg_check_numeric(tdg_ctx ctx, const tdg_obs* obs, int32_t batch, const tdg_
 int tdg_profile_enable(tdg_ctx ctx, int32_t on);
 int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* launches);
 
+/* Launch-shape selection for the stage kernel.  The fused contraction +
+ * commutator kernel exists in a few variants (threads per block, unroll
+ * depth, occupancy target).  With autotuning on (the default), the first
+ * tdg_propagate of a shape (operator kind, dtype, N, nk, batch, rank) times
+ * each variant on the first RK4 stage (which leaves rho untouched), keeps the
+ * fastest for the context and restarts the integration; variants differ only
+ * in summation order. */
+#define TDG_OPT_AUTOTUNE 0      /* 1 = tune on first use (default), 0 = use variant 0 */
+#define TDG_OPT_STAGE_VARIANT 1 /* >= 0 forces that variant index, -1 = tuned/default */
+int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
+/* Name of the stage-kernel variant the last tdg_propagate used ("" before any). */
+const char* tdg_last_variant(tdg_ctx ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -225,6 +225,13 @@ class Context:
         self._check(self._lib.tdg_check_numeric(self.h, C.byref(result["_obs_struct"]), len(fa), fa,
                                                 tr_tol, herm_tol))
 
+    # --- launch-shape selection ---------------------------------------------
+    def set_option(self, option: int, value: int) -> None:
+        self._check(self._lib.tdg_set_option(self.h, option, int(value)))
+
+    def last_variant(self) -> str:
+        return self._lib.tdg_last_variant(self.h).decode()
+
     # --- measurement ------------------------------------------------------
     def profile_enable(self, on: bool = True) -> None:
         self._check(self._lib.tdg_profile_enable(self.h, int(on)))

@@ -20,6 +20,8 @@ TDG_OP_DENSE = 0
 TDG_OP_LOWRANK = 1
 TDG_KCLASS_STAGE = 0
 TDG_KCLASS_PROJECT = 1
+TDG_OPT_AUTOTUNE = 0
+TDG_OPT_STAGE_VARIANT = 1
 
 P = C.c_void_p
 
@@ -72,6 +74,8 @@ SIGNATURES = {
                        C.c_int32, C.POINTER(Obs)], C.c_int),
     "tdg_observables": ([P, C.POINTER(Model), P, C.c_int32, C.POINTER(Field), P], C.c_int),
     "tdg_check_numeric": ([P, C.POINTER(Obs), C.c_int32, C.POINTER(Field), C.c_double, C.c_double], C.c_int),
+    "tdg_set_option": ([P, C.c_int32, C.c_int64], C.c_int),
+    "tdg_last_variant": ([P], C.c_char_p),
     "tdg_profile_enable": ([P, C.c_int32], C.c_int),
     "tdg_profile_read": ([P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
 }

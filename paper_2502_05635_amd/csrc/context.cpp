@@ -143,6 +143,22 @@ int tdg_set_stream(tdg_ctx ctx, void* hip_stream) {
 
 const char* tdg_last_error(tdg_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
+int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value) {
+  if (!ctx) return TDG_E_INVAL;
+  if (option == TDG_OPT_AUTOTUNE) {
+    ctx->autotune = value != 0;
+    return TDG_OK;
+  }
+  if (option == TDG_OPT_STAGE_VARIANT) {
+    if (value < -1 || value > 64) return fail(ctx, TDG_E_INVAL, "variant index %lld", (long long)value);
+    ctx->forced_variant = (int)value;
+    return TDG_OK;
+  }
+  return fail(ctx, TDG_E_INVAL, "unknown option %d", option);
+}
+
+const char* tdg_last_variant(tdg_ctx ctx) { return ctx ? ctx->last_variant.c_str() : ""; }
+
 int tdg_profile_enable(tdg_ctx ctx, int32_t on) {
   if (!ctx) return TDG_E_INVAL;
   ctx->prof = on != 0;

@@ -26,6 +26,8 @@ enum WsSlot {
   WS_SOLVER_D,   // eigenvalues / off-diagonal, double [2n]
   WS_SOLVER_I,   // info, permutation, kept eigenvalues
   WS_MISC,       // small scratch (row sums, flags)
+  WS_RHO_N,      // rho(t_n) in sorted instance order, c128 [B][nk][nb][nb]
+  WS_PERM,       // sorted position -> caller's instance index, int [B]
   WS_COUNT
 };
 
@@ -49,6 +51,11 @@ struct tdg_ctx_s {
   bool prof = false;
   std::vector<tdg::EventPair> events[2];
   size_t used[2] = {0, 0};
+  // stage-kernel variant selection (see tdg_set_option)
+  bool autotune = true;
+  int forced_variant = -1;
+  std::vector<std::pair<std::string, int>> tuned;  // shape key -> variant index
+  std::string last_variant;
 };
 
 namespace tdg {

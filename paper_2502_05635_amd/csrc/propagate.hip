@@ -10,20 +10,30 @@
 // builds H_k, evaluates f = -i [H_k, rho_k], advances the RK4 stage and
 // writes the next stage's drho gather.  Launch boundaries are the global
 // synchronisation every stage needs (each stage contracts all of drho).
+// Every global load a block needs is issued before its first use, so a
+// block's lifetime is about one memory round trip plus on-chip work.
 // Observables of rho(t_n) are formed per k in the first stage of step n and
 // reduced over k in fixed order by a separate kernel every few steps.
+//
+// Instances are integrated in order of decreasing length: the host sorts
+// them, so at every step the instances still running are a prefix and the
+// grid covers exactly those.  The working state lives in that sorted order
+// and is scattered back to the caller's order at the end.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <vector>
 
 #include "internal.h"
 
 namespace {
 
-constexpr int THREADS = 256;
-constexpr int WAVES = THREADS / 64;
+constexpr int THREADS = 256;  // dense stage kernel and auxiliary kernels
+constexpr int LR_THREADS = 64; // low-rank stage kernel and projection: one wave per block
 constexpr int NB2_MAX = TDG_NB_MAX * TDG_NB_MAX;
 constexpr int ROWS = 4;  // kernel rows contracted together (shared drho loads)
+constexpr int ZSPLIT_MAX = 4;  // low rank: largest number of projection column slices
+constexpr int PROJ_THREADS = 256;
 constexpr size_t OBS_PART_BUDGET = size_t(64) << 20;
 
 template <typename T>
@@ -47,22 +57,38 @@ __device__ inline double field_value(const tdg_field& f, double t) {
 
 // ---- row dot products ------------------------------------------------------
 // acc_r = sum_j A[r][j] x[j] for r < nvalid (rows lda apart), this thread's
-// share of the columns; the block reduction below completes the sums.
-
+// share of the columns; the block reduction below completes the sums.  The
+// column loop is unrolled UNROLL times with all loads issued before the
+// arithmetic, so each wave keeps UNROLL * (ROWS + 1) 16-byte loads in flight.
+template <int NT, int UNROLL>
 __device__ inline void rows_dot(const float2* __restrict__ A, int64_t lda, int nvalid, int ncols,
                                 const float2* __restrict__ x, float (&ar)[ROWS], float (&ai)[ROWS]) {
   if (((lda | (int64_t)(uintptr_t)A / 8 | (int64_t)(uintptr_t)x / 8) & 1) == 0) {
     // two complex numbers per 16-byte load
     const int npair = ncols >> 1;
     const float4* x4 = reinterpret_cast<const float4*>(x);
-    for (int j = threadIdx.x; j < npair; j += THREADS) {
-      const float4 xv = x4[j];
+    for (int j0 = threadIdx.x; j0 < npair; j0 += NT * UNROLL) {
+      float4 xv[UNROLL], a[UNROLL][ROWS];
 #pragma unroll
-      for (int r = 0; r < ROWS; ++r) {
-        if (r < nvalid) {
-          const float4 a = reinterpret_cast<const float4*>(A + r * lda)[j];
-          ar[r] += a.x * xv.x - a.y * xv.y + a.z * xv.z - a.w * xv.w;
-          ai[r] += a.x * xv.y + a.y * xv.x + a.z * xv.w + a.w * xv.z;
+      for (int u = 0; u < UNROLL; ++u) {
+        const int j = j0 + u * NT;
+        if (j < npair) {
+          xv[u] = x4[j];
+#pragma unroll
+          for (int r = 0; r < ROWS; ++r)
+            if (r < nvalid) a[u][r] = reinterpret_cast<const float4*>(A + r * lda)[j];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        if (j0 + u * NT < npair) {
+#pragma unroll
+          for (int r = 0; r < ROWS; ++r) {
+            if (r < nvalid) {
+              ar[r] += a[u][r].x * xv[u].x - a[u][r].y * xv[u].y + a[u][r].z * xv[u].z - a[u][r].w * xv[u].w;
+              ai[r] += a[u][r].x * xv[u].y + a[u][r].y * xv[u].x + a[u][r].z * xv[u].w + a[u][r].w * xv[u].z;
+            }
+          }
         }
       }
     }
@@ -75,7 +101,7 @@ __device__ inline void rows_dot(const float2* __restrict__ A, int64_t lda, int n
       }
     }
   } else {
-    for (int j = threadIdx.x; j < ncols; j += THREADS) {
+    for (int j = threadIdx.x; j < ncols; j += NT) {
       const float2 xv = x[j];
 #pragma unroll
       for (int r = 0; r < ROWS; ++r) {
@@ -89,16 +115,31 @@ __device__ inline void rows_dot(const float2* __restrict__ A, int64_t lda, int n
   }
 }
 
+template <int NT, int UNROLL>
 __device__ inline void rows_dot(const double2* __restrict__ A, int64_t lda, int nvalid, int ncols,
                                 const double2* __restrict__ x, double (&ar)[ROWS], double (&ai)[ROWS]) {
-  for (int j = threadIdx.x; j < ncols; j += THREADS) {
-    const double2 xv = x[j];
+  for (int j0 = threadIdx.x; j0 < ncols; j0 += NT * UNROLL) {
+    double2 xv[UNROLL], a[UNROLL][ROWS];
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      if (r < nvalid) {
-        const double2 a = A[r * lda + j];
-        ar[r] += a.x * xv.x - a.y * xv.y;
-        ai[r] += a.x * xv.y + a.y * xv.x;
+    for (int u = 0; u < UNROLL; ++u) {
+      const int j = j0 + u * NT;
+      if (j < ncols) {
+        xv[u] = x[j];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+          if (r < nvalid) a[u][r] = A[r * lda + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      if (j0 + u * NT < ncols) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+          if (r < nvalid) {
+            ar[r] += a[u][r].x * xv[u].x - a[u][r].y * xv[u].y;
+            ai[r] += a[u][r].x * xv[u].y + a[u][r].y * xv[u].x;
+          }
+        }
       }
     }
   }
@@ -106,8 +147,9 @@ __device__ inline void rows_dot(const double2* __restrict__ A, int64_t lda, int 
 
 // Sum each thread's ROWS complex partials over the block; out[2r], out[2r+1]
 // receive row r (as double).  Wave shuffles, then a fixed-order sum over waves.
-template <typename T>
+template <typename T, int NT>
 __device__ inline void block_reduce(T (&ar)[ROWS], T (&ai)[ROWS], double* red, double* out) {
+  constexpr int WAVES = NT / 64;
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -136,42 +178,40 @@ struct StageParams {
   const void* A;      // dense: K [N][lda]; low rank: S [N][lda = rank]
   int64_t lda;
   int ncols;          // N (dense) or rank (low rank)
-  const void* vec;    // contracted vector per instance: drho gather (dense) or z (low rank)
+  const void* vec;    // contracted vector per instance: drho gather (dense) or z slices (low rank)
   int64_t vstride;
+  int zsplit;         // low rank: number of projection column slices summed by the stage kernel
+  int64_t zsplit_stride;  // elements between consecutive slices of z
   const void* kdiag;  // low rank: K_diag [N]; dense: NULL
   const void* xcur;   // drho gather of this stage [B][xstride]
   void* xnext;        // drho gather of the next stage
   int64_t xstride;
-  double2* rho_n;     // rho(t_n) [B][nk][nb][nb]
+  double2* rho_n;     // rho(t_n), sorted instance order [B][nk][nb][nb]
   double2* rho_s;     // state of this stage
   double2* acc;       // RK4 sum of stage derivatives
   const double* eps;
   const double2* dip;
   const double2* vel;
-  const tdg_field* fields;
+  const tdg_field* fields;  // sorted instance order
   double* obs_part;   // [slot][B][nk][5] or NULL
   int obs_slot;
   int nk, nb, nv, npair, block, batch;
+  int n_dyn;          // blocks with blockIdx.y < n_dyn integrate; the others only record observables
   int step, stage;
   double dt;
 };
 
-// Per-k observables of s_rho into obs_part (threads t < nb^2 participate).
-__device__ inline void per_k_observables(const StageParams& sp, const double2* s_rho, double (*s_obs)[NB2_MAX],
-                                         const tdg_field& F, int k, int b) {
+// Per-k observables of s_rho (LDS) into obs_part; de, ve are this thread's
+// element of e.d and e.v (threads t < nb^2 participate).
+__device__ inline void obs_partial(const StageParams& sp, const double2* s_rho, double (*s_obs)[NB2_MAX],
+                                   double2 de, double2 ve, int k, int b) {
   const int nb = sp.nb, nb2 = nb * nb, t = threadIdx.x;
   if (t < nb2) {
     const int n = t / nb, m = t % nb;
-    const size_t base = (size_t)k * nb2 + t;
-    const size_t plane = (size_t)sp.nk * nb2;
-    const double2 d = make_double2(F.ex * sp.dip[base].x + F.ey * sp.dip[plane + base].x,
-                                   F.ex * sp.dip[base].y + F.ey * sp.dip[plane + base].y);
-    const double2 v = make_double2(F.ex * sp.vel[base].x + F.ey * sp.vel[plane + base].x,
-                                   F.ex * sp.vel[base].y + F.ey * sp.vel[plane + base].y);
     const double2 rmn = s_rho[m * nb + n];
     const double2 rnm = s_rho[t];
-    s_obs[0][t] = d.x * rmn.x - d.y * rmn.y;  // Re(d_nm rho_mn)
-    s_obs[1][t] = v.x * rmn.x - v.y * rmn.y;
+    s_obs[0][t] = de.x * rmn.x - de.y * rmn.y;  // Re(d_nm rho_mn)
+    s_obs[1][t] = ve.x * rmn.x - ve.y * rmn.y;
     s_obs[2][t] = (n == m && n == sp.nv) ? rnm.x : 0.0;
     s_obs[3][t] = (n == m) ? rnm.x : 0.0;
     const double hx = rnm.x - rmn.x, hy = rnm.y + rmn.y;
@@ -194,14 +234,26 @@ __device__ inline void per_k_observables(const StageParams& sp, const double2* s
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(THREADS) stage_kernel(StageParams sp) {
+__device__ inline double2 proj_e(const tdg_field& F, double2 a, double2 b) {
+  return make_double2(F.ex * a.x + F.ey * b.x, F.ex * a.y + F.ey * b.y);
+}
+
+// Stage kernel: one block per (k point, instance).  LOWRANK selects the
+// low-rank expansion (rows of S against z, plus K_diag o x); it is a template
+// parameter so the two paths are distinct kernels in traces.  NT threads per
+// block (a k point's rows are split over the block's columns), U-fold unrolled
+// row streams, WPE = minimum waves per SIMD requested from the compiler.
+template <typename T, bool LOWRANK, int NT, int U, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+stage_kernel(StageParams sp) {
   using C = typename Cx<T>::type;
+  constexpr int WAVES = NT / 64;
   const int k = blockIdx.x, b = blockIdx.y;
-  const tdg_field F = sp.fields[b];
-  const int64_t nsb = (int64_t)F.nsteps;
-  if (sp.step > nsb) return;                     // instance finished
-  if (sp.stage != 0 && sp.step >= nsb) return;
+  const bool dyn = b < sp.n_dyn;
+  const int nb = sp.nb, nb2 = nb * nb, P = sp.npair, t = threadIdx.x;
+  const size_t kb = ((size_t)b * sp.nk + k) * nb2;
+  const size_t base = (size_t)k * nb2 + t;
+  const size_t plane = (size_t)sp.nk * nb2;
 
   __shared__ double2 s_rho[NB2_MAX];
   __shared__ double2 s_h[NB2_MAX];
@@ -209,29 +261,97 @@ __global__ void __launch_bounds__(THREADS) stage_kernel(StageParams sp) {
   __shared__ double s_red[WAVES * 2 * ROWS];
   __shared__ double s_obs[5][NB2_MAX];
 
-  const int nb = sp.nb, nb2 = nb * nb, P = sp.npair, t = threadIdx.x;
-  const size_t kb = ((size_t)b * sp.nk + k) * nb2;
-  if (t < nb2) s_rho[t] = sp.rho_s[kb + t];
-  __syncthreads();
-  if (sp.stage == 0 && sp.obs_part) per_k_observables(sp, s_rho, s_obs, F, k, b);
-  if (sp.step == nsb) return;                    // final time: observables only
-
-  // ---- contraction: y_p = sum_j A[k P + p][j] vec[j] ----------------------
+  // ---- loads: the low-rank kernel issues every load of the block before any
+  // use (its lifetime is latency-bound); the dense kernel loads the per-k
+  // state after its row stream (bandwidth-bound, registers kept for the stream)
+  const tdg_field F = sp.fields[b];
+  double2 r_s = make_double2(0.0, 0.0), r_n = r_s, r_acc = r_s, d0 = r_s, d1 = r_s, v0 = r_s, v1 = r_s;
+  double e_nn = 0.0;
+  auto load_state = [&]() {
+    if (t < nb2) {
+      r_s = sp.rho_s[kb + t];
+      d0 = sp.dip[base];
+      d1 = sp.dip[plane + base];
+      if (sp.stage == 0) {
+        v0 = sp.vel[base];
+        v1 = sp.vel[plane + base];
+      }
+      if (dyn) {
+        r_n = sp.rho_n[kb + t];
+        if (sp.stage != 0) r_acc = sp.acc[kb + t];
+        if (t / nb == t % nb) e_nn = sp.eps[(size_t)k * nb + t / nb];
+      }
+    }
+  };
+  if (LOWRANK) load_state();
   const C* A = reinterpret_cast<const C*>(sp.A);
   const C* vec = reinterpret_cast<const C*>(sp.vec) + (size_t)b * sp.vstride;
-  for (int r0 = 0; r0 < P; r0 += ROWS) {
-    const int nvalid = min(ROWS, P - r0);
-    T ar[ROWS], ai[ROWS];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) ar[r] = ai[r] = (T)0;
-    rows_dot(A + ((int64_t)k * P + r0) * sp.lda, sp.lda, nvalid, sp.ncols, vec, ar, ai);
-    block_reduce<T>(ar, ai, s_red, s_y + 2 * r0);
-  }
   const C* xcur = reinterpret_cast<const C*>(sp.xcur) + (size_t)b * sp.xstride;
-  if (sp.kdiag && t < P) {
-    const C kd = reinterpret_cast<const C*>(sp.kdiag)[(size_t)k * P + t];
-    const C xv = xcur[(size_t)k * P + t];
-    const T re = kd.x * xv.x - kd.y * xv.y, im = kd.x * xv.y + kd.y * xv.x;
+  C kd_t, x_t;
+  if (LOWRANK && dyn && t < P) {
+    kd_t = reinterpret_cast<const C*>(sp.kdiag)[(size_t)k * P + t];
+    x_t = xcur[(size_t)k * P + t];
+  }
+
+  // ---- contraction: y_p = sum_j A[k P + p][j] vec[j] ----------------------
+  if (dyn) {
+    for (int r0 = 0; r0 < P; r0 += ROWS) {
+      const int nvalid = min(ROWS, P - r0);
+      T ar[ROWS], ai[ROWS];
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) ar[r] = ai[r] = (T)0;
+      const C* Ar = A + ((int64_t)k * P + r0) * sp.lda;
+      if (LOWRANK) {
+        // rows of S against z = sum of the projection's column slices (at most
+        // ZSPLIT_MAX); each thread sums the slices of its own columns.  Two
+        // columns per pass with every load of the pass issued first.
+        for (int j0 = t; j0 < sp.ncols; j0 += 2 * NT) {
+          C zv[2][ZSPLIT_MAX], av[2][ROWS];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int j = j0 + u * NT;
+            if (j < sp.ncols) {
+#pragma unroll
+              for (int q = 0; q < ZSPLIT_MAX; ++q)
+                if (q < sp.zsplit) zv[u][q] = vec[(size_t)q * sp.zsplit_stride + j];
+#pragma unroll
+              for (int r = 0; r < ROWS; ++r)
+                if (r < nvalid) av[u][r] = Ar[r * sp.lda + j];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (j0 + u * NT < sp.ncols) {
+              T zr = (T)0, zi = (T)0;
+#pragma unroll
+              for (int q = 0; q < ZSPLIT_MAX; ++q)
+                if (q < sp.zsplit) {
+                  zr += zv[u][q].x;
+                  zi += zv[u][q].y;
+                }
+#pragma unroll
+              for (int r = 0; r < ROWS; ++r) {
+                if (r < nvalid) {
+                  ar[r] += av[u][r].x * zr - av[u][r].y * zi;
+                  ai[r] += av[u][r].x * zi + av[u][r].y * zr;
+                }
+              }
+            }
+          }
+        }
+      } else {
+        rows_dot<NT, U>(Ar, sp.lda, nvalid, sp.ncols, vec, ar, ai);
+      }
+      block_reduce<T, NT>(ar, ai, s_red, s_y + 2 * r0);
+    }
+  }
+  if (!LOWRANK) load_state();
+  if (t < nb2) s_rho[t] = r_s;
+  __syncthreads();
+  if (sp.stage == 0 && sp.obs_part) obs_partial(sp, s_rho, s_obs, proj_e(F, d0, d1), proj_e(F, v0, v1), k, b);
+  if (!dyn) return;                              // final time of this instance: observables only
+  if (LOWRANK && t < P) {
+    const T re = kd_t.x * x_t.x - kd_t.y * x_t.y, im = kd_t.x * x_t.y + kd_t.y * x_t.x;
     s_y[2 * t] += (double)re;
     s_y[2 * t + 1] += (double)im;
   }
@@ -253,11 +373,9 @@ __global__ void __launch_bounds__(THREADS) stage_kernel(StageParams sp) {
       const int p = (m - sp.nv) * sp.nv + n;
       ds = make_double2(s_y[2 * p], -s_y[2 * p + 1]);
     }
-    const size_t base = (size_t)k * nb2 + t;
-    const size_t plane = (size_t)sp.nk * nb2;
-    const double2 d0 = sp.dip[base], d1 = sp.dip[plane + base];
-    double2 h = make_double2(ds.x - ef * (F.ex * d0.x + F.ey * d1.x), ds.y - ef * (F.ex * d0.y + F.ey * d1.y));
-    if (n == m) h.x += sp.eps[(size_t)k * nb + n];
+    const double2 de = proj_e(F, d0, d1);
+    double2 h = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
+    if (n == m) h.x += e_nn;
     s_h[t] = h;
   }
   __syncthreads();
@@ -274,23 +392,19 @@ __global__ void __launch_bounds__(THREADS) stage_kernel(StageParams sp) {
     }
     const double2 f = make_double2(c.y, -c.x);  // -i c
     const size_t g = kb + t;
-    const double2 r0 = sp.rho_n[g];
     double2 next;
     if (sp.stage == 0) {
       sp.acc[g] = f;
-      next = make_double2(r0.x + 0.5 * sp.dt * f.x, r0.y + 0.5 * sp.dt * f.y);
+      next = make_double2(r_n.x + 0.5 * sp.dt * f.x, r_n.y + 0.5 * sp.dt * f.y);
     } else if (sp.stage == 1) {
-      const double2 a = sp.acc[g];
-      sp.acc[g] = make_double2(a.x + 2.0 * f.x, a.y + 2.0 * f.y);
-      next = make_double2(r0.x + 0.5 * sp.dt * f.x, r0.y + 0.5 * sp.dt * f.y);
+      sp.acc[g] = make_double2(r_acc.x + 2.0 * f.x, r_acc.y + 2.0 * f.y);
+      next = make_double2(r_n.x + 0.5 * sp.dt * f.x, r_n.y + 0.5 * sp.dt * f.y);
     } else if (sp.stage == 2) {
-      const double2 a = sp.acc[g];
-      sp.acc[g] = make_double2(a.x + 2.0 * f.x, a.y + 2.0 * f.y);
-      next = make_double2(r0.x + sp.dt * f.x, r0.y + sp.dt * f.y);
+      sp.acc[g] = make_double2(r_acc.x + 2.0 * f.x, r_acc.y + 2.0 * f.y);
+      next = make_double2(r_n.x + sp.dt * f.x, r_n.y + sp.dt * f.y);
     } else {
-      const double2 a = sp.acc[g];
       const double w = sp.dt / 6.0;
-      next = make_double2(r0.x + w * (a.x + f.x), r0.y + w * (a.y + f.y));
+      next = make_double2(r_n.x + w * (r_acc.x + f.x), r_n.y + w * (r_acc.y + f.y));
       sp.rho_n[g] = next;
     }
     sp.rho_s[g] = next;
@@ -309,43 +423,48 @@ __global__ void __launch_bounds__(THREADS) stage_kernel(StageParams sp) {
   }
 }
 
-// Low-rank projection z_j = sum_i W[j][i] x_i (W = V^H), ROWS rows per block.
+// Low-rank projection z_j = sum_i W[j][i] x_i (W = V^H): block (g, q, b) takes
+// rows ROWS*g .. ROWS*g + ROWS - 1 over the q-th of zsplit column slices and
+// writes its partial to zpart[q][b][j]; the stage kernel sums the slices.
 template <typename T>
-__global__ void __launch_bounds__(THREADS) project_kernel(const void* __restrict__ W, int64_t n, int rank,
-                                                          const void* __restrict__ x, int64_t xstride, void* z,
-                                                          int64_t zstride, const tdg_field* fields, int step) {
+__global__ void __launch_bounds__(PROJ_THREADS) project_kernel(const void* __restrict__ W, int64_t n, int rank,
+                                                     const void* __restrict__ x, int64_t xstride, void* zpart,
+                                                     int64_t zstride, int64_t slice, int64_t split_stride) {
   using C = typename Cx<T>::type;
-  const int b = blockIdx.y;
-  if (step >= (int64_t)fields[b].nsteps) return;
-  __shared__ double s_red[WAVES * 2 * ROWS];
+  const int q = blockIdx.y, b = blockIdx.z;
+  __shared__ double s_red[PROJ_THREADS / 64 * 2 * ROWS];
   __shared__ double s_out[2 * ROWS];
   const int r0 = blockIdx.x * ROWS;
   const int nvalid = min(ROWS, rank - r0);
+  const int64_t c0 = (int64_t)q * slice;
+  const int ncols = (int)max<int64_t>(0, min<int64_t>(slice, n - c0));
   T ar[ROWS], ai[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) ar[r] = ai[r] = (T)0;
-  rows_dot(reinterpret_cast<const C*>(W) + (int64_t)r0 * n, n, nvalid, (int)n,
-           reinterpret_cast<const C*>(x) + (size_t)b * xstride, ar, ai);
-  block_reduce<T>(ar, ai, s_red, s_out);
+  rows_dot<PROJ_THREADS, 8>(reinterpret_cast<const C*>(W) + (int64_t)r0 * n + c0, n, nvalid, ncols,
+                            reinterpret_cast<const C*>(x) + (size_t)b * xstride + c0, ar, ai);
+  block_reduce<T, PROJ_THREADS>(ar, ai, s_red, s_out);
   if (threadIdx.x < nvalid) {
     C v;
     v.x = (T)s_out[2 * threadIdx.x];
     v.y = (T)s_out[2 * threadIdx.x + 1];
-    reinterpret_cast<C*>(z)[(size_t)b * zstride + r0 + threadIdx.x] = v;
+    reinterpret_cast<C*>(zpart)[(size_t)q * split_stride + (size_t)b * zstride + r0 + threadIdx.x] = v;
   }
 }
 
-// rho_n <- rho_eq (optional), rho_s <- rho_n, x <- (rho_n - rho_eq)[pairs].
+// Working state from the caller's rho: rho_n <- rho_eq or rho[perm[b]],
+// rho_s <- rho_n, x <- (rho_n - rho_eq)[pairs]; b is the sorted position.
 template <typename T>
-__global__ void init_kernel(double2* rho_n, double2* rho_s, void* x, int64_t xstride, int nk, int nb, int nv,
-                            int npair, int block, int init_eq) {
+__global__ void init_kernel(const double2* __restrict__ rho_in, const int* __restrict__ perm, double2* rho_n,
+                            double2* rho_s, void* x, int64_t xstride, int nk, int nb, int nv, int npair, int block,
+                            int init_eq) {
   using C = typename Cx<T>::type;
   const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x, nb2 = nb * nb;
   if (t >= nb2) return;
   const int n = t / nb, m = t % nb;
   const size_t g = ((size_t)b * nk + k) * nb2 + t;
   const double occ = (n == m && n < nv) ? 1.0 : 0.0;
-  double2 r = init_eq ? make_double2(occ, 0.0) : rho_n[g];
+  const double2 r = init_eq ? make_double2(occ, 0.0) : rho_in[((size_t)perm[b] * nk + k) * nb2 + t];
   rho_n[g] = r;
   rho_s[g] = r;
   int p = -1;
@@ -361,21 +480,38 @@ __global__ void init_kernel(double2* rho_n, double2* rho_s, void* x, int64_t xst
   }
 }
 
-// Observables of an arbitrary state (tdg_observables).
+// rho[perm[b]] <- rho_n[b]
+__global__ void finish_kernel(const double2* __restrict__ rho_n, const int* __restrict__ perm, double2* rho_out,
+                              int nk, int nb2) {
+  const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+  if (t >= nb2) return;
+  rho_out[((size_t)perm[b] * nk + k) * nb2 + t] = rho_n[((size_t)b * nk + k) * nb2 + t];
+}
+
+// Observables of an arbitrary state (tdg_observables), caller's order.
 __global__ void obs_state_kernel(StageParams sp) {
-  const int k = blockIdx.x, b = blockIdx.y;
+  const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
   __shared__ double2 s_rho[NB2_MAX];
   __shared__ double s_obs[5][NB2_MAX];
   const int nb2 = sp.nb * sp.nb;
-  if (threadIdx.x < nb2) s_rho[threadIdx.x] = sp.rho_s[((size_t)b * sp.nk + k) * nb2 + threadIdx.x];
+  const tdg_field F = sp.fields[b];
+  double2 de = make_double2(0.0, 0.0), ve = de;
+  if (t < nb2) {
+    const size_t base = (size_t)k * nb2 + t, plane = (size_t)sp.nk * nb2;
+    s_rho[t] = sp.rho_s[((size_t)b * sp.nk + k) * nb2 + t];
+    de = proj_e(F, sp.dip[base], sp.dip[plane + base]);
+    ve = proj_e(F, sp.vel[base], sp.vel[plane + base]);
+  }
   __syncthreads();
-  per_k_observables(sp, s_rho, s_obs, sp.fields[b], k, b);
+  obs_partial(sp, s_rho, s_obs, de, ve, k, b);
 }
 
 // Fixed-order reduction of per-k observables: sums (P, J, occ) / nk and
-// maxima (tr, herm), for steps step0 .. step0 + gridDim.x - 1.
+// maxima (tr, herm), for steps step0 .. step0 + gridDim.x - 1 of the sorted
+// instance b, written to row perm[b] (or to out5[b] for tdg_observables).
 __global__ void __launch_bounds__(THREADS) obs_reduce_kernel(const double* __restrict__ part, int nk, int batch,
-                                                             int step0, const tdg_field* fields, tdg_obs obs,
+                                                             int step0, const tdg_field* fields,
+                                                             const int* __restrict__ perm, tdg_obs obs,
                                                              double* out5) {
   const int slot = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
   const int step = step0 + slot;
@@ -413,7 +549,7 @@ __global__ void __launch_bounds__(THREADS) obs_reduce_kernel(const double* __res
       o[3] = s[3][0];
       o[4] = s[4][0];
     } else {
-      const size_t i = (size_t)b * obs.stride + step;
+      const size_t i = (size_t)perm[b] * obs.stride + step;
       obs.P[i] = s[0][0] * inv;
       obs.J[i] = s[1][0] * inv;
       obs.occ[i] = s[2][0] * inv;
@@ -445,15 +581,54 @@ static int validate_fields(tdg_ctx ctx, const tdg_field* fields, int batch, int6
   return TDG_OK;
 }
 
-static int upload_fields(tdg_ctx ctx, const tdg_field* fields, int batch, tdg_field** dev) {
-  void* p = nullptr;
-  TDG_TRY(ws_reserve(ctx, WS_FIELDS, sizeof(tdg_field) * batch, &p));
-  TDG_TRY(hip_check(ctx, hipMemcpyAsync(p, fields, sizeof(tdg_field) * batch, hipMemcpyHostToDevice, ctx->stream),
-                    "field upload"));
-  // the host array need not outlive this call
-  TDG_TRY(hip_check(ctx, hipStreamSynchronize(ctx->stream), "field upload sync"));
-  *dev = (tdg_field*)p;
-  return TDG_OK;
+// Copy a host array into a workspace slot (synchronously: the host array
+// need not outlive the call).
+static int upload(tdg_ctx ctx, WsSlot slot, const void* src, size_t bytes, void** dev) {
+  TDG_TRY(ws_reserve(ctx, slot, bytes, dev));
+  TDG_TRY(hip_check(ctx, hipMemcpyAsync(*dev, src, bytes, hipMemcpyHostToDevice, ctx->stream), "upload"));
+  return hip_check(ctx, hipStreamSynchronize(ctx->stream), "upload sync");
+}
+
+// ---- stage-kernel variants -------------------------------------------------
+using StageLaunch = void (*)(dim3, size_t, hipStream_t, const StageParams&);
+
+template <typename T, bool LR, int NT, int U, int WPE>
+static void launch_stage(dim3 grid, size_t lds, hipStream_t stream, const StageParams& sp) {
+  hipLaunchKernelGGL((stage_kernel<T, LR, NT, U, WPE>), grid, dim3(NT), lds, stream, sp);
+}
+
+struct Variant {
+  const char* name;
+  StageLaunch fn;
+};
+
+static const Variant kDenseF32[] = {
+    {"dense_f32_nt256_u2_w6", launch_stage<float, false, 256, 2, 6>},
+    {"dense_f32_nt256_u4_w4", launch_stage<float, false, 256, 4, 4>},
+    {"dense_f32_nt256_u1_w8", launch_stage<float, false, 256, 1, 8>},
+    {"dense_f32_nt128_u4_w4", launch_stage<float, false, 128, 4, 4>},
+    {"dense_f32_nt512_u2_w4", launch_stage<float, false, 512, 2, 4>},
+};
+static const Variant kDenseF64[] = {
+    {"dense_f64_nt256_u2_w4", launch_stage<double, false, 256, 2, 4>},
+    {"dense_f64_nt256_u1_w6", launch_stage<double, false, 256, 1, 6>},
+    {"dense_f64_nt128_u2_w4", launch_stage<double, false, 128, 2, 4>},
+};
+static const Variant kLowF32[] = {
+    {"lowrank_f32_nt64", launch_stage<float, true, 64, 1, 2>},
+    {"lowrank_f32_nt128", launch_stage<float, true, 128, 1, 2>},
+    {"lowrank_f32_nt256", launch_stage<float, true, 256, 1, 2>},
+};
+static const Variant kLowF64[] = {
+    {"lowrank_f64_nt64", launch_stage<double, true, 64, 1, 2>},
+    {"lowrank_f64_nt128", launch_stage<double, true, 128, 1, 2>},
+    {"lowrank_f64_nt256", launch_stage<double, true, 256, 1, 2>},
+};
+
+template <size_t N>
+static void table(const Variant (&v)[N], const Variant*& out, int& count) {
+  out = v;
+  count = (int)N;
 }
 
 extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model, const tdg_field* fields,
@@ -467,8 +642,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const int nk = model->nk1 * model->nk2;
   const int64_t n = (int64_t)nk * npair;
   if (op->n != n) return fail(ctx, TDG_E_INVAL, "operator n = %lld, model gives N = %lld", (long long)op->n, (long long)n);
-  if (n > (int64_t)1 << 30) return fail(ctx, TDG_E_UNSUPPORTED, "N = %lld too large", (long long)n);
+  if (n > ((int64_t)1 << 30)) return fail(ctx, TDG_E_UNSUPPORTED, "N = %lld too large", (long long)n);
   const size_t elt = op->dtype == TDG_C128 ? 16 : 8;
+  const bool lowrank = op->kind == TDG_OP_LOWRANK;
   const void* A = nullptr;
   int64_t lda = 0;
   int ncols = 0;
@@ -478,7 +654,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     A = op->K;
     lda = op->ld;
     ncols = (int)n;
-  } else if (op->kind == TDG_OP_LOWRANK) {
+  } else if (lowrank) {
     if (!op->kdiag || !op->us || !op->w) return fail(ctx, TDG_E_INVAL, "low-rank operator with NULL factor");
     if (op->rank < 1 || op->rank > n) return fail(ctx, TDG_E_INVAL, "rank %lld outside [1, N]", (long long)op->rank);
     A = op->us;
@@ -499,45 +675,72 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
                 (long long)(max_steps + 1));
   TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
 
+  // instances by decreasing length: the running ones are always a prefix
+  std::vector<int> perm(batch);
+  for (int i = 0; i < batch; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return fields[x].nsteps > fields[y].nsteps; });
+  std::vector<tdg_field> sorted(batch);
+  std::vector<int64_t> len(batch);
+  for (int i = 0; i < batch; ++i) {
+    sorted[i] = fields[perm[i]];
+    len[i] = (int64_t)sorted[i].nsteps;
+  }
+
   const int nb2 = model->nb * model->nb;
   const size_t state_bytes = (size_t)batch * nk * nb2 * sizeof(double2);
   const int64_t xstride = (n + 1) & ~int64_t(1);
   const int64_t zstride = (op->rank + 1) & ~int64_t(1);
-  void *rho_s, *acc, *x0, *x1, *z = nullptr, *part;
+  void *rho_n, *rho_s, *acc, *x0, *x1, *z = nullptr, *part, *dperm, *dfields;
+  TDG_TRY(ws_reserve(ctx, WS_RHO_N, state_bytes, &rho_n));
   TDG_TRY(ws_reserve(ctx, WS_RHO_S, state_bytes, &rho_s));
   TDG_TRY(ws_reserve(ctx, WS_ACC, state_bytes, &acc));
   TDG_TRY(ws_reserve(ctx, WS_X0, (size_t)batch * xstride * elt, &x0));
   TDG_TRY(ws_reserve(ctx, WS_X1, (size_t)batch * xstride * elt, &x1));
-  if (op->kind == TDG_OP_LOWRANK) TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)batch * zstride * elt, &z));
+  // low rank: the projection is split over zsplit column slices (at least
+  // about 256 blocks per instance, at most ZSPLIT_MAX slices); the stage
+  // kernel sums the slices it reads
+  int zsplit = 1;
+  int64_t zslice = n;
+  if (lowrank) {
+    const int64_t groups = (op->rank + ROWS - 1) / ROWS;
+    zsplit = (int)std::min<int64_t>(ZSPLIT_MAX, std::max<int64_t>(1, (256 + groups - 1) / groups));
+    zslice = ((n + zsplit - 1) / zsplit + 1) & ~int64_t(1);
+    zsplit = (int)((n + zslice - 1) / zslice);
+    TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)zsplit * batch * zstride * elt, &z));
+  }
   const size_t part_per_step = (size_t)batch * nk * 5 * sizeof(double);
-  int chunk = (int)std::min<size_t>(256, std::max<size_t>(1, OBS_PART_BUDGET / part_per_step));
+  const int chunk = (int)std::min<size_t>(256, std::max<size_t>(1, OBS_PART_BUDGET / part_per_step));
   TDG_TRY(ws_reserve(ctx, WS_OBS_PART, part_per_step * chunk, &part));
-  tdg_field* dfields = nullptr;
-  TDG_TRY(upload_fields(ctx, fields, batch, &dfields));
+  TDG_TRY(upload(ctx, WS_FIELDS, sorted.data(), sizeof(tdg_field) * batch, &dfields));
+  TDG_TRY(upload(ctx, WS_PERM, perm.data(), sizeof(int) * batch, &dperm));
 
-  const dim3 kgrid(nk, batch);
   const int init_threads = ((nb2 + 63) / 64) * 64;
-  if (op->dtype == TDG_C128)
-    hipLaunchKernelGGL(init_kernel<double>, kgrid, dim3(init_threads), 0, ctx->stream, (double2*)rho, (double2*)rho_s,
-                       x0, xstride, nk, model->nb, model->nv, npair, op->block, init_eq);
-  else
-    hipLaunchKernelGGL(init_kernel<float>, kgrid, dim3(init_threads), 0, ctx->stream, (double2*)rho, (double2*)rho_s,
-                       x0, xstride, nk, model->nb, model->nv, npair, op->block, init_eq);
-  TDG_TRY(launch_check(ctx, "init launch"));
+  auto init = [&]() {
+    if (op->dtype == TDG_C128)
+      hipLaunchKernelGGL(init_kernel<double>, dim3(nk, batch), dim3(init_threads), 0, ctx->stream,
+                         (const double2*)rho, (const int*)dperm, (double2*)rho_n, (double2*)rho_s, x0, xstride, nk,
+                         model->nb, model->nv, npair, op->block, init_eq);
+    else
+      hipLaunchKernelGGL(init_kernel<float>, dim3(nk, batch), dim3(init_threads), 0, ctx->stream,
+                         (const double2*)rho, (const int*)dperm, (double2*)rho_n, (double2*)rho_s, x0, xstride, nk,
+                         model->nb, model->nv, npair, op->block, init_eq);
+    return launch_check(ctx, "init launch");
+  };
+  TDG_TRY(init());
 
-  StageParams sp;
+  StageParams sp = {};
   sp.A = A;
   sp.lda = lda;
   sp.ncols = ncols;
-  sp.kdiag = op->kind == TDG_OP_LOWRANK ? op->kdiag : nullptr;
+  sp.kdiag = lowrank ? op->kdiag : nullptr;
   sp.xstride = xstride;
-  sp.rho_n = (double2*)rho;
+  sp.rho_n = (double2*)rho_n;
   sp.rho_s = (double2*)rho_s;
   sp.acc = (double2*)acc;
   sp.eps = model->eps;
   sp.dip = (const double2*)model->dip;
   sp.vel = (const double2*)model->vel;
-  sp.fields = dfields;
+  sp.fields = (const tdg_field*)dfields;
   sp.obs_part = (double*)part;
   sp.nk = nk;
   sp.nb = model->nb;
@@ -546,50 +749,133 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   sp.block = op->block;
   sp.batch = batch;
   sp.dt = dt;
-  tdg_obs ob = *obs;
+  const int64_t split_stride = (int64_t)batch * zstride;
+  sp.zsplit = zsplit;
+  sp.zsplit_stride = split_stride;
+  const unsigned groups = (unsigned)((op->rank + ROWS - 1) / ROWS);
 
+  auto project = [&](const void* xin, int active) {
+    const dim3 g(groups, zsplit, active);
+    if (op->dtype == TDG_C128)
+      hipLaunchKernelGGL(project_kernel<double>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, n, (int)op->rank, xin, xstride,
+                         z, zstride, zslice, split_stride);
+    else
+      hipLaunchKernelGGL(project_kernel<float>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, n, (int)op->rank, xin, xstride,
+                         z, zstride, zslice, split_stride);
+  };
+  // instances with len > step integrate; those with len == step only record
+  auto count_gt = [&](int64_t step) {
+    int c = 0;
+    while (c < batch && len[c] > step) ++c;
+    return c;
+  };
+  auto count_ge = [&](int64_t step) {
+    int c = 0;
+    while (c < batch && len[c] >= step) ++c;
+    return c;
+  };
+
+  // ---- variant choice ------------------------------------------------------
+  const Variant* vt = nullptr;
+  int nvar = 0;
+  if (op->dtype == TDG_C128)
+    lowrank ? table(kLowF64, vt, nvar) : table(kDenseF64, vt, nvar);
+  else
+    lowrank ? table(kLowF32, vt, nvar) : table(kDenseF32, vt, nvar);
+  int var = 0;
+  if (ctx->forced_variant >= 0) {
+    if (ctx->forced_variant >= nvar)
+      return fail(ctx, TDG_E_INVAL, "variant %d of %d for this operator", ctx->forced_variant, nvar);
+    var = ctx->forced_variant;
+  } else if (ctx->autotune && max_steps > 0) {
+    char key[160];
+    snprintf(key, sizeof(key), "%d/%d/%lld/%d/%d/%lld/%d", op->kind, op->dtype, (long long)n, nk, batch,
+             (long long)op->rank, op->block);
+    int found = -1;
+    for (auto& kv : ctx->tuned)
+      if (kv.first == key) found = kv.second;
+    if (found >= 0) {
+      var = found;
+    } else {
+      // time each variant on stage 0 of step 0: it reads rho and writes only
+      // the stage state, accumulator and next gather, which init restores
+      hipEvent_t ea, eb;
+      TDG_TRY(hip_check(ctx, hipEventCreate(&ea), "tuner event"));
+      TDG_TRY(hip_check(ctx, hipEventCreate(&eb), "tuner event"));
+      const int dyn0 = count_gt(0);
+      sp.step = 0;
+      sp.stage = 0;
+      sp.obs_slot = 0;
+      sp.n_dyn = dyn0;
+      sp.xcur = x0;
+      sp.xnext = x1;
+      sp.vec = lowrank ? z : x0;
+      sp.vstride = lowrank ? zstride : xstride;
+      if (lowrank) project(x0, dyn0);
+      const dim3 g(nk, dyn0);
+      float best = 1e30f;
+      for (int v = 0; v < nvar; ++v) {
+        vt[v].fn(g, 0, ctx->stream, sp);  // warm-up
+        hipEventRecord(ea, ctx->stream);
+        for (int rep = 0; rep < 3; ++rep) vt[v].fn(g, 0, ctx->stream, sp);
+        hipEventRecord(eb, ctx->stream);
+        TDG_TRY(launch_check(ctx, "tuner launch"));
+        TDG_TRY(hip_check(ctx, hipEventSynchronize(eb), "tuner sync"));
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ea, eb);
+        if (ms < best) {
+          best = ms;
+          var = v;
+        }
+      }
+      hipEventDestroy(ea);
+      hipEventDestroy(eb);
+      ctx->tuned.emplace_back(key, var);
+      TDG_TRY(init());  // the caller's rho was only read
+    }
+  }
+  ctx->last_variant = vt[var].name;
+  const StageLaunch stage_fn = vt[var].fn;
+
+  tdg_obs ob = *obs;
   void* xc = x0;
   void* xn = x1;
   int slot = 0;
   int64_t chunk_start = 0;
-  const dim3 pgrid((unsigned)((op->rank + ROWS - 1) / ROWS), batch);
   for (int64_t step = 0; step <= max_steps; ++step) {
+    const int n_obs = count_ge(step), n_dyn = count_gt(step);
+    sp.n_dyn = n_dyn;
     for (int s = 0; s < 4; ++s) {
-      if (step == max_steps && s > 0) break;
-      if (op->kind == TDG_OP_LOWRANK && step < max_steps) {
+      const int active = s == 0 ? n_obs : n_dyn;
+      if (active == 0) break;
+      if (lowrank && n_dyn > 0) {
         prof_begin(ctx, TDG_KCLASS_PROJECT);
-        if (op->dtype == TDG_C128)
-          hipLaunchKernelGGL(project_kernel<double>, pgrid, dim3(THREADS), 0, ctx->stream, op->w, n, (int)op->rank,
-                             xc, xstride, z, zstride, dfields, (int)step);
-        else
-          hipLaunchKernelGGL(project_kernel<float>, pgrid, dim3(THREADS), 0, ctx->stream, op->w, n, (int)op->rank,
-                             xc, xstride, z, zstride, dfields, (int)step);
+        project(xc, n_dyn);
         prof_end(ctx, TDG_KCLASS_PROJECT);
       }
-      sp.vec = op->kind == TDG_OP_LOWRANK ? z : xc;
-      sp.vstride = op->kind == TDG_OP_LOWRANK ? zstride : xstride;
+      sp.vec = lowrank ? z : xc;
+      sp.vstride = lowrank ? zstride : xstride;
       sp.xcur = xc;
       sp.xnext = xn;
       sp.step = (int)step;
       sp.stage = s;
       sp.obs_slot = slot;
       prof_begin(ctx, TDG_KCLASS_STAGE);
-      if (op->dtype == TDG_C128)
-        hipLaunchKernelGGL(stage_kernel<double>, kgrid, dim3(THREADS), 0, ctx->stream, sp);
-      else
-        hipLaunchKernelGGL(stage_kernel<float>, kgrid, dim3(THREADS), 0, ctx->stream, sp);
+      stage_fn(dim3(nk, active), 0, ctx->stream, sp);
       prof_end(ctx, TDG_KCLASS_STAGE);
       std::swap(xc, xn);
     }
     ++slot;
     if (slot == chunk || step == max_steps) {
       hipLaunchKernelGGL(obs_reduce_kernel, dim3(slot, batch), dim3(THREADS), 0, ctx->stream, (const double*)part, nk,
-                         batch, (int)chunk_start, dfields, ob, (double*)nullptr);
+                         batch, (int)chunk_start, (const tdg_field*)dfields, (const int*)dperm, ob, (double*)nullptr);
       chunk_start += slot;
       slot = 0;
     }
     if ((step & 63) == 0) TDG_TRY(launch_check(ctx, "propagation launch"));
   }
+  hipLaunchKernelGGL(finish_kernel, dim3(nk, batch), dim3(init_threads), 0, ctx->stream, (const double2*)rho_n,
+                     (const int*)dperm, (double2*)rho, nk, nb2);
   return launch_check(ctx, "propagation launch");
 }
 
@@ -602,15 +888,14 @@ extern "C" int tdg_observables(tdg_ctx ctx, const tdg_model* model, const void* 
   TDG_TRY(validate_fields(ctx, fields, batch, &mx));
   TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
   const int nk = model->nk1 * model->nk2;
-  void* part = nullptr;
+  void *part = nullptr, *dfields = nullptr;
   TDG_TRY(ws_reserve(ctx, WS_OBS_PART, (size_t)batch * nk * 5 * sizeof(double), &part));
-  tdg_field* dfields = nullptr;
-  TDG_TRY(upload_fields(ctx, fields, batch, &dfields));
+  TDG_TRY(upload(ctx, WS_FIELDS, fields, sizeof(tdg_field) * batch, &dfields));
   StageParams sp = {};
   sp.rho_s = (double2*)rho;
   sp.dip = (const double2*)model->dip;
   sp.vel = (const double2*)model->vel;
-  sp.fields = dfields;
+  sp.fields = (const tdg_field*)dfields;
   sp.obs_part = (double*)part;
   sp.obs_slot = 0;
   sp.nk = nk;
@@ -621,7 +906,7 @@ extern "C" int tdg_observables(tdg_ctx ctx, const tdg_model* model, const void* 
   TDG_TRY(launch_check(ctx, "observables launch"));
   tdg_obs none = {};
   hipLaunchKernelGGL(obs_reduce_kernel, dim3(1, batch), dim3(THREADS), 0, ctx->stream, (const double*)part, nk, batch,
-                     0, dfields, none, out);
+                     0, (const tdg_field*)dfields, (const int*)nullptr, none, out);
   return launch_check(ctx, "observables reduce launch");
 }
 

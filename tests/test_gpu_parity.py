@@ -248,3 +248,50 @@ def test_check_numeric_reports_nan(P, ctx, tb4_6):
     with pytest.raises(P.TdgError) as e:
         ctx.check_numeric(res, f)
     assert e.value.code == -5 and "step 0" in str(e.value)
+
+
+# --- full-size four-band workload against the stored FP64 oracle series -------
+# The strong-field run is chaotic after the pulse peak: a 6e-8 perturbation of
+# K grows to ~3e-4 in P(t) by the end (recorded with the stored series), so the
+# FP32 bound 1e-4 is applied over the first half of the run (t <= t0), where
+# trajectories are still predictable; the full-run error is printed.
+
+import json  # noqa: E402
+import os  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def c2_golden():
+    path = os.path.join(GOLDEN, "tb4_36x36_oracle_series.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle series missing (python -m tests.golden.make_golden)")
+    info = json.load(open(os.path.join(GOLDEN, "tb4_36x36_fixed_error.json")))
+    return np.load(path), info
+
+
+@pytest.mark.parametrize("kind", ["dense", "lowrank"])
+def test_full_size_fp32_vs_stored_oracle(P, ctx, c2_golden, kind):
+    g, info = c2_golden
+    cfg = get_config(1)
+    m = cfg.model()
+    dm = _dev(P, m)
+    _log(f"full-size {cfg.name} {kind} FP32 4000 steps vs stored FP64 oracle")
+    kg = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
+    op = kg
+    pre = "dense"
+    if kind == "lowrank":
+        op = ctx.kernel_compress(kg, "fraction", info["chosen"]["fraction"])
+        assert op.rank == info["chosen"]["rank"]
+        pre = "low"
+    res = ctx.propagate(op, dm, "eh", cfg.fields, cfg.dt)
+    half = int(cfg.fields.nsteps[0]) // 2 + 1
+    for key in ("P", "J"):
+        got = res[key][0].cpu().numpy()
+        ref = g[f"{pre}_{key}"]
+        e_half = float(np.abs(got[:half] - ref[:half]).max() / np.abs(ref[:half]).max())
+        e_full = err_rel(got, ref)
+        _log(f"  err_{key}: first half {e_half:.2e}, full run {e_full:.2e}")
+        assert e_half <= 1e-4, key
+    ctx.check_numeric(res, cfg.fields, 1e-5, 1e-5)

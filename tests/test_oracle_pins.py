@@ -401,7 +401,8 @@ def test_absorption_peak_at_lowest_bright_exciton(tb4_4, k_tb4_eh):
     amat, lab = O.linear_operator(m, k_tb4_eh, "eh")
     ev, vec = np.linalg.eigh(amat)
     kn, n, mm = lab[:, 0], lab[:, 1], lab[:, 2]
-    osc = np.abs(vec.conj().T @ m.dip[0][kn, mm, n]) ** 2
+    # the pulse drives drho_cv through d_cv: strength |<A^S | d_cv>|^2
+    osc = np.abs(vec.conj().T @ m.dip[0][kn, n, mm]) ** 2
     bright = ev[osc > 1e-2 * osc.max()]
     target = bright[0]
     t = np.arange(out["P"].shape[0]) * DT
