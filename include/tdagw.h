@@ -218,7 +218,8 @@ int tdg_check_numeric(tdg_ctx ctx, const tdg_obs* obs, int32_t batch, const tdg_
  * by events; tdg_profile_read synchronises and returns the summed duration
  * (ms) and launch count of a class since the last reset. */
 #define TDG_KCLASS_STAGE 0   /* fused contraction + commutator + RK4 stage kernel */
-#define TDG_KCLASS_PROJECT 1 /* low-rank projection z = V^H x */
+#define TDG_KCLASS_PROJECT 1 /* low-rank projection z = V^H x (single-instance path) */
+#define TDG_KCLASS_GEMM 2    /* matrix-core products of the batched path */
 int tdg_profile_enable(tdg_ctx ctx, int32_t on);
 int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* launches);
 
@@ -231,6 +232,11 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * in summation order. */
 #define TDG_OPT_AUTOTUNE 0      /* 1 = tune on first use (default), 0 = use variant 0 */
 #define TDG_OPT_STAGE_VARIANT 1 /* >= 0 forces that variant index, -1 = tuned/default */
+/* Batched path: with a TDG_C64 operator and at least this many instances
+ * (default 4), each stage contracts all running instances at once as complex
+ * FP32 matrix products on the matrix cores (split-K partials summed by the
+ * stage kernel); below it, every instance streams the operator itself. */
+#define TDG_OPT_BATCHED_MIN 2
 int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
 /* Name of the stage-kernel variant the last tdg_propagate used ("" before any). */
 const char* tdg_last_variant(tdg_ctx ctx);

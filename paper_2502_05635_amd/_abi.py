@@ -20,8 +20,10 @@ TDG_OP_DENSE = 0
 TDG_OP_LOWRANK = 1
 TDG_KCLASS_STAGE = 0
 TDG_KCLASS_PROJECT = 1
+TDG_KCLASS_GEMM = 2
 TDG_OPT_AUTOTUNE = 0
 TDG_OPT_STAGE_VARIANT = 1
+TDG_OPT_BATCHED_MIN = 2
 
 P = C.c_void_p
 

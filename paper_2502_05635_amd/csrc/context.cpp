@@ -1,6 +1,7 @@
 // Context lifetime, error reporting, workspace and profiling events.
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 #include "internal.h"
@@ -149,6 +150,11 @@ int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value) {
     ctx->autotune = value != 0;
     return TDG_OK;
   }
+  if (option == TDG_OPT_BATCHED_MIN) {
+    if (value < 1) return fail(ctx, TDG_E_INVAL, "batched minimum must be >= 1");
+    ctx->batched_min = (int)std::min<int64_t>(value, 1 << 30);
+    return TDG_OK;
+  }
   if (option == TDG_OPT_STAGE_VARIANT) {
     if (value < -1 || value > 64) return fail(ctx, TDG_E_INVAL, "variant index %lld", (long long)value);
     ctx->forced_variant = (int)value;
@@ -162,13 +168,13 @@ const char* tdg_last_variant(tdg_ctx ctx) { return ctx ? ctx->last_variant.c_str
 int tdg_profile_enable(tdg_ctx ctx, int32_t on) {
   if (!ctx) return TDG_E_INVAL;
   ctx->prof = on != 0;
-  ctx->used[0] = ctx->used[1] = 0;
+  ctx->used[0] = ctx->used[1] = ctx->used[2] = 0;
   return TDG_OK;
 }
 
 int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* launches) {
   if (!ctx) return TDG_E_INVAL;
-  if (kclass < 0 || kclass > 1 || !total_ms || !launches)
+  if (kclass < 0 || kclass > 2 || !total_ms || !launches)
     return fail(ctx, TDG_E_INVAL, "profile_read: bad class or NULL output");
   TDG_TRY(hip_check(ctx, hipStreamSynchronize(ctx->stream), "profile sync"));
   double tot = 0.0;

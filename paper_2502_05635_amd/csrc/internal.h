@@ -28,6 +28,8 @@ enum WsSlot {
   WS_MISC,       // small scratch (row sums, flags)
   WS_RHO_N,      // rho(t_n) in sorted instance order, c128 [B][nk][nb][nb]
   WS_PERM,       // sorted position -> caller's instance index, int [B]
+  WS_Y,          // batched: contraction result / split-K partials, c64
+  WS_ZSUM,       // batched low rank: projection summed over its split-K slices, c64
   WS_COUNT
 };
 
@@ -49,11 +51,12 @@ struct tdg_ctx_s {
   tdg::Buf ws[tdg::WS_COUNT];
   void* blas = nullptr;  // rocblas_handle, created on first compression
   bool prof = false;
-  std::vector<tdg::EventPair> events[2];
-  size_t used[2] = {0, 0};
+  std::vector<tdg::EventPair> events[3];
+  size_t used[3] = {0, 0, 0};
   // stage-kernel variant selection (see tdg_set_option)
   bool autotune = true;
   int forced_variant = -1;
+  int batched_min = 4;  // complex64 operators use the matrix-core path from this batch size
   std::vector<std::pair<std::string, int>> tuned;  // shape key -> variant index
   std::string last_variant;
 };
@@ -73,6 +76,12 @@ int validate_model(tdg_ctx ctx, const tdg_model* m);
 int pairs_per_k(const tdg_model* m, int block);
 // Destroy the context's rocBLAS handle if compression created one.
 void release_blas(tdg_ctx ctx);
+// Complex FP32 matrix-core product Y[s] = A * sum(X slices) (gemm.hip).
+void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
+               int x_slices, int64_t x_slice_stride, void* Y, int64_t ldy, int64_t y_slice_stride, int ncols,
+               int kslice);
+// out = sum of `slices` complex64 arrays of `count` elements, `stride` apart.
+void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stride, int64_t count, void* out);
 
 }  // namespace tdg
 

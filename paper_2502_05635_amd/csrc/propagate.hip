@@ -454,10 +454,12 @@ __global__ void __launch_bounds__(PROJ_THREADS) project_kernel(const void* __res
 
 // Working state from the caller's rho: rho_n <- rho_eq or rho[perm[b]],
 // rho_s <- rho_n, x <- (rho_n - rho_eq)[pairs]; b is the sorted position.
+// x_inst_minor selects the batched path's drho layout [N][xstride] (instance
+// fastest) instead of [B][xstride].
 template <typename T>
 __global__ void init_kernel(const double2* __restrict__ rho_in, const int* __restrict__ perm, double2* rho_n,
                             double2* rho_s, void* x, int64_t xstride, int nk, int nb, int nv, int npair, int block,
-                            int init_eq) {
+                            int init_eq, int x_inst_minor) {
   using C = typename Cx<T>::type;
   const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x, nb2 = nb * nb;
   if (t >= nb2) return;
@@ -476,7 +478,8 @@ __global__ void init_kernel(const double2* __restrict__ rho_in, const int* __res
     C xv;
     xv.x = (T)(r.x - occ);
     xv.y = (T)r.y;
-    reinterpret_cast<C*>(x)[(size_t)b * xstride + (size_t)k * npair + p] = xv;
+    const size_t i = (size_t)k * npair + p;
+    reinterpret_cast<C*>(x)[x_inst_minor ? i * xstride + b : (size_t)b * xstride + i] = xv;
   }
 }
 
@@ -486,6 +489,167 @@ __global__ void finish_kernel(const double2* __restrict__ rho_n, const int* __re
   const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
   if (t >= nb2) return;
   rho_out[((size_t)perm[b] * nk + k) * nb2 + t] = rho_n[((size_t)b * nk + k) * nb2 + t];
+}
+
+// ---- batched path: per-k stage after the matrix-core contraction -----------
+struct BatchParams {
+  const float2* Y;    // contraction result, [slice][N][ldy] (instance fastest)
+  int64_t ldy;
+  int y_slices;
+  int64_t y_slice_stride;
+  const float2* kdiag;  // low rank: K_diag [N]; dense: NULL
+  const float2* xcur;   // drho gather of this stage, [N][ldx]
+  float2* xnext;
+  int64_t ldx;
+  double2* rho_n;
+  double2* rho_s;
+  double2* acc;
+  const double* eps;
+  const double2* dip;
+  const double2* vel;
+  const tdg_field* fields;
+  double* obs_part;
+  int obs_slot;
+  int nk, nb, nv, npair, block, batch;
+  int n_active;  // instances with blocks in this launch (stage 0: also those at their final time)
+  int n_dyn;     // instances that integrate
+  int step, stage;
+  double dt;
+};
+
+// One block per (k point, group of instances): thread (li, e) owns element
+// e = (n, m) of instance blockIdx.y * ib + li, ib = blockDim.x / nb^2.
+__global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
+  __shared__ double2 s_rho[256];
+  __shared__ double2 s_h[256];
+  __shared__ double s_obs[5][256];
+  const int nb = bp.nb, nb2 = nb * nb, ib = blockDim.x / nb2;
+  const int li = threadIdx.x / nb2, e = threadIdx.x % nb2, n = e / nb, m = e % nb;
+  const int k = blockIdx.x, b = blockIdx.y * ib + li;
+  const bool act = li < ib && b < bp.n_active, dyn = act && b < bp.n_dyn;
+  const size_t g = ((size_t)b * bp.nk + k) * nb2 + e;
+  const size_t base = (size_t)k * nb2 + e, plane = (size_t)bp.nk * nb2;
+  const int P = bp.npair;
+
+  tdg_field F = {};
+  double2 r_s = make_double2(0.0, 0.0), r_n = r_s, r_acc = r_s, d0 = r_s, d1 = r_s, v0 = r_s, v1 = r_s;
+  double e_nn = 0.0;
+  int p = -1;
+  bool partner = false;  // element (v, c) of the conduction-valence block: conj of (c, v)
+  if (bp.block == TDG_BLOCK_ALL) {
+    p = e;
+  } else if (n >= bp.nv && m < bp.nv) {
+    p = (n - bp.nv) * bp.nv + m;
+  } else if (n < bp.nv && m >= bp.nv) {
+    p = (m - bp.nv) * bp.nv + n;
+    partner = true;
+  }
+  double2 ds = make_double2(0.0, 0.0);
+  if (act) {
+    F = bp.fields[b];
+    r_s = bp.rho_s[g];
+    d0 = bp.dip[base];
+    d1 = bp.dip[plane + base];
+    if (bp.stage == 0) {
+      v0 = bp.vel[base];
+      v1 = bp.vel[plane + base];
+    }
+  }
+  if (dyn) {
+    r_n = bp.rho_n[g];
+    if (bp.stage != 0) r_acc = bp.acc[g];
+    if (n == m) e_nn = bp.eps[(size_t)k * nb + n];
+    if (p >= 0) {
+      const size_t row = (size_t)k * P + p;
+      float yr = 0.f, yi = 0.f;
+      for (int sl = 0; sl < bp.y_slices; ++sl) {
+        const float2 y = bp.Y[sl * bp.y_slice_stride + row * bp.ldy + b];
+        yr += y.x;
+        yi += y.y;
+      }
+      if (bp.kdiag) {
+        const float2 kd = bp.kdiag[row], xv = bp.xcur[row * bp.ldx + b];
+        yr += kd.x * xv.x - kd.y * xv.y;
+        yi += kd.x * xv.y + kd.y * xv.x;
+      }
+      ds = make_double2((double)yr, partner ? -(double)yi : (double)yi);
+    }
+  }
+  s_rho[threadIdx.x] = r_s;
+  __syncthreads();
+
+  // observables of rho(t_n), per (instance, k)
+  if (bp.stage == 0 && bp.obs_part) {
+    if (act) {
+      const double2 de = proj_e(F, d0, d1), ve = proj_e(F, v0, v1);
+      const double2 rmn = s_rho[li * nb2 + m * nb + n];
+      s_obs[0][threadIdx.x] = de.x * rmn.x - de.y * rmn.y;
+      s_obs[1][threadIdx.x] = ve.x * rmn.x - ve.y * rmn.y;
+      s_obs[2][threadIdx.x] = (n == m && n == bp.nv) ? r_s.x : 0.0;
+      s_obs[3][threadIdx.x] = (n == m) ? r_s.x : 0.0;
+      const double hx = r_s.x - rmn.x, hy = r_s.y + rmn.y;
+      s_obs[4][threadIdx.x] = sqrt(hx * hx + hy * hy);
+    }
+    __syncthreads();
+    if (act && e == 0) {
+      double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < nb2; ++i) {
+        const int q = li * nb2 + i;
+        o[0] += s_obs[0][q];
+        o[1] += s_obs[1][q];
+        o[2] += s_obs[2][q];
+        o[3] += s_obs[3][q];
+        if (s_obs[4][q] > o[4] || s_obs[4][q] != s_obs[4][q]) o[4] = s_obs[4][q];
+      }
+      o[3] = fabs(o[3] - (double)bp.nv);
+      double* dst = bp.obs_part + (((size_t)bp.obs_slot * bp.batch + b) * bp.nk + k) * 5;
+      for (int c = 0; c < 5; ++c) dst[c] = o[c];
+    }
+  }
+
+  // H = eps + dSigma - E(t) e.d
+  if (dyn) {
+    const double cs = (bp.stage == 0) ? 0.0 : (bp.stage == 3 ? 1.0 : 0.5);
+    const double ef = field_value(F, (double)bp.step * bp.dt + cs * bp.dt);
+    const double2 de = proj_e(F, d0, d1);
+    double2 h = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
+    if (n == m) h.x += e_nn;
+    s_h[threadIdx.x] = h;
+  }
+  __syncthreads();
+  if (!dyn) return;
+
+  // f = -i [H, rho], RK4 stage, next drho gather
+  const double2* H = s_h + li * nb2;
+  const double2* R = s_rho + li * nb2;
+  double2 c = make_double2(0.0, 0.0);
+  for (int l = 0; l < nb; ++l) {
+    const double2 hr = cmul(H[n * nb + l], R[l * nb + m]);
+    const double2 rh = cmul(R[n * nb + l], H[l * nb + m]);
+    c.x += hr.x - rh.x;
+    c.y += hr.y - rh.y;
+  }
+  const double2 f = make_double2(c.y, -c.x);
+  double2 next;
+  if (bp.stage == 0) {
+    bp.acc[g] = f;
+    next = make_double2(r_n.x + 0.5 * bp.dt * f.x, r_n.y + 0.5 * bp.dt * f.y);
+  } else if (bp.stage == 1) {
+    bp.acc[g] = make_double2(r_acc.x + 2.0 * f.x, r_acc.y + 2.0 * f.y);
+    next = make_double2(r_n.x + 0.5 * bp.dt * f.x, r_n.y + 0.5 * bp.dt * f.y);
+  } else if (bp.stage == 2) {
+    bp.acc[g] = make_double2(r_acc.x + 2.0 * f.x, r_acc.y + 2.0 * f.y);
+    next = make_double2(r_n.x + bp.dt * f.x, r_n.y + bp.dt * f.y);
+  } else {
+    const double w = bp.dt / 6.0;
+    next = make_double2(r_n.x + w * (r_acc.x + f.x), r_n.y + w * (r_acc.y + f.y));
+    bp.rho_n[g] = next;
+  }
+  bp.rho_s[g] = next;
+  if (p >= 0 && !partner) {
+    const double dre = next.x - ((n == m && n < bp.nv) ? 1.0 : 0.0);
+    bp.xnext[((size_t)k * P + p) * bp.ldx + b] = make_float2((float)dre, (float)next.y);
+  }
 }
 
 // Observables of an arbitrary state (tdg_observables), caller's order.
@@ -688,20 +852,25 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
 
   const int nb2 = model->nb * model->nb;
   const size_t state_bytes = (size_t)batch * nk * nb2 * sizeof(double2);
-  const int64_t xstride = (n + 1) & ~int64_t(1);
+  // matrix-core path: complex64 operator and enough instances
+  const bool batched = op->dtype == TDG_C64 && batch >= ctx->batched_min;
+  if (batched && (nb2 > 256 || n > 2147483647 / 2))
+    return fail(ctx, TDG_E_UNSUPPORTED, "batched path: nb^2 <= 256 and N < 2^30 required");
+  const int64_t xstride = batched ? (int64_t)batch : ((n + 1) & ~int64_t(1));
   const int64_t zstride = (op->rank + 1) & ~int64_t(1);
   void *rho_n, *rho_s, *acc, *x0, *x1, *z = nullptr, *part, *dperm, *dfields;
   TDG_TRY(ws_reserve(ctx, WS_RHO_N, state_bytes, &rho_n));
   TDG_TRY(ws_reserve(ctx, WS_RHO_S, state_bytes, &rho_s));
   TDG_TRY(ws_reserve(ctx, WS_ACC, state_bytes, &acc));
-  TDG_TRY(ws_reserve(ctx, WS_X0, (size_t)batch * xstride * elt, &x0));
-  TDG_TRY(ws_reserve(ctx, WS_X1, (size_t)batch * xstride * elt, &x1));
+  const size_t xbytes = batched ? (size_t)n * xstride * elt : (size_t)batch * xstride * elt;
+  TDG_TRY(ws_reserve(ctx, WS_X0, xbytes, &x0));
+  TDG_TRY(ws_reserve(ctx, WS_X1, xbytes, &x1));
   // low rank: the projection is split over zsplit column slices (at least
   // about 256 blocks per instance, at most ZSPLIT_MAX slices); the stage
   // kernel sums the slices it reads
   int zsplit = 1;
   int64_t zslice = n;
-  if (lowrank) {
+  if (lowrank && !batched) {
     const int64_t groups = (op->rank + ROWS - 1) / ROWS;
     zsplit = (int)std::min<int64_t>(ZSPLIT_MAX, std::max<int64_t>(1, (256 + groups - 1) / groups));
     zslice = ((n + zsplit - 1) / zsplit + 1) & ~int64_t(1);
@@ -719,11 +888,11 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     if (op->dtype == TDG_C128)
       hipLaunchKernelGGL(init_kernel<double>, dim3(nk, batch), dim3(init_threads), 0, ctx->stream,
                          (const double2*)rho, (const int*)dperm, (double2*)rho_n, (double2*)rho_s, x0, xstride, nk,
-                         model->nb, model->nv, npair, op->block, init_eq);
+                         model->nb, model->nv, npair, op->block, init_eq, (int)batched);
     else
       hipLaunchKernelGGL(init_kernel<float>, dim3(nk, batch), dim3(init_threads), 0, ctx->stream,
                          (const double2*)rho, (const int*)dperm, (double2*)rho_n, (double2*)rho_s, x0, xstride, nk,
-                         model->nb, model->nv, npair, op->block, init_eq);
+                         model->nb, model->nv, npair, op->block, init_eq, (int)batched);
     return launch_check(ctx, "init launch");
   };
   TDG_TRY(init());
@@ -774,6 +943,112 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     while (c < batch && len[c] >= step) ++c;
     return c;
   };
+
+  if (batched) {
+    // split-K so that each product launches about 1024 blocks; slices are
+    // multiples of 16 complex columns (the GEMM's LDS stage)
+    auto kslice_for = [&](int64_t M, int64_t Kc) {
+      const int64_t tiles = ((M + 63) / 64) * ((batch + 63) / 64);
+      int64_t splits = std::max<int64_t>(1, std::min<int64_t>(64, (1024 + tiles - 1) / tiles));
+      int64_t ks = (Kc + splits - 1) / splits;
+      ks = std::max<int64_t>(16, (ks + 15) / 16 * 16);
+      return ks;
+    };
+    const int64_t ldy = batch;
+    int64_t ks_main, ks_proj = 0;
+    int y_slices, z_slices = 0;
+    void* Ybuf = nullptr;
+    void* Zbuf = nullptr;
+    void* Zsum = nullptr;
+    if (!lowrank) {
+      ks_main = kslice_for(n, n);
+      y_slices = (int)((n + ks_main - 1) / ks_main);
+      TDG_TRY(ws_reserve(ctx, WS_Y, (size_t)y_slices * n * ldy * 8, &Ybuf));
+    } else {
+      ks_proj = kslice_for(op->rank, n);
+      z_slices = (int)((n + ks_proj - 1) / ks_proj);
+      TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)z_slices * op->rank * ldy * 8, &Zbuf));
+      ks_main = (op->rank + 15) / 16 * 16;
+      y_slices = 1;
+      TDG_TRY(ws_reserve(ctx, WS_Y, (size_t)n * ldy * 8, &Ybuf));
+      TDG_TRY(ws_reserve(ctx, WS_ZSUM, (size_t)op->rank * ldy * 8, &Zsum));
+    }
+    BatchParams bp = {};
+    bp.Y = (const float2*)Ybuf;
+    bp.ldy = ldy;
+    bp.y_slices = y_slices;
+    bp.y_slice_stride = n * ldy;
+    bp.kdiag = lowrank ? (const float2*)op->kdiag : nullptr;
+    bp.ldx = xstride;
+    bp.rho_n = (double2*)rho_n;
+    bp.rho_s = (double2*)rho_s;
+    bp.acc = (double2*)acc;
+    bp.eps = model->eps;
+    bp.dip = (const double2*)model->dip;
+    bp.vel = (const double2*)model->vel;
+    bp.fields = (const tdg_field*)dfields;
+    bp.obs_part = (double*)part;
+    bp.nk = nk;
+    bp.nb = model->nb;
+    bp.nv = model->nv;
+    bp.npair = npair;
+    bp.block = op->block;
+    bp.batch = batch;
+    bp.dt = dt;
+    const int ib = 256 / nb2;
+    ctx->last_variant = lowrank ? "batched_mfma_lowrank_f32" : "batched_mfma_dense_f32";
+    tdg_obs ob = *obs;
+    void* xc = x0;
+    void* xn = x1;
+    int slot = 0;
+    int64_t chunk_start = 0;
+    for (int64_t step = 0; step <= max_steps; ++step) {
+      const int n_obs = count_ge(step), n_dyn = count_gt(step);
+      bp.n_dyn = n_dyn;
+      for (int s = 0; s < 4; ++s) {
+        const int active = s == 0 ? n_obs : n_dyn;
+        if (active == 0) break;
+        if (n_dyn > 0) {
+          prof_begin(ctx, TDG_KCLASS_GEMM);
+          if (!lowrank) {
+            cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xc, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
+                      (int)ks_main);
+          } else {
+            // projection split over K, summed once in fixed order, then expansion
+            cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xc, xstride, 1, 0, Zbuf, ldy,
+                      op->rank * ldy, n_dyn, (int)ks_proj);
+            sum_slices_c64(ctx->stream, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
+            cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, 0, n_dyn,
+                      (int)ks_main);
+          }
+          prof_end(ctx, TDG_KCLASS_GEMM);
+        }
+        bp.xcur = (const float2*)xc;
+        bp.xnext = (float2*)xn;
+        bp.step = (int)step;
+        bp.stage = s;
+        bp.obs_slot = slot;
+        bp.n_active = active;
+        prof_begin(ctx, TDG_KCLASS_STAGE);
+        hipLaunchKernelGGL(batched_stage_kernel, dim3(nk, (active + ib - 1) / ib), dim3(ib * nb2), 0,
+                           ctx->stream, bp);
+        prof_end(ctx, TDG_KCLASS_STAGE);
+        std::swap(xc, xn);
+      }
+      ++slot;
+      if (slot == chunk || step == max_steps) {
+        hipLaunchKernelGGL(obs_reduce_kernel, dim3(slot, batch), dim3(THREADS), 0, ctx->stream, (const double*)part,
+                           nk, batch, (int)chunk_start, (const tdg_field*)dfields, (const int*)dperm, ob,
+                           (double*)nullptr);
+        chunk_start += slot;
+        slot = 0;
+      }
+      if ((step & 63) == 0) TDG_TRY(launch_check(ctx, "batched propagation launch"));
+    }
+    hipLaunchKernelGGL(finish_kernel, dim3(nk, batch), dim3(init_threads), 0, ctx->stream, (const double2*)rho_n,
+                       (const int*)dperm, (double2*)rho, nk, nb2);
+    return launch_check(ctx, "batched propagation launch");
+  }
 
   // ---- variant choice ------------------------------------------------------
   const Variant* vt = nullptr;

@@ -295,3 +295,65 @@ def test_full_size_fp32_vs_stored_oracle(P, ctx, c2_golden, kind):
         _log(f"  err_{key}: first half {e_half:.2e}, full run {e_full:.2e}")
         assert e_half <= 1e-4, key
     ctx.check_numeric(res, cfg.fields, 1e-5, 1e-5)
+
+
+# --- batched matrix-core path -----------------------------------------------
+
+def _uneven_fields(n_inst, seed=5):
+    rng = np.random.default_rng(seed)
+    tabs = []
+    for i in range(n_inst):
+        ns = int(rng.integers(1, 260))
+        t = ns * DT
+        tabs.append(FieldTable.single(10 ** rng.uniform(-4, -2), rng.uniform(0.5, 3.0) / HARTREE_EV,
+                                      max(t / 10.0, 0.5 * FS_AU), t / 2.0, ns, ex=np.cos(0.3 * i),
+                                      ey=np.sin(0.3 * i)))
+    tabs[0] = FieldTable.single(3e-3, 1.2 / HARTREE_EV, 1.0 * FS_AU, 2.0 * FS_AU, 0)
+    return FieldTable.stack(tabs)
+
+
+@pytest.mark.parametrize("kind", ["dense", "lowrank"])
+def test_batched_mfma_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind):
+    """Uneven batch (lengths 0 .. 259, mixed polarisations) through the
+    matrix-core path, each instance against its own FP64 oracle run."""
+    from paper_2502_05635_amd import _abi as abi
+    fields = _uneven_fields(6)
+    dm = _dev(P, tb4_6)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c64")
+    op, oracle_op = kg, O.DenseOp(k_tb4_6)
+    if kind == "lowrank":
+        op = ctx.kernel_compress(kg, "rank", 37)
+        oracle_op = O.LowRankOp.from_factors(O.compress(k_tb4_6, "rank", 37))
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 2)
+    _log(f"batched {kind} FP32 on the matrix cores, 6 instances")
+    res = ctx.propagate(op, dm, "eh", fields, DT)
+    assert ctx.last_variant().startswith("batched_mfma")
+    for b in range(fields.batch):
+        ref = O.propagate(tb4_6, oracle_op, "eh", fields, DT, instance=b)
+        nsb = int(fields.nsteps[b])
+        for key in ("P", "J"):
+            got = res[key][b, : nsb + 1].cpu().numpy()
+            scale = max(np.abs(ref[key]).max(), 1e-300)
+            assert np.abs(got - ref[key]).max() <= 1e-4 * scale, (b, key)
+        np.testing.assert_allclose(res["rho"][b].cpu().numpy(), ref["rho"], rtol=0, atol=1e-5)
+
+
+@pytest.mark.parametrize("kind", ["dense", "lowrank"])
+def test_batched_mfma_matches_per_instance_path(P, ctx, kind):
+    """70 instances (two instance tiles of the matrix-core product) agree with
+    the per-instance streaming path on the same device to FP32 accuracy."""
+    from paper_2502_05635_amd import _abi as abi
+    m = tb4_model(4, A, 0.5)
+    dm = _dev(P, m)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c64")
+    op = kg if kind == "dense" else ctx.kernel_compress(kg, "fraction", 0.5)
+    fields = _uneven_fields(70, seed=9)
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 2)
+    res_b = ctx.propagate(op, dm, "eh", fields, DT)
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 1 << 20)
+    res_s = ctx.propagate(op, dm, "eh", fields, DT)
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 4)
+    for key in ("P", "J", "occ"):
+        a, b = res_b[key].cpu().numpy(), res_s[key].cpu().numpy()
+        scale = np.abs(b).max(axis=1, keepdims=True) + 1e-300
+        assert (np.abs(a - b) / scale).max() <= 1e-4, key
