@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--factors-cache", default=None,
                     help="npz file: load the compressed factors from it if present, else compute and save them "
                          "(lets a counter-collection run skip the eigensolver)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batched 60x60 sweep measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -219,6 +220,15 @@ def main():
     value = args.steps / out["lowrank"]["secs"]
     dense_value = args.steps / out["dense"]["secs"]
 
+    rank_cut = int(np.count_nonzero(fac.sigma > 1e-3 * fac.sigma[0]))
+    sweep = None
+    if not args.no_sweep:
+        for v in out.values():
+            v.pop("res", None)
+        del K, fac, res
+        torch.cuda.empty_cache()
+        sweep = batched_sweep(P, abi, ctx, frac)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, frac, args.cpu_seconds)
@@ -240,7 +250,7 @@ def main():
             "workload": f"{cfg.name}: seeded 4-band lattice model, 36x36 k-grid, conduction-valence kernel "
                         f"N={n} complex64, 1 field instance, dt=0.05 fs; FP32 contraction, FP64 state",
             "operator": "low-rank K_diag + S V^H",
-            "kept_fraction": frac, "rank": r, "rank_rel_cut_1e-3": int(np.count_nonzero(fac.sigma > 1e-3 * fac.sigma[0])),
+            "kept_fraction": frac, "rank": r, "rank_rel_cut_1e-3": rank_cut,
             "batch": 1, "parallelism": "none",
         },
         "dense": {"value": dense_value, "ms_per_step": 1e3 / dense_value, "variant": out["dense"]["variant"],
@@ -259,9 +269,56 @@ def main():
             "avg_launch_us": dom_avg_s * 1e6, "bytes_per_launch": dom_bytes,
         },
         "cpu_baseline": cpu,
+        "batched_sweep": sweep,
     }
     ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def batched_sweep(P, abi, ctx, frac):
+    """The 60x60 batched field sweep: 64 instances of uneven length (2000 to
+    8000 steps) integrated together on the matrix-core path, dense and
+    low-rank at the same kept fraction; instance.steps/s = sum of lengths / time."""
+    import numpy as np
+    import torch
+
+    from workloads import FieldTable, get_config
+    cfg = get_config(2)
+    model = cfg.model()
+    dm = P.DeviceModel.from_model(model)
+    K = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
+    fac = ctx.kernel_compress(K, "fraction", frac)
+    f = cfg.fields
+    total = int(f.nsteps.sum())
+    n, r, B = K.shape[0], fac.rank, f.batch
+    short = FieldTable(f.e0, f.omega, f.tau, f.t0, f.ex, f.ey, np.full(B, 40, dtype=np.int64))
+    res = {"workload": f"{cfg.name}: 60x60 k-grid, N={n} complex64, {B} instances, "
+                       f"{int(f.nsteps.min())}-{int(f.nsteps.max())} steps each, sum {total}",
+           "rank": r, "kept_fraction": frac}
+    for name, op in (("dense", K), ("lowrank", fac)):
+        ctx.propagate(op, dm, "eh", short, cfg.dt)            # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.propagate(op, dm, "eh", f, cfg.dt)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        ctx.profile_enable(True)
+        ctx.propagate(op, dm, "eh", short, cfg.dt)
+        g_ms, g_n = ctx.profile_read(abi.TDG_KCLASS_GEMM)
+        s_ms, s_n = ctx.profile_read(abi.TDG_KCLASS_STAGE)
+        ctx.profile_enable(False)
+        # complex products as real flops: 8 per complex multiply-add, all 64 instances
+        flops = 8.0 * n * n * B if name == "dense" else 16.0 * n * r * B
+        gemm_s = g_ms / g_n * 1e-3
+        res[name] = {"value": total / secs, "seconds": secs, "variant": ctx.last_variant(),
+                     "contraction_us_per_stage": gemm_s * 1e6,
+                     "contraction_TFLOPs": flops / gemm_s / 1e12,
+                     "contraction_mfma_frac_fp32": flops / gemm_s / 157.3e12,
+                     "stage_kernel_us": s_ms / s_n * 1e3}
+    res["speedup_lowrank_vs_dense"] = res["lowrank"]["value"] / res["dense"]["value"]
+    del K, fac
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(cfg, frac, seconds):

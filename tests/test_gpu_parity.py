@@ -357,3 +357,28 @@ def test_batched_mfma_matches_per_instance_path(P, ctx, kind):
         a, b = res_b[key].cpu().numpy(), res_s[key].cpu().numpy()
         scale = np.abs(b).max(axis=1, keepdims=True) + 1e-300
         assert (np.abs(a - b) / scale).max() <= 1e-4, key
+
+
+def test_batched_full_size_first_steps_vs_oracle(P, ctx):
+    """The 60x60 sweep's operator (N = 14400) through the matrix-core path:
+    the first 12 steps of 4 instances against the FP64 dense oracle."""
+    from paper_2502_05635_amd import _abi as abi
+    cfg = get_config(2)
+    m = cfg.model()
+    f = cfg.fields.subset([0, 21, 42, 63])
+    short = FieldTable(np.full(4, 5e-3), f.omega, np.full(4, 1.0 * FS_AU), np.full(4, 10 * DT), f.ex, f.ey,
+                       np.full(4, 12))
+    _log(f"batched full-size {cfg.name}: 4 instances x 12 steps vs FP64 oracle")
+    dm = _dev(P, m)
+    kg = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 2)
+    res = ctx.propagate(kg, dm, "eh", short, cfg.dt)
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 4)
+    del kg
+    k = O.build_kernel(m, cfg.r0, "eh")
+    for b in range(4):
+        ref = O.propagate(m, O.DenseOp(k), "eh", short, cfg.dt, instance=b)
+        for key in ("P", "J"):
+            e = err_rel(res[key][b].cpu().numpy(), ref[key])
+            _log(f"  instance {b} err_{key} = {e:.2e}")
+            assert e <= 1e-4, (b, key)
