@@ -47,6 +47,13 @@ extern "C" {
 
 #define TDG_C128 0 /* complex double storage, FP64 arithmetic */
 #define TDG_C64 1  /* complex float storage, FP32 arithmetic with FP32 accumulation */
+/* BF16 split precision: a complex matrix [rows][ld] is stored as a plane of
+ * bf16 (re, im) pairs holding hi = bf16(a), followed by a plane holding
+ * lo = bf16(a - hi) (8 bytes per element, like TDG_C64; a ~ hi + lo to about
+ * 16 significant bits).  Products run as A_hi x_hi + A_hi x_lo + A_lo x_hi on
+ * the BF16 matrix cores with FP32 accumulation (x split the same way on the
+ * fly).  Requires ld % 4 == 0.  Used by the batched propagation path only. */
+#define TDG_BF16X2 2
 
 #define TDG_BLOCK_ALL 0 /* every band pair (n, m) */
 #define TDG_BLOCK_EH 1  /* conduction-valence block; dSigma_vc = conj(dSigma_cv) */
@@ -103,8 +110,9 @@ int tdg_kernel_dim(const tdg_model* model, int32_t block, int64_t* n_out);
 /* Build the direct electron-hole kernel of the lattice model (paper
  * Eq. sigma-from-k with the single-G limit of Eq. bse-direct-def):
  *   K_{(n m k),(n' m' k')} = -W(|fold(k - k')|) / (nk a^2) <n k|n' k'> <m' k'|m k>
- * into K (dtype TDG_C128 or TDG_C64, row-major [N][ld], ld >= N; for C64
- * K must be 16-byte aligned and ld even).  Overwrites the N x N block only. */
+ * into K (dtype TDG_C128, TDG_C64 or TDG_BF16X2, row-major [N][ld], ld >= N;
+ * for C64 K must be 16-byte aligned and ld even, for BF16X2 ld % 4 == 0).
+ * Overwrites the N x N block (BF16X2: and zero-fills columns N .. ld-1). */
 int tdg_kernel_build(tdg_ctx ctx, const tdg_model* model, const tdg_coulomb* coulomb,
                      int32_t dtype, void* K, int64_t ld);
 
@@ -123,10 +131,13 @@ typedef struct {
 
 /* Output of compression.  The caller sets n, max_rank, dtype and the
  * pointers; the library fills rank and the norms.
- *   kdiag  device [n]               diagonal of K (dtype)
- *   us     device, n*max_rank elts  S = U diag(s), row-major [n][rank] (dtype)
- *   w      device, max_rank*n elts  V^H, row-major [rank][n] (dtype)
- *   sigma  HOST double [n] or NULL  all singular values of K_off, descending */
+ *   kdiag  device [n]               diagonal of K (dtype; TDG_C64 when dtype is TDG_BF16X2)
+ *   us     device, n*max_rank elts  S = U diag(s), row-major [n][rank] (dtype);
+ *                                   TDG_BF16X2: row stride ld_us = rank rounded up to a
+ *                                   multiple of 4 (zero columns), capacity n*(max_rank+3)
+ *   w      device, max_rank*n elts  V^H, row-major [rank][n] (dtype; BF16X2 needs n % 4 == 0)
+ *   sigma  HOST double [n] or NULL  all singular values of K_off, descending
+ * The output dtype may differ from the dtype of K. */
 typedef struct {
   int64_t n, max_rank;
   int32_t dtype, pad;
@@ -162,6 +173,7 @@ typedef struct {
 
 /* The kernel operator applied each RK4 stage.  dtype selects arithmetic:
  * TDG_C128 -> FP64 contraction, TDG_C64 -> FP32 contraction with FP32
+ * accumulation, TDG_BF16X2 -> BF16 split-precision products with FP32
  * accumulation (drho is formed in FP64 and rounded; dSigma is widened back
  * to FP64 before the commutator).  Dense: K [n][ld].  Low rank: kdiag [n],
  * us [n][rank], w [rank][n] as written by tdg_kernel_compress. */
@@ -237,6 +249,8 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * FP32 matrix products on the matrix cores (split-K partials summed by the
  * stage kernel); below it, every instance streams the operator itself. */
 #define TDG_OPT_BATCHED_MIN 2
+/* Rows per block of the batched path's matrix-core product: 64 (default) or 128. */
+#define TDG_OPT_GEMM_TILE 3
 int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
 /* Name of the stage-kernel variant the last tdg_propagate used ("" before any). */
 const char* tdg_last_variant(tdg_ctx ctx);

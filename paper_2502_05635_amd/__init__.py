@@ -52,7 +52,22 @@ def _cdtype(dtype: str):
         return abi.TDG_C128, torch.complex128
     if dtype == "c64":
         return abi.TDG_C64, torch.complex64
+    if dtype == "bf16x2":  # two bf16 planes, 8 bytes per element like complex64
+        return abi.TDG_BF16X2, torch.complex64
     raise ValueError(dtype)
+
+
+@dataclass
+class Bf16x2Matrix:
+    """A complex matrix in BF16 split storage (hi plane, then lo plane);
+    `data` only provides the device memory (rows * ld * 8 bytes)."""
+    data: torch.Tensor
+    rows: int
+    cols: int
+    ld: int
+
+    def data_ptr(self) -> int:
+        return self.data.data_ptr()
 
 
 def _block(block: str) -> int:
@@ -146,32 +161,43 @@ class Context:
         return n.value
 
     def kernel_build(self, model: DeviceModel, r0: float, block: str, dtype: str = "c128",
-                     nquad: int = 64, out: torch.Tensor | None = None) -> torch.Tensor:
+                     nquad: int = 64, out: torch.Tensor | None = None):
         code, tdt = _cdtype(dtype)
         n = self.kernel_dim(model, block)
-        if out is None:
-            out = torch.empty((n, n), dtype=tdt, device=f"cuda:{self.device}")
         ms = model.struct()
         cs = abi.Coulomb(r0, _block(block), nquad)
+        if dtype == "bf16x2":
+            ld = (n + 3) // 4 * 4
+            mat = Bf16x2Matrix(torch.empty(n * ld, dtype=tdt, device=f"cuda:{self.device}"), n, n, ld)
+            self._check(self._lib.tdg_kernel_build(self.h, C.byref(ms), C.byref(cs), code, _ptr(mat), ld))
+            return mat
+        if out is None:
+            out = torch.empty((n, n), dtype=tdt, device=f"cuda:{self.device}")
         self._check(self._lib.tdg_kernel_build(self.h, C.byref(ms), C.byref(cs), code, _ptr(out), out.stride(0)))
         return out
 
     def kernel_compress(self, K: torch.Tensor, rule: str = "rel_cut", value: float = 1e-3,
-                        max_rank: int | None = None) -> LowRankFactors:
-        dtype = "c128" if K.dtype == torch.complex128 else "c64"
+                        max_rank: int | None = None, out_dtype: str | None = None) -> LowRankFactors:
+        """Truncated SVD of K_off; factors in out_dtype (default: K's dtype;
+        "bf16x2" writes split-precision factors with a complex64 K_diag)."""
+        kdtype = "c128" if K.dtype == torch.complex128 else "c64"
+        kcode, _ = _cdtype(kdtype)
+        dtype = out_dtype or kdtype
         code, tdt = _cdtype(dtype)
         n = K.shape[0]
         max_rank = n if max_rank is None else int(max_rank)
         dev = K.device
         kdiag = torch.empty(n, dtype=tdt, device=dev)
-        us = torch.empty(n * max_rank, dtype=tdt, device=dev)
+        us = torch.empty(n * (max_rank + 3), dtype=tdt, device=dev)
         w = torch.empty(n * max_rank, dtype=tdt, device=dev)
         sigma = np.zeros(n, dtype=np.float64)
         lr = abi.LowRank(n, max_rank, code, 0, kdiag.data_ptr(), us.data_ptr(), w.data_ptr(),
                          sigma.ctypes.data, 0, 0.0, 0.0)
         tr = abi.Trunc(abi.TDG_TRUNC[rule], 0, float(value))
-        self._check(self._lib.tdg_kernel_compress(self.h, _ptr(K), K.stride(0), code, C.byref(tr), C.byref(lr)))
+        self._check(self._lib.tdg_kernel_compress(self.h, _ptr(K), K.stride(0), kcode, C.byref(tr), C.byref(lr)))
         r = int(lr.rank)
+        if dtype == "bf16x2":
+            return LowRankFactors(kdiag, us, w, sigma, r, lr.tail_fro, lr.tail_spec, dtype)
         return LowRankFactors(kdiag, us[: n * r].view(n, r), w[: n * r].view(r, n), sigma, r,
                               lr.tail_fro, lr.tail_spec, dtype)
 
@@ -181,6 +207,9 @@ class Context:
             code, _ = _cdtype(op.dtype)
             return abi.Operator(abi.TDG_OP_LOWRANK, code, _block(block), 0, n, None, 0,
                                 op.kdiag.data_ptr(), op.us.data_ptr(), op.w.data_ptr(), op.rank)
+        if isinstance(op, Bf16x2Matrix):
+            return abi.Operator(abi.TDG_OP_DENSE, abi.TDG_BF16X2, _block(block), 0, n, op.data_ptr(), op.ld,
+                                None, None, None, 0)
         code, _ = _cdtype("c128" if op.dtype == torch.complex128 else "c64")
         return abi.Operator(abi.TDG_OP_DENSE, code, _block(block), 0, n, op.data_ptr(), op.stride(0),
                             None, None, None, 0)

@@ -12,6 +12,7 @@ TDG_E_SOLVER = -6
 
 TDG_C128 = 0
 TDG_C64 = 1
+TDG_BF16X2 = 2
 TDG_BLOCK_ALL = 0
 TDG_BLOCK_EH = 1
 TDG_NB_MAX = 8
@@ -24,6 +25,7 @@ TDG_KCLASS_GEMM = 2
 TDG_OPT_AUTOTUNE = 0
 TDG_OPT_STAGE_VARIANT = 1
 TDG_OPT_BATCHED_MIN = 2
+TDG_OPT_GEMM_TILE = 3
 
 P = C.c_void_p
 

@@ -37,16 +37,27 @@ struct Cx<float> {
 // kdiag[r] <- K(r, r).  One row r of K per blockIdx.y, coalesced over c.
 template <typename T>
 __global__ void prep_kernel(const typename Cx<T>::type* __restrict__ K, int64_t ld, int64_t n, double2* __restrict__ A,
-                            typename Cx<T>::type* __restrict__ kdiag) {
+                            double2* __restrict__ kdiag) {
   const int64_t r = blockIdx.y;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
     const auto v = K[r * ld + c];
     double2 o = make_double2((double)v.x, -(double)v.y);
     if (c == r) {
-      kdiag[r] = v;
+      kdiag[r] = make_double2((double)v.x, (double)v.y);
       o = make_double2(0.0, 0.0);
     }
     A[c + r * n] = o;
+  }
+}
+
+// Diagonal in the output precision.
+template <typename T>
+__global__ void kdiag_out_kernel(const double2* __restrict__ in, int64_t n, typename Cx<T>::type* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    typename Cx<T>::type v;
+    v.x = (T)in[i].x;
+    v.y = (T)in[i].y;
+    out[i] = v;
   }
 }
 
@@ -140,12 +151,15 @@ extern "C" int tdg_kernel_compress(tdg_ctx ctx, const void* K, int64_t ld, int32
   if (!ctx) return TDG_E_INVAL;
   if (!K || !trunc || !out) return fail(ctx, TDG_E_INVAL, "NULL argument");
   if (dtype != TDG_C128 && dtype != TDG_C64) return fail(ctx, TDG_E_INVAL, "dtype %d", dtype);
-  if (out->dtype != dtype) return fail(ctx, TDG_E_INVAL, "output dtype %d differs from K dtype %d", out->dtype, dtype);
+  if (out->dtype != TDG_C128 && out->dtype != TDG_C64 && out->dtype != TDG_BF16X2)
+    return fail(ctx, TDG_E_INVAL, "output dtype %d", out->dtype);
   const int64_t n = out->n;
   if (n < 2 || n > 200000) return fail(ctx, TDG_E_INVAL, "n = %lld outside [2, 200000]", (long long)n);
   if (ld < n) return fail(ctx, TDG_E_INVAL, "ld < n");
   if (out->max_rank < 1 || out->max_rank > n) return fail(ctx, TDG_E_INVAL, "max_rank outside [1, n]");
   if (!out->kdiag || !out->us || !out->w) return fail(ctx, TDG_E_INVAL, "output factor pointer is NULL");
+  if (out->dtype == TDG_BF16X2 && ((n % 4) != 0 || (((uintptr_t)out->us | (uintptr_t)out->w) & 15)))
+    return fail(ctx, TDG_E_UNSUPPORTED, "BF16X2 factors need n %% 4 == 0 and 16-byte aligned buffers");
   if (trunc->mode < TDG_TRUNC_REL_CUT || trunc->mode > TDG_TRUNC_R2)
     return fail(ctx, TDG_E_INVAL, "truncation mode %d", trunc->mode);
   if (!std::isfinite(trunc->value) || trunc->value < 0.0) return fail(ctx, TDG_E_INVAL, "truncation value");
@@ -158,15 +172,23 @@ extern "C" int tdg_kernel_compress(tdg_ctx ctx, const void* K, int64_t ld, int32
   TDG_TRY(ws_reserve(ctx, WS_SOLVER_D, (size_t)2 * n * sizeof(double), &D));
   TDG_TRY(ws_reserve(ctx, WS_SOLVER_I, (size_t)n * (sizeof(int) + sizeof(double)) + 256, &I));
   TDG_TRY(ws_reserve(ctx, WS_MISC, (size_t)n * sizeof(double2), &M));
+  void* KD = nullptr;
+  TDG_TRY(ws_reserve(ctx, WS_TMP2, (size_t)n * sizeof(double2), &KD));
 
   const int bx = (int)std::min<int64_t>((n + 255) / 256, 64);
   if (n > 65535) return fail(ctx, TDG_E_UNSUPPORTED, "n = %lld exceeds the launch grid", (long long)n);
   if (dtype == TDG_C128)
     hipLaunchKernelGGL(prep_kernel<double>, dim3(bx, (unsigned)n), dim3(256), 0, ctx->stream, (const double2*)K, ld, n,
-                       (double2*)A, (double2*)out->kdiag);
+                       (double2*)A, (double2*)KD);
   else
     hipLaunchKernelGGL(prep_kernel<float>, dim3(bx, (unsigned)n), dim3(256), 0, ctx->stream, (const float2*)K, ld, n,
-                       (double2*)A, (float2*)out->kdiag);
+                       (double2*)A, (double2*)KD);
+  if (out->dtype == TDG_C128)
+    hipLaunchKernelGGL(kdiag_out_kernel<double>, dim3(bx), dim3(256), 0, ctx->stream, (const double2*)KD, n,
+                       (double2*)out->kdiag);
+  else
+    hipLaunchKernelGGL(kdiag_out_kernel<float>, dim3(bx), dim3(256), 0, ctx->stream, (const double2*)KD, n,
+                       (float2*)out->kdiag);
   TDG_TRY(launch_check(ctx, "compress prep"));
   hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)n), dim3(256), 0, ctx->stream, (const double2*)A, n, (double2*)M);
   TDG_TRY(launch_check(ctx, "compress row sums"));
@@ -232,12 +254,24 @@ extern "C" int tdg_kernel_compress(tdg_ctx ctx, const void* K, int64_t ld, int32
   TDG_TRY(hip_check(ctx, hipMemcpy(dperm, perm.data(), r * sizeof(int), hipMemcpyHostToDevice), "perm upload"));
   TDG_TRY(hip_check(ctx, hipMemcpy(dkept, kept.data(), r * sizeof(double), hipMemcpyHostToDevice), "lambda upload"));
   if (r > 65535) return fail(ctx, TDG_E_UNSUPPORTED, "rank exceeds the launch grid");
-  if (dtype == TDG_C128)
+  if (out->dtype == TDG_C128) {
     hipLaunchKernelGGL(gather_kernel<double>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, (const double2*)A, n,
                        dperm, dkept, r, (double2*)out->us, (double2*)out->w);
-  else
+  } else if (out->dtype == TDG_C64) {
     hipLaunchKernelGGL(gather_kernel<float>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, (const double2*)A, n,
                        dperm, dkept, r, (float2*)out->us, (float2*)out->w);
+  } else {
+    // gather in FP64, then split into hi / lo planes (us row stride: rank rounded up to 4)
+    void *tus = nullptr, *tw = nullptr;
+    TDG_TRY(ws_reserve(ctx, WS_TMP1, (size_t)n * r * sizeof(double2), &tus));
+    TDG_TRY(ws_reserve(ctx, WS_TMP3, (size_t)n * r * sizeof(double2), &tw));
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, (const double2*)A, n,
+                       dperm, dkept, r, (double2*)tus, (double2*)tw);
+    TDG_TRY(launch_check(ctx, "compress gather"));
+    const int64_t ld_us = (r + 3) / 4 * 4;
+    split_bf16x2(ctx->stream, tus, 1, r, n, r, out->us, ld_us);
+    split_bf16x2(ctx->stream, tw, 1, n, r, n, out->w, n);
+  }
   TDG_TRY(launch_check(ctx, "compress gather"));
   return hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress sync");
 }

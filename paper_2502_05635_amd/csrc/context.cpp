@@ -155,6 +155,11 @@ int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value) {
     ctx->batched_min = (int)std::min<int64_t>(value, 1 << 30);
     return TDG_OK;
   }
+  if (option == TDG_OPT_GEMM_TILE) {
+    if (value != 64 && value != 128) return fail(ctx, TDG_E_INVAL, "GEMM tile must be 64 or 128");
+    ctx->gemm_tile = (int)value;
+    return TDG_OK;
+  }
   if (option == TDG_OPT_STAGE_VARIANT) {
     if (value < -1 || value > 64) return fail(ctx, TDG_E_INVAL, "variant index %lld", (long long)value);
     ctx->forced_variant = (int)value;

@@ -118,6 +118,143 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma(GemmArgs g) {
   }
 }
 
+// Second tiling: 128 rows x 64 instances per block; wave w owns rows
+// 64*(w/2) .. +63 and real columns 64*(w%2) .. +63 as 2 x 2 MFMA accumulators,
+// so each fragment read from LDS feeds two products.  The next K tile is
+// loaded into registers while the current one is multiplied (one LDS buffer,
+// two barriers per tile).  AVEC: A rows are 16-byte aligned (lda even), so A
+// is read two complex numbers per load; X rows are always read that way (the
+// host keeps ldx even).
+constexpr int BM2 = 128;
+
+template <bool AVEC>
+__global__ void __launch_bounds__(256) cgemm_f32_mfma_128(GemmArgs g) {
+  __shared__ float As[BM2][2 * BKC + APAD];
+  __shared__ float Bs[2 * BKC][2 * BNI];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.x * BM2, b0 = blockIdx.y * BNI, s = blockIdx.z;
+  const int kc_begin = s * g.kslice;
+  const int kc_end = min(g.Kc, kc_begin + g.kslice);
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  floatx16 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  // A loader: rows t/2 and t/2 + 128/2 ... : thread t covers row t/2, complex
+  // columns 8*(t%2) .. +7 (4 pairs);  X loader: row t/16, instances 4*(t%16) .. +3
+  const int arow = t >> 1, acol = (t & 1) * 8;
+  const int xrow = t >> 4, xcol = (t & 15) * 4;
+  const int gi = m0 + arow;
+  float2 av[8], xv[4];
+
+  auto load_tile = [&](int kc0) {
+    if (AVEC) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kc = kc0 + acol + 2 * q;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gi < g.M) {
+          if (kc + 1 < kc_end) {
+            v = *reinterpret_cast<const float4*>(g.A + (int64_t)gi * g.lda + kc);
+          } else if (kc < kc_end) {
+            const float2 u = g.A[(int64_t)gi * g.lda + kc];
+            v = make_float4(u.x, u.y, 0.f, 0.f);
+          }
+        }
+        av[2 * q] = make_float2(v.x, v.y);
+        av[2 * q + 1] = make_float2(v.z, v.w);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int kc = kc0 + acol + q;
+        av[q] = (gi < g.M && kc < kc_end) ? g.A[(int64_t)gi * g.lda + kc] : make_float2(0.f, 0.f);
+      }
+    }
+    const int kx = kc0 + xrow;
+    float4 x01 = make_float4(0.f, 0.f, 0.f, 0.f), x23 = x01;
+    const int b = b0 + xcol;
+    if (kx < kc_end && b < g.ncols) {
+      for (int sl = 0; sl < g.x_slices; ++sl) {
+        const float2* src = g.X + sl * g.x_slice_stride + (int64_t)kx * g.ldx + b;
+        const float4 u = *reinterpret_cast<const float4*>(src);
+        x01.x += u.x;
+        x01.y += u.y;
+        x01.z += u.z;
+        x01.w += u.w;
+        if (b + 2 < g.ncols) {
+          const float4 v = *reinterpret_cast<const float4*>(src + 2);
+          x23.x += v.x;
+          x23.y += v.y;
+          x23.z += v.z;
+          x23.w += v.w;
+        }
+      }
+      // instances at or beyond ncols contribute nothing
+      if (b + 1 >= g.ncols) x01.z = x01.w = 0.f;
+      if (b + 3 >= g.ncols) x23.z = x23.w = 0.f;
+      if (b + 2 >= g.ncols) x23.x = x23.y = 0.f;
+    }
+    xv[0] = make_float2(x01.x, x01.y);
+    xv[1] = make_float2(x01.z, x01.w);
+    xv[2] = make_float2(x23.x, x23.y);
+    xv[3] = make_float2(x23.z, x23.w);
+  };
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[arow][2 * (acol + q)] = av[q].x;
+      As[arow][2 * (acol + q) + 1] = av[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Bs[2 * xrow][xcol + q] = xv[q].x;
+      Bs[2 * xrow + 1][xcol + q] = -xv[q].y;
+      Bs[2 * xrow][BNI + xcol + q] = xv[q].y;
+      Bs[2 * xrow + 1][BNI + xcol + q] = xv[q].x;
+    }
+  };
+
+  if (kc_begin < kc_end) {
+    load_tile(kc_begin);
+    store_tile();
+  }
+  __syncthreads();
+  for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC) {
+    const bool more = kc0 + BKC < kc_end;
+    if (more) load_tile(kc0 + BKC);
+#pragma unroll
+    for (int k2 = 0; k2 < 2 * BKC; k2 += 2) {
+      const float a0 = As[wr + (lane & 31)][k2 + (lane >> 5)];
+      const float a1 = As[wr + 32 + (lane & 31)][k2 + (lane >> 5)];
+      const float x0 = Bs[k2 + (lane >> 5)][wc + (lane & 31)];
+      const float x1 = Bs[k2 + (lane >> 5)][wc + 32 + (lane & 31)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, x0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, x1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, x0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, x1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) store_tile();
+    __syncthreads();
+  }
+
+  float* Yf = reinterpret_cast<float*>(g.Y + s * g.y_slice_stride);
+  const int part = wc >> 6;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int row = m0 + wr + 32 * ti + i;
+      if (row >= g.M) continue;
+      const int b_0 = b0 + (lane & 31), b_1 = b0 + 32 + (lane & 31);
+      if (b_0 < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b_0) + part] = acc[ti][0][r];
+      if (b_1 < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b_1) + part] = acc[ti][1][r];
+    }
+}
+
 // out[i] = sum_s in[s * stride + i] for i < count (complex), fixed order.
 __global__ void __launch_bounds__(256) sum_slices_kernel(const float2* __restrict__ in, int slices, int64_t stride,
                                                         int64_t count, float2* __restrict__ out) {
@@ -145,10 +282,12 @@ void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stri
 int cgemm_f32_kslices(int kc) { return (kc + BKC - 1) / BKC; }
 
 // Launch Y[s] = A * sum(X slices) over split-K slices of `kslice` complex
-// columns (a multiple of 16; the number of slices is ceil(Kc / kslice)).
+// columns (a multiple of 16; the number of slices is ceil(Kc / kslice)),
+// with 64-row (tile = 64) or 128-row (tile = 128) blocks.  ldx and the X
+// slice stride must be even (two instances per 16-byte load).
 void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
                int x_slices, int64_t x_slice_stride, void* Y, int64_t ldy, int64_t y_slice_stride, int ncols,
-               int kslice) {
+               int kslice, int tile) {
   GemmArgs g;
   g.A = (const float2*)A;
   g.lda = lda;
@@ -164,8 +303,215 @@ void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, co
   g.ncols = ncols;
   g.kslice = kslice;
   const int splits = (Kc + kslice - 1) / kslice;
+  if (tile == 64) {
+    const dim3 grid((M + BM - 1) / BM, (ncols + BNI - 1) / BNI, splits);
+    hipLaunchKernelGGL(cgemm_f32_mfma, grid, dim3(256), 0, stream, g);
+    return;
+  }
+  const dim3 grid((M + BM2 - 1) / BM2, (ncols + BNI - 1) / BNI, splits);
+  const bool avec = ((lda & 1) == 0) && (((uintptr_t)A & 15) == 0);
+  if (avec)
+    hipLaunchKernelGGL(cgemm_f32_mfma_128<true>, grid, dim3(256), 0, stream, g);
+  else
+    hipLaunchKernelGGL(cgemm_f32_mfma_128<false>, grid, dim3(256), 0, stream, g);
+}
+
+}  // namespace tdg
+
+// ---- BF16 split-precision product ------------------------------------------
+// A in TDG_BF16X2 storage: a high plane of bf16 (re, im) pairs, row-major
+// [M][lda] complex, followed by a low plane of the same shape; the element is
+// hi + lo (about 16 significant bits).  X (complex64) is split the same way
+// while it is staged into LDS.  Y = A_hi X_hi + A_hi X_lo + A_lo X_hi with
+// FP32 accumulation (the dropped A_lo X_lo term is ~2^-16 relative) on
+// v_mfma_f32_32x32x16_bf16, whose operand layout (checked on the device) is:
+// lane l holds A[l%32][8*(l/32) + j] and B[8*(l/32) + j][l%32], j = 0..7.
+// Tiles: 64 rows x 64 instances per block, 32 complex K columns per LDS stage,
+// wave w owns rows 32*(w/2) .. +31 and real columns 64*(w%2) .. +63.  The
+// expanded X tile is kept transposed in LDS (column-major) so each lane's 8
+// consecutive K values are one 16-byte read.  Requires lda % 4 == 0.
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int BKC2 = 32;                 // complex K columns per stage
+constexpr int KR = 2 * BKC2;             // real K per stage
+constexpr int LPAD = 8;                  // bf16 padding per LDS row
+
+__device__ inline unsigned short f2bf(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);       // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+struct GemmBf16Args {
+  const unsigned short* Ahi;  // bf16 bits, [M][2*lda]
+  const unsigned short* Alo;
+  int64_t lda;                // complex elements per row
+  int M, Kc;
+  const float2* X;
+  int64_t ldx;
+  float2* Y;
+  int64_t ldy;
+  int64_t y_slice_stride;
+  int ncols;
+  int kslice;
+};
+
+__global__ void __launch_bounds__(256) cgemm_bf16x2_mfma(GemmBf16Args g) {
+  __shared__ __align__(16) unsigned short Ah[BM][KR + LPAD];
+  __shared__ __align__(16) unsigned short Al[BM][KR + LPAD];
+  __shared__ __align__(16) unsigned short Xh[2 * BNI][KR + LPAD];
+  __shared__ __align__(16) unsigned short Xl[2 * BNI][KR + LPAD];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.x * BM, b0 = blockIdx.y * BNI, s = blockIdx.z;
+  const int kc_begin = s * g.kslice;
+  const int kc_end = min(g.Kc, kc_begin + g.kslice);
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 64;
+  floatx16 acc0, acc1;
+  for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
+
+  // A loader: row t/4, real K 16*(t%4) .. +15 of both planes (2 x 16 B each)
+  const int arow = t >> 2, akr = (t & 3) * 16;
+  const int gi = m0 + arow;
+  // X loader: complex row t/8, instances 8*(t%8) .. +7
+  const int xrow = t >> 3, xcol = (t & 7) * 8;
+  for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC2) {
+    {
+      const int kr0 = 2 * kc0 + akr;              // real K index of this thread's chunk
+      const int kr_end = 2 * kc_end;
+      uint4 h0 = make_uint4(0, 0, 0, 0), h1 = h0, l0 = h0, l1 = h0;
+      if (gi < g.M) {
+        const int64_t off = (int64_t)gi * 2 * g.lda + kr0;
+        if (kr0 + 16 <= kr_end) {
+          h0 = *reinterpret_cast<const uint4*>(g.Ahi + off);
+          h1 = *reinterpret_cast<const uint4*>(g.Ahi + off + 8);
+          l0 = *reinterpret_cast<const uint4*>(g.Alo + off);
+          l1 = *reinterpret_cast<const uint4*>(g.Alo + off + 8);
+        } else {
+          unsigned short hb[16], lb[16];
+          for (int q = 0; q < 16; ++q) {
+            const bool in = kr0 + q < kr_end;
+            hb[q] = in ? g.Ahi[off + q] : (unsigned short)0;
+            lb[q] = in ? g.Alo[off + q] : (unsigned short)0;
+          }
+          h0 = *reinterpret_cast<uint4*>(hb);
+          h1 = *reinterpret_cast<uint4*>(hb + 8);
+          l0 = *reinterpret_cast<uint4*>(lb);
+          l1 = *reinterpret_cast<uint4*>(lb + 8);
+        }
+      }
+      *reinterpret_cast<uint4*>(&Ah[arow][akr]) = h0;
+      *reinterpret_cast<uint4*>(&Ah[arow][akr + 8]) = h1;
+      *reinterpret_cast<uint4*>(&Al[arow][akr]) = l0;
+      *reinterpret_cast<uint4*>(&Al[arow][akr + 8]) = l1;
+    }
+    {
+      const int kx = kc0 + xrow;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int b = b0 + xcol + q;
+        float2 v = make_float2(0.f, 0.f);
+        if (kx < kc_end && b < g.ncols) v = g.X[(int64_t)kx * g.ldx + b];
+        const unsigned short rh = f2bf(v.x), ih = f2bf(v.y);
+        const unsigned short rl = f2bf(v.x - bf2f(rh)), il = f2bf(v.y - bf2f(ih));
+        const unsigned short nih = ih ^ 0x8000u, nil = il ^ 0x8000u;  // -Im, exact
+        const int c = xcol + q, kr = 2 * xrow;
+        // real expansion: [2k][b] = re, [2k+1][b] = -im, [2k][64+b] = im, [2k+1][64+b] = re
+        *reinterpret_cast<unsigned int*>(&Xh[c][kr]) = (unsigned int)rh | ((unsigned int)nih << 16);
+        *reinterpret_cast<unsigned int*>(&Xh[BNI + c][kr]) = (unsigned int)ih | ((unsigned int)rh << 16);
+        *reinterpret_cast<unsigned int*>(&Xl[c][kr]) = (unsigned int)rl | ((unsigned int)nil << 16);
+        *reinterpret_cast<unsigned int*>(&Xl[BNI + c][kr]) = (unsigned int)il | ((unsigned int)rl << 16);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KR; ks += 16) {
+      const int kb = ks + 8 * (lane >> 5);
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Ah[wr + (lane & 31)][kb]);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(&Al[wr + (lane & 31)][kb]);
+      const bf16x8 xh0 = *reinterpret_cast<const bf16x8*>(&Xh[wc + (lane & 31)][kb]);
+      const bf16x8 xl0 = *reinterpret_cast<const bf16x8*>(&Xl[wc + (lane & 31)][kb]);
+      const bf16x8 xh1 = *reinterpret_cast<const bf16x8*>(&Xh[wc + 32 + (lane & 31)][kb]);
+      const bf16x8 xl1 = *reinterpret_cast<const bf16x8*>(&Xl[wc + 32 + (lane & 31)][kb]);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh0, acc0, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl0, acc0, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh1, acc1, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl1, acc1, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh1, acc1, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  float* Yf = reinterpret_cast<float*>(g.Y + s * g.y_slice_stride);
+  const int part = wc >> 6;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int row = m0 + wr + i;
+    if (row >= g.M) continue;
+    const int b_0 = b0 + (lane & 31), b_1 = b0 + 32 + (lane & 31);
+    if (b_0 < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b_0) + part] = acc0[r];
+    if (b_1 < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b_1) + part] = acc1[r];
+  }
+}
+
+// dst (TDG_BF16X2, [rows][ld_dst]) <- src complex (float or double, [rows][ld_src]);
+// columns cols .. ld_dst-1 of dst are zero-filled.
+template <typename S>
+__global__ void split_bf16x2_kernel(const S* __restrict__ src, int64_t ld_src, int64_t rows, int64_t cols,
+                                    unsigned short* __restrict__ dst, int64_t ld_dst) {
+  const int64_t plane = rows * ld_dst * 2;
+  const int64_t i = blockIdx.y;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ld_dst; c += (int64_t)gridDim.x * blockDim.x) {
+    float re = 0.f, im = 0.f;
+    if (c < cols) {
+      re = (float)src[i * ld_src + c].x;
+      im = (float)src[i * ld_src + c].y;
+    }
+    const unsigned short rh = f2bf(re), ih = f2bf(im);
+    const int64_t o = (i * ld_dst + c) * 2;
+    dst[o] = rh;
+    dst[o + 1] = ih;
+    dst[plane + o] = f2bf(re - bf2f(rh));
+    dst[plane + o + 1] = f2bf(im - bf2f(ih));
+  }
+}
+
+}  // namespace
+
+namespace tdg {
+
+void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
+                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice) {
+  GemmBf16Args g;
+  g.Ahi = (const unsigned short*)A;
+  g.Alo = (const unsigned short*)A + (int64_t)M * lda * 2;
+  g.lda = lda;
+  g.M = M;
+  g.Kc = Kc;
+  g.X = (const float2*)X;
+  g.ldx = ldx;
+  g.Y = (float2*)Y;
+  g.ldy = ldy;
+  g.y_slice_stride = y_slice_stride;
+  g.ncols = ncols;
+  g.kslice = kslice;
+  const int splits = (Kc + kslice - 1) / kslice;
   const dim3 grid((M + BM - 1) / BM, (ncols + BNI - 1) / BNI, splits);
-  hipLaunchKernelGGL(cgemm_f32_mfma, grid, dim3(256), 0, stream, g);
+  hipLaunchKernelGGL(cgemm_bf16x2_mfma, grid, dim3(256), 0, stream, g);
+}
+
+void split_bf16x2(hipStream_t stream, const void* src, int src_is_double, int64_t ld_src, int64_t rows, int64_t cols,
+                  void* dst, int64_t ld_dst) {
+  const dim3 grid((unsigned)std::min<int64_t>(64, (ld_dst + 255) / 256), (unsigned)rows);
+  if (src_is_double)
+    hipLaunchKernelGGL(split_bf16x2_kernel<double2>, grid, dim3(256), 0, stream, (const double2*)src, ld_src, rows,
+                       cols, (unsigned short*)dst, ld_dst);
+  else
+    hipLaunchKernelGGL(split_bf16x2_kernel<float2>, grid, dim3(256), 0, stream, (const float2*)src, ld_src, rows,
+                       cols, (unsigned short*)dst, ld_dst);
 }
 
 }  // namespace tdg

@@ -30,6 +30,9 @@ enum WsSlot {
   WS_PERM,       // sorted position -> caller's instance index, int [B]
   WS_Y,          // batched: contraction result / split-K partials, c64
   WS_ZSUM,       // batched low rank: projection summed over its split-K slices, c64
+  WS_TMP1,       // conversion staging (complex64 copies before a BF16X2 split)
+  WS_TMP2,
+  WS_TMP3,
   WS_COUNT
 };
 
@@ -57,6 +60,7 @@ struct tdg_ctx_s {
   bool autotune = true;
   int forced_variant = -1;
   int batched_min = 4;  // complex64 operators use the matrix-core path from this batch size
+  int gemm_tile = 64;   // rows per block of the matrix-core product (64 or 128)
   std::vector<std::pair<std::string, int>> tuned;  // shape key -> variant index
   std::string last_variant;
 };
@@ -79,7 +83,14 @@ void release_blas(tdg_ctx ctx);
 // Complex FP32 matrix-core product Y[s] = A * sum(X slices) (gemm.hip).
 void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
                int x_slices, int64_t x_slice_stride, void* Y, int64_t ldy, int64_t y_slice_stride, int ncols,
-               int kslice);
+               int kslice, int tile);
+// BF16 split-precision product: A in TDG_BF16X2 storage (hi plane, then lo
+// plane, [M][lda], lda % 4 == 0), X complex64 [Kc][ldx] (gemm.hip).
+void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
+                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice);
+// dst (TDG_BF16X2 [rows][ld_dst]) <- complex src [rows][ld_src]; columns >= cols zero.
+void split_bf16x2(hipStream_t stream, const void* src, int src_is_double, int64_t ld_src, int64_t rows, int64_t cols,
+                  void* dst, int64_t ld_dst);
 // out = sum of `slices` complex64 arrays of `count` elements, `stride` apart.
 void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stride, int64_t count, void* out);
 

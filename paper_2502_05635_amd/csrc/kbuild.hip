@@ -159,11 +159,13 @@ extern "C" int tdg_kernel_build(tdg_ctx ctx, const tdg_model* model, const tdg_c
   if (npair <= 0) return fail(ctx, TDG_E_INVAL, "unknown block %d", coul->block);
   if (model->nk1 != model->nk2)
     return fail(ctx, TDG_E_UNSUPPORTED, "the q = 0 cell average is implemented for square grids only");
-  if (dtype != TDG_C128 && dtype != TDG_C64) return fail(ctx, TDG_E_INVAL, "dtype %d", dtype);
+  if (dtype != TDG_C128 && dtype != TDG_C64 && dtype != TDG_BF16X2) return fail(ctx, TDG_E_INVAL, "dtype %d", dtype);
   const int nk = model->nk1 * model->nk2;
   const int64_t n = (int64_t)nk * npair;
   if (!K) return fail(ctx, TDG_E_INVAL, "K is NULL");
   if (ld < n) return fail(ctx, TDG_E_INVAL, "ld = %lld < N = %lld", (long long)ld, (long long)n);
+  if (dtype == TDG_BF16X2 && ((ld % 4) != 0 || ((uintptr_t)K & 15)))
+    return fail(ctx, TDG_E_INVAL, "BF16X2 storage needs ld %% 4 == 0 and a 16-byte aligned buffer");
   if (nk > 65535) return fail(ctx, TDG_E_UNSUPPORTED, "nk = %d exceeds the launch grid", nk);
   const int nquad = coul->nquad > 0 ? coul->nquad : 64;
   if (nquad > 4096) return fail(ctx, TDG_E_INVAL, "nquad = %d too large", nquad);
@@ -189,6 +191,19 @@ extern "C" int tdg_kernel_build(tdg_ctx ctx, const tdg_model* model, const tdg_c
   TDG_TRY(hip_check(ctx, hipMemcpyAsync(wdev, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
                     "W table upload"));
   dim3 grid((nk + 255) / 256, nk);
+  if (dtype == TDG_BF16X2) {
+    // build in complex64, then split into the hi / lo planes
+    void* tmp = nullptr;
+    TDG_TRY(ws_reserve(ctx, WS_TMP1, (size_t)n * n * sizeof(float2), &tmp));
+    hipLaunchKernelGGL(build_kernel_k<float>, grid, dim3(256), 0, ctx->stream, (const double*)wdev,
+                       (const double2*)model->evec, model->nk1, model->nk2, model->nb, model->nv, coul->block, npair,
+                       (float2*)tmp, n);
+    TDG_TRY(launch_check(ctx, "build_kernel launch"));
+    if (n > 65535) return fail(ctx, TDG_E_UNSUPPORTED, "N exceeds the conversion grid");
+    split_bf16x2(ctx->stream, tmp, 0, n, n, n, K, ld);
+    TDG_TRY(launch_check(ctx, "bf16 split launch"));
+    return hip_check(ctx, hipStreamSynchronize(ctx->stream), "kernel build sync");
+  }
   if (dtype == TDG_C128)
     hipLaunchKernelGGL(build_kernel_k<double>, grid, dim3(256), 0, ctx->stream, (const double*)wdev,
                        (const double2*)model->evec, model->nk1, model->nk2, model->nb, model->nv, coul->block, npair,

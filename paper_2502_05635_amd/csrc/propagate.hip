@@ -800,14 +800,16 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   if (!ctx) return TDG_E_INVAL;
   TDG_TRY(validate_model(ctx, model));
   if (!op) return fail(ctx, TDG_E_INVAL, "operator is NULL");
-  if (op->dtype != TDG_C128 && op->dtype != TDG_C64) return fail(ctx, TDG_E_INVAL, "operator dtype %d", op->dtype);
+  if (op->dtype != TDG_C128 && op->dtype != TDG_C64 && op->dtype != TDG_BF16X2)
+    return fail(ctx, TDG_E_INVAL, "operator dtype %d", op->dtype);
+  const bool bf16 = op->dtype == TDG_BF16X2;
   const int npair = pairs_per_k(model, op->block);
   if (npair <= 0) return fail(ctx, TDG_E_INVAL, "unknown block %d", op->block);
   const int nk = model->nk1 * model->nk2;
   const int64_t n = (int64_t)nk * npair;
   if (op->n != n) return fail(ctx, TDG_E_INVAL, "operator n = %lld, model gives N = %lld", (long long)op->n, (long long)n);
   if (n > ((int64_t)1 << 30)) return fail(ctx, TDG_E_UNSUPPORTED, "N = %lld too large", (long long)n);
-  const size_t elt = op->dtype == TDG_C128 ? 16 : 8;
+  const size_t elt = op->dtype == TDG_C128 ? 16 : 8;  // x and z are complex64 for C64 and BF16X2
   const bool lowrank = op->kind == TDG_OP_LOWRANK;
   const void* A = nullptr;
   int64_t lda = 0;
@@ -829,6 +831,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   }
   if (((uintptr_t)A | (uintptr_t)op->kdiag | (uintptr_t)op->w) & (elt == 16 ? 15 : 7))
     return fail(ctx, TDG_E_INVAL, "operator arrays must be aligned to their complex element size");
+  if (bf16 && ((((uintptr_t)A | (uintptr_t)op->w) & 15) || (op->kind == TDG_OP_DENSE && op->ld % 4 != 0) ||
+               (lowrank && n % 4 != 0)))
+    return fail(ctx, TDG_E_INVAL, "BF16X2 operators need 16-byte aligned planes and row strides that are multiples of 4");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, TDG_E_INVAL, "dt must be positive");
   if (!rho || ((uintptr_t)rho & 15)) return fail(ctx, TDG_E_INVAL, "rho NULL or not 16-byte aligned");
   int64_t max_steps = 0;
@@ -853,10 +858,11 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const int nb2 = model->nb * model->nb;
   const size_t state_bytes = (size_t)batch * nk * nb2 * sizeof(double2);
   // matrix-core path: complex64 operator and enough instances
-  const bool batched = op->dtype == TDG_C64 && batch >= ctx->batched_min;
+  const bool batched = bf16 || (op->dtype == TDG_C64 && batch >= ctx->batched_min);
   if (batched && (nb2 > 256 || n > 2147483647 / 2))
     return fail(ctx, TDG_E_UNSUPPORTED, "batched path: nb^2 <= 256 and N < 2^30 required");
-  const int64_t xstride = batched ? (int64_t)batch : ((n + 1) & ~int64_t(1));
+  // batched rows hold an even number of instances (two per 16-byte load)
+  const int64_t xstride = batched ? (((int64_t)batch + 1) & ~int64_t(1)) : ((n + 1) & ~int64_t(1));
   const int64_t zstride = (op->rank + 1) & ~int64_t(1);
   void *rho_n, *rho_s, *acc, *x0, *x1, *z = nullptr, *part, *dperm, *dfields;
   TDG_TRY(ws_reserve(ctx, WS_RHO_N, state_bytes, &rho_n));
@@ -947,14 +953,15 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   if (batched) {
     // split-K so that each product launches about 1024 blocks; slices are
     // multiples of 16 complex columns (the GEMM's LDS stage)
+    const int tile = ctx->gemm_tile;
     auto kslice_for = [&](int64_t M, int64_t Kc) {
-      const int64_t tiles = ((M + 63) / 64) * ((batch + 63) / 64);
+      const int64_t tiles = ((M + tile - 1) / tile) * ((batch + 63) / 64);
       int64_t splits = std::max<int64_t>(1, std::min<int64_t>(64, (1024 + tiles - 1) / tiles));
       int64_t ks = (Kc + splits - 1) / splits;
-      ks = std::max<int64_t>(16, (ks + 15) / 16 * 16);
+      ks = std::max<int64_t>(32, (ks + 31) / 32 * 32);
       return ks;
     };
-    const int64_t ldy = batch;
+    const int64_t ldy = xstride;
     int64_t ks_main, ks_proj = 0;
     int y_slices, z_slices = 0;
     void* Ybuf = nullptr;
@@ -968,9 +975,12 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       ks_proj = kslice_for(op->rank, n);
       z_slices = (int)((n + ks_proj - 1) / ks_proj);
       TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)z_slices * op->rank * ldy * 8, &Zbuf));
-      ks_main = (op->rank + 15) / 16 * 16;
-      y_slices = 1;
-      TDG_TRY(ws_reserve(ctx, WS_Y, (size_t)n * ldy * 8, &Ybuf));
+      // the expansion has few K columns (the rank): split it too, at most 8
+      // ways, and let the stage kernel sum the slices it reads
+      ks_main = std::max<int64_t>(kslice_for(n, op->rank), (op->rank + 7) / 8);
+      ks_main = (ks_main + 31) / 32 * 32;
+      y_slices = (int)((op->rank + ks_main - 1) / ks_main);
+      TDG_TRY(ws_reserve(ctx, WS_Y, (size_t)y_slices * n * ldy * 8, &Ybuf));
       TDG_TRY(ws_reserve(ctx, WS_ZSUM, (size_t)op->rank * ldy * 8, &Zsum));
     }
     BatchParams bp = {};
@@ -996,7 +1006,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     bp.batch = batch;
     bp.dt = dt;
     const int ib = 256 / nb2;
-    ctx->last_variant = lowrank ? "batched_mfma_lowrank_f32" : "batched_mfma_dense_f32";
+    ctx->last_variant = std::string(lowrank ? "batched_mfma_lowrank_" : "batched_mfma_dense_") +
+                        (bf16 ? "bf16x2" : "f32");
     tdg_obs ob = *obs;
     void* xc = x0;
     void* xn = x1;
@@ -1010,16 +1021,29 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         if (active == 0) break;
         if (n_dyn > 0) {
           prof_begin(ctx, TDG_KCLASS_GEMM);
+          const int64_t ld_us = bf16 ? (op->rank + 3) / 4 * 4 : op->rank;
           if (!lowrank) {
-            cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xc, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
-                      (int)ks_main);
+            if (bf16)
+              cgemm_bf16x2(ctx->stream, op->K, op->ld, (int)n, (int)n, xc, xstride, Ybuf, ldy, n * ldy, n_dyn,
+                           (int)ks_main);
+            else
+              cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xc, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
+                        (int)ks_main, tile);
           } else {
             // projection split over K, summed once in fixed order, then expansion
-            cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xc, xstride, 1, 0, Zbuf, ldy,
-                      op->rank * ldy, n_dyn, (int)ks_proj);
+            if (bf16)
+              cgemm_bf16x2(ctx->stream, op->w, n, (int)op->rank, (int)n, xc, xstride, Zbuf, ldy, op->rank * ldy,
+                           n_dyn, (int)ks_proj);
+            else
+              cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xc, xstride, 1, 0, Zbuf, ldy,
+                        op->rank * ldy, n_dyn, (int)ks_proj, tile);
             sum_slices_c64(ctx->stream, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
-            cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, 0, n_dyn,
-                      (int)ks_main);
+            if (bf16)
+              cgemm_bf16x2(ctx->stream, op->us, ld_us, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
+                           (int)ks_main);
+            else
+              cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy,
+                        n_dyn, (int)ks_main, tile);
           }
           prof_end(ctx, TDG_KCLASS_GEMM);
         }

@@ -382,3 +382,45 @@ def test_batched_full_size_first_steps_vs_oracle(P, ctx):
             e = err_rel(res[key][b].cpu().numpy(), ref[key])
             _log(f"  instance {b} err_{key} = {e:.2e}")
             assert e <= 1e-4, (b, key)
+
+
+# --- BF16 split-precision operators ------------------------------------------
+
+def test_bf16x2_kernel_storage(P, ctx, tb4_6, k_tb4_6):
+    """hi + lo planes reconstruct the kernel to ~2^-16 of its largest element."""
+    kb = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", "bf16x2")
+    raw = kb.data.view(torch.int16).cpu().numpy().view(np.uint16).astype(np.uint32)
+    plane = kb.rows * kb.ld * 2
+    as_f = lambda u: (u << 16).view(np.float32).astype(np.float64)  # noqa: E731
+    hi, lo = as_f(raw[:plane]), as_f(raw[plane:2 * plane])
+    v = (hi + lo).reshape(kb.rows, kb.ld, 2)
+    rec = v[:, : kb.cols, 0] + 1j * v[:, : kb.cols, 1]
+    assert np.abs(rec - k_tb4_6).max() <= 2.0 ** -15 * np.abs(k_tb4_6).max()
+    assert np.all(v[:, kb.cols:] == 0)
+
+
+@pytest.mark.parametrize("kind", ["dense", "lowrank"])
+def test_bf16x2_batched_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind):
+    """BF16 split-precision products (FP32 accumulation) against the FP64
+    oracle on an uneven batch; the error is printed per instance."""
+    fields = _uneven_fields(6)
+    dm = _dev(P, tb4_6)
+    if kind == "dense":
+        op = ctx.kernel_build(dm, R0_STABLE, "eh", "bf16x2")
+        oracle_op = O.DenseOp(k_tb4_6)
+    else:
+        kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c64")
+        op = ctx.kernel_compress(kg, "rank", 37, out_dtype="bf16x2")
+        oracle_op = O.LowRankOp.from_factors(O.compress(k_tb4_6, "rank", 37))
+    res = ctx.propagate(op, dm, "eh", fields, DT)
+    assert ctx.last_variant().endswith("bf16x2")
+    worst = 0.0
+    for b in range(fields.batch):
+        ref = O.propagate(tb4_6, oracle_op, "eh", fields, DT, instance=b)
+        nsb = int(fields.nsteps[b])
+        for key in ("P", "J"):
+            got = res[key][b, : nsb + 1].cpu().numpy()
+            scale = max(np.abs(ref[key]).max(), 1e-300)
+            worst = max(worst, float(np.abs(got - ref[key]).max() / scale))
+    _log(f"  bf16x2 {kind}: worst err over P, J and instances = {worst:.2e}")
+    assert worst <= 1e-4
