@@ -159,6 +159,33 @@ typedef struct {
 int tdg_kernel_compress(tdg_ctx ctx, const void* K, int64_t ld, int32_t dtype,
                         const tdg_trunc* trunc, tdg_lowrank* out);
 
+/* Same truncated factorisation as tdg_kernel_compress, for kernels too large
+ * for an exact eigendecomposition (N in the tens of thousands).  Not the
+ * paper's method: a randomized range finder with power iterations and a
+ * Rayleigh-Ritz step on the Hermitian K_off (Halko, Martinsson, Tropp, SIAM
+ * Review 53 (2011), Algs. 4.3/4.4 and 5.3), all in FP64 except the products
+ * with K, which run in the precision of K:
+ *   Y = K_off Omega; power_iters times { Q = qr(Y); Y = K_off Q };
+ *   Q = qr(Y); T = Q^H K_off Q = W L W^H; keep the largest |l|;
+ *   S = (Q W)_r L_r, V^H = (Q W)_r^H.
+ *   K       device, dtype TDG_C128 or TDG_C64, row-major [n][ld], Hermitian
+ *   omega   device c128, the n x l test matrix stored column by column
+ *           (omega[j * n + i] = Omega_{ij}); the caller draws it
+ *   l       number of test vectors, rank + oversampling, 1 <= l <= n
+ * The rank rules read the l Ritz values |l| as singular values, with
+ * ||K_off||_F and the mean of K_off computed exactly from K; a rule whose
+ * rank is not reached within the l values fails with TDG_E_INVAL.
+ * out->sigma (if not NULL) receives the l Ritz values, descending;
+ * tail_fro = sqrt(max(0, ||K_off||_F^2 - sum_{i < rank} s_i^2)) and tail_spec
+ * = s_rank are the corresponding estimates (exact when the range is; tail_spec
+ * is NaN when rank == l < n).
+ * Output dtypes and layouts as for tdg_kernel_compress.  Device workspace
+ * about (3 n l + l^2) * 16 bytes, held by the context.  Synchronises the
+ * stream. */
+int tdg_kernel_compress_randomized(tdg_ctx ctx, const void* K, int64_t ld, int32_t dtype,
+                                   const tdg_trunc* trunc, const void* omega, int64_t l,
+                                   int32_t power_iters, tdg_lowrank* out);
+
 /* One driving-field instance (atomic units): a Gaussian-enveloped carrier
  * E(t) = e0 exp(-(t - t0)^2 / (2 tau^2)) cos(omega t) along (ex, ey), run for
  * nsteps RK4 steps.  64 bytes; arrays of it are HOST memory. */

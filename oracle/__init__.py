@@ -22,7 +22,7 @@ from .kernel import (  # noqa: F401
     pair_table, rytova_keldysh, cell_average_w0, fold_q, coulomb_matrix, build_kernel,
     kernel_element,
 )
-from .compress import split_diag, svd_offdiag, choose_rank, compress  # noqa: F401
+from .compress import split_diag, svd_offdiag, choose_rank, compress, randomized_compress  # noqa: F401
 from .propagate import field_at, DenseOp, LowRankOp, propagate, rho_equilibrium  # noqa: F401
 from .observables import observables  # noqa: F401
 from .bse import linear_operator, linear_response  # noqa: F401

@@ -90,3 +90,39 @@ def compress(k: np.ndarray, rule: str = "rel_cut", value: float = 1e-3, method: 
         "tail_fro": float(np.sqrt(np.sum(s[r:] ** 2))),
         "tail_spec": float(s[r]) if r < s.shape[0] else 0.0,
     }
+
+
+def randomized_compress(k: np.ndarray, rank: int, omega: np.ndarray, power_iters: int = 2):
+    """Truncated factorisation of K through a randomized range finder.
+
+    Not part of the paper (its SVD is exact); a standard randomized range
+    finder with power iterations and a Rayleigh-Ritz step on the Hermitian
+    K_off (Halko, Martinsson and Tropp, SIAM Review 53 (2011), Algs. 4.3/4.4
+    and 5.3), used when an exact decomposition of K_off is too large:
+      Y = K_off Omega;  repeat power_iters times: Q = orth(Y), Y = K_off Q;
+      Q = orth(Y);  T = Q^H K_off Q;  T = W diag(l) W^H;
+      keep the `rank` largest |l| (never splitting equal values);
+      S = (Q W)_r diag(l_r),  V^H = (Q W)_r^H.
+    omega: [n][l] test matrix, l >= rank.  Returns the dict of compress().
+    """
+    kdiag, koff = split_diag(k)
+    y = koff @ omega
+    for _ in range(power_iters):
+        q, _ = np.linalg.qr(y)
+        y = koff @ q
+    q, _ = np.linalg.qr(y)
+    t = q.conj().T @ (koff @ q)
+    t = 0.5 * (t + t.conj().T)
+    lam, w = np.linalg.eigh(t)
+    order = np.argsort(-np.abs(lam), kind="stable")
+    lam, w = lam[order], w[:, order]
+    s = np.abs(lam)
+    r = choose_rank(s, "rank", rank)
+    u = q @ w[:, :r]
+    return {
+        "kdiag": kdiag,
+        "US": np.ascontiguousarray(u * lam[None, :r]),
+        "Vh": np.ascontiguousarray(u.conj().T),
+        "s": s,
+        "r": r,
+    }

@@ -195,11 +195,42 @@ class Context:
                          sigma.ctypes.data, 0, 0.0, 0.0)
         tr = abi.Trunc(abi.TDG_TRUNC[rule], 0, float(value))
         self._check(self._lib.tdg_kernel_compress(self.h, _ptr(K), K.stride(0), kcode, C.byref(tr), C.byref(lr)))
-        r = int(lr.rank)
+        return self._factors(kdiag, us, w, sigma, lr, dtype)
+
+    @staticmethod
+    def _factors(kdiag, us, w, sigma, lr, dtype) -> LowRankFactors:
+        n, r = int(lr.n), int(lr.rank)
         if dtype == "bf16x2":
             return LowRankFactors(kdiag, us, w, sigma, r, lr.tail_fro, lr.tail_spec, dtype)
         return LowRankFactors(kdiag, us[: n * r].view(n, r), w[: n * r].view(r, n), sigma, r,
                               lr.tail_fro, lr.tail_spec, dtype)
+
+    def kernel_compress_randomized(self, K: torch.Tensor, omega_t: torch.Tensor, rule: str = "rank",
+                                   value: float = 1.0, power_iters: int = 2, max_rank: int | None = None,
+                                   out_dtype: str | None = None) -> LowRankFactors:
+        """Randomized range-finder factorisation of K_off.  omega_t is the
+        test matrix transposed, a contiguous complex128 device tensor [l][n]
+        (row j = test vector j); sigma holds the l Ritz values."""
+        kdtype = "c128" if K.dtype == torch.complex128 else "c64"
+        kcode, _ = _cdtype(kdtype)
+        dtype = out_dtype or kdtype
+        code, tdt = _cdtype(dtype)
+        n = K.shape[0]
+        if omega_t.dtype != torch.complex128 or not omega_t.is_contiguous() or omega_t.shape[1] != n:
+            raise ValueError("omega_t must be a contiguous complex128 tensor [l][n]")
+        l = omega_t.shape[0]
+        max_rank = min(n, l) if max_rank is None else int(max_rank)
+        dev = K.device
+        kdiag = torch.empty(n, dtype=tdt, device=dev)
+        us = torch.empty(n * (max_rank + 3), dtype=tdt, device=dev)
+        w = torch.empty(n * max_rank, dtype=tdt, device=dev)
+        sigma = np.zeros(l, dtype=np.float64)
+        lr = abi.LowRank(n, max_rank, code, 0, kdiag.data_ptr(), us.data_ptr(), w.data_ptr(),
+                         sigma.ctypes.data, 0, 0.0, 0.0)
+        tr = abi.Trunc(abi.TDG_TRUNC[rule], 0, float(value))
+        self._check(self._lib.tdg_kernel_compress_randomized(self.h, _ptr(K), K.stride(0), kcode, C.byref(tr),
+                                                             _ptr(omega_t), l, int(power_iters), C.byref(lr)))
+        return self._factors(kdiag, us, w, sigma, lr, dtype)
 
     # --- propagation --------------------------------------------------------
     def _operator(self, op, block: str, n: int) -> abi.Operator:

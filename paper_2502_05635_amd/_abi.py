@@ -74,6 +74,8 @@ SIGNATURES = {
     "tdg_kernel_dim": ([C.POINTER(Model), C.c_int32, C.POINTER(C.c_int64)], C.c_int),
     "tdg_kernel_build": ([P, C.POINTER(Model), C.POINTER(Coulomb), C.c_int32, P, C.c_int64], C.c_int),
     "tdg_kernel_compress": ([P, P, C.c_int64, C.c_int32, C.POINTER(Trunc), C.POINTER(LowRank)], C.c_int),
+    "tdg_kernel_compress_randomized": ([P, P, C.c_int64, C.c_int32, C.POINTER(Trunc), P, C.c_int64, C.c_int32,
+                                        C.POINTER(LowRank)], C.c_int),
     "tdg_propagate": ([P, C.POINTER(Operator), C.POINTER(Model), C.POINTER(Field), C.c_int32, C.c_double, P,
                        C.c_int32, C.POINTER(Obs)], C.c_int),
     "tdg_observables": ([P, C.POINTER(Model), P, C.c_int32, C.POINTER(Field), P], C.c_int),

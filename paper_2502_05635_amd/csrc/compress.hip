@@ -104,6 +104,70 @@ __global__ void gather_kernel(const double2* __restrict__ Q, int64_t n, const in
   }
 }
 
+// Per-row sums of K_off (re, im, |.|^2) in FP64 for the rank rules, and the
+// diagonal of K.  One row of K per block, coalesced over columns.
+template <typename T>
+__global__ void __launch_bounds__(256) koff_stats_kernel(const typename Cx<T>::type* __restrict__ K, int64_t ld,
+                                                         int64_t n, double2* __restrict__ kdiag,
+                                                         double* __restrict__ stats) {
+  __shared__ double sh[3][256];
+  const int64_t r = blockIdx.x;
+  double a = 0.0, b = 0.0, m = 0.0;
+  for (int64_t c = threadIdx.x; c < n; c += 256) {
+    const auto v = K[r * ld + c];
+    const double x = (double)v.x, y = (double)v.y;
+    if (c == r) {
+      kdiag[r] = make_double2(x, y);
+      continue;
+    }
+    a += x;
+    b += y;
+    m += x * x + y * y;
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) stats[3 * r + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void to_c64_kernel(const double2* __restrict__ in, int64_t total, float2* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+// Y = KX - diag(K) X for an n-row column-major block (K_off X from K X).
+template <typename T>
+__global__ void diag_sub_kernel(const typename Cx<T>::type* __restrict__ KX, const double2* __restrict__ X,
+                                const double2* __restrict__ kd, int64_t n, int64_t total, double2* __restrict__ Y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 d = kd[i % n];
+    const double2 x = X[i];
+    const auto p = KX[i];
+    Y[i] = make_double2((double)p.x - (d.x * x.x - d.y * x.y), (double)p.y - (d.x * x.y + d.y * x.x));
+  }
+}
+
+// T <- (T + T^H) / 2 for a column-major l x l matrix; one thread per pair.
+__global__ void hermitize_kernel(double2* __restrict__ T, int64_t l) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i > j || j >= l) return;
+  if (i == j) {
+    T[i + j * l].y = 0.0;
+    return;
+  }
+  const double2 a = T[i + j * l], b = T[j + i * l];
+  const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  T[i + j * l] = m;
+  T[j + i * l] = make_double2(m.x, -m.y);
+}
+
 }  // namespace
 
 namespace tdg {
@@ -113,6 +177,57 @@ void release_blas(tdg_ctx ctx) {
     rocblas_destroy_handle((rocblas_handle)ctx->blas);
     ctx->blas = nullptr;
   }
+}
+
+static int blas_handle(tdg_ctx ctx, rocblas_handle* out) {
+  if (!ctx->blas) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_create_handle");
+    ctx->blas = h;
+  }
+  *out = (rocblas_handle)ctx->blas;
+  if (rocblas_set_stream(*out, ctx->stream) != rocblas_status_success)
+    return fail(ctx, TDG_E_SOLVER, "rocblas_set_stream");
+  return TDG_OK;
+}
+
+// Writes kdiag (from its FP64 copy KD) and the factors S = Q[:, perm] diag(kept),
+// V^H = Q[:, perm]^H from the column-major n-row matrix Q, in out->dtype.
+static int write_factors(tdg_ctx ctx, const double2* KD, const double2* Q, int64_t n, int64_t r,
+                         const std::vector<int>& perm, const std::vector<double>& kept, tdg_lowrank* out) {
+  const int bx = (int)std::min<int64_t>((n + 255) / 256, 64);
+  if (out->dtype == TDG_C128)
+    hipLaunchKernelGGL(kdiag_out_kernel<double>, dim3(bx), dim3(256), 0, ctx->stream, KD, n, (double2*)out->kdiag);
+  else
+    hipLaunchKernelGGL(kdiag_out_kernel<float>, dim3(bx), dim3(256), 0, ctx->stream, KD, n, (float2*)out->kdiag);
+  TDG_TRY(launch_check(ctx, "compress diagonal"));
+  if (r > 65535) return fail(ctx, TDG_E_UNSUPPORTED, "rank exceeds the launch grid");
+  void* I = nullptr;
+  TDG_TRY(ws_reserve(ctx, WS_SOLVER_I, (size_t)r * (sizeof(int) + sizeof(double)) + 256, &I));
+  int* dperm = (int*)I;
+  double* dkept = (double*)((char*)I + (((size_t)r * sizeof(int) + 255) / 256) * 256);
+  TDG_TRY(hip_check(ctx, hipMemcpy(dperm, perm.data(), r * sizeof(int), hipMemcpyHostToDevice), "perm upload"));
+  TDG_TRY(hip_check(ctx, hipMemcpy(dkept, kept.data(), r * sizeof(double), hipMemcpyHostToDevice), "lambda upload"));
+  if (out->dtype == TDG_C128) {
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, Q, n, dperm, dkept, r,
+                       (double2*)out->us, (double2*)out->w);
+  } else if (out->dtype == TDG_C64) {
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, Q, n, dperm, dkept, r,
+                       (float2*)out->us, (float2*)out->w);
+  } else {
+    // gather in FP64, then split into hi / lo planes (us row stride: rank rounded up to 4)
+    void *tus = nullptr, *tw = nullptr;
+    TDG_TRY(ws_reserve(ctx, WS_TMP1, (size_t)n * r * sizeof(double2), &tus));
+    TDG_TRY(ws_reserve(ctx, WS_TMP3, (size_t)n * r * sizeof(double2), &tw));
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, Q, n, dperm, dkept, r,
+                       (double2*)tus, (double2*)tw);
+    TDG_TRY(launch_check(ctx, "compress gather"));
+    const int64_t ld_us = (r + 3) / 4 * 4;
+    split_bf16x2(ctx->stream, tus, 1, r, n, r, out->us, ld_us);
+    split_bf16x2(ctx->stream, tw, 1, n, r, n, out->w, n);
+  }
+  TDG_TRY(launch_check(ctx, "compress gather"));
+  return hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress sync");
 }
 
 // Rank rule on singular values s (descending).  dev2 = sum |K_off - mean|^2.
@@ -183,23 +298,12 @@ extern "C" int tdg_kernel_compress(tdg_ctx ctx, const void* K, int64_t ld, int32
   else
     hipLaunchKernelGGL(prep_kernel<float>, dim3(bx, (unsigned)n), dim3(256), 0, ctx->stream, (const float2*)K, ld, n,
                        (double2*)A, (double2*)KD);
-  if (out->dtype == TDG_C128)
-    hipLaunchKernelGGL(kdiag_out_kernel<double>, dim3(bx), dim3(256), 0, ctx->stream, (const double2*)KD, n,
-                       (double2*)out->kdiag);
-  else
-    hipLaunchKernelGGL(kdiag_out_kernel<float>, dim3(bx), dim3(256), 0, ctx->stream, (const double2*)KD, n,
-                       (float2*)out->kdiag);
   TDG_TRY(launch_check(ctx, "compress prep"));
   hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)n), dim3(256), 0, ctx->stream, (const double2*)A, n, (double2*)M);
   TDG_TRY(launch_check(ctx, "compress row sums"));
 
-  if (!ctx->blas) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_create_handle");
-    ctx->blas = h;
-  }
-  rocblas_handle h = (rocblas_handle)ctx->blas;
-  if (rocblas_set_stream(h, ctx->stream) != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_set_stream");
+  rocblas_handle h = nullptr;
+  TDG_TRY(blas_handle(ctx, &h));
   double* dvals = (double*)D;
   double* evals_off = dvals + n;
   int* info = (int*)I;
@@ -249,29 +353,195 @@ extern "C" int tdg_kernel_compress(tdg_ctx ctx, const void* K, int64_t ld, int32
     perm[c] = order[c];
     kept[c] = lam[order[c]];
   }
-  int* dperm = (int*)((char*)I + 256);
-  double* dkept = (double*)M;  // row sums are no longer needed
-  TDG_TRY(hip_check(ctx, hipMemcpy(dperm, perm.data(), r * sizeof(int), hipMemcpyHostToDevice), "perm upload"));
-  TDG_TRY(hip_check(ctx, hipMemcpy(dkept, kept.data(), r * sizeof(double), hipMemcpyHostToDevice), "lambda upload"));
-  if (r > 65535) return fail(ctx, TDG_E_UNSUPPORTED, "rank exceeds the launch grid");
-  if (out->dtype == TDG_C128) {
-    hipLaunchKernelGGL(gather_kernel<double>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, (const double2*)A, n,
-                       dperm, dkept, r, (double2*)out->us, (double2*)out->w);
-  } else if (out->dtype == TDG_C64) {
-    hipLaunchKernelGGL(gather_kernel<float>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, (const double2*)A, n,
-                       dperm, dkept, r, (float2*)out->us, (float2*)out->w);
+  return write_factors(ctx, (const double2*)KD, (const double2*)A, n, r, perm, kept, out);
+}
+
+// Rank rule on the l Ritz values s (descending) of an n x n K_off with
+// ||K_off||_F^2 = fro2 and sum |K_off - mean|^2 = dev2.  Returns -1 when the
+// rule's rank cannot be decided within the l values.
+static int64_t choose_rank_ritz(const std::vector<double>& s, int64_t n, int mode, double value, double fro2,
+                                double dev2) {
+  const int64_t l = (int64_t)s.size();
+  int64_t r = -1;
+  if (mode == TDG_TRUNC_REL_CUT) {
+    r = 0;
+    for (int64_t i = 0; i < l; ++i)
+      if (s[i] > value * s[0]) ++r;
+    if (r == l && l < n) return -1;  // values beyond the range block may still pass the cut
+  } else if (mode == TDG_TRUNC_FRACTION) {
+    r = std::max<int64_t>(1, (int64_t)std::llround(value * (double)n));
+  } else if (mode == TDG_TRUNC_RANK) {
+    r = (int64_t)value;
   } else {
-    // gather in FP64, then split into hi / lo planes (us row stride: rank rounded up to 4)
-    void *tus = nullptr, *tw = nullptr;
-    TDG_TRY(ws_reserve(ctx, WS_TMP1, (size_t)n * r * sizeof(double2), &tus));
-    TDG_TRY(ws_reserve(ctx, WS_TMP3, (size_t)n * r * sizeof(double2), &tw));
-    hipLaunchKernelGGL(gather_kernel<double>, dim3(bx, (unsigned)r), dim3(256), 0, ctx->stream, (const double2*)A, n,
-                       dperm, dkept, r, (double2*)tus, (double2*)tw);
-    TDG_TRY(launch_check(ctx, "compress gather"));
-    const int64_t ld_us = (r + 3) / 4 * 4;
-    split_bf16x2(ctx->stream, tus, 1, r, n, r, out->us, ld_us);
-    split_bf16x2(ctx->stream, tw, 1, n, r, n, out->w, n);
+    double kept = 0.0;
+    for (int64_t i = 0; i <= l; ++i) {
+      if (1.0 - std::max(0.0, fro2 - kept) / dev2 >= value) {
+        r = i;
+        break;
+      }
+      if (i < l) kept += s[i] * s[i];
+    }
+    if (r < 0) return -1;
   }
-  TDG_TRY(launch_check(ctx, "compress gather"));
-  return hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress sync");
+  if (r > l) return -1;
+  while (r > 0 && r < l && s[r - 1] - s[r] <= MULTIPLET_TOL * s[0]) ++r;
+  return r;
+}
+
+extern "C" int tdg_kernel_compress_randomized(tdg_ctx ctx, const void* K, int64_t ld, int32_t dtype,
+                                              const tdg_trunc* trunc, const void* omega, int64_t l,
+                                              int32_t power_iters, tdg_lowrank* out) {
+  if (!ctx) return TDG_E_INVAL;
+  if (!K || !trunc || !out || !omega) return fail(ctx, TDG_E_INVAL, "NULL argument");
+  if (dtype != TDG_C128 && dtype != TDG_C64) return fail(ctx, TDG_E_INVAL, "dtype %d", dtype);
+  if (out->dtype != TDG_C128 && out->dtype != TDG_C64 && out->dtype != TDG_BF16X2)
+    return fail(ctx, TDG_E_INVAL, "output dtype %d", out->dtype);
+  const int64_t n = out->n;
+  if (n < 2 || n > 200000) return fail(ctx, TDG_E_INVAL, "n = %lld outside [2, 200000]", (long long)n);
+  if (ld < n) return fail(ctx, TDG_E_INVAL, "ld < n");
+  if (l < 1 || l > n || l > 32768) return fail(ctx, TDG_E_INVAL, "l = %lld outside [1, min(n, 32768)]", (long long)l);
+  if (power_iters < 0 || power_iters > 16) return fail(ctx, TDG_E_INVAL, "power_iters outside [0, 16]");
+  if (out->max_rank < 1 || out->max_rank > n) return fail(ctx, TDG_E_INVAL, "max_rank outside [1, n]");
+  if (!out->kdiag || !out->us || !out->w) return fail(ctx, TDG_E_INVAL, "output factor pointer is NULL");
+  if (out->dtype == TDG_BF16X2 && ((n % 4) != 0 || (((uintptr_t)out->us | (uintptr_t)out->w) & 15)))
+    return fail(ctx, TDG_E_UNSUPPORTED, "BF16X2 factors need n %% 4 == 0 and 16-byte aligned buffers");
+  if (trunc->mode < TDG_TRUNC_REL_CUT || trunc->mode > TDG_TRUNC_R2)
+    return fail(ctx, TDG_E_INVAL, "truncation mode %d", trunc->mode);
+  if (!std::isfinite(trunc->value) || trunc->value < 0.0) return fail(ctx, TDG_E_INVAL, "truncation value");
+  if (dtype == TDG_C64 && (((uintptr_t)K & 7) != 0)) return fail(ctx, TDG_E_INVAL, "C64 kernel must be 8-byte aligned");
+  TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+
+  const size_t nl = (size_t)n * (size_t)l;
+  void *Y = nullptr, *Z = nullptr, *F = nullptr, *T = nullptr, *D = nullptr, *I = nullptr, *ST = nullptr, *KD = nullptr;
+  TDG_TRY(ws_reserve(ctx, WS_RSVD_Y, nl * sizeof(double2), &Y));
+  TDG_TRY(ws_reserve(ctx, WS_RSVD_Z, nl * sizeof(double2), &Z));
+  if (dtype == TDG_C64) TDG_TRY(ws_reserve(ctx, WS_RSVD_F, 2 * nl * sizeof(float2), &F));
+  const size_t t_bytes = ((size_t)l * l * sizeof(double2) + 255) / 256 * 256;
+  TDG_TRY(ws_reserve(ctx, WS_RSVD_T, t_bytes + (size_t)l * sizeof(double2), &T));
+  TDG_TRY(ws_reserve(ctx, WS_SOLVER_D, (size_t)2 * l * sizeof(double), &D));
+  TDG_TRY(ws_reserve(ctx, WS_MISC, (size_t)3 * n * sizeof(double) + 256, &ST));
+  TDG_TRY(ws_reserve(ctx, WS_TMP2, (size_t)n * sizeof(double2), &KD));
+  double2* tau = (double2*)((char*)T + t_bytes);
+  int* info = (int*)((char*)ST + (size_t)3 * n * sizeof(double));
+
+  // kdiag and the exact statistics of K_off
+  if (dtype == TDG_C128)
+    hipLaunchKernelGGL(koff_stats_kernel<double>, dim3((unsigned)n), dim3(256), 0, ctx->stream, (const double2*)K, ld, n,
+                       (double2*)KD, (double*)ST);
+  else
+    hipLaunchKernelGGL(koff_stats_kernel<float>, dim3((unsigned)n), dim3(256), 0, ctx->stream, (const float2*)K, ld, n,
+                       (double2*)KD, (double*)ST);
+  TDG_TRY(launch_check(ctx, "compress statistics"));
+
+  rocblas_handle h = nullptr;
+  TDG_TRY(blas_handle(ctx, &h));
+  const unsigned eb = (unsigned)std::min<size_t>((nl + 255) / 256, 8192);
+
+  // dst = K_off src for an n x l column-major block (K row-major: K = (K as column-major)^T)
+  auto apply_koff = [&](const double2* src, double2* dst) -> int {
+    rocblas_status st;
+    if (dtype == TDG_C128) {
+      const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+      st = rocblas_zgemm_64(h, rocblas_operation_transpose, rocblas_operation_none, n, l, n, &one,
+                            (const rocblas_double_complex*)K, ld, (const rocblas_double_complex*)src, n, &zero,
+                            (rocblas_double_complex*)dst, n);
+      if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_zgemm status %d", (int)st);
+      hipLaunchKernelGGL(diag_sub_kernel<double>, dim3(eb), dim3(256), 0, ctx->stream, (const double2*)dst, src,
+                         (const double2*)KD, n, (int64_t)nl, dst);
+    } else {
+      float2* xf = (float2*)F;
+      float2* yf = xf + nl;
+      hipLaunchKernelGGL(to_c64_kernel, dim3(eb), dim3(256), 0, ctx->stream, src, (int64_t)nl, xf);
+      TDG_TRY(launch_check(ctx, "compress conversion"));
+      const rocblas_float_complex one(1.0f, 0.0f), zero(0.0f, 0.0f);
+      st = rocblas_cgemm_64(h, rocblas_operation_transpose, rocblas_operation_none, n, l, n, &one,
+                            (const rocblas_float_complex*)K, ld, (const rocblas_float_complex*)xf, n, &zero,
+                            (rocblas_float_complex*)yf, n);
+      if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_cgemm status %d", (int)st);
+      hipLaunchKernelGGL(diag_sub_kernel<float>, dim3(eb), dim3(256), 0, ctx->stream, (const float2*)yf, src,
+                         (const double2*)KD, n, (int64_t)nl, dst);
+    }
+    return launch_check(ctx, "compress diagonal removal");
+  };
+  // Q <- orthonormal basis of the columns of Y, in place (Householder QR)
+  auto orthonormalise = [&](double2* A) -> int {
+    rocblas_status st = rocsolver_zgeqrf(h, (rocblas_int)n, (rocblas_int)l, (rocblas_double_complex*)A, (rocblas_int)n,
+                                         (rocblas_double_complex*)tau);
+    if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocsolver_zgeqrf status %d", (int)st);
+    st = rocsolver_zungqr(h, (rocblas_int)n, (rocblas_int)l, (rocblas_int)l, (rocblas_double_complex*)A, (rocblas_int)n,
+                          (rocblas_double_complex*)tau);
+    if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocsolver_zungqr status %d", (int)st);
+    return TDG_OK;
+  };
+
+  double2* y = (double2*)Y;
+  double2* z = (double2*)Z;
+  TDG_TRY(apply_koff((const double2*)omega, y));
+  for (int it = 0; it < power_iters; ++it) {
+    TDG_TRY(orthonormalise(y));
+    TDG_TRY(apply_koff(y, z));
+    std::swap(y, z);
+  }
+  TDG_TRY(orthonormalise(y));
+  TDG_TRY(apply_koff(y, z));
+  {
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    rocblas_status st = rocblas_zgemm_64(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, l, l, n,
+                                         &one, (const rocblas_double_complex*)y, n, (const rocblas_double_complex*)z,
+                                         n, &zero, (rocblas_double_complex*)T, l);
+    if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_zgemm status %d", (int)st);
+  }
+  hipLaunchKernelGGL(hermitize_kernel, dim3((unsigned)((l + 255) / 256), (unsigned)l), dim3(256), 0, ctx->stream,
+                     (double2*)T, l);
+  TDG_TRY(launch_check(ctx, "compress hermitize"));
+  double* dvals = (double*)D;
+  rocblas_status st = rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)l,
+                                       (rocblas_double_complex*)T, (rocblas_int)l, dvals, dvals + l, info);
+  if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocsolver_zheevd status %d", (int)st);
+  {  // U = Q W for every Ritz vector (the rank rule picks the columns)
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    st = rocblas_zgemm_64(h, rocblas_operation_none, rocblas_operation_none, n, l, l, &one,
+                          (const rocblas_double_complex*)y, n, (const rocblas_double_complex*)T, l, &zero,
+                          (rocblas_double_complex*)z, n);
+    if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_zgemm status %d", (int)st);
+  }
+  TDG_TRY(hip_check(ctx, hipStreamSynchronize(ctx->stream), "randomized compression sync"));
+  int hinfo = 0;
+  TDG_TRY(hip_check(ctx, hipMemcpy(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost), "info copy"));
+  if (hinfo != 0) return fail(ctx, TDG_E_SOLVER, "rocsolver_zheevd info = %d", hinfo);
+  std::vector<double> lam(l), stats((size_t)3 * n);
+  TDG_TRY(hip_check(ctx, hipMemcpy(lam.data(), dvals, l * sizeof(double), hipMemcpyDeviceToHost), "eigenvalue copy"));
+  TDG_TRY(hip_check(ctx, hipMemcpy(stats.data(), ST, stats.size() * sizeof(double), hipMemcpyDeviceToHost),
+                    "statistics copy"));
+
+  std::vector<int> order(l);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return std::fabs(lam[a]) > std::fabs(lam[b]); });
+  std::vector<double> s(l);
+  for (int64_t i = 0; i < l; ++i) s[i] = std::fabs(lam[order[i]]);
+  double sr = 0.0, si = 0.0, fro2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    sr += stats[3 * i];
+    si += stats[3 * i + 1];
+    fro2 += stats[3 * i + 2];
+  }
+  const double dev2 = fro2 - (sr * sr + si * si) / ((double)n * (double)n);
+  const int64_t r = choose_rank_ritz(s, n, trunc->mode, trunc->value, fro2, dev2);
+  if (out->sigma) std::copy(s.begin(), s.end(), out->sigma);
+  if (r < 0) return fail(ctx, TDG_E_INVAL, "the rank rule is not decided within l = %lld Ritz values", (long long)l);
+  out->rank = r;
+  double kept2 = 0.0;
+  for (int64_t i = 0; i < r; ++i) kept2 += s[i] * s[i];
+  out->tail_fro = std::sqrt(std::max(0.0, fro2 - kept2));
+  out->tail_spec = r < l ? s[r] : (l < n ? std::nan("") : 0.0);
+  if (r < 1) return fail(ctx, TDG_E_INVAL, "truncation keeps no singular value");
+  if (r > out->max_rank)
+    return fail(ctx, TDG_E_INVAL, "rank %lld exceeds max_rank %lld", (long long)r, (long long)out->max_rank);
+  std::vector<int> perm(r);
+  std::vector<double> kept(r);
+  for (int64_t c = 0; c < r; ++c) {
+    perm[c] = order[c];
+    kept[c] = lam[order[c]];
+  }
+  return write_factors(ctx, (const double2*)KD, z, n, r, perm, kept, out);
 }

@@ -33,6 +33,10 @@ enum WsSlot {
   WS_TMP1,       // conversion staging (complex64 copies before a BF16X2 split)
   WS_TMP2,
   WS_TMP3,
+  WS_RSVD_Y,     // randomized compression: range block, then Q, c128 column-major [l][n]
+  WS_RSVD_Z,     // randomized compression: K_off Q, then Q W, c128 column-major [l][n]
+  WS_RSVD_F,     // randomized compression: complex64 copies of Q and K Q for a C64 kernel
+  WS_RSVD_T,     // randomized compression: Q^H K_off Q, c128 [l][l], and Householder scalars
   WS_COUNT
 };
 

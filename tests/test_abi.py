@@ -77,4 +77,5 @@ def test_host_validation_without_device(tdg):
     assert L.tdg_propagate(None, None, None, None, 1, 1.0, None, 1, None) == abi.TDG_E_INVAL
     assert L.tdg_kernel_build(None, None, None, 0, None, 0) == abi.TDG_E_INVAL
     assert L.tdg_kernel_compress(None, None, 0, 0, None, None) == abi.TDG_E_INVAL
+    assert L.tdg_kernel_compress_randomized(None, None, 0, 0, None, None, 0, 0, None) == abi.TDG_E_INVAL
     assert L.tdg_version() >= 100

@@ -424,3 +424,91 @@ def test_bf16x2_batched_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind):
             worst = max(worst, float(np.abs(got - ref[key]).max() / scale))
     _log(f"  bf16x2 {kind}: worst err over P, J and instances = {worst:.2e}")
     assert worst <= 1e-4
+
+
+# --- randomized compression -------------------------------------------------
+
+
+def _omega_t(n, l, seed):
+    """The seeded test matrix, transposed to [l][n] on the device."""
+    from workloads.random_matrices import gaussian_test_matrix
+    return torch.from_numpy(np.ascontiguousarray(gaussian_test_matrix(n, l, seed).T)).cuda()
+
+
+def _apply(us, w, x):
+    return us @ (w @ x)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_randomized_compress_matches_oracle(P, ctx, tb4_6, k_tb4_6, dtype):
+    """Same test matrix on both sides: Ritz values, the diagonal and the
+    action of U S V^H on seeded vectors agree with the oracle's range finder
+    (for a complex64 K the oracle takes the same rounded K)."""
+    from workloads.random_matrices import gaussian_test_matrix
+    n, l, r, q = k_tb4_6.shape[0], 48, 24, 2
+    _log(f"randomized compress tb4 6x6 eh {dtype} l={l} rank={r} power_iters={q}")
+    kg = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", dtype)
+    k_in = kg.cpu().numpy().astype(np.complex128)
+    f = ctx.kernel_compress_randomized(kg, _omega_t(n, l, 11), "rank", r, power_iters=q)
+    ref = O.randomized_compress(k_in, r, gaussian_test_matrix(n, l, 11), q)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert f.rank == ref["r"] == r
+    np.testing.assert_allclose(f.sigma, ref["s"], rtol=0, atol=tol * ref["s"][0])
+    np.testing.assert_allclose(f.kdiag.cpu().numpy(), ref["kdiag"], rtol=1e-7 if dtype == "c64" else 1e-15)
+    x = gaussian_test_matrix(n, 8, 12)
+    got = _apply(f.us.cpu().numpy().astype(np.complex128), f.w.cpu().numpy().astype(np.complex128), x)
+    want = _apply(ref["US"], ref["Vh"], x)
+    assert np.abs(got - want).max() <= 50 * tol * np.abs(want).max()
+    _, koff = O.split_diag(k_in)
+    tail = np.sqrt(max(0.0, np.linalg.norm(koff) ** 2 - np.sum(ref["s"][:r] ** 2)))
+    np.testing.assert_allclose(f.tail_fro, tail, rtol=1e-6 if dtype == "c64" else 1e-9)
+
+
+def test_randomized_full_width_equals_exact(P, ctx, tb4_6, k_tb4_6):
+    """l = n spans the whole space: every rank rule picks the exact rank and
+    the factors reproduce the exact truncated SVD."""
+    n = k_tb4_6.shape[0]
+    kg = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", "c128")
+    om = _omega_t(n, n, 13)
+    for rule, val in (("rel_cut", 1e-2), ("rank", 17), ("r2", 0.9), ("fraction", 0.2)):
+        f = ctx.kernel_compress_randomized(kg, om, rule, val, power_iters=0)
+        ex = ctx.kernel_compress(kg, rule, val)
+        assert f.rank == ex.rank == O.compress(k_tb4_6, rule, val)["r"], rule
+        a = (f.us @ f.w).cpu().numpy()
+        b = (ex.us @ ex.w).cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max(), rule
+
+
+def test_randomized_rank_rule_needs_enough_values(P, ctx, tb4_6):
+    """A relative cut that every Ritz value passes cannot be decided, and a
+    rank above l is refused; both report an error, not a guess."""
+    n = ctx.kernel_dim(_dev(P, tb4_6), "eh")
+    kg = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", "c128")
+    om = _omega_t(n, 16, 14)
+    with pytest.raises(P.TdgError):
+        ctx.kernel_compress_randomized(kg, om, "rel_cut", 1e-6)
+    with pytest.raises(P.TdgError):
+        ctx.kernel_compress_randomized(kg, om, "rank", 20)
+
+
+def test_randomized_full_size_vs_oracle(P, ctx):
+    """36x36 e-h workload (N = 5184), the rank of the 5% rule with l = 2 r test
+    vectors and 4 power iterations, FP64 on both sides: Ritz values and the
+    action on seeded vectors agree with the oracle's range finder."""
+    from workloads.random_matrices import gaussian_test_matrix
+    cfg = get_config(1)
+    m = cfg.model()
+    n, r, q = cfg.n, 259, 4
+    l = 2 * r
+    _log(f"randomized compress {cfg.name} N={n} c128 rank={r} l={l} power_iters={q}")
+    kg = ctx.kernel_build(_dev(P, m), cfg.r0, "eh", "c128")
+    f = ctx.kernel_compress_randomized(kg, _omega_t(n, l, 21), "rank", r, power_iters=q)
+    del kg
+    ref = O.randomized_compress(O.build_kernel(m, cfg.r0, "eh"), r, gaussian_test_matrix(n, l, 21), q)
+    e_s = float(np.abs(f.sigma - ref["s"]).max() / ref["s"][0])
+    x = gaussian_test_matrix(n, 4, 22)
+    got = _apply(f.us.cpu().numpy(), f.w.cpu().numpy(), x)
+    want = _apply(ref["US"], ref["Vh"], x)
+    e_x = float(np.abs(got - want).max() / np.abs(want).max())
+    _log(f"  Ritz values {e_s:.2e}, action {e_x:.2e}, tail_fro {f.tail_fro:.6e}")
+    assert e_s <= 1e-10 and e_x <= 1e-8

@@ -420,3 +420,35 @@ def test_linear_response_of_literal_r0_grows():
     k = O.build_kernel(m, R0_LITERAL, "all")
     lmat, _ = O.linear_operator(m, k, "all")
     assert np.abs(np.linalg.eigvals(lmat).imag).max() > 1e-3
+
+
+# --- randomized range finder (an addition for large kernels, not the paper's) --
+
+def test_randomized_full_width_is_exact(k_tb4_eh):
+    """With as many test vectors as rows the range finder spans everything and
+    the factorisation equals the exact truncated SVD."""
+    from workloads.random_matrices import gaussian_test_matrix
+    n = k_tb4_eh.shape[0]
+    exact = O.compress(k_tb4_eh, "rank", 20)
+    rnd = O.randomized_compress(k_tb4_eh, 20, gaussian_test_matrix(n, n, 1), power_iters=0)
+    np.testing.assert_allclose(rnd["s"][:20], exact["s"][:20], rtol=1e-10)
+    np.testing.assert_allclose(rnd["US"] @ rnd["Vh"], exact["US"] @ exact["Vh"], atol=1e-12 * exact["s"][0])
+
+
+def test_randomized_recovers_a_low_rank_plus_noise_matrix():
+    """Planted spectrum with a gap: the randomized factors find the top
+    eigenpairs; the residual obeys the Eckart-Young floor."""
+    from workloads.random_matrices import gaussian_test_matrix
+    rng = np.random.default_rng(3)
+    n, r = 200, 12
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = np.concatenate([np.linspace(5, 2, r) * rng.choice([-1, 1], r), 1e-3 * rng.standard_normal(n - r)])
+    koff = (q * lam) @ q.conj().T
+    k = koff + np.diag(rng.standard_normal(n))          # diagonal is split off first
+    k = 0.5 * (k + k.conj().T)
+    rnd = O.randomized_compress(k, r, gaussian_test_matrix(n, r + 10, 2), power_iters=2)
+    exact = O.compress(k, "rank", r)
+    np.testing.assert_allclose(rnd["s"][:r], exact["s"][:r], rtol=1e-4)
+    _, koff_k = O.split_diag(k)
+    resid = np.linalg.norm(koff_k - rnd["US"] @ rnd["Vh"], 2)
+    assert resid <= 1.01 * exact["s"][r]
