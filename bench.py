@@ -44,6 +44,10 @@ def parse():
                     help="npz file: load the compressed factors from it if present, else compute and save them "
                          "(lets a counter-collection run skip the eigensolver)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 60x60 sweep measurement")
+    ap.add_argument("--large-grid", action="store_true",
+                    help="also measure the 120x120 workload (N = 57600, 256 instances): randomized "
+                         "compression, then dense FP32, low-rank FP32 and low-rank BF16X2 throughput")
+    ap.add_argument("--large-grid-steps", type=int, default=40, help="RK4 steps per instance timed there")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -228,6 +232,7 @@ def main():
         del K, fac, res
         torch.cuda.empty_cache()
         sweep = batched_sweep(P, abi, ctx, frac)
+    large = large_grid(P, abi, args.large_grid_steps) if args.large_grid else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -270,6 +275,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "batched_sweep": sweep,
+        "large_grid": large,
     }
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -317,6 +323,77 @@ def batched_sweep(P, abi, ctx, frac):
                      "stage_kernel_us": s_ms / s_n * 1e3}
     res["speedup_lowrank_vs_dense"] = res["lowrank"]["value"] / res["dense"]["value"]
     del K, fac
+    torch.cuda.empty_cache()
+    return res
+
+
+def large_grid(P, abi, steps):
+    """The 120x120 workload: K_off compressed by the randomized range finder
+    (5 % of N kept, l = r + 128 test vectors, 2 power iterations), then 256
+    instances integrated together for `steps` RK4 steps each with the dense
+    FP32 kernel, FP32 factors and BF16 hi+lo factors.  Its own context, so its
+    workspace is released afterwards."""
+    import numpy as np
+    import torch
+
+    from workloads import FieldTable, get_config
+    cfg = get_config(4)
+    model = cfg.model()
+    ctx = P.Context(0)
+    dm = P.DeviceModel.from_model(model)
+    n = cfg.n
+    r = int(round(0.05 * n))
+    l, q = r + 128, 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    K = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    g = torch.Generator(device=f"cuda:{ctx.device}")
+    g.manual_seed(2026)
+    om = (torch.randn(l, n, dtype=torch.float64, device=K.device, generator=g)
+          + 1j * torch.randn(l, n, dtype=torch.float64, device=K.device, generator=g)).contiguous()
+    ops = {}
+    t0 = time.perf_counter()
+    ops["lowrank_bf16x2"] = ctx.kernel_compress_randomized(K, om, "rank", r, power_iters=q, out_dtype="bf16x2")
+    torch.cuda.synchronize()
+    compress_s = time.perf_counter() - t0
+    ops["lowrank_f32"] = ctx.kernel_compress_randomized(K, om, "rank", r, power_iters=q, out_dtype="c64")
+    del om
+    torch.cuda.empty_cache()
+    ops["dense_f32"] = K
+    f = cfg.fields
+    B = f.batch
+    res = {"workload": f"{cfg.name}: 120x120 k-grid, N={n} complex64, {B} instances; {steps} of the 4000 "
+                       f"RK4 steps of every instance timed",
+           "rank": r, "kept_fraction": r / n, "test_vectors": l, "power_iters": q,
+           "kernel_build_seconds": build_s, "randomized_compress_seconds": compress_s}
+    for name, op in ops.items():
+        nst = max(4, steps // 4) if name == "dense_f32" else steps
+        run = FieldTable(f.e0, f.omega, f.tau, f.t0, f.ex, f.ey, np.full(B, nst, dtype=np.int64))
+        warm = FieldTable(f.e0, f.omega, f.tau, f.t0, f.ex, f.ey, np.full(B, 2, dtype=np.int64))
+        ctx.propagate(op, dm, "eh", warm, cfg.dt, diagnostics=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.propagate(op, dm, "eh", run, cfg.dt, diagnostics=False)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        ctx.profile_enable(True)
+        ctx.propagate(op, dm, "eh", warm, cfg.dt, diagnostics=False)
+        g_ms, g_n = ctx.profile_read(abi.TDG_KCLASS_GEMM)
+        ctx.profile_enable(False)
+        flops = 8.0 * n * n * B if name == "dense_f32" else 16.0 * n * r * B   # useful complex flops per stage
+        gemm_s = g_ms / g_n * 1e-3                                          # all products of one stage
+        entry = {"value": B * nst / secs, "steps_timed": nst, "seconds": secs, "variant": ctx.last_variant(),
+                 "contraction_us_per_stage": gemm_s * 1e6, "contraction_TFLOPs": flops / gemm_s / 1e12,
+                 "contraction_frac_of_fp32_peak": flops / gemm_s / 157.3e12}
+        if name == "lowrank_bf16x2":   # three BF16 products per real product
+            entry["bf16_issued_frac"] = 3.0 * flops / gemm_s / 2.5e15
+        res[name] = entry
+    res["speedup_lowrank_bf16x2_vs_dense"] = res["lowrank_bf16x2"]["value"] / res["dense_f32"]["value"]
+    res["speedup_lowrank_f32_vs_dense"] = res["lowrank_f32"]["value"] / res["dense_f32"]["value"]
+    del K, ops
+    ctx.close()
     torch.cuda.empty_cache()
     return res
 

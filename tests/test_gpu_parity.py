@@ -512,3 +512,63 @@ def test_randomized_full_size_vs_oracle(P, ctx):
     e_x = float(np.abs(got - want).max() / np.abs(want).max())
     _log(f"  Ritz values {e_s:.2e}, action {e_x:.2e}, tail_fro {f.tail_fro:.6e}")
     assert e_s <= 1e-10 and e_x <= 1e-8
+
+
+def test_large_grid_bf16x2_vs_fp64_lowrank(P):
+    """120x120 e-h workload (N = 57600): the randomized factors are written
+    once in complex128 and once as BF16 hi+lo pairs (same test matrix, so the
+    same FP64 factors before rounding).  The BF16X2 batched path is compared
+    with the FP64 low-rank path on P(t) (4000 steps) and on the absorption
+    spectrum A(w) where the pulse has spectral weight."""
+    cfg = get_config(4)
+    m = cfg.model()
+    n = cfg.n
+    r = int(round(0.05 * n))
+    l, q = r + 128, 2
+    c = P.Context(0)
+    try:
+        dm = _dev(P, m)
+        _log(f"large grid {cfg.name} N={n}: randomized compression rank={r} l={l} power_iters={q}")
+        kg = c.kernel_build(dm, cfg.r0, "eh", "c64")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(2026)
+        om = (torch.randn(l, n, dtype=torch.float64, device="cuda", generator=g)
+              + 1j * torch.randn(l, n, dtype=torch.float64, device="cuda", generator=g)).contiguous()
+        f64 = c.kernel_compress_randomized(kg, om, "rank", r, power_iters=q, out_dtype="c128")
+        fbf = c.kernel_compress_randomized(kg, om, "rank", r, power_iters=q, out_dtype="bf16x2")
+        assert f64.rank == fbf.rank == r
+        del kg, om
+        torch.cuda.empty_cache()
+        idx = [0, cfg.fields.batch - 1]              # weakest and strongest amplitude
+        fields = cfg.fields.subset(idx)
+        _log("  FP64 low-rank reference, 2 instances x 4000 steps")
+        ref = c.propagate(f64, dm, "eh", fields, cfg.dt, diagnostics=False)
+        _log("  BF16X2 batched, same instances")
+        got = c.propagate(fbf, dm, "eh", fields, cfg.dt, diagnostics=False)
+        assert c.last_variant().endswith("bf16x2")
+        half = 2001
+        worst = {}
+        for b in range(2):
+            for key in ("P", "J"):
+                x = got[key][b].cpu().numpy()
+                y = ref[key][b].cpu().numpy()
+                e_half = float(np.abs(x[:half] - y[:half]).max() / np.abs(y[:half]).max())
+                _log(f"  instance {idx[b]} E0={fields.e0[b]:.1e}: err_{key} first half {e_half:.2e}, "
+                     f"full run {err_rel(x, y):.2e}")
+                worst[(b, key)] = e_half
+        # absorption of the weak pulse
+        p_ref = ref["P"][0].cpu().numpy()
+        p_got = got["P"][0].cpu().numpy()
+        t = np.arange(p_ref.shape[0]) * cfg.dt
+        e = np.array([O.field_at(tt, fields, 0) for tt in t])
+        w0 = fields.omega[0]
+        om_grid = np.linspace(w0 - 0.15 / HARTREE_EV, w0 + 0.15 / HARTREE_EV, 301)
+        eta = 0.05 / HARTREE_EV
+        a_ref = O.absorption(p_ref, e, cfg.dt, om_grid, eta)
+        a_got = O.absorption(p_got, e, cfg.dt, om_grid, eta)
+        e_abs = float(np.abs(a_got - a_ref).max() / np.abs(a_ref).max())
+        _log(f"  absorption within +-0.15 eV of the carrier: rel err {e_abs:.2e}")
+        assert max(worst.values()) <= 1e-4
+        assert e_abs <= 1e-4
+    finally:
+        c.close()
