@@ -16,6 +16,8 @@ Modules, each following the paper's definitions step by step:
   bse.py         linearised operator (Bethe-Salpeter Hamiltonian) and the
                  linear-response solution used as a brute-force pin
   spectra.py     absorption and high-harmonic spectra from time series
+  adjoint.py     reverse-mode derivative of the discrete RK4 propagation
+                 (not in the paper; the exact gradient of the scheme above)
 """
 
 from .kernel import (  # noqa: F401
@@ -27,3 +29,4 @@ from .propagate import field_at, DenseOp, LowRankOp, propagate, rho_equilibrium 
 from .observables import observables  # noqa: F401
 from .bse import linear_operator, linear_response  # noqa: F401
 from .spectra import absorption, hhg  # noqa: F401
+from .adjoint import propagate_adjoint, harmonic_loss, field_param_derivs  # noqa: F401

@@ -18,6 +18,7 @@ KERNEL = importlib.import_module("oracle.kernel")
 OBSERVABLES = importlib.import_module("oracle.observables")
 PROPAGATE = importlib.import_module("oracle.propagate")
 BSE = importlib.import_module("oracle.bse")
+ADJOINT = importlib.import_module("oracle.adjoint")
 
 
 @pytest.fixture(scope="module")
@@ -51,6 +52,36 @@ def _transposed_trace(a, rho):
     return complex(np.einsum("knm,knm->", a, rho))
 
 
+def _pull_commutator_unconjugated(h, y, g):
+    return 1j * (h @ g - g @ h), -1j * (g @ y - y @ g)
+
+
+def _pull_commutator_ybar_sign(h, y, g):
+    a, b = ADJOINT.__dict__["_real_pull_commutator"](h, y, g)
+    return -a, b
+
+
+def _pull_field_no_conj(dmat, y, g):
+    return float(np.sum((g * (1j * (dmat @ y - y @ dmat))).real))
+
+
+def _omega_derivative_sign(t, fields, b):
+    d = ADJOINT.__dict__["_real_field_param_derivs"](t, fields, b)
+    d[1] = -d[1]
+    return d
+
+
+def _cotangent_wrong_band(model, ex, ey, gp, gj, gocc):
+    d = ex * model.dip[0] + ey * model.dip[1]
+    v = ex * model.vel[0] + ey * model.vel[1]
+    g = (gp * d.conj().transpose(0, 2, 1) + gj * v.conj().transpose(0, 2, 1)).astype(np.complex128)
+    g[:, model.nv - 1, model.nv - 1] += gocc
+    return g / model.nk
+
+
+ADJOINT._real_pull_commutator = ADJOINT.pull_commutator
+ADJOINT._real_field_param_derivs = ADJOINT.field_param_derivs
+
 CASES = {
     "dense operand transposed": (O.DenseOp, "apply", _transposed_dense, "weak_bse"),
     "commutator sign flipped": (PROPAGATE, "minus_i_commutator", _flipped_commutator, "two_level"),
@@ -61,6 +92,14 @@ CASES = {
                             lambda q, r0: 4 * np.pi / (np.asarray(q) * (1 + r0 * np.asarray(q))), "row_sum"),
     "k difference not folded": (KERNEL, "fold_q", lambda dk, a: dk, "circulant"),
     "trace operand transposed": (OBSERVABLES, "_trace_prod", _transposed_trace, "two_level"),
+    "adjoint: commutator pullback order swapped": (ADJOINT, "pull_commutator", _pull_commutator_unconjugated,
+                                                   "adjoint_factors"),
+    "adjoint: state cotangent sign flipped": (ADJOINT, "pull_commutator", _pull_commutator_ybar_sign,
+                                              "adjoint_fields"),
+    "adjoint: field pullback not conjugated": (ADJOINT, "pull_field", _pull_field_no_conj, "adjoint_fields"),
+    "adjoint: omega derivative sign": (ADJOINT, "field_param_derivs", _omega_derivative_sign, "adjoint_fields"),
+    "adjoint: occupation cotangent on the wrong band": (ADJOINT, "observable_cotangent", _cotangent_wrong_band,
+                                                        "adjoint_fields"),
 }
 
 
@@ -76,6 +115,13 @@ def _run_pin(name, small):
         pins.test_kernel_row_sum_is_brillouin_zone_integral()
     elif name == "circulant":
         pins.test_flat_band_kernel_is_circulant()
+    elif name in ("adjoint_fields", "adjoint_factors"):
+        import test_oracle_adjoint as adj
+        lr = O.LowRankOp.from_factors(O.compress(O.build_kernel(t4, R0_STABLE, "eh"), "rank", 12))
+        if name == "adjoint_fields":
+            adj.test_adjoint_field_params_lowrank_eh(t4, lr)
+        else:
+            adj.test_adjoint_lowrank_factors_and_initial_state(t4, lr)
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
