@@ -240,6 +240,44 @@ int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
                   const tdg_field* fields, int32_t batch, double dt, void* rho,
                   int32_t init_eq, const tdg_obs* obs);
 
+/* Reverse-mode derivative of tdg_propagate (not in the paper, which
+ * integrates forward only): the exact gradient of the discrete RK4 scheme
+ * for a real loss L given by its cotangents on the observable series,
+ *   dL = sum_b sum_n gP[b][n] dP_b(t_n) + gJ[b][n] dJ_b(t_n) + gocc[b][n] docc_b(t_n),
+ * device double arrays [batch][stride], stride >= nsteps + 1 (NULL = 0). */
+typedef struct {
+  const double* gP;
+  const double* gJ;
+  const double* gocc;
+  int64_t stride;
+} tdg_obs_grad;
+
+/* Gradients, caller-owned device buffers, each NULL to skip.  Complex
+ * gradients are dL/dRe Z + i dL/dIm Z.
+ *   dfield  double [batch][4]          dL/d(e0, omega, tau, t0) of each instance
+ *   dE      double [batch][nsteps][4]  dL/dE at the four stage times of each step
+ *   drho0   c128 [batch][nk][nb][nb]   dL/drho(t_0)
+ *   dus     c128 [n][rank]             dL/dS (low-rank operator only)
+ *   dw      c128 [rank][n]             dL/dV^H (low-rank operator only) */
+typedef struct {
+  double* dfield;
+  double* dE;
+  void* drho0;
+  void* dus;
+  void* dw;
+} tdg_grads;
+
+/* Integrates forward from rho0 (device c128 [batch][nk][nb][nb]; NULL =
+ * rho_eq) keeping rho every checkpoint_every steps, then pulls the loss back
+ * step by step, recomputing each segment from its checkpoint.  FP64 only:
+ * op->dtype must be TDG_C128 (dense or low rank).  Every instance must have
+ * the same nsteps.  Device workspace about (nsteps / M + M + 12) states plus
+ * 4 (M for low rank) x 2 x n x batch complex128 values, held by the context.
+ * Synchronises the stream. */
+int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
+                          const tdg_field* fields, int32_t batch, double dt, const void* rho0,
+                          int32_t checkpoint_every, const tdg_obs_grad* g, tdg_grads* out);
+
 /* Observables of a given state: out device double [batch][5] =
  * (P, J, occ, tr, herm) as defined for tdg_obs, with e taken from fields
  * (host, batch entries). */

@@ -273,6 +273,37 @@ class Context:
         arrs["_obs_struct"] = obs
         return arrs
 
+    def propagate_adjoint(self, op, model: DeviceModel, block: str, fields, dt: float, gP=None, gJ=None,
+                          gocc=None, rho0: torch.Tensor | None = None, checkpoint_every: int = 50,
+                          factor_grads: bool = True) -> dict:
+        """Gradient of L = sum_n gP_n P(t_n) + gJ_n J(t_n) + gocc_n occ(t_n) (each [B][nsteps + 1]
+        or None) by the adjoint RK4 on the device.  Returns dfield [B][4] (d e0, omega, tau, t0),
+        dE [B][nsteps][4], drho0 and, for complex128 low-rank factors, dus and dw."""
+        fa = field_array(fields)
+        batch = len(fa)
+        nsteps = int(fa[0].nsteps)
+        dev = f"cuda:{self.device}"
+        ws = {}
+        for key, g in (("gP", gP), ("gJ", gJ), ("gocc", gocc)):
+            if g is not None:
+                ws[key] = torch.as_tensor(g, dtype=torch.float64).to(dev).reshape(batch, nsteps + 1).contiguous()
+        og = abi.ObsGrad(_ptr(ws.get("gP")), _ptr(ws.get("gJ")), _ptr(ws.get("gocc")), nsteps + 1)
+        out = {"dfield": torch.zeros((batch, 4), dtype=torch.float64, device=dev),
+               "dE": torch.zeros((batch, nsteps, 4), dtype=torch.float64, device=dev),
+               "drho0": torch.zeros((batch, model.nk, model.nb, model.nb), dtype=torch.complex128, device=dev)}
+        lowrank = isinstance(op, LowRankFactors)
+        if lowrank and factor_grads:
+            out["dus"] = torch.zeros(tuple(op.us.shape), dtype=torch.complex128, device=dev)
+            out["dw"] = torch.zeros(tuple(op.w.shape), dtype=torch.complex128, device=dev)
+        gr = abi.Grads(_ptr(out["dfield"]), _ptr(out["dE"]), _ptr(out["drho0"]), _ptr(out.get("dus")),
+                       _ptr(out.get("dw")))
+        n = self.kernel_dim(model, block)
+        opr = self._operator(op, block, n)
+        ms = model.struct()
+        self._check(self._lib.tdg_propagate_adjoint(self.h, C.byref(opr), C.byref(ms), fa, batch, float(dt),
+                                                    _ptr(rho0), int(checkpoint_every), C.byref(og), C.byref(gr)))
+        return out
+
     def observables(self, model: DeviceModel, rho: torch.Tensor, fields) -> torch.Tensor:
         fa = field_array(fields)
         out = torch.zeros((len(fa), 5), dtype=torch.float64, device=rho.device)
@@ -301,3 +332,68 @@ class Context:
         cnt = C.c_int64()
         self._check(self._lib.tdg_profile_read(self.h, kclass, C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
+
+
+# --- differentiable propagation ---------------------------------------------
+
+def _field_records(params: torch.Tensor, nsteps: int, ex: float, ey: float) -> np.ndarray:
+    p = params.detach().to("cpu", torch.float64).numpy()
+    rec = np.zeros((p.shape[0], 8))
+    rec[:, :4] = p
+    rec[:, 4], rec[:, 5], rec[:, 6] = ex, ey, nsteps
+    return rec
+
+
+class _Propagate(torch.autograd.Function):
+    """P, J, occ series as functions of the pulse parameters and the low-rank
+    factors; backward runs the library's adjoint RK4."""
+
+    @staticmethod
+    def forward(fctx, params, us, w, cfg):
+        ctx, model, block, kdiag, K, dt, nsteps, ex, ey, every = cfg
+        rec = _field_records(params, nsteps, ex, ey)
+        op = K if K is not None else LowRankFactors(kdiag, us, w, None, us.shape[1], 0.0, 0.0, "c128")
+        res = ctx.propagate(op, model, block, rec, dt, diagnostics=False)
+        fctx.cfg = cfg
+        fctx.save_for_backward(params, us, w)
+        return res["P"], res["J"], res["occ"]
+
+    @staticmethod
+    def backward(fctx, gP, gJ, gocc):
+        params, us, w = fctx.saved_tensors
+        ctx, model, block, kdiag, K, dt, nsteps, ex, ey, every = fctx.cfg
+        rec = _field_records(params, nsteps, ex, ey)
+        lowrank = K is None
+        op = K if not lowrank else LowRankFactors(kdiag, us, w, None, us.shape[1], 0.0, 0.0, "c128")
+        want = lowrank and (fctx.needs_input_grad[1] or fctx.needs_input_grad[2])
+        g = ctx.propagate_adjoint(op, model, block, rec, dt, gP=gP, gJ=gJ, gocc=gocc, checkpoint_every=every,
+                                  factor_grads=want)
+        dparams = g["dfield"].to(params.device, params.dtype)
+        dus = g["dus"] if want and fctx.needs_input_grad[1] else None
+        dw = g["dw"] if want and fctx.needs_input_grad[2] else None
+        return dparams, dus, dw, None
+
+
+def propagate_differentiable(ctx: Context, model: DeviceModel, block: str, params: torch.Tensor, dt: float,
+                             nsteps: int, *, factors: LowRankFactors | None = None,
+                             us: torch.Tensor | None = None, w: torch.Tensor | None = None,
+                             K: torch.Tensor | None = None, ex: float = 1.0, ey: float = 0.0,
+                             checkpoint_every: int = 50):
+    """Differentiable P, J, occ [B][nsteps + 1] (FP64 on the device).
+
+    params: [B][4] float64 (e0, omega, tau, t0) per instance.  The operator is
+    either complex128 low-rank factors (K_diag from `factors`; S and V^H from
+    `us`, `w` if given, so gradients can flow into them) or a dense complex128
+    K (gradients for the pulse parameters only).  Backward runs the adjoint
+    RK4 with a checkpoint every `checkpoint_every` steps."""
+    if K is None:
+        if factors is None or factors.dtype != "c128":
+            raise ValueError("complex128 low-rank factors or a dense complex128 K are required")
+        us = factors.us if us is None else us
+        w = factors.w if w is None else w
+        kdiag = factors.kdiag
+    else:
+        us = w = torch.zeros(1, dtype=torch.complex128, device=K.device)
+        kdiag = None
+    cfg = (ctx, model, block, kdiag, K, float(dt), int(nsteps), float(ex), float(ey), int(checkpoint_every))
+    return _Propagate.apply(params, us, w, cfg)

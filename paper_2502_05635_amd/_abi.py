@@ -65,6 +65,14 @@ class Obs(C.Structure):
     _fields_ = [("P", P), ("J", P), ("occ", P), ("tr", P), ("herm", P), ("stride", C.c_int64)]
 
 
+class ObsGrad(C.Structure):
+    _fields_ = [("gP", P), ("gJ", P), ("gocc", P), ("stride", C.c_int64)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("dfield", P), ("dE", P), ("drho0", P), ("dus", P), ("dw", P)]
+
+
 SIGNATURES = {
     "tdg_version": ([], C.c_int),
     "tdg_create": ([C.POINTER(P), C.c_int, P], C.c_int),
@@ -78,6 +86,8 @@ SIGNATURES = {
                                         C.POINTER(LowRank)], C.c_int),
     "tdg_propagate": ([P, C.POINTER(Operator), C.POINTER(Model), C.POINTER(Field), C.c_int32, C.c_double, P,
                        C.c_int32, C.POINTER(Obs)], C.c_int),
+    "tdg_propagate_adjoint": ([P, C.POINTER(Operator), C.POINTER(Model), C.POINTER(Field), C.c_int32, C.c_double,
+                               P, C.c_int32, C.POINTER(ObsGrad), C.POINTER(Grads)], C.c_int),
     "tdg_observables": ([P, C.POINTER(Model), P, C.c_int32, C.POINTER(Field), P], C.c_int),
     "tdg_check_numeric": ([P, C.POINTER(Obs), C.c_int32, C.POINTER(Field), C.c_double, C.c_double], C.c_int),
     "tdg_set_option": ([P, C.c_int32, C.c_int64], C.c_int),

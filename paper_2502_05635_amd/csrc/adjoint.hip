@@ -1,0 +1,559 @@
+// Reverse-mode derivative of the RK4 propagation: the exact gradient of the
+// discrete scheme integrated by tdg_propagate (classical RK4, the field at
+// t_n, t_n + dt/2 twice and t_n + dt), for a real loss L given through its
+// cotangents on the observable series P, J, occupation.  The paper integrates
+// forward only; this is the standard adjoint of an explicit Runge-Kutta step.
+//
+// For f(t, y) = -i [H(t, y), y], H = diag(eps) + dSigma(x) - E(t) e.d with
+// x = gather(y - rho_eq) and dSigma = K x (or K_diag o x + S (V^H x)), a
+// cotangent g of f pulls back to
+//   ybar   = i [H^H, g] + scatter(K^H sbar),
+//   Sigbar = -i [y^H, g],  sbar = gather(Sigbar) (e-h block: Sigbar_cv + conj(Sigbar_vc)),
+//   dL/dE  = Re sum conj(g) i [e.d, y],
+//   dL/dS += sbar (V^H x)^H,  dL/dV^H += (S^H sbar) x^H.
+// Complex gradients are dL/dRe + i dL/dIm.  The step is pulled back from its
+// fourth stage to its first: with a = dL/drho_{n+1},
+//   g_4 = dt/6 a, g_3 = dt/3 a + dt ybar_4, g_2 = dt/3 a + dt/2 ybar_3,
+//   g_1 = dt/6 a + dt/2 ybar_2,  dL/drho_n = a + sum_s ybar_s + (observable cotangent at t_n).
+//
+// Memory: rho is stored every M steps on the forward sweep; the backward
+// sweep recomputes a segment's states from its checkpoint, then each step's
+// four stages (states, dSigma pairs, x, z) before pulling the step back.
+// Products with K, S and V run as plain complex FP64 GEMMs (rocBLAS); the
+// per-k commutator pullbacks run in the kernels below.  The factor gradients
+// are accumulated once per segment with two GEMMs over its stage columns.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int AT = 64;  // threads per block of the per-k kernels (a block holds 64 / nb^2 k points)
+
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+__device__ inline double field_value(const tdg_field& f, double t) {
+  const double d = t - f.t0;
+  return f.e0 * exp(-d * d / (2.0 * f.tau * f.tau)) * cos(f.omega * t);
+}
+
+struct AdjArgs {
+  int nk, nb, nv, npair, block, batch, nsteps;
+  int64_t n;  // nk * npair
+  double dt;
+  const double* eps;
+  const double2* dip;
+  const double2* vel;
+  const tdg_field* fields;  // device [B]
+  const double2* kdiag;     // low rank: K_diag [n]; dense: NULL
+};
+
+__device__ inline double stage_offset(int s) { return s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5); }
+
+// Thread t of a block: local k point t / nb^2, matrix element t % nb^2.
+struct Slot {
+  int lk, e, k, b, nn, m;
+  bool active;
+  size_t g;
+};
+
+__device__ inline Slot slot_of(const AdjArgs& a) {
+  Slot s;
+  const int nb2 = a.nb * a.nb, kpb = AT / nb2;
+  s.lk = threadIdx.x / nb2;
+  s.e = threadIdx.x % nb2;
+  s.k = blockIdx.x * kpb + s.lk;
+  s.b = blockIdx.y;
+  s.active = s.lk < kpb && s.k < a.nk;
+  s.nn = s.e / a.nb;
+  s.m = s.e % a.nb;
+  s.g = ((size_t)s.b * a.nk + s.k) * nb2 + s.e;
+  return s;
+}
+
+// Pair index of element (n, m) in the gathered vector, or -1.
+__device__ inline int pair_of(const AdjArgs& a, int nn, int m) {
+  if (a.block == TDG_BLOCK_ALL) return nn * a.nb + m;
+  if (nn >= a.nv && m < a.nv) return (nn - a.nv) * a.nv + m;
+  return -1;
+}
+
+__device__ inline double2 proj_e(const tdg_field& F, const AdjArgs& a, const double2* arr, int k, int e) {
+  const size_t base = (size_t)k * a.nb * a.nb + e, plane = (size_t)a.nk * a.nb * a.nb;
+  const double2 u = arr[base], v = arr[plane + base];
+  return make_double2(F.ex * u.x + F.ey * v.x, F.ex * u.y + F.ey * v.y);
+}
+
+// dSigma pair value: S (from the GEMM) plus K_diag o x for the low-rank form.
+__device__ inline double2 sigma_pair(const AdjArgs& a, const double2* S, const double2* X, int b, int k, int p) {
+  const size_t i = (size_t)b * a.n + (size_t)k * a.npair + p;
+  double2 v = S[i];
+  if (a.kdiag) v = cadd(v, cmul(a.kdiag[(size_t)k * a.npair + p], X[i]));
+  return v;
+}
+
+// Element (n, m) of H_k = diag(eps) + dSigma - E e.d (e-h block: dSigma_vc = conj(dSigma_cv)).
+__device__ inline double2 ham_element(const AdjArgs& a, const double2* S, const double2* X, const Slot& s, double ef,
+                                      double2 de) {
+  double2 ds = make_double2(0.0, 0.0);
+  const int p = pair_of(a, s.nn, s.m);
+  if (p >= 0) {
+    ds = sigma_pair(a, S, X, s.b, s.k, p);
+  } else if (a.block == TDG_BLOCK_EH && s.nn < a.nv && s.m >= a.nv) {
+    ds = cconj(sigma_pair(a, S, X, s.b, s.k, (s.m - a.nv) * a.nv + s.nn));
+  }
+  double2 h = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
+  if (s.nn == s.m) h.x += a.eps[(size_t)s.k * a.nb + s.nn];
+  return h;
+}
+
+// Cotangent of rho(t_n) from the observable weights: (gP D^H + gJ V^H) / nk,
+// plus gocc / nk on the first conduction band's occupation.
+__device__ inline double2 obs_cotangent(const AdjArgs& a, const Slot& s, const tdg_field& F, const double* gP,
+                                        const double* gJ, const double* gocc, int64_t gstride, int step) {
+  const size_t w = (size_t)s.b * gstride + step;
+  const double wp = gP ? gP[w] : 0.0, wj = gJ ? gJ[w] : 0.0, wo = gocc ? gocc[w] : 0.0;
+  const int et = s.m * a.nb + s.nn;  // transposed element
+  double2 c = make_double2(0.0, 0.0);
+  if (wp != 0.0) {
+    const double2 d = proj_e(F, a, a.dip, s.k, et);
+    c.x += wp * d.x;
+    c.y -= wp * d.y;
+  }
+  if (wj != 0.0) {
+    const double2 v = proj_e(F, a, a.vel, s.k, et);
+    c.x += wj * v.x;
+    c.y -= wj * v.y;
+  }
+  if (s.nn == s.m && s.nn == a.nv) c.x += wo;
+  return make_double2(c.x / a.nk, c.y / a.nk);
+}
+
+__global__ void __launch_bounds__(AT) adj_init_kernel(AdjArgs a, const double2* rho_in, double2* rho, double2* abar,
+                                                      const double* gP, const double* gJ, const double* gocc,
+                                                      int64_t gstride) {
+  const Slot s = slot_of(a);
+  if (!s.active) return;
+  const double occ = (s.nn == s.m && s.nn < a.nv) ? 1.0 : 0.0;
+  rho[s.g] = rho_in ? rho_in[s.g] : make_double2(occ, 0.0);
+  abar[s.g] = obs_cotangent(a, s, a.fields[s.b], gP, gJ, gocc, gstride, a.nsteps);
+}
+
+// x[b][k P + p] = (y - rho_eq)[pair p of k], column-major [n] x [B].
+__global__ void __launch_bounds__(AT) adj_gather_kernel(AdjArgs a, const double2* __restrict__ y, double2* x) {
+  const Slot s = slot_of(a);
+  if (!s.active) return;
+  const int p = pair_of(a, s.nn, s.m);
+  if (p < 0) return;
+  const double2 v = y[s.g];
+  x[(size_t)s.b * a.n + (size_t)s.k * a.npair + p] =
+      make_double2(v.x - ((s.nn == s.m && s.nn < a.nv) ? 1.0 : 0.0), v.y);
+}
+
+// Forward stage s of step `step` at the state y: f = -i [H, y]; RK4
+// accumulation; the next stage's state (or rho_{n+1} after the fourth stage)
+// into y_next and its gather into x_next (if not NULL).
+__global__ void __launch_bounds__(AT) adj_fwd_stage_kernel(AdjArgs a, int step, int st, const double2* rho_n,
+                                                           const double2* y, const double2* S, const double2* X,
+                                                           double2* acc, double2* y_next, double2* x_next) {
+  __shared__ double2 sh_y[AT], sh_h[AT];
+  const Slot s = slot_of(a);
+  const int t = threadIdx.x, nb = a.nb, o = s.lk * nb * nb;
+  if (s.active) {
+    const tdg_field F = a.fields[s.b];
+    const double ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
+    sh_y[t] = y[s.g];
+    sh_h[t] = ham_element(a, S, X, s, ef, proj_e(F, a, a.dip, s.k, s.e));
+  }
+  __syncthreads();
+  if (!s.active) return;
+  double2 c = make_double2(0.0, 0.0);
+  for (int l = 0; l < nb; ++l) {
+    const double2 hr = cmul(sh_h[o + s.nn * nb + l], sh_y[o + l * nb + s.m]);
+    const double2 rh = cmul(sh_y[o + s.nn * nb + l], sh_h[o + l * nb + s.m]);
+    c.x += hr.x - rh.x;
+    c.y += hr.y - rh.y;
+  }
+  const double2 f = make_double2(c.y, -c.x);  // -i c
+  const double2 rn = rho_n[s.g];
+  const double dt = a.dt;
+  double2 next;
+  if (st == 0) {
+    acc[s.g] = f;
+    next = make_double2(rn.x + 0.5 * dt * f.x, rn.y + 0.5 * dt * f.y);
+  } else if (st == 1) {
+    const double2 ac = acc[s.g];
+    acc[s.g] = make_double2(ac.x + 2.0 * f.x, ac.y + 2.0 * f.y);
+    next = make_double2(rn.x + 0.5 * dt * f.x, rn.y + 0.5 * dt * f.y);
+  } else if (st == 2) {
+    const double2 ac = acc[s.g];
+    acc[s.g] = make_double2(ac.x + 2.0 * f.x, ac.y + 2.0 * f.y);
+    next = make_double2(rn.x + dt * f.x, rn.y + dt * f.y);
+  } else {
+    const double2 ac = acc[s.g];
+    const double w = dt / 6.0;
+    next = make_double2(rn.x + w * (ac.x + f.x), rn.y + w * (ac.y + f.y));
+  }
+  y_next[s.g] = next;
+  const int p = pair_of(a, s.nn, s.m);
+  if (x_next && p >= 0)
+    x_next[(size_t)s.b * a.n + (size_t)s.k * a.npair + p] =
+        make_double2(next.x - ((s.nn == s.m && s.nn < a.nv) ? 1.0 : 0.0), next.y);
+}
+
+// Pullback, first half, for stage s: g = coef * abar + cnext * ybar_next;
+// ydirect = i [H^H, g]; sbc = conj(gather(Sigbar)) with Sigbar = -i [y^H, g];
+// part[s][b][k] = Re sum conj(g) i [e.d, y] over the k point's elements.
+__global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int st, const double2* y, const double2* S,
+                                                       const double2* X, const double2* abar, double coef,
+                                                       const double2* ybar_next, double cnext, double2* ydirect,
+                                                       double2* sbc, double* part) {
+  __shared__ double2 sh_y[AT], sh_h[AT], sh_g[AT], sh_d[AT], sh_sig[AT];
+  __shared__ double sh_de[AT];
+  const Slot s = slot_of(a);
+  const int t = threadIdx.x, nb = a.nb, nb2 = nb * nb, o = s.lk * nb2;
+  if (s.active) {
+    const tdg_field F = a.fields[s.b];
+    const double ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
+    const double2 de = proj_e(F, a, a.dip, s.k, s.e);
+    const double2 ab = abar[s.g];
+    double2 g = make_double2(coef * ab.x, coef * ab.y);
+    if (ybar_next) {
+      const double2 yb = ybar_next[s.g];
+      g.x += cnext * yb.x;
+      g.y += cnext * yb.y;
+    }
+    sh_y[t] = y[s.g];
+    sh_h[t] = ham_element(a, S, X, s, ef, de);
+    sh_g[t] = g;
+    sh_d[t] = de;
+  }
+  __syncthreads();
+  if (s.active) {
+    double2 c1 = make_double2(0.0, 0.0), c2 = c1, c3 = c1;
+    for (int l = 0; l < nb; ++l) {
+      // (H^H)[n][l] g[l][m] - g[n][l] (H^H)[l][m],  (H^H)[i][j] = conj(H[j][i])
+      const double2 a1 = cmul(cconj(sh_h[o + l * nb + s.nn]), sh_g[o + l * nb + s.m]);
+      const double2 b1 = cmul(sh_g[o + s.nn * nb + l], cconj(sh_h[o + s.m * nb + l]));
+      c1.x += a1.x - b1.x;
+      c1.y += a1.y - b1.y;
+      const double2 a2 = cmul(cconj(sh_y[o + l * nb + s.nn]), sh_g[o + l * nb + s.m]);
+      const double2 b2 = cmul(sh_g[o + s.nn * nb + l], cconj(sh_y[o + s.m * nb + l]));
+      c2.x += a2.x - b2.x;
+      c2.y += a2.y - b2.y;
+      const double2 a3 = cmul(sh_d[o + s.nn * nb + l], sh_y[o + l * nb + s.m]);
+      const double2 b3 = cmul(sh_y[o + s.nn * nb + l], sh_d[o + l * nb + s.m]);
+      c3.x += a3.x - b3.x;
+      c3.y += a3.y - b3.y;
+    }
+    ydirect[s.g] = make_double2(-c1.y, c1.x);  // i c1
+    sh_sig[t] = make_double2(c2.y, -c2.x);     // -i c2
+    // Re(conj(g) * i c3) = g.x (-c3.y) + g.y c3.x
+    const double2 g = sh_g[t];
+    sh_de[t] = -g.x * c3.y + g.y * c3.x;
+  }
+  __syncthreads();
+  if (!s.active) return;
+  const int p = pair_of(a, s.nn, s.m);
+  if (p >= 0) {
+    double2 sb = sh_sig[t];
+    if (a.block == TDG_BLOCK_EH) {
+      const double2 tr = sh_sig[o + s.m * nb + s.nn];
+      sb = make_double2(sb.x + tr.x, sb.y - tr.y);
+    }
+    sbc[(size_t)s.b * a.n + (size_t)s.k * a.npair + p] = cconj(sb);
+  }
+  if (s.e == 0) {
+    double v = 0.0;
+    for (int i = 0; i < nb2; ++i) v += sh_de[o + i];
+    part[((size_t)st * a.batch + s.b) * a.nk + s.k] = v;
+  }
+}
+
+// Pullback, second half, for stage s: ybar = ydirect + scatter(conj(T + K_diag o sbc));
+// acca accumulates dL/drho_n; after the first stage abar <- acca + ybar + observable cotangent.
+__global__ void __launch_bounds__(AT) adj_bwd_b_kernel(AdjArgs a, int step, int st, const double2* ydirect,
+                                                       const double2* T, const double2* sbc, double2* ybar,
+                                                       double2* acca, double2* abar, const double* gP,
+                                                       const double* gJ, const double* gocc, int64_t gstride) {
+  const Slot s = slot_of(a);
+  if (!s.active) return;
+  double2 yb = ydirect[s.g];
+  const int p = pair_of(a, s.nn, s.m);
+  if (p >= 0) {
+    const size_t i = (size_t)s.b * a.n + (size_t)s.k * a.npair + p;
+    double2 v = T[i];
+    if (a.kdiag) v = cadd(v, cmul(a.kdiag[(size_t)s.k * a.npair + p], sbc[i]));
+    yb.x += v.x;
+    yb.y -= v.y;
+  }
+  ybar[s.g] = yb;
+  if (st == 3) {
+    const double2 ab = abar[s.g];
+    acca[s.g] = make_double2(ab.x + yb.x, ab.y + yb.y);
+  } else if (st > 0) {
+    const double2 ac = acca[s.g];
+    acca[s.g] = make_double2(ac.x + yb.x, ac.y + yb.y);
+  } else {
+    const double2 ac = acca[s.g];
+    const double2 oc = obs_cotangent(a, s, a.fields[s.b], gP, gJ, gocc, gstride, step);
+    abar[s.g] = make_double2(ac.x + yb.x + oc.x, ac.y + yb.y + oc.y);
+  }
+}
+
+// dL/dE at the four stage times of `step` (sum over k in fixed order) and
+// its contribution to dL/d(e0, omega, tau, t0).  One block per instance.
+__global__ void __launch_bounds__(256) adj_de_kernel(AdjArgs a, int step, const double* part, double* dE,
+                                                     double* dfield) {
+  __shared__ double red[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const tdg_field F = a.fields[b];
+  for (int st = 0; st < 4; ++st) {
+    double v = 0.0;
+    for (int k = t; k < a.nk; k += 256) v += part[((size_t)st * a.batch + b) * a.nk + k];
+    red[t] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    if (t == 0) {
+      const double d = red[0];
+      if (dE) dE[((size_t)b * a.nsteps + step) * 4 + st] = d;
+      const double tt = ((double)step + stage_offset(st)) * a.dt;
+      const double dd = tt - F.t0, g = exp(-dd * dd / (2.0 * F.tau * F.tau));
+      const double c = cos(F.omega * tt), sn = sin(F.omega * tt);
+      double* df = dfield + (size_t)b * 4;
+      df[0] += d * (g * c);
+      df[1] += d * (-F.e0 * g * tt * sn);
+      df[2] += d * (F.e0 * g * c * dd * dd / (F.tau * F.tau * F.tau));
+      df[3] += d * (F.e0 * g * c * dd / (F.tau * F.tau));
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void fill_zero_kernel(double* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+__global__ void conj_kernel(double2* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i].y = -p[i].y;
+}
+
+// Carves 256-byte-aligned pieces out of one workspace block.
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
+
+}  // namespace
+
+using namespace tdg;
+
+extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
+                                     const tdg_field* fields, int32_t batch, double dt, const void* rho0,
+                                     int32_t checkpoint_every, const tdg_obs_grad* gobs, tdg_grads* out) {
+  if (!ctx) return TDG_E_INVAL;
+  if (!op || !model || !fields || !gobs || !out) return fail(ctx, TDG_E_INVAL, "NULL argument");
+  TDG_TRY(validate_model(ctx, model));
+  if (op->dtype != TDG_C128) return fail(ctx, TDG_E_UNSUPPORTED, "the adjoint runs on TDG_C128 operators only");
+  if (op->kind != TDG_OP_DENSE && op->kind != TDG_OP_LOWRANK) return fail(ctx, TDG_E_INVAL, "operator kind %d", op->kind);
+  const bool lowrank = op->kind == TDG_OP_LOWRANK;
+  const int npair = pairs_per_k(model, op->block);
+  if (npair <= 0) return fail(ctx, TDG_E_INVAL, "unknown block %d", op->block);
+  const int nk = model->nk1 * model->nk2, nb = model->nb, nb2 = nb * nb;
+  const int64_t n = (int64_t)nk * npair;
+  if (op->n != n) return fail(ctx, TDG_E_INVAL, "operator n = %lld, model needs %lld", (long long)op->n, (long long)n);
+  if (batch < 1 || batch > 65535) return fail(ctx, TDG_E_INVAL, "batch = %d", batch);
+  if (!(dt > 0.0)) return fail(ctx, TDG_E_INVAL, "dt must be positive");
+  const int64_t rank = lowrank ? op->rank : 0;
+  if (lowrank) {
+    if (!op->kdiag || !op->us || !op->w || rank < 1 || rank > n) return fail(ctx, TDG_E_INVAL, "low-rank operator");
+  } else {
+    if (!op->K || op->ld < n) return fail(ctx, TDG_E_INVAL, "dense operator");
+    if (out->dus || out->dw) return fail(ctx, TDG_E_INVAL, "factor gradients need a low-rank operator");
+  }
+  const double ns = fields[0].nsteps;
+  for (int b = 0; b < batch; ++b) {
+    const tdg_field& f = fields[b];
+    if (!(f.tau > 0.0) || !std::isfinite(f.e0) || !std::isfinite(f.omega) || !std::isfinite(f.t0))
+      return fail(ctx, TDG_E_INVAL, "field %d parameters", b);
+    if (f.nsteps != ns) return fail(ctx, TDG_E_UNSUPPORTED, "the adjoint needs equal nsteps for every instance");
+  }
+  if (!(ns >= 1.0) || ns > 1e8 || ns != std::floor(ns)) return fail(ctx, TDG_E_INVAL, "nsteps");
+  const int nsteps = (int)ns;
+  if ((gobs->gP || gobs->gJ || gobs->gocc) && gobs->stride < nsteps + 1)
+    return fail(ctx, TDG_E_INVAL, "observable cotangent stride < nsteps + 1");
+  if (checkpoint_every < 1) return fail(ctx, TDG_E_INVAL, "checkpoint_every must be >= 1");
+  const int M = std::min(checkpoint_every, nsteps);
+  const int nck = (nsteps + M - 1) / M;
+  TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+
+  // ---- workspace ---------------------------------------------------------
+  const size_t st_el = (size_t)batch * nk * nb2;
+  const size_t st_b = st_el * sizeof(double2);
+  const int cblocks = (lowrank ? M : 1) * 4;
+  const size_t xn_b = (size_t)n * batch * sizeof(double2);
+  const size_t zr_b = (size_t)std::max<int64_t>(rank, 1) * batch * sizeof(double2);
+  Carver cv;
+  const size_t o_ck = cv.take(st_b * nck), o_seg = cv.take(st_b * M), o_ys = cv.take(st_b * 3),
+               o_out = cv.take(st_b), o_acc = cv.take(st_b), o_abar = cv.take(st_b), o_ybar = cv.take(st_b),
+               o_yd = cv.take(st_b), o_acca = cv.take(st_b), o_s = cv.take(xn_b * 4), o_x = cv.take(xn_b * cblocks),
+               o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
+               o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)4 * batch * nk * sizeof(double)),
+               o_df = cv.take((size_t)batch * 4 * sizeof(double)), o_f = cv.take((size_t)batch * sizeof(tdg_field));
+  void* base = nullptr;
+  TDG_TRY(ws_reserve(ctx, WS_ADJ, cv.off, &base));
+  char* wb = (char*)base;
+  auto P2 = [&](size_t o) { return (double2*)(wb + o); };
+  double2 *CK = P2(o_ck), *SEG = P2(o_seg), *YS = P2(o_ys), *OUT = P2(o_out), *ACC = P2(o_acc), *ABAR = P2(o_abar),
+          *YBAR = P2(o_ybar), *YD = P2(o_yd), *ACCA = P2(o_acca), *SS = P2(o_s), *XS = P2(o_x), *SBC = P2(o_sbc),
+          *TT = P2(o_t), *ZS = P2(o_z), *UC = P2(o_uc);
+  double* part = (double*)(wb + o_part);
+  double* dfacc = (double*)(wb + o_df);
+  tdg_field* dfields = (tdg_field*)(wb + o_f);
+  TDG_TRY(hip_check(ctx, hipMemcpyAsync(dfields, fields, sizeof(tdg_field) * batch, hipMemcpyHostToDevice, ctx->stream),
+                    "field upload"));
+
+  AdjArgs a;
+  a.nk = nk;
+  a.nb = nb;
+  a.nv = model->nv;
+  a.npair = npair;
+  a.block = op->block;
+  a.batch = batch;
+  a.nsteps = nsteps;
+  a.n = n;
+  a.dt = dt;
+  a.eps = model->eps;
+  a.dip = (const double2*)model->dip;
+  a.vel = (const double2*)model->vel;
+  a.fields = dfields;
+  a.kdiag = lowrank ? (const double2*)op->kdiag : nullptr;
+
+  rocblas_handle h = nullptr;
+  TDG_TRY(blas_handle(ctx, (void**)&h));
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  auto gemm = [&](rocblas_operation ta, rocblas_operation tb, int64_t m_, int64_t n_, int64_t k_, const void* A,
+                  int64_t lda, const void* B, int64_t ldb, const rocblas_double_complex* beta, void* C,
+                  int64_t ldc) -> int {
+    const rocblas_status st =
+        rocblas_zgemm_64(h, ta, tb, m_, n_, k_, &one, (const rocblas_double_complex*)A, lda,
+                         (const rocblas_double_complex*)B, ldb, beta, (rocblas_double_complex*)C, ldc);
+    if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_zgemm status %d", (int)st);
+    return TDG_OK;
+  };
+  const rocblas_operation NN = rocblas_operation_none, TR = rocblas_operation_transpose;
+  // S = K X (dense) or Z = W X, S = US Z (low rank); K, W, US row-major
+  auto apply_k = [&](const double2* X, double2* S, double2* Z) -> int {
+    if (!lowrank) return gemm(TR, NN, n, batch, n, op->K, op->ld, X, n, &zero, S, n);
+    TDG_TRY(gemm(TR, NN, rank, batch, n, op->w, n, X, n, &zero, Z, rank));
+    return gemm(TR, NN, n, batch, rank, op->us, rank, Z, rank, &zero, S, n);
+  };
+  // T with K^H sbar = conj(T) (+ K_diag term in the kernel): T = K^T conj(sbar), or
+  // Uc = US^T conj(sbar) = conj(US^H sbar), T = W^T Uc
+  auto apply_kh = [&](const double2* Sbc, double2* Uc) -> int {
+    if (!lowrank) return gemm(NN, NN, n, batch, n, op->K, op->ld, Sbc, n, &zero, TT, n);
+    TDG_TRY(gemm(NN, NN, rank, batch, n, op->us, rank, Sbc, n, &zero, Uc, rank));
+    return gemm(NN, NN, n, batch, rank, op->w, n, Uc, rank, &zero, TT, n);
+  };
+
+  const int kpb = AT / nb2;
+  const dim3 grid((unsigned)((nk + kpb - 1) / kpb), (unsigned)batch);
+  auto xblk = [&](int cb) { return XS + (size_t)cb * n * batch; };
+  auto sbcblk = [&](int cb) { return SBC + (size_t)cb * n * batch; };
+  auto zblk = [&](int cb) { return ZS + (size_t)cb * rank * batch; };
+  auto ucblk = [&](int cb) { return UC + (size_t)cb * rank * batch; };
+  auto sst = [&](int s) { return SS + (size_t)s * n * batch; };
+  auto ys = [&](int s) { return YS + (size_t)(s - 1) * st_el; };  // s = 1, 2, 3
+
+  // One forward step from rho_in to rho_out, keeping y_s, S_s, X_s, Z_s of
+  // its stages in the column block group j.
+  auto run_step = [&](int step, const double2* rho_in, double2* rho_out, int j) -> int {
+    hipLaunchKernelGGL(adj_gather_kernel, grid, dim3(AT), 0, ctx->stream, a, rho_in, xblk(j * 4));
+    for (int s = 0; s < 4; ++s) {
+      const double2* y = s == 0 ? rho_in : ys(s);
+      TDG_TRY(apply_k(xblk(j * 4 + s), sst(s), lowrank ? zblk(j * 4 + s) : nullptr));
+      hipLaunchKernelGGL(adj_fwd_stage_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, rho_in, y, sst(s),
+                         xblk(j * 4 + s), ACC, s < 3 ? ys(s + 1) : rho_out, s < 3 ? xblk(j * 4 + s + 1) : nullptr);
+    }
+    return launch_check(ctx, "adjoint forward step");
+  };
+
+  // ---- forward sweep with checkpoints -------------------------------------
+  hipLaunchKernelGGL(adj_init_kernel, grid, dim3(AT), 0, ctx->stream, a, (const double2*)rho0, CK, ABAR, gobs->gP,
+                     gobs->gJ, gobs->gocc, gobs->stride);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(256), 0, ctx->stream, dfacc, (int64_t)batch * 4);
+  if (lowrank && out->dus)
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(256), dim3(256), 0, ctx->stream, (double*)out->dus, n * rank * 2);
+  if (lowrank && out->dw)
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(256), dim3(256), 0, ctx->stream, (double*)out->dw, n * rank * 2);
+  TDG_TRY(launch_check(ctx, "adjoint init"));
+  for (int c = 0; c + 1 < nck; ++c) {
+    // steps c M .. (c + 1) M - 1, the last landing on checkpoint c + 1; the
+    // states between alternate over SEG's first slot and OUT (both idle here)
+    const double2* rin = CK + (size_t)c * st_el;
+    for (int i = 0; i < M; ++i) {
+      double2* rout = (i == M - 1) ? CK + (size_t)(c + 1) * st_el : ((i & 1) ? OUT : SEG);
+      TDG_TRY(run_step(c * M + i, rin, rout, 0));
+      rin = rout;
+    }
+  }
+
+  // ---- backward sweep ------------------------------------------------------
+  for (int c = nck - 1; c >= 0; --c) {
+    const int start = c * M, end = std::min(nsteps, start + M);
+    // states rho_start .. rho_{end-1}: slot 0 is the checkpoint itself
+    auto seg = [&](int i) { return i == 0 ? CK + (size_t)c * st_el : SEG + (size_t)i * st_el; };
+    for (int i = 0; i + 1 < end - start; ++i) TDG_TRY(run_step(start + i, seg(i), seg(i + 1), 0));
+    for (int step = end - 1; step >= start; --step) {
+      const int j = lowrank ? step - start : 0;
+      TDG_TRY(run_step(step, seg(step - start), OUT, j));
+      static const double coef[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+      static const double cnext[4] = {0.5, 0.5, 1.0, 0.0};
+      for (int s = 3; s >= 0; --s) {
+        const double2* y = s == 0 ? seg(step - start) : ys(s);
+        const int cb = j * 4 + s;
+        hipLaunchKernelGGL(adj_bwd_a_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, y, sst(s), xblk(cb), ABAR,
+                           coef[s] * dt, s == 3 ? (const double2*)nullptr : YBAR, cnext[s] * dt, YD, sbcblk(cb), part);
+        TDG_TRY(apply_kh(sbcblk(cb), lowrank ? ucblk(cb) : nullptr));
+        hipLaunchKernelGGL(adj_bwd_b_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, YD, TT, sbcblk(cb), YBAR,
+                           ACCA, ABAR, gobs->gP, gobs->gJ, gobs->gocc, gobs->stride);
+      }
+      hipLaunchKernelGGL(adj_de_kernel, dim3(batch), dim3(256), 0, ctx->stream, a, step, part, out->dE, dfacc);
+      TDG_TRY(launch_check(ctx, "adjoint backward step"));
+    }
+    if (lowrank && (out->dus || out->dw)) {
+      // conj(dL/dS)^T += Z Sbc^T and conj(dL/dV^H)^T += X Uc^T over the segment's stage columns
+      const int64_t cols = (int64_t)(end - start) * 4 * batch;
+      if (out->dus) TDG_TRY(gemm(NN, TR, rank, n, cols, ZS, rank, SBC, n, &one, out->dus, rank));
+      if (out->dw) TDG_TRY(gemm(NN, TR, n, rank, cols, XS, n, UC, rank, &one, out->dw, n));
+    }
+  }
+
+  if (lowrank && out->dus)
+    hipLaunchKernelGGL(conj_kernel, dim3(256), dim3(256), 0, ctx->stream, (double2*)out->dus, n * rank);
+  if (lowrank && out->dw)
+    hipLaunchKernelGGL(conj_kernel, dim3(256), dim3(256), 0, ctx->stream, (double2*)out->dw, n * rank);
+  if (out->drho0)
+    TDG_TRY(hip_check(ctx, hipMemcpyAsync(out->drho0, ABAR, st_b, hipMemcpyDeviceToDevice, ctx->stream), "drho0 copy"));
+  if (out->dfield)
+    TDG_TRY(hip_check(ctx, hipMemcpyAsync(out->dfield, dfacc, (size_t)batch * 4 * sizeof(double),
+                                          hipMemcpyDeviceToDevice, ctx->stream),
+                      "dfield copy"));
+  TDG_TRY(launch_check(ctx, "adjoint finish"));
+  return hip_check(ctx, hipStreamSynchronize(ctx->stream), "adjoint sync");
+}

@@ -179,7 +179,8 @@ void release_blas(tdg_ctx ctx) {
   }
 }
 
-static int blas_handle(tdg_ctx ctx, rocblas_handle* out) {
+int blas_handle(tdg_ctx ctx, void** out_handle) {
+  rocblas_handle* out = (rocblas_handle*)out_handle;
   if (!ctx->blas) {
     rocblas_handle h = nullptr;
     if (rocblas_create_handle(&h) != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_create_handle");
@@ -303,7 +304,7 @@ extern "C" int tdg_kernel_compress(tdg_ctx ctx, const void* K, int64_t ld, int32
   TDG_TRY(launch_check(ctx, "compress row sums"));
 
   rocblas_handle h = nullptr;
-  TDG_TRY(blas_handle(ctx, &h));
+  TDG_TRY(blas_handle(ctx, (void**)&h));
   double* dvals = (double*)D;
   double* evals_off = dvals + n;
   int* info = (int*)I;
@@ -434,7 +435,7 @@ extern "C" int tdg_kernel_compress_randomized(tdg_ctx ctx, const void* K, int64_
   TDG_TRY(launch_check(ctx, "compress statistics"));
 
   rocblas_handle h = nullptr;
-  TDG_TRY(blas_handle(ctx, &h));
+  TDG_TRY(blas_handle(ctx, (void**)&h));
   const unsigned eb = (unsigned)std::min<size_t>((nl + 255) / 256, 8192);
 
   // dst = K_off src for an n x l column-major block (K row-major: K = (K as column-major)^T)

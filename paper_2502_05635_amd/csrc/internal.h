@@ -37,6 +37,7 @@ enum WsSlot {
   WS_RSVD_Z,     // randomized compression: K_off Q, then Q W, c128 column-major [l][n]
   WS_RSVD_F,     // randomized compression: complex64 copies of Q and K Q for a C64 kernel
   WS_RSVD_T,     // randomized compression: Q^H K_off Q, c128 [l][l], and Householder scalars
+  WS_ADJ,        // adjoint propagation: checkpoints, segment states, stage data, cotangents
   WS_COUNT
 };
 
@@ -84,6 +85,8 @@ int validate_model(tdg_ctx ctx, const tdg_model* m);
 int pairs_per_k(const tdg_model* m, int block);
 // Destroy the context's rocBLAS handle if compression created one.
 void release_blas(tdg_ctx ctx);
+// The context's rocBLAS handle (created on first use), bound to its stream.
+int blas_handle(tdg_ctx ctx, void** handle);
 // Complex FP32 matrix-core product Y[s] = A * sum(X slices) (gemm.hip).
 void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
                int x_slices, int64_t x_slice_stride, void* Y, int64_t ldy, int64_t y_slice_stride, int ncols,
