@@ -314,8 +314,14 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * FP32 matrix products on the matrix cores (split-K partials summed by the
  * stage kernel); below it, every instance streams the operator itself. */
 #define TDG_OPT_BATCHED_MIN 2
-/* Rows per block of the batched path's matrix-core product: 64 (default) or 128. */
+/* Tiling of the batched path's complex FP32 matrix-core products:
+ * TDG_OPT_GEMM_VARIANT -1 (default) times the tilings on the first use of each
+ * product shape (M, K, instances, split) and keeps the fastest for the
+ * context; 0 = 64-row tiles, 1 = 64-row tiles with the next K tile prefetched
+ * into registers and two LDS buffers, 2 = 128-row tiles.  The tilings differ
+ * only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects 0 / 2. */
 #define TDG_OPT_GEMM_TILE 3
+#define TDG_OPT_GEMM_VARIANT 4
 int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
 /* Name of the stage-kernel variant the last tdg_propagate used ("" before any). */
 const char* tdg_last_variant(tdg_ctx ctx);

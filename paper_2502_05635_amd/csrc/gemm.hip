@@ -255,6 +255,126 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_128(GemmArgs g) {
     }
 }
 
+// Third tiling: the first one's 64 rows x 64 instances and wave layout, with
+// the next K tile loaded into registers while the current one is multiplied
+// and two LDS buffers, so one barrier per tile separates the writers of one
+// buffer from the readers of the other.  AVEC as above.
+template <bool AVEC>
+__global__ void __launch_bounds__(256) cgemm_f32_mfma_pf(GemmArgs g) {
+  __shared__ float As[2][BM][2 * BKC + APAD];
+  __shared__ float Bs[2][2 * BKC][2 * BNI];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.x * BM, b0 = blockIdx.y * BNI, s = blockIdx.z;
+  const int kc_begin = s * g.kslice;
+  const int kc_end = min(g.Kc, kc_begin + g.kslice);
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 64;
+  floatx16 acc0, acc1;
+  for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
+
+  const int arow = t >> 2, acol = (t & 3) * 4;
+  const int xrow = t >> 4, xcol = (t & 15) * 4;
+  const int gi = m0 + arow;
+  float2 av[4], xv[4];
+
+  auto load_tile = [&](int kc0) {
+    if (AVEC) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int kc = kc0 + acol + 2 * q;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gi < g.M) {
+          if (kc + 1 < kc_end) {
+            v = *reinterpret_cast<const float4*>(g.A + (int64_t)gi * g.lda + kc);
+          } else if (kc < kc_end) {
+            const float2 u = g.A[(int64_t)gi * g.lda + kc];
+            v = make_float4(u.x, u.y, 0.f, 0.f);
+          }
+        }
+        av[2 * q] = make_float2(v.x, v.y);
+        av[2 * q + 1] = make_float2(v.z, v.w);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kc = kc0 + acol + q;
+        av[q] = (gi < g.M && kc < kc_end) ? g.A[(int64_t)gi * g.lda + kc] : make_float2(0.f, 0.f);
+      }
+    }
+    const int kx = kc0 + xrow;
+    float4 x01 = make_float4(0.f, 0.f, 0.f, 0.f), x23 = x01;
+    const int b = b0 + xcol;
+    if (kx < kc_end && b < g.ncols) {
+      for (int sl = 0; sl < g.x_slices; ++sl) {
+        const float2* src = g.X + sl * g.x_slice_stride + (int64_t)kx * g.ldx + b;
+        const float4 u = *reinterpret_cast<const float4*>(src);
+        x01.x += u.x;
+        x01.y += u.y;
+        x01.z += u.z;
+        x01.w += u.w;
+        if (b + 2 < g.ncols) {
+          const float4 v = *reinterpret_cast<const float4*>(src + 2);
+          x23.x += v.x;
+          x23.y += v.y;
+          x23.z += v.z;
+          x23.w += v.w;
+        }
+      }
+      if (b + 1 >= g.ncols) x01.z = x01.w = 0.f;
+      if (b + 3 >= g.ncols) x23.z = x23.w = 0.f;
+      if (b + 2 >= g.ncols) x23.x = x23.y = 0.f;
+    }
+    xv[0] = make_float2(x01.x, x01.y);
+    xv[1] = make_float2(x01.z, x01.w);
+    xv[2] = make_float2(x23.x, x23.y);
+    xv[3] = make_float2(x23.z, x23.w);
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[buf][arow][2 * (acol + q)] = av[q].x;
+      As[buf][arow][2 * (acol + q) + 1] = av[q].y;
+      Bs[buf][2 * xrow][xcol + q] = xv[q].x;
+      Bs[buf][2 * xrow + 1][xcol + q] = -xv[q].y;
+      Bs[buf][2 * xrow][BNI + xcol + q] = xv[q].y;
+      Bs[buf][2 * xrow + 1][BNI + xcol + q] = xv[q].x;
+    }
+  };
+
+  if (kc_begin < kc_end) {
+    load_tile(kc_begin);
+    store_tile(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC) {
+    const bool more = kc0 + BKC < kc_end;
+    if (more) load_tile(kc0 + BKC);
+#pragma unroll
+    for (int k2 = 0; k2 < 2 * BKC; k2 += 2) {
+      const float a = As[buf][wr + (lane & 31)][k2 + (lane >> 5)];
+      const float x0 = Bs[buf][k2 + (lane >> 5)][wc + (lane & 31)];
+      const float x1 = Bs[buf][k2 + (lane >> 5)][wc + 32 + (lane & 31)];
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, x0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, x1, acc1, 0, 0, 0);
+    }
+    if (more) store_tile(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  float* Yf = reinterpret_cast<float*>(g.Y + s * g.y_slice_stride);
+  const int part = wc >> 6;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int row = m0 + wr + i;
+    if (row >= g.M) continue;
+    const int b_0 = b0 + (lane & 31), b_1 = b0 + 32 + (lane & 31);
+    if (b_0 < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b_0) + part] = acc0[r];
+    if (b_1 < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b_1) + part] = acc1[r];
+  }
+}
+
 // out[i] = sum_s in[s * stride + i] for i < count (complex), fixed order.
 __global__ void __launch_bounds__(256) sum_slices_kernel(const float2* __restrict__ in, int slices, int64_t stride,
                                                         int64_t count, float2* __restrict__ out) {
@@ -282,12 +402,13 @@ void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stri
 int cgemm_f32_kslices(int kc) { return (kc + BKC - 1) / BKC; }
 
 // Launch Y[s] = A * sum(X slices) over split-K slices of `kslice` complex
-// columns (a multiple of 16; the number of slices is ceil(Kc / kslice)),
-// with 64-row (tile = 64) or 128-row (tile = 128) blocks.  ldx and the X
-// slice stride must be even (two instances per 16-byte load).
+// columns (a multiple of 16; the number of slices is ceil(Kc / kslice)) with
+// tiling `variant`: 0 = 64 rows, 1 = 64 rows with the next tile prefetched
+// and two LDS buffers, 2 = 128 rows.  ldx and the X slice stride must be even
+// (two instances per 16-byte load).
 void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
                int x_slices, int64_t x_slice_stride, void* Y, int64_t ldy, int64_t y_slice_stride, int ncols,
-               int kslice, int tile) {
+               int kslice, int variant) {
   GemmArgs g;
   g.A = (const float2*)A;
   g.lda = lda;
@@ -303,13 +424,21 @@ void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, co
   g.ncols = ncols;
   g.kslice = kslice;
   const int splits = (Kc + kslice - 1) / kslice;
-  if (tile == 64) {
+  const bool avec = ((lda & 1) == 0) && (((uintptr_t)A & 15) == 0);
+  if (variant == 0) {
     const dim3 grid((M + BM - 1) / BM, (ncols + BNI - 1) / BNI, splits);
     hipLaunchKernelGGL(cgemm_f32_mfma, grid, dim3(256), 0, stream, g);
     return;
   }
+  if (variant == 1) {
+    const dim3 grid((M + BM - 1) / BM, (ncols + BNI - 1) / BNI, splits);
+    if (avec)
+      hipLaunchKernelGGL(cgemm_f32_mfma_pf<true>, grid, dim3(256), 0, stream, g);
+    else
+      hipLaunchKernelGGL(cgemm_f32_mfma_pf<false>, grid, dim3(256), 0, stream, g);
+    return;
+  }
   const dim3 grid((M + BM2 - 1) / BM2, (ncols + BNI - 1) / BNI, splits);
-  const bool avec = ((lda & 1) == 0) && (((uintptr_t)A & 15) == 0);
   if (avec)
     hipLaunchKernelGGL(cgemm_f32_mfma_128<true>, grid, dim3(256), 0, stream, g);
   else

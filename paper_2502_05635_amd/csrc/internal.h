@@ -65,7 +65,7 @@ struct tdg_ctx_s {
   bool autotune = true;
   int forced_variant = -1;
   int batched_min = 4;  // complex64 operators use the matrix-core path from this batch size
-  int gemm_tile = 64;   // rows per block of the matrix-core product (64 or 128)
+  int gemm_variant = -1; // tiling of the matrix-core product: -1 tuned per shape, else 0..2 (cgemm_f32)
   std::vector<std::pair<std::string, int>> tuned;  // shape key -> variant index
   std::string last_variant;
 };
@@ -87,10 +87,11 @@ int pairs_per_k(const tdg_model* m, int block);
 void release_blas(tdg_ctx ctx);
 // The context's rocBLAS handle (created on first use), bound to its stream.
 int blas_handle(tdg_ctx ctx, void** handle);
-// Complex FP32 matrix-core product Y[s] = A * sum(X slices) (gemm.hip).
+// Complex FP32 matrix-core product Y[s] = A * sum(X slices) (gemm.hip); variant
+// 0 = 64-row tiles, 1 = 64-row tiles with a prefetched next tile, 2 = 128-row tiles.
 void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
                int x_slices, int64_t x_slice_stride, void* Y, int64_t ldy, int64_t y_slice_stride, int ncols,
-               int kslice, int tile);
+               int kslice, int variant);
 // BF16 split-precision product: A in TDG_BF16X2 storage (hi plane, then lo
 // plane, [M][lda], lda % 4 == 0), X complex64 [Kc][ldx] (gemm.hip).
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,

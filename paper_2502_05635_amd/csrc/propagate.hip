@@ -20,6 +20,7 @@
 // grid covers exactly those.  The working state lives in that sorted order
 // and is scattered back to the caller's order at the end.
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -951,9 +952,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   };
 
   if (batched) {
-    // split-K so that each product launches about 1024 blocks; slices are
-    // multiples of 16 complex columns (the GEMM's LDS stage)
-    const int tile = ctx->gemm_tile;
+    // split-K so that each product launches about 1024 blocks of 64 rows;
+    // slices are multiples of 32 complex columns (whole LDS stages)
+    const int tile = 64;
     auto kslice_for = [&](int64_t M, int64_t Kc) {
       const int64_t tiles = ((M + tile - 1) / tile) * ((batch + 63) / 64);
       int64_t splits = std::max<int64_t>(1, std::min<int64_t>(64, (1024 + tiles - 1) / tiles));
@@ -1006,8 +1007,74 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     bp.batch = batch;
     bp.dt = dt;
     const int ib = 256 / nb2;
+
+    // tiling of each FP32 product: forced, cached for its shape, or timed now
+    // (every tiling twice on the step-0 operands, the second run timed); the
+    // products only write Y / Z, which the loop below recomputes
+    int gv_main = 0, gv_proj = 0;
+    const int n_dyn0 = count_gt(0);
+    if (!bf16 && n_dyn0 > 0) {
+      auto pick = [&](const char* what, int64_t M, int64_t Kc, int64_t ks, const std::function<void(int)>& run,
+                      int* out) -> int {
+        if (ctx->gemm_variant >= 0) {
+          *out = ctx->gemm_variant;
+          return TDG_OK;
+        }
+        char key[160];
+        snprintf(key, sizeof(key), "gemm/%s/%lld/%lld/%d/%lld", what, (long long)M, (long long)Kc, n_dyn0,
+                 (long long)ks);
+        for (auto& kv : ctx->tuned)
+          if (kv.first == key) {
+            *out = kv.second;
+            return TDG_OK;
+          }
+        hipEvent_t e0, e1;
+        TDG_TRY(hip_check(ctx, hipEventCreate(&e0), "event"));
+        TDG_TRY(hip_check(ctx, hipEventCreate(&e1), "event"));
+        float best = 0.f;
+        int bestv = 0;
+        for (int v = 0; v < 3; ++v) {
+          run(v);
+          hipEventRecord(e0, ctx->stream);
+          run(v);
+          hipEventRecord(e1, ctx->stream);
+          TDG_TRY(hip_check(ctx, hipEventSynchronize(e1), "GEMM tuning"));
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, e0, e1);
+          if (v == 0 || ms < best) {
+            best = ms;
+            bestv = v;
+          }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        TDG_TRY(launch_check(ctx, "GEMM tuning"));
+        ctx->tuned.emplace_back(key, bestv);
+        *out = bestv;
+        return TDG_OK;
+      };
+      if (!lowrank) {
+        TDG_TRY(pick("dense", n, n, ks_main, [&](int v) {
+          cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, x0, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn0,
+                    (int)ks_main, v);
+        }, &gv_main));
+      } else {
+        TDG_TRY(pick("project", op->rank, n, ks_proj, [&](int v) {
+          cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, x0, xstride, 1, 0, Zbuf, ldy, op->rank * ldy,
+                    n_dyn0, (int)ks_proj, v);
+        }, &gv_proj));
+        sum_slices_c64(ctx->stream, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
+        TDG_TRY(pick("expand", n, op->rank, ks_main, [&](int v) {
+          cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy,
+                    n_dyn0, (int)ks_main, v);
+        }, &gv_main));
+      }
+    }
     ctx->last_variant = std::string(lowrank ? "batched_mfma_lowrank_" : "batched_mfma_dense_") +
                         (bf16 ? "bf16x2" : "f32");
+    if (!bf16)
+      ctx->last_variant += lowrank ? " (tilings " + std::to_string(gv_proj) + "/" + std::to_string(gv_main) + ")"
+                                   : " (tiling " + std::to_string(gv_main) + ")";
     tdg_obs ob = *obs;
     void* xc = x0;
     void* xn = x1;
@@ -1028,7 +1095,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
                            (int)ks_main);
             else
               cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xc, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
-                        (int)ks_main, tile);
+                        (int)ks_main, gv_main);
           } else {
             // projection split over K, summed once in fixed order, then expansion
             if (bf16)
@@ -1036,14 +1103,14 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
                            n_dyn, (int)ks_proj);
             else
               cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xc, xstride, 1, 0, Zbuf, ldy,
-                        op->rank * ldy, n_dyn, (int)ks_proj, tile);
+                        op->rank * ldy, n_dyn, (int)ks_proj, gv_proj);
             sum_slices_c64(ctx->stream, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
             if (bf16)
               cgemm_bf16x2(ctx->stream, op->us, ld_us, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
                            (int)ks_main);
             else
               cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy,
-                        n_dyn, (int)ks_main, tile);
+                        n_dyn, (int)ks_main, gv_main);
           }
           prof_end(ctx, TDG_KCLASS_GEMM);
         }
