@@ -186,6 +186,40 @@ int tdg_kernel_compress_randomized(tdg_ctx ctx, const void* K, int64_t ld, int32
                                    const tdg_trunc* trunc, const void* omega, int64_t l,
                                    int32_t power_iters, tdg_lowrank* out);
 
+/* Channel-wise compression (paper Eq. svd-channel-wise).  Channel (p, q) is
+ * the nk x nk block K[k P + p][k' P + q] over k, k' (a transition between
+ * band pairs p and q, Sec. "SVD analysis of electron-hole kernel").  Every
+ * off-diagonal channel (p != q) is replaced by its own truncated SVD
+ * S^{pq} V^{pq H} (S = U M), with the rank rule applied to that channel's nk
+ * singular values (R^2 over its elements); the diagonal channels, close to
+ * full rank in the paper, are kept whole.  The SVD of a channel A comes in
+ * FP64 from the eigendecomposition of the Hermitian dilation [[0, A], [A^H, 0]]
+ * (rocSOLVER heevd of order 2 nk).  The caller sets nk, npair, dtype, rmax
+ * and the pointers:
+ *   diag   device [P][nk][nk]              channel (p, p), row-major (dtype)
+ *   s      device [nk P][(P - 1) rmax]     row k P + p: S^{pq}[k][0 .. rmax) for
+ *                                          q != p in increasing q, zero past the rank
+ *   w      device [P][P - 1][rmax][nk]     V^{pq H} rows, same order, zero past the rank
+ *   ranks  HOST int64 [P][P] or NULL       kept rank per channel (nk on the diagonal)
+ *   sigma  HOST double [P][P][nk] or NULL  singular values per off-diagonal channel
+ * rmax is a multiple of 4 in [4, nk]; a channel needing more fails with
+ * TDG_E_INVAL after the ranks before it are reported.  K is TDG_C128 or
+ * TDG_C64 [nk P][ld]; dtype (of the outputs) TDG_C128 or TDG_C64.  Device
+ * workspace 16 (2 nk)^2 bytes.  Synchronises the stream. */
+typedef struct {
+  int64_t nk;
+  int32_t npair, dtype;
+  int64_t rmax;
+  void* diag;
+  void* s;
+  void* w;
+  int64_t* ranks;
+  double* sigma;
+} tdg_channels;
+
+int tdg_kernel_compress_channels(tdg_ctx ctx, const void* K, int64_t ld, int32_t dtype,
+                                 const tdg_trunc* trunc, tdg_channels* out);
+
 /* One driving-field instance (atomic units): a Gaussian-enveloped carrier
  * E(t) = e0 exp(-(t - t0)^2 / (2 tau^2)) cos(omega t) along (ex, ey), run for
  * nsteps RK4 steps.  64 bytes; arrays of it are HOST memory. */
@@ -197,13 +231,17 @@ typedef struct {
 
 #define TDG_OP_DENSE 0
 #define TDG_OP_LOWRANK 1
+#define TDG_OP_CHANNEL 2
 
 /* The kernel operator applied each RK4 stage.  dtype selects arithmetic:
  * TDG_C128 -> FP64 contraction, TDG_C64 -> FP32 contraction with FP32
  * accumulation, TDG_BF16X2 -> BF16 split-precision products with FP32
  * accumulation (drho is formed in FP64 and rounded; dSigma is widened back
  * to FP64 before the commutator).  Dense: K [n][ld].  Low rank: kdiag [n],
- * us [n][rank], w [rank][n] as written by tdg_kernel_compress. */
+ * us [n][rank], w [rank][n] as written by tdg_kernel_compress.  Channel-wise
+ * (TDG_C128 or TDG_C64, one instance at a time): K = tdg_channels.diag,
+ * us = tdg_channels.s, w = tdg_channels.w, rank = tdg_channels.rmax; kdiag
+ * and ld unused. */
 typedef struct {
   int32_t kind, dtype, block, pad;
   int64_t n;

@@ -9,7 +9,8 @@ the seeded inputs in ``workloads``).
 Modules, each following the paper's definitions step by step:
   kernel.py      direct (screened) electron-hole kernel on the lattice model
                  (Eq. sigma-from-k, Eq. bse-direct-def in its single-G limit)
-  compress.py    K = K_diag + U M V^H truncated SVD (Eq. svd_diag_offdiag)
+  compress.py    K = K_diag + U M V^H truncated SVD (Eq. svd_diag_offdiag) and the
+                 channel-wise truncated SVD (Eq. svd-channel-wise)
   propagate.py   RK4 integration of the TD-aGW equation of motion
                  (Eq. tdagw with Eq. sigma-from-k or Eq. svd_acc)
   observables.py polarisation, current, band occupation (Sec. SVD acceleration)
@@ -24,8 +25,10 @@ from .kernel import (  # noqa: F401
     pair_table, rytova_keldysh, cell_average_w0, fold_q, coulomb_matrix, build_kernel,
     kernel_element,
 )
-from .compress import split_diag, svd_offdiag, choose_rank, compress, randomized_compress  # noqa: F401
-from .propagate import field_at, DenseOp, LowRankOp, propagate, rho_equilibrium  # noqa: F401
+from .compress import (  # noqa: F401
+    split_diag, svd_offdiag, choose_rank, compress, randomized_compress, channel_blocks, compress_channelwise,
+)
+from .propagate import field_at, DenseOp, LowRankOp, ChannelOp, propagate, rho_equilibrium  # noqa: F401
 from .observables import observables  # noqa: F401
 from .bse import linear_operator, linear_response  # noqa: F401
 from .spectra import absorption, hhg  # noqa: F401

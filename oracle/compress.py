@@ -126,3 +126,33 @@ def randomized_compress(k: np.ndarray, rank: int, omega: np.ndarray, power_iters
         "s": s,
         "r": r,
     }
+
+
+def channel_blocks(k: np.ndarray, nk: int, npair: int):
+    """Channel (p, q) of K: the N_k x N_k block K[k P + p, k' P + q] over k, k'
+    (paper Sec. "SVD analysis of electron-hole kernel": a channel is a
+    transition (n1 n2) -> (n3 n4) between band pairs, over k and k')."""
+    kk = k.reshape(nk, npair, nk, npair)
+    return {(p, q): np.ascontiguousarray(kk[:, p, :, q]) for p in range(npair) for q in range(npair)}
+
+
+def compress_channelwise(k: np.ndarray, nk: int, npair: int, rule: str = "fraction", value: float = 0.05):
+    """Channel-wise truncated SVD, Eq. (svd-channel-wise): every off-diagonal
+    channel (p != q) K^{pq} ~ U~ M~ V~^H with its own rank (the rule applied to
+    that channel's singular values, N_k of them; R^2 over that channel's
+    elements); the diagonal channels are kept whole, as in the paper's
+    "K^{diag-ch} + 5 % K^{off-ch}".  Returns dict(diag {p: [nk][nk]},
+    off {(p, q): (S = U M [nk][r], V^H [r][nk], s)}, ranks {(p, q): r})."""
+    blocks = channel_blocks(k, nk, npair)
+    out = {"diag": {}, "off": {}, "ranks": {}}
+    for (p, q), a in blocks.items():
+        if p == q:
+            out["diag"][p] = a
+            out["ranks"][(p, q)] = nk
+            continue
+        u, s, vh = np.linalg.svd(a)
+        dev2 = float(np.sum(np.abs(a - a.mean()) ** 2))
+        r = choose_rank(s, rule, value, koff_mean_dev2=dev2)
+        out["off"][(p, q)] = (np.ascontiguousarray(u[:, :r] * s[None, :r]), np.ascontiguousarray(vh[:r]), s)
+        out["ranks"][(p, q)] = r
+    return out

@@ -51,6 +51,27 @@ class LowRankOp:
         return self.kdiag * x + self.us @ (self.vh @ x)
 
 
+class ChannelOp:
+    """dSigma with channel-wise factors (Eq. svd-channel-wise): pair p of k
+    receives sum_k' K^{pp}[k, k'] x[k' P + p] + sum_{q != p} S^{pq} (V^{pq H} x_q)[k],
+    x_q = x[q::P] (channel blocks of the k-major pair index)."""
+
+    def __init__(self, factors: dict, nk: int, npair: int):
+        self.f, self.nk, self.npair = factors, nk, npair
+
+    def apply(self, x: np.ndarray) -> np.ndarray:
+        P = self.npair
+        xs = x.reshape(self.nk, P)
+        y = np.zeros_like(xs)
+        for p in range(P):
+            y[:, p] = self.f["diag"][p] @ xs[:, p]
+            for q in range(P):
+                if q != p:
+                    s, vh, _ = self.f["off"][(p, q)]
+                    y[:, p] += s @ (vh @ xs[:, q])
+        return y.reshape(-1)
+
+
 def minus_i_commutator(h: np.ndarray, rho: np.ndarray) -> np.ndarray:
     """-i [H, rho] per k point."""
     return -1j * (h @ rho - rho @ h)

@@ -124,6 +124,18 @@ class LowRankFactors:
     dtype: str
 
 
+@dataclass
+class ChannelFactors:
+    """Channel-wise compressed kernel (see tdg_channels)."""
+    diag: torch.Tensor      # [P][nk][nk]
+    s: torch.Tensor         # [nk P][(P - 1) rmax]
+    w: torch.Tensor         # [P][P - 1][rmax][nk]
+    rmax: int
+    ranks: np.ndarray       # [P][P]
+    sigma: np.ndarray       # [P][P][nk]
+    dtype: str
+
+
 class Context:
     """A library context bound to one device and the current torch stream."""
 
@@ -232,8 +244,35 @@ class Context:
                                                              _ptr(omega_t), l, int(power_iters), C.byref(lr)))
         return self._factors(kdiag, us, w, sigma, lr, dtype)
 
+    def kernel_compress_channels(self, K: torch.Tensor, nk: int, npair: int, rule: str = "fraction",
+                                 value: float = 0.05, rmax: int | None = None,
+                                 out_dtype: str | None = None) -> ChannelFactors:
+        """Channel-wise truncated SVD (off-diagonal channels), diagonal channels kept."""
+        kdtype = "c128" if K.dtype == torch.complex128 else "c64"
+        kcode, _ = _cdtype(kdtype)
+        dtype = out_dtype or kdtype
+        code, tdt = _cdtype(dtype)
+        rmax = (nk + 3) // 4 * 4 if rmax is None else int(rmax)
+        rmax = min(rmax, nk // 4 * 4)
+        dev = K.device
+        diag = torch.empty((npair, nk, nk), dtype=tdt, device=dev)
+        s = torch.empty((nk * npair, (npair - 1) * rmax), dtype=tdt, device=dev)
+        w = torch.empty((npair, npair - 1, rmax, nk), dtype=tdt, device=dev)
+        ranks = np.zeros((npair, npair), dtype=np.int64)
+        sigma = np.zeros((npair, npair, nk), dtype=np.float64)
+        ch = abi.Channels(nk, npair, code, rmax, diag.data_ptr(), s.data_ptr(), w.data_ptr(), ranks.ctypes.data,
+                          sigma.ctypes.data)
+        tr = abi.Trunc(abi.TDG_TRUNC[rule], 0, float(value))
+        self._check(self._lib.tdg_kernel_compress_channels(self.h, _ptr(K), K.stride(0), kcode, C.byref(tr),
+                                                           C.byref(ch)))
+        return ChannelFactors(diag, s, w, rmax, ranks, sigma, dtype)
+
     # --- propagation --------------------------------------------------------
     def _operator(self, op, block: str, n: int) -> abi.Operator:
+        if isinstance(op, ChannelFactors):
+            code, _ = _cdtype(op.dtype)
+            return abi.Operator(abi.TDG_OP_CHANNEL, code, _block(block), 0, n, op.diag.data_ptr(), 0,
+                                None, op.s.data_ptr(), op.w.data_ptr(), op.rmax)
         if isinstance(op, LowRankFactors):
             code, _ = _cdtype(op.dtype)
             return abi.Operator(abi.TDG_OP_LOWRANK, code, _block(block), 0, n, None, 0,

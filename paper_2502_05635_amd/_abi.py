@@ -19,6 +19,7 @@ TDG_NB_MAX = 8
 TDG_TRUNC = {"rel_cut": 0, "fraction": 1, "rank": 2, "r2": 3}
 TDG_OP_DENSE = 0
 TDG_OP_LOWRANK = 1
+TDG_OP_CHANNEL = 2
 TDG_KCLASS_STAGE = 0
 TDG_KCLASS_PROJECT = 1
 TDG_KCLASS_GEMM = 2
@@ -49,6 +50,11 @@ class LowRank(C.Structure):
     _fields_ = [("n", C.c_int64), ("max_rank", C.c_int64), ("dtype", C.c_int32), ("pad", C.c_int32),
                 ("kdiag", P), ("us", P), ("w", P), ("sigma", P),
                 ("rank", C.c_int64), ("tail_fro", C.c_double), ("tail_spec", C.c_double)]
+
+
+class Channels(C.Structure):
+    _fields_ = [("nk", C.c_int64), ("npair", C.c_int32), ("dtype", C.c_int32), ("rmax", C.c_int64),
+                ("diag", P), ("s", P), ("w", P), ("ranks", P), ("sigma", P)]
 
 
 class Field(C.Structure):
@@ -85,6 +91,7 @@ SIGNATURES = {
     "tdg_kernel_compress": ([P, P, C.c_int64, C.c_int32, C.POINTER(Trunc), C.POINTER(LowRank)], C.c_int),
     "tdg_kernel_compress_randomized": ([P, P, C.c_int64, C.c_int32, C.POINTER(Trunc), P, C.c_int64, C.c_int32,
                                         C.POINTER(LowRank)], C.c_int),
+    "tdg_kernel_compress_channels": ([P, P, C.c_int64, C.c_int32, C.POINTER(Trunc), C.POINTER(Channels)], C.c_int),
     "tdg_propagate": ([P, C.POINTER(Operator), C.POINTER(Model), C.POINTER(Field), C.c_int32, C.c_double, P,
                        C.c_int32, C.POINTER(Obs)], C.c_int),
     "tdg_propagate_adjoint": ([P, C.POINTER(Operator), C.POINTER(Model), C.POINTER(Field), C.c_int32, C.c_double,

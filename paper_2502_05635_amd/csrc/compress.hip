@@ -168,6 +168,90 @@ __global__ void hermitize_kernel(double2* __restrict__ T, int64_t l) {
   T[j + i * l] = make_double2(m.x, -m.y);
 }
 
+// Hermitian dilation H = [[0, A], [A^H, 0]] (column-major c128, 2 nk x 2 nk)
+// of channel (p, q) of K: A[i][j] = K[i P + p][j P + q].  Its eigenvalues are
+// +-s_i; the eigenvector of +s_i is (u_i, v_i) / sqrt(2).
+template <typename T>
+__global__ void dilation_kernel(const typename Cx<T>::type* __restrict__ K, int64_t ld, int64_t nk, int P, int p,
+                                int q, double2* __restrict__ H) {
+  const int64_t c = blockIdx.y, m = 2 * nk;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    double2 v = make_double2(0.0, 0.0);
+    if (r < nk && c >= nk) {
+      const auto a = K[(r * P + p) * ld + (c - nk) * P + q];
+      v = make_double2((double)a.x, (double)a.y);
+    } else if (r >= nk && c < nk) {
+      const auto a = K[(c * P + p) * ld + (r - nk) * P + q];
+      v = make_double2((double)a.x, -(double)a.y);
+    }
+    H[r + c * m] = v;
+  }
+}
+
+// Row sums of channel (p, q), FP64, for the R^2 rule's mean.
+template <typename T>
+__global__ void channel_rowsum_kernel(const typename Cx<T>::type* __restrict__ K, int64_t ld, int64_t nk, int P,
+                                      int p, int q, double2* __restrict__ out) {
+  __shared__ double sr[256], si[256];
+  const int64_t r = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t c = threadIdx.x; c < nk; c += 256) {
+    const auto v = K[(r * P + p) * ld + c * P + q];
+    a += (double)v.x;
+    b += (double)v.y;
+  }
+  sr[threadIdx.x] = a;
+  si[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sr[threadIdx.x] += sr[threadIdx.x + w];
+      si[threadIdx.x] += si[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = make_double2(sr[0], si[0]);
+}
+
+// Diagonal channel p, row-major [nk][nk], in the output precision.
+template <typename T, typename TO>
+__global__ void diag_channel_kernel(const typename Cx<T>::type* __restrict__ K, int64_t ld, int64_t nk, int P, int p,
+                                    typename Cx<TO>::type* __restrict__ out) {
+  const int64_t r = blockIdx.y;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nk; c += (int64_t)gridDim.x * blockDim.x) {
+    const auto v = K[(r * P + p) * ld + c * P + p];
+    typename Cx<TO>::type o;
+    o.x = (TO)v.x;
+    o.y = (TO)v.y;
+    out[r * nk + c] = o;
+  }
+}
+
+// Factors of channel (p, q) from the dilation's eigenvectors Q (ascending
+// eigenvalues; s_j belongs to column 2 nk - 1 - j): S^{pq}[i][j] = s_j sqrt2 Q_top,
+// V^{pq H}[j][i] = conj(sqrt2 Q_bottom) for j < r, zero for r <= j < rmax.
+template <typename TO>
+__global__ void channel_factor_kernel(const double2* __restrict__ Q, int64_t nk, int P, int p, int slot, int64_t rmax,
+                                      int64_t r, const double* __restrict__ sig, typename Cx<TO>::type* __restrict__ S,
+                                      typename Cx<TO>::type* __restrict__ W) {
+  const int64_t j = blockIdx.y, ls = (int64_t)(P - 1) * rmax, m = 2 * nk;
+  const double sq2 = 1.4142135623730951;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
+    typename Cx<TO>::type a, b;
+    a.x = a.y = b.x = b.y = (TO)0;
+    if (j < r) {
+      const int64_t col = m - 1 - j;
+      const double2 u = Q[i + col * m], v = Q[nk + i + col * m];
+      a.x = (TO)(sig[j] * sq2 * u.x);
+      a.y = (TO)(sig[j] * sq2 * u.y);
+      b.x = (TO)(sq2 * v.x);
+      b.y = (TO)(-sq2 * v.y);
+    }
+    S[(i * P + p) * ls + slot * rmax + j] = a;
+    W[(((int64_t)p * (P - 1) + slot) * rmax + j) * nk + i] = b;
+  }
+}
+
 }  // namespace
 
 namespace tdg {
@@ -545,4 +629,118 @@ extern "C" int tdg_kernel_compress_randomized(tdg_ctx ctx, const void* K, int64_
     kept[c] = lam[order[c]];
   }
   return write_factors(ctx, (const double2*)KD, z, n, r, perm, kept, out);
+}
+
+extern "C" int tdg_kernel_compress_channels(tdg_ctx ctx, const void* K, int64_t ld, int32_t dtype,
+                                            const tdg_trunc* trunc, tdg_channels* out) {
+  if (!ctx) return TDG_E_INVAL;
+  if (!K || !trunc || !out) return fail(ctx, TDG_E_INVAL, "NULL argument");
+  if (dtype != TDG_C128 && dtype != TDG_C64) return fail(ctx, TDG_E_INVAL, "dtype %d", dtype);
+  if (out->dtype != TDG_C128 && out->dtype != TDG_C64)
+    return fail(ctx, TDG_E_UNSUPPORTED, "channel-wise factors are TDG_C128 or TDG_C64");
+  const int64_t nk = out->nk, rmax = out->rmax;
+  const int P = out->npair;
+  if (P < 2 || P > TDG_NB_MAX * TDG_NB_MAX) return fail(ctx, TDG_E_INVAL, "npair = %d", P);
+  if (nk < 2 || nk > 32767) return fail(ctx, TDG_E_INVAL, "nk = %lld outside [2, 32767]", (long long)nk);
+  if (rmax < 4 || rmax % 4 != 0 || rmax > nk) return fail(ctx, TDG_E_INVAL, "rmax must be a multiple of 4 in [4, nk]");
+  const int64_t n = nk * P;
+  if (ld < n) return fail(ctx, TDG_E_INVAL, "ld < nk * npair");
+  if (!out->diag || !out->s || !out->w) return fail(ctx, TDG_E_INVAL, "output pointer is NULL");
+  if (trunc->mode < TDG_TRUNC_REL_CUT || trunc->mode > TDG_TRUNC_R2)
+    return fail(ctx, TDG_E_INVAL, "truncation mode %d", trunc->mode);
+  if (!std::isfinite(trunc->value) || trunc->value < 0.0) return fail(ctx, TDG_E_INVAL, "truncation value");
+  TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+
+  const int64_t m = 2 * nk;
+  void *H = nullptr, *D = nullptr, *I = nullptr, *M = nullptr;
+  TDG_TRY(ws_reserve(ctx, WS_SOLVER_A, (size_t)m * m * sizeof(double2), &H));
+  TDG_TRY(ws_reserve(ctx, WS_SOLVER_D, (size_t)2 * m * sizeof(double), &D));
+  TDG_TRY(ws_reserve(ctx, WS_SOLVER_I, (size_t)nk * sizeof(double) + 256, &I));
+  TDG_TRY(ws_reserve(ctx, WS_MISC, (size_t)nk * sizeof(double2), &M));
+  rocblas_handle h = nullptr;
+  TDG_TRY(blas_handle(ctx, (void**)&h));
+  const int bx = (int)std::min<int64_t>((m + 255) / 256, 64);
+  const bool o64 = out->dtype == TDG_C128;
+  int* info = (int*)I;
+  double* dsig = (double*)((char*)I + 256);
+  std::vector<double> lam(m);
+  std::vector<double2> rows(nk);
+
+  for (int p = 0; p < P; ++p) {
+    // the diagonal channel is kept whole
+    auto* dst = (char*)out->diag + (size_t)p * nk * nk * (o64 ? 16 : 8);
+    if (dtype == TDG_C128) {
+      if (o64)
+        hipLaunchKernelGGL((diag_channel_kernel<double, double>), dim3(bx, (unsigned)nk), dim3(256), 0, ctx->stream,
+                           (const double2*)K, ld, nk, P, p, (double2*)dst);
+      else
+        hipLaunchKernelGGL((diag_channel_kernel<double, float>), dim3(bx, (unsigned)nk), dim3(256), 0, ctx->stream,
+                           (const double2*)K, ld, nk, P, p, (float2*)dst);
+    } else {
+      if (o64)
+        hipLaunchKernelGGL((diag_channel_kernel<float, double>), dim3(bx, (unsigned)nk), dim3(256), 0, ctx->stream,
+                           (const float2*)K, ld, nk, P, p, (double2*)dst);
+      else
+        hipLaunchKernelGGL((diag_channel_kernel<float, float>), dim3(bx, (unsigned)nk), dim3(256), 0, ctx->stream,
+                           (const float2*)K, ld, nk, P, p, (float2*)dst);
+    }
+    TDG_TRY(launch_check(ctx, "diagonal channel copy"));
+    if (out->ranks) out->ranks[p * P + p] = nk;
+    if (out->sigma) std::fill(out->sigma + ((size_t)p * P + p) * nk, out->sigma + ((size_t)p * P + p + 1) * nk, 0.0);
+
+    for (int q = 0; q < P; ++q) {
+      if (q == p) continue;
+      const int slot = q < p ? q : q - 1;
+      if (dtype == TDG_C128) {
+        hipLaunchKernelGGL(dilation_kernel<double>, dim3(bx, (unsigned)m), dim3(256), 0, ctx->stream,
+                           (const double2*)K, ld, nk, P, p, q, (double2*)H);
+        hipLaunchKernelGGL(channel_rowsum_kernel<double>, dim3((unsigned)nk), dim3(256), 0, ctx->stream,
+                           (const double2*)K, ld, nk, P, p, q, (double2*)M);
+      } else {
+        hipLaunchKernelGGL(dilation_kernel<float>, dim3(bx, (unsigned)m), dim3(256), 0, ctx->stream, (const float2*)K,
+                           ld, nk, P, p, q, (double2*)H);
+        hipLaunchKernelGGL(channel_rowsum_kernel<float>, dim3((unsigned)nk), dim3(256), 0, ctx->stream,
+                           (const float2*)K, ld, nk, P, p, q, (double2*)M);
+      }
+      TDG_TRY(launch_check(ctx, "channel dilation"));
+      double* dvals = (double*)D;
+      rocblas_status st = rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)m,
+                                           (rocblas_double_complex*)H, (rocblas_int)m, dvals, dvals + m, info);
+      if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocsolver_zheevd status %d", (int)st);
+      TDG_TRY(hip_check(ctx, hipStreamSynchronize(ctx->stream), "channel eigensolver sync"));
+      int hinfo = 0;
+      TDG_TRY(hip_check(ctx, hipMemcpy(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost), "info copy"));
+      if (hinfo != 0) return fail(ctx, TDG_E_SOLVER, "rocsolver_zheevd info = %d (channel %d,%d)", hinfo, p, q);
+      TDG_TRY(hip_check(ctx, hipMemcpy(lam.data(), dvals, m * sizeof(double), hipMemcpyDeviceToHost), "eigenvalues"));
+      TDG_TRY(hip_check(ctx, hipMemcpy(rows.data(), M, nk * sizeof(double2), hipMemcpyDeviceToHost), "row sums"));
+      // singular values, descending: the nk largest eigenvalues of the dilation
+      std::vector<double> sv(nk);
+      double fro2 = 0.0, sr = 0.0, si = 0.0;
+      for (int64_t j = 0; j < nk; ++j) {
+        sv[j] = std::fabs(lam[m - 1 - j]);
+        fro2 += sv[j] * sv[j];
+      }
+      for (int64_t i = 0; i < nk; ++i) {
+        sr += rows[i].x;
+        si += rows[i].y;
+      }
+      const double dev2 = fro2 - (sr * sr + si * si) / ((double)nk * (double)nk);
+      const int64_t r = choose_rank(sv, trunc->mode, trunc->value, dev2);
+      if (out->ranks) out->ranks[p * P + q] = r;
+      if (out->sigma) std::copy(sv.begin(), sv.end(), out->sigma + ((size_t)p * P + q) * nk);
+      if (r > rmax)
+        return fail(ctx, TDG_E_INVAL, "channel (%d,%d) rank %lld exceeds rmax %lld", p, q, (long long)r, (long long)rmax);
+      if (r > 0)
+        TDG_TRY(hip_check(ctx, hipMemcpy(dsig, sv.data(), r * sizeof(double), hipMemcpyHostToDevice), "sigma upload"));
+      const int fb = (int)std::min<int64_t>((nk + 255) / 256, 64);
+      if (o64)
+        hipLaunchKernelGGL(channel_factor_kernel<double>, dim3(fb, (unsigned)rmax), dim3(256), 0, ctx->stream,
+                           (const double2*)H, nk, P, p, slot, rmax, r, dsig, (double2*)out->s, (double2*)out->w);
+      else
+        hipLaunchKernelGGL(channel_factor_kernel<float>, dim3(fb, (unsigned)rmax), dim3(256), 0, ctx->stream,
+                           (const double2*)H, nk, P, p, slot, rmax, r, dsig, (float2*)out->s, (float2*)out->w);
+      TDG_TRY(launch_check(ctx, "channel factors"));
+    }
+  }
+  return hip_check(ctx, hipStreamSynchronize(ctx->stream), "channel compression sync");
 }

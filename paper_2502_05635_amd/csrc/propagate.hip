@@ -184,6 +184,8 @@ struct StageParams {
   int zsplit;         // low rank: number of projection column slices summed by the stage kernel
   int64_t zsplit_stride;  // elements between consecutive slices of z
   const void* kdiag;  // low rank: K_diag [N]; dense: NULL
+  const void* chS;    // channel-wise: off-diagonal channel factors S, row (k, p) = [(P-1) rmax]
+  int chLS;           // channel-wise: (P-1) rmax
   const void* xcur;   // drho gather of this stage [B][xstride]
   void* xnext;        // drho gather of the next stage
   int64_t xstride;
@@ -244,10 +246,11 @@ __device__ inline double2 proj_e(const tdg_field& F, double2 a, double2 b) {
 // parameter so the two paths are distinct kernels in traces.  NT threads per
 // block (a k point's rows are split over the block's columns), U-fold unrolled
 // row streams, WPE = minimum waves per SIMD requested from the compiler.
-template <typename T, bool LOWRANK, int NT, int U, int WPE>
+template <typename T, int MODE, int NT, int U, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 stage_kernel(StageParams sp) {
   using C = typename Cx<T>::type;
+  constexpr bool LOWRANK = MODE == 1, CHANNEL = MODE == 2;
   constexpr int WAVES = NT / 64;
   const int k = blockIdx.x, b = blockIdx.y;
   const bool dyn = b < sp.n_dyn;
@@ -258,7 +261,7 @@ stage_kernel(StageParams sp) {
 
   __shared__ double2 s_rho[NB2_MAX];
   __shared__ double2 s_h[NB2_MAX];
-  __shared__ double s_y[2 * NB2_MAX];
+  __shared__ double s_y[2 * NB2_MAX + 2 * ROWS];
   __shared__ double s_red[WAVES * 2 * ROWS];
   __shared__ double s_obs[5][NB2_MAX];
 
@@ -295,7 +298,19 @@ stage_kernel(StageParams sp) {
   }
 
   // ---- contraction: y_p = sum_j A[k P + p][j] vec[j] ----------------------
-  if (dyn) {
+  if (CHANNEL && dyn) {
+    // pair p of k: its diagonal channel's row k against x_p (channel-major
+    // drho), plus its off-diagonal channels' S rows against z_p
+    const C* S = reinterpret_cast<const C*>(sp.chS);
+    for (int p = 0; p < P; ++p) {
+      T ar[ROWS], ai[ROWS];
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) ar[r] = ai[r] = (T)0;
+      rows_dot<NT, U>(A + ((int64_t)p * sp.nk + k) * sp.lda, sp.lda, 1, sp.ncols, xcur + (size_t)p * sp.nk, ar, ai);
+      rows_dot<NT, U>(S + ((int64_t)k * P + p) * sp.chLS, sp.chLS, 1, sp.chLS, vec + (size_t)p * sp.chLS, ar, ai);
+      block_reduce<T, NT>(ar, ai, s_red, s_y + 2 * p);
+    }
+  } else if (dyn) {
     for (int r0 = 0; r0 < P; r0 += ROWS) {
       const int nvalid = min(ROWS, P - r0);
       T ar[ROWS], ai[ROWS];
@@ -419,7 +434,8 @@ stage_kernel(StageParams sp) {
       C xv;
       xv.x = (T)dre;
       xv.y = (T)next.y;
-      reinterpret_cast<C*>(sp.xnext)[(size_t)b * sp.xstride + (size_t)k * P + p] = xv;
+      reinterpret_cast<C*>(sp.xnext)[(size_t)b * sp.xstride + (CHANNEL ? (size_t)p * sp.nk + k : (size_t)k * P + p)] =
+          xv;
     }
   }
 }
@@ -427,12 +443,21 @@ stage_kernel(StageParams sp) {
 // Low-rank projection z_j = sum_i W[j][i] x_i (W = V^H): block (g, q, b) takes
 // rows ROWS*g .. ROWS*g + ROWS - 1 over the q-th of zsplit column slices and
 // writes its partial to zpart[q][b][j]; the stage kernel sums the slices.
+// Channel-wise (ch_ls > 0): W holds the V^H rows of every off-diagonal channel,
+// P blocks of ch_ls rows (P - 1 channels of ch_rmax rows each).
 template <typename T>
 __global__ void __launch_bounds__(PROJ_THREADS) project_kernel(const void* __restrict__ W, int64_t n, int rank,
                                                      const void* __restrict__ x, int64_t xstride, void* zpart,
-                                                     int64_t zstride, int64_t slice, int64_t split_stride) {
+                                                     int64_t zstride, int64_t slice, int64_t split_stride,
+                                                     int ch_ls, int ch_rmax) {
   using C = typename Cx<T>::type;
   const int q = blockIdx.y, b = blockIdx.z;
+  if (ch_ls > 0) {
+    // channel-wise: rows of the (p, q) block of V^H read x_q (channel-major,
+    // n = nk columns per channel); a group of ROWS rows never spans two blocks
+    const int pp = (int)(blockIdx.x * ROWS) / ch_ls, slot = ((int)(blockIdx.x * ROWS) % ch_ls) / ch_rmax;
+    x = reinterpret_cast<const C*>(x) + (size_t)(slot < pp ? slot : slot + 1) * n;
+  }
   __shared__ double s_red[PROJ_THREADS / 64 * 2 * ROWS];
   __shared__ double s_out[2 * ROWS];
   const int r0 = blockIdx.x * ROWS;
@@ -455,12 +480,12 @@ __global__ void __launch_bounds__(PROJ_THREADS) project_kernel(const void* __res
 
 // Working state from the caller's rho: rho_n <- rho_eq or rho[perm[b]],
 // rho_s <- rho_n, x <- (rho_n - rho_eq)[pairs]; b is the sorted position.
-// x_inst_minor selects the batched path's drho layout [N][xstride] (instance
-// fastest) instead of [B][xstride].
+// x_layout: 0 = [B][xstride] with pair index k P + p; 1 = the batched path's
+// [N][xstride] (instance fastest); 2 = [B][xstride] channel-major, p nk + k.
 template <typename T>
 __global__ void init_kernel(const double2* __restrict__ rho_in, const int* __restrict__ perm, double2* rho_n,
                             double2* rho_s, void* x, int64_t xstride, int nk, int nb, int nv, int npair, int block,
-                            int init_eq, int x_inst_minor) {
+                            int init_eq, int x_layout) {
   using C = typename Cx<T>::type;
   const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x, nb2 = nb * nb;
   if (t >= nb2) return;
@@ -479,8 +504,8 @@ __global__ void init_kernel(const double2* __restrict__ rho_in, const int* __res
     C xv;
     xv.x = (T)(r.x - occ);
     xv.y = (T)r.y;
-    const size_t i = (size_t)k * npair + p;
-    reinterpret_cast<C*>(x)[x_inst_minor ? i * xstride + b : (size_t)b * xstride + i] = xv;
+    const size_t i = x_layout == 2 ? (size_t)p * nk + k : (size_t)k * npair + p;
+    reinterpret_cast<C*>(x)[x_layout == 1 ? i * xstride + b : (size_t)b * xstride + i] = xv;
   }
 }
 
@@ -757,9 +782,9 @@ static int upload(tdg_ctx ctx, WsSlot slot, const void* src, size_t bytes, void*
 // ---- stage-kernel variants -------------------------------------------------
 using StageLaunch = void (*)(dim3, size_t, hipStream_t, const StageParams&);
 
-template <typename T, bool LR, int NT, int U, int WPE>
+template <typename T, int MODE, int NT, int U, int WPE>
 static void launch_stage(dim3 grid, size_t lds, hipStream_t stream, const StageParams& sp) {
-  hipLaunchKernelGGL((stage_kernel<T, LR, NT, U, WPE>), grid, dim3(NT), lds, stream, sp);
+  hipLaunchKernelGGL((stage_kernel<T, MODE, NT, U, WPE>), grid, dim3(NT), lds, stream, sp);
 }
 
 struct Variant {
@@ -768,26 +793,35 @@ struct Variant {
 };
 
 static const Variant kDenseF32[] = {
-    {"dense_f32_nt256_u2_w6", launch_stage<float, false, 256, 2, 6>},
-    {"dense_f32_nt256_u4_w4", launch_stage<float, false, 256, 4, 4>},
-    {"dense_f32_nt256_u1_w8", launch_stage<float, false, 256, 1, 8>},
-    {"dense_f32_nt128_u4_w4", launch_stage<float, false, 128, 4, 4>},
-    {"dense_f32_nt512_u2_w4", launch_stage<float, false, 512, 2, 4>},
+    {"dense_f32_nt256_u2_w6", launch_stage<float, 0, 256, 2, 6>},
+    {"dense_f32_nt256_u4_w4", launch_stage<float, 0, 256, 4, 4>},
+    {"dense_f32_nt256_u1_w8", launch_stage<float, 0, 256, 1, 8>},
+    {"dense_f32_nt128_u4_w4", launch_stage<float, 0, 128, 4, 4>},
+    {"dense_f32_nt512_u2_w4", launch_stage<float, 0, 512, 2, 4>},
 };
 static const Variant kDenseF64[] = {
-    {"dense_f64_nt256_u2_w4", launch_stage<double, false, 256, 2, 4>},
-    {"dense_f64_nt256_u1_w6", launch_stage<double, false, 256, 1, 6>},
-    {"dense_f64_nt128_u2_w4", launch_stage<double, false, 128, 2, 4>},
+    {"dense_f64_nt256_u2_w4", launch_stage<double, 0, 256, 2, 4>},
+    {"dense_f64_nt256_u1_w6", launch_stage<double, 0, 256, 1, 6>},
+    {"dense_f64_nt128_u2_w4", launch_stage<double, 0, 128, 2, 4>},
 };
 static const Variant kLowF32[] = {
-    {"lowrank_f32_nt64", launch_stage<float, true, 64, 1, 2>},
-    {"lowrank_f32_nt128", launch_stage<float, true, 128, 1, 2>},
-    {"lowrank_f32_nt256", launch_stage<float, true, 256, 1, 2>},
+    {"lowrank_f32_nt64", launch_stage<float, 1, 64, 1, 2>},
+    {"lowrank_f32_nt128", launch_stage<float, 1, 128, 1, 2>},
+    {"lowrank_f32_nt256", launch_stage<float, 1, 256, 1, 2>},
+};
+static const Variant kChanF32[] = {
+    {"channel_f32_nt256_u2_w6", launch_stage<float, 2, 256, 2, 6>},
+    {"channel_f32_nt256_u4_w4", launch_stage<float, 2, 256, 4, 4>},
+    {"channel_f32_nt128_u4_w4", launch_stage<float, 2, 128, 4, 4>},
+};
+static const Variant kChanF64[] = {
+    {"channel_f64_nt256_u2_w4", launch_stage<double, 2, 256, 2, 4>},
+    {"channel_f64_nt128_u2_w4", launch_stage<double, 2, 128, 2, 4>},
 };
 static const Variant kLowF64[] = {
-    {"lowrank_f64_nt64", launch_stage<double, true, 64, 1, 2>},
-    {"lowrank_f64_nt128", launch_stage<double, true, 128, 1, 2>},
-    {"lowrank_f64_nt256", launch_stage<double, true, 256, 1, 2>},
+    {"lowrank_f64_nt64", launch_stage<double, 1, 64, 1, 2>},
+    {"lowrank_f64_nt128", launch_stage<double, 1, 128, 1, 2>},
+    {"lowrank_f64_nt256", launch_stage<double, 1, 256, 1, 2>},
 };
 
 template <size_t N>
@@ -812,10 +846,23 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   if (n > ((int64_t)1 << 30)) return fail(ctx, TDG_E_UNSUPPORTED, "N = %lld too large", (long long)n);
   const size_t elt = op->dtype == TDG_C128 ? 16 : 8;  // x and z are complex64 for C64 and BF16X2
   const bool lowrank = op->kind == TDG_OP_LOWRANK;
+  const bool channel = op->kind == TDG_OP_CHANNEL;
   const void* A = nullptr;
   int64_t lda = 0;
   int ncols = 0;
-  if (op->kind == TDG_OP_DENSE) {
+  int ch_ls = 0;
+  if (channel) {
+    // diagonal channels [P][nk][nk] in K, off-diagonal factors in us / w, rank = rmax
+    if (!op->K || !op->us || !op->w) return fail(ctx, TDG_E_INVAL, "channel-wise operator with NULL array");
+    if (bf16) return fail(ctx, TDG_E_UNSUPPORTED, "channel-wise operators are TDG_C128 or TDG_C64");
+    if (op->rank < 4 || op->rank % 4 != 0 || op->rank > nk)
+      return fail(ctx, TDG_E_INVAL, "channel rank capacity %lld must be a multiple of 4 in [4, nk]", (long long)op->rank);
+    if (npair < 2) return fail(ctx, TDG_E_INVAL, "channel-wise operators need at least two pairs per k");
+    A = op->K;
+    lda = nk;
+    ncols = nk;
+    ch_ls = (int)((npair - 1) * op->rank);
+  } else if (op->kind == TDG_OP_DENSE) {
     if (!op->K) return fail(ctx, TDG_E_INVAL, "dense operator without K");
     if (op->ld < n) return fail(ctx, TDG_E_INVAL, "K ld = %lld < N", (long long)op->ld);
     A = op->K;
@@ -830,7 +877,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   } else {
     return fail(ctx, TDG_E_INVAL, "operator kind %d", op->kind);
   }
-  if (((uintptr_t)A | (uintptr_t)op->kdiag | (uintptr_t)op->w) & (elt == 16 ? 15 : 7))
+  if (((uintptr_t)A | (uintptr_t)op->kdiag | (uintptr_t)op->w | (channel ? (uintptr_t)op->us : 0)) &
+      (elt == 16 ? 15 : 7))
     return fail(ctx, TDG_E_INVAL, "operator arrays must be aligned to their complex element size");
   if (bf16 && ((((uintptr_t)A | (uintptr_t)op->w) & 15) || (op->kind == TDG_OP_DENSE && op->ld % 4 != 0) ||
                (lowrank && n % 4 != 0)))
@@ -859,12 +907,12 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const int nb2 = model->nb * model->nb;
   const size_t state_bytes = (size_t)batch * nk * nb2 * sizeof(double2);
   // matrix-core path: complex64 operator and enough instances
-  const bool batched = bf16 || (op->dtype == TDG_C64 && batch >= ctx->batched_min);
+  const bool batched = !channel && (bf16 || (op->dtype == TDG_C64 && batch >= ctx->batched_min));
   if (batched && (nb2 > 256 || n > 2147483647 / 2))
     return fail(ctx, TDG_E_UNSUPPORTED, "batched path: nb^2 <= 256 and N < 2^30 required");
   // batched rows hold an even number of instances (two per 16-byte load)
   const int64_t xstride = batched ? (((int64_t)batch + 1) & ~int64_t(1)) : ((n + 1) & ~int64_t(1));
-  const int64_t zstride = (op->rank + 1) & ~int64_t(1);
+  const int64_t zstride = channel ? (int64_t)npair * ch_ls : (op->rank + 1) & ~int64_t(1);
   void *rho_n, *rho_s, *acc, *x0, *x1, *z = nullptr, *part, *dperm, *dfields;
   TDG_TRY(ws_reserve(ctx, WS_RHO_N, state_bytes, &rho_n));
   TDG_TRY(ws_reserve(ctx, WS_RHO_S, state_bytes, &rho_s));
@@ -877,7 +925,10 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   // kernel sums the slices it reads
   int zsplit = 1;
   int64_t zslice = n;
-  if (lowrank && !batched) {
+  if (channel) {
+    zslice = nk;
+    TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)batch * zstride * elt, &z));
+  } else if (lowrank && !batched) {
     const int64_t groups = (op->rank + ROWS - 1) / ROWS;
     zsplit = (int)std::min<int64_t>(ZSPLIT_MAX, std::max<int64_t>(1, (256 + groups - 1) / groups));
     zslice = ((n + zsplit - 1) / zsplit + 1) & ~int64_t(1);
@@ -895,11 +946,11 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     if (op->dtype == TDG_C128)
       hipLaunchKernelGGL(init_kernel<double>, dim3(nk, batch), dim3(init_threads), 0, ctx->stream,
                          (const double2*)rho, (const int*)dperm, (double2*)rho_n, (double2*)rho_s, x0, xstride, nk,
-                         model->nb, model->nv, npair, op->block, init_eq, (int)batched);
+                         model->nb, model->nv, npair, op->block, init_eq, batched ? 1 : (channel ? 2 : 0));
     else
       hipLaunchKernelGGL(init_kernel<float>, dim3(nk, batch), dim3(init_threads), 0, ctx->stream,
                          (const double2*)rho, (const int*)dperm, (double2*)rho_n, (double2*)rho_s, x0, xstride, nk,
-                         model->nb, model->nv, npair, op->block, init_eq, (int)batched);
+                         model->nb, model->nv, npair, op->block, init_eq, batched ? 1 : (channel ? 2 : 0));
     return launch_check(ctx, "init launch");
   };
   TDG_TRY(init());
@@ -909,6 +960,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   sp.lda = lda;
   sp.ncols = ncols;
   sp.kdiag = lowrank ? op->kdiag : nullptr;
+  sp.chS = channel ? op->us : nullptr;
+  sp.chLS = ch_ls;
   sp.xstride = xstride;
   sp.rho_n = (double2*)rho_n;
   sp.rho_s = (double2*)rho_s;
@@ -928,17 +981,21 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const int64_t split_stride = (int64_t)batch * zstride;
   sp.zsplit = zsplit;
   sp.zsplit_stride = split_stride;
-  const unsigned groups = (unsigned)((op->rank + ROWS - 1) / ROWS);
+  // projection rows: the rank (low rank) or every off-diagonal channel's rows (channel-wise)
+  const int prows = channel ? npair * ch_ls : (int)op->rank;
+  const int64_t pcols = channel ? nk : n;
+  const unsigned groups = (unsigned)((prows + ROWS - 1) / ROWS);
 
   auto project = [&](const void* xin, int active) {
     const dim3 g(groups, zsplit, active);
     if (op->dtype == TDG_C128)
-      hipLaunchKernelGGL(project_kernel<double>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, n, (int)op->rank, xin, xstride,
-                         z, zstride, zslice, split_stride);
+      hipLaunchKernelGGL(project_kernel<double>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
+                         xstride, z, zstride, zslice, split_stride, ch_ls, (int)(channel ? op->rank : 0));
     else
-      hipLaunchKernelGGL(project_kernel<float>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, n, (int)op->rank, xin, xstride,
-                         z, zstride, zslice, split_stride);
+      hipLaunchKernelGGL(project_kernel<float>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
+                         xstride, z, zstride, zslice, split_stride, ch_ls, (int)(channel ? op->rank : 0));
   };
+  const bool projects = lowrank || channel;
   // instances with len > step integrate; those with len == step only record
   auto count_gt = [&](int64_t step) {
     int c = 0;
@@ -1145,9 +1202,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const Variant* vt = nullptr;
   int nvar = 0;
   if (op->dtype == TDG_C128)
-    lowrank ? table(kLowF64, vt, nvar) : table(kDenseF64, vt, nvar);
+    channel ? table(kChanF64, vt, nvar) : (lowrank ? table(kLowF64, vt, nvar) : table(kDenseF64, vt, nvar));
   else
-    lowrank ? table(kLowF32, vt, nvar) : table(kDenseF32, vt, nvar);
+    channel ? table(kChanF32, vt, nvar) : (lowrank ? table(kLowF32, vt, nvar) : table(kDenseF32, vt, nvar));
   int var = 0;
   if (ctx->forced_variant >= 0) {
     if (ctx->forced_variant >= nvar)
@@ -1175,9 +1232,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       sp.n_dyn = dyn0;
       sp.xcur = x0;
       sp.xnext = x1;
-      sp.vec = lowrank ? z : x0;
-      sp.vstride = lowrank ? zstride : xstride;
-      if (lowrank) project(x0, dyn0);
+      sp.vec = projects ? z : x0;
+      sp.vstride = projects ? zstride : xstride;
+      if (projects) project(x0, dyn0);
       const dim3 g(nk, dyn0);
       float best = 1e30f;
       for (int v = 0; v < nvar; ++v) {
@@ -1214,13 +1271,13 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     for (int s = 0; s < 4; ++s) {
       const int active = s == 0 ? n_obs : n_dyn;
       if (active == 0) break;
-      if (lowrank && n_dyn > 0) {
+      if (projects && n_dyn > 0) {
         prof_begin(ctx, TDG_KCLASS_PROJECT);
         project(xc, n_dyn);
         prof_end(ctx, TDG_KCLASS_PROJECT);
       }
-      sp.vec = lowrank ? z : xc;
-      sp.vstride = lowrank ? zstride : xstride;
+      sp.vec = projects ? z : xc;
+      sp.vstride = projects ? zstride : xstride;
       sp.xcur = xc;
       sp.xnext = xn;
       sp.step = (int)step;

@@ -46,7 +46,7 @@ def test_ctypes_layouts_match_c(tmp_path, tdg):
     from paper_2502_05635_amd import _abi as abi
     structs = {"tdg_model": abi.Model, "tdg_coulomb": abi.Coulomb, "tdg_trunc": abi.Trunc,
                "tdg_lowrank": abi.LowRank, "tdg_field": abi.Field, "tdg_operator": abi.Operator,
-               "tdg_obs": abi.Obs, "tdg_obs_grad": abi.ObsGrad, "tdg_grads": abi.Grads}
+               "tdg_obs": abi.Obs, "tdg_obs_grad": abi.ObsGrad, "tdg_grads": abi.Grads, "tdg_channels": abi.Channels}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tdagw.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
@@ -79,4 +79,5 @@ def test_host_validation_without_device(tdg):
     assert L.tdg_kernel_compress(None, None, 0, 0, None, None) == abi.TDG_E_INVAL
     assert L.tdg_kernel_compress_randomized(None, None, 0, 0, None, None, 0, 0, None) == abi.TDG_E_INVAL
     assert L.tdg_propagate_adjoint(None, None, None, None, 1, 1.0, None, 50, None, None) == abi.TDG_E_INVAL
+    assert L.tdg_kernel_compress_channels(None, None, 0, 0, None, None) == abi.TDG_E_INVAL
     assert L.tdg_version() >= 100

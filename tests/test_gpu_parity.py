@@ -572,3 +572,85 @@ def test_large_grid_bf16x2_vs_fp64_lowrank(P):
         assert e_abs <= 1e-4
     finally:
         c.close()
+
+
+# --- channel-wise compression (Eq. svd-channel-wise) ------------------------
+
+
+def _channel_apply(fac, nk, P, x):
+    """Action of device channel factors, assembled in numpy."""
+    d = fac.diag.cpu().numpy().astype(np.complex128)
+    s = fac.s.cpu().numpy().astype(np.complex128)
+    w = fac.w.cpu().numpy().astype(np.complex128)
+    R = fac.rmax
+    xs = x.reshape(nk, P)
+    y = np.zeros_like(xs)
+    for p in range(P):
+        y[:, p] = d[p] @ xs[:, p]
+        for slot in range(P - 1):
+            q = slot if slot < p else slot + 1
+            y[:, p] += s[p::P, slot * R:(slot + 1) * R] @ (w[p, slot] @ xs[:, q])
+    return y.reshape(-1)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_channel_compress_matches_oracle(P, ctx, tb4_6, k_tb4_6, dtype):
+    nk, NP = tb4_6.nk, 4
+    _log(f"channel-wise compress tb4 6x6 eh {dtype}, 20 % per off-diagonal channel")
+    kg = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", dtype)
+    fac = ctx.kernel_compress_channels(kg, nk, NP, "fraction", 0.2, rmax=12)
+    k_in = kg.cpu().numpy().astype(np.complex128)
+    ref = O.compress_channelwise(k_in, nk, NP, "fraction", 0.2)
+    tol = 1e-12 if dtype == "c128" else 1e-6
+    for (p, q), r in ref["ranks"].items():
+        assert fac.ranks[p, q] == r, (p, q)
+        if p != q:
+            sv = ref["off"][(p, q)][2]
+            np.testing.assert_allclose(fac.sigma[p, q], sv, rtol=0, atol=tol * sv[0])
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(nk * NP) + 1j * rng.standard_normal(nk * NP)
+    got = _channel_apply(fac, nk, NP, x)
+    want = O.ChannelOp(ref, nk, NP).apply(x)
+    e = float(np.abs(got - want).max() / np.abs(want).max())
+    _log(f"  operator action vs oracle: {e:.2e}")
+    assert e <= 10 * tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_channel_propagation_parity(P, ctx, tb4_6, k_tb4_6, dtype, tol):
+    nk, NP = tb4_6.nk, 4
+    dm = _dev(P, tb4_6)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", dtype)
+    fac = ctx.kernel_compress_channels(kg, nk, NP, "fraction", 0.2, rmax=12)
+    f = strong(300)
+    _log(f"channel-wise propagation tb4 6x6 {dtype}, 300 steps")
+    res = ctx.propagate(fac, dm, "eh", f, DT)
+    assert ctx.last_variant().startswith("channel_")
+    ref = O.propagate(tb4_6, O.ChannelOp(O.compress_channelwise(k_tb4_6, nk, NP, "fraction", 0.2), nk, NP), "eh",
+                      f, DT)
+    for key in ("P", "J", "occ"):
+        e = err_rel(res[key][0].cpu().numpy(), ref[key])
+        _log(f"  err_{key} = {e:.2e}")
+        assert e <= tol, key
+
+
+def test_channel_full_rank_equals_dense(P, ctx, tb4_6):
+    nk = tb4_6.nk
+    dm = _dev(P, tb4_6)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c128")
+    fac = ctx.kernel_compress_channels(kg, nk, 4, "fraction", 1.0, rmax=nk)
+    f = strong(200)
+    a = ctx.propagate(fac, dm, "eh", f, DT)
+    b = ctx.propagate(kg, dm, "eh", f, DT)
+    e = err_rel(a["P"][0].cpu().numpy(), b["P"][0].cpu().numpy())
+    _log(f"  channel-wise at full rank vs dense: {e:.2e}")
+    assert e <= 1e-11
+
+
+def test_channel_invalid_arguments(P, ctx, tb4_6):
+    nk = tb4_6.nk
+    kg = ctx.kernel_build(_dev(P, tb4_6), R0_STABLE, "eh", "c128")
+    with pytest.raises(P.TdgError):                       # rank above capacity
+        ctx.kernel_compress_channels(kg, nk, 4, "fraction", 0.5, rmax=8)
+    with pytest.raises(P.TdgError):                       # capacity not a multiple of 4
+        P.Context.kernel_compress_channels(ctx, kg, nk, 4, "rank", 2, rmax=6)

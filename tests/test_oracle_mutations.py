@@ -79,6 +79,19 @@ def _cotangent_wrong_band(model, ex, ey, gp, gj, gocc):
     return g / model.nk
 
 
+def _channel_wrong_source(self, x):
+    P = self.npair
+    xs = x.reshape(self.nk, P)
+    y = np.zeros_like(xs)
+    for p in range(P):
+        y[:, p] = self.f["diag"][p] @ xs[:, p]
+        for q in range(P):
+            if q != p:
+                s, vh, _ = self.f["off"][(p, q)]
+                y[:, p] += s @ (vh @ xs[:, p])
+    return y.reshape(-1)
+
+
 ADJOINT._real_pull_commutator = ADJOINT.pull_commutator
 ADJOINT._real_field_param_derivs = ADJOINT.field_param_derivs
 
@@ -92,6 +105,8 @@ CASES = {
                             lambda q, r0: 4 * np.pi / (np.asarray(q) * (1 + r0 * np.asarray(q))), "row_sum"),
     "k difference not folded": (KERNEL, "fold_q", lambda dk, a: dk, "circulant"),
     "trace operand transposed": (OBSERVABLES, "_trace_prod", _transposed_trace, "two_level"),
+    "channel-wise: off-diagonal channel reads its own pair": (PROPAGATE.ChannelOp, "apply", _channel_wrong_source,
+                                                            "channel_full_rank"),
     "adjoint: commutator pullback order swapped": (ADJOINT, "pull_commutator", _pull_commutator_unconjugated,
                                                    "adjoint_factors"),
     "adjoint: state cotangent sign flipped": (ADJOINT, "pull_commutator", _pull_commutator_ybar_sign,
@@ -115,6 +130,8 @@ def _run_pin(name, small):
         pins.test_kernel_row_sum_is_brillouin_zone_integral()
     elif name == "circulant":
         pins.test_flat_band_kernel_is_circulant()
+    elif name == "channel_full_rank":
+        pins.test_channelwise_full_rank_equals_dense(t4, O.build_kernel(t4, R0_STABLE, "eh"))
     elif name in ("adjoint_fields", "adjoint_factors"):
         import test_oracle_adjoint as adj
         lr = O.LowRankOp.from_factors(O.compress(O.build_kernel(t4, R0_STABLE, "eh"), "rank", 12))

@@ -452,3 +452,56 @@ def test_randomized_recovers_a_low_rank_plus_noise_matrix():
     _, koff_k = O.split_diag(k)
     resid = np.linalg.norm(koff_k - rnd["US"] @ rnd["Vh"], 2)
     assert resid <= 1.01 * exact["s"][r]
+
+
+# --- channel-wise SVD (Eq. svd-channel-wise) ---------------------------------
+
+def test_channel_blocks_follow_the_element_definition(tb4_4, k_tb4_eh):
+    """Element (k, k') of channel (p, q) is the kernel element of pair p at k
+    and pair q at k', from the element-by-element definition."""
+    P = 4
+    blocks = O.channel_blocks(k_tb4_eh, tb4_4.nk, P)
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        p, q = rng.integers(0, P, 2)
+        kk, kq = rng.integers(0, tb4_4.nk, 2)
+        ref = O.kernel_element(tb4_4, R0_STABLE, "eh", kk * P + p, kq * P + q)
+        assert abs(blocks[(p, q)][kk, kq] - ref) <= 1e-14 * abs(ref) + 1e-18
+
+
+def test_channel_pairing_and_eckart_young(tb4_4, k_tb4_eh):
+    """K Hermitian => K^{qp} = (K^{pq})^H, so the two channels share singular
+    values; each truncated channel's residual is its discarded tail."""
+    P, nk = 4, tb4_4.nk
+    f = O.compress_channelwise(k_tb4_eh, nk, P, "rank", 5)
+    blocks = O.channel_blocks(k_tb4_eh, nk, P)
+    for (p, q), (s_, vh, sv) in f["off"].items():
+        np.testing.assert_allclose(sv, f["off"][(q, p)][2], rtol=1e-12, atol=1e-14 * sv[0])
+        r = f["ranks"][(p, q)]
+        resid = blocks[(p, q)] - s_ @ vh
+        np.testing.assert_allclose(np.linalg.norm(resid) ** 2, np.sum(sv[r:] ** 2), rtol=1e-9)
+        np.testing.assert_allclose(np.linalg.norm(resid, 2), sv[r], rtol=1e-9)
+    for p in range(P):
+        np.testing.assert_array_equal(f["diag"][p], blocks[(p, p)])
+
+
+def test_channelwise_full_rank_equals_dense(tb4_4, k_tb4_eh):
+    P, nk = 4, tb4_4.nk
+    f = O.compress_channelwise(k_tb4_eh, nk, P, "fraction", 1.0)
+    op = O.ChannelOp(f, nk, P)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(nk * P) + 1j * rng.standard_normal(nk * P)
+    ref = k_tb4_eh @ x
+    assert np.abs(op.apply(x) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_channelwise_truncation_keeps_hermiticity(tb4_4, k_tb4_eh):
+    """Equal ranks on (p, q) and (q, p) give a Hermitian operator: <y, A x> = <A y, x>."""
+    P, nk = 4, tb4_4.nk
+    op = O.ChannelOp(O.compress_channelwise(k_tb4_eh, nk, P, "rank", 4), nk, P)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(nk * P) + 1j * rng.standard_normal(nk * P)
+    y = rng.standard_normal(nk * P) + 1j * rng.standard_normal(nk * P)
+    a = np.vdot(y, op.apply(x))
+    b = np.vdot(op.apply(y), x)
+    assert abs(a - b) <= 1e-13 * abs(a)
