@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 
 GOLDEN_JSON = os.path.join(ROOT, "tests", "golden", "tb4_36x36_fixed_error.json")
 GOLDEN_NPZ = os.path.join(ROOT, "tests", "golden", "tb4_36x36_oracle_series.npz")
+CHAN_JSON = os.path.join(ROOT, "tests", "golden", "tb4_36x36_channels.json")
+CHAN_NPZ = os.path.join(ROOT, "tests", "golden", "tb4_36x36_channel_series.npz")
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "traffic_stage_kernel_tb4_36x36.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_05635_amd", "csrc", "propagate.hip")
 HBM_PEAK_GBS = 8000.0
@@ -187,6 +189,20 @@ def main():
         _, _, prof = timed(op, args.steps, args.warmup, True)
         out[name] = {"secs": secs, "res": res, "prof": prof, "variant": variant}
 
+    # channel-wise compression (Eq. svd-channel-wise) at its own fixed-error fraction
+    chan_golden = json.load(open(CHAN_JSON)) if os.path.exists(CHAN_JSON) else None
+    chan_frac = chan_golden["chosen"]["fraction"] if chan_golden else 0.05
+    npair = (nb - model.nv) * model.nv
+    rmax = min(nk // 4 * 4, (int(round(chan_frac * nk)) + 8 + 3) // 4 * 4)
+    t0 = time.perf_counter()
+    chan = ctx.kernel_compress_channels(K, nk, npair, "fraction", chan_frac, rmax=rmax)
+    torch.cuda.synchronize()
+    chan_compress_s = time.perf_counter() - t0
+    res, secs, _ = timed(chan, args.steps, args.warmup, False)
+    variant = ctx.last_variant()
+    _, _, prof = timed(chan, args.steps, args.warmup, True)
+    out["channel"] = {"secs": secs, "res": res, "prof": prof, "variant": variant}
+
     # errors against the stored FP64 oracle series (same operator, same steps):
     # over the first half of the run (t <= t0, before the post-pulse chaotic
     # divergence; the parity window) and over the whole run
@@ -208,6 +224,28 @@ def main():
         errs["fixed_error_criterion"] = golden["criterion"]
         errs["bright_exciton_shift_ev"] = golden["chosen"]["shift_ev"]
 
+    chan_errs = {}
+    if os.path.exists(CHAN_NPZ) and chan_golden:
+        g = np.load(CHAN_NPZ)
+        m_ = min(args.steps, int(cfg.fields.nsteps[0])) + 1
+        half = min(m_, int(cfg.fields.nsteps[0]) // 2 + 1)
+        for k in ("P", "J"):
+            got = out["channel"]["res"][k][0, :m_].cpu().numpy()
+            chan_errs[f"{k}_first_half"] = err_rel(got[:half], g[k][:half])
+            chan_errs[f"{k}_full"] = err_rel(got, g[k][:m_])
+    cp = out["channel"]["prof"]
+    channelwise = {
+        "value": args.steps / out["channel"]["secs"], "ms_per_step": 1e3 * out["channel"]["secs"] / args.steps,
+        "variant": out["channel"]["variant"], "kept_fraction_per_offdiag_channel": chan_frac,
+        "ranks_offdiag": sorted({int(x) for i, row in enumerate(chan.ranks) for j, x in enumerate(row) if i != j}),
+        "stage_kernel_us": cp["stage"][0] / cp["stage"][1] * 1e3,
+        "project_kernel_us": cp["project"][0] / cp["project"][1] * 1e3,
+        "compress_seconds": chan_compress_s,
+        "errors_vs_fp64_oracle": chan_errs or None,
+        "bright_exciton_shift_ev": next((row["shift_ev"] for row in chan_golden["table"]
+                                         if row["fraction"] == chan_frac), None) if chan_golden else None,
+    }
+
     # dominant kernel of the low-rank path and the dense stage kernel
     lp = out["lowrank"]["prof"]
     dom = "stage" if lp["stage"][0] >= lp["project"][0] else "project"
@@ -223,13 +261,14 @@ def main():
         traffic = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     value = args.steps / out["lowrank"]["secs"]
     dense_value = args.steps / out["dense"]["secs"]
+    channelwise["speedup_vs_dense"] = channelwise["value"] / dense_value
 
     rank_cut = int(np.count_nonzero(fac.sigma > 1e-3 * fac.sigma[0]))
     sweep = None
     if not args.no_sweep:
         for v in out.values():
             v.pop("res", None)
-        del K, fac, res
+        del K, fac, res, chan
         torch.cuda.empty_cache()
         sweep = batched_sweep(P, abi, ctx, frac)
     large = large_grid(P, abi, args.large_grid_steps) if args.large_grid else None
@@ -263,6 +302,7 @@ def main():
                   "stage_kernel_GBps": dense_bytes / dense_avg_s / 1e9,
                   "stage_kernel_hbm_frac": dense_bytes / dense_avg_s / 1e9 / HBM_PEAK_GBS},
         "speedup_lowrank_vs_dense": value / dense_value,
+        "channelwise": channelwise,
         "errors_vs_fp64_oracle": errs or None,
         "compress_seconds": compress_s,
         "roofline": {

@@ -360,6 +360,12 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects 0 / 2. */
 #define TDG_OPT_GEMM_TILE 3
 #define TDG_OPT_GEMM_VARIANT 4
+/* Batched path: 1 captures one RK4 step (products, stage kernels) per running
+ * instance count into a HIP graph on a private stream and replays it on the
+ * context stream for every step in which no instance reaches its final time
+ * (the stage kernels then read the step index from device memory); 0
+ * (default) launches every kernel directly.  Results are identical. */
+#define TDG_OPT_GRAPHS 5
 int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
 /* Name of the stage-kernel variant the last tdg_propagate used ("" before any). */
 const char* tdg_last_variant(tdg_ctx ctx);

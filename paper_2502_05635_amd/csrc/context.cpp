@@ -160,6 +160,10 @@ int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value) {
     ctx->gemm_variant = value == 64 ? 0 : 2;
     return TDG_OK;
   }
+  if (option == TDG_OPT_GRAPHS) {
+    ctx->graphs = value != 0;
+    return TDG_OK;
+  }
   if (option == TDG_OPT_GEMM_VARIANT) {
     if (value < -1 || value > 2) return fail(ctx, TDG_E_INVAL, "GEMM variant %lld outside [-1, 2]", (long long)value);
     ctx->gemm_variant = (int)value;

@@ -38,6 +38,7 @@ enum WsSlot {
   WS_RSVD_F,     // randomized compression: complex64 copies of Q and K Q for a C64 kernel
   WS_RSVD_T,     // randomized compression: Q^H K_off Q, c128 [l][l], and Householder scalars
   WS_ADJ,        // adjoint propagation: checkpoints, segment states, stage data, cotangents
+  WS_STEP,       // batched path: step counter read by graph replays
   WS_COUNT
 };
 
@@ -66,6 +67,7 @@ struct tdg_ctx_s {
   int forced_variant = -1;
   int batched_min = 4;  // complex64 operators use the matrix-core path from this batch size
   int gemm_variant = -1; // tiling of the matrix-core product: -1 tuned per shape, else 0..2 (cgemm_f32)
+  bool graphs = false;   // batched path: replay captured RK4 steps (TDG_OPT_GRAPHS)
   std::vector<std::pair<std::string, int>> tuned;  // shape key -> variant index
   std::string last_variant;
 };

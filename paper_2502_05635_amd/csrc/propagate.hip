@@ -541,7 +541,19 @@ struct BatchParams {
   int n_dyn;     // instances that integrate
   int step, stage;
   double dt;
+  const int* step_dev;  // graph replays: the step is read here (obs slot = step % chunk); else NULL
+  int chunk;
 };
+
+// The step counter of graph replays (vector stores: the address depends on the lane).
+__global__ void set_step_kernel(int* c, int v) {
+  const int t = threadIdx.x;
+  if (t == 0) c[t] = v;
+}
+__global__ void advance_step_kernel(int* c) {
+  const int t = threadIdx.x;
+  if (t == 0) c[t] = c[t] + 1;
+}
 
 // One block per (k point, group of instances): thread (li, e) owns element
 // e = (n, m) of instance blockIdx.y * ib + li, ib = blockDim.x / nb^2.
@@ -553,6 +565,8 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   const int li = threadIdx.x / nb2, e = threadIdx.x % nb2, n = e / nb, m = e % nb;
   const int k = blockIdx.x, b = blockIdx.y * ib + li;
   const bool act = li < ib && b < bp.n_active, dyn = act && b < bp.n_dyn;
+  const int step = bp.step_dev ? bp.step_dev[0] : bp.step;
+  const int obs_slot = bp.step_dev ? step % bp.chunk : bp.obs_slot;
   const size_t g = ((size_t)b * bp.nk + k) * nb2 + e;
   const size_t base = (size_t)k * nb2 + e, plane = (size_t)bp.nk * nb2;
   const int P = bp.npair;
@@ -628,7 +642,7 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
         if (s_obs[4][q] > o[4] || s_obs[4][q] != s_obs[4][q]) o[4] = s_obs[4][q];
       }
       o[3] = fabs(o[3] - (double)bp.nv);
-      double* dst = bp.obs_part + (((size_t)bp.obs_slot * bp.batch + b) * bp.nk + k) * 5;
+      double* dst = bp.obs_part + (((size_t)obs_slot * bp.batch + b) * bp.nk + k) * 5;
       for (int c = 0; c < 5; ++c) dst[c] = o[c];
     }
   }
@@ -636,7 +650,7 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   // H = eps + dSigma - E(t) e.d
   if (dyn) {
     const double cs = (bp.stage == 0) ? 0.0 : (bp.stage == 3 ? 1.0 : 0.5);
-    const double ef = field_value(F, (double)bp.step * bp.dt + cs * bp.dt);
+    const double ef = field_value(F, (double)step * bp.dt + cs * bp.dt);
     const double2 de = proj_e(F, d0, d1);
     double2 h = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
     if (n == m) h.x += e_nn;
@@ -1132,56 +1146,112 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     if (!bf16)
       ctx->last_variant += lowrank ? " (tilings " + std::to_string(gv_proj) + "/" + std::to_string(gv_main) + ")"
                                    : " (tiling " + std::to_string(gv_main) + ")";
+    if (ctx->graphs && !ctx->prof) ctx->last_variant += " graphs";
     tdg_obs ob = *obs;
-    void* xc = x0;
-    void* xn = x1;
-    int slot = 0;
-    int64_t chunk_start = 0;
-    for (int64_t step = 0; step <= max_steps; ++step) {
-      const int n_obs = count_ge(step), n_dyn = count_gt(step);
+    void* dstep = nullptr;
+    TDG_TRY(ws_reserve(ctx, WS_STEP, 256, &dstep));
+    bp.chunk = chunk;
+
+    // One RK4 step's launches on stream st.  dev_step: the stage kernels read
+    // the step from the device counter (the form captured into graphs); every
+    // step ends by advancing that counter.
+    auto issue_step = [&](hipStream_t st, int64_t step, int slot_, int n_obs, int n_dyn, bool dev_step, bool prof) {
       bp.n_dyn = n_dyn;
+      bp.step_dev = dev_step ? (const int*)dstep : nullptr;
+      void* xc = x0;
+      void* xn = x1;
       for (int s = 0; s < 4; ++s) {
         const int active = s == 0 ? n_obs : n_dyn;
         if (active == 0) break;
         if (n_dyn > 0) {
-          prof_begin(ctx, TDG_KCLASS_GEMM);
+          if (prof) prof_begin(ctx, TDG_KCLASS_GEMM);
           const int64_t ld_us = bf16 ? (op->rank + 3) / 4 * 4 : op->rank;
           if (!lowrank) {
             if (bf16)
-              cgemm_bf16x2(ctx->stream, op->K, op->ld, (int)n, (int)n, xc, xstride, Ybuf, ldy, n * ldy, n_dyn,
-                           (int)ks_main);
+              cgemm_bf16x2(st, op->K, op->ld, (int)n, (int)n, xc, xstride, Ybuf, ldy, n * ldy, n_dyn, (int)ks_main);
             else
-              cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xc, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
+              cgemm_f32(st, op->K, op->ld, (int)n, (int)n, xc, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
                         (int)ks_main, gv_main);
           } else {
             // projection split over K, summed once in fixed order, then expansion
             if (bf16)
-              cgemm_bf16x2(ctx->stream, op->w, n, (int)op->rank, (int)n, xc, xstride, Zbuf, ldy, op->rank * ldy,
-                           n_dyn, (int)ks_proj);
+              cgemm_bf16x2(st, op->w, n, (int)op->rank, (int)n, xc, xstride, Zbuf, ldy, op->rank * ldy, n_dyn,
+                           (int)ks_proj);
             else
-              cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xc, xstride, 1, 0, Zbuf, ldy,
-                        op->rank * ldy, n_dyn, (int)ks_proj, gv_proj);
-            sum_slices_c64(ctx->stream, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
+              cgemm_f32(st, op->w, n, (int)op->rank, (int)n, xc, xstride, 1, 0, Zbuf, ldy, op->rank * ldy, n_dyn,
+                        (int)ks_proj, gv_proj);
+            sum_slices_c64(st, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
             if (bf16)
-              cgemm_bf16x2(ctx->stream, op->us, ld_us, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
+              cgemm_bf16x2(st, op->us, ld_us, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
                            (int)ks_main);
             else
-              cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy,
-                        n_dyn, (int)ks_main, gv_main);
+              cgemm_f32(st, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
+                        (int)ks_main, gv_main);
           }
-          prof_end(ctx, TDG_KCLASS_GEMM);
+          if (prof) prof_end(ctx, TDG_KCLASS_GEMM);
         }
         bp.xcur = (const float2*)xc;
         bp.xnext = (float2*)xn;
         bp.step = (int)step;
         bp.stage = s;
-        bp.obs_slot = slot;
+        bp.obs_slot = slot_;
         bp.n_active = active;
-        prof_begin(ctx, TDG_KCLASS_STAGE);
-        hipLaunchKernelGGL(batched_stage_kernel, dim3(nk, (active + ib - 1) / ib), dim3(ib * nb2), 0,
-                           ctx->stream, bp);
-        prof_end(ctx, TDG_KCLASS_STAGE);
+        if (prof) prof_begin(ctx, TDG_KCLASS_STAGE);
+        hipLaunchKernelGGL(batched_stage_kernel, dim3(nk, (active + ib - 1) / ib), dim3(ib * nb2), 0, st, bp);
+        if (prof) prof_end(ctx, TDG_KCLASS_STAGE);
         std::swap(xc, xn);
+      }
+      hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, (int*)dstep);
+    };
+
+    // Graph replays (TDG_OPT_GRAPHS): a step in which no instance reaches its
+    // final time is the same launch sequence for a given running count; it is
+    // captured once per count on a private stream and replayed on the
+    // context stream.  Steps where instances finish, the observable
+    // reductions and profiled runs stay direct launches.
+    const bool use_graphs = ctx->graphs && !ctx->prof;
+    std::vector<std::pair<int, hipGraphExec_t>> execs;
+    hipStream_t cap = nullptr;
+    auto release = [&]() {
+      for (auto& e : execs) hipGraphExecDestroy(e.second);
+      execs.clear();
+      if (cap) hipStreamDestroy(cap);
+      cap = nullptr;
+    };
+    if (use_graphs && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+      return fail(ctx, TDG_E_HIP, "capture stream");
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, ctx->stream, (int*)dstep, 0);
+    int slot = 0;
+    int64_t chunk_start = 0;
+    int rc = TDG_OK;
+    for (int64_t step = 0; step <= max_steps && rc == TDG_OK; ++step) {
+      const int n_obs = count_ge(step), n_dyn = count_gt(step);
+      if (use_graphs && n_dyn > 0 && n_obs == n_dyn) {
+        hipGraphExec_t ex = nullptr;
+        for (auto& e : execs)
+          if (e.first == n_dyn) ex = e.second;
+        if (!ex) {
+          hipGraph_t g = nullptr;
+          if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = fail(ctx, TDG_E_HIP, "graph capture begin");
+            break;
+          }
+          issue_step(cap, step, 0, n_obs, n_dyn, true, false);
+          const hipError_t e1 = hipStreamEndCapture(cap, &g);
+          const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) : e1;
+          if (g) hipGraphDestroy(g);
+          if (e2 != hipSuccess) {
+            rc = fail(ctx, TDG_E_HIP, "graph capture: %s", hipGetErrorString(e2));
+            break;
+          }
+          execs.emplace_back(n_dyn, ex);
+        }
+        if (hipGraphLaunch(ex, ctx->stream) != hipSuccess) {
+          rc = fail(ctx, TDG_E_HIP, "graph launch");
+          break;
+        }
+      } else {
+        issue_step(ctx->stream, step, slot, n_obs, n_dyn, false, ctx->prof);
       }
       ++slot;
       if (slot == chunk || step == max_steps) {
@@ -1191,8 +1261,11 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         chunk_start += slot;
         slot = 0;
       }
-      if ((step & 63) == 0) TDG_TRY(launch_check(ctx, "batched propagation launch"));
+      if ((step & 63) == 0) rc = launch_check(ctx, "batched propagation launch");
     }
+    if (use_graphs) hipStreamSynchronize(ctx->stream);
+    release();
+    TDG_TRY(rc);
     hipLaunchKernelGGL(finish_kernel, dim3(nk, batch), dim3(init_threads), 0, ctx->stream, (const double2*)rho_n,
                        (const int*)dperm, (double2*)rho, nk, nb2);
     return launch_check(ctx, "batched propagation launch");

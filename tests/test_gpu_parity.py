@@ -654,3 +654,64 @@ def test_channel_invalid_arguments(P, ctx, tb4_6):
         ctx.kernel_compress_channels(kg, nk, 4, "fraction", 0.5, rmax=8)
     with pytest.raises(P.TdgError):                       # capacity not a multiple of 4
         P.Context.kernel_compress_channels(ctx, kg, nk, 4, "rank", 2, rmax=6)
+
+
+def test_channel_full_size_fp32_vs_stored_oracle(P, ctx):
+    """36x36 e-h workload, channel-wise kernel at the stored fixed-error
+    fraction, FP32, 4000 steps, against the stored FP64 oracle series
+    (parity window: the first half of the run, as for the other operators)."""
+    path = os.path.join(GOLDEN, "tb4_36x36_channel_series.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored channel-wise series missing (python -m tests.golden.make_golden_channels)")
+    info = json.load(open(os.path.join(GOLDEN, "tb4_36x36_channels.json")))
+    g = np.load(path)
+    cfg = get_config(1)
+    m = cfg.model()
+    dm = _dev(P, m)
+    frac = info["chosen"]["fraction"]
+    kg = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
+    npair = 4
+    rmax = min(m.nk // 4 * 4, (int(round(frac * m.nk)) + 8 + 3) // 4 * 4)
+    fac = ctx.kernel_compress_channels(kg, m.nk, npair, "fraction", frac, rmax=rmax)
+    for key, r in info["chosen"]["ranks"].items():
+        p, q = (int(v) for v in key.split(","))
+        assert fac.ranks[p, q] == r, key
+    _log(f"full-size {cfg.name} channel-wise FP32 (fraction {frac}) 4000 steps vs stored FP64 oracle")
+    res = ctx.propagate(fac, dm, "eh", cfg.fields, cfg.dt)
+    half = int(cfg.fields.nsteps[0]) // 2 + 1
+    for key in ("P", "J"):
+        got = res[key][0].cpu().numpy()
+        e_half = float(np.abs(got[:half] - g[key][:half]).max() / np.abs(g[key][:half]).max())
+        _log(f"  err_{key}: first half {e_half:.2e}, full run {err_rel(got, g[key]):.2e}")
+        assert e_half <= 1e-4, key
+
+
+@pytest.mark.parametrize("kind", ["dense", "lowrank", "bf16x2"])
+def test_batched_graph_replay_matches_direct(P, ctx, tb4_6, kind):
+    """Captured RK4 steps replayed as HIP graphs give bit-identical series and
+    final states to direct launches, over an uneven batch (instances finish
+    at different steps, so graphs for several running counts are replayed,
+    with direct steps and observable reductions between them)."""
+    from paper_2502_05635_amd import _abi as abi
+    dm = _dev(P, tb4_6)
+    fields = _uneven_fields(9, seed=13)
+    if kind == "dense":
+        op = ctx.kernel_build(dm, R0_STABLE, "eh", "c64")
+    elif kind == "lowrank":
+        op = ctx.kernel_compress(ctx.kernel_build(dm, R0_STABLE, "eh", "c64"), "rank", 37)
+    else:
+        op = ctx.kernel_compress(ctx.kernel_build(dm, R0_STABLE, "eh", "c64"), "rank", 37, out_dtype="bf16x2")
+    ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, 0)
+    try:
+        ctx.set_option(abi.TDG_OPT_GRAPHS, 0)
+        a = ctx.propagate(op, dm, "eh", fields, DT)
+        ctx.set_option(abi.TDG_OPT_GRAPHS, 1)
+        for rep in range(2):
+            b = ctx.propagate(op, dm, "eh", fields, DT)
+            torch.cuda.synchronize()
+            assert "graphs" in ctx.last_variant()
+            for key in ("P", "J", "occ", "tr", "herm", "rho"):
+                assert torch.equal(a[key], b[key]), (kind, rep, key)
+    finally:
+        ctx.set_option(abi.TDG_OPT_GRAPHS, 0)
+        ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
