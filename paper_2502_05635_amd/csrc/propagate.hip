@@ -480,8 +480,8 @@ __global__ void __launch_bounds__(PROJ_THREADS) project_kernel(const void* __res
 
 // Working state from the caller's rho: rho_n <- rho_eq or rho[perm[b]],
 // rho_s <- rho_n, x <- (rho_n - rho_eq)[pairs]; b is the sorted position.
-// x_layout: 0 = [B][xstride] with pair index k P + p; 1 = the batched path's
-// [N][xstride] (instance fastest); 2 = [B][xstride] channel-major, p nk + k.
+// x_layout: 0 = [B][xstride] with pair index k P + p; 2 = [B][xstride]
+// channel-major, p nk + k.  (The batched path has init_batched_kernel.)
 template <typename T>
 __global__ void init_kernel(const double2* __restrict__ rho_in, const int* __restrict__ perm, double2* rho_n,
                             double2* rho_s, void* x, int64_t xstride, int nk, int nb, int nv, int npair, int block,
@@ -505,7 +505,7 @@ __global__ void init_kernel(const double2* __restrict__ rho_in, const int* __res
     xv.x = (T)(r.x - occ);
     xv.y = (T)r.y;
     const size_t i = x_layout == 2 ? (size_t)p * nk + k : (size_t)k * npair + p;
-    reinterpret_cast<C*>(x)[x_layout == 1 ? i * xstride + b : (size_t)b * xstride + i] = xv;
+    reinterpret_cast<C*>(x)[(size_t)b * xstride + i] = xv;
   }
 }
 
@@ -555,50 +555,57 @@ __global__ void advance_step_kernel(int* c) {
   if (t == 0) c[t] = c[t] + 1;
 }
 
-// One block per (k point, group of instances): thread (li, e) owns element
-// e = (n, m) of instance blockIdx.y * ib + li, ib = blockDim.x / nb^2.
+// Batched state layout: element e of instance b at k is [(k nb^2 + e) ldx + b]
+// (instance fastest; ldx = the drho row stride), so a wave reads and writes
+// consecutive instances of one element.  Per-k observable partials keep the
+// [slot][B][nk][5] layout of obs_reduce_kernel.
+__device__ inline size_t bidx(const BatchParams& bp, int k, int e, int b) {
+  return ((size_t)k * bp.nb * bp.nb + e) * bp.ldx + b;
+}
+
+// One block per (k point, group of IB instances): thread t has lane i = t % IB
+// (instance group * IB + i) and row n = t / IB, and owns the row's elements
+// (n, m), m = 0 .. nb-1.  The instances' H and rho blocks are staged in LDS as
+// [element][lane] (dynamic, 2 nb^2 IB double2 + 5 nb IB double).
 __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
-  __shared__ double2 s_rho[256];
-  __shared__ double2 s_h[256];
-  __shared__ double s_obs[5][256];
-  const int nb = bp.nb, nb2 = nb * nb, ib = blockDim.x / nb2;
-  const int li = threadIdx.x / nb2, e = threadIdx.x % nb2, n = e / nb, m = e % nb;
-  const int k = blockIdx.x, b = blockIdx.y * ib + li;
-  const bool act = li < ib && b < bp.n_active, dyn = act && b < bp.n_dyn;
+  extern __shared__ double2 dyn_lds[];
+  const int nb = bp.nb, nb2 = nb * nb, IB = blockDim.x / nb;
+  double2* s_rho = dyn_lds;
+  double2* s_h = dyn_lds + nb2 * IB;
+  double* s_o = reinterpret_cast<double*>(dyn_lds + 2 * nb2 * IB);  // [5][nb][IB]
+  const int i = threadIdx.x % IB, n = threadIdx.x / IB;
+  const int k = blockIdx.x, b = blockIdx.y * IB + i;
+  const bool act = b < bp.n_active, dyn = act && b < bp.n_dyn;
   const int step = bp.step_dev ? bp.step_dev[0] : bp.step;
   const int obs_slot = bp.step_dev ? step % bp.chunk : bp.obs_slot;
-  const size_t g = ((size_t)b * bp.nk + k) * nb2 + e;
-  const size_t base = (size_t)k * nb2 + e, plane = (size_t)bp.nk * nb2;
   const int P = bp.npair;
+  const size_t plane = (size_t)bp.nk * nb2;
 
   tdg_field F = {};
-  double2 r_s = make_double2(0.0, 0.0), r_n = r_s, r_acc = r_s, d0 = r_s, d1 = r_s, v0 = r_s, v1 = r_s;
-  double e_nn = 0.0;
-  int p = -1;
-  bool partner = false;  // element (v, c) of the conduction-valence block: conj of (c, v)
-  if (bp.block == TDG_BLOCK_ALL) {
-    p = e;
-  } else if (n >= bp.nv && m < bp.nv) {
-    p = (n - bp.nv) * bp.nv + m;
-  } else if (n < bp.nv && m >= bp.nv) {
-    p = (m - bp.nv) * bp.nv + n;
-    partner = true;
-  }
-  double2 ds = make_double2(0.0, 0.0);
-  if (act) {
-    F = bp.fields[b];
-    r_s = bp.rho_s[g];
-    d0 = bp.dip[base];
-    d1 = bp.dip[plane + base];
-    if (bp.stage == 0) {
-      v0 = bp.vel[base];
-      v1 = bp.vel[plane + base];
+  if (act) F = bp.fields[b];
+  double2 r_n[TDG_NB_MAX], r_acc[TDG_NB_MAX], ds[TDG_NB_MAX];
+#pragma unroll
+  for (int m = 0; m < TDG_NB_MAX; ++m) {
+    if (m >= nb) break;
+    const int e = n * nb + m;
+    double2 rs = make_double2(0.0, 0.0);
+    r_n[m] = r_acc[m] = ds[m] = rs;
+    if (act) rs = bp.rho_s[bidx(bp, k, e, b)];
+    s_rho[e * IB + i] = rs;
+    if (!dyn) continue;
+    const size_t g = bidx(bp, k, e, b);
+    r_n[m] = bp.rho_n[g];
+    if (bp.stage != 0) r_acc[m] = bp.acc[g];
+    int p = -1;
+    bool partner = false;  // element (v, c) of the conduction-valence block: conj of (c, v)
+    if (bp.block == TDG_BLOCK_ALL) {
+      p = e;
+    } else if (n >= bp.nv && m < bp.nv) {
+      p = (n - bp.nv) * bp.nv + m;
+    } else if (n < bp.nv && m >= bp.nv) {
+      p = (m - bp.nv) * bp.nv + n;
+      partner = true;
     }
-  }
-  if (dyn) {
-    r_n = bp.rho_n[g];
-    if (bp.stage != 0) r_acc = bp.acc[g];
-    if (n == m) e_nn = bp.eps[(size_t)k * nb + n];
     if (p >= 0) {
       const size_t row = (size_t)k * P + p;
       float yr = 0.f, yi = 0.f;
@@ -612,38 +619,47 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
         yr += kd.x * xv.x - kd.y * xv.y;
         yi += kd.x * xv.y + kd.y * xv.x;
       }
-      ds = make_double2((double)yr, partner ? -(double)yi : (double)yi);
+      ds[m] = make_double2((double)yr, partner ? -(double)yi : (double)yi);
     }
   }
-  s_rho[threadIdx.x] = r_s;
   __syncthreads();
 
-  // observables of rho(t_n), per (instance, k)
+  // observables of rho(t_n), per (k, instance): row sums, then a fixed-order sum over rows
   if (bp.stage == 0 && bp.obs_part) {
+    double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (act) {
-      const double2 de = proj_e(F, d0, d1), ve = proj_e(F, v0, v1);
-      const double2 rmn = s_rho[li * nb2 + m * nb + n];
-      s_obs[0][threadIdx.x] = de.x * rmn.x - de.y * rmn.y;
-      s_obs[1][threadIdx.x] = ve.x * rmn.x - ve.y * rmn.y;
-      s_obs[2][threadIdx.x] = (n == m && n == bp.nv) ? r_s.x : 0.0;
-      s_obs[3][threadIdx.x] = (n == m) ? r_s.x : 0.0;
-      const double hx = r_s.x - rmn.x, hy = r_s.y + rmn.y;
-      s_obs[4][threadIdx.x] = sqrt(hx * hx + hy * hy);
-    }
-    __syncthreads();
-    if (act && e == 0) {
-      double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      for (int i = 0; i < nb2; ++i) {
-        const int q = li * nb2 + i;
-        o[0] += s_obs[0][q];
-        o[1] += s_obs[1][q];
-        o[2] += s_obs[2][q];
-        o[3] += s_obs[3][q];
-        if (s_obs[4][q] > o[4] || s_obs[4][q] != s_obs[4][q]) o[4] = s_obs[4][q];
+#pragma unroll
+      for (int m = 0; m < TDG_NB_MAX; ++m) {
+        if (m >= nb) break;
+        const int e = n * nb + m;
+        const size_t base = (size_t)k * nb2 + e;
+        const double2 de = proj_e(F, bp.dip[base], bp.dip[plane + base]);
+        const double2 ve = proj_e(F, bp.vel[base], bp.vel[plane + base]);
+        const double2 rmn = s_rho[(m * nb + n) * IB + i], rnm = s_rho[e * IB + i];
+        o[0] += de.x * rmn.x - de.y * rmn.y;
+        o[1] += ve.x * rmn.x - ve.y * rmn.y;
+        if (n == m && n == bp.nv) o[2] += rnm.x;
+        if (n == m) o[3] += rnm.x;
+        const double hx = rnm.x - rmn.x, hy = rnm.y + rmn.y, h = sqrt(hx * hx + hy * hy);
+        if (h > o[4] || h != h) o[4] = h;
       }
-      o[3] = fabs(o[3] - (double)bp.nv);
-      double* dst = bp.obs_part + (((size_t)obs_slot * bp.batch + b) * bp.nk + k) * 5;
-      for (int c = 0; c < 5; ++c) dst[c] = o[c];
+    }
+    for (int c = 0; c < 5; ++c) s_o[(c * nb + n) * IB + i] = o[c];
+    __syncthreads();
+    if (act && n < 5) {
+      // row n of the block's threads writes observables n, n + nb, ... (< 5)
+      for (int c = n; c < 5; c += nb) {
+        double v = 0.0;
+        for (int r = 0; r < nb; ++r) {
+          const double q = s_o[(c * nb + r) * IB + i];
+          if (c < 4)
+            v += q;  // P, J, occupation and the trace are sums over rows
+          else if (q > v || q != q)
+            v = q;   // the Hermiticity residual is a maximum
+        }
+        if (c == 3) v = fabs(v - (double)bp.nv);
+        bp.obs_part[(((size_t)obs_slot * bp.batch + b) * bp.nk + k) * 5 + c] = v;
+      }
     }
   }
 
@@ -651,44 +667,91 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   if (dyn) {
     const double cs = (bp.stage == 0) ? 0.0 : (bp.stage == 3 ? 1.0 : 0.5);
     const double ef = field_value(F, (double)step * bp.dt + cs * bp.dt);
-    const double2 de = proj_e(F, d0, d1);
-    double2 h = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
-    if (n == m) h.x += e_nn;
-    s_h[threadIdx.x] = h;
+#pragma unroll
+    for (int m = 0; m < TDG_NB_MAX; ++m) {
+      if (m >= nb) break;
+      const int e = n * nb + m;
+      const size_t base = (size_t)k * nb2 + e;
+      const double2 de = proj_e(F, bp.dip[base], bp.dip[plane + base]);
+      double2 h = make_double2(ds[m].x - ef * de.x, ds[m].y - ef * de.y);
+      if (n == m) h.x += bp.eps[(size_t)k * nb + n];
+      s_h[e * IB + i] = h;
+    }
   }
   __syncthreads();
   if (!dyn) return;
 
   // f = -i [H, rho], RK4 stage, next drho gather
-  const double2* H = s_h + li * nb2;
-  const double2* R = s_rho + li * nb2;
-  double2 c = make_double2(0.0, 0.0);
-  for (int l = 0; l < nb; ++l) {
-    const double2 hr = cmul(H[n * nb + l], R[l * nb + m]);
-    const double2 rh = cmul(R[n * nb + l], H[l * nb + m]);
-    c.x += hr.x - rh.x;
-    c.y += hr.y - rh.y;
+#pragma unroll
+  for (int m = 0; m < TDG_NB_MAX; ++m) {
+    if (m >= nb) break;
+    const int e = n * nb + m;
+    double2 c = make_double2(0.0, 0.0);
+    for (int l = 0; l < nb; ++l) {
+      const double2 hr = cmul(s_h[(n * nb + l) * IB + i], s_rho[(l * nb + m) * IB + i]);
+      const double2 rh = cmul(s_rho[(n * nb + l) * IB + i], s_h[(l * nb + m) * IB + i]);
+      c.x += hr.x - rh.x;
+      c.y += hr.y - rh.y;
+    }
+    const double2 f = make_double2(c.y, -c.x);
+    const size_t g = bidx(bp, k, e, b);
+    double2 next;
+    if (bp.stage == 0) {
+      bp.acc[g] = f;
+      next = make_double2(r_n[m].x + 0.5 * bp.dt * f.x, r_n[m].y + 0.5 * bp.dt * f.y);
+    } else if (bp.stage == 1) {
+      bp.acc[g] = make_double2(r_acc[m].x + 2.0 * f.x, r_acc[m].y + 2.0 * f.y);
+      next = make_double2(r_n[m].x + 0.5 * bp.dt * f.x, r_n[m].y + 0.5 * bp.dt * f.y);
+    } else if (bp.stage == 2) {
+      bp.acc[g] = make_double2(r_acc[m].x + 2.0 * f.x, r_acc[m].y + 2.0 * f.y);
+      next = make_double2(r_n[m].x + bp.dt * f.x, r_n[m].y + bp.dt * f.y);
+    } else {
+      const double w = bp.dt / 6.0;
+      next = make_double2(r_n[m].x + w * (r_acc[m].x + f.x), r_n[m].y + w * (r_acc[m].y + f.y));
+      bp.rho_n[g] = next;
+    }
+    bp.rho_s[g] = next;
+    int p = -1;
+    if (bp.block == TDG_BLOCK_ALL)
+      p = e;
+    else if (n >= bp.nv && m < bp.nv)
+      p = (n - bp.nv) * bp.nv + m;
+    if (p >= 0) {
+      const double dre = next.x - ((n == m && n < bp.nv) ? 1.0 : 0.0);
+      bp.xnext[((size_t)k * P + p) * bp.ldx + b] = make_float2((float)dre, (float)next.y);
+    }
   }
-  const double2 f = make_double2(c.y, -c.x);
-  double2 next;
-  if (bp.stage == 0) {
-    bp.acc[g] = f;
-    next = make_double2(r_n.x + 0.5 * bp.dt * f.x, r_n.y + 0.5 * bp.dt * f.y);
-  } else if (bp.stage == 1) {
-    bp.acc[g] = make_double2(r_acc.x + 2.0 * f.x, r_acc.y + 2.0 * f.y);
-    next = make_double2(r_n.x + 0.5 * bp.dt * f.x, r_n.y + 0.5 * bp.dt * f.y);
-  } else if (bp.stage == 2) {
-    bp.acc[g] = make_double2(r_acc.x + 2.0 * f.x, r_acc.y + 2.0 * f.y);
-    next = make_double2(r_n.x + bp.dt * f.x, r_n.y + bp.dt * f.y);
-  } else {
-    const double w = bp.dt / 6.0;
-    next = make_double2(r_n.x + w * (r_acc.x + f.x), r_n.y + w * (r_acc.y + f.y));
-    bp.rho_n[g] = next;
+}
+
+// Batched state from the caller's rho: element e of instance b (sorted
+// position) at k to [(k nb^2 + e) ldx + b]; drho gather [N][ldx].  One block per k.
+__global__ void init_batched_kernel(const double2* __restrict__ rho_in, const int* __restrict__ perm, double2* rho_n,
+                                    double2* rho_s, float2* x, int64_t ldx, int nk, int nb, int nv, int npair,
+                                    int block, int init_eq, int batch) {
+  const int k = blockIdx.x, nb2 = nb * nb;
+  for (int idx = threadIdx.x; idx < nb2 * batch; idx += blockDim.x) {
+    const int e = idx / batch, b = idx % batch, n = e / nb, m = e % nb;
+    const double occ = (n == m && n < nv) ? 1.0 : 0.0;
+    const double2 r = init_eq ? make_double2(occ, 0.0) : rho_in[((size_t)perm[b] * nk + k) * nb2 + e];
+    const size_t g = ((size_t)k * nb2 + e) * ldx + b;
+    rho_n[g] = r;
+    rho_s[g] = r;
+    int p = -1;
+    if (block == TDG_BLOCK_ALL)
+      p = e;
+    else if (n >= nv && m < nv)
+      p = (n - nv) * nv + m;
+    if (p >= 0) x[((size_t)k * npair + p) * ldx + b] = make_float2((float)(r.x - occ), (float)r.y);
   }
-  bp.rho_s[g] = next;
-  if (p >= 0 && !partner) {
-    const double dre = next.x - ((n == m && n < bp.nv) ? 1.0 : 0.0);
-    bp.xnext[((size_t)k * P + p) * bp.ldx + b] = make_float2((float)dre, (float)next.y);
+}
+
+// rho[perm[b]] <- batched rho_n.  One block per k.
+__global__ void finish_batched_kernel(const double2* __restrict__ rho_n, const int* __restrict__ perm,
+                                      double2* rho_out, int64_t ldx, int nk, int nb2, int batch) {
+  const int k = blockIdx.x;
+  for (int idx = threadIdx.x; idx < nb2 * batch; idx += blockDim.x) {
+    const int e = idx / batch, b = idx % batch;
+    rho_out[((size_t)perm[b] * nk + k) * nb2 + e] = rho_n[((size_t)k * nb2 + e) * ldx + b];
   }
 }
 
@@ -919,13 +982,13 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   }
 
   const int nb2 = model->nb * model->nb;
-  const size_t state_bytes = (size_t)batch * nk * nb2 * sizeof(double2);
   // matrix-core path: complex64 operator and enough instances
   const bool batched = !channel && (bf16 || (op->dtype == TDG_C64 && batch >= ctx->batched_min));
-  if (batched && (nb2 > 256 || n > 2147483647 / 2))
-    return fail(ctx, TDG_E_UNSUPPORTED, "batched path: nb^2 <= 256 and N < 2^30 required");
+  if (batched && n > 2147483647 / 2) return fail(ctx, TDG_E_UNSUPPORTED, "batched path: N < 2^30 required");
   // batched rows hold an even number of instances (two per 16-byte load)
   const int64_t xstride = batched ? (((int64_t)batch + 1) & ~int64_t(1)) : ((n + 1) & ~int64_t(1));
+  // batched state is instance fastest with the drho row stride
+  const size_t state_bytes = (size_t)(batched ? xstride : batch) * nk * nb2 * sizeof(double2);
   const int64_t zstride = channel ? (int64_t)npair * ch_ls : (op->rank + 1) & ~int64_t(1);
   void *rho_n, *rho_s, *acc, *x0, *x1, *z = nullptr, *part, *dperm, *dfields;
   TDG_TRY(ws_reserve(ctx, WS_RHO_N, state_bytes, &rho_n));
@@ -947,8 +1010,14 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     zsplit = (int)std::min<int64_t>(ZSPLIT_MAX, std::max<int64_t>(1, (256 + groups - 1) / groups));
     zslice = ((n + zsplit - 1) / zsplit + 1) & ~int64_t(1);
     zsplit = (int)((n + zslice - 1) / zslice);
-    TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)zsplit * batch * zstride * elt, &z));
+    // room for the tuner's largest split
+    TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)ZSPLIT_MAX * batch * zstride * elt, &z));
   }
+  // a split of the projection's columns into `want` slices (at most ZSPLIT_MAX)
+  auto set_split = [&](int want) {
+    zslice = ((n + want - 1) / want + 1) & ~int64_t(1);
+    zsplit = (int)((n + zslice - 1) / zslice);
+  };
   const size_t part_per_step = (size_t)batch * nk * 5 * sizeof(double);
   const int chunk = (int)std::min<size_t>(256, std::max<size_t>(1, OBS_PART_BUDGET / part_per_step));
   TDG_TRY(ws_reserve(ctx, WS_OBS_PART, part_per_step * chunk, &part));
@@ -957,14 +1026,20 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
 
   const int init_threads = ((nb2 + 63) / 64) * 64;
   auto init = [&]() {
+    if (batched) {
+      hipLaunchKernelGGL(init_batched_kernel, dim3(nk), dim3(256), 0, ctx->stream, (const double2*)rho,
+                         (const int*)dperm, (double2*)rho_n, (double2*)rho_s, (float2*)x0, xstride, nk, model->nb,
+                         model->nv, npair, op->block, init_eq, batch);
+      return launch_check(ctx, "init launch");
+    }
     if (op->dtype == TDG_C128)
       hipLaunchKernelGGL(init_kernel<double>, dim3(nk, batch), dim3(init_threads), 0, ctx->stream,
                          (const double2*)rho, (const int*)dperm, (double2*)rho_n, (double2*)rho_s, x0, xstride, nk,
-                         model->nb, model->nv, npair, op->block, init_eq, batched ? 1 : (channel ? 2 : 0));
+                         model->nb, model->nv, npair, op->block, init_eq, channel ? 2 : 0);
     else
       hipLaunchKernelGGL(init_kernel<float>, dim3(nk, batch), dim3(init_threads), 0, ctx->stream,
                          (const double2*)rho, (const int*)dperm, (double2*)rho_n, (double2*)rho_s, x0, xstride, nk,
-                         model->nb, model->nv, npair, op->block, init_eq, batched ? 1 : (channel ? 2 : 0));
+                         model->nb, model->nv, npair, op->block, init_eq, channel ? 2 : 0);
     return launch_check(ctx, "init launch");
   };
   TDG_TRY(init());
@@ -993,7 +1068,6 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   sp.batch = batch;
   sp.dt = dt;
   const int64_t split_stride = (int64_t)batch * zstride;
-  sp.zsplit = zsplit;
   sp.zsplit_stride = split_stride;
   // projection rows: the rank (low rank) or every off-diagonal channel's rows (channel-wise)
   const int prows = channel ? npair * ch_ls : (int)op->rank;
@@ -1001,6 +1075,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const unsigned groups = (unsigned)((prows + ROWS - 1) / ROWS);
 
   auto project = [&](const void* xin, int active) {
+    sp.zsplit = zsplit;
     const dim3 g(groups, zsplit, active);
     if (op->dtype == TDG_C128)
       hipLaunchKernelGGL(project_kernel<double>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
@@ -1077,7 +1152,10 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     bp.block = op->block;
     bp.batch = batch;
     bp.dt = dt;
-    const int ib = 256 / nb2;
+    // stage kernel blocks: IB instances x nb rows, LDS for their H and rho blocks and row sums
+    int IB = 16;  // instances per block: up to 64 for nb <= 4, matched to the batch
+    while (model->nb <= 4 && IB < 64 && IB < batch) IB *= 2;
+    const size_t stage_lds = (size_t)2 * nb2 * IB * sizeof(double2) + (size_t)5 * model->nb * IB * sizeof(double);
 
     // tiling of each FP32 product: forced, cached for its shape, or timed now
     // (every tiling twice on the step-0 operands, the second run timed); the
@@ -1197,7 +1275,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         bp.obs_slot = slot_;
         bp.n_active = active;
         if (prof) prof_begin(ctx, TDG_KCLASS_STAGE);
-        hipLaunchKernelGGL(batched_stage_kernel, dim3(nk, (active + ib - 1) / ib), dim3(ib * nb2), 0, st, bp);
+        hipLaunchKernelGGL(batched_stage_kernel, dim3(nk, (active + IB - 1) / IB), dim3(IB * model->nb), stage_lds,
+                           st, bp);
         if (prof) prof_end(ctx, TDG_KCLASS_STAGE);
         std::swap(xc, xn);
       }
@@ -1266,8 +1345,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     if (use_graphs) hipStreamSynchronize(ctx->stream);
     release();
     TDG_TRY(rc);
-    hipLaunchKernelGGL(finish_kernel, dim3(nk, batch), dim3(init_threads), 0, ctx->stream, (const double2*)rho_n,
-                       (const int*)dperm, (double2*)rho, nk, nb2);
+    hipLaunchKernelGGL(finish_batched_kernel, dim3(nk), dim3(256), 0, ctx->stream, (const double2*)rho_n,
+                       (const int*)dperm, (double2*)rho, xstride, nk, nb2, batch);
     return launch_check(ctx, "batched propagation launch");
   }
 
@@ -1279,6 +1358,10 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   else
     channel ? table(kChanF32, vt, nvar) : (lowrank ? table(kLowF32, vt, nvar) : table(kDenseF32, vt, nvar));
   int var = 0;
+  sp.zsplit = zsplit;
+  // low rank: the tuner also picks the projection's column split
+  const bool tune_split = lowrank && !batched;
+  const int splits[3] = {1, 2, ZSPLIT_MAX};
   if (ctx->forced_variant >= 0) {
     if (ctx->forced_variant >= nvar)
       return fail(ctx, TDG_E_INVAL, "variant %d of %d for this operator", ctx->forced_variant, nvar);
@@ -1291,7 +1374,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     for (auto& kv : ctx->tuned)
       if (kv.first == key) found = kv.second;
     if (found >= 0) {
-      var = found;
+      var = found % 100;
+      if (tune_split) set_split(splits[found / 100]);
     } else {
       // time each variant on stage 0 of step 0: it reads rho and writes only
       // the stage state, accumulator and next gather, which init restores
@@ -1307,30 +1391,50 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       sp.xnext = x1;
       sp.vec = projects ? z : x0;
       sp.vstride = projects ? zstride : xstride;
-      if (projects) project(x0, dyn0);
       const dim3 g(nk, dyn0);
       float best = 1e30f;
-      for (int v = 0; v < nvar; ++v) {
-        vt[v].fn(g, 0, ctx->stream, sp);  // warm-up
-        hipEventRecord(ea, ctx->stream);
-        for (int rep = 0; rep < 3; ++rep) vt[v].fn(g, 0, ctx->stream, sp);
-        hipEventRecord(eb, ctx->stream);
-        TDG_TRY(launch_check(ctx, "tuner launch"));
-        TDG_TRY(hip_check(ctx, hipEventSynchronize(eb), "tuner sync"));
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, ea, eb);
-        if (ms < best) {
-          best = ms;
-          var = v;
+      int best_split = 0;
+      const int nsplit = tune_split ? 3 : 1;
+      for (int si = 0; si < nsplit; ++si) {
+        if (tune_split) set_split(splits[si]);
+        // with the split tuned, each timed repetition includes the projection
+        auto run = [&](int v) {
+          if (projects && (tune_split || si == 0)) project(x0, dyn0);
+          vt[v].fn(g, 0, ctx->stream, sp);
+        };
+        if (projects && !tune_split) project(x0, dyn0);
+        for (int v = 0; v < nvar; ++v) {
+          run(v);  // warm-up
+          hipEventRecord(ea, ctx->stream);
+          for (int rep = 0; rep < 3; ++rep) {
+            if (tune_split) {
+              run(v);
+            } else {
+              vt[v].fn(g, 0, ctx->stream, sp);
+            }
+          }
+          hipEventRecord(eb, ctx->stream);
+          TDG_TRY(launch_check(ctx, "tuner launch"));
+          TDG_TRY(hip_check(ctx, hipEventSynchronize(eb), "tuner sync"));
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, ea, eb);
+          if (ms < best) {
+            best = ms;
+            var = v;
+            best_split = si;
+          }
         }
       }
       hipEventDestroy(ea);
       hipEventDestroy(eb);
-      ctx->tuned.emplace_back(key, var);
+      if (tune_split) set_split(splits[best_split]);
+      ctx->tuned.emplace_back(key, var + 100 * best_split);
       TDG_TRY(init());  // the caller's rho was only read
     }
   }
   ctx->last_variant = vt[var].name;
+  if (tune_split) ctx->last_variant += "_z" + std::to_string(zsplit);
+  sp.zsplit = zsplit;
   const StageLaunch stage_fn = vt[var].fn;
 
   tdg_obs ob = *obs;

@@ -715,3 +715,31 @@ def test_batched_graph_replay_matches_direct(P, ctx, tb4_6, kind):
     finally:
         ctx.set_option(abi.TDG_OPT_GRAPHS, 0)
         ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
+
+
+@pytest.mark.parametrize("kind,dtype,tol", [("dense", "c128", 1e-10), ("lowrank", "c64", 1e-4)])
+def test_four_band_all_pairs(P, ctx, kind, dtype, tol):
+    """The all-pairs kernel of the four-band model (16 band pairs per k, the
+    intraband cc/vv channels included): kernel elements and propagation
+    against the oracle."""
+    m = tb4_model(4, A, 0.5)
+    dm = _dev(P, m)
+    kg = ctx.kernel_build(dm, R0_STABLE, "all", dtype)
+    ko = O.build_kernel(m, R0_STABLE, "all")
+    assert kg.shape[0] == 16 * m.nk
+    e_k = float(np.abs(kg.cpu().numpy() - ko).max() / np.abs(ko).max())
+    assert e_k <= (1e-14 if dtype == "c128" else 1e-7)
+    if kind == "dense":
+        op, oop = kg, O.DenseOp(ko)
+    else:
+        op = ctx.kernel_compress(kg, "fraction", 0.3)
+        oop = O.LowRankOp.from_factors(O.compress(kg.cpu().numpy().astype(np.complex128), "fraction", 0.3))
+    f = strong(300)
+    _log(f"four-band all pairs {kind} {dtype}: N={kg.shape[0]}, 300 steps")
+    res = ctx.propagate(op, dm, "all", f, DT)
+    ref = O.propagate(m, oop, "all", f, DT)
+    for key in ("P", "J", "occ"):
+        e = err_rel(res[key][0].cpu().numpy(), ref[key])
+        _log(f"  err_{key} = {e:.2e}")
+        assert e <= tol, key
+    assert res["herm"].max().item() < 1e-6
