@@ -50,6 +50,10 @@ def parse():
                     help="also measure the 120x120 workload (N = 57600, 256 instances): randomized "
                          "compression, then dense FP32, low-rank FP32 and low-rank BF16X2 throughput")
     ap.add_argument("--large-grid-steps", type=int, default=40, help="RK4 steps per instance timed there")
+    ap.add_argument("--no-channelwise", action="store_true", help="skip the channel-wise compression leg")
+    ap.add_argument("--sweep-only", type=int, default=0, metavar="STEPS",
+                    help="only run the batched 60x60 sweep, every instance for STEPS steps (for counter runs; "
+                         "with --factors-cache the sweep's factors are cached as well)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -135,6 +139,15 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(instances or k-blocks would shard across GPUs; see the design notes).", file=sys.stderr)
         sys.exit(2)
+    if args.sweep_only:
+        import paper_2502_05635_amd as P
+        from paper_2502_05635_amd import _abi as abi
+        ctx = P.Context(0)
+        cache = args.factors_cache + ".sweep.npz" if args.factors_cache else None
+        print(json.dumps({"batched_sweep": batched_sweep(P, abi, ctx, 0.05, steps=args.sweep_only, cache=cache)}),
+              flush=True)
+        ctx.close()
+        return
 
     import numpy as np
     import torch
@@ -192,16 +205,19 @@ def main():
     # channel-wise compression (Eq. svd-channel-wise) at its own fixed-error fraction
     chan_golden = json.load(open(CHAN_JSON)) if os.path.exists(CHAN_JSON) else None
     chan_frac = chan_golden["chosen"]["fraction"] if chan_golden else 0.05
+    channelwise = None
     npair = (nb - model.nv) * model.nv
     rmax = min(nk // 4 * 4, (int(round(chan_frac * nk)) + 8 + 3) // 4 * 4)
-    t0 = time.perf_counter()
-    chan = ctx.kernel_compress_channels(K, nk, npair, "fraction", chan_frac, rmax=rmax)
-    torch.cuda.synchronize()
-    chan_compress_s = time.perf_counter() - t0
-    res, secs, _ = timed(chan, args.steps, args.warmup, False)
-    variant = ctx.last_variant()
-    _, _, prof = timed(chan, args.steps, args.warmup, True)
-    out["channel"] = {"secs": secs, "res": res, "prof": prof, "variant": variant}
+    chan = None
+    if not args.no_channelwise:
+        t0 = time.perf_counter()
+        chan = ctx.kernel_compress_channels(K, nk, npair, "fraction", chan_frac, rmax=rmax)
+        torch.cuda.synchronize()
+        chan_compress_s = time.perf_counter() - t0
+        res, secs, _ = timed(chan, args.steps, args.warmup, False)
+        variant = ctx.last_variant()
+        _, _, prof = timed(chan, args.steps, args.warmup, True)
+        out["channel"] = {"secs": secs, "res": res, "prof": prof, "variant": variant}
 
     # errors against the stored FP64 oracle series (same operator, same steps):
     # over the first half of the run (t <= t0, before the post-pulse chaotic
@@ -225,7 +241,7 @@ def main():
         errs["bright_exciton_shift_ev"] = golden["chosen"]["shift_ev"]
 
     chan_errs = {}
-    if os.path.exists(CHAN_NPZ) and chan_golden:
+    if chan is not None and os.path.exists(CHAN_NPZ) and chan_golden:
         g = np.load(CHAN_NPZ)
         m_ = min(args.steps, int(cfg.fields.nsteps[0])) + 1
         half = min(m_, int(cfg.fields.nsteps[0]) // 2 + 1)
@@ -233,18 +249,19 @@ def main():
             got = out["channel"]["res"][k][0, :m_].cpu().numpy()
             chan_errs[f"{k}_first_half"] = err_rel(got[:half], g[k][:half])
             chan_errs[f"{k}_full"] = err_rel(got, g[k][:m_])
-    cp = out["channel"]["prof"]
-    channelwise = {
-        "value": args.steps / out["channel"]["secs"], "ms_per_step": 1e3 * out["channel"]["secs"] / args.steps,
-        "variant": out["channel"]["variant"], "kept_fraction_per_offdiag_channel": chan_frac,
-        "ranks_offdiag": sorted({int(x) for i, row in enumerate(chan.ranks) for j, x in enumerate(row) if i != j}),
-        "stage_kernel_us": cp["stage"][0] / cp["stage"][1] * 1e3,
-        "project_kernel_us": cp["project"][0] / cp["project"][1] * 1e3,
-        "compress_seconds": chan_compress_s,
-        "errors_vs_fp64_oracle": chan_errs or None,
-        "bright_exciton_shift_ev": next((row["shift_ev"] for row in chan_golden["table"]
-                                         if row["fraction"] == chan_frac), None) if chan_golden else None,
-    }
+    if chan is not None:
+        cp = out["channel"]["prof"]
+        channelwise = {
+            "value": args.steps / out["channel"]["secs"], "ms_per_step": 1e3 * out["channel"]["secs"] / args.steps,
+            "variant": out["channel"]["variant"], "kept_fraction_per_offdiag_channel": chan_frac,
+            "ranks_offdiag": sorted({int(x) for i, row in enumerate(chan.ranks) for j, x in enumerate(row) if i != j}),
+            "stage_kernel_us": cp["stage"][0] / cp["stage"][1] * 1e3,
+            "project_kernel_us": cp["project"][0] / cp["project"][1] * 1e3,
+            "compress_seconds": chan_compress_s,
+            "errors_vs_fp64_oracle": chan_errs or None,
+            "bright_exciton_shift_ev": next((row["shift_ev"] for row in chan_golden["table"]
+                                             if row["fraction"] == chan_frac), None) if chan_golden else None,
+        }
 
     # dominant kernel of the low-rank path and the dense stage kernel
     lp = out["lowrank"]["prof"]
@@ -261,7 +278,8 @@ def main():
         traffic = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     value = args.steps / out["lowrank"]["secs"]
     dense_value = args.steps / out["dense"]["secs"]
-    channelwise["speedup_vs_dense"] = channelwise["value"] / dense_value
+    if channelwise:
+        channelwise["speedup_vs_dense"] = channelwise["value"] / dense_value
 
     rank_cut = int(np.count_nonzero(fac.sigma > 1e-3 * fac.sigma[0]))
     sweep = None
@@ -307,7 +325,7 @@ def main():
         "compress_seconds": compress_s,
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"stage_kernel<float,true> ({out['lowrank']['variant']})" if dom == "stage"
+            "kernel": (f"stage_kernel<float, 1, ...> ({out['lowrank']['variant']})" if dom == "stage"
                        else "project_kernel<float>"),
             "achieved": dom_bytes / dom_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom_bytes / dom_avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
@@ -321,7 +339,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def batched_sweep(P, abi, ctx, frac):
+def batched_sweep(P, abi, ctx, frac, steps=0, cache=None):
     """The 60x60 batched field sweep: 64 instances of uneven length (2000 to
     8000 steps) integrated together on the matrix-core path, dense and
     low-rank at the same kept fraction; instance.steps/s = sum of lengths / time."""
@@ -333,8 +351,15 @@ def batched_sweep(P, abi, ctx, frac):
     model = cfg.model()
     dm = P.DeviceModel.from_model(model)
     K = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
-    fac = ctx.kernel_compress(K, "fraction", frac)
+    if cache and os.path.exists(cache):
+        fac = load_factors(P, cache, K.shape[0], frac)
+    else:
+        fac = ctx.kernel_compress(K, "fraction", frac)
+        if cache:
+            save_factors(fac, cache, frac)
     f = cfg.fields
+    if steps:
+        f = FieldTable(f.e0, f.omega, f.tau, f.t0, f.ex, f.ey, np.full(f.batch, steps, dtype=np.int64))
     total = int(f.nsteps.sum())
     n, r, B = K.shape[0], fac.rank, f.batch
     short = FieldTable(f.e0, f.omega, f.tau, f.t0, f.ex, f.ey, np.full(B, 40, dtype=np.int64))
