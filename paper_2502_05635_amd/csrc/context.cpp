@@ -76,6 +76,21 @@ void prof_end(tdg_ctx ctx, int kclass) {
   ctx->used[kclass] = i + 1;
 }
 
+void prof_pair(tdg_ctx ctx, int kclass, hipEvent_t* a, hipEvent_t* b) {
+  *a = *b = nullptr;
+  if (!ctx->prof) return;
+  auto& v = ctx->events[kclass];
+  size_t i = ctx->used[kclass];
+  if (i == v.size()) {
+    EventPair p;
+    if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return;
+    v.push_back(p);
+  }
+  *a = v[i].a;
+  *b = v[i].b;
+  ctx->used[kclass] = i + 1;
+}
+
 int pairs_per_k(const tdg_model* m, int block) {
   if (block == TDG_BLOCK_ALL) return m->nb * m->nb;
   if (block == TDG_BLOCK_EH) return (m->nb - m->nv) * m->nv;

@@ -83,6 +83,9 @@ int launch_check(tdg_ctx ctx, const char* what);
 // Profiling brackets (no-ops unless profiling is on).
 void prof_begin(tdg_ctx ctx, int kclass);
 void prof_end(tdg_ctx ctx, int kclass);
+// Events for one kernel launched with hipExtLaunchKernelGGL (timestamps of the
+// dispatch itself); both NULL unless profiling is on.
+void prof_pair(tdg_ctx ctx, int kclass, hipEvent_t* a, hipEvent_t* b);
 int validate_model(tdg_ctx ctx, const tdg_model* m);
 int pairs_per_k(const tdg_model* m, int block);
 // Destroy the context's rocBLAS handle if compression created one.

@@ -25,6 +25,8 @@
 #include <cstdio>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace {
@@ -857,11 +859,16 @@ static int upload(tdg_ctx ctx, WsSlot slot, const void* src, size_t bytes, void*
 }
 
 // ---- stage-kernel variants -------------------------------------------------
-using StageLaunch = void (*)(dim3, size_t, hipStream_t, const StageParams&);
+// Stage-kernel launch; with events (profiling) the dispatch itself is timed.
+using StageLaunch = void (*)(dim3, size_t, hipStream_t, const StageParams&, hipEvent_t, hipEvent_t);
 
 template <typename T, int MODE, int NT, int U, int WPE>
-static void launch_stage(dim3 grid, size_t lds, hipStream_t stream, const StageParams& sp) {
-  hipLaunchKernelGGL((stage_kernel<T, MODE, NT, U, WPE>), grid, dim3(NT), lds, stream, sp);
+static void launch_stage(dim3 grid, size_t lds, hipStream_t stream, const StageParams& sp, hipEvent_t ea,
+                         hipEvent_t eb) {
+  if (ea)
+    hipExtLaunchKernelGGL((stage_kernel<T, MODE, NT, U, WPE>), grid, dim3(NT), (uint32_t)lds, stream, ea, eb, 0u, sp);
+  else
+    hipLaunchKernelGGL((stage_kernel<T, MODE, NT, U, WPE>), grid, dim3(NT), lds, stream, sp);
 }
 
 struct Variant {
@@ -1074,15 +1081,16 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const int64_t pcols = channel ? nk : n;
   const unsigned groups = (unsigned)((prows + ROWS - 1) / ROWS);
 
-  auto project = [&](const void* xin, int active) {
+  auto project = [&](const void* xin, int active, hipEvent_t ea = nullptr, hipEvent_t eb = nullptr) {
     sp.zsplit = zsplit;
     const dim3 g(groups, zsplit, active);
+    const int chr = (int)(channel ? op->rank : 0);
     if (op->dtype == TDG_C128)
-      hipLaunchKernelGGL(project_kernel<double>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
-                         xstride, z, zstride, zslice, split_stride, ch_ls, (int)(channel ? op->rank : 0));
+      hipExtLaunchKernelGGL(project_kernel<double>, g, dim3(PROJ_THREADS), 0u, ctx->stream, ea, eb, 0u, op->w, pcols,
+                            prows, xin, xstride, z, zstride, zslice, split_stride, ch_ls, chr);
     else
-      hipLaunchKernelGGL(project_kernel<float>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
-                         xstride, z, zstride, zslice, split_stride, ch_ls, (int)(channel ? op->rank : 0));
+      hipExtLaunchKernelGGL(project_kernel<float>, g, dim3(PROJ_THREADS), 0u, ctx->stream, ea, eb, 0u, op->w, pcols,
+                            prows, xin, xstride, z, zstride, zslice, split_stride, ch_ls, chr);
   };
   const bool projects = lowrank || channel;
   // instances with len > step integrate; those with len == step only record
@@ -1400,7 +1408,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         // with the split tuned, each timed repetition includes the projection
         auto run = [&](int v) {
           if (projects && (tune_split || si == 0)) project(x0, dyn0);
-          vt[v].fn(g, 0, ctx->stream, sp);
+          vt[v].fn(g, 0, ctx->stream, sp, nullptr, nullptr);
         };
         if (projects && !tune_split) project(x0, dyn0);
         for (int v = 0; v < nvar; ++v) {
@@ -1410,7 +1418,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
             if (tune_split) {
               run(v);
             } else {
-              vt[v].fn(g, 0, ctx->stream, sp);
+              vt[v].fn(g, 0, ctx->stream, sp, nullptr, nullptr);
             }
           }
           hipEventRecord(eb, ctx->stream);
@@ -1449,9 +1457,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       const int active = s == 0 ? n_obs : n_dyn;
       if (active == 0) break;
       if (projects && n_dyn > 0) {
-        prof_begin(ctx, TDG_KCLASS_PROJECT);
-        project(xc, n_dyn);
-        prof_end(ctx, TDG_KCLASS_PROJECT);
+        hipEvent_t pa, pb;
+        prof_pair(ctx, TDG_KCLASS_PROJECT, &pa, &pb);
+        project(xc, n_dyn, pa, pb);
       }
       sp.vec = projects ? z : xc;
       sp.vstride = projects ? zstride : xstride;
@@ -1460,9 +1468,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       sp.step = (int)step;
       sp.stage = s;
       sp.obs_slot = slot;
-      prof_begin(ctx, TDG_KCLASS_STAGE);
-      stage_fn(dim3(nk, active), 0, ctx->stream, sp);
-      prof_end(ctx, TDG_KCLASS_STAGE);
+      hipEvent_t sa, sb;
+      prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
+      stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
       std::swap(xc, xn);
     }
     ++slot;
