@@ -291,7 +291,7 @@ class Context:
         P, J, occ (and tr, herm) of shape [B][max nsteps + 1] and rho(T)."""
         fa = field_array(fields)
         batch = len(fa)
-        maxn = max(int(f.nsteps) for f in fa)
+        maxn = max((int(f.nsteps) for f in fa), default=0)
         dev = f"cuda:{self.device}"
         if rho is None:
             rho = torch.empty((batch, model.nk, model.nb, model.nb), dtype=torch.complex128, device=dev)

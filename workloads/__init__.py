@@ -10,6 +10,7 @@ no observables.
 """
 
 from .models import (  # noqa: F401
+    multiband_model,
     HARTREE_EV, FS_AU, BOHR_NM, EFIELD_AU_V_PER_CM,
     Model, mp_grid, dirac_model, tb4_model, load_tb4_table,
 )

@@ -163,3 +163,29 @@ def tb4_model(nk: int, a: float = 6.0, shift: float = 0.5, table: dict | None = 
                              tab["delta_ev"] / HARTREE_EV)
     eps, evec, vel, dip = _bands(hk, dh, 2)
     return Model("tb4", nk, nk, shift, a, 4, 2, kpts, eps, evec, vel, dip, hk)
+
+
+def multiband_model(nk: int, nb: int = 8, nv: int = 4, seed: int = 3, a: float = 6.0, shift: float = 0.5,
+                    delta_ev: float = 3.0, tmin_ev: float = 0.05, tmax_ev: float = 0.2) -> Model:
+    """Seeded random nb-band nearest-neighbour model (edge cases with many
+    bands): H0 = diag(+delta on nb - nv bands, -delta on nv bands), hoppings
+    T_x, T_y with magnitudes U[tmin, tmax] eV and phases U[0, 2 pi) drawn in
+    the order |Tx|, arg Tx, |Ty|, arg Ty from PCG64(seed); the small hoppings
+    keep the nv lowest bands separated from the others."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ts = []
+    for _ in range(2):
+        mag = rng.uniform(tmin_ev, tmax_ev, size=(nb, nb))
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=(nb, nb))
+        ts.append(mag * np.exp(1j * ph) / HARTREE_EV)
+    tx, ty = ts
+    kpts = mp_grid(nk, nk, a, shift)
+    d = delta_ev / HARTREE_EV
+    h0 = np.diag([d] * (nb - nv) + [-d] * nv).astype(np.complex128)
+    ex = np.exp(1j * kpts[:, 0] * a)[:, None, None]
+    ey = np.exp(1j * kpts[:, 1] * a)[:, None, None]
+    hk = h0[None] + tx[None] * ex + tx.conj().T[None] * ex.conj() + ty[None] * ey + ty.conj().T[None] * ey.conj()
+    dhx = 1j * a * (tx[None] * ex - tx.conj().T[None] * ex.conj())
+    dhy = 1j * a * (ty[None] * ey - ty.conj().T[None] * ey.conj())
+    eps, evec, vel, dip = _bands(hk, np.stack([dhx, dhy]), nv)
+    return Model(f"mb{nb}", nk, nk, shift, a, nb, nv, kpts, eps, evec, vel, dip, hk)
