@@ -586,6 +586,132 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma(GemmBf16Args g) {
   }
 }
 
+// ---- BF16 split-precision product, second tiling ---------------------------
+// X is split and expanded once per product into XB (bf16 bits): for column
+// tile ct of 64 instances, plane p (0 = hi, 1 = lo), row c < 128 and real K
+// index kr, XB[((ct * 2 + p) * 128 + c) * ldxb + kr] holds the real expansion
+// of x[k][64 ct + (c % 64)]: rows c < 64 (real parts of the outputs) carry
+// (re, -im) at kr = (2k, 2k + 1), rows c >= 64 (imaginary parts) carry (im, re).
+// Rows are K-contiguous, so a lane's 8 consecutive K are one 16-byte read,
+// and zero from 2 Kc up to ldxb = 2 Kc rounded up to 64.
+constexpr int XB_ROWS = 2 * BNI;
+
+__global__ void __launch_bounds__(256) expand_bf16x2_kernel(const float2* __restrict__ X, int64_t ldx, int Kc,
+                                                            int ncols, unsigned short* __restrict__ XB,
+                                                            int64_t ldxb) {
+  // 32 complex K rows x 64 instances through LDS: read along instances, write along K
+  __shared__ float2 tile[32][BNI + 1];
+  const int ct = blockIdx.y, k0 = blockIdx.x * 32, t = threadIdx.x;
+  for (int i = t; i < 32 * BNI; i += 256) {
+    const int r = i / BNI, b = i % BNI;
+    const int k = k0 + r, bb = ct * BNI + b;
+    tile[r][b] = (k < Kc && bb < ncols) ? X[(int64_t)k * ldx + bb] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  for (int i = t; i < 2 * XB_ROWS * 32; i += 256) {
+    const int kk = i % 32, c = (i / 32) % XB_ROWS, p = i / (32 * XB_ROWS);
+    const float2 v = tile[kk][c % BNI];
+    const unsigned short rh = f2bf(v.x), ih = f2bf(v.y);
+    const unsigned short re = p ? f2bf(v.x - bf2f(rh)) : rh, im = p ? f2bf(v.y - bf2f(ih)) : ih;
+    const unsigned int word = c < BNI ? ((unsigned int)re | ((unsigned int)(im ^ 0x8000u) << 16))
+                                      : ((unsigned int)im | ((unsigned int)re << 16));
+    *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + c) * ldxb + 2 * (k0 + kk)]) = word;
+  }
+}
+
+// 128 rows x 64 instances per block, 16 complex K columns per LDS stage; wave
+// w owns rows 64*(w/2) .. +63 and real columns 64*(w%2) .. +63 as 2 x 2 MFMA
+// accumulators, so each 16-byte fragment read from LDS feeds six products.
+constexpr int BM3 = 128;
+constexpr int BKC3 = 16;
+constexpr int KR3 = 2 * BKC3;
+constexpr int LPAD3 = 8;
+
+__global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, const unsigned short* __restrict__ XB,
+                                                             int64_t ldxb) {
+  __shared__ __align__(16) unsigned short As[2][BM3][KR3 + LPAD3];
+  __shared__ __align__(16) unsigned short Xs[2][XB_ROWS][KR3 + LPAD3];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.x * BM3, ct = blockIdx.y, b0 = ct * BNI, s = blockIdx.z;
+  const int kc_begin = s * g.kslice;
+  const int kc_end = min(g.Kc, kc_begin + g.kslice);
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  floatx16 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC3) {
+    const int kr0 = 2 * kc0, kr_end = 2 * kc_end;
+    // A: 2 planes x 128 rows x 4 chunks of 8 bf16; zero past the slice's K
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int i = t + 256 * it;
+      const int q = i & 3, row = (i >> 2) & (BM3 - 1), p = i >> 9;
+      const int kr = kr0 + 8 * q, gi = m0 + row;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gi < g.M) {
+        const unsigned short* src = (p ? g.Alo : g.Ahi) + (int64_t)gi * 2 * g.lda + kr;
+        if (kr + 8 <= kr_end) {
+          v = *reinterpret_cast<const uint4*>(src);
+        } else if (kr < kr_end) {
+          unsigned short hb[8];
+          for (int e = 0; e < 8; ++e) hb[e] = kr + e < kr_end ? src[e] : (unsigned short)0;
+          v = *reinterpret_cast<uint4*>(hb);
+        }
+      }
+      *reinterpret_cast<uint4*>(&As[p][row][8 * q]) = v;
+    }
+    // X: 2 planes x 128 rows x 4 chunks; the padded rows of XB cover every stage
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int i = t + 256 * it;
+      const int q = i & 3, row = (i >> 2) & (XB_ROWS - 1), p = i >> 9;
+      const uint4 v =
+          *reinterpret_cast<const uint4*>(XB + ((int64_t)(ct * 2 + p) * XB_ROWS + row) * ldxb + kr0 + 8 * q);
+      *reinterpret_cast<uint4*>(&Xs[p][row][8 * q]) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KR3; ks += 16) {
+      const int kb = ks + 8 * (lane >> 5);
+      bf16x8 ah[2], al[2], xh[2], xl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ah[i] = *reinterpret_cast<const bf16x8*>(&As[0][wr + 32 * i + (lane & 31)][kb]);
+        al[i] = *reinterpret_cast<const bf16x8*>(&As[1][wr + 32 * i + (lane & 31)][kb]);
+        xh[i] = *reinterpret_cast<const bf16x8*>(&Xs[0][wc + 32 * i + (lane & 31)][kb]);
+        xl[i] = *reinterpret_cast<const bf16x8*>(&Xs[1][wc + 32 * i + (lane & 31)][kb]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], xh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], xl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], xh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+
+  // real column wc + 32 j + lane % 32: instance 32 j + lane % 32 of the tile, part wc / 64
+  float* Yf = reinterpret_cast<float*>(g.Y + s * g.y_slice_stride);
+  const int part = wc >> 6;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = m0 + wr + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (row >= g.M) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int b = b0 + 32 * j + (lane & 31);
+        if (b < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b) + part] = acc[i][j][r];
+      }
+    }
+}
+
 // dst (TDG_BF16X2, [rows][ld_dst]) <- src complex (float or double, [rows][ld_src]);
 // columns cols .. ld_dst-1 of dst are zero-filled.
 template <typename S>
@@ -612,8 +738,15 @@ __global__ void split_bf16x2_kernel(const S* __restrict__ src, int64_t ld_src, i
 
 namespace tdg {
 
+size_t cgemm_bf16x2_work_bytes(int Kc, int ncols) {
+  const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
+  return (size_t)((ncols + BNI - 1) / BNI) * 2 * XB_ROWS * ldxb * sizeof(unsigned short);
+}
+
+// variant 0: 64-row tiles, X split while staged; variant 1: X split and
+// expanded once into `work` (cgemm_bf16x2_work_bytes), 128-row tiles.
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
-                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice) {
+                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant, void* work) {
   GemmBf16Args g;
   g.Ahi = (const unsigned short*)A;
   g.Alo = (const unsigned short*)A + (int64_t)M * lda * 2;
@@ -628,6 +761,15 @@ void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc,
   g.ncols = ncols;
   g.kslice = kslice;
   const int splits = (Kc + kslice - 1) / kslice;
+  if (variant == 1 && work) {
+    const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
+    const int tiles = (ncols + BNI - 1) / BNI;
+    hipLaunchKernelGGL(expand_bf16x2_kernel, dim3((unsigned)(ldxb / 64), (unsigned)tiles), dim3(256), 0, stream,
+                       (const float2*)X, ldx, Kc, ncols, (unsigned short*)work, ldxb);
+    const dim3 grid((M + BM3 - 1) / BM3, tiles, splits);
+    hipLaunchKernelGGL(cgemm_bf16x2_mfma_v2, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
+    return;
+  }
   const dim3 grid((M + BM - 1) / BM, (ncols + BNI - 1) / BNI, splits);
   hipLaunchKernelGGL(cgemm_bf16x2_mfma, grid, dim3(256), 0, stream, g);
 }

@@ -39,6 +39,7 @@ enum WsSlot {
   WS_RSVD_T,     // randomized compression: Q^H K_off Q, c128 [l][l], and Householder scalars
   WS_ADJ,        // adjoint propagation: checkpoints, segment states, stage data, cotangents
   WS_STEP,       // batched path: step counter read by graph replays
+  WS_XB,         // batched BF16X2 path: X split into bf16 planes once per product
   WS_COUNT
 };
 
@@ -99,8 +100,11 @@ void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, co
                int kslice, int variant);
 // BF16 split-precision product: A in TDG_BF16X2 storage (hi plane, then lo
 // plane, [M][lda], lda % 4 == 0), X complex64 [Kc][ldx] (gemm.hip).
+// variant 0: 64-row tiles splitting X while staged; 1: X split once into
+// `work` (cgemm_bf16x2_work_bytes bytes), 128-row tiles.
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
-                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice);
+                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant, void* work);
+size_t cgemm_bf16x2_work_bytes(int Kc, int ncols);
 // dst (TDG_BF16X2 [rows][ld_dst]) <- complex src [rows][ld_src]; columns >= cols zero.
 void split_bf16x2(hipStream_t stream, const void* src, int src_is_double, int64_t ld_src, int64_t rows, int64_t cols,
                   void* dst, int64_t ld_dst);

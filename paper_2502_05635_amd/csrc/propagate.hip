@@ -1170,16 +1170,20 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     // products only write Y / Z, which the loop below recomputes
     int gv_main = 0, gv_proj = 0;
     const int n_dyn0 = count_gt(0);
-    if (!bf16 && n_dyn0 > 0) {
+    // BF16X2: the second tiling needs X split once into a bf16 work array
+    void* xbw = nullptr;
+    if (bf16) TDG_TRY(ws_reserve(ctx, WS_XB, cgemm_bf16x2_work_bytes((int)n, batch), &xbw));
+    const int ntilings = bf16 ? 2 : 3;
+    if (n_dyn0 > 0) {
       auto pick = [&](const char* what, int64_t M, int64_t Kc, int64_t ks, const std::function<void(int)>& run,
                       int* out) -> int {
         if (ctx->gemm_variant >= 0) {
-          *out = ctx->gemm_variant;
+          *out = std::min(ctx->gemm_variant, ntilings - 1);
           return TDG_OK;
         }
         char key[160];
-        snprintf(key, sizeof(key), "gemm/%s/%lld/%lld/%d/%lld", what, (long long)M, (long long)Kc, n_dyn0,
-                 (long long)ks);
+        snprintf(key, sizeof(key), "gemm/%s/%s/%lld/%lld/%d/%lld", bf16 ? "bf16x2" : "f32", what, (long long)M,
+                 (long long)Kc, n_dyn0, (long long)ks);
         for (auto& kv : ctx->tuned)
           if (kv.first == key) {
             *out = kv.second;
@@ -1190,7 +1194,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         TDG_TRY(hip_check(ctx, hipEventCreate(&e1), "event"));
         float best = 0.f;
         int bestv = 0;
-        for (int v = 0; v < 3; ++v) {
+        for (int v = 0; v < ntilings; ++v) {
           run(v);
           hipEventRecord(e0, ctx->stream);
           run(v);
@@ -1210,28 +1214,40 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         *out = bestv;
         return TDG_OK;
       };
+      const int64_t ld_us0 = bf16 ? (op->rank + 3) / 4 * 4 : op->rank;
       if (!lowrank) {
         TDG_TRY(pick("dense", n, n, ks_main, [&](int v) {
-          cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, x0, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn0,
-                    (int)ks_main, v);
+          if (bf16)
+            cgemm_bf16x2(ctx->stream, op->K, op->ld, (int)n, (int)n, x0, xstride, Ybuf, ldy, n * ldy, n_dyn0,
+                         (int)ks_main, v, xbw);
+          else
+            cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, x0, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn0,
+                      (int)ks_main, v);
         }, &gv_main));
       } else {
         TDG_TRY(pick("project", op->rank, n, ks_proj, [&](int v) {
-          cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, x0, xstride, 1, 0, Zbuf, ldy, op->rank * ldy,
-                    n_dyn0, (int)ks_proj, v);
+          if (bf16)
+            cgemm_bf16x2(ctx->stream, op->w, n, (int)op->rank, (int)n, x0, xstride, Zbuf, ldy, op->rank * ldy,
+                         n_dyn0, (int)ks_proj, v, xbw);
+          else
+            cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, x0, xstride, 1, 0, Zbuf, ldy, op->rank * ldy,
+                      n_dyn0, (int)ks_proj, v);
         }, &gv_proj));
         sum_slices_c64(ctx->stream, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
         TDG_TRY(pick("expand", n, op->rank, ks_main, [&](int v) {
-          cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy,
-                    n_dyn0, (int)ks_main, v);
+          if (bf16)
+            cgemm_bf16x2(ctx->stream, op->us, ld_us0, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn0,
+                         (int)ks_main, v, xbw);
+          else
+            cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy,
+                      n_dyn0, (int)ks_main, v);
         }, &gv_main));
       }
     }
     ctx->last_variant = std::string(lowrank ? "batched_mfma_lowrank_" : "batched_mfma_dense_") +
                         (bf16 ? "bf16x2" : "f32");
-    if (!bf16)
-      ctx->last_variant += lowrank ? " (tilings " + std::to_string(gv_proj) + "/" + std::to_string(gv_main) + ")"
-                                   : " (tiling " + std::to_string(gv_main) + ")";
+    ctx->last_variant += lowrank ? " (tilings " + std::to_string(gv_proj) + "/" + std::to_string(gv_main) + ")"
+                                 : " (tiling " + std::to_string(gv_main) + ")";
     if (ctx->graphs && !ctx->prof) ctx->last_variant += " graphs";
     tdg_obs ob = *obs;
     void* dstep = nullptr;
@@ -1254,7 +1270,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
           const int64_t ld_us = bf16 ? (op->rank + 3) / 4 * 4 : op->rank;
           if (!lowrank) {
             if (bf16)
-              cgemm_bf16x2(st, op->K, op->ld, (int)n, (int)n, xc, xstride, Ybuf, ldy, n * ldy, n_dyn, (int)ks_main);
+              cgemm_bf16x2(st, op->K, op->ld, (int)n, (int)n, xc, xstride, Ybuf, ldy, n * ldy, n_dyn, (int)ks_main,
+                           gv_main, xbw);
             else
               cgemm_f32(st, op->K, op->ld, (int)n, (int)n, xc, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
                         (int)ks_main, gv_main);
@@ -1262,14 +1279,14 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
             // projection split over K, summed once in fixed order, then expansion
             if (bf16)
               cgemm_bf16x2(st, op->w, n, (int)op->rank, (int)n, xc, xstride, Zbuf, ldy, op->rank * ldy, n_dyn,
-                           (int)ks_proj);
+                           (int)ks_proj, gv_proj, xbw);
             else
               cgemm_f32(st, op->w, n, (int)op->rank, (int)n, xc, xstride, 1, 0, Zbuf, ldy, op->rank * ldy, n_dyn,
                         (int)ks_proj, gv_proj);
             sum_slices_c64(st, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
             if (bf16)
               cgemm_bf16x2(st, op->us, ld_us, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
-                           (int)ks_main);
+                           (int)ks_main, gv_main, xbw);
             else
               cgemm_f32(st, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
                         (int)ks_main, gv_main);
