@@ -19,6 +19,8 @@ Modules, each following the paper's definitions step by step:
   spectra.py     absorption and high-harmonic spectra from time series
   adjoint.py     reverse-mode derivative of the discrete RK4 propagation
                  (not in the paper; the exact gradient of the scheme above)
+  intraband.py   intraband part of the length-gauge field coupling: covariant
+                 k-derivative with parallel-transport links (Eq. tdagw, App. A.1)
 """
 
 from .kernel import (  # noqa: F401
@@ -33,3 +35,4 @@ from .observables import observables  # noqa: F401
 from .bse import linear_operator, linear_response  # noqa: F401
 from .spectra import absorption, hhg  # noqa: F401
 from .adjoint import propagate_adjoint, harmonic_loss, field_param_derivs  # noqa: F401
+from .intraband import transport_links, covariant_derivative, polar_unitary, grid_spacing  # noqa: F401

@@ -8,7 +8,9 @@ along the field direction e and normalised per k point as the occupation is:
   P = (1/N_k) sum_k Tr(e.d_k rho_k),  J = (1/N_k) sum_k Tr(e.v_k rho_k),
 real parts reported.  Two diagnostics ride along: the largest deviation of a
 per-k trace from the number of valence bands, and the largest element of
-rho_k - rho_k^H.
+rho_k - rho_k^H.  With the intraband (k-derivative) field coupling charge
+moves between k points, so the trace diagnostic is then the deviation of the
+grid average, |(1/N_k) sum_k Tr rho_k - N_v|.
 """
 
 from __future__ import annotations
@@ -21,7 +23,7 @@ def _trace_prod(a: np.ndarray, rho: np.ndarray) -> complex:
     return complex(np.einsum("knm,kmn->", a, rho))
 
 
-def observables(model, rho: np.ndarray, ex: float, ey: float) -> dict:
+def observables(model, rho: np.ndarray, ex: float, ey: float, grid_trace: bool = False) -> dict:
     nk = model.nk
     d = ex * model.dip[0] + ey * model.dip[1]
     v = ex * model.vel[0] + ey * model.vel[1]
@@ -30,6 +32,6 @@ def observables(model, rho: np.ndarray, ex: float, ey: float) -> dict:
         "P": _trace_prod(d, rho).real / nk,
         "J": _trace_prod(v, rho).real / nk,
         "occ": float(np.sum(rho[:, model.nv, model.nv].real)) / nk,
-        "tr": float(np.max(np.abs(tr - model.nv))),
+        "tr": float(abs(np.mean(tr) - model.nv)) if grid_trace else float(np.max(np.abs(tr - model.nv))),
         "herm": float(np.max(np.abs(rho - rho.conj().transpose(0, 2, 1)))),
     }

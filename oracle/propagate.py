@@ -11,12 +11,15 @@ Readings where the paper is silent:
     dSigma_vc = conj(dSigma_cv), dSigma_cc = dSigma_vv = 0;
   * the integrator, which the paper does not name, is classical RK4 with the
     field evaluated at t_n, t_n + dt/2 (twice) and t_n + dt; t_n = n dt.
+With transport links (intraband.py) the field also acts through the
+intraband part of r: d rho_k/dt gains -E(t) e_hat . (rho)_{;k}.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
+from .intraband import covariant_derivative
 from .kernel import pair_table
 from .observables import observables
 
@@ -84,8 +87,10 @@ def rho_equilibrium(model) -> np.ndarray:
 
 
 def propagate(model, op, block: str, fields, dt: float, instance: int = 0,
-              nsteps: int | None = None, rho0: np.ndarray | None = None) -> dict:
+              nsteps: int | None = None, rho0: np.ndarray | None = None, links: np.ndarray | None = None) -> dict:
     """Integrate one field instance; observables at t_0 .. t_nsteps.
+    links: transport links of intraband.transport_links, or None for the
+    k-local field coupling only.
 
     Returns dict(P, J, occ, tr, herm: [nsteps + 1] arrays, rho: final state).
     """
@@ -111,14 +116,18 @@ def propagate(model, op, block: str, fields, dt: float, instance: int = 0,
         return ds
 
     def rhs(t, rho):
-        h = h0 + delta_sigma(rho - rho_eq) - field_at(t, fields, b) * dfield
-        return minus_i_commutator(h, rho)
+        e = field_at(t, fields, b)
+        h = h0 + delta_sigma(rho - rho_eq) - e * dfield
+        f = minus_i_commutator(h, rho)
+        if links is not None:
+            f = f - e * covariant_derivative(model, links, rho, ex, ey)
+        return f
 
     rho = rho_eq.copy() if rho0 is None else np.array(rho0, dtype=np.complex128)
     out = {key: np.zeros(nsteps + 1) for key in ("P", "J", "occ", "tr", "herm")}
 
     def record(n, r):
-        o = observables(model, r, ex, ey)
+        o = observables(model, r, ex, ey, grid_trace=links is not None)
         for key in out:
             out[key][n] = o[key]
 

@@ -19,6 +19,7 @@ OBSERVABLES = importlib.import_module("oracle.observables")
 PROPAGATE = importlib.import_module("oracle.propagate")
 BSE = importlib.import_module("oracle.bse")
 ADJOINT = importlib.import_module("oracle.adjoint")
+INTRABAND = importlib.import_module("oracle.intraband")
 
 
 @pytest.fixture(scope="module")
@@ -92,6 +93,19 @@ def _channel_wrong_source(self, x):
     return y.reshape(-1)
 
 
+def _backward_link_not_daggered(model, links, y, ex, ey):
+    out = np.zeros_like(y)
+    for a, e in ((0, ex), (1, ey)):
+        fwd = INTRABAND._neighbour(model, a, +1)
+        bwd = INTRABAND._neighbour(model, a, -1)
+        lf, lb = links[a], links[a][bwd]
+        diff = lf @ y[fwd] @ lf.conj().transpose(0, 2, 1) - lb @ y[bwd] @ lb.conj().transpose(0, 2, 1)
+        out += (e / (2.0 * INTRABAND.grid_spacing(model, a))) * diff
+    return out
+
+
+INTRABAND._real_neighbour = INTRABAND._neighbour
+INTRABAND._real_covariant_derivative = INTRABAND.covariant_derivative
 ADJOINT._real_pull_commutator = ADJOINT.pull_commutator
 ADJOINT._real_field_param_derivs = ADJOINT.field_param_derivs
 
@@ -115,6 +129,21 @@ CASES = {
     "adjoint: omega derivative sign": (ADJOINT, "field_param_derivs", _omega_derivative_sign, "adjoint_fields"),
     "adjoint: occupation cotangent on the wrong band": (ADJOINT, "observable_cotangent", _cotangent_wrong_band,
                                                         "adjoint_fields"),
+    "intraband: backward link not conjugate-transposed": (PROPAGATE, "covariant_derivative",
+                                                          _backward_link_not_daggered, "intra_rotated"),
+    "intraband: drift sign flipped": (PROPAGATE, "covariant_derivative",
+                                      lambda *a: -INTRABAND._real_covariant_derivative(*a), "intra_fft"),
+    "intraband: grid spacing halved": (INTRABAND, "grid_spacing",
+                                       lambda model, axis: np.pi / ((model.nk1, model.nk2)[axis] * model.a),
+                                       "intra_fft"),
+    "intraband: axes swapped": (INTRABAND, "_neighbour",
+                                lambda model, axis, step: INTRABAND._real_neighbour(model, 1 - axis, step),
+                                "intra_fft"),
+    "intraband: raw overlap instead of its polar factor": (INTRABAND, "polar_unitary", lambda b: b.copy(),
+                                                           "intra_charge"),
+    "intraband: polar factor conjugate-transposed": (INTRABAND, "polar_unitary",
+                                                     lambda b: np.linalg.svd(b)[2].conj().T
+                                                     @ np.linalg.svd(b)[0].conj().T, "intra_rotated"),
 }
 
 
@@ -132,6 +161,14 @@ def _run_pin(name, small):
         pins.test_flat_band_kernel_is_circulant()
     elif name == "channel_full_rank":
         pins.test_channelwise_full_rank_equals_dense(t4, O.build_kernel(t4, R0_STABLE, "eh"))
+    elif name.startswith("intra_"):
+        import test_oracle_intraband as intra
+        if name == "intra_fft":
+            intra.test_drift_matches_fft_closed_form(0.8, 0.6)
+        elif name == "intra_rotated":
+            intra.test_rotated_degenerate_bases_give_the_same_dynamics()
+        else:
+            intra.test_total_charge_and_equilibrium_conserved(tb4_model(6, A, 0.5))
     elif name in ("adjoint_fields", "adjoint_factors"):
         import test_oracle_adjoint as adj
         lr = O.LowRankOp.from_factors(O.compress(O.build_kernel(t4, R0_STABLE, "eh"), "rank", 12))

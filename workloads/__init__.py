@@ -10,7 +10,7 @@ no observables.
 """
 
 from .models import (  # noqa: F401
-    multiband_model,
+    multiband_model, flat_band_model, diagonal_band_model,
     HARTREE_EV, FS_AU, BOHR_NM, EFIELD_AU_V_PER_CM,
     Model, mp_grid, dirac_model, tb4_model, load_tb4_table,
 )

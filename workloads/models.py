@@ -189,3 +189,72 @@ def multiband_model(nk: int, nb: int = 8, nv: int = 4, seed: int = 3, a: float =
     dhy = 1j * a * (ty[None] * ey - ty.conj().T[None] * ey.conj())
     eps, evec, vel, dip = _bands(hk, np.stack([dhx, dhy]), nv)
     return Model(f"mb{nb}", nk, nk, shift, a, nb, nv, kpts, eps, evec, vel, dip, hk)
+
+
+def _haar_unitary(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Haar-random n x n unitary (QR of a complex Gaussian, phases of R fixed)."""
+    z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r)
+    return q * (d / np.abs(d))[None, :]
+
+
+def flat_band_model(nk1: int, nk2: int, nb: int = 4, nv: int = 2, gap_ev: float = 2.0, a: float = 6.0,
+                    shift: float = 0.5, dip_seed: int | None = None, dip_bohr: float = 1.0,
+                    gauge_seed: int | None = None) -> Model:
+    """Flat degenerate bands on an nk1 x nk2 grid: nv valence bands at -gap/2 and
+    nb - nv conduction bands at +gap/2, H(k) constant, velocity zero.
+
+    dip_seed draws a constant interband dipole d0 in the orbital basis
+    (Hermitian, nonzero only between the two subspaces, entries of magnitude
+    U[0.2, 1] dip_bohr, phases U[0, 2 pi)); None gives d0 = 0.  gauge_seed
+    draws, per k, Haar-random unitaries R_v(k) and R_c(k) within the two
+    degenerate subspaces and uses them as the Bloch states, evec_k =
+    blockdiag(R_v, R_c), with dip_k = evec_k^H d0 evec_k; None keeps evec = I.
+    Draw order (PCG64): d0 magnitudes, d0 phases; then per k R_v, R_c."""
+    nk = nk1 * nk2
+    g = gap_ev / HARTREE_EV
+    kpts = mp_grid(nk1, nk2, a, shift)
+    eps = np.tile(np.array([-0.5 * g] * nv + [0.5 * g] * (nb - nv)), (nk, 1))
+    hk = np.zeros((nk, nb, nb), dtype=np.complex128)
+    hk[:, np.arange(nb), np.arange(nb)] = eps
+    d0 = np.zeros((2, nb, nb), dtype=np.complex128)
+    if dip_seed is not None:
+        rng = np.random.Generator(np.random.PCG64(dip_seed))
+        mag = rng.uniform(0.2, 1.0, size=(2, nv, nb - nv)) * dip_bohr
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=(2, nv, nb - nv))
+        d0[:, :nv, nv:] = mag * np.exp(1j * ph)
+        d0[:, nv:, :nv] = d0[:, :nv, nv:].conj().transpose(0, 2, 1)
+    evec = np.broadcast_to(np.eye(nb, dtype=np.complex128), (nk, nb, nb)).copy()
+    if gauge_seed is not None:
+        rng = np.random.Generator(np.random.PCG64(gauge_seed))
+        for k in range(nk):
+            evec[k, :nv, :nv] = _haar_unitary(rng, nv)
+            evec[k, nv:, nv:] = _haar_unitary(rng, nb - nv)
+    dip = np.einsum("kan,xab,kbm->xknm", evec.conj(), d0, evec)
+    vel = np.zeros_like(dip)
+    return Model(f"flat{nb}", nk1, nk2, shift, a, nb, nv, kpts, eps, evec, vel, dip, hk)
+
+
+def diagonal_band_model(nk1: int, nk2: int, nb: int = 4, nv: int = 2, gap_ev: float = 2.0,
+                        width_ev: float = 0.3, a: float = 6.0, shift: float = 0.5) -> Model:
+    """Dispersive bands with k-independent Bloch states (evec = I, dipole 0):
+    eps_n(k) = c_n + w_n (cos kx a + 0.5 cos ky a), centres 0.2 eV apart within
+    each subspace (valence below -gap/2, conduction above +gap/2),
+    w_n = width (1 + 0.2 n), so the bands never cross; velocity
+    v^a_nn = d eps_n / dk_a (diagonal)."""
+    nk = nk1 * nk2
+    kpts = mp_grid(nk1, nk2, a, shift)
+    g, w, s = gap_ev / HARTREE_EV, width_ev / HARTREE_EV, 0.2 / HARTREE_EV
+    cen = np.array([-0.5 * g - (nv - 1 - n) * s for n in range(nv)] + [0.5 * g + n * s for n in range(nb - nv)])
+    wid = np.array([w * (1.0 + 0.2 * n) for n in range(nb)])
+    cx, cy = np.cos(kpts[:, 0] * a), np.cos(kpts[:, 1] * a)
+    sx, sy = np.sin(kpts[:, 0] * a), np.sin(kpts[:, 1] * a)
+    eps = cen[None, :] + wid[None, :] * (cx + 0.5 * cy)[:, None]
+    vel = np.zeros((2, nk, nb, nb), dtype=np.complex128)
+    vel[0][:, np.arange(nb), np.arange(nb)] = -a * wid[None, :] * sx[:, None]
+    vel[1][:, np.arange(nb), np.arange(nb)] = -0.5 * a * wid[None, :] * sy[:, None]
+    hk = np.zeros((nk, nb, nb), dtype=np.complex128)
+    hk[:, np.arange(nb), np.arange(nb)] = eps
+    evec = np.broadcast_to(np.eye(nb, dtype=np.complex128), (nk, nb, nb)).copy()
+    return Model(f"diag{nb}", nk1, nk2, shift, a, nb, nv, kpts, eps, evec, vel, np.zeros_like(vel), hk)
