@@ -80,10 +80,14 @@ const char* tdg_last_error(tdg_ctx ctx);
 /* Band-structure input: quasiparticle energies, Bloch states, position and
  * velocity operators (paper Appendix A.1: H^QP and the dipole matrix r in a
  * smooth gauge; the velocity operator of the HHG current).  Device arrays:
- *   eps  double [nk][nb]          band energies (Ha), ascending per k
- *   evec c128   [nk][nb][nb]      evec[k][alpha][n] = <alpha | n k>
- *   dip  c128   [2][nk][nb][nb]   d^a_{nm k} (bohr), a = x, y
- *   vel  c128   [2][nk][nb][nb]   v^a_{nm k} (Ha bohr)
+ *   eps   double [nk][nb]          band energies (Ha), ascending per k
+ *   evec  c128   [nk][nb][nb]      evec[k][alpha][n] = <alpha | n k>
+ *   dip   c128   [2][nk][nb][nb]   interband position d^a_{nm k} (bohr), a = x, y
+ *   vel   c128   [2][nk][nb][nb]   v^a_{nm k} (Ha bohr)
+ *   links c128   [2][nk][nb][nb]   optional (NULL = none): parallel-transport links
+ *                                  from tdg_links_build.  When set, the intraband
+ *                                  part of r acts too: d rho_k/dt gains
+ *                                  -E(t) e.(rho)_{;k} (see tdg_links_build).
  * nk = nk1*nk2 points of the uniform grid k = (2pi/a)((i + shift)/N - 1/2);
  * the lowest nv bands are occupied in rho_eq. */
 typedef struct {
@@ -93,7 +97,23 @@ typedef struct {
   const void* evec;
   const void* dip;
   const void* vel;
+  const void* links;
 } tdg_model;
+
+/* Parallel-transport links for the intraband part of the position operator
+ * (paper Eq. tdagw in the length gauge, r in the smooth gauge of Appendix
+ * A.1; the paper gives no discretisation, this is the library's reading).
+ * [r_intra, rho]_k = i (rho)_{;k}, discretised on the periodic grid as
+ *   (rho)_{;a}(k) = [L_a(k) rho(k+b_a) L_a(k)^H - L_a(k-b_a)^H rho(k-b_a) L_a(k-b_a)] / (2|b_a|),
+ * |b_a| = 2pi/(N_a a), a = x (index i1), y (index i2).  L_a(k) is block
+ * diagonal: on the valence block (bands < nv) and on the conduction block it
+ * is the unitary polar factor of that block of M = evec_k^H evec_{k+b_a}
+ * (M_nm = <n k|m k+b_a>); zero between the blocks.  Writes links, device c128
+ * [2][nk][nb][nb] row-major, caller-owned, 16-byte aligned (model->links is
+ * ignored).  Synchronises the stream; TDG_E_NUMERIC names the first (axis, k)
+ * whose block overlap is singular (neighbouring subspaces orthogonal: the
+ * grid is too coarse for a transport) or whose polar iteration failed. */
+int tdg_links_build(tdg_ctx ctx, const tdg_model* model, void* links);
 
 /* Screened interaction for the kernel build: 2D Rytova-Keldysh
  * W(q) = 2pi / (q (1 + r0 q)); at q = 0 the average of W over the grid cell
@@ -258,7 +278,9 @@ typedef struct {
  *   P    (1/nk) sum_k Re Tr(e.d_k rho_k)        polarisation along e
  *   J    (1/nk) sum_k Re Tr(e.v_k rho_k)        current along e
  *   occ  (1/nk) sum_k Re rho_{c1 c1 k}          first conduction band
- *   tr   max_k |Tr rho_k - nv|                  diagnostic (may be NULL)
+ *   tr   max_k |Tr rho_k - nv|                  diagnostic (may be NULL); with
+ *        model links, |(1/nk) sum_k Tr rho_k - nv| (the drift moves charge
+ *        between k points, only the total is conserved)
  *   herm max_k max_nm |rho_nm - conj rho_mn|    diagnostic (may be NULL) */
 typedef struct {
   double* P;
@@ -309,9 +331,10 @@ typedef struct {
  * rho_eq) keeping rho every checkpoint_every steps, then pulls the loss back
  * step by step, recomputing each segment from its checkpoint.  FP64 only:
  * op->dtype must be TDG_C128 (dense or low rank).  Every instance must have
- * the same nsteps.  Device workspace about (nsteps / M + M + 12) states plus
- * 4 (M for low rank) x 2 x n x batch complex128 values, held by the context.
- * Synchronises the stream. */
+ * the same nsteps.  With model->links the intraband term is differentiated
+ * too (its covariant difference is anti-self-adjoint).  Device workspace about
+ * (nsteps / M + M + 15) states plus 4 (M for low rank) x 2 x n x batch
+ * complex128 values, held by the context.  Synchronises the stream. */
 int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
                           const tdg_field* fields, int32_t batch, double dt, const void* rho0,
                           int32_t checkpoint_every, const tdg_obs_grad* g, tdg_grads* out);

@@ -15,6 +15,10 @@ and a cotangent g of f, the pullback is
   dL/dE(t) = Re sum conj(g) (i [D, y]),
 and, for dSigma = K_diag o x + S (V^H x) with x = gather(y - rho_eq),
   dL/dS += sbar (V^H x)^H,  dL/dV^H += (S^H sbar) x^H.
+With the intraband term of intraband.py, f gains -E(t) D(y), D = e_hat.(.)_{;k};
+D is anti-self-adjoint for Re sum conj(a) b (the transport to k + b and back
+to k - b are each other's adjoints, the central difference swaps them), so
+  ybar += E(t) D(g),  dL/dE(t) += -Re sum conj(g) D(y).
 The RK4 step rho' = rho + dt/6 (k1 + 2 k2 + 2 k3 + k4), k_s = f(t_s, y_s),
 y_1 = rho, y_2 = rho + dt/2 k1, y_3 = rho + dt/2 k2, y_4 = rho + dt k3, is
 pulled back from stage 4 to stage 1.  The pulse parameters enter through
@@ -25,6 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .intraband import covariant_derivative
 from .kernel import pair_table
 from .propagate import LowRankOp, field_at, minus_i_commutator, rho_equilibrium
 
@@ -62,8 +67,10 @@ def observable_cotangent(model, ex: float, ey: float, gp: float, gj: float, gocc
 
 
 def propagate_adjoint(model, op, block: str, fields, dt: float, gP=None, gJ=None, gocc=None,
-                      instance: int = 0, nsteps: int | None = None, rho0: np.ndarray | None = None) -> dict:
-    """Gradient of L = sum_n gP_n P_n + gJ_n J_n + gocc_n occ_n for one instance.
+                      instance: int = 0, nsteps: int | None = None, rho0: np.ndarray | None = None,
+                      links: np.ndarray | None = None) -> dict:
+    """Gradient of L = sum_n gP_n P_n + gJ_n J_n + gocc_n occ_n for one instance
+    (links: the intraband term of propagate.propagate, or None).
 
     Returns dict(dE [nsteps][4] (dL/dE at the four stage times of each step),
     dfield [4] (dL/d e0, omega, tau, t0), drho0, and for a LowRankOp dus, dvh).
@@ -100,7 +107,10 @@ def propagate_adjoint(model, op, block: str, fields, dt: float, gP=None, gJ=None
         return h0 + delta_sigma(gather(y - rho_eq)) - field_at(t, fields, b) * dmat
 
     def rhs(t, y):
-        return minus_i_commutator(hamiltonian(t, y), y)
+        f = minus_i_commutator(hamiltonian(t, y), y)
+        if links is not None:
+            f = f - field_at(t, fields, b) * covariant_derivative(model, links, y, ex, ey)
+        return f
 
     def apply_adjoint(sbar):
         if lowrank:
@@ -122,6 +132,10 @@ def propagate_adjoint(model, op, block: str, fields, dt: float, gP=None, gJ=None
         xbar = apply_adjoint(sbar).reshape(model.nk, len(pairs))
         ybar[:, pa, pb] += xbar
         de = pull_field(dmat, y, g)
+        if links is not None:
+            e = field_at(t, fields, b)
+            ybar += e * covariant_derivative(model, links, g, ex, ey)
+            de -= float(np.sum((g.conj() * covariant_derivative(model, links, y, ex, ey)).real))
         grads["dE"][n, s] = de
         grads["dfield"] += de * field_param_derivs(t, fields, b)
         if lowrank:

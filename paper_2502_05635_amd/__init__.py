@@ -9,6 +9,7 @@ fallback; loading fails loudly when the library is missing.
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import os
 from dataclasses import dataclass
 
@@ -95,6 +96,7 @@ class DeviceModel:
     evec: torch.Tensor
     dip: torch.Tensor
     vel: torch.Tensor
+    links: torch.Tensor | None = None   # [2][nk][nb][nb] from Context.links_build: intraband term on
 
     @staticmethod
     def from_model(m, device="cuda") -> "DeviceModel":
@@ -109,7 +111,12 @@ class DeviceModel:
 
     def struct(self) -> abi.Model:
         return abi.Model(self.nk1, self.nk2, self.nb, self.nv, self.shift, self.a,
-                         self.eps.data_ptr(), self.evec.data_ptr(), self.dip.data_ptr(), self.vel.data_ptr())
+                         self.eps.data_ptr(), self.evec.data_ptr(), self.dip.data_ptr(), self.vel.data_ptr(),
+                         self.links.data_ptr() if self.links is not None else None)
+
+    def with_links(self, links: torch.Tensor | None) -> "DeviceModel":
+        """The same model with the intraband term switched on (links) or off (None)."""
+        return dataclasses.replace(self, links=links)
 
 
 @dataclass
@@ -171,6 +178,14 @@ class Context:
         ms = model.struct()
         self._check(self._lib.tdg_kernel_dim(C.byref(ms), _block(block), C.byref(n)))
         return n.value
+
+    def links_build(self, model: DeviceModel) -> torch.Tensor:
+        """Parallel-transport links [2][nk][nb][nb] complex128 of the model's
+        Bloch states (tdg_links_build); pass them with model.with_links()."""
+        out = torch.empty((2, model.nk, model.nb, model.nb), dtype=torch.complex128, device=f"cuda:{self.device}")
+        ms = model.struct()
+        self._check(self._lib.tdg_links_build(self.h, C.byref(ms), _ptr(out)))
+        return out
 
     def kernel_build(self, model: DeviceModel, r0: float, block: str, dtype: str = "c128",
                      nquad: int = 64, out: torch.Tensor | None = None):

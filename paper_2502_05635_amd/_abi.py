@@ -36,7 +36,7 @@ P = C.c_void_p
 class Model(C.Structure):
     _fields_ = [("nk1", C.c_int32), ("nk2", C.c_int32), ("nb", C.c_int32), ("nv", C.c_int32),
                 ("shift", C.c_double), ("a_bohr", C.c_double),
-                ("eps", P), ("evec", P), ("dip", P), ("vel", P)]
+                ("eps", P), ("evec", P), ("dip", P), ("vel", P), ("links", P)]
 
 
 class Coulomb(C.Structure):
@@ -88,6 +88,7 @@ SIGNATURES = {
     "tdg_set_stream": ([P, P], C.c_int),
     "tdg_last_error": ([P], C.c_char_p),
     "tdg_kernel_dim": ([C.POINTER(Model), C.c_int32, C.POINTER(C.c_int64)], C.c_int),
+    "tdg_links_build": ([P, C.POINTER(Model), P], C.c_int),
     "tdg_kernel_build": ([P, C.POINTER(Model), C.POINTER(Coulomb), C.c_int32, P, C.c_int64], C.c_int),
     "tdg_kernel_compress": ([P, P, C.c_int64, C.c_int32, C.POINTER(Trunc), C.POINTER(LowRank)], C.c_int),
     "tdg_kernel_compress_randomized": ([P, P, C.c_int64, C.c_int32, C.POINTER(Trunc), P, C.c_int64, C.c_int32,

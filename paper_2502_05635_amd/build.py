@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtdagw.so")
-SOURCES = ["context.cpp", "kbuild.hip", "propagate.hip", "compress.hip", "gemm.hip", "adjoint.hip"]
+SOURCES = ["context.cpp", "kbuild.hip", "propagate.hip", "compress.hip", "gemm.hip", "adjoint.hip", "intraband.hip"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 

@@ -11,6 +11,11 @@
 //   Sigbar = -i [y^H, g],  sbar = gather(Sigbar) (e-h block: Sigbar_cv + conj(Sigbar_vc)),
 //   dL/dE  = Re sum conj(g) i [e.d, y],
 //   dL/dS += sbar (V^H x)^H,  dL/dV^H += (S^H sbar) x^H.
+// With the intraband term (model links) f gains -E(t) D(y), D = e.(.)_{;k} the
+// covariant central difference; D is anti-self-adjoint for Re sum conj(a) b
+// (transport to k + b and to k - b are each other's adjoints), so
+//   ybar += E(t) D(g),  dL/dE += -Re sum conj(g) D(y),
+// with D(g) = coef D(abar) + cnext D(ybar_next) from the linearity of D.
 // Complex gradients are dL/dRe + i dL/dIm.  The step is pulled back from its
 // fourth stage to its first: with a = dL/drho_{n+1},
 //   g_4 = dt/6 a, g_3 = dt/3 a + dt ybar_4, g_2 = dt/3 a + dt/2 ybar_3,
@@ -161,13 +166,15 @@ __global__ void __launch_bounds__(AT) adj_gather_kernel(AdjArgs a, const double2
 // into y_next and its gather into x_next (if not NULL).
 __global__ void __launch_bounds__(AT) adj_fwd_stage_kernel(AdjArgs a, int step, int st, const double2* rho_n,
                                                            const double2* y, const double2* S, const double2* X,
-                                                           double2* acc, double2* y_next, double2* x_next) {
+                                                           const double2* dy, double2* acc, double2* y_next,
+                                                           double2* x_next) {
   __shared__ double2 sh_y[AT], sh_h[AT];
   const Slot s = slot_of(a);
   const int t = threadIdx.x, nb = a.nb, o = s.lk * nb * nb;
+  double ef = 0.0;
   if (s.active) {
     const tdg_field F = a.fields[s.b];
-    const double ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
+    ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
     sh_y[t] = y[s.g];
     sh_h[t] = ham_element(a, S, X, s, ef, proj_e(F, a, a.dip, s.k, s.e));
   }
@@ -180,7 +187,13 @@ __global__ void __launch_bounds__(AT) adj_fwd_stage_kernel(AdjArgs a, int step, 
     c.x += hr.x - rh.x;
     c.y += hr.y - rh.y;
   }
-  const double2 f = make_double2(c.y, -c.x);  // -i c
+  double2 f = make_double2(c.y, -c.x);  // -i c
+  if (dy) {
+    // intraband term -E(t) D(y)
+    const double2 d = dy[s.g];
+    f.x -= ef * d.x;
+    f.y -= ef * d.y;
+  }
   const double2 rn = rho_n[s.g];
   const double dt = a.dt;
   double2 next;
@@ -210,17 +223,21 @@ __global__ void __launch_bounds__(AT) adj_fwd_stage_kernel(AdjArgs a, int step, 
 // Pullback, first half, for stage s: g = coef * abar + cnext * ybar_next;
 // ydirect = i [H^H, g]; sbc = conj(gather(Sigbar)) with Sigbar = -i [y^H, g];
 // part[s][b][k] = Re sum conj(g) i [e.d, y] over the k point's elements.
+// Intraband term (dy = D(y) not NULL; da = D(abar), dyb = D(ybar_next)):
+// ydirect += E D(g), part -= Re sum conj(g) D(y).
 __global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int st, const double2* y, const double2* S,
                                                        const double2* X, const double2* abar, double coef,
-                                                       const double2* ybar_next, double cnext, double2* ydirect,
+                                                       const double2* ybar_next, double cnext, const double2* dy,
+                                                       const double2* da, const double2* dyb, double2* ydirect,
                                                        double2* sbc, double* part) {
   __shared__ double2 sh_y[AT], sh_h[AT], sh_g[AT], sh_d[AT], sh_sig[AT];
   __shared__ double sh_de[AT];
   const Slot s = slot_of(a);
   const int t = threadIdx.x, nb = a.nb, nb2 = nb * nb, o = s.lk * nb2;
+  double ef = 0.0;
   if (s.active) {
     const tdg_field F = a.fields[s.b];
-    const double ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
+    ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
     const double2 de = proj_e(F, a, a.dip, s.k, s.e);
     const double2 ab = abar[s.g];
     double2 g = make_double2(coef * ab.x, coef * ab.y);
@@ -252,11 +269,26 @@ __global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int 
       c3.x += a3.x - b3.x;
       c3.y += a3.y - b3.y;
     }
-    ydirect[s.g] = make_double2(-c1.y, c1.x);  // i c1
-    sh_sig[t] = make_double2(c2.y, -c2.x);     // -i c2
+    double2 yd = make_double2(-c1.y, c1.x);  // i c1
+    sh_sig[t] = make_double2(c2.y, -c2.x);   // -i c2
     // Re(conj(g) * i c3) = g.x (-c3.y) + g.y c3.x
     const double2 g = sh_g[t];
-    sh_de[t] = -g.x * c3.y + g.y * c3.x;
+    double dl = -g.x * c3.y + g.y * c3.x;
+    if (dy) {
+      const double2 d_a = da[s.g];
+      double2 dg = make_double2(coef * d_a.x, coef * d_a.y);
+      if (ybar_next) {
+        const double2 d_y = dyb[s.g];
+        dg.x += cnext * d_y.x;
+        dg.y += cnext * d_y.y;
+      }
+      yd.x += ef * dg.x;
+      yd.y += ef * dg.y;
+      const double2 d = dy[s.g];
+      dl -= g.x * d.x + g.y * d.y;
+    }
+    ydirect[s.g] = yd;
+    sh_de[t] = dl;
   }
   __syncthreads();
   if (!s.active) return;
@@ -398,6 +430,8 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   if ((gobs->gP || gobs->gJ || gobs->gocc) && gobs->stride < nsteps + 1)
     return fail(ctx, TDG_E_INVAL, "observable cotangent stride < nsteps + 1");
   if (checkpoint_every < 1) return fail(ctx, TDG_E_INVAL, "checkpoint_every must be >= 1");
+  if (model->links && (int64_t)nk * nb2 * batch > ((int64_t)1 << 38))
+    return fail(ctx, TDG_E_UNSUPPORTED, "intraband term: nk * nb^2 * batch too large for one launch");
   const int M = std::min(checkpoint_every, nsteps);
   const int nck = (nsteps + M - 1) / M;
   TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
@@ -415,6 +449,9 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
                o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
                o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)4 * batch * nk * sizeof(double)),
                o_df = cv.take((size_t)batch * 4 * sizeof(double)), o_f = cv.take((size_t)batch * sizeof(tdg_field));
+  // intraband term: D of a stage state, of abar and of ybar
+  const bool intra = model->links != nullptr;
+  const size_t o_dy = cv.take(intra ? st_b : 0), o_da = cv.take(intra ? st_b : 0), o_dyb = cv.take(intra ? st_b : 0);
   void* base = nullptr;
   TDG_TRY(ws_reserve(ctx, WS_ADJ, cv.off, &base));
   char* wb = (char*)base;
@@ -422,6 +459,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   double2 *CK = P2(o_ck), *SEG = P2(o_seg), *YS = P2(o_ys), *OUT = P2(o_out), *ACC = P2(o_acc), *ABAR = P2(o_abar),
           *YBAR = P2(o_ybar), *YD = P2(o_yd), *ACCA = P2(o_acca), *SS = P2(o_s), *XS = P2(o_x), *SBC = P2(o_sbc),
           *TT = P2(o_t), *ZS = P2(o_z), *UC = P2(o_uc);
+  double2 *DY = intra ? P2(o_dy) : nullptr, *DA = intra ? P2(o_da) : nullptr, *DYB = intra ? P2(o_dyb) : nullptr;
   double* part = (double*)(wb + o_part);
   double* dfacc = (double*)(wb + o_df);
   tdg_field* dfields = (tdg_field*)(wb + o_f);
@@ -480,6 +518,10 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   auto sst = [&](int s) { return SS + (size_t)s * n * batch; };
   auto ys = [&](int s) { return YS + (size_t)(s - 1) * st_el; };  // s = 1, 2, 3
 
+  // D(v) of a state-shaped array (caller's instance order) into out
+  auto covd = [&](const double2* v, double2* o) {
+    covariant_derivative(ctx->stream, model, v, (int64_t)nk * nb2, nb2, 1, dfields, batch, o);
+  };
   // One forward step from rho_in to rho_out, keeping y_s, S_s, X_s, Z_s of
   // its stages in the column block group j.
   auto run_step = [&](int step, const double2* rho_in, double2* rho_out, int j) -> int {
@@ -487,8 +529,10 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     for (int s = 0; s < 4; ++s) {
       const double2* y = s == 0 ? rho_in : ys(s);
       TDG_TRY(apply_k(xblk(j * 4 + s), sst(s), lowrank ? zblk(j * 4 + s) : nullptr));
+      if (intra) covd(y, DY);
       hipLaunchKernelGGL(adj_fwd_stage_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, rho_in, y, sst(s),
-                         xblk(j * 4 + s), ACC, s < 3 ? ys(s + 1) : rho_out, s < 3 ? xblk(j * 4 + s + 1) : nullptr);
+                         xblk(j * 4 + s), (const double2*)DY, ACC, s < 3 ? ys(s + 1) : rho_out,
+                         s < 3 ? xblk(j * 4 + s + 1) : nullptr);
     }
     return launch_check(ctx, "adjoint forward step");
   };
@@ -524,11 +568,17 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
       TDG_TRY(run_step(step, seg(step - start), OUT, j));
       static const double coef[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
       static const double cnext[4] = {0.5, 0.5, 1.0, 0.0};
+      if (intra) covd(ABAR, DA);
       for (int s = 3; s >= 0; --s) {
         const double2* y = s == 0 ? seg(step - start) : ys(s);
         const int cb = j * 4 + s;
+        if (intra) {
+          covd(y, DY);
+          if (s < 3) covd(YBAR, DYB);
+        }
         hipLaunchKernelGGL(adj_bwd_a_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, y, sst(s), xblk(cb), ABAR,
-                           coef[s] * dt, s == 3 ? (const double2*)nullptr : YBAR, cnext[s] * dt, YD, sbcblk(cb), part);
+                           coef[s] * dt, s == 3 ? (const double2*)nullptr : YBAR, cnext[s] * dt, (const double2*)DY,
+                           (const double2*)DA, (const double2*)DYB, YD, sbcblk(cb), part);
         TDG_TRY(apply_kh(sbcblk(cb), lowrank ? ucblk(cb) : nullptr));
         hipLaunchKernelGGL(adj_bwd_b_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, YD, TT, sbcblk(cb), YBAR,
                            ACCA, ABAR, gobs->gP, gobs->gJ, gobs->gocc, gobs->stride);

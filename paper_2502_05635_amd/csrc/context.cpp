@@ -105,7 +105,7 @@ int validate_model(tdg_ctx ctx, const tdg_model* m) {
   if (m->nv < 1 || m->nv >= m->nb) return fail(ctx, TDG_E_INVAL, "nv = %d outside [1, nb-1]", m->nv);
   if (!(m->a_bohr > 0.0)) return fail(ctx, TDG_E_INVAL, "lattice constant must be positive");
   if (!m->eps || !m->evec || !m->dip || !m->vel) return fail(ctx, TDG_E_INVAL, "model array pointer is NULL");
-  if (((uintptr_t)m->evec | (uintptr_t)m->dip | (uintptr_t)m->vel) & 15)
+  if (((uintptr_t)m->evec | (uintptr_t)m->dip | (uintptr_t)m->vel | (uintptr_t)m->links) & 15)
     return fail(ctx, TDG_E_INVAL, "complex model arrays must be 16-byte aligned");
   return TDG_OK;
 }

@@ -40,6 +40,7 @@ enum WsSlot {
   WS_ADJ,        // adjoint propagation: checkpoints, segment states, stage data, cotangents
   WS_STEP,       // batched path: step counter read by graph replays
   WS_XB,         // batched BF16X2 path: X split into bf16 planes once per product
+  WS_INTRA,      // intraband term: covariant derivative of the stage state, c128 like the state
   WS_COUNT
 };
 
@@ -108,6 +109,13 @@ size_t cgemm_bf16x2_work_bytes(int Kc, int ncols);
 // dst (TDG_BF16X2 [rows][ld_dst]) <- complex src [rows][ld_src]; columns >= cols zero.
 void split_bf16x2(hipStream_t stream, const void* src, int src_is_double, int64_t ld_src, int64_t rows, int64_t cols,
                   void* dst, int64_t ld_dst);
+// out = e.(y)_{;k} per instance (intraband.hip): the covariant k-derivative of
+// the per-k matrices y with model->links, y and out addressed as
+// b*sb + k*sk + e*se (element e = n*nb + m), e taken from fields[b] (device).
+// Launch only (no error check: also used under graph capture); the caller
+// keeps nk * nb^2 * batch at most 2^38 (the grid limit).
+void covariant_derivative(hipStream_t stream, const tdg_model* model, const void* y, int64_t sb, int64_t sk,
+                          int64_t se, const tdg_field* fields, int batch, void* out);
 // out = sum of `slices` complex64 arrays of `count` elements, `stride` apart.
 void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stride, int64_t count, void* out);
 

@@ -204,6 +204,8 @@ struct StageParams {
   int n_dyn;          // blocks with blockIdx.y < n_dyn integrate; the others only record observables
   int step, stage;
   double dt;
+  const double2* intra;  // intraband term e.(rho_s)_{;k} of this stage, laid out as rho_s; NULL = none
+  int tr_signed;         // per-k trace partial signed (summed over k) instead of |.| (maximised)
 };
 
 // Per-k observables of s_rho (LDS) into obs_part; de, ve are this thread's
@@ -233,7 +235,7 @@ __device__ inline void obs_partial(const StageParams& sp, const double2* s_rho, 
       const double h = s_obs[4][i];
       if (h > o[4] || h != h) o[4] = h;
     }
-    o[3] = fabs(o[3] - (double)sp.nv);
+    o[3] = sp.tr_signed ? o[3] - (double)sp.nv : fabs(o[3] - (double)sp.nv);
     double* dst = sp.obs_part + (((size_t)sp.obs_slot * sp.batch + b) * sp.nk + k) * 5;
     for (int c = 0; c < 5; ++c) dst[c] = o[c];
   }
@@ -408,8 +410,14 @@ stage_kernel(StageParams sp) {
       c.x += hr.x - rh.x;
       c.y += hr.y - rh.y;
     }
-    const double2 f = make_double2(c.y, -c.x);  // -i c
+    double2 f = make_double2(c.y, -c.x);  // -i c
     const size_t g = kb + t;
+    if (sp.intra) {
+      // intraband part of the field term: -E(t) e.(rho)_{;k}
+      const double2 dv = sp.intra[g];
+      f.x -= ef * dv.x;
+      f.y -= ef * dv.y;
+    }
     double2 next;
     if (sp.stage == 0) {
       sp.acc[g] = f;
@@ -545,6 +553,8 @@ struct BatchParams {
   double dt;
   const int* step_dev;  // graph replays: the step is read here (obs slot = step % chunk); else NULL
   int chunk;
+  const double2* intra;  // intraband term e.(rho_s)_{;k} of this stage, laid out as rho_s; NULL = none
+  int tr_signed;         // per-k trace partial signed (summed over k) instead of |.| (maximised)
 };
 
 // The step counter of graph replays (vector stores: the address depends on the lane).
@@ -659,16 +669,17 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
           else if (q > v || q != q)
             v = q;   // the Hermiticity residual is a maximum
         }
-        if (c == 3) v = fabs(v - (double)bp.nv);
+        if (c == 3) v = bp.tr_signed ? v - (double)bp.nv : fabs(v - (double)bp.nv);
         bp.obs_part[(((size_t)obs_slot * bp.batch + b) * bp.nk + k) * 5 + c] = v;
       }
     }
   }
 
   // H = eps + dSigma - E(t) e.d
+  double ef = 0.0;
   if (dyn) {
     const double cs = (bp.stage == 0) ? 0.0 : (bp.stage == 3 ? 1.0 : 0.5);
-    const double ef = field_value(F, (double)step * bp.dt + cs * bp.dt);
+    ef = field_value(F, (double)step * bp.dt + cs * bp.dt);
 #pragma unroll
     for (int m = 0; m < TDG_NB_MAX; ++m) {
       if (m >= nb) break;
@@ -695,8 +706,14 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
       c.x += hr.x - rh.x;
       c.y += hr.y - rh.y;
     }
-    const double2 f = make_double2(c.y, -c.x);
+    double2 f = make_double2(c.y, -c.x);
     const size_t g = bidx(bp, k, e, b);
+    if (bp.intra) {
+      // intraband part of the field term: -E(t) e.(rho)_{;k}
+      const double2 dv = bp.intra[g];
+      f.x -= ef * dv.x;
+      f.y -= ef * dv.y;
+    }
     double2 next;
     if (bp.stage == 0) {
       bp.acc[g] = f;
@@ -778,10 +795,11 @@ __global__ void obs_state_kernel(StageParams sp) {
 // Fixed-order reduction of per-k observables: sums (P, J, occ) / nk and
 // maxima (tr, herm), for steps step0 .. step0 + gridDim.x - 1 of the sorted
 // instance b, written to row perm[b] (or to out5[b] for tdg_observables).
+// tr_mean: the trace partials are signed and the result is |sum| / nk.
 __global__ void __launch_bounds__(THREADS) obs_reduce_kernel(const double* __restrict__ part, int nk, int batch,
                                                              int step0, const tdg_field* fields,
                                                              const int* __restrict__ perm, tdg_obs obs,
-                                                             double* out5) {
+                                                             double* out5, int tr_mean) {
   const int slot = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
   const int step = step0 + slot;
   if (out5 == nullptr && step > (int64_t)fields[b].nsteps) return;
@@ -793,7 +811,8 @@ __global__ void __launch_bounds__(THREADS) obs_reduce_kernel(const double* __res
     a[0] += q[0];
     a[1] += q[1];
     a[2] += q[2];
-    for (int c = 3; c < 5; ++c)
+    if (tr_mean) a[3] += q[3];
+    for (int c = tr_mean ? 4 : 3; c < 5; ++c)
       if (q[c] > a[c] || q[c] != q[c]) a[c] = q[c];
   }
   for (int c = 0; c < 5; ++c) s[c][t] = a[c];
@@ -801,7 +820,8 @@ __global__ void __launch_bounds__(THREADS) obs_reduce_kernel(const double* __res
   for (int w = THREADS / 2; w > 0; w >>= 1) {
     if (t < w) {
       for (int c = 0; c < 3; ++c) s[c][t] += s[c][t + w];
-      for (int c = 3; c < 5; ++c) {
+      if (tr_mean) s[3][t] += s[3][t + w];
+      for (int c = tr_mean ? 4 : 3; c < 5; ++c) {
         const double o = s[c][t + w];
         if (o > s[c][t] || o != o) s[c][t] = o;
       }
@@ -810,6 +830,7 @@ __global__ void __launch_bounds__(THREADS) obs_reduce_kernel(const double* __res
   }
   if (t == 0) {
     const double inv = 1.0 / (double)nk;
+    if (tr_mean) s[3][0] = fabs(s[3][0]) * inv;
     if (out5) {
       double* o = out5 + (size_t)b * 5;
       o[0] = s[0][0] * inv;
@@ -997,7 +1018,12 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   // batched state is instance fastest with the drho row stride
   const size_t state_bytes = (size_t)(batched ? xstride : batch) * nk * nb2 * sizeof(double2);
   const int64_t zstride = channel ? (int64_t)npair * ch_ls : (op->rank + 1) & ~int64_t(1);
-  void *rho_n, *rho_s, *acc, *x0, *x1, *z = nullptr, *part, *dperm, *dfields;
+  void *rho_n, *rho_s, *acc, *x0, *x1, *z = nullptr, *part, *dperm, *dfields, *dintra = nullptr;
+  // intraband term: e.(rho_s)_{;k} of each stage, computed before the stage kernel
+  const bool intra = model->links != nullptr;
+  if (intra && (int64_t)nk * nb2 * batch > ((int64_t)1 << 38))
+    return fail(ctx, TDG_E_UNSUPPORTED, "intraband term: nk * nb^2 * batch too large for one launch");
+  if (intra) TDG_TRY(ws_reserve(ctx, WS_INTRA, state_bytes, &dintra));
   TDG_TRY(ws_reserve(ctx, WS_RHO_N, state_bytes, &rho_n));
   TDG_TRY(ws_reserve(ctx, WS_RHO_S, state_bytes, &rho_s));
   TDG_TRY(ws_reserve(ctx, WS_ACC, state_bytes, &acc));
@@ -1074,6 +1100,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   sp.block = op->block;
   sp.batch = batch;
   sp.dt = dt;
+  sp.tr_signed = intra;
   const int64_t split_stride = (int64_t)batch * zstride;
   sp.zsplit_stride = split_stride;
   // projection rows: the rank (low rank) or every off-diagonal channel's rows (channel-wise)
@@ -1160,6 +1187,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     bp.block = op->block;
     bp.batch = batch;
     bp.dt = dt;
+    bp.tr_signed = intra;
     // stage kernel blocks: IB instances x nb rows, LDS for their H and rho blocks and row sums
     int IB = 16;  // instances per block: up to 64 for nb <= 4, matched to the batch
     while (model->nb <= 4 && IB < 64 && IB < batch) IB *= 2;
@@ -1299,6 +1327,10 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         bp.stage = s;
         bp.obs_slot = slot_;
         bp.n_active = active;
+        bp.intra = (intra && n_dyn > 0) ? (const double2*)dintra : nullptr;
+        if (bp.intra)
+          covariant_derivative(st, model, rho_s, 1, (int64_t)nb2 * xstride, xstride, (const tdg_field*)dfields, n_dyn,
+                               dintra);
         if (prof) prof_begin(ctx, TDG_KCLASS_STAGE);
         hipLaunchKernelGGL(batched_stage_kernel, dim3(nk, (active + IB - 1) / IB), dim3(IB * model->nb), stage_lds,
                            st, bp);
@@ -1361,7 +1393,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       if (slot == chunk || step == max_steps) {
         hipLaunchKernelGGL(obs_reduce_kernel, dim3(slot, batch), dim3(THREADS), 0, ctx->stream, (const double*)part,
                            nk, batch, (int)chunk_start, (const tdg_field*)dfields, (const int*)dperm, ob,
-                           (double*)nullptr);
+                           (double*)nullptr, (int)intra);
         chunk_start += slot;
         slot = 0;
       }
@@ -1485,6 +1517,10 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       sp.step = (int)step;
       sp.stage = s;
       sp.obs_slot = slot;
+      sp.intra = (intra && n_dyn > 0) ? (const double2*)dintra : nullptr;
+      if (sp.intra)
+        covariant_derivative(ctx->stream, model, rho_s, (int64_t)nk * nb2, nb2, 1, (const tdg_field*)dfields, n_dyn,
+                             dintra);
       hipEvent_t sa, sb;
       prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
       stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
@@ -1493,7 +1529,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     ++slot;
     if (slot == chunk || step == max_steps) {
       hipLaunchKernelGGL(obs_reduce_kernel, dim3(slot, batch), dim3(THREADS), 0, ctx->stream, (const double*)part, nk,
-                         batch, (int)chunk_start, (const tdg_field*)dfields, (const int*)dperm, ob, (double*)nullptr);
+                         batch, (int)chunk_start, (const tdg_field*)dfields, (const int*)dperm, ob, (double*)nullptr,
+                         (int)intra);
       chunk_start += slot;
       slot = 0;
     }
@@ -1527,11 +1564,12 @@ extern "C" int tdg_observables(tdg_ctx ctx, const tdg_model* model, const void* 
   sp.nb = model->nb;
   sp.nv = model->nv;
   sp.batch = batch;
+  sp.tr_signed = model->links != nullptr;
   hipLaunchKernelGGL(obs_state_kernel, dim3(nk, batch), dim3(64), 0, ctx->stream, sp);
   TDG_TRY(launch_check(ctx, "observables launch"));
   tdg_obs none = {};
   hipLaunchKernelGGL(obs_reduce_kernel, dim3(1, batch), dim3(THREADS), 0, ctx->stream, (const double*)part, nk, batch,
-                     0, (const tdg_field*)dfields, (const int*)nullptr, none, out);
+                     0, (const tdg_field*)dfields, (const int*)nullptr, none, out, sp.tr_signed);
   return launch_check(ctx, "observables reduce launch");
 }
 

@@ -24,8 +24,8 @@ def _weights(seed):
     return rng.standard_normal(NSTEPS + 1), rng.standard_normal(NSTEPS + 1), rng.standard_normal(NSTEPS + 1)
 
 
-def _loss(model, op, block, fields, w, rho0=None):
-    r = O.propagate(model, op, block, fields, DT, rho0=rho0)
+def _loss(model, op, block, fields, w, rho0=None, links=None):
+    r = O.propagate(model, op, block, fields, DT, rho0=rho0, links=links)
     return float(np.dot(w[0], r["P"]) + np.dot(w[1], r["J"]) + np.dot(w[2], r["occ"]))
 
 
@@ -46,12 +46,12 @@ def lowrank_tb4(tb4_4):
     return O.LowRankOp.from_factors(O.compress(O.build_kernel(tb4_4, R0_STABLE, "eh"), "rank", 12))
 
 
-def _check_field_params(model, op, block, fields, w, grads):
+def _check_field_params(model, op, block, fields, w, grads, links=None):
     for i, name in enumerate(("e0", "omega", "tau", "t0")):
         v = float(getattr(fields, name)[0])
         h = 1e-5 * abs(v)
-        fd = (_loss(model, op, block, _with(fields, name, v + h), w)
-              - _loss(model, op, block, _with(fields, name, v - h), w)) / (2 * h)
+        fd = (_loss(model, op, block, _with(fields, name, v + h), w, links=links)
+              - _loss(model, op, block, _with(fields, name, v - h), w, links=links)) / (2 * h)
         assert abs(grads["dfield"][i] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(grads["dfield"]).max()), name
 
 
@@ -118,3 +118,21 @@ def test_harmonic_loss_gradient(tb4_4, lowrank_tb4):
         h = 1e-5 * abs(v)
         fd = (total(_with(f, name, v + h))[0] - total(_with(f, name, v - h))[0]) / (2 * h)
         assert abs(grad[i] - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(grad).max()), name
+
+
+def test_adjoint_with_intraband_term(tb4_4, lowrank_tb4):
+    """The intraband (covariant k-derivative) term: field parameters and the
+    initial state against central differences, field along (0.6, 0.8)."""
+    f = FieldTable.single(8e-3, 1.2 / HARTREE_EV, 2.0 * FS_AU, 4.0 * FS_AU, NSTEPS, ex=0.6, ey=0.8)
+    w = _weights(7)
+    links = O.transport_links(tb4_4)
+    g = O.propagate_adjoint(tb4_4, lowrank_tb4, "eh", f, DT, *w, links=links)
+    g_local = O.propagate_adjoint(tb4_4, lowrank_tb4, "eh", f, DT, *w)
+    assert np.abs(g["dfield"] - g_local["dfield"]).max() > 1e-3 * np.abs(g["dfield"]).max()  # the term matters
+    _check_field_params(tb4_4, lowrank_tb4, "eh", f, w, g, links=links)
+    rng = np.random.default_rng(8)
+    rho_eq = O.rho_equilibrium(tb4_4)
+    d_rho = rng.standard_normal(rho_eq.shape) + 1j * rng.standard_normal(rho_eq.shape)
+    d_rho = 0.5 * (d_rho + d_rho.conj().transpose(0, 2, 1))
+    fd = _directional(lambda r0: _loss(tb4_4, lowrank_tb4, "eh", f, w, rho0=r0, links=links), rho_eq, d_rho, 1e-6)
+    assert abs(np.sum((g["drho0"].conj() * d_rho).real) - fd) <= 1e-6 * abs(fd)

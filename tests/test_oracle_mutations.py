@@ -131,6 +131,8 @@ CASES = {
                                                         "adjoint_fields"),
     "intraband: backward link not conjugate-transposed": (PROPAGATE, "covariant_derivative",
                                                           _backward_link_not_daggered, "intra_rotated"),
+    "adjoint: intraband term with the backward link not conjugate-transposed": (
+        ADJOINT, "covariant_derivative", _backward_link_not_daggered, "adjoint_intraband"),
     "intraband: drift sign flipped": (PROPAGATE, "covariant_derivative",
                                       lambda *a: -INTRABAND._real_covariant_derivative(*a), "intra_fft"),
     "intraband: grid spacing halved": (INTRABAND, "grid_spacing",
@@ -169,6 +171,10 @@ def _run_pin(name, small):
             intra.test_rotated_degenerate_bases_give_the_same_dynamics()
         else:
             intra.test_total_charge_and_equilibrium_conserved(tb4_model(6, A, 0.5))
+    elif name == "adjoint_intraband":
+        import test_oracle_adjoint as adj
+        adj.test_adjoint_with_intraband_term(t4, O.LowRankOp.from_factors(
+            O.compress(O.build_kernel(t4, R0_STABLE, "eh"), "rank", 12)))
     elif name in ("adjoint_fields", "adjoint_factors"):
         import test_oracle_adjoint as adj
         lr = O.LowRankOp.from_factors(O.compress(O.build_kernel(t4, R0_STABLE, "eh"), "rank", 12))
