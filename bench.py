@@ -51,6 +51,7 @@ def parse():
                          "compression, then dense FP32, low-rank FP32 and low-rank BF16X2 throughput")
     ap.add_argument("--large-grid-steps", type=int, default=40, help="RK4 steps per instance timed there")
     ap.add_argument("--no-channelwise", action="store_true", help="skip the channel-wise compression leg")
+    ap.add_argument("--no-intraband", action="store_true", help="skip the intraband field-coupling leg")
     ap.add_argument("--sweep-only", type=int, default=0, metavar="STEPS",
                     help="only run the batched 60x60 sweep, every instance for STEPS steps (for counter runs; "
                          "with --factors-cache the sweep's factors are cached as well)")
@@ -179,17 +180,18 @@ def main():
     compress_s = time.perf_counter() - t0
     n, r, nk, nb = K.shape[0], fac.rank, model.nk, model.nb
 
-    def timed(op, steps, warmup, profile):
-        ctx.propagate(op, dm, "eh", fields_for(warmup), cfg.dt)
+    def timed(op, steps, warmup, profile, model=dm):
+        ctx.propagate(op, model, "eh", fields_for(warmup), cfg.dt)
         ctx.profile_enable(profile)
         torch.cuda.synchronize()
         t_a = time.perf_counter()
-        res = ctx.propagate(op, dm, "eh", fields_for(steps), cfg.dt)
+        res = ctx.propagate(op, model, "eh", fields_for(steps), cfg.dt)
         torch.cuda.synchronize()
         t_b = time.perf_counter()
         prof = {}
         if profile:
-            for name, cls in (("stage", abi.TDG_KCLASS_STAGE), ("project", abi.TDG_KCLASS_PROJECT)):
+            for name, cls in (("stage", abi.TDG_KCLASS_STAGE), ("project", abi.TDG_KCLASS_PROJECT),
+                              ("intra", abi.TDG_KCLASS_INTRA)):
                 ms, cnt = ctx.profile_read(cls)
                 prof[name] = (ms, cnt)
         ctx.profile_enable(False)
@@ -218,6 +220,27 @@ def main():
         variant = ctx.last_variant()
         _, _, prof = timed(chan, args.steps, args.warmup, True)
         out["channel"] = {"secs": secs, "res": res, "prof": prof, "variant": variant}
+
+    # intraband part of the field coupling (covariant k-derivative with
+    # parallel-transport links) on the same low-rank operator
+    intraband = None
+    if not args.no_intraband:
+        t0 = time.perf_counter()
+        dml = dm.with_links(ctx.links_build(dm))
+        links_s = time.perf_counter() - t0
+        _, secs, _ = timed(fac, args.steps, args.warmup, False, model=dml)
+        variant = ctx.last_variant()
+        _, _, prof = timed(fac, args.steps, args.warmup, True, model=dml)
+        us = {k: prof[k][0] / prof[k][1] * 1e3 for k in ("stage", "project", "intra") if prof[k][1]}
+        intraband = {
+            "value": args.steps / secs, "ms_per_step": 1e3 * secs / args.steps, "variant": variant,
+            "stage_kernel_us": us.get("stage"), "project_kernel_us": us.get("project"),
+            "covariant_derivative_kernel_us": us.get("intra"), "links_build_seconds": links_s,
+            # one read of the stage state, of both link planes, one write of the result
+            "covariant_derivative_bytes_per_launch": 4 * nk * nb * nb * 16,
+        }
+        if us.get("intra"):
+            intraband["covariant_derivative_GBps"] = intraband["covariant_derivative_bytes_per_launch"] / us["intra"] / 1e3
 
     # errors against the stored FP64 oracle series (same operator, same steps):
     # over the first half of the run (t <= t0, before the post-pulse chaotic
@@ -280,6 +303,8 @@ def main():
     dense_value = args.steps / out["dense"]["secs"]
     if channelwise:
         channelwise["speedup_vs_dense"] = channelwise["value"] / dense_value
+    if intraband:
+        intraband["cost_vs_k_local_lowrank"] = value / intraband["value"]
 
     rank_cut = int(np.count_nonzero(fac.sigma > 1e-3 * fac.sigma[0]))
     sweep = None
@@ -321,6 +346,7 @@ def main():
                   "stage_kernel_hbm_frac": dense_bytes / dense_avg_s / 1e9 / HBM_PEAK_GBS},
         "speedup_lowrank_vs_dense": value / dense_value,
         "channelwise": channelwise,
+        "intraband": intraband,
         "errors_vs_fp64_oracle": errs or None,
         "compress_seconds": compress_s,
         "roofline": {

@@ -23,6 +23,7 @@ TDG_OP_CHANNEL = 2
 TDG_KCLASS_STAGE = 0
 TDG_KCLASS_PROJECT = 1
 TDG_KCLASS_GEMM = 2
+TDG_KCLASS_INTRA = 3
 TDG_OPT_AUTOTUNE = 0
 TDG_OPT_STAGE_VARIANT = 1
 TDG_OPT_BATCHED_MIN = 2

@@ -197,13 +197,13 @@ const char* tdg_last_variant(tdg_ctx ctx) { return ctx ? ctx->last_variant.c_str
 int tdg_profile_enable(tdg_ctx ctx, int32_t on) {
   if (!ctx) return TDG_E_INVAL;
   ctx->prof = on != 0;
-  ctx->used[0] = ctx->used[1] = ctx->used[2] = 0;
+  for (auto& u : ctx->used) u = 0;
   return TDG_OK;
 }
 
 int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* launches) {
   if (!ctx) return TDG_E_INVAL;
-  if (kclass < 0 || kclass > 2 || !total_ms || !launches)
+  if (kclass < 0 || kclass >= KCLASS_COUNT || !total_ms || !launches)
     return fail(ctx, TDG_E_INVAL, "profile_read: bad class or NULL output");
   TDG_TRY(hip_check(ctx, hipStreamSynchronize(ctx->stream), "profile sync"));
   double tot = 0.0;

@@ -53,6 +53,8 @@ struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
+constexpr int KCLASS_COUNT = 4;  // TDG_KCLASS_STAGE .. TDG_KCLASS_INTRA
+
 }  // namespace tdg
 
 struct tdg_ctx_s {
@@ -62,8 +64,8 @@ struct tdg_ctx_s {
   tdg::Buf ws[tdg::WS_COUNT];
   void* blas = nullptr;  // rocblas_handle, created on first compression
   bool prof = false;
-  std::vector<tdg::EventPair> events[3];
-  size_t used[3] = {0, 0, 0};
+  std::vector<tdg::EventPair> events[tdg::KCLASS_COUNT];
+  size_t used[tdg::KCLASS_COUNT] = {};
   // stage-kernel variant selection (see tdg_set_option)
   bool autotune = true;
   int forced_variant = -1;
@@ -113,9 +115,11 @@ void split_bf16x2(hipStream_t stream, const void* src, int src_is_double, int64_
 // the per-k matrices y with model->links, y and out addressed as
 // b*sb + k*sk + e*se (element e = n*nb + m), e taken from fields[b] (device).
 // Launch only (no error check: also used under graph capture); the caller
-// keeps nk * nb^2 * batch at most 2^38 (the grid limit).
+// keeps nk * nb^2 * batch at most 2^38 (the grid limit).  ea / eb: dispatch
+// timestamp events (prof_pair) or NULL.
 void covariant_derivative(hipStream_t stream, const tdg_model* model, const void* y, int64_t sb, int64_t sk,
-                          int64_t se, const tdg_field* fields, int batch, void* out);
+                          int64_t se, const tdg_field* fields, int batch, void* out, hipEvent_t ea = nullptr,
+                          hipEvent_t eb = nullptr);
 // out = sum of `slices` complex64 arrays of `count` elements, `stride` apart.
 void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stride, int64_t count, void* out);
 

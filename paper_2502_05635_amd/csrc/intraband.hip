@@ -15,6 +15,8 @@
 // factor of each diagonal block of the overlap M = evec_k^H evec_{k + b_a}
 // and zero between the blocks.  Unitary links conserve sum_k Tr rho_k and
 // leave rho_eq unchanged.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 #include <vector>
 
@@ -215,15 +217,15 @@ __global__ void __launch_bounds__(256) covariant_derivative_kernel(
 namespace tdg {
 
 void covariant_derivative(hipStream_t stream, const tdg_model* model, const void* y, int64_t sb, int64_t sk,
-                          int64_t se, const tdg_field* fields, int batch, void* out) {
+                          int64_t se, const tdg_field* fields, int batch, void* out, hipEvent_t ea, hipEvent_t eb) {
   const int nk = model->nk1 * model->nk2, nb = model->nb;
   const int64_t total = (int64_t)nk * nb * nb * batch;
   if (total == 0) return;
   const double c1 = model->nk1 * model->a_bohr / (4.0 * M_PI);  // 1 / (2 |b_1|)
   const double c2 = model->nk2 * model->a_bohr / (4.0 * M_PI);
-  hipLaunchKernelGGL(covariant_derivative_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
-                     (const double2*)y, sb, sk, se, (const double2*)model->links, fields, model->nk1, model->nk2, nb,
-                     model->nv, batch, c1, c2, (double2*)out);
+  hipExtLaunchKernelGGL(covariant_derivative_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0u, stream, ea,
+                        eb, 0u, (const double2*)y, sb, sk, se, (const double2*)model->links, fields, model->nk1,
+                        model->nk2, nb, model->nv, batch, c1, c2, (double2*)out);
 }
 
 }  // namespace tdg

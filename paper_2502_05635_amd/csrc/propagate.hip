@@ -1518,9 +1518,12 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       sp.stage = s;
       sp.obs_slot = slot;
       sp.intra = (intra && n_dyn > 0) ? (const double2*)dintra : nullptr;
-      if (sp.intra)
+      if (sp.intra) {
+        hipEvent_t ia, ib;
+        prof_pair(ctx, TDG_KCLASS_INTRA, &ia, &ib);
         covariant_derivative(ctx->stream, model, rho_s, (int64_t)nk * nb2, nb2, 1, (const tdg_field*)dfields, n_dyn,
-                             dintra);
+                             dintra, ia, ib);
+      }
       hipEvent_t sa, sb;
       prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
       stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
