@@ -58,6 +58,27 @@ __device__ inline double field_value(const tdg_field& f, double t) {
   return f.e0 * exp(-d * d / (2.0 * f.tau * f.tau)) * cos(f.omega * t);
 }
 
+// E_b at the four stage times of steps step0 .. step0 + count - 1, as
+// tab[(slot * batch + b) * 4 + stage].  The stage kernels load their value
+// instead of evaluating exp and cos (a long dependent FP64 chain) at the end
+// of their critical path.
+__global__ void field_table_kernel(const tdg_field* __restrict__ fields, int batch, int step0, int count, double dt,
+                                   double* __restrict__ tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count * batch * 4) return;
+  const int s = i & 3, b = (i >> 2) % batch, slot = (i >> 2) / batch;
+  const double cs = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
+  tab[i] = field_value(fields[b], (double)(step0 + slot) * dt + cs * dt);
+}
+
+// Barrier for the per-k epilogue, which only the block's first wave runs
+// (nb^2 <= 64 elements): wave-level ordering of its LDS accesses.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---- row dot products ------------------------------------------------------
 // acc_r = sum_j A[r][j] x[j] for r < nvalid (rows lda apart), this thread's
 // share of the columns; the block reduction below completes the sums.  The
@@ -206,10 +227,12 @@ struct StageParams {
   double dt;
   const double2* intra;  // intraband term e.(rho_s)_{;k} of this stage, laid out as rho_s; NULL = none
   int tr_signed;         // per-k trace partial signed (summed over k) instead of |.| (maximised)
+  const double* ftab;    // field at the stage times, [obs slot][B][4] (field_table_kernel)
 };
 
 // Per-k observables of s_rho (LDS) into obs_part; de, ve are this thread's
-// element of e.d and e.v (threads t < nb^2 participate).
+// element of e.d and e.v (threads t < nb^2 participate).  Called by the first
+// wave of a block only.
 __device__ inline void obs_partial(const StageParams& sp, const double2* s_rho, double (*s_obs)[NB2_MAX],
                                    double2 de, double2 ve, int k, int b) {
   const int nb = sp.nb, nb2 = nb * nb, t = threadIdx.x;
@@ -224,7 +247,7 @@ __device__ inline void obs_partial(const StageParams& sp, const double2* s_rho, 
     const double hx = rnm.x - rmn.x, hy = rnm.y + rmn.y;
     s_obs[4][t] = sqrt(hx * hx + hy * hy);
   }
-  __syncthreads();
+  wave_sync();
   if (t == 0) {
     double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = 0; i < nb2; ++i) {
@@ -273,6 +296,7 @@ stage_kernel(StageParams sp) {
   // use (its lifetime is latency-bound); the dense kernel loads the per-k
   // state after its row stream (bandwidth-bound, registers kept for the stream)
   const tdg_field F = sp.fields[b];
+  const double ef = dyn ? sp.ftab[((size_t)sp.obs_slot * sp.batch + b) * 4 + sp.stage] : 0.0;
   double2 r_s = make_double2(0.0, 0.0), r_n = r_s, r_acc = r_s, d0 = r_s, d1 = r_s, v0 = r_s, v1 = r_s;
   double e_nn = 0.0;
   auto load_state = [&]() {
@@ -366,8 +390,10 @@ stage_kernel(StageParams sp) {
     }
   }
   if (!LOWRANK) load_state();
+  // the per-k epilogue runs in the first wave (nb^2 <= 64 elements, P <= 64 pairs)
+  if (t >= 64) return;
   if (t < nb2) s_rho[t] = r_s;
-  __syncthreads();
+  wave_sync();
   if (sp.stage == 0 && sp.obs_part) obs_partial(sp, s_rho, s_obs, proj_e(F, d0, d1), proj_e(F, v0, v1), k, b);
   if (!dyn) return;                              // final time of this instance: observables only
   if (LOWRANK && t < P) {
@@ -375,12 +401,9 @@ stage_kernel(StageParams sp) {
     s_y[2 * t] += (double)re;
     s_y[2 * t + 1] += (double)im;
   }
-  __syncthreads();
+  wave_sync();
 
   // ---- H_k = eps_k + dSigma_k - E(t) e.d_k ----------------------------------
-  const double cs = (sp.stage == 0) ? 0.0 : (sp.stage == 3 ? 1.0 : 0.5);
-  const double tt = (double)sp.step * sp.dt + cs * sp.dt;
-  const double ef = field_value(F, tt);
   if (t < nb2) {
     const int n = t / nb, m = t % nb;
     double2 ds = make_double2(0.0, 0.0);
@@ -398,7 +421,7 @@ stage_kernel(StageParams sp) {
     if (n == m) h.x += e_nn;
     s_h[t] = h;
   }
-  __syncthreads();
+  wave_sync();
 
   // ---- f = -i [H, rho], RK4 stage update, next drho gather ----------------
   if (t < nb2) {
@@ -555,6 +578,7 @@ struct BatchParams {
   int chunk;
   const double2* intra;  // intraband term e.(rho_s)_{;k} of this stage, laid out as rho_s; NULL = none
   int tr_signed;         // per-k trace partial signed (summed over k) instead of |.| (maximised)
+  const double* ftab;    // field at the stage times, [obs slot][B][4] (field_table_kernel)
 };
 
 // The step counter of graph replays (vector stores: the address depends on the lane).
@@ -595,6 +619,7 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
 
   tdg_field F = {};
   if (act) F = bp.fields[b];
+  const double ef_stage = dyn ? bp.ftab[((size_t)obs_slot * bp.batch + b) * 4 + bp.stage] : 0.0;
   double2 r_n[TDG_NB_MAX], r_acc[TDG_NB_MAX], ds[TDG_NB_MAX];
 #pragma unroll
   for (int m = 0; m < TDG_NB_MAX; ++m) {
@@ -676,10 +701,8 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   }
 
   // H = eps + dSigma - E(t) e.d
-  double ef = 0.0;
+  const double ef = ef_stage;
   if (dyn) {
-    const double cs = (bp.stage == 0) ? 0.0 : (bp.stage == 3 ? 1.0 : 0.5);
-    ef = field_value(F, (double)step * bp.dt + cs * bp.dt);
 #pragma unroll
     for (int m = 0; m < TDG_NB_MAX; ++m) {
       if (m >= nb) break;
@@ -1054,6 +1077,15 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const size_t part_per_step = (size_t)batch * nk * 5 * sizeof(double);
   const int chunk = (int)std::min<size_t>(256, std::max<size_t>(1, OBS_PART_BUDGET / part_per_step));
   TDG_TRY(ws_reserve(ctx, WS_OBS_PART, part_per_step * chunk, &part));
+  // field at the stage times of one chunk of steps (refilled at each chunk start)
+  void* ftab = nullptr;
+  TDG_TRY(ws_reserve(ctx, WS_FTAB, (size_t)chunk * batch * 4 * sizeof(double), &ftab));
+  auto field_table = [&](int64_t step0) {
+    const int count = (int)std::min<int64_t>(chunk, max_steps - step0 + 1);
+    const int total = count * batch * 4;
+    hipLaunchKernelGGL(field_table_kernel, dim3((total + 255) / 256), dim3(256), 0, ctx->stream,
+                       (const tdg_field*)dfields, batch, (int)step0, count, dt, (double*)ftab);
+  };
   TDG_TRY(upload(ctx, WS_FIELDS, sorted.data(), sizeof(tdg_field) * batch, &dfields));
   TDG_TRY(upload(ctx, WS_PERM, perm.data(), sizeof(int) * batch, &dperm));
 
@@ -1101,6 +1133,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   sp.batch = batch;
   sp.dt = dt;
   sp.tr_signed = intra;
+  sp.ftab = (const double*)ftab;
   const int64_t split_stride = (int64_t)batch * zstride;
   sp.zsplit_stride = split_stride;
   // projection rows: the rank (low rank) or every off-diagonal channel's rows (channel-wise)
@@ -1188,6 +1221,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     bp.batch = batch;
     bp.dt = dt;
     bp.tr_signed = intra;
+    bp.ftab = (const double*)ftab;
     // stage kernel blocks: IB instances x nb rows, LDS for their H and rho blocks and row sums
     int IB = 16;  // instances per block: up to 64 for nb <= 4, matched to the batch
     while (model->nb <= 4 && IB < 64 && IB < batch) IB *= 2;
@@ -1362,6 +1396,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     int rc = TDG_OK;
     for (int64_t step = 0; step <= max_steps && rc == TDG_OK; ++step) {
       const int n_obs = count_ge(step), n_dyn = count_gt(step);
+      if (slot == 0) field_table(step);
       if (use_graphs && n_dyn > 0 && n_obs == n_dyn) {
         hipGraphExec_t ex = nullptr;
         for (auto& e : execs)
@@ -1440,6 +1475,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       TDG_TRY(hip_check(ctx, hipEventCreate(&ea), "tuner event"));
       TDG_TRY(hip_check(ctx, hipEventCreate(&eb), "tuner event"));
       const int dyn0 = count_gt(0);
+      field_table(0);
       sp.step = 0;
       sp.stage = 0;
       sp.obs_slot = 0;
@@ -1501,6 +1537,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   int64_t chunk_start = 0;
   for (int64_t step = 0; step <= max_steps; ++step) {
     const int n_obs = count_ge(step), n_dyn = count_gt(step);
+    if (slot == 0) field_table(step);
     sp.n_dyn = n_dyn;
     for (int s = 0; s < 4; ++s) {
       const int active = s == 0 ? n_obs : n_dyn;
