@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--large-grid-steps", type=int, default=40, help="RK4 steps per instance timed there")
     ap.add_argument("--no-channelwise", action="store_true", help="skip the channel-wise compression leg")
     ap.add_argument("--no-intraband", action="store_true", help="skip the intraband field-coupling leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--sweep-only", type=int, default=0, metavar="STEPS",
                     help="only run the batched 60x60 sweep, every instance for STEPS steps (for counter runs; "
                          "with --factors-cache the sweep's factors are cached as well)")
@@ -315,6 +316,7 @@ def main():
         torch.cuda.empty_cache()
         sweep = batched_sweep(P, abi, ctx, frac)
     large = large_grid(P, abi, args.large_grid_steps) if args.large_grid else None
+    adjoint = None if args.no_adjoint else adjoint_leg(P, ctx)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -360,6 +362,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_sweep": sweep,
         "large_grid": large,
+        "adjoint": adjoint,
     }
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -487,6 +490,45 @@ def large_grid(P, abi, steps):
     ctx.close()
     torch.cuda.empty_cache()
     return res
+
+
+def adjoint_leg(P, ctx):
+    """Gradient of the third-harmonic intensity of J on the differentiation
+    workload (24x24 e-h kernel, N = 2304, complex128 factors at 5 % of N, one
+    3000-step pulse, checkpoints every 50 steps): the forward propagation and
+    the adjoint pass timed separately."""
+    import numpy as np
+    import torch
+    from workloads import get_config
+
+    cfg = get_config(3)
+    m = cfg.model()
+    dm = P.DeviceModel.from_model(m)
+    fac = ctx.kernel_compress(ctx.kernel_build(dm, cfg.r0, "eh", "c128"), "fraction", 0.05)
+    fl = cfg.fields
+    nsteps = int(fl.nsteps[0])
+    ctx.propagate(fac, dm, "eh", fl, cfg.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.propagate(fac, dm, "eh", fl, cfg.dt)
+    torch.cuda.synchronize()
+    fwd_s = time.perf_counter() - t0
+    # L = |3 w dt sum_n J_n exp(-3 i w t_n)|^2 and its cotangent on J
+    j = res["J"][0].cpu().numpy()
+    om = float(fl.omega[0])
+    ph = np.exp(-3j * om * cfg.dt * np.arange(nsteps + 1))
+    a = 3.0 * om * cfg.dt * np.sum(j * ph)
+    gj = 2.0 * (np.conj(a) * 3.0 * om * cfg.dt * ph).real
+    ctx.propagate_adjoint(fac, dm, "eh", fl, cfg.dt, gJ=gj[None], checkpoint_every=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.propagate_adjoint(fac, dm, "eh", fl, cfg.dt, gJ=gj[None], checkpoint_every=50)
+    torch.cuda.synchronize()
+    adj_s = time.perf_counter() - t0
+    return {"workload": f"{cfg.name}: 24x24 k-grid, N={cfg.n}, complex128 low-rank factors rank {fac.rank}, "
+                        f"{nsteps} steps, checkpoints every 50; loss = third-harmonic intensity of J",
+            "forward_steps_per_s": nsteps / fwd_s, "gradient_steps_per_s": nsteps / adj_s,
+            "gradient_vs_forward_time": adj_s / fwd_s, "loss": float(abs(a) ** 2)}
 
 
 def cpu_baseline(cfg, frac, seconds):

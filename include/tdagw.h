@@ -376,12 +376,15 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * FP32 matrix products on the matrix cores (split-K partials summed by the
  * stage kernel); below it, every instance streams the operator itself. */
 #define TDG_OPT_BATCHED_MIN 2
-/* Tiling of the batched path's complex FP32 matrix-core products:
- * TDG_OPT_GEMM_VARIANT -1 (default) times the tilings on the first use of each
- * product shape (M, K, instances, split) and keeps the fastest for the
- * context; 0 = 64-row tiles, 1 = 64-row tiles with the next K tile prefetched
- * into registers and two LDS buffers, 2 = 128-row tiles.  The tilings differ
- * only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects 0 / 2. */
+/* Tiling and split-K of the batched path's complex matrix-core products:
+ * TDG_OPT_GEMM_VARIANT -1 (default) times, on the first use of each product
+ * shape (M, K, instances), every tiling with each of a few split-K widths (the
+ * default of about 1024 blocks, no split, and about 256 j blocks for j = 1..4)
+ * and keeps the fastest pair for the context.  FP32 tilings: 0 = 64-row tiles,
+ * 1 = 64-row tiles with the next K tile prefetched into registers and two LDS
+ * buffers, 2 = 128-row tiles; BF16X2 tilings 0 and 1 (see TDG_BF16X2).  A
+ * value >= 0 forces that tiling with the default split.  Tilings and splits
+ * differ only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects 0 / 2. */
 #define TDG_OPT_GEMM_TILE 3
 #define TDG_OPT_GEMM_VARIANT 4
 /* Batched path: 1 captures one RK4 step (products, stage kernels) per running

@@ -376,16 +376,39 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_pf(GemmArgs g) {
 }
 
 // out[i] = sum_s in[s * stride + i] for i < count (complex), fixed order.
-__global__ void __launch_bounds__(256) sum_slices_kernel(const float2* __restrict__ in, int slices, int64_t stride,
-                                                        int64_t count, float2* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
-    float2 v = make_float2(0.f, 0.f);
-    for (int sl = 0; sl < slices; ++sl) {
-      const float2 u = in[sl * stride + i];
-      v.x += u.x;
-      v.y += u.y;
+// Blocks of 64 outputs x 4 slice groups: thread (o, g) sums slices g, g + 4,
+// ... of its output pair (16-byte loads, four in flight), then the four group
+// sums are added in order.  count and stride are even (pairs of complex).
+__global__ void __launch_bounds__(256) sum_slices_kernel(const float4* __restrict__ in, int slices, int64_t stride2,
+                                                        int64_t count2, float4* __restrict__ out) {
+  __shared__ float4 red[4][64];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + o;
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (i < count2) {
+    int sl = g;
+    for (; sl + 12 < slices; sl += 16) {
+      const float4 a = in[sl * stride2 + i], b = in[(sl + 4) * stride2 + i], c = in[(sl + 8) * stride2 + i],
+                   d = in[(sl + 12) * stride2 + i];
+      v.x += a.x; v.y += a.y; v.z += a.z; v.w += a.w;
+      v.x += b.x; v.y += b.y; v.z += b.z; v.w += b.w;
+      v.x += c.x; v.y += c.y; v.z += c.z; v.w += c.w;
+      v.x += d.x; v.y += d.y; v.z += d.z; v.w += d.w;
     }
-    out[i] = v;
+    for (; sl < slices; sl += 4) {
+      const float4 a = in[sl * stride2 + i];
+      v.x += a.x; v.y += a.y; v.z += a.z; v.w += a.w;
+    }
+  }
+  red[g][o] = v;
+  __syncthreads();
+  if (g == 0 && i < count2) {
+    float4 r = red[0][o];
+    for (int q = 1; q < 4; ++q) {
+      const float4 a = red[q][o];
+      r.x += a.x; r.y += a.y; r.z += a.z; r.w += a.w;
+    }
+    out[i] = r;
   }
 }
 
@@ -394,9 +417,10 @@ __global__ void __launch_bounds__(256) sum_slices_kernel(const float2* __restric
 namespace tdg {
 
 void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stride, int64_t count, void* out) {
-  const int64_t blocks = std::min<int64_t>(4096, (count + 255) / 256);
+  // pairs of complex values: count and stride are even (the batched row stride is)
+  const int64_t count2 = count / 2, blocks = (count2 + 63) / 64;
   hipLaunchKernelGGL(sum_slices_kernel, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, stream,
-                     (const float2*)in, slices, stride, count, (float2*)out);
+                     (const float4*)in, slices, stride / 2, count2, (float4*)out);
 }
 
 int cgemm_f32_kslices(int kc) { return (kc + BKC - 1) / BKC; }

@@ -121,7 +121,8 @@ void split_bf16x2(hipStream_t stream, const void* src, int src_is_double, int64_
 void covariant_derivative(hipStream_t stream, const tdg_model* model, const void* y, int64_t sb, int64_t sk,
                           int64_t se, const tdg_field* fields, int batch, void* out, hipEvent_t ea = nullptr,
                           hipEvent_t eb = nullptr);
-// out = sum of `slices` complex64 arrays of `count` elements, `stride` apart.
+// out = sum of `slices` complex64 arrays of `count` elements, `stride` apart
+// (count, stride even; in and out 16-byte aligned).
 void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stride, int64_t count, void* out);
 
 }  // namespace tdg

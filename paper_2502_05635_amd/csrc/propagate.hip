@@ -582,6 +582,13 @@ struct BatchParams {
 };
 
 // The step counter of graph replays (vector stores: the address depends on the lane).
+// A fixed non-zero operand for timing the products (the step-0 gather of
+// rho_eq is all zeros): element i = ((i % 13) - 6) * 1e-3 (1 + i).
+__global__ void pattern_fill_kernel(float2* x, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = make_float2((float)((i % 13) - 6) * 1e-3f, (float)((i % 7) - 3) * 1e-3f);
+}
+
 __global__ void set_step_kernel(int* c, int v) {
   const int t = threadIdx.x;
   if (t == 0) c[t] = v;
@@ -1182,20 +1189,21 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     void* Ybuf = nullptr;
     void* Zbuf = nullptr;
     void* Zsum = nullptr;
+    // the buffers hold up to twice the default number of slices (tuner range)
     if (!lowrank) {
       ks_main = kslice_for(n, n);
       y_slices = (int)((n + ks_main - 1) / ks_main);
-      TDG_TRY(ws_reserve(ctx, WS_Y, (size_t)y_slices * n * ldy * 8, &Ybuf));
+      TDG_TRY(ws_reserve(ctx, WS_Y, (size_t)2 * y_slices * n * ldy * 8, &Ybuf));
     } else {
       ks_proj = kslice_for(op->rank, n);
       z_slices = (int)((n + ks_proj - 1) / ks_proj);
-      TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)z_slices * op->rank * ldy * 8, &Zbuf));
+      TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)2 * z_slices * op->rank * ldy * 8, &Zbuf));
       // the expansion has few K columns (the rank): split it too, at most 8
       // ways, and let the stage kernel sum the slices it reads
       ks_main = std::max<int64_t>(kslice_for(n, op->rank), (op->rank + 7) / 8);
       ks_main = (ks_main + 31) / 32 * 32;
       y_slices = (int)((op->rank + ks_main - 1) / ks_main);
-      TDG_TRY(ws_reserve(ctx, WS_Y, (size_t)y_slices * n * ldy * 8, &Ybuf));
+      TDG_TRY(ws_reserve(ctx, WS_Y, (size_t)2 * y_slices * n * ldy * 8, &Ybuf));
       TDG_TRY(ws_reserve(ctx, WS_ZSUM, (size_t)op->rank * ldy * 8, &Zsum));
     }
     BatchParams bp = {};
@@ -1227,9 +1235,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     while (model->nb <= 4 && IB < 64 && IB < batch) IB *= 2;
     const size_t stage_lds = (size_t)2 * nb2 * IB * sizeof(double2) + (size_t)5 * model->nb * IB * sizeof(double);
 
-    // tiling of each FP32 product: forced, cached for its shape, or timed now
-    // (every tiling twice on the step-0 operands, the second run timed); the
-    // products only write Y / Z, which the loop below recomputes
+    // tiling and split-K of each product (pick below): the tuner runs the
+    // products on the step-0 operands; they only write Y / Z, which the loop
+    // below recomputes
     int gv_main = 0, gv_proj = 0;
     const int n_dyn0 = count_gt(0);
     // BF16X2: the second tiling needs X split once into a bf16 work array
@@ -1237,79 +1245,124 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     if (bf16) TDG_TRY(ws_reserve(ctx, WS_XB, cgemm_bf16x2_work_bytes((int)n, batch), &xbw));
     const int ntilings = bf16 ? 2 : 3;
     if (n_dyn0 > 0) {
-      auto pick = [&](const char* what, int64_t M, int64_t Kc, int64_t ks, const std::function<void(int)>& run,
-                      int* out) -> int {
+      // Split-K candidates: the default (about 1024 blocks), no split, twice
+      // the default, and slice counts that put about 256 j blocks (j = 1..4)
+      // on the 256 CUs; at most twice the default (the buffers' size).
+      auto split_options = [&](int64_t M, int64_t Kc, int64_t ks_def) {
+        const int64_t tiles = ((M + tile - 1) / tile) * ((n_dyn0 + 63) / 64);
+        const int64_t s_def = (Kc + ks_def - 1) / ks_def;
+        std::vector<int64_t> out{ks_def};
+        std::vector<int64_t> counts{1, 2 * s_def};
+        for (int j = 1; j <= 4; ++j) counts.push_back((256 * j) / tiles);
+        for (int64_t sc : counts) {
+          if (sc < 1 || sc > 2 * s_def) continue;
+          const int64_t ks = std::max<int64_t>(32, ((Kc + sc - 1) / sc + 31) / 32 * 32);
+          if (std::find(out.begin(), out.end(), ks) == out.end()) out.push_back(ks);
+        }
+        return out;
+      };
+      // tiling v and slice width ks of one product: forced tiling (default
+      // split), cached for its shape, or timed now (each pair once to warm up,
+      // then twice, the fastest pair kept; the projection's timing includes
+      // the sum of its slices)
+      auto pick = [&](const char* what, int64_t M, int64_t Kc, int64_t ks_def,
+                      const std::function<void(int, int64_t)>& run, int* out_v, int64_t* out_ks) -> int {
+        *out_ks = ks_def;
         if (ctx->gemm_variant >= 0) {
-          *out = std::min(ctx->gemm_variant, ntilings - 1);
+          *out_v = std::min(ctx->gemm_variant, ntilings - 1);
           return TDG_OK;
         }
         char key[160];
         snprintf(key, sizeof(key), "gemm/%s/%s/%lld/%lld/%d/%lld", bf16 ? "bf16x2" : "f32", what, (long long)M,
-                 (long long)Kc, n_dyn0, (long long)ks);
+                 (long long)Kc, n_dyn0, (long long)ks_def);
         for (auto& kv : ctx->tuned)
           if (kv.first == key) {
-            *out = kv.second;
+            *out_v = kv.second % 4;
+            *out_ks = kv.second / 4;
             return TDG_OK;
           }
         hipEvent_t e0, e1;
         TDG_TRY(hip_check(ctx, hipEventCreate(&e0), "event"));
         TDG_TRY(hip_check(ctx, hipEventCreate(&e1), "event"));
-        float best = 0.f;
+        const std::vector<int64_t> opts = split_options(M, Kc, ks_def);
+        std::vector<float> tmin(opts.size() * ntilings, 1e30f);
+        for (int round = 0; round < 3; ++round)
+          for (size_t oi = 0; oi < opts.size(); ++oi)
+            for (int v = 0; v < ntilings; ++v) {
+              run(v, opts[oi]);
+              hipEventRecord(e0, ctx->stream);
+              run(v, opts[oi]);
+              run(v, opts[oi]);
+              hipEventRecord(e1, ctx->stream);
+              TDG_TRY(hip_check(ctx, hipEventSynchronize(e1), "GEMM tuning"));
+              float ms = 0.f;
+              hipEventElapsedTime(&ms, e0, e1);
+              float& m = tmin[oi * ntilings + v];
+              m = std::min(m, ms);
+            }
+        float best = 1e30f;
         int bestv = 0;
-        for (int v = 0; v < ntilings; ++v) {
-          run(v);
-          hipEventRecord(e0, ctx->stream);
-          run(v);
-          hipEventRecord(e1, ctx->stream);
-          TDG_TRY(hip_check(ctx, hipEventSynchronize(e1), "GEMM tuning"));
-          float ms = 0.f;
-          hipEventElapsedTime(&ms, e0, e1);
-          if (v == 0 || ms < best) {
-            best = ms;
-            bestv = v;
-          }
-        }
+        int64_t bestks = ks_def;
+        for (size_t oi = 0; oi < opts.size(); ++oi)
+          for (int v = 0; v < ntilings; ++v)
+            if (tmin[oi * ntilings + v] < best) {
+              best = tmin[oi * ntilings + v];
+              bestv = v;
+              bestks = opts[oi];
+            }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         TDG_TRY(launch_check(ctx, "GEMM tuning"));
-        ctx->tuned.emplace_back(key, bestv);
-        *out = bestv;
+        ctx->tuned.emplace_back(key, (int)(bestks * 4 + bestv));
+        *out_v = bestv;
+        *out_ks = bestks;
         return TDG_OK;
       };
+      // timing operand: a non-zero pattern in the second gather buffer, which
+      // stage 0 of step 0 overwrites
+      void* xt = x1;
+      hipLaunchKernelGGL(pattern_fill_kernel, dim3(1024), dim3(256), 0, ctx->stream, (float2*)xt,
+                         (int64_t)n * xstride);
       const int64_t ld_us0 = bf16 ? (op->rank + 3) / 4 * 4 : op->rank;
       if (!lowrank) {
-        TDG_TRY(pick("dense", n, n, ks_main, [&](int v) {
+        TDG_TRY(pick("dense", n, n, ks_main, [&](int v, int64_t ks) {
           if (bf16)
-            cgemm_bf16x2(ctx->stream, op->K, op->ld, (int)n, (int)n, x0, xstride, Ybuf, ldy, n * ldy, n_dyn0,
-                         (int)ks_main, v, xbw);
+            cgemm_bf16x2(ctx->stream, op->K, op->ld, (int)n, (int)n, xt, xstride, Ybuf, ldy, n * ldy, n_dyn0,
+                         (int)ks, v, xbw);
           else
-            cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, x0, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn0,
-                      (int)ks_main, v);
-        }, &gv_main));
+            cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xt, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn0,
+                      (int)ks, v);
+        }, &gv_main, &ks_main));
+        y_slices = (int)((n + ks_main - 1) / ks_main);
       } else {
-        TDG_TRY(pick("project", op->rank, n, ks_proj, [&](int v) {
+        TDG_TRY(pick("project", op->rank, n, ks_proj, [&](int v, int64_t ks) {
           if (bf16)
-            cgemm_bf16x2(ctx->stream, op->w, n, (int)op->rank, (int)n, x0, xstride, Zbuf, ldy, op->rank * ldy,
-                         n_dyn0, (int)ks_proj, v, xbw);
+            cgemm_bf16x2(ctx->stream, op->w, n, (int)op->rank, (int)n, xt, xstride, Zbuf, ldy, op->rank * ldy,
+                         n_dyn0, (int)ks, v, xbw);
           else
-            cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, x0, xstride, 1, 0, Zbuf, ldy, op->rank * ldy,
-                      n_dyn0, (int)ks_proj, v);
-        }, &gv_proj));
-        sum_slices_c64(ctx->stream, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
-        TDG_TRY(pick("expand", n, op->rank, ks_main, [&](int v) {
+            cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xt, xstride, 1, 0, Zbuf, ldy, op->rank * ldy,
+                      n_dyn0, (int)ks, v);
+          sum_slices_c64(ctx->stream, Zbuf, (int)((n + ks - 1) / ks), op->rank * ldy, op->rank * ldy, Zsum);
+        }, &gv_proj, &ks_proj));
+        z_slices = (int)((n + ks_proj - 1) / ks_proj);
+        // Zsum now holds the step-0 projection (the expansion's timing input)
+        TDG_TRY(pick("expand", n, op->rank, ks_main, [&](int v, int64_t ks) {
           if (bf16)
             cgemm_bf16x2(ctx->stream, op->us, ld_us0, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn0,
-                         (int)ks_main, v, xbw);
+                         (int)ks, v, xbw);
           else
             cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy,
-                      n_dyn0, (int)ks_main, v);
-        }, &gv_main));
+                      n_dyn0, (int)ks, v);
+        }, &gv_main, &ks_main));
+        y_slices = (int)((op->rank + ks_main - 1) / ks_main);
       }
+      bp.y_slices = y_slices;
     }
     ctx->last_variant = std::string(lowrank ? "batched_mfma_lowrank_" : "batched_mfma_dense_") +
                         (bf16 ? "bf16x2" : "f32");
-    ctx->last_variant += lowrank ? " (tilings " + std::to_string(gv_proj) + "/" + std::to_string(gv_main) + ")"
-                                 : " (tiling " + std::to_string(gv_main) + ")";
+    ctx->last_variant += lowrank ? " (tilings " + std::to_string(gv_proj) + "/" + std::to_string(gv_main) +
+                                       ", slices " + std::to_string(z_slices) + "/" + std::to_string(y_slices) + ")"
+                                 : " (tiling " + std::to_string(gv_main) + ", slices " + std::to_string(y_slices) + ")";
     if (ctx->graphs && !ctx->prof) ctx->last_variant += " graphs";
     tdg_obs ob = *obs;
     void* dstep = nullptr;
