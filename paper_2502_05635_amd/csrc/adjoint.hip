@@ -495,18 +495,33 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     return TDG_OK;
   };
   const rocblas_operation NN = rocblas_operation_none, TR = rocblas_operation_transpose;
+  // C[:, b] = op(A) B[:, b] for every instance b (A column-major m_ x k_ with
+  // op = N, or k_ x m_ with op = T).  With few instances the product is a
+  // matrix-vector product per instance: one strided-batched GEMV sharing A
+  // (a GEMM tile of 64 columns would hold one useful column and stream all
+  // of K through two work-groups).
+  auto prod = [&](rocblas_operation ta, int64_t m_, int64_t k_, const void* A, int64_t lda, const void* B,
+                  void* C) -> int {
+    if (batch > 8) return gemm(ta, NN, m_, batch, k_, A, lda, B, k_, &zero, C, m_);
+    const bool tr = ta == TR;
+    const rocblas_status st = rocblas_zgemv_strided_batched_64(
+        h, ta, tr ? k_ : m_, tr ? m_ : k_, &one, (const rocblas_double_complex*)A, lda, 0,
+        (const rocblas_double_complex*)B, 1, k_, &zero, (rocblas_double_complex*)C, 1, m_, batch);
+    if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_zgemv status %d", (int)st);
+    return TDG_OK;
+  };
   // S = K X (dense) or Z = W X, S = US Z (low rank); K, W, US row-major
   auto apply_k = [&](const double2* X, double2* S, double2* Z) -> int {
-    if (!lowrank) return gemm(TR, NN, n, batch, n, op->K, op->ld, X, n, &zero, S, n);
-    TDG_TRY(gemm(TR, NN, rank, batch, n, op->w, n, X, n, &zero, Z, rank));
-    return gemm(TR, NN, n, batch, rank, op->us, rank, Z, rank, &zero, S, n);
+    if (!lowrank) return prod(TR, n, n, op->K, op->ld, X, S);
+    TDG_TRY(prod(TR, rank, n, op->w, n, X, Z));
+    return prod(TR, n, rank, op->us, rank, Z, S);
   };
   // T with K^H sbar = conj(T) (+ K_diag term in the kernel): T = K^T conj(sbar), or
   // Uc = US^T conj(sbar) = conj(US^H sbar), T = W^T Uc
   auto apply_kh = [&](const double2* Sbc, double2* Uc) -> int {
-    if (!lowrank) return gemm(NN, NN, n, batch, n, op->K, op->ld, Sbc, n, &zero, TT, n);
-    TDG_TRY(gemm(NN, NN, rank, batch, n, op->us, rank, Sbc, n, &zero, Uc, rank));
-    return gemm(NN, NN, n, batch, rank, op->w, n, Uc, rank, &zero, TT, n);
+    if (!lowrank) return prod(NN, n, n, op->K, op->ld, Sbc, TT);
+    TDG_TRY(prod(NN, rank, n, op->us, rank, Sbc, Uc));
+    return prod(NN, n, rank, op->w, n, Uc, TT);
   };
 
   const int kpb = AT / nb2;
