@@ -376,6 +376,23 @@ __global__ void fill_zero_kernel(double* p, int64_t count) {
     p[i] = 0.0;
 }
 
+// out[j][i] = in[i][j] for in [rows][cols] row-major (32 x 32 tiles through LDS).
+__global__ void __launch_bounds__(256) transpose_kernel(const double2* __restrict__ in, int64_t rows, int64_t cols,
+                                                        double2* __restrict__ out) {
+  __shared__ double2 tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t r = r0 + q, c = c0 + tx;
+    if (r < rows && c < cols) tile[q][tx] = in[r * cols + c];
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t c = c0 + q, r = r0 + tx;
+    if (r < rows && c < cols) out[c * rows + r] = tile[tx][q];
+  }
+}
+
 __global__ void conj_kernel(double2* p, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i].y = -p[i].y;
@@ -449,6 +466,10 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
                o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
                o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)4 * batch * nk * sizeof(double)),
                o_df = cv.take((size_t)batch * 4 * sizeof(double)), o_f = cv.take((size_t)batch * sizeof(tdg_field));
+  // low rank, few instances: S transposed ([rank][n]) so that S^T conj(sbar) is a
+  // transposed matrix-vector product (rank output rows are too few to spread)
+  const bool use_ust = lowrank && batch <= 8;
+  const size_t o_ust = cv.take(use_ust ? (size_t)n * rank * sizeof(double2) : 0);
   // intraband term: D of a stage state, of abar and of ybar
   const bool intra = model->links != nullptr;
   const size_t o_dy = cv.take(intra ? st_b : 0), o_da = cv.take(intra ? st_b : 0), o_dyb = cv.take(intra ? st_b : 0);
@@ -460,6 +481,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
           *YBAR = P2(o_ybar), *YD = P2(o_yd), *ACCA = P2(o_acca), *SS = P2(o_s), *XS = P2(o_x), *SBC = P2(o_sbc),
           *TT = P2(o_t), *ZS = P2(o_z), *UC = P2(o_uc);
   double2 *DY = intra ? P2(o_dy) : nullptr, *DA = intra ? P2(o_da) : nullptr, *DYB = intra ? P2(o_dyb) : nullptr;
+  double2* UST = use_ust ? P2(o_ust) : nullptr;
   double* part = (double*)(wb + o_part);
   double* dfacc = (double*)(wb + o_df);
   tdg_field* dfields = (tdg_field*)(wb + o_f);
@@ -520,9 +542,14 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   // Uc = US^T conj(sbar) = conj(US^H sbar), T = W^T Uc
   auto apply_kh = [&](const double2* Sbc, double2* Uc) -> int {
     if (!lowrank) return prod(NN, n, n, op->K, op->ld, Sbc, TT);
-    TDG_TRY(prod(NN, rank, n, op->us, rank, Sbc, Uc));
+    TDG_TRY(use_ust ? prod(TR, rank, n, UST, n, Sbc, Uc) : prod(NN, rank, n, op->us, rank, Sbc, Uc));
     return prod(NN, n, rank, op->w, n, Uc, TT);
   };
+  if (use_ust) {
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((rank + 31) / 32), (unsigned)((n + 31) / 32)), dim3(256), 0,
+                       ctx->stream, (const double2*)op->us, n, rank, UST);
+    TDG_TRY(launch_check(ctx, "transpose launch"));
+  }
 
   const int kpb = AT / nb2;
   const dim3 grid((unsigned)((nk + kpb - 1) / kpb), (unsigned)batch);
