@@ -610,12 +610,17 @@ __device__ inline size_t bidx(const BatchParams& bp, int k, int e, int b) {
 // (instance group * IB + i) and row n = t / IB, and owns the row's elements
 // (n, m), m = 0 .. nb-1.  The instances' H and rho blocks are staged in LDS as
 // [element][lane] (dynamic, 2 nb^2 IB double2 + 5 nb IB double).
+// NBT: a bound on nb (4 or TDG_NB_MAX) sizing the per-thread row arrays.  The
+// observable sums [5][nb][IB] share the H blocks' LDS when they fit (nb >= 3):
+// they are consumed before H is built.
+template <int NBT>
 __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   extern __shared__ double2 dyn_lds[];
   const int nb = bp.nb, nb2 = nb * nb, IB = blockDim.x / nb;
   double2* s_rho = dyn_lds;
   double2* s_h = dyn_lds + nb2 * IB;
-  double* s_o = reinterpret_cast<double*>(dyn_lds + 2 * nb2 * IB);  // [5][nb][IB]
+  const bool o_shared = nb >= 3;
+  double* s_o = reinterpret_cast<double*>(o_shared ? s_h : dyn_lds + 2 * nb2 * IB);  // [5][nb][IB]
   const int i = threadIdx.x % IB, n = threadIdx.x / IB;
   const int k = blockIdx.x, b = blockIdx.y * IB + i;
   const bool act = b < bp.n_active, dyn = act && b < bp.n_dyn;
@@ -627,9 +632,9 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   tdg_field F = {};
   if (act) F = bp.fields[b];
   const double ef_stage = dyn ? bp.ftab[((size_t)obs_slot * bp.batch + b) * 4 + bp.stage] : 0.0;
-  double2 r_n[TDG_NB_MAX], r_acc[TDG_NB_MAX], ds[TDG_NB_MAX];
+  double2 r_n[NBT], r_acc[NBT], ds[NBT];
 #pragma unroll
-  for (int m = 0; m < TDG_NB_MAX; ++m) {
+  for (int m = 0; m < NBT; ++m) {
     if (m >= nb) break;
     const int e = n * nb + m;
     double2 rs = make_double2(0.0, 0.0);
@@ -673,7 +678,7 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
     double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (act) {
 #pragma unroll
-      for (int m = 0; m < TDG_NB_MAX; ++m) {
+      for (int m = 0; m < NBT; ++m) {
         if (m >= nb) break;
         const int e = n * nb + m;
         const size_t base = (size_t)k * nb2 + e;
@@ -707,11 +712,14 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
     }
   }
 
+  // the observable sums share LDS with the H blocks written next
+  if (o_shared && bp.stage == 0 && bp.obs_part) __syncthreads();
+
   // H = eps + dSigma - E(t) e.d
   const double ef = ef_stage;
   if (dyn) {
 #pragma unroll
-    for (int m = 0; m < TDG_NB_MAX; ++m) {
+    for (int m = 0; m < NBT; ++m) {
       if (m >= nb) break;
       const int e = n * nb + m;
       const size_t base = (size_t)k * nb2 + e;
@@ -726,7 +734,7 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
 
   // f = -i [H, rho], RK4 stage, next drho gather
 #pragma unroll
-  for (int m = 0; m < TDG_NB_MAX; ++m) {
+  for (int m = 0; m < NBT; ++m) {
     if (m >= nb) break;
     const int e = n * nb + m;
     double2 c = make_double2(0.0, 0.0);
@@ -1233,7 +1241,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     // stage kernel blocks: IB instances x nb rows, LDS for their H and rho blocks and row sums
     int IB = 16;  // instances per block: up to 64 for nb <= 4, matched to the batch
     while (model->nb <= 4 && IB < 64 && IB < batch) IB *= 2;
-    const size_t stage_lds = (size_t)2 * nb2 * IB * sizeof(double2) + (size_t)5 * model->nb * IB * sizeof(double);
+    // H and rho blocks; the observable sums share the H blocks' space when they fit (nb >= 3)
+    const size_t stage_lds = (size_t)2 * nb2 * IB * sizeof(double2) +
+                             (model->nb >= 3 ? 0 : (size_t)5 * model->nb * IB * sizeof(double));
 
     // tiling and split-K of each product (pick below): the tuner runs the
     // products on the step-0 operands; they only write Y / Z, which the loop
@@ -1419,8 +1429,12 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
           covariant_derivative(st, model, rho_s, 1, (int64_t)nb2 * xstride, xstride, (const tdg_field*)dfields, n_dyn,
                                dintra);
         if (prof) prof_begin(ctx, TDG_KCLASS_STAGE);
-        hipLaunchKernelGGL(batched_stage_kernel, dim3(nk, (active + IB - 1) / IB), dim3(IB * model->nb), stage_lds,
-                           st, bp);
+        if (model->nb <= 4)
+          hipLaunchKernelGGL(batched_stage_kernel<4>, dim3(nk, (active + IB - 1) / IB), dim3(IB * model->nb),
+                             stage_lds, st, bp);
+        else
+          hipLaunchKernelGGL(batched_stage_kernel<TDG_NB_MAX>, dim3(nk, (active + IB - 1) / IB),
+                             dim3(IB * model->nb), stage_lds, st, bp);
         if (prof) prof_end(ctx, TDG_KCLASS_STAGE);
         std::swap(xc, xn);
       }
