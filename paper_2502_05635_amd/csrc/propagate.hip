@@ -609,10 +609,11 @@ __device__ inline size_t bidx(const BatchParams& bp, int k, int e, int b) {
 // One block per (k point, group of IB instances): thread t has lane i = t % IB
 // (instance group * IB + i) and row n = t / IB, and owns the row's elements
 // (n, m), m = 0 .. nb-1.  The instances' H and rho blocks are staged in LDS as
-// [element][lane] (dynamic, 2 nb^2 IB double2 + 5 nb IB double).
+// [element][lane] (dynamic LDS: 2 nb^2 IB double2), followed by the k point's
+// dipole and velocity planes and band energies (4 nb^2 double2 + nb double).
 // NBT: a bound on nb (4 or TDG_NB_MAX) sizing the per-thread row arrays.  The
 // observable sums [5][nb][IB] share the H blocks' LDS when they fit (nb >= 3):
-// they are consumed before H is built.
+// they are consumed before H is built; otherwise they follow the H blocks.
 template <int NBT>
 __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   extern __shared__ double2 dyn_lds[];
@@ -628,6 +629,19 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   const int obs_slot = bp.step_dev ? step % bp.chunk : bp.obs_slot;
   const int P = bp.npair;
   const size_t plane = (size_t)bp.nk * nb2;
+  // this k point's dipole planes, velocity planes (stage 0) and band energies,
+  // shared by the block's instances: [dx][dy][vx][vy] blocks, then eps
+  double2* s_d = dyn_lds + 2 * nb2 * IB + (o_shared ? 0 : (5 * nb * IB + 1) / 2);
+  double* s_eps = reinterpret_cast<double*>(s_d + 4 * nb2);
+  const bool want_obs = bp.stage == 0 && bp.obs_part;
+  for (int q = threadIdx.x; q < 4 * nb2; q += blockDim.x) {
+    const int pl = q / nb2, e = q - pl * nb2;
+    if (pl < 2)
+      s_d[q] = bp.dip[pl * plane + (size_t)k * nb2 + e];
+    else if (want_obs)
+      s_d[q] = bp.vel[(pl - 2) * plane + (size_t)k * nb2 + e];
+  }
+  if (threadIdx.x < nb) s_eps[threadIdx.x] = bp.eps[(size_t)k * nb + threadIdx.x];
 
   tdg_field F = {};
   if (act) F = bp.fields[b];
@@ -674,16 +688,15 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   __syncthreads();
 
   // observables of rho(t_n), per (k, instance): row sums, then a fixed-order sum over rows
-  if (bp.stage == 0 && bp.obs_part) {
+  if (want_obs) {
     double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (act) {
 #pragma unroll
       for (int m = 0; m < NBT; ++m) {
         if (m >= nb) break;
         const int e = n * nb + m;
-        const size_t base = (size_t)k * nb2 + e;
-        const double2 de = proj_e(F, bp.dip[base], bp.dip[plane + base]);
-        const double2 ve = proj_e(F, bp.vel[base], bp.vel[plane + base]);
+        const double2 de = proj_e(F, s_d[e], s_d[nb2 + e]);
+        const double2 ve = proj_e(F, s_d[2 * nb2 + e], s_d[3 * nb2 + e]);
         const double2 rmn = s_rho[(m * nb + n) * IB + i], rnm = s_rho[e * IB + i];
         o[0] += de.x * rmn.x - de.y * rmn.y;
         o[1] += ve.x * rmn.x - ve.y * rmn.y;
@@ -713,7 +726,7 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   }
 
   // the observable sums share LDS with the H blocks written next
-  if (o_shared && bp.stage == 0 && bp.obs_part) __syncthreads();
+  if (o_shared && want_obs) __syncthreads();
 
   // H = eps + dSigma - E(t) e.d
   const double ef = ef_stage;
@@ -722,10 +735,9 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
     for (int m = 0; m < NBT; ++m) {
       if (m >= nb) break;
       const int e = n * nb + m;
-      const size_t base = (size_t)k * nb2 + e;
-      const double2 de = proj_e(F, bp.dip[base], bp.dip[plane + base]);
+      const double2 de = proj_e(F, s_d[e], s_d[nb2 + e]);
       double2 h = make_double2(ds[m].x - ef * de.x, ds[m].y - ef * de.y);
-      if (n == m) h.x += bp.eps[(size_t)k * nb + n];
+      if (n == m) h.x += s_eps[n];
       s_h[e * IB + i] = h;
     }
   }
@@ -1243,7 +1255,8 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     while (model->nb <= 4 && IB < 64 && IB < batch) IB *= 2;
     // H and rho blocks; the observable sums share the H blocks' space when they fit (nb >= 3)
     const size_t stage_lds = (size_t)2 * nb2 * IB * sizeof(double2) +
-                             (model->nb >= 3 ? 0 : (size_t)5 * model->nb * IB * sizeof(double));
+                             (model->nb >= 3 ? 0 : (size_t)(5 * model->nb * IB + 1) / 2 * sizeof(double2)) +
+                             (size_t)4 * nb2 * sizeof(double2) + (size_t)model->nb * sizeof(double);
 
     // tiling and split-K of each product (pick below): the tuner runs the
     // products on the step-0 operands; they only write Y / Z, which the loop
