@@ -4,9 +4,8 @@
 //
 //   Y[s][i][b] = sum_{c in slice s} A[i][c] * X[c][b]      (complex)
 //
-// A is row-major complex [M][lda]; X is complex [Kc][ldx], optionally the sum
-// of several slices (the split-K partials of a previous product); b runs over
-// the first ncols instances.  The complex product is done as one real product
+// A is row-major complex [M][lda]; X is complex [Kc][ldx]; b runs over the
+// first ncols instances.  The complex product is done as one real product
 // on v_mfma_f32_32x32x2f32: A viewed as real [M][2Kc] (re, im interleaved)
 // times the real expansion
 //     Xr[2c][b] = Re x,  Xr[2c+1][b] = -Im x,  Xr[2c][64+b] = Im x,  Xr[2c+1][64+b] = Re x
@@ -38,14 +37,55 @@ struct GemmArgs {
   int M, Kc;
   const float2* X;
   int64_t ldx;
-  int x_slices;
-  int64_t x_slice_stride;
   float2* Y;
   int64_t ldy;
   int64_t y_slice_stride;
   int ncols;
   int kslice;
 };
+
+// Tile loads only issue loads into zero-initialised registers; masking and
+// recombination happen when the tile is written to LDS.  A prefetched tile's
+// loads are then not waited for before the current tile's products (a value
+// combined right after its load forces the wait there).
+
+// Instances b .. b + 3 of complex row kx of X (raw; zero where out of range).
+__device__ inline void x_load(const GemmArgs& g, int kx, int kc_end, int b, float4& x01, float4& x23) {
+  x01 = make_float4(0.f, 0.f, 0.f, 0.f);
+  x23 = x01;
+  if (kx < kc_end && b < g.ncols) {
+    const float2* src = g.X + (int64_t)kx * g.ldx + b;
+    x01 = *reinterpret_cast<const float4*>(src);
+    if (b + 2 < g.ncols) x23 = *reinterpret_cast<const float4*>(src + 2);
+  }
+}
+// The four instances of a raw X load, those at or beyond ncols zeroed.
+__device__ inline void x_mask(const GemmArgs& g, int b, float4 x01, float4 x23, float2 (&xv)[4]) {
+  xv[0] = make_float2(x01.x, x01.y);
+  xv[1] = (b + 1 < g.ncols) ? make_float2(x01.z, x01.w) : make_float2(0.f, 0.f);
+  xv[2] = (b + 2 < g.ncols) ? make_float2(x23.x, x23.y) : make_float2(0.f, 0.f);
+  xv[3] = (b + 3 < g.ncols) ? make_float2(x23.z, x23.w) : make_float2(0.f, 0.f);
+}
+// Complex columns kc, kc + 1 of row gi of A as one 16-byte load, or the last
+// column alone when kc + 1 is past the slice (raw; zero out of range).
+__device__ inline void a_load2(const GemmArgs& g, int gi, int kc, int kc_end, float4& v, float2& tail) {
+  // two independent predicated loads (nested branches made the compiler wait
+  // for one load before issuing the next)
+  v = make_float4(0.f, 0.f, 0.f, 0.f);
+  tail = make_float2(0.f, 0.f);
+  const float2* src = g.A + (int64_t)gi * g.lda + kc;
+  if (gi < g.M && kc + 1 < kc_end) v = *reinterpret_cast<const float4*>(src);
+  if (gi < g.M && kc + 1 == kc_end) tail = *src;
+}
+__device__ inline void a_pair(int kc, int kc_end, float4 v, float2 tail, float2& lo, float2& hi) {
+  if (kc + 1 < kc_end) {
+    lo = make_float2(v.x, v.y);
+    hi = make_float2(v.z, v.w);
+  } else {
+    lo = tail;
+    hi = make_float2(0.f, 0.f);
+  }
+}
 
 __global__ void __launch_bounds__(256) cgemm_f32_mfma(GemmArgs g) {
   __shared__ float As[BM][2 * BKC + APAD];
@@ -70,19 +110,9 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma(GemmArgs g) {
       const int kc = kc0 + acol + q;
       av[q] = (gi < g.M && kc < kc_end) ? g.A[(int64_t)gi * g.lda + kc] : make_float2(0.f, 0.f);
     }
-    const int kx = kc0 + xrow;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = b0 + xcol + q;
-      float2 v = make_float2(0.f, 0.f);
-      if (kx < kc_end && b < g.ncols)
-        for (int sl = 0; sl < g.x_slices; ++sl) {
-          const float2 u = g.X[sl * g.x_slice_stride + (int64_t)kx * g.ldx + b];
-          v.x += u.x;
-          v.y += u.y;
-        }
-      xv[q] = v;
-    }
+    float4 x01, x23;
+    x_load(g, kc0 + xrow, kc_end, b0 + xcol, x01, x23);
+    x_mask(g, b0 + xcol, x01, x23, xv);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       As[arow][2 * (acol + q)] = av[q].x;
@@ -146,25 +176,16 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_128(GemmArgs g) {
   const int arow = t >> 1, acol = (t & 1) * 8;
   const int xrow = t >> 4, xcol = (t & 15) * 4;
   const int gi = m0 + arow;
-  float2 av[8], xv[4];
+  // raw loads of the tile in flight (see a_load2 / x_load) and its first column
+  float4 ar[4], xr01, xr23;
+  float2 at[4], av[8], xv[4];
+  int kc_tile = kc_begin;
 
   auto load_tile = [&](int kc0) {
+    kc_tile = kc0;
     if (AVEC) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kc = kc0 + acol + 2 * q;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gi < g.M) {
-          if (kc + 1 < kc_end) {
-            v = *reinterpret_cast<const float4*>(g.A + (int64_t)gi * g.lda + kc);
-          } else if (kc < kc_end) {
-            const float2 u = g.A[(int64_t)gi * g.lda + kc];
-            v = make_float4(u.x, u.y, 0.f, 0.f);
-          }
-        }
-        av[2 * q] = make_float2(v.x, v.y);
-        av[2 * q + 1] = make_float2(v.z, v.w);
-      }
+      for (int q = 0; q < 4; ++q) a_load2(g, gi, kc0 + acol + 2 * q, kc_end, ar[q], at[q]);
     } else {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -172,36 +193,14 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_128(GemmArgs g) {
         av[q] = (gi < g.M && kc < kc_end) ? g.A[(int64_t)gi * g.lda + kc] : make_float2(0.f, 0.f);
       }
     }
-    const int kx = kc0 + xrow;
-    float4 x01 = make_float4(0.f, 0.f, 0.f, 0.f), x23 = x01;
-    const int b = b0 + xcol;
-    if (kx < kc_end && b < g.ncols) {
-      for (int sl = 0; sl < g.x_slices; ++sl) {
-        const float2* src = g.X + sl * g.x_slice_stride + (int64_t)kx * g.ldx + b;
-        const float4 u = *reinterpret_cast<const float4*>(src);
-        x01.x += u.x;
-        x01.y += u.y;
-        x01.z += u.z;
-        x01.w += u.w;
-        if (b + 2 < g.ncols) {
-          const float4 v = *reinterpret_cast<const float4*>(src + 2);
-          x23.x += v.x;
-          x23.y += v.y;
-          x23.z += v.z;
-          x23.w += v.w;
-        }
-      }
-      // instances at or beyond ncols contribute nothing
-      if (b + 1 >= g.ncols) x01.z = x01.w = 0.f;
-      if (b + 3 >= g.ncols) x23.z = x23.w = 0.f;
-      if (b + 2 >= g.ncols) x23.x = x23.y = 0.f;
-    }
-    xv[0] = make_float2(x01.x, x01.y);
-    xv[1] = make_float2(x01.z, x01.w);
-    xv[2] = make_float2(x23.x, x23.y);
-    xv[3] = make_float2(x23.z, x23.w);
+    x_load(g, kc0 + xrow, kc_end, b0 + xcol, xr01, xr23);
   };
   auto store_tile = [&]() {
+    if (AVEC) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a_pair(kc_tile + acol + 2 * q, kc_end, ar[q], at[q], av[2 * q], av[2 * q + 1]);
+    }
+    x_mask(g, b0 + xcol, xr01, xr23, xv);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       As[arow][2 * (acol + q)] = av[q].x;
@@ -274,25 +273,16 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_pf(GemmArgs g) {
   const int arow = t >> 2, acol = (t & 3) * 4;
   const int xrow = t >> 4, xcol = (t & 15) * 4;
   const int gi = m0 + arow;
-  float2 av[4], xv[4];
+  // raw loads of the tile in flight (see a_load2 / x_load) and its first column
+  float4 ar[2], xr01, xr23;
+  float2 at[2], av[4], xv[4];
+  int kc_tile = kc_begin;
 
   auto load_tile = [&](int kc0) {
+    kc_tile = kc0;
     if (AVEC) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int kc = kc0 + acol + 2 * q;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gi < g.M) {
-          if (kc + 1 < kc_end) {
-            v = *reinterpret_cast<const float4*>(g.A + (int64_t)gi * g.lda + kc);
-          } else if (kc < kc_end) {
-            const float2 u = g.A[(int64_t)gi * g.lda + kc];
-            v = make_float4(u.x, u.y, 0.f, 0.f);
-          }
-        }
-        av[2 * q] = make_float2(v.x, v.y);
-        av[2 * q + 1] = make_float2(v.z, v.w);
-      }
+      for (int q = 0; q < 2; ++q) a_load2(g, gi, kc0 + acol + 2 * q, kc_end, ar[q], at[q]);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -300,35 +290,14 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_pf(GemmArgs g) {
         av[q] = (gi < g.M && kc < kc_end) ? g.A[(int64_t)gi * g.lda + kc] : make_float2(0.f, 0.f);
       }
     }
-    const int kx = kc0 + xrow;
-    float4 x01 = make_float4(0.f, 0.f, 0.f, 0.f), x23 = x01;
-    const int b = b0 + xcol;
-    if (kx < kc_end && b < g.ncols) {
-      for (int sl = 0; sl < g.x_slices; ++sl) {
-        const float2* src = g.X + sl * g.x_slice_stride + (int64_t)kx * g.ldx + b;
-        const float4 u = *reinterpret_cast<const float4*>(src);
-        x01.x += u.x;
-        x01.y += u.y;
-        x01.z += u.z;
-        x01.w += u.w;
-        if (b + 2 < g.ncols) {
-          const float4 v = *reinterpret_cast<const float4*>(src + 2);
-          x23.x += v.x;
-          x23.y += v.y;
-          x23.z += v.z;
-          x23.w += v.w;
-        }
-      }
-      if (b + 1 >= g.ncols) x01.z = x01.w = 0.f;
-      if (b + 3 >= g.ncols) x23.z = x23.w = 0.f;
-      if (b + 2 >= g.ncols) x23.x = x23.y = 0.f;
-    }
-    xv[0] = make_float2(x01.x, x01.y);
-    xv[1] = make_float2(x01.z, x01.w);
-    xv[2] = make_float2(x23.x, x23.y);
-    xv[3] = make_float2(x23.z, x23.w);
+    x_load(g, kc0 + xrow, kc_end, b0 + xcol, xr01, xr23);
   };
   auto store_tile = [&](int buf) {
+    if (AVEC) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) a_pair(kc_tile + acol + 2 * q, kc_end, ar[q], at[q], av[2 * q], av[2 * q + 1]);
+    }
+    x_mask(g, b0 + xcol, xr01, xr23, xv);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       As[buf][arow][2 * (acol + q)] = av[q].x;
@@ -425,14 +394,12 @@ void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stri
 
 int cgemm_f32_kslices(int kc) { return (kc + BKC - 1) / BKC; }
 
-// Launch Y[s] = A * sum(X slices) over split-K slices of `kslice` complex
-// columns (a multiple of 16; the number of slices is ceil(Kc / kslice)) with
-// tiling `variant`: 0 = 64 rows, 1 = 64 rows with the next tile prefetched
-// and two LDS buffers, 2 = 128 rows.  ldx and the X slice stride must be even
-// (two instances per 16-byte load).
-void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
-               int x_slices, int64_t x_slice_stride, void* Y, int64_t ldy, int64_t y_slice_stride, int ncols,
-               int kslice, int variant) {
+// Launch Y[s] = A * X over split-K slices of `kslice` complex columns (a
+// multiple of 16; the number of slices is ceil(Kc / kslice)) with tiling
+// `variant`: 0 = 64 rows, 1 = 64 rows with the next tile prefetched and two
+// LDS buffers, 2 = 128 rows.  ldx must be even (two instances per 16-byte load).
+void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx, void* Y,
+               int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant) {
   GemmArgs g;
   g.A = (const float2*)A;
   g.lda = lda;
@@ -440,8 +407,6 @@ void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, co
   g.Kc = Kc;
   g.X = (const float2*)X;
   g.ldx = ldx;
-  g.x_slices = x_slices;
-  g.x_slice_stride = x_slice_stride;
   g.Y = (float2*)Y;
   g.ldy = ldy;
   g.y_slice_stride = y_slice_stride;

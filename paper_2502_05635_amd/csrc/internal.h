@@ -97,11 +97,11 @@ int pairs_per_k(const tdg_model* m, int block);
 void release_blas(tdg_ctx ctx);
 // The context's rocBLAS handle (created on first use), bound to its stream.
 int blas_handle(tdg_ctx ctx, void** handle);
-// Complex FP32 matrix-core product Y[s] = A * sum(X slices) (gemm.hip); variant
-// 0 = 64-row tiles, 1 = 64-row tiles with a prefetched next tile, 2 = 128-row tiles.
-void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
-               int x_slices, int64_t x_slice_stride, void* Y, int64_t ldy, int64_t y_slice_stride, int ncols,
-               int kslice, int variant);
+// Complex FP32 matrix-core product Y[s] = A * X over split-K slices s (gemm.hip);
+// variant 0 = 64-row tiles, 1 = 64-row tiles with a prefetched next tile, 2 =
+// 128-row tiles.
+void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx, void* Y,
+               int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant);
 // BF16 split-precision product: A in TDG_BF16X2 storage (hi plane, then lo
 // plane, [M][lda], lda % 4 == 0), X complex64 [Kc][ldx] (gemm.hip).
 // variant 0: 64-row tiles splitting X while staged; 1: X split once into

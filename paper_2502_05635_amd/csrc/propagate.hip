@@ -1353,7 +1353,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
             cgemm_bf16x2(ctx->stream, op->K, op->ld, (int)n, (int)n, xt, xstride, Ybuf, ldy, n * ldy, n_dyn0,
                          (int)ks, v, xbw);
           else
-            cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xt, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn0,
+            cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xt, xstride, Ybuf, ldy, n * ldy, n_dyn0,
                       (int)ks, v);
         }, &gv_main, &ks_main));
         y_slices = (int)((n + ks_main - 1) / ks_main);
@@ -1363,7 +1363,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
             cgemm_bf16x2(ctx->stream, op->w, n, (int)op->rank, (int)n, xt, xstride, Zbuf, ldy, op->rank * ldy,
                          n_dyn0, (int)ks, v, xbw);
           else
-            cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xt, xstride, 1, 0, Zbuf, ldy, op->rank * ldy,
+            cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xt, xstride, Zbuf, ldy, op->rank * ldy,
                       n_dyn0, (int)ks, v);
           sum_slices_c64(ctx->stream, Zbuf, (int)((n + ks - 1) / ks), op->rank * ldy, op->rank * ldy, Zsum);
         }, &gv_proj, &ks_proj));
@@ -1374,7 +1374,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
             cgemm_bf16x2(ctx->stream, op->us, ld_us0, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn0,
                          (int)ks, v, xbw);
           else
-            cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy,
+            cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy,
                       n_dyn0, (int)ks, v);
         }, &gv_main, &ks_main));
         y_slices = (int)((op->rank + ks_main - 1) / ks_main);
@@ -1411,7 +1411,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
               cgemm_bf16x2(st, op->K, op->ld, (int)n, (int)n, xc, xstride, Ybuf, ldy, n * ldy, n_dyn, (int)ks_main,
                            gv_main, xbw);
             else
-              cgemm_f32(st, op->K, op->ld, (int)n, (int)n, xc, xstride, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
+              cgemm_f32(st, op->K, op->ld, (int)n, (int)n, xc, xstride, Ybuf, ldy, n * ldy, n_dyn,
                         (int)ks_main, gv_main);
           } else {
             // projection split over K, summed once in fixed order, then expansion
@@ -1419,14 +1419,14 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
               cgemm_bf16x2(st, op->w, n, (int)op->rank, (int)n, xc, xstride, Zbuf, ldy, op->rank * ldy, n_dyn,
                            (int)ks_proj, gv_proj, xbw);
             else
-              cgemm_f32(st, op->w, n, (int)op->rank, (int)n, xc, xstride, 1, 0, Zbuf, ldy, op->rank * ldy, n_dyn,
+              cgemm_f32(st, op->w, n, (int)op->rank, (int)n, xc, xstride, Zbuf, ldy, op->rank * ldy, n_dyn,
                         (int)ks_proj, gv_proj);
             sum_slices_c64(st, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
             if (bf16)
               cgemm_bf16x2(st, op->us, ld_us, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
                            (int)ks_main, gv_main, xbw);
             else
-              cgemm_f32(st, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, 1, 0, Ybuf, ldy, n * ldy, n_dyn,
+              cgemm_f32(st, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
                         (int)ks_main, gv_main);
           }
           if (prof) prof_end(ctx, TDG_KCLASS_GEMM);
