@@ -123,13 +123,19 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma(GemmArgs g) {
       Bs[2 * xrow + 1][BNI + xcol + q] = xv[q].x;
     }
     __syncthreads();
+    // the stage's fragments first, then its products: LDS latency overlaps the MFMAs
+    float fa[BKC], fx0[BKC], fx1[BKC];
 #pragma unroll
-    for (int k2 = 0; k2 < 2 * BKC; k2 += 2) {
-      const float a = As[wr + (lane & 31)][k2 + (lane >> 5)];
-      const float x0 = Bs[k2 + (lane >> 5)][wc + (lane & 31)];
-      const float x1 = Bs[k2 + (lane >> 5)][wc + 32 + (lane & 31)];
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, x0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, x1, acc1, 0, 0, 0);
+    for (int q = 0; q < BKC; ++q) {
+      fa[q] = As[wr + (lane & 31)][2 * q + (lane >> 5)];
+      fx0[q] = Bs[2 * q + (lane >> 5)][wc + (lane & 31)];
+      fx1[q] = Bs[2 * q + (lane >> 5)][wc + 32 + (lane & 31)];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
+#pragma unroll
+    for (int q = 0; q < BKC; ++q) {
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[q], fx0[q], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[q], fx1[q], acc1, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -223,16 +229,27 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_128(GemmArgs g) {
   for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC) {
     const bool more = kc0 + BKC < kc_end;
     if (more) load_tile(kc0 + BKC);
+    // fragments of half a stage first, then its products (LDS latency overlaps the MFMAs)
 #pragma unroll
-    for (int k2 = 0; k2 < 2 * BKC; k2 += 2) {
-      const float a0 = As[wr + (lane & 31)][k2 + (lane >> 5)];
-      const float a1 = As[wr + 32 + (lane & 31)][k2 + (lane >> 5)];
-      const float x0 = Bs[k2 + (lane >> 5)][wc + (lane & 31)];
-      const float x1 = Bs[k2 + (lane >> 5)][wc + 32 + (lane & 31)];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, x0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, x1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, x0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, x1, acc[1][1], 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      constexpr int HQ = BKC / 2;
+      float fa0[HQ], fa1[HQ], fx0[HQ], fx1[HQ];
+#pragma unroll
+      for (int q = 0; q < HQ; ++q) {
+        const int k2 = 2 * (h * HQ + q);
+        fa0[q] = As[wr + (lane & 31)][k2 + (lane >> 5)];
+        fa1[q] = As[wr + 32 + (lane & 31)][k2 + (lane >> 5)];
+        fx0[q] = Bs[k2 + (lane >> 5)][wc + (lane & 31)];
+        fx1[q] = Bs[k2 + (lane >> 5)][wc + 32 + (lane & 31)];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
+#pragma unroll
+      for (int q = 0; q < HQ; ++q) {
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa0[q], fx0[q], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa0[q], fx1[q], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa1[q], fx0[q], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa1[q], fx1[q], acc[1][1], 0, 0, 0);
+      }
     }
     __syncthreads();
     if (more) store_tile();
@@ -318,13 +335,19 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_pf(GemmArgs g) {
   for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC) {
     const bool more = kc0 + BKC < kc_end;
     if (more) load_tile(kc0 + BKC);
+    // the stage's fragments first, then its products (LDS latency overlaps the MFMAs)
+    float fa[BKC], fx0[BKC], fx1[BKC];
 #pragma unroll
-    for (int k2 = 0; k2 < 2 * BKC; k2 += 2) {
-      const float a = As[buf][wr + (lane & 31)][k2 + (lane >> 5)];
-      const float x0 = Bs[buf][k2 + (lane >> 5)][wc + (lane & 31)];
-      const float x1 = Bs[buf][k2 + (lane >> 5)][wc + 32 + (lane & 31)];
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, x0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, x1, acc1, 0, 0, 0);
+    for (int q = 0; q < BKC; ++q) {
+      fa[q] = As[buf][wr + (lane & 31)][2 * q + (lane >> 5)];
+      fx0[q] = Bs[buf][2 * q + (lane >> 5)][wc + (lane & 31)];
+      fx1[q] = Bs[buf][2 * q + (lane >> 5)][wc + 32 + (lane & 31)];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
+#pragma unroll
+    for (int q = 0; q < BKC; ++q) {
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[q], fx0[q], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[q], fx1[q], acc1, 0, 0, 0);
     }
     if (more) store_tile(buf ^ 1);
     __syncthreads();
