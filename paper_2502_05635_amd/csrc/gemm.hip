@@ -634,6 +634,13 @@ __global__ void __launch_bounds__(256) expand_bf16x2_kernel(const float2* __rest
 // 128 rows x 64 instances per block, 16 complex K columns per LDS stage; wave
 // w owns rows 64*(w/2) .. +63 and real columns 64*(w%2) .. +63 as 2 x 2 MFMA
 // accumulators, so each 16-byte fragment read from LDS feeds six products.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// A word of two bf16 at positions e, e + 1: those at or past `end` zeroed.
+__device__ inline unsigned int bf16_pair_mask(unsigned int w, int e, int end) {
+  return e >= end ? 0u : (e + 1 >= end ? (w & 0xffffu) : w);
+}
+
 constexpr int BM3 = 128;
 constexpr int BKC3 = 16;
 constexpr int KR3 = 2 * BKC3;
@@ -653,37 +660,51 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
     for (int j = 0; j < 2; ++j)
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC3) {
-    const int kr0 = 2 * kc0, kr_end = 2 * kc_end;
-    // A: 2 planes x 128 rows x 4 chunks of 8 bf16; zero past the slice's K
+  // Tile loads go into registers (the next stage's while the current one is
+  // multiplied); bf16 past the slice's K are zeroed when the tile is written to
+  // LDS.  A chunk of 8 bf16 (4 complex) never crosses a split-K boundary
+  // (slices are multiples of 32 complex) and stays inside its row (ld % 4 == 0).
+  const int kr_end = 2 * kc_end;
+  u32x4 ra[4], rx[4];
+  auto load_tile = [&](int kc0) {
+    const int kr0 = 2 * kc0;
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-      const int i = t + 256 * it;
-      const int q = i & 3, row = (i >> 2) & (BM3 - 1), p = i >> 9;
+      // chunk q of row `row` in plane p (it = 0, 1: hi plane; 2, 3: lo plane)
+      const int q = t & 3, row = ((t >> 2) + 64 * it) & (BM3 - 1), p = it >> 1;
       const int kr = kr0 + 8 * q, gi = m0 + row;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (gi < g.M) {
-        const unsigned short* src = (p ? g.Alo : g.Ahi) + (int64_t)gi * 2 * g.lda + kr;
-        if (kr + 8 <= kr_end) {
-          v = *reinterpret_cast<const uint4*>(src);
-        } else if (kr < kr_end) {
-          unsigned short hb[8];
-          for (int e = 0; e < 8; ++e) hb[e] = kr + e < kr_end ? src[e] : (unsigned short)0;
-          v = *reinterpret_cast<uint4*>(hb);
-        }
-      }
-      *reinterpret_cast<uint4*>(&As[p][row][8 * q]) = v;
+      ra[it] = u32x4{0u, 0u, 0u, 0u};
+      if (gi < g.M && kr < kr_end)
+        ra[it] = *reinterpret_cast<const u32x4*>((p ? g.Alo : g.Ahi) + (int64_t)gi * 2 * g.lda + kr);
+      // X: the padded rows of XB cover every stage
+      rx[it] = *reinterpret_cast<const u32x4*>(XB + ((int64_t)(ct * 2 + p) * XB_ROWS + row) * ldxb + kr);
     }
-    // X: 2 planes x 128 rows x 4 chunks; the padded rows of XB cover every stage
+  };
+  auto store_tile = [&](int kc0) {
+    const int kr0 = 2 * kc0;
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-      const int i = t + 256 * it;
-      const int q = i & 3, row = (i >> 2) & (XB_ROWS - 1), p = i >> 9;
-      const uint4 v =
-          *reinterpret_cast<const uint4*>(XB + ((int64_t)(ct * 2 + p) * XB_ROWS + row) * ldxb + kr0 + 8 * q);
-      *reinterpret_cast<uint4*>(&Xs[p][row][8 * q]) = v;
+      const int q = t & 3, row = ((t >> 2) + 64 * it) & (BM3 - 1), p = it >> 1;
+      const int kr = kr0 + 8 * q;
+      u32x4 v = ra[it];
+      // keep bf16 e of the chunk only while kr + e < kr_end (two per 32-bit word)
+      v.x = bf16_pair_mask(v.x, kr, kr_end);
+      v.y = bf16_pair_mask(v.y, kr + 2, kr_end);
+      v.z = bf16_pair_mask(v.z, kr + 4, kr_end);
+      v.w = bf16_pair_mask(v.w, kr + 6, kr_end);
+      *reinterpret_cast<u32x4*>(&As[p][row][8 * q]) = v;
+      *reinterpret_cast<u32x4*>(&Xs[p][row][8 * q]) = rx[it];
     }
-    __syncthreads();
+  };
+
+  if (kc_begin < kc_end) {
+    load_tile(kc_begin);
+    store_tile(kc_begin);
+  }
+  __syncthreads();
+  for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC3) {
+    const bool more = kc0 + BKC3 < kc_end;
+    if (more) load_tile(kc0 + BKC3);
 #pragma unroll
     for (int ks = 0; ks < KR3; ks += 16) {
       const int kb = ks + 8 * (lane >> 5);
@@ -695,6 +716,7 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
         xh[i] = *reinterpret_cast<const bf16x8*>(&Xs[0][wc + 32 * i + (lane & 31)][kb]);
         xl[i] = *reinterpret_cast<const bf16x8*>(&Xs[1][wc + 32 * i + (lane & 31)][kb]);
       }
+      __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -704,6 +726,8 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], xh[j], acc[i][j], 0, 0, 0);
         }
     }
+    __syncthreads();
+    if (more) store_tile(kc0 + BKC3);
     __syncthreads();
   }
 
