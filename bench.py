@@ -131,6 +131,11 @@ def algorithmic_bytes(kind, n, r, nk, nb, elt=8):
     raise ValueError(kind)
 
 
+def progress(msg):
+    """One line on stderr as each part of the run starts (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -200,6 +205,7 @@ def main():
 
     out = {}
     for name, op in (("dense", K), ("lowrank", fac)):
+        progress(f"{name} operator, {args.steps} steps")
         res, secs, _ = timed(op, args.steps, args.warmup, False)
         variant = ctx.last_variant()
         _, _, prof = timed(op, args.steps, args.warmup, True)
@@ -213,6 +219,7 @@ def main():
     rmax = min(nk // 4 * 4, (int(round(chan_frac * nk)) + 8 + 3) // 4 * 4)
     chan = None
     if not args.no_channelwise:
+        progress("channel-wise operator")
         t0 = time.perf_counter()
         chan = ctx.kernel_compress_channels(K, nk, npair, "fraction", chan_frac, rmax=rmax)
         torch.cuda.synchronize()
@@ -226,6 +233,7 @@ def main():
     # parallel-transport links) on the same low-rank operator
     intraband = None
     if not args.no_intraband:
+        progress("intraband term")
         t0 = time.perf_counter()
         dml = dm.with_links(ctx.links_build(dm))
         links_s = time.perf_counter() - t0
@@ -314,12 +322,18 @@ def main():
             v.pop("res", None)
         del K, fac, res, chan
         torch.cuda.empty_cache()
+        progress("60x60 batched sweep")
         sweep = batched_sweep(P, abi, ctx, frac)
+    if args.large_grid:
+        progress("120x120 large grid")
     large = large_grid(P, abi, args.large_grid_steps) if args.large_grid else None
+    if not args.no_adjoint:
+        progress("adjoint")
     adjoint = None if args.no_adjoint else adjoint_leg(P, ctx)
 
     cpu = None
     if not args.no_cpu_baseline:
+        progress("CPU baseline (oracle)")
         cpu = cpu_baseline(cfg, frac, args.cpu_seconds)
 
     line = {

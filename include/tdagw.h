@@ -379,12 +379,15 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
 /* Tiling and split-K of the batched path's complex matrix-core products:
  * TDG_OPT_GEMM_VARIANT -1 (default) times, on the first use of each product
  * shape (M, K, instances), every tiling with each of a few split-K widths (the
- * default of about 1024 blocks, no split, and about 256 j blocks for j = 1..4)
- * and keeps the fastest pair for the context.  FP32 tilings: 0 = 64-row tiles,
- * 1 = 64-row tiles with the next K tile prefetched into registers and two LDS
- * buffers, 2 = 128-row tiles; BF16X2 tilings 0 and 1 (see TDG_BF16X2).  A
- * value >= 0 forces that tiling with the default split.  Tilings and splits
- * differ only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects 0 / 2. */
+ * default of about 1024 blocks, no split, twice the default, and about 256 j
+ * blocks for j = 1..4), each followed by one pass over the slices it wrote, and
+ * keeps for the context the first pair (default split first) within 2 % of the
+ * fastest.  FP32 tilings: 0 = 64-row tiles, 1 = 64-row tiles with the next K
+ * tile prefetched into registers and two LDS buffers, 2 = 128-row tiles;
+ * BF16X2 tilings 0 and 1 (see TDG_BF16X2).  A value >= 0 forces that tiling
+ * with the default split (or the one TDG_OPT_GEMM_SLICES gives).  Tilings and
+ * splits differ only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects
+ * 0 / 2. */
 #define TDG_OPT_GEMM_TILE 3
 #define TDG_OPT_GEMM_VARIANT 4
 /* Batched path: 1 captures one RK4 step (products, stage kernels) per running
@@ -393,6 +396,12 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * (the stage kernels then read the step index from device memory); 0
  * (default) launches every kernel directly.  Results are identical. */
 #define TDG_OPT_GRAPHS 5
+/* Batched path: a value in [1, 4096] splits every matrix-core product's K
+ * range into that many slices (clamped to twice the default count, the size of
+ * the slice buffers) with the tiling the tuner or TDG_OPT_GEMM_VARIANT gives;
+ * 0 (default) lets the tuner choose.  Other values: TDG_E_INVAL.  Results
+ * differ only in summation order. */
+#define TDG_OPT_GEMM_SLICES 6
 int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
 /* Name of the stage-kernel variant the last tdg_propagate used ("" before any). */
 const char* tdg_last_variant(tdg_ctx ctx);

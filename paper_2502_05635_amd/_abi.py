@@ -30,6 +30,7 @@ TDG_OPT_BATCHED_MIN = 2
 TDG_OPT_GEMM_TILE = 3
 TDG_OPT_GEMM_VARIANT = 4
 TDG_OPT_GRAPHS = 5
+TDG_OPT_GEMM_SLICES = 6
 
 P = C.c_void_p
 

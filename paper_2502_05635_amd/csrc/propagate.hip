@@ -272,7 +272,8 @@ __device__ inline double2 proj_e(const tdg_field& F, double2 a, double2 b) {
 // low-rank expansion (rows of S against z, plus K_diag o x); it is a template
 // parameter so the two paths are distinct kernels in traces.  NT threads per
 // block (a k point's rows are split over the block's columns), U-fold unrolled
-// row streams, WPE = minimum waves per SIMD requested from the compiler.
+// row streams (low rank: 2 U columns of S per thread and pass), WPE = minimum
+// waves per SIMD requested from the compiler.
 template <typename T, int MODE, int NT, int U, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 stage_kernel(StageParams sp) {
@@ -347,12 +348,13 @@ stage_kernel(StageParams sp) {
       const C* Ar = A + ((int64_t)k * P + r0) * sp.lda;
       if (LOWRANK) {
         // rows of S against z = sum of the projection's column slices (at most
-        // ZSPLIT_MAX); each thread sums the slices of its own columns.  Two
-        // columns per pass with every load of the pass issued first.
-        for (int j0 = t; j0 < sp.ncols; j0 += 2 * NT) {
-          C zv[2][ZSPLIT_MAX], av[2][ROWS];
+        // ZSPLIT_MAX); each thread sums the slices of its own columns.  2 U
+        // columns per thread and pass, every load of the pass issued first.
+        constexpr int CP = 2 * U;
+        for (int j0 = t; j0 < sp.ncols; j0 += CP * NT) {
+          C zv[CP][ZSPLIT_MAX], av[CP][ROWS];
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
+          for (int u = 0; u < CP; ++u) {
             const int j = j0 + u * NT;
             if (j < sp.ncols) {
 #pragma unroll
@@ -364,7 +366,7 @@ stage_kernel(StageParams sp) {
             }
           }
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
+          for (int u = 0; u < CP; ++u) {
             if (j0 + u * NT < sp.ncols) {
               T zr = (T)0, zi = (T)0;
 #pragma unroll
@@ -583,10 +585,16 @@ struct BatchParams {
 
 // The step counter of graph replays (vector stores: the address depends on the lane).
 // A fixed non-zero operand for timing the products (the step-0 gather of
-// rho_eq is all zeros): element i = ((i % 13) - 6) * 1e-3 (1 + i).
+// rho_eq is all zeros): values in (-1e-3, 1e-3) from an integer hash of the
+// element index, so the matrix cores see varied operands like the propagated ones.
 __global__ void pattern_fill_kernel(float2* x, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = make_float2((float)((i % 13) - 6) * 1e-3f, (float)((i % 7) - 3) * 1e-3f);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(i >> 32);
+    h ^= h >> 16; h *= 0x85EBCA6Bu; h ^= h >> 13; h *= 0xC2B2AE35u; h ^= h >> 16;
+    const float re = ((float)(h & 0xFFFFu) - 32767.5f) * (1e-3f / 32768.f);
+    const float im = ((float)(h >> 16) - 32767.5f) * (1e-3f / 32768.f);
+    x[i] = make_float2(re, im);
+  }
 }
 
 __global__ void set_step_kernel(int* c, int v) {
@@ -963,6 +971,8 @@ static const Variant kLowF32[] = {
     {"lowrank_f32_nt64", launch_stage<float, 1, 64, 1, 2>},
     {"lowrank_f32_nt128", launch_stage<float, 1, 128, 1, 2>},
     {"lowrank_f32_nt256", launch_stage<float, 1, 256, 1, 2>},
+    {"lowrank_f32_nt128_c4", launch_stage<float, 1, 128, 2, 2>},
+    {"lowrank_f32_nt64_c6", launch_stage<float, 1, 64, 3, 2>},
 };
 static const Variant kChanF32[] = {
     {"channel_f32_nt256_u2_w6", launch_stage<float, 2, 256, 2, 6>},
@@ -1284,62 +1294,94 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         }
         return out;
       };
-      // tiling v and slice width ks of one product: forced tiling (default
-      // split), cached for its shape, or timed now (each pair once to warm up,
-      // then twice, the fastest pair kept; the projection's timing includes
-      // the sum of its slices)
+      // tiling v and slice width ks of one product: forced tiling (default or
+      // forced split), cached for its shape, or timed now (the projection's
+      // timing includes the sum of its slices)
       auto pick = [&](const char* what, int64_t M, int64_t Kc, int64_t ks_def,
                       const std::function<void(int, int64_t)>& run, int* out_v, int64_t* out_ks) -> int {
-        *out_ks = ks_def;
+        // forced slice count (TDG_OPT_GEMM_SLICES), at most twice the default (the buffers' size)
+        int64_t ks_forced = 0;
+        if (ctx->gemm_slices > 0) {
+          const int64_t s_def = (Kc + ks_def - 1) / ks_def;
+          const int64_t sc = std::max<int64_t>(1, std::min<int64_t>(ctx->gemm_slices, 2 * s_def));
+          ks_forced = std::max<int64_t>(32, ((Kc + sc - 1) / sc + 31) / 32 * 32);
+        }
+        *out_ks = ks_forced > 0 ? ks_forced : ks_def;
         if (ctx->gemm_variant >= 0) {
           *out_v = std::min(ctx->gemm_variant, ntilings - 1);
           return TDG_OK;
         }
         char key[160];
-        snprintf(key, sizeof(key), "gemm/%s/%s/%lld/%lld/%d/%lld", bf16 ? "bf16x2" : "f32", what, (long long)M,
-                 (long long)Kc, n_dyn0, (long long)ks_def);
+        snprintf(key, sizeof(key), "gemm/%s/%s/%lld/%lld/%d/%lld/%lld", bf16 ? "bf16x2" : "f32", what, (long long)M,
+                 (long long)Kc, n_dyn0, (long long)ks_def, (long long)ks_forced);
         for (auto& kv : ctx->tuned)
           if (kv.first == key) {
             *out_v = kv.second % 4;
             *out_ks = kv.second / 4;
             return TDG_OK;
           }
-        hipEvent_t e0, e1;
-        TDG_TRY(hip_check(ctx, hipEventCreate(&e0), "event"));
-        TDG_TRY(hip_check(ctx, hipEventCreate(&e1), "event"));
-        const std::vector<int64_t> opts = split_options(M, Kc, ks_def);
-        std::vector<float> tmin(opts.size() * ntilings, 1e30f);
-        for (int round = 0; round < 3; ++round)
-          for (size_t oi = 0; oi < opts.size(); ++oi)
-            for (int v = 0; v < ntilings; ++v) {
-              run(v, opts[oi]);
-              hipEventRecord(e0, ctx->stream);
-              run(v, opts[oi]);
-              run(v, opts[oi]);
-              hipEventRecord(e1, ctx->stream);
-              TDG_TRY(hip_check(ctx, hipEventSynchronize(e1), "GEMM tuning"));
-              float ms = 0.f;
-              hipEventElapsedTime(&ms, e0, e1);
-              float& m = tmin[oi * ntilings + v];
-              m = std::min(m, ms);
-            }
-        float best = 1e30f;
+        const std::vector<int64_t> opts =
+            ks_forced > 0 ? std::vector<int64_t>{ks_forced} : split_options(M, Kc, ks_def);
+        const size_t ncand = opts.size() * ntilings;
+        std::vector<hipEvent_t> ev(2 * ncand, nullptr);
+        int erc = TDG_OK;
+        for (auto& e : ev)
+          if (erc == TDG_OK) erc = hip_check(ctx, hipEventCreate(&e), "event");
+        auto destroy = [&]() {
+          for (auto& e : ev)
+            if (e) hipEventDestroy(e);
+        };
+        if (erc != TDG_OK) {
+          destroy();
+          return erc;
+        }
+        // one untimed round, then each candidate timed once per round, right
+        // after another candidate's run (back-to-back repeats of one product
+        // slow down and would penalise the wider splits)
+        std::vector<float> tmin(ncand, 1e30f);
+        for (int round = 0; round < 6; ++round) {
+          for (size_t c = 0; c < ncand; ++c) {
+            hipEventRecord(ev[2 * c], ctx->stream);
+            run((int)(c % ntilings), opts[c / ntilings]);
+            hipEventRecord(ev[2 * c + 1], ctx->stream);
+          }
+          erc = hip_check(ctx, hipEventSynchronize(ev[2 * ncand - 1]), "GEMM tuning");
+          if (erc != TDG_OK) {
+            destroy();
+            return erc;
+          }
+          for (size_t c = 0; c < ncand && round > 0; ++c) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]);
+            tmin[c] = std::min(tmin[c], ms);
+          }
+        }
+        destroy();
+        // the earliest (split, tiling) within 2 % of the fastest (the default split first)
+        const float fastest = *std::min_element(tmin.begin(), tmin.end());
         int bestv = 0;
         int64_t bestks = ks_def;
-        for (size_t oi = 0; oi < opts.size(); ++oi)
+        bool found = false;
+        for (size_t oi = 0; oi < opts.size() && !found; ++oi)
           for (int v = 0; v < ntilings; ++v)
-            if (tmin[oi * ntilings + v] < best) {
-              best = tmin[oi * ntilings + v];
+            if (tmin[oi * ntilings + v] <= 1.02f * fastest) {
               bestv = v;
               bestks = opts[oi];
+              found = true;
+              break;
             }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
         TDG_TRY(launch_check(ctx, "GEMM tuning"));
         ctx->tuned.emplace_back(key, (int)(bestks * 4 + bestv));
         *out_v = bestv;
         *out_ks = bestks;
         return TDG_OK;
+      };
+      // The stage kernel reads every slice of the dense or expansion product:
+      // their timing includes one fixed-order pass over the slices as a proxy.
+      void* slice_out = nullptr;
+      TDG_TRY(ws_reserve(ctx, WS_TMP2, (size_t)n * ldy * 8, &slice_out));
+      auto slice_read = [&](int slices) {
+        sum_slices_c64(ctx->stream, Ybuf, slices, n * ldy, n * ldy, slice_out);
       };
       // timing operand: a non-zero pattern in the second gather buffer, which
       // stage 0 of step 0 overwrites
@@ -1355,6 +1397,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
           else
             cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xt, xstride, Ybuf, ldy, n * ldy, n_dyn0,
                       (int)ks, v);
+          slice_read((int)((n + ks - 1) / ks));
         }, &gv_main, &ks_main));
         y_slices = (int)((n + ks_main - 1) / ks_main);
       } else {
@@ -1376,6 +1419,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
           else
             cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy,
                       n_dyn0, (int)ks, v);
+          slice_read((int)((op->rank + ks - 1) / ks));
         }, &gv_main, &ks_main));
         y_slices = (int)((op->rank + ks_main - 1) / ks_main);
       }
@@ -1599,14 +1643,18 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
           }
         }
       }
-      float best = 1e30f;
-      int best_split = 0;
+      // the earliest (split, variant) within 2 % of the fastest: near-equal
+      // candidates would otherwise alternate between runs with timing noise
+      float fastest = 1e30f;
       for (int si = 0; si < nsplit; ++si)
+        for (int v = 0; v < nvar; ++v) fastest = std::min(fastest, tmin[si][v]);
+      int best_split = -1;
+      for (int si = 0; si < nsplit && best_split < 0; ++si)
         for (int v = 0; v < nvar; ++v)
-          if (tmin[si][v] < best) {
-            best = tmin[si][v];
+          if (tmin[si][v] <= 1.02f * fastest) {
             var = v;
             best_split = si;
+            break;
           }
       hipEventDestroy(ea);
       hipEventDestroy(eb);

@@ -182,6 +182,36 @@ def test_lowrank_fp32_parity_odd_rank(P, ctx, tb4_6, k_tb4_6):
         assert err_rel(res[key][0].cpu().numpy(), ref[key]) <= 1e-4, key
 
 
+def test_lowrank_fp32_every_stage_variant(P, ctx):
+    """Each low-rank FP32 stage-kernel variant, forced in turn, against the
+    FP64 oracle.  Rank 401 on a 12x12 grid (N = 576) gives every variant a
+    ragged last pass: 4 passes of 128 columns, 2 of 256, and single passes of
+    512 and of 384 + 17 columns."""
+    from paper_2502_05635_amd import _abi as abi
+    m = tb4_model(12, A, 0.5)
+    dm = _dev(P, m)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c64")
+    r = 401
+    ref_fac = O.compress(kg.cpu().numpy().astype(np.complex128), "rank", r)
+    f = strong(300)
+    ref = O.propagate(m, O.LowRankOp.from_factors(ref_fac), "eh", f, DT)
+    fac = ctx.kernel_compress(kg, "rank", r)
+    assert fac.rank == r
+    names = []
+    try:
+        for v in range(5):
+            ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, v)
+            res = ctx.propagate(fac, dm, "eh", f, DT)
+            names.append(ctx.last_variant())
+            for key in ("P", "J"):
+                e = err_rel(res[key][0].cpu().numpy(), ref[key])
+                _log(f"  {names[-1]}: err_{key} = {e:.3e}")
+                assert e <= 1e-4, (names[-1], key)
+    finally:
+        ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, -1)
+    assert len(set(n.split("_z")[0] for n in names)) == 5, names
+
+
 def test_batched_uneven_instances(P, ctx):
     m = tb4_model(4, A, 0.5)
     k = O.build_kernel(m, R0_STABLE, "eh")
@@ -312,10 +342,16 @@ def _uneven_fields(n_inst, seed=5):
     return FieldTable.stack(tabs)
 
 
-@pytest.mark.parametrize("kind", ["dense", "lowrank"])
-def test_batched_mfma_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind):
+_BATCHED_REFS = {}
+
+
+@pytest.mark.parametrize("kind,slices", [("dense", 0), ("lowrank", 0), ("dense", 1), ("lowrank", 1),
+                                         ("dense", 4096), ("lowrank", 4096)])
+def test_batched_mfma_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, slices):
     """Uneven batch (lengths 0 .. 259, mixed polarisations) through the
-    matrix-core path, each instance against its own FP64 oracle run."""
+    matrix-core path, each instance against its own FP64 oracle run; with the
+    tuned split-K, and forced to one slice and to the most slices allowed
+    (4096 is clamped to twice the default count)."""
     from paper_2502_05635_amd import _abi as abi
     fields = _uneven_fields(6)
     dm = _dev(P, tb4_6)
@@ -325,11 +361,21 @@ def test_batched_mfma_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind):
         op = ctx.kernel_compress(kg, "rank", 37)
         oracle_op = O.LowRankOp.from_factors(O.compress(k_tb4_6, "rank", 37))
     ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 2)
-    _log(f"batched {kind} FP32 on the matrix cores, 6 instances")
-    res = ctx.propagate(op, dm, "eh", fields, DT)
-    assert ctx.last_variant().startswith("batched_mfma")
+    ctx.set_option(abi.TDG_OPT_GEMM_SLICES, slices)
+    _log(f"batched {kind} FP32 on the matrix cores, 6 instances, forced slices {slices}")
+    try:
+        res = ctx.propagate(op, dm, "eh", fields, DT)
+    finally:
+        ctx.set_option(abi.TDG_OPT_GEMM_SLICES, 0)
+    variant = ctx.last_variant()
+    _log(f"  {variant}")
+    assert variant.startswith("batched_mfma")
+    if slices == 1:
+        assert ("slices 1/1)" if kind == "lowrank" else "slices 1)") in variant
     for b in range(fields.batch):
-        ref = O.propagate(tb4_6, oracle_op, "eh", fields, DT, instance=b)
+        if (kind, b) not in _BATCHED_REFS:
+            _BATCHED_REFS[kind, b] = O.propagate(tb4_6, oracle_op, "eh", fields, DT, instance=b)
+        ref = _BATCHED_REFS[kind, b]
         nsb = int(fields.nsteps[b])
         for key in ("P", "J"):
             got = res[key][b, : nsb + 1].cpu().numpy()
