@@ -623,7 +623,8 @@ __device__ inline size_t bidx(const BatchParams& bp, int k, int e, int b) {
 // observable sums [5][nb][IB] share the H blocks' LDS when they fit (nb >= 3):
 // they are consumed before H is built; otherwise they follow the H blocks.
 template <int NBT>
-__global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBT <= 4 ? 3 : 1, 8)))
+batched_stage_kernel(BatchParams bp) {
   extern __shared__ double2 dyn_lds[];
   const int nb = bp.nb, nb2 = nb * nb, IB = blockDim.x / nb;
   double2* s_rho = dyn_lds;
@@ -654,44 +655,77 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
   tdg_field F = {};
   if (act) F = bp.fields[b];
   const double ef_stage = dyn ? bp.ftab[((size_t)obs_slot * bp.batch + b) * 4 + bp.stage] : 0.0;
-  double2 r_n[NBT], r_acc[NBT], ds[NBT];
+  // Every global load of the thread's row is issued before its first use:
+  // the state elements (and the intraband term), K_diag o x, then the
+  // product's slices for the row's pair elements, SG slices at a time (sums
+  // in slice order).
+  double2 rs[NBT], r_n[NBT], r_acc[NBT], ds[NBT], dv[NBT];
+  int prow[NBT];       // product row (k P + p) of element m, -1 = none
+  bool partner[NBT];   // element (v, c) of the conduction-valence block: conj of (c, v)
 #pragma unroll
   for (int m = 0; m < NBT; ++m) {
-    if (m >= nb) break;
-    const int e = n * nb + m;
-    double2 rs = make_double2(0.0, 0.0);
-    r_n[m] = r_acc[m] = ds[m] = rs;
-    if (act) rs = bp.rho_s[bidx(bp, k, e, b)];
-    s_rho[e * IB + i] = rs;
+    rs[m] = r_n[m] = r_acc[m] = ds[m] = dv[m] = make_double2(0.0, 0.0);
+    prow[m] = -1;
+    partner[m] = false;
+    if (m >= nb || !act) continue;
+    const size_t g = bidx(bp, k, n * nb + m, b);
+    rs[m] = bp.rho_s[g];
     if (!dyn) continue;
-    const size_t g = bidx(bp, k, e, b);
     r_n[m] = bp.rho_n[g];
     if (bp.stage != 0) r_acc[m] = bp.acc[g];
+    if (bp.intra) dv[m] = bp.intra[g];
     int p = -1;
-    bool partner = false;  // element (v, c) of the conduction-valence block: conj of (c, v)
     if (bp.block == TDG_BLOCK_ALL) {
-      p = e;
+      p = n * nb + m;
     } else if (n >= bp.nv && m < bp.nv) {
       p = (n - bp.nv) * bp.nv + m;
     } else if (n < bp.nv && m >= bp.nv) {
       p = (m - bp.nv) * bp.nv + n;
-      partner = true;
+      partner[m] = true;
     }
-    if (p >= 0) {
-      const size_t row = (size_t)k * P + p;
-      float yr = 0.f, yi = 0.f;
-      for (int sl = 0; sl < bp.y_slices; ++sl) {
-        const float2 y = bp.Y[sl * bp.y_slice_stride + row * bp.ldy + b];
-        yr += y.x;
-        yi += y.y;
-      }
+    if (p >= 0) prow[m] = k * P + p;
+  }
+  float2 kd[NBT], xk[NBT];
+  float yr[NBT], yi[NBT];
+#pragma unroll
+  for (int m = 0; m < NBT; ++m) {
+    yr[m] = yi[m] = 0.f;
+    kd[m] = xk[m] = make_float2(0.f, 0.f);
+    if (bp.kdiag && prow[m] >= 0) {
+      kd[m] = bp.kdiag[prow[m]];
+      xk[m] = bp.xcur[(size_t)prow[m] * bp.ldx + b];
+    }
+  }
+  constexpr int SG = NBT <= 4 ? 4 : 2;  // slices per group
+  for (int s0 = 0; s0 < bp.y_slices; s0 += SG) {
+    float2 yv[NBT][SG];
+#pragma unroll
+    for (int m = 0; m < NBT; ++m)
+#pragma unroll
+      for (int q = 0; q < SG; ++q)
+        yv[m][q] = (prow[m] >= 0 && s0 + q < bp.y_slices)
+                       ? bp.Y[(size_t)(s0 + q) * bp.y_slice_stride + (size_t)prow[m] * bp.ldy + b]
+                       : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int m = 0; m < NBT; ++m)
+#pragma unroll
+      for (int q = 0; q < SG; ++q)
+        if (prow[m] >= 0 && s0 + q < bp.y_slices) {
+          yr[m] += yv[m][q].x;
+          yi[m] += yv[m][q].y;
+        }
+  }
+#pragma unroll
+  for (int m = 0; m < NBT; ++m) {
+    if (prow[m] >= 0) {
+      float zr = yr[m], zi = yi[m];
       if (bp.kdiag) {
-        const float2 kd = bp.kdiag[row], xv = bp.xcur[row * bp.ldx + b];
-        yr += kd.x * xv.x - kd.y * xv.y;
-        yi += kd.x * xv.y + kd.y * xv.x;
+        zr += kd[m].x * xk[m].x - kd[m].y * xk[m].y;
+        zi += kd[m].x * xk[m].y + kd[m].y * xk[m].x;
       }
-      ds[m] = make_double2((double)yr, partner ? -(double)yi : (double)yi);
+      ds[m] = make_double2((double)zr, partner[m] ? -(double)zi : (double)zi);
     }
+    if (m < nb) s_rho[(n * nb + m) * IB + i] = rs[m];
   }
   __syncthreads();
 
@@ -768,9 +802,8 @@ __global__ void __launch_bounds__(256) batched_stage_kernel(BatchParams bp) {
     const size_t g = bidx(bp, k, e, b);
     if (bp.intra) {
       // intraband part of the field term: -E(t) e.(rho)_{;k}
-      const double2 dv = bp.intra[g];
-      f.x -= ef * dv.x;
-      f.y -= ef * dv.y;
+      f.x -= ef * dv[m].x;
+      f.y -= ef * dv[m].y;
     }
     double2 next;
     if (bp.stage == 0) {
