@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-channelwise", action="store_true", help="skip the channel-wise compression leg")
     ap.add_argument("--no-intraband", action="store_true", help="skip the intraband field-coupling leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
+    ap.add_argument("--no-sweep-bf16x2", action="store_true",
+                    help="skip the sweep's BF16X2 low-rank leg (its randomized factorisation calls rocSOLVER)")
     ap.add_argument("--sweep-only", type=int, default=0, metavar="STEPS",
                     help="only run the batched 60x60 sweep, every instance for STEPS steps (for counter runs; "
                          "with --factors-cache the sweep's factors are cached as well)")
@@ -151,8 +153,8 @@ def main():
         from paper_2502_05635_amd import _abi as abi
         ctx = P.Context(0)
         cache = args.factors_cache + ".sweep.npz" if args.factors_cache else None
-        print(json.dumps({"batched_sweep": batched_sweep(P, abi, ctx, 0.05, steps=args.sweep_only, cache=cache)}),
-              flush=True)
+        print(json.dumps({"batched_sweep": batched_sweep(P, abi, ctx, 0.05, steps=args.sweep_only, cache=cache,
+                                                         bf16x2=not args.no_sweep_bf16x2)}), flush=True)
         ctx.close()
         return
 
@@ -323,7 +325,7 @@ def main():
         del K, fac, res, chan
         torch.cuda.empty_cache()
         progress("60x60 batched sweep")
-        sweep = batched_sweep(P, abi, ctx, frac)
+        sweep = batched_sweep(P, abi, ctx, frac, bf16x2=not args.no_sweep_bf16x2)
     if args.large_grid:
         progress("120x120 large grid")
     large = large_grid(P, abi, args.large_grid_steps) if args.large_grid else None
@@ -382,10 +384,11 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def batched_sweep(P, abi, ctx, frac, steps=0, cache=None):
+def batched_sweep(P, abi, ctx, frac, steps=0, cache=None, bf16x2=True):
     """The 60x60 batched field sweep: 64 instances of uneven length (2000 to
     8000 steps) integrated together on the matrix-core path, dense and
-    low-rank at the same kept fraction; instance.steps/s = sum of lengths / time."""
+    low-rank at the same kept fraction (FP32, and BF16 hi+lo factors of the
+    same rank); instance.steps/s = sum of lengths / time."""
     import numpy as np
     import torch
 
@@ -409,7 +412,23 @@ def batched_sweep(P, abi, ctx, frac, steps=0, cache=None):
     res = {"workload": f"{cfg.name}: 60x60 k-grid, N={n} complex64, {B} instances, "
                        f"{int(f.nsteps.min())}-{int(f.nsteps.max())} steps each, sum {total}",
            "rank": r, "kept_fraction": frac}
-    for name, op in (("dense", K), ("lowrank", fac)):
+    def bf16x2_factors():
+        # split-precision factors of the same rank from the randomized range
+        # finder (l = r + 128 test vectors, 2 power iterations)
+        g = torch.Generator(device=f"cuda:{ctx.device}")
+        g.manual_seed(2027)
+        om = (torch.randn(r + 128, n, dtype=torch.float64, device=K.device, generator=g)
+              + 1j * torch.randn(r + 128, n, dtype=torch.float64, device=K.device, generator=g)).contiguous()
+        out = ctx.kernel_compress_randomized(K, om, "rank", r, power_iters=2, out_dtype="bf16x2")
+        del om
+        torch.cuda.empty_cache()
+        return out
+
+    legs = [("dense", lambda: K), ("lowrank", lambda: fac)]
+    if bf16x2:
+        legs.append(("lowrank_bf16x2", bf16x2_factors))
+    for name, make in legs:
+        op = make()
         ctx.propagate(op, dm, "eh", short, cfg.dt)            # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -429,7 +448,14 @@ def batched_sweep(P, abi, ctx, frac, steps=0, cache=None):
                      "contraction_TFLOPs": flops / gemm_s / 1e12,
                      "contraction_mfma_frac_fp32": flops / gemm_s / 157.3e12,
                      "stage_kernel_us": s_ms / s_n * 1e3}
+        if name == "lowrank_bf16x2":
+            # three BF16 products per real product, against the dense BF16 peak
+            res[name]["factors"] = "randomized range finder, same rank"
+            res[name]["bf16_issued_frac"] = 3.0 * flops / gemm_s / 2.5e15
+            del op
     res["speedup_lowrank_vs_dense"] = res["lowrank"]["value"] / res["dense"]["value"]
+    if bf16x2:
+        res["speedup_lowrank_bf16x2_vs_dense"] = res["lowrank_bf16x2"]["value"] / res["dense"]["value"]
     del K, fac
     torch.cuda.empty_cache()
     return res

@@ -497,7 +497,7 @@ extern "C" int tdg_kernel_compress_randomized(tdg_ctx ctx, const void* K, int64_
   TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
 
   const size_t nl = (size_t)n * (size_t)l;
-  void *Y = nullptr, *Z = nullptr, *F = nullptr, *T = nullptr, *D = nullptr, *I = nullptr, *ST = nullptr, *KD = nullptr;
+  void *Y = nullptr, *Z = nullptr, *F = nullptr, *T = nullptr, *D = nullptr, *ST = nullptr, *KD = nullptr;
   TDG_TRY(ws_reserve(ctx, WS_RSVD_Y, nl * sizeof(double2), &Y));
   TDG_TRY(ws_reserve(ctx, WS_RSVD_Z, nl * sizeof(double2), &Z));
   if (dtype == TDG_C64) TDG_TRY(ws_reserve(ctx, WS_RSVD_F, 2 * nl * sizeof(float2), &F));

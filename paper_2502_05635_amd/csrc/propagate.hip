@@ -32,7 +32,6 @@
 namespace {
 
 constexpr int THREADS = 256;  // dense stage kernel and auxiliary kernels
-constexpr int LR_THREADS = 64; // low-rank stage kernel and projection: one wave per block
 constexpr int NB2_MAX = TDG_NB_MAX * TDG_NB_MAX;
 constexpr int ROWS = 4;  // kernel rows contracted together (shared drho loads)
 constexpr int ZSPLIT_MAX = 4;  // low rank: largest number of projection column slices
@@ -1022,6 +1021,20 @@ static const Variant kLowF64[] = {
     {"lowrank_f64_nt256", launch_stage<double, 1, 256, 1, 2>},
 };
 
+// Timing events of a tuner, destroyed on every exit path.
+struct TunerEvents {
+  std::vector<hipEvent_t> ev;
+  int create(tdg_ctx ctx, size_t count) {
+    ev.assign(count, nullptr);
+    for (auto& e : ev) TDG_TRY(hip_check(ctx, hipEventCreate(&e), "tuner event"));
+    return TDG_OK;
+  }
+  ~TunerEvents() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 template <size_t N>
 static void table(const Variant (&v)[N], const Variant*& out, int& count) {
   out = v;
@@ -1356,40 +1369,26 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
         const std::vector<int64_t> opts =
             ks_forced > 0 ? std::vector<int64_t>{ks_forced} : split_options(M, Kc, ks_def);
         const size_t ncand = opts.size() * ntilings;
-        std::vector<hipEvent_t> ev(2 * ncand, nullptr);
-        int erc = TDG_OK;
-        for (auto& e : ev)
-          if (erc == TDG_OK) erc = hip_check(ctx, hipEventCreate(&e), "event");
-        auto destroy = [&]() {
-          for (auto& e : ev)
-            if (e) hipEventDestroy(e);
-        };
-        if (erc != TDG_OK) {
-          destroy();
-          return erc;
-        }
+        TunerEvents te;
+        TDG_TRY(te.create(ctx, 2 * ncand));
+        const std::vector<hipEvent_t>& ev = te.ev;
         // one untimed round, then each candidate timed once per round, right
         // after another candidate's run (back-to-back repeats of one product
         // slow down and would penalise the wider splits)
         std::vector<float> tmin(ncand, 1e30f);
         for (int round = 0; round < 6; ++round) {
           for (size_t c = 0; c < ncand; ++c) {
-            hipEventRecord(ev[2 * c], ctx->stream);
+            (void)hipEventRecord(ev[2 * c], ctx->stream);
             run((int)(c % ntilings), opts[c / ntilings]);
-            hipEventRecord(ev[2 * c + 1], ctx->stream);
+            (void)hipEventRecord(ev[2 * c + 1], ctx->stream);
           }
-          erc = hip_check(ctx, hipEventSynchronize(ev[2 * ncand - 1]), "GEMM tuning");
-          if (erc != TDG_OK) {
-            destroy();
-            return erc;
-          }
+          TDG_TRY(hip_check(ctx, hipEventSynchronize(ev[2 * ncand - 1]), "GEMM tuning"));
           for (size_t c = 0; c < ncand && round > 0; ++c) {
             float ms = 0.f;
-            hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]);
+            if (hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]) != hipSuccess) ms = 1e30f;
             tmin[c] = std::min(tmin[c], ms);
           }
         }
-        destroy();
         // the earliest (split, tiling) within 2 % of the fastest (the default split first)
         const float fastest = *std::min_element(tmin.begin(), tmin.end());
         int bestv = 0;
@@ -1540,9 +1539,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     std::vector<std::pair<int, hipGraphExec_t>> execs;
     hipStream_t cap = nullptr;
     auto release = [&]() {
-      for (auto& e : execs) hipGraphExecDestroy(e.second);
+      for (auto& e : execs) (void)hipGraphExecDestroy(e.second);
       execs.clear();
-      if (cap) hipStreamDestroy(cap);
+      if (cap) (void)hipStreamDestroy(cap);
       cap = nullptr;
     };
     if (use_graphs && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
@@ -1567,7 +1566,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
           issue_step(cap, step, 0, n_obs, n_dyn, true, false);
           const hipError_t e1 = hipStreamEndCapture(cap, &g);
           const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) : e1;
-          if (g) hipGraphDestroy(g);
+          if (g) (void)hipGraphDestroy(g);
           if (e2 != hipSuccess) {
             rc = fail(ctx, TDG_E_HIP, "graph capture: %s", hipGetErrorString(e2));
             break;
@@ -1591,7 +1590,11 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       }
       if ((step & 63) == 0) rc = launch_check(ctx, "batched propagation launch");
     }
-    if (use_graphs) hipStreamSynchronize(ctx->stream);
+    // the graph executables are destroyed only after their replays finished
+    if (use_graphs) {
+      const hipError_t es = hipStreamSynchronize(ctx->stream);
+      if (es != hipSuccess && rc == TDG_OK) rc = fail(ctx, TDG_E_HIP, "graph replay: %s", hipGetErrorString(es));
+    }
     release();
     TDG_TRY(rc);
     hipLaunchKernelGGL(finish_batched_kernel, dim3(nk), dim3(256), 0, ctx->stream, (const double2*)rho_n,
@@ -1628,9 +1631,9 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     } else {
       // time each variant on stage 0 of step 0: it reads rho and writes only
       // the stage state, accumulator and next gather, which init restores
-      hipEvent_t ea, eb;
-      TDG_TRY(hip_check(ctx, hipEventCreate(&ea), "tuner event"));
-      TDG_TRY(hip_check(ctx, hipEventCreate(&eb), "tuner event"));
+      TunerEvents te;
+      TDG_TRY(te.create(ctx, 2));
+      const hipEvent_t ea = te.ev[0], eb = te.ev[1];
       const int dyn0 = count_gt(0);
       field_table(0);
       sp.step = 0;
@@ -1659,7 +1662,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
           if (projects && !tune_split) project(x0, dyn0);
           for (int v = 0; v < nvar; ++v) {
             run(v);  // warm-up
-            hipEventRecord(ea, ctx->stream);
+            (void)hipEventRecord(ea, ctx->stream);
             for (int rep = 0; rep < 8; ++rep) {
               if (tune_split) {
                 run(v);
@@ -1667,11 +1670,11 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
                 vt[v].fn(g, 0, ctx->stream, sp, nullptr, nullptr);
               }
             }
-            hipEventRecord(eb, ctx->stream);
+            (void)hipEventRecord(eb, ctx->stream);
             TDG_TRY(launch_check(ctx, "tuner launch"));
             TDG_TRY(hip_check(ctx, hipEventSynchronize(eb), "tuner sync"));
             float ms = 0.f;
-            hipEventElapsedTime(&ms, ea, eb);
+            if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) ms = 1e30f;
             tmin[si][v] = std::min(tmin[si][v], ms);
           }
         }
@@ -1689,8 +1692,6 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
             best_split = si;
             break;
           }
-      hipEventDestroy(ea);
-      hipEventDestroy(eb);
       if (tune_split) set_split(splits[best_split]);
       ctx->tuned.emplace_back(key, var + 100 * best_split);
       TDG_TRY(init());  // the caller's rho was only read

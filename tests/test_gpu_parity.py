@@ -265,6 +265,14 @@ def test_invalid_arguments_rejected(P, ctx, tb4_6):
         ctx.propagate(kg, dm, "eh", strong(10), -1.0)          # negative dt
     with pytest.raises(P.TdgError):
         ctx.kernel_compress(kg, "rank", 50, max_rank=10)       # rank above capacity
+    from paper_2502_05635_amd import _abi as abi
+    for option, bad in ((abi.TDG_OPT_GEMM_SLICES, -1), (abi.TDG_OPT_GEMM_SLICES, 4097),
+                        (abi.TDG_OPT_GEMM_VARIANT, 3), (abi.TDG_OPT_GEMM_VARIANT, -2)):
+        with pytest.raises(P.TdgError) as e:
+            ctx.set_option(option, bad)
+        assert e.value.code == -1, (option, bad)
+    ctx.set_option(abi.TDG_OPT_GEMM_SLICES, 0)
+    ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
 
 
 def test_check_numeric_reports_nan(P, ctx, tb4_6):
