@@ -168,17 +168,51 @@ __device__ inline void rows_dot(const double2* __restrict__ A, int64_t lda, int 
   }
 }
 
+// One 32-bit word of lane l ^ 1, l ^ 2 (quad permutes), of the mirrored lane
+// in the 8-lane half row, or of the mirrored lane in the 16-lane row (DPP).
+template <int CTRL>
+__device__ inline int dpp_word(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(dpp_word<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_word<CTRL>((int)(b & 0xffffffffLL)), hi = dpp_word<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float lane_value(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of v over the 64 lanes of a full wave, returned to every lane: within
+// each 16-lane row by four DPP steps (quad permutes [1,0,3,2] and [2,3,0,1],
+// half-row mirror, row mirror), then the four row sums in row order.
+template <typename T>
+__device__ inline T wave_sum(T v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
 // Sum each thread's ROWS complex partials over the block; out[2r], out[2r+1]
-// receive row r (as double).  Wave shuffles, then a fixed-order sum over waves.
+// receive row r (as double).  Wave sums (every lane of the block calls it),
+// then a fixed-order sum over waves.
 template <typename T, int NT>
 __device__ inline void block_reduce(T (&ar)[ROWS], T (&ai)[ROWS], double* red, double* out) {
   constexpr int WAVES = NT / 64;
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
-    for (int off = 32; off > 0; off >>= 1) {
-      ar[r] += __shfl_xor(ar[r], off, 64);
-      ai[r] += __shfl_xor(ai[r], off, 64);
-    }
+    ar[r] = wave_sum(ar[r]);
+    ai[r] = wave_sum(ai[r]);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
