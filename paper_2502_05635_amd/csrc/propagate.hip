@@ -297,9 +297,10 @@ __device__ inline void obs_partial(const StageParams& sp, const double2* s_rho, 
   }
 }
 
-__device__ inline double2 proj_e(const tdg_field& F, double2 a, double2 b) {
-  return make_double2(F.ex * a.x + F.ey * b.x, F.ex * a.y + F.ey * b.y);
+__device__ inline double2 proj_e(double ex, double ey, double2 a, double2 b) {
+  return make_double2(ex * a.x + ey * b.x, ex * a.y + ey * b.y);
 }
+__device__ inline double2 proj_e(const tdg_field& F, double2 a, double2 b) { return proj_e(F.ex, F.ey, a, b); }
 
 // Stage kernel: one block per (k point, instance).  LOWRANK selects the
 // low-rank expansion (rows of S against z, plus K_diag o x); it is a template
@@ -329,8 +330,6 @@ stage_kernel(StageParams sp) {
   // ---- loads: the low-rank kernel issues every load of the block before any
   // use (its lifetime is latency-bound); the dense kernel loads the per-k
   // state after its row stream (bandwidth-bound, registers kept for the stream)
-  const tdg_field F = sp.fields[b];
-  const double ef = dyn ? sp.ftab[((size_t)sp.obs_slot * sp.batch + b) * 4 + sp.stage] : 0.0;
   double2 r_s = make_double2(0.0, 0.0), r_n = r_s, r_acc = r_s, d0 = r_s, d1 = r_s, v0 = r_s, v1 = r_s;
   double e_nn = 0.0;
   auto load_state = [&]() {
@@ -349,7 +348,24 @@ stage_kernel(StageParams sp) {
       }
     }
   };
-  if (LOWRANK) load_state();
+  // E(t) of this stage and the polarisation, for the epilogue only, read by
+  // vector loads issued after the state loads.  As scalar loads they formed a
+  // pointer chase (argument, table, value) ahead of the first vector load, and
+  // scalar loads complete out of order, so each use waited for all of them.
+  // The offset is a zero held in a vector register, opaque to the compiler,
+  // which then cannot treat the addresses as uniform.
+  double ef = 0.0, fex = 0.0, fey = 0.0;
+  auto load_field = [&]() {
+    int vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+    fex = (&sp.fields[b].ex)[vzero];
+    fey = (&sp.fields[b].ey)[vzero];
+    if (dyn) ef = sp.ftab[((size_t)sp.obs_slot * sp.batch + b) * 4 + sp.stage + vzero];
+  };
+  if (LOWRANK) {
+    load_state();
+    load_field();
+  }
   const C* A = reinterpret_cast<const C*>(sp.A);
   const C* vec = reinterpret_cast<const C*>(sp.vec) + (size_t)b * sp.vstride;
   const C* xcur = reinterpret_cast<const C*>(sp.xcur) + (size_t)b * sp.xstride;
@@ -424,12 +440,16 @@ stage_kernel(StageParams sp) {
       block_reduce<T, NT>(ar, ai, s_red, s_y + 2 * r0);
     }
   }
-  if (!LOWRANK) load_state();
+  if (!LOWRANK) {
+    load_state();
+    load_field();
+  }
   // the per-k epilogue runs in the first wave (nb^2 <= 64 elements, P <= 64 pairs)
   if (t >= 64) return;
   if (t < nb2) s_rho[t] = r_s;
   wave_sync();
-  if (sp.stage == 0 && sp.obs_part) obs_partial(sp, s_rho, s_obs, proj_e(F, d0, d1), proj_e(F, v0, v1), k, b);
+  if (sp.stage == 0 && sp.obs_part)
+    obs_partial(sp, s_rho, s_obs, proj_e(fex, fey, d0, d1), proj_e(fex, fey, v0, v1), k, b);
   if (!dyn) return;                              // final time of this instance: observables only
   if (LOWRANK && t < P) {
     const T re = kd_t.x * x_t.x - kd_t.y * x_t.y, im = kd_t.x * x_t.y + kd_t.y * x_t.x;
@@ -451,7 +471,7 @@ stage_kernel(StageParams sp) {
       const int p = (m - sp.nv) * sp.nv + n;
       ds = make_double2(s_y[2 * p], -s_y[2 * p + 1]);
     }
-    const double2 de = proj_e(F, d0, d1);
+    const double2 de = proj_e(fex, fey, d0, d1);
     double2 h = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
     if (n == m) h.x += e_nn;
     s_h[t] = h;
