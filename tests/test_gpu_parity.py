@@ -467,6 +467,23 @@ def test_bf16x2_batched_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, tiling):
         ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
 
 
+@pytest.mark.parametrize("kind,slices", [("dense", 1), ("lowrank", 4096)])
+def test_bf16x2_batched_forced_split_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, slices):
+    """The BF16X2 products with the split-K forced to one slice and to the
+    most slices allowed (second tiling), against the FP64 oracle."""
+    from paper_2502_05635_amd import _abi as abi
+    ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, 1)
+    ctx.set_option(abi.TDG_OPT_GEMM_SLICES, slices)
+    try:
+        _bf16x2_batched_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind)
+        _log(f"  {ctx.last_variant()}")
+        if slices == 1:
+            assert "slices 1)" in ctx.last_variant()
+    finally:
+        ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
+        ctx.set_option(abi.TDG_OPT_GEMM_SLICES, 0)
+
+
 def _bf16x2_batched_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind):
     fields = _uneven_fields(6)
     dm = _dev(P, tb4_6)
