@@ -328,13 +328,17 @@ typedef struct {
 } tdg_grads;
 
 /* Integrates forward from rho0 (device c128 [batch][nk][nb][nb]; NULL =
- * rho_eq) keeping rho every checkpoint_every steps, then pulls the loss back
- * step by step, recomputing each segment from its checkpoint.  FP64 only:
- * op->dtype must be TDG_C128 (dense or low rank).  Every instance must have
- * the same nsteps.  With model->links the intraband term is differentiated
- * too (its covariant difference is anti-self-adjoint).  Device workspace about
- * (nsteps / M + M + 15) states plus 4 (M for low rank) x 2 x n x batch
- * complex128 values, held by the context.  Synchronises the stream. */
+ * rho_eq) keeping rho every checkpoint_every (M) steps, then pulls the loss
+ * back step by step, recomputing each segment from its checkpoint once and
+ * keeping every step's stage states, products and gathers of the segment
+ * (when those take at most 8 GiB; beyond that each backward step recomputes
+ * its own forward step).  FP64 only: op->dtype must be TDG_C128 (dense or low
+ * rank).  Every instance must have the same nsteps.  With model->links the
+ * intraband term is differentiated too (its covariant difference is
+ * anti-self-adjoint).  Device workspace about (nsteps / M + 4 M + 12) states
+ * plus 12 M x n x batch complex128 values (without the stash: nsteps / M +
+ * M + 15 states plus 4 (M for low rank) x 2 x n x batch values), held by the
+ * context.  Synchronises the stream. */
 int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
                           const tdg_field* fields, int32_t batch, double dt, const void* rho0,
                           int32_t checkpoint_every, const tdg_obs_grad* g, tdg_grads* out);
@@ -402,6 +406,11 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * 0 (default) lets the tuner choose.  Other values: TDG_E_INVAL.  Results
  * differ only in summation order. */
 #define TDG_OPT_GEMM_SLICES 6
+/* tdg_propagate_adjoint: 1 (default) keeps each segment's stage data when it
+ * fits (see there); 0 always recomputes each backward step's forward step,
+ * for the smaller workspace.  Results are identical.  Other values:
+ * TDG_E_INVAL. */
+#define TDG_OPT_ADJOINT_STASH 7
 int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
 /* Name of the stage-kernel variant the last tdg_propagate used ("" before any). */
 const char* tdg_last_variant(tdg_ctx ctx);

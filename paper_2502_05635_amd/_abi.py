@@ -31,6 +31,7 @@ TDG_OPT_GEMM_TILE = 3
 TDG_OPT_GEMM_VARIANT = 4
 TDG_OPT_GRAPHS = 5
 TDG_OPT_GEMM_SLICES = 6
+TDG_OPT_ADJOINT_STASH = 7
 
 P = C.c_void_p
 

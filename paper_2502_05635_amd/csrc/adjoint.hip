@@ -38,6 +38,9 @@
 namespace {
 
 constexpr int AT = 64;  // threads per block of the per-k kernels (a block holds 64 / nb^2 k points)
+// Largest per-segment stage stash (bytes) kept instead of rerunning each
+// forward step in the backward sweep.
+constexpr double ADJ_STASH_BYTES = 8.0 * (1 << 30);
 
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -456,13 +459,20 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   // ---- workspace ---------------------------------------------------------
   const size_t st_el = (size_t)batch * nk * nb2;
   const size_t st_b = st_el * sizeof(double2);
-  const int cblocks = (lowrank ? M : 1) * 4;
   const size_t xn_b = (size_t)n * batch * sizeof(double2);
   const size_t zr_b = (size_t)std::max<int64_t>(rank, 1) * batch * sizeof(double2);
+  // Stage stash: when a segment's stage states, products and gathers fit in
+  // ADJ_STASH_BYTES, the segment's recompute keeps them for every step and the
+  // backward steps read them; otherwise each backward step reruns its forward
+  // step (one more forward pass).
+  const bool stash = ctx->adj_stash && (double)M * (3.0 * st_b + 8.0 * xn_b) <= ADJ_STASH_BYTES;
+  const int per_step = stash ? M : 1;
+  const int cblocks = (lowrank || stash ? M : 1) * 4;
   Carver cv;
-  const size_t o_ck = cv.take(st_b * nck), o_seg = cv.take(st_b * M), o_ys = cv.take(st_b * 3),
+  const size_t o_ck = cv.take(st_b * nck), o_seg = cv.take(st_b * M), o_ys = cv.take(st_b * 3 * per_step),
                o_out = cv.take(st_b), o_acc = cv.take(st_b), o_abar = cv.take(st_b), o_ybar = cv.take(st_b),
-               o_yd = cv.take(st_b), o_acca = cv.take(st_b), o_s = cv.take(xn_b * 4), o_x = cv.take(xn_b * cblocks),
+               o_yd = cv.take(st_b), o_acca = cv.take(st_b), o_s = cv.take(xn_b * 4 * per_step),
+               o_x = cv.take(xn_b * cblocks),
                o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
                o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)4 * batch * nk * sizeof(double)),
                o_df = cv.take((size_t)batch * 4 * sizeof(double)), o_f = cv.take((size_t)batch * sizeof(tdg_field));
@@ -557,23 +567,24 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   auto sbcblk = [&](int cb) { return SBC + (size_t)cb * n * batch; };
   auto zblk = [&](int cb) { return ZS + (size_t)cb * rank * batch; };
   auto ucblk = [&](int cb) { return UC + (size_t)cb * rank * batch; };
-  auto sst = [&](int s) { return SS + (size_t)s * n * batch; };
-  auto ys = [&](int s) { return YS + (size_t)(s - 1) * st_el; };  // s = 1, 2, 3
+  // stage s of stash slot j (slot 0 without the stash)
+  auto sst = [&](int s, int j) { return SS + ((size_t)j * 4 + s) * n * batch; };
+  auto ys = [&](int s, int j) { return YS + ((size_t)j * 3 + s - 1) * st_el; };  // s = 1, 2, 3
 
   // D(v) of a state-shaped array (caller's instance order) into out
   auto covd = [&](const double2* v, double2* o) {
     covariant_derivative(ctx->stream, model, v, (int64_t)nk * nb2, nb2, 1, dfields, batch, o);
   };
-  // One forward step from rho_in to rho_out, keeping y_s, S_s, X_s, Z_s of
-  // its stages in the column block group j.
-  auto run_step = [&](int step, const double2* rho_in, double2* rho_out, int j) -> int {
+  // One forward step from rho_in to rho_out, keeping X_s, Z_s of its stages
+  // in the column block group j and y_s, S_s in stash slot js.
+  auto run_step = [&](int step, const double2* rho_in, double2* rho_out, int j, int js) -> int {
     hipLaunchKernelGGL(adj_gather_kernel, grid, dim3(AT), 0, ctx->stream, a, rho_in, xblk(j * 4));
     for (int s = 0; s < 4; ++s) {
-      const double2* y = s == 0 ? rho_in : ys(s);
-      TDG_TRY(apply_k(xblk(j * 4 + s), sst(s), lowrank ? zblk(j * 4 + s) : nullptr));
+      const double2* y = s == 0 ? rho_in : ys(s, js);
+      TDG_TRY(apply_k(xblk(j * 4 + s), sst(s, js), lowrank ? zblk(j * 4 + s) : nullptr));
       if (intra) covd(y, DY);
-      hipLaunchKernelGGL(adj_fwd_stage_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, rho_in, y, sst(s),
-                         xblk(j * 4 + s), (const double2*)DY, ACC, s < 3 ? ys(s + 1) : rho_out,
+      hipLaunchKernelGGL(adj_fwd_stage_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, rho_in, y, sst(s, js),
+                         xblk(j * 4 + s), (const double2*)DY, ACC, s < 3 ? ys(s + 1, js) : rho_out,
                          s < 3 ? xblk(j * 4 + s + 1) : nullptr);
     }
     return launch_check(ctx, "adjoint forward step");
@@ -594,7 +605,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     const double2* rin = CK + (size_t)c * st_el;
     for (int i = 0; i < M; ++i) {
       double2* rout = (i == M - 1) ? CK + (size_t)(c + 1) * st_el : ((i & 1) ? OUT : SEG);
-      TDG_TRY(run_step(c * M + i, rin, rout, 0));
+      TDG_TRY(run_step(c * M + i, rin, rout, 0, 0));
       rin = rout;
     }
   }
@@ -604,21 +615,28 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     const int start = c * M, end = std::min(nsteps, start + M);
     // states rho_start .. rho_{end-1}: slot 0 is the checkpoint itself
     auto seg = [&](int i) { return i == 0 ? CK + (size_t)c * st_el : SEG + (size_t)i * st_el; };
-    for (int i = 0; i + 1 < end - start; ++i) TDG_TRY(run_step(start + i, seg(i), seg(i + 1), 0));
+    if (stash) {
+      // every step of the segment once, each keeping its stages in slot i
+      for (int i = 0; i < end - start; ++i)
+        TDG_TRY(run_step(start + i, seg(i), i + 1 < end - start ? seg(i + 1) : OUT, i, i));
+    } else {
+      for (int i = 0; i + 1 < end - start; ++i) TDG_TRY(run_step(start + i, seg(i), seg(i + 1), 0, 0));
+    }
     for (int step = end - 1; step >= start; --step) {
-      const int j = lowrank ? step - start : 0;
-      TDG_TRY(run_step(step, seg(step - start), OUT, j));
+      const int j = lowrank || stash ? step - start : 0;
+      const int js = stash ? step - start : 0;
+      if (!stash) TDG_TRY(run_step(step, seg(step - start), OUT, j, 0));
       static const double coef[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
       static const double cnext[4] = {0.5, 0.5, 1.0, 0.0};
       if (intra) covd(ABAR, DA);
       for (int s = 3; s >= 0; --s) {
-        const double2* y = s == 0 ? seg(step - start) : ys(s);
+        const double2* y = s == 0 ? seg(step - start) : ys(s, js);
         const int cb = j * 4 + s;
         if (intra) {
           covd(y, DY);
           if (s < 3) covd(YBAR, DYB);
         }
-        hipLaunchKernelGGL(adj_bwd_a_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, y, sst(s), xblk(cb), ABAR,
+        hipLaunchKernelGGL(adj_bwd_a_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, y, sst(s, js), xblk(cb), ABAR,
                            coef[s] * dt, s == 3 ? (const double2*)nullptr : YBAR, cnext[s] * dt, (const double2*)DY,
                            (const double2*)DA, (const double2*)DYB, YD, sbcblk(cb), part);
         TDG_TRY(apply_kh(sbcblk(cb), lowrank ? ucblk(cb) : nullptr));

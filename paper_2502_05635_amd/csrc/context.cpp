@@ -179,6 +179,11 @@ int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value) {
     ctx->graphs = value != 0;
     return TDG_OK;
   }
+  if (option == TDG_OPT_ADJOINT_STASH) {
+    if (value != 0 && value != 1) return fail(ctx, TDG_E_INVAL, "adjoint stash %lld is not 0 or 1", (long long)value);
+    ctx->adj_stash = (int)value;
+    return TDG_OK;
+  }
   if (option == TDG_OPT_GEMM_SLICES) {
     if (value < 0 || value > 4096) return fail(ctx, TDG_E_INVAL, "GEMM slices %lld outside [0, 4096]", (long long)value);
     ctx->gemm_slices = (int)value;

@@ -74,6 +74,7 @@ struct tdg_ctx_s {
   int gemm_variant = -1; // tiling of the matrix-core product: -1 tuned per shape, else 0..2 (cgemm_f32)
   bool graphs = false;   // batched path: replay captured RK4 steps (TDG_OPT_GRAPHS)
   int gemm_slices = 0;   // batched products: 0 = tuned split-K, else this many K slices (TDG_OPT_GEMM_SLICES)
+  int adj_stash = 1;     // adjoint: keep a segment's stage data when it fits (TDG_OPT_ADJOINT_STASH)
   std::vector<std::pair<std::string, int>> tuned;  // shape key -> variant index
   std::string last_variant;
 };

@@ -104,6 +104,38 @@ def test_adjoint_dense_matches_oracle(P, ctx, block):
     assert max(errs.values()) <= 1e-10
 
 
+@pytest.mark.parametrize("kind", ["dense", "lowrank"])
+def test_adjoint_stash_matches_recompute(P, ctx, kind):
+    """Keeping each segment's stage data (default) and rerunning every
+    backward step's forward step (TDG_OPT_ADJOINT_STASH 0) are the same
+    arithmetic: every gradient agrees bitwise, with a ragged last segment."""
+    from paper_2502_05635_amd import _abi as abi
+    m = tb4_model(4, A, 0.5)
+    dm = P.DeviceModel.from_model(m)
+    if kind == "dense":
+        op = ctx.kernel_build(dm, R0_STABLE, "eh", "c128")
+    else:
+        n = ctx.kernel_dim(dm, "eh")
+        kd, us, vh = hermitian_lowrank_factors(n, 12, 0.03, -0.01, 31)
+        op = P.LowRankFactors(torch.from_numpy(kd).cuda(), torch.from_numpy(us).cuda(), torch.from_numpy(vh).cuda(),
+                              None, 12, 0.0, 0.0, "c128")
+    f = _fields()
+    w = _weights(2, 34)
+    out = []
+    try:
+        for stash in (1, 0):
+            ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, stash)
+            out.append(ctx.propagate_adjoint(op, dm, "eh", f, DT, gP=w[0], gJ=w[1], gocc=w[2], checkpoint_every=7))
+    finally:
+        ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, 1)
+    for key, v in out[0].items():
+        if v is None:
+            continue
+        assert torch.equal(v, out[1][key]), key
+    with pytest.raises(P.TdgError):
+        ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, 2)
+
+
 def test_adjoint_rejects_unsupported(P, ctx):
     m = tb4_model(4, A, 0.5)
     dm = P.DeviceModel.from_model(m)
