@@ -245,13 +245,13 @@ def main():
         us = {k: prof[k][0] / prof[k][1] * 1e3 for k in ("stage", "project", "intra") if prof[k][1]}
         intraband = {
             "value": args.steps / secs, "ms_per_step": 1e3 * secs / args.steps, "variant": variant,
+            # one instance: the covariant difference is formed in the stage
+            # kernel's epilogue (no launch of its own)
             "stage_kernel_us": us.get("stage"), "project_kernel_us": us.get("project"),
-            "covariant_derivative_kernel_us": us.get("intra"), "links_build_seconds": links_s,
-            # one read of the stage state, of both link planes, one write of the result
-            "covariant_derivative_bytes_per_launch": 4 * nk * nb * nb * 16,
+            "links_build_seconds": links_s,
+            # per stage kernel: the neighbours' states and both link planes
+            "covariant_difference_extra_bytes_per_launch": 4 * nk * nb * nb * 16,
         }
-        if us.get("intra"):
-            intraband["covariant_derivative_GBps"] = intraband["covariant_derivative_bytes_per_launch"] / us["intra"] / 1e3
 
     # errors against the stored FP64 oracle series (same operator, same steps):
     # over the first half of the run (t <= t0, before the post-pulse chaotic

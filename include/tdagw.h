@@ -362,7 +362,7 @@ int tdg_check_numeric(tdg_ctx ctx, const tdg_obs* obs, int32_t batch, const tdg_
 #define TDG_KCLASS_STAGE 0   /* fused contraction + commutator + RK4 stage kernel */
 #define TDG_KCLASS_PROJECT 1 /* low-rank projection z = V^H x (single-instance path) */
 #define TDG_KCLASS_GEMM 2    /* matrix-core products of the batched path */
-#define TDG_KCLASS_INTRA 3   /* intraband covariant derivative (single-instance path, model links) */
+#define TDG_KCLASS_INTRA 3   /* intraband covariant derivative launches (batched path, model links; the per-instance path forms it in the stage kernel) */
 int tdg_profile_enable(tdg_ctx ctx, int32_t on);
 int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* launches);
 

@@ -41,6 +41,7 @@ enum WsSlot {
   WS_STEP,       // batched path: step counter read by graph replays
   WS_XB,         // batched BF16X2 path: X split into bf16 planes once per product
   WS_INTRA,      // intraband term: covariant derivative of the stage state, c128 like the state
+  WS_RHO_S2,     // intraband term, per-instance path: second stage-state buffer (stages alternate)
   WS_FTAB,       // field at the stage times of a chunk of steps, double [chunk][B][4]
   WS_COUNT
 };

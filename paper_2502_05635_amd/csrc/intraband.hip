@@ -20,6 +20,7 @@
 #include <cmath>
 #include <vector>
 
+#include "covariant.h"
 #include "internal.h"
 
 namespace {
@@ -173,38 +174,22 @@ __global__ void __launch_bounds__(256) covariant_derivative_kernel(
   const int e = (int)((j / batch) % nb2);
   const int k = (int)(j / ((int64_t)batch * nb2));
   const int n = e / nb, m = e - n * nb;
-  const int on = n < nv ? 0 : nv, sn = n < nv ? nv : nb - nv;
-  const int om = m < nv ? 0 : nv, sm = m < nv ? nv : nb - nv;
-  const int i1 = k / nk2, i2 = k - i1 * nk2;
   const tdg_field F = fields[b];
   const double2* yb = y + (int64_t)b * sb;
   double2 acc = make_double2(0.0, 0.0);
   for (int a = 0; a < 2; ++a) {
     const double ea = a == 0 ? F.ex : F.ey;
     if (ea == 0.0) continue;
-    const int kf = a == 0 ? ((i1 + 1) % nk1) * nk2 + i2 : i1 * nk2 + (i2 + 1) % nk2;
-    const int kb = a == 0 ? ((i1 + nk1 - 1) % nk1) * nk2 + i2 : i1 * nk2 + (i2 + nk2 - 1) % nk2;
+    int kf, kb;
+    tdg::covariant_neighbours(k, a, nk1, nk2, kf, kb);
     const double2* lf = links + ((size_t)a * nk + k) * nb2;   // L_a(k)
     const double2* lb = links + ((size_t)a * nk + kb) * nb2;  // L_a(k - b_a)
     const double2* yf = yb + (int64_t)kf * sk;
     const double2* yk = yb + (int64_t)kb * sk;
-    double2 t = make_double2(0.0, 0.0);
-    for (int i = on; i < on + sn; ++i) {
-      // forward: L[n][i] sum_j y_f[i][j] conj(L[m][j]);  backward: conj(Lb[i][n]) sum_j y_b[i][j] Lb[j][m]
-      double2 sf = make_double2(0.0, 0.0), sbk = make_double2(0.0, 0.0);
-      for (int jj = om; jj < om + sm; ++jj) {
-        const double2 pf = zmulc(lf[m * nb + jj], yf[(int64_t)(i * nb + jj) * se]);
-        const double2 pb = zmul(yk[(int64_t)(i * nb + jj) * se], lb[jj * nb + m]);
-        sf.x += pf.x;
-        sf.y += pf.y;
-        sbk.x += pb.x;
-        sbk.y += pb.y;
-      }
-      const double2 f = zmul(lf[n * nb + i], sf);
-      const double2 g = zmulc(lb[i * nb + n], sbk);
-      t.x += f.x - g.x;
-      t.y += f.y - g.y;
-    }
+    const double2 t = tdg::covariant_axis_element(
+        n, m, nb, nv, [&](int r, int c) { return yf[(int64_t)(r * nb + c) * se]; },
+        [&](int r, int c) { return yk[(int64_t)(r * nb + c) * se]; }, [&](int r, int c) { return lf[r * nb + c]; },
+        [&](int r, int c) { return lb[r * nb + c]; });
     const double c = ea * (a == 0 ? c1 : c2);
     acc.x += c * t.x;
     acc.y += c * t.y;

@@ -27,6 +27,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "covariant.h"
 #include "internal.h"
 
 namespace {
@@ -258,9 +259,13 @@ struct StageParams {
   int n_dyn;          // blocks with blockIdx.y < n_dyn integrate; the others only record observables
   int step, stage;
   double dt;
-  const double2* intra;  // intraband term e.(rho_s)_{;k} of this stage, laid out as rho_s; NULL = none
-  int tr_signed;         // per-k trace partial signed (summed over k) instead of |.| (maximised)
-  const double* ftab;    // field at the stage times, [obs slot][B][4] (field_table_kernel)
+  double2* rho_s_out;    // where the next stage state goes: rho_s itself, or (with links) the other buffer
+  const double2* links;  // intraband term: links L_a(k) [2][nk][nb][nb], the covariant difference of
+                         // rho_s formed in the epilogue from the neighbours' states; NULL = none
+  int nk1, nk2;
+  double cov_c1, cov_c2;  // 1 / (2 |b_a|) per grid axis
+  int tr_signed;          // per-k trace partial signed (summed over k) instead of |.| (maximised)
+  const double* ftab;     // field at the stage times, [obs slot][B][4] (field_table_kernel)
 };
 
 // Per-k observables of s_rho (LDS) into obs_part; de, ve are this thread's
@@ -326,6 +331,7 @@ stage_kernel(StageParams sp) {
   __shared__ double s_y[2 * NB2_MAX + 2 * ROWS];
   __shared__ double s_red[WAVES * 2 * ROWS];
   __shared__ double s_obs[5][NB2_MAX];
+  __shared__ double2 s_cov[8][NB2_MAX];  // per axis: y(k + b), y(k - b), L(k), L(k - b)
 
   // ---- loads: the low-rank kernel issues every load of the block before any
   // use (its lifetime is latency-bound); the dense kernel loads the per-k
@@ -446,6 +452,22 @@ stage_kernel(StageParams sp) {
   }
   // the per-k epilogue runs in the first wave (nb^2 <= 64 elements, P <= 64 pairs)
   if (t >= 64) return;
+  if (sp.links && dyn && t < nb2) {
+    // intraband term: this lane's element of the neighbour states and links
+    // straight into LDS (read from rho_s while this kernel writes the next
+    // stage state to the other buffer); loaded here, not with the state, so
+    // that no variant holds them in registers across the contraction
+    const size_t sb = (size_t)b * sp.nk;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      int kf, kr;
+      tdg::covariant_neighbours(k, a, sp.nk1, sp.nk2, kf, kr);
+      s_cov[4 * a][t] = sp.rho_s[(sb + kf) * nb2 + t];
+      s_cov[4 * a + 1][t] = sp.rho_s[(sb + kr) * nb2 + t];
+      s_cov[4 * a + 2][t] = sp.links[((size_t)a * sp.nk + k) * nb2 + t];
+      s_cov[4 * a + 3][t] = sp.links[((size_t)a * sp.nk + kr) * nb2 + t];
+    }
+  }
   if (t < nb2) s_rho[t] = r_s;
   wave_sync();
   if (sp.stage == 0 && sp.obs_part)
@@ -490,9 +512,20 @@ stage_kernel(StageParams sp) {
     }
     double2 f = make_double2(c.y, -c.x);  // -i c
     const size_t g = kb + t;
-    if (sp.intra) {
+    if (sp.links) {
       // intraband part of the field term: -E(t) e.(rho)_{;k}
-      const double2 dv = sp.intra[g];
+      double2 dv = make_double2(0.0, 0.0);
+      for (int a = 0; a < 2; ++a) {
+        const double ea = a == 0 ? fex : fey;
+        if (ea == 0.0) continue;
+        const double2 *yf = s_cov[4 * a], *yr = s_cov[4 * a + 1], *lf = s_cov[4 * a + 2], *lr = s_cov[4 * a + 3];
+        const double2 tt = tdg::covariant_axis_element(
+            n, m, nb, sp.nv, [&](int r, int q) { return yf[r * nb + q]; }, [&](int r, int q) { return yr[r * nb + q]; },
+            [&](int r, int q) { return lf[r * nb + q]; }, [&](int r, int q) { return lr[r * nb + q]; });
+        const double cf = ea * (a == 0 ? sp.cov_c1 : sp.cov_c2);
+        dv.x += cf * tt.x;
+        dv.y += cf * tt.y;
+      }
       f.x -= ef * dv.x;
       f.y -= ef * dv.y;
     }
@@ -511,7 +544,7 @@ stage_kernel(StageParams sp) {
       next = make_double2(r_n.x + w * (r_acc.x + f.x), r_n.y + w * (r_acc.y + f.y));
       sp.rho_n[g] = next;
     }
-    sp.rho_s[g] = next;
+    sp.rho_s_out[g] = next;
     int p = -1;
     if (sp.block == TDG_BLOCK_ALL)
       p = t;
@@ -1179,11 +1212,16 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   const size_t state_bytes = (size_t)(batched ? xstride : batch) * nk * nb2 * sizeof(double2);
   const int64_t zstride = channel ? (int64_t)npair * ch_ls : (op->rank + 1) & ~int64_t(1);
   void *rho_n, *rho_s, *acc, *x0, *x1, *z = nullptr, *part, *dperm, *dfields, *dintra = nullptr;
-  // intraband term: e.(rho_s)_{;k} of each stage, computed before the stage kernel
+  // intraband term: e.(rho_s)_{;k} of each stage.  Batched path: computed by
+  // its own launch before the stage kernel.  Per-instance path: formed in the
+  // stage kernel's epilogue from the neighbours' states, read from one
+  // stage-state buffer while the next stage state goes to the other.
   const bool intra = model->links != nullptr;
   if (intra && (int64_t)nk * nb2 * batch > ((int64_t)1 << 38))
     return fail(ctx, TDG_E_UNSUPPORTED, "intraband term: nk * nb^2 * batch too large for one launch");
-  if (intra) TDG_TRY(ws_reserve(ctx, WS_INTRA, state_bytes, &dintra));
+  void* rho_s2 = nullptr;
+  if (intra && batched) TDG_TRY(ws_reserve(ctx, WS_INTRA, state_bytes, &dintra));
+  if (intra && !batched) TDG_TRY(ws_reserve(ctx, WS_RHO_S2, state_bytes, &rho_s2));
   TDG_TRY(ws_reserve(ctx, WS_RHO_N, state_bytes, &rho_n));
   TDG_TRY(ws_reserve(ctx, WS_RHO_S, state_bytes, &rho_s));
   TDG_TRY(ws_reserve(ctx, WS_ACC, state_bytes, &acc));
@@ -1271,6 +1309,14 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   sp.dt = dt;
   sp.tr_signed = intra;
   sp.ftab = (const double*)ftab;
+  sp.rho_s_out = intra && !batched ? (double2*)rho_s2 : (double2*)rho_s;
+  if (intra && !batched) {
+    sp.links = (const double2*)model->links;
+    sp.nk1 = model->nk1;
+    sp.nk2 = model->nk2;
+    sp.cov_c1 = model->nk1 * model->a_bohr / (4.0 * M_PI);  // 1 / (2 |b_1|)
+    sp.cov_c2 = model->nk2 * model->a_bohr / (4.0 * M_PI);
+  }
   const int64_t split_stride = (int64_t)batch * zstride;
   sp.zsplit_stride = split_stride;
   // projection rows: the rank (low rank) or every off-diagonal channel's rows (channel-wise)
@@ -1780,17 +1826,13 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
       sp.step = (int)step;
       sp.stage = s;
       sp.obs_slot = slot;
-      sp.intra = (intra && n_dyn > 0) ? (const double2*)dintra : nullptr;
-      if (sp.intra) {
-        hipEvent_t ia, ib;
-        prof_pair(ctx, TDG_KCLASS_INTRA, &ia, &ib);
-        covariant_derivative(ctx->stream, model, rho_s, (int64_t)nk * nb2, nb2, 1, (const tdg_field*)dfields, n_dyn,
-                             dintra, ia, ib);
-      }
       hipEvent_t sa, sb;
       prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
       stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
       std::swap(xc, xn);
+      // with links the next stage reads the buffer this one wrote (four
+      // stages per step: every step starts from the first buffer)
+      if (sp.links) std::swap(sp.rho_s, sp.rho_s_out);
     }
     ++slot;
     if (slot == chunk || step == max_steps) {
