@@ -30,6 +30,10 @@
 #include "covariant.h"
 #include "internal.h"
 
+// operand types of the direct-to-LDS load builtin: a global source, an LDS destination
+typedef __attribute__((address_space(1))) void lds_dma_src;
+typedef __attribute__((address_space(3))) void lds_dma_dst;
+
 namespace {
 
 constexpr int THREADS = 256;  // dense stage kernel and auxiliary kernels
@@ -331,7 +335,9 @@ stage_kernel(StageParams sp) {
   __shared__ double s_y[2 * NB2_MAX + 2 * ROWS];
   __shared__ double s_red[WAVES * 2 * ROWS];
   __shared__ double s_obs[5][NB2_MAX];
-  __shared__ double2 s_cov[8][NB2_MAX];  // per axis: y(k + b), y(k - b), L(k), L(k - b)
+  // intraband term: entry (4 a + w) nb^2 + e holds element e of, for axis a,
+  // w = 0: y(k + b_a), 1: y(k - b_a), 2: L_a(k), 3: L_a(k - b_a)
+  __shared__ __align__(16) double2 s_cov[8 * NB2_MAX];
 
   // ---- loads: the low-rank kernel issues every load of the block before any
   // use (its lifetime is latency-bound); the dense kernel loads the per-k
@@ -368,6 +374,27 @@ stage_kernel(StageParams sp) {
     fey = (&sp.fields[b].ey)[vzero];
     if (dyn) ef = sp.ftab[((size_t)sp.obs_slot * sp.batch + b) * 4 + sp.stage + vzero];
   };
+  // intraband term: the first wave copies the neighbours' state elements and
+  // the links into LDS with direct-to-LDS loads issued now (lane l of a copy
+  // writes entry base + l); nothing is held in registers, and the epilogue
+  // waits for them before reading.  The states are read from rho_s while this
+  // kernel writes the next stage state to the other buffer.
+  if (sp.links && dyn && t < 64) {
+    const int count = 8 * nb2;
+    for (int base = 0; base < count; base += 64) {
+      const int i = base + t;
+      if (i < count) {
+        const int q = i / nb2, e = i - q * nb2, a = q >> 2, w = q & 3;
+        int kf, kr;
+        tdg::covariant_neighbours(k, a, sp.nk1, sp.nk2, kf, kr);
+        const double2* src = w == 0   ? sp.rho_s + ((size_t)b * sp.nk + kf) * nb2 + e
+                             : w == 1 ? sp.rho_s + ((size_t)b * sp.nk + kr) * nb2 + e
+                             : w == 2 ? sp.links + ((size_t)a * sp.nk + k) * nb2 + e
+                                      : sp.links + ((size_t)a * sp.nk + kr) * nb2 + e;
+        __builtin_amdgcn_global_load_lds((lds_dma_src*)src, (lds_dma_dst*)(s_cov + base), 16, 0, 0);
+      }
+    }
+  }
   if (LOWRANK) {
     load_state();
     load_field();
@@ -452,22 +479,9 @@ stage_kernel(StageParams sp) {
   }
   // the per-k epilogue runs in the first wave (nb^2 <= 64 elements, P <= 64 pairs)
   if (t >= 64) return;
-  if (sp.links && dyn && t < nb2) {
-    // intraband term: this lane's element of the neighbour states and links
-    // straight into LDS (read from rho_s while this kernel writes the next
-    // stage state to the other buffer); loaded here, not with the state, so
-    // that no variant holds them in registers across the contraction
-    const size_t sb = (size_t)b * sp.nk;
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      int kf, kr;
-      tdg::covariant_neighbours(k, a, sp.nk1, sp.nk2, kf, kr);
-      s_cov[4 * a][t] = sp.rho_s[(sb + kf) * nb2 + t];
-      s_cov[4 * a + 1][t] = sp.rho_s[(sb + kr) * nb2 + t];
-      s_cov[4 * a + 2][t] = sp.links[((size_t)a * sp.nk + k) * nb2 + t];
-      s_cov[4 * a + 3][t] = sp.links[((size_t)a * sp.nk + kr) * nb2 + t];
-    }
-  }
+  // the direct-to-LDS copies of the intraband neighbours have landed once
+  // this wave's vector memory counter is zero
+  if (sp.links && dyn) __builtin_amdgcn_s_waitcnt(0x0F70);
   if (t < nb2) s_rho[t] = r_s;
   wave_sync();
   if (sp.stage == 0 && sp.obs_part)
@@ -518,7 +532,7 @@ stage_kernel(StageParams sp) {
       for (int a = 0; a < 2; ++a) {
         const double ea = a == 0 ? fex : fey;
         if (ea == 0.0) continue;
-        const double2 *yf = s_cov[4 * a], *yr = s_cov[4 * a + 1], *lf = s_cov[4 * a + 2], *lr = s_cov[4 * a + 3];
+        const double2 *yf = s_cov + (4 * a) * nb2, *yr = yf + nb2, *lf = yr + nb2, *lr = lf + nb2;
         const double2 tt = tdg::covariant_axis_element(
             n, m, nb, sp.nv, [&](int r, int q) { return yf[r * nb + q]; }, [&](int r, int q) { return yr[r * nb + q]; },
             [&](int r, int q) { return lf[r * nb + q]; }, [&](int r, int q) { return lr[r * nb + q]; });
