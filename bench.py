@@ -339,9 +339,9 @@ def main():
         cpu = cpu_baseline(cfg, frac, args.cpu_seconds)
 
     line = {
-        "metric": "instance*RK4-steps/s, low-rank vs dense K, at fixed error vs FP64 oracle",
+        "metric": "instance·RK4 steps/sec, low-rank vs dense K, at fixed error vs FP64 oracle",
         "value": value,
-        "unit": "instance*RK4-steps/s",
+        "unit": "instance·RK4 steps/sec",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -592,7 +592,7 @@ def cpu_baseline(cfg, frac, seconds):
     O.propagate(model, op, "eh", cfg.fields, cfg.dt, nsteps=nsamp)
     secs = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    return {"value": nsamp / secs, "unit": "instance*RK4-steps/s", "cores": int(threads), "kind": "oracle",
+    return {"value": nsamp / secs, "unit": "instance·RK4 steps/sec", "cores": int(threads), "kind": "oracle",
             "sample": f"first {nsamp} of {int(cfg.fields.nsteps[0])} RK4 steps of the same workload, FP64 numpy "
                       f"oracle, low-rank operator at rank {fac['r']} (kernel build and SVD untimed)"}
 
