@@ -165,6 +165,41 @@ def test_tb4_intraband_per_instance_path(P, ctx, tb4_6, k_tb4_6, kind, dtype, to
     _compare(res, refs, tol, 1e-10 if dtype == "c128" else 1e-5)
 
 
+@pytest.mark.parametrize("model_kind", ["tb4", "multiband8"])
+def test_intraband_per_instance_uneven_lengths(P, ctx, model_kind):
+    """Per-instance path (FP64) with the intraband term and instances of
+    uneven length, one of zero steps: each stage reads the neighbours from
+    one stage-state buffer and writes the other, and a finished instance is
+    observed from the buffer its last step wrote.  The 8-band model stages
+    8 nb^2 = 512 neighbour entries per k (eight 64-lane copies)."""
+    from paper_2502_05635_amd import _abi as abi
+    m = tb4_model(6, A, 0.5) if model_kind == "tb4" else multiband_model(6, nb=8, nv=4)
+    dm = _with_links(P, ctx, m)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c128")
+    ko = O.build_kernel(m, R0_STABLE, "eh")
+    if model_kind == "tb4":
+        op = ctx.kernel_compress(kg, "fraction", 0.3)
+        oop = O.LowRankOp.from_factors(O.compress(ko, "fraction", 0.3))
+    else:
+        op, oop = kg, O.DenseOp(ko)
+    tabs = []
+    for i, ns in enumerate((0, 37, 121, 160)):
+        t = max(ns, 1) * DT
+        tabs.append(FieldTable.single(3e-3, 1.4 / HARTREE_EV, max(t / 10.0, 0.5 * FS_AU), t / 2.0, ns,
+                                      ex=np.cos(0.9 * i), ey=np.sin(0.9 * i)))
+    fields = FieldTable.stack(tabs)
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 1 << 20)
+    try:
+        _log(f"{model_kind} intraband per-instance FP64, lengths 0/37/121/160")
+        res = ctx.propagate(op, dm, "eh", fields, DT)
+    finally:
+        ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 4)
+    assert not ctx.last_variant().startswith("batched")
+    links = O.transport_links(m)
+    refs = [O.propagate(m, oop, "eh", fields, DT, instance=b, links=links) for b in range(4)]
+    _compare(res, refs, 1e-10, 1e-10)
+
+
 @pytest.mark.parametrize("kind", ["dense", "lowrank", "lowrank_bf16x2"])
 def test_tb4_intraband_batched_path(P, ctx, tb4_6, k_tb4_6, kind):
     """Uneven batch through the matrix-core path with the intraband term."""
