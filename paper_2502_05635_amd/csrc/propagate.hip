@@ -33,6 +33,9 @@
 // operand types of the direct-to-LDS load builtin: a global source, an LDS destination
 typedef __attribute__((address_space(1))) void lds_dma_src;
 typedef __attribute__((address_space(3))) void lds_dma_dst;
+// s_waitcnt immediate for vmcnt(0) alone (gfx9 encoding: vmcnt in bits 3:0 and
+// 15:14 = 0, expcnt in 6:4 and lgkmcnt in 11:8 at their maxima, i.e. no wait)
+constexpr int WAIT_VMCNT0 = 0x0F70;
 
 namespace {
 
@@ -375,14 +378,14 @@ stage_kernel(StageParams sp) {
     if (dyn) ef = sp.ftab[((size_t)sp.obs_slot * sp.batch + b) * 4 + sp.stage + vzero];
   };
   // intraband term: the first wave copies the neighbours' state elements and
-  // the links into LDS with direct-to-LDS loads issued now (lane l of a copy
-  // writes entry base + l); nothing is held in registers, and the epilogue
-  // waits for them before reading.  The states are read from rho_s while this
-  // kernel writes the next stage state to the other buffer.
+  // the links into LDS with direct-to-LDS loads issued now (lane l of the copy
+  // starting at entry c0 writes entry c0 + l); nothing is held in registers,
+  // and the epilogue waits for them before reading.  The states are read from
+  // rho_s while this kernel writes the next stage state to the other buffer.
   if (sp.links && dyn && t < 64) {
     const int count = 8 * nb2;
-    for (int base = 0; base < count; base += 64) {
-      const int i = base + t;
+    for (int c0 = 0; c0 < count; c0 += 64) {
+      const int i = c0 + t;
       if (i < count) {
         const int q = i / nb2, e = i - q * nb2, a = q >> 2, w = q & 3;
         int kf, kr;
@@ -391,7 +394,7 @@ stage_kernel(StageParams sp) {
                              : w == 1 ? sp.rho_s + ((size_t)b * sp.nk + kr) * nb2 + e
                              : w == 2 ? sp.links + ((size_t)a * sp.nk + k) * nb2 + e
                                       : sp.links + ((size_t)a * sp.nk + kr) * nb2 + e;
-        __builtin_amdgcn_global_load_lds((lds_dma_src*)src, (lds_dma_dst*)(s_cov + base), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((lds_dma_src*)src, (lds_dma_dst*)(s_cov + c0), 16, 0, 0);
       }
     }
   }
@@ -481,7 +484,7 @@ stage_kernel(StageParams sp) {
   if (t >= 64) return;
   // the direct-to-LDS copies of the intraband neighbours have landed once
   // this wave's vector memory counter is zero
-  if (sp.links && dyn) __builtin_amdgcn_s_waitcnt(0x0F70);
+  if (sp.links && dyn) __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
   if (t < nb2) s_rho[t] = r_s;
   wave_sync();
   if (sp.stage == 0 && sp.obs_part)
