@@ -65,6 +65,23 @@ def test_ctypes_layouts_match_c(tmp_path, tdg):
             assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, f"{cname}.{fname}"
 
 
+def test_constants_match_header():
+    """Every integer TDG_* constant the binding defines equals the header's,
+    and every option and kernel-class constant of the header is bound."""
+    import re
+
+    from paper_2502_05635_amd import _abi as abi
+    text = open(os.path.join(ROOT, "include", "tdagw.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(TDG_\w+)\s+\(?(-?\d+)\)?", text)}
+    assert defs, "no integer constants found in the header"
+    for name, value in defs.items():
+        if hasattr(abi, name):
+            assert getattr(abi, name) == value, name
+    for name in defs:
+        if name.startswith(("TDG_OPT_", "TDG_KCLASS_")):
+            assert hasattr(abi, name), f"{name} is not in the binding"
+
+
 def test_host_validation_without_device(tdg):
     from paper_2502_05635_amd import _abi as abi
     L = tdg.lib()
