@@ -146,7 +146,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(instances or k-blocks would shard across GPUs; see the design notes).", file=sys.stderr)
+              "(field instances, or blocks of k rows, would shard across GPUs).", file=sys.stderr)
         sys.exit(2)
     if args.sweep_only:
         import paper_2502_05635_amd as P

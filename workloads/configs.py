@@ -1,6 +1,6 @@
 """The five synthetic workloads, with every unstated physical constant fixed.
 
-Readings of what the paper leaves open (each is listed in the design notes):
+Readings of what the paper leaves open:
   * lattice constant a = 6 bohr (MoS2-like, the paper's testbed material);
   * screening length r0 = 5 nm = 94.486 bohr for all parity and timing runs:
     with r0 = 5 bohr the two-band model's ground state is unstable (negative
