@@ -38,6 +38,8 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000, help="timed RK4 steps per path")
+    ap.add_argument("--repeats", type=int, default=4,
+                    help="further timed runs of the dense and low-rank paths (median reported beside value)")
     ap.add_argument("--warmup", type=int, default=400, help="untimed RK4 steps per path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
@@ -210,8 +212,10 @@ def main():
         progress(f"{name} operator, {args.steps} steps")
         res, secs, _ = timed(op, args.steps, args.warmup, False)
         variant = ctx.last_variant()
+        # further runs of the same K steps, for the spread between runs
+        again = [timed(op, args.steps, args.warmup, False)[1] for _ in range(args.repeats)]
         _, _, prof = timed(op, args.steps, args.warmup, True)
-        out[name] = {"secs": secs, "res": res, "prof": prof, "variant": variant}
+        out[name] = {"secs": secs, "res": res, "prof": prof, "variant": variant, "runs": [secs] + again}
 
     # channel-wise compression (Eq. svd-channel-wise) at its own fixed-error fraction
     chan_golden = json.load(open(CHAN_JSON)) if os.path.exists(CHAN_JSON) else None
@@ -363,6 +367,9 @@ def main():
                   "stage_kernel_GBps": dense_bytes / dense_avg_s / 1e9,
                   "stage_kernel_hbm_frac": dense_bytes / dense_avg_s / 1e9 / HBM_PEAK_GBS},
         "speedup_lowrank_vs_dense": value / dense_value,
+        "runs": {name: {"steps_per_s": [args.steps / t for t in out[name]["runs"]],
+                        "median_steps_per_s": float(np.median([args.steps / t for t in out[name]["runs"]]))}
+                 for name in ("lowrank", "dense")},
         "channelwise": channelwise,
         "intraband": intraband,
         "errors_vs_fp64_oracle": errs or None,
