@@ -20,6 +20,7 @@ PROPAGATE = importlib.import_module("oracle.propagate")
 BSE = importlib.import_module("oracle.bse")
 ADJOINT = importlib.import_module("oracle.adjoint")
 INTRABAND = importlib.import_module("oracle.intraband")
+COMPRESS = importlib.import_module("oracle.compress")
 
 
 @pytest.fixture(scope="module")
@@ -104,7 +105,45 @@ def _backward_link_not_daggered(model, links, y, ex, ey):
     return out
 
 
+def _vh_unconjugated(self, x):
+    return self.kdiag * x + self.us @ (self.vh.conj() @ x)
+
+
+def _diagonal_left_in(k):
+    return np.diag(k).copy(), k.copy()
+
+
+def _eigh_route_without_signs(koff, method="svd"):
+    if method == "svd":
+        return COMPRESS._real_svd_offdiag(koff, method)
+    lam, q = np.linalg.eigh(koff)
+    order = np.argsort(-np.abs(lam), kind="stable")
+    q = q[:, order]
+    return q, np.abs(lam[order]), q.conj().T
+
+
+def _fraction_off_by_one(s, rule, value, koff_fro2=None, koff_mean_dev2=None):
+    r = COMPRESS._real_choose_rank(s, rule, value, koff_fro2, koff_mean_dev2)
+    return r + 1 if rule == "fraction" else r
+
+
+def _randomized_vh_unconjugated(k, rank, omega, power_iters=2):
+    f = COMPRESS._real_randomized_compress(k, rank, omega, power_iters)
+    f["Vh"] = f["Vh"].conj()
+    return f
+
+
+def _randomized_ritz_signs_dropped(k, rank, omega, power_iters=2):
+    f = COMPRESS._real_randomized_compress(k, rank, omega, power_iters)
+    u = f["Vh"].conj().T
+    f["US"] = u * f["s"][None, :f["r"]]
+    return f
+
+
 INTRABAND._real_neighbour = INTRABAND._neighbour
+COMPRESS._real_svd_offdiag = COMPRESS.svd_offdiag
+COMPRESS._real_choose_rank = COMPRESS.choose_rank
+COMPRESS._real_randomized_compress = COMPRESS.randomized_compress
 INTRABAND._real_covariant_derivative = INTRABAND.covariant_derivative
 ADJOINT._real_pull_commutator = ADJOINT.pull_commutator
 ADJOINT._real_field_param_derivs = ADJOINT.field_param_derivs
@@ -143,6 +182,16 @@ CASES = {
                                 "intra_fft"),
     "intraband: raw overlap instead of its polar factor": (INTRABAND, "polar_unitary", lambda b: b.copy(),
                                                            "intra_charge"),
+    "low rank: V^H applied unconjugated": (PROPAGATE.LowRankOp, "apply", _vh_unconjugated, "lowrank_full_rank"),
+    "compression: diagonal left in K_off": (COMPRESS, "split_diag", _diagonal_left_in, "eckart_young"),
+    "compression: eigenvector route drops the eigenvalue signs": (COMPRESS, "svd_offdiag",
+                                                                  _eigh_route_without_signs, "eckart_young"),
+    "compression: fraction rule keeps one value too many": (COMPRESS, "choose_rank", _fraction_off_by_one,
+                                                             "rank_rules"),
+    "randomized: V^H unconjugated": (COMPRESS, "randomized_compress", _randomized_vh_unconjugated,
+                                     "randomized_full_width"),
+    "randomized: Ritz value signs dropped": (COMPRESS, "randomized_compress", _randomized_ritz_signs_dropped,
+                                             "randomized_full_width"),
     "intraband: polar factor conjugate-transposed": (INTRABAND, "polar_unitary",
                                                      lambda b: np.linalg.svd(b)[2].conj().T
                                                      @ np.linalg.svd(b)[0].conj().T, "intra_rotated"),
@@ -161,6 +210,16 @@ def _run_pin(name, small):
         pins.test_kernel_row_sum_is_brillouin_zone_integral()
     elif name == "circulant":
         pins.test_flat_band_kernel_is_circulant()
+    elif name in ("lowrank_full_rank", "eckart_young", "rank_rules", "randomized_full_width"):
+        k = O.build_kernel(t4, R0_STABLE, "eh")
+        if name == "lowrank_full_rank":
+            pins.test_lowrank_full_rank_equals_dense(t4, k)
+        elif name == "eckart_young":
+            pins.test_svd_eckart_young(k)
+        elif name == "rank_rules":
+            pins.test_rank_rules(k)
+        else:
+            pins.test_randomized_full_width_is_exact(k)
     elif name == "channel_full_rank":
         pins.test_channelwise_full_rank_equals_dense(t4, O.build_kernel(t4, R0_STABLE, "eh"))
     elif name.startswith("intra_"):
@@ -188,8 +247,9 @@ def _run_pin(name, small):
 def test_planted_mistake_is_caught(case, small, monkeypatch):
     target, attr, repl, pin = CASES[case]
     _run_pin(pin, small)                       # passes on the real oracle
+    orig = getattr(target, attr)
     monkeypatch.setattr(target, attr, repl)
-    if target is KERNEL and attr == "build_kernel":
-        monkeypatch.setattr(O, "build_kernel", repl)
+    if getattr(O, attr, None) is orig:
+        monkeypatch.setattr(O, attr, repl)     # the package's re-export of the same function
     with pytest.raises(AssertionError):
         _run_pin(pin, small)
