@@ -140,6 +140,18 @@ def _randomized_ritz_signs_dropped(k, rank, omega, power_iters=2):
     return f
 
 
+def _one_band_too_many_filled(model):
+    occ = np.zeros(model.nb)
+    occ[: model.nv + 1] = 1.0
+    return np.broadcast_to(np.diag(occ).astype(np.complex128), (model.nk, model.nb, model.nb)).copy()
+
+
+def _current_not_averaged(model, rho, ex, ey, grid_trace=False):
+    o = OBSERVABLES.observables(model, rho, ex, ey, grid_trace)
+    o["J"] *= model.nk
+    return o
+
+
 INTRABAND._real_neighbour = INTRABAND._neighbour
 COMPRESS._real_svd_offdiag = COMPRESS.svd_offdiag
 COMPRESS._real_choose_rank = COMPRESS.choose_rank
@@ -182,6 +194,9 @@ CASES = {
                                 "intra_fft"),
     "intraband: raw overlap instead of its polar factor": (INTRABAND, "polar_unitary", lambda b: b.copy(),
                                                            "intra_charge"),
+    "equilibrium: one band too many filled": (PROPAGATE, "rho_equilibrium", _one_band_too_many_filled,
+                                               "two_level"),
+    "current not averaged over the k grid": (PROPAGATE, "observables", _current_not_averaged, "two_level"),
     "low rank: V^H applied unconjugated": (PROPAGATE.LowRankOp, "apply", _vh_unconjugated, "lowrank_full_rank"),
     "compression: diagonal left in K_off": (COMPRESS, "split_diag", _diagonal_left_in, "eckart_young"),
     "compression: eigenvector route drops the eigenvalue signs": (COMPRESS, "svd_offdiag",
