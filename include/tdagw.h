@@ -22,8 +22,12 @@
  *     comment says "host".  The library never frees caller memory; it owns
  *     only the workspace inside a context.
  *   - Calls enqueue work on the context's stream and return; results are
- *     valid after that stream is synchronised.  tdg_kernel_compress and
- *     tdg_check_numeric synchronise the stream themselves.
+ *     valid after that stream is synchronised.  Host arrays passed in (field
+ *     records) are copied when the call is queued and may be freed on return.
+ *     Calls that wait for the stream: the three compressions,
+ *     tdg_links_build, tdg_propagate_adjoint, tdg_check_numeric and
+ *     tdg_profile_read; tdg_propagate only while it tunes a new shape (its
+ *     first call for that shape) and when it checks a caller's rho(0).
  *   - Every call returns TDG_OK (0) or a negative TDG_E_* code and never
  *     aborts or throws; tdg_last_error() describes the last failure.
  *     Arguments are validated on the host before any device work is queued.
@@ -71,7 +75,10 @@ int tdg_version(void);
 int tdg_create(tdg_ctx* out, int device, void* hip_stream);
 /* Release the context and its workspace (waits for its stream first). */
 int tdg_destroy(tdg_ctx ctx);
-/* Rebind the context to another stream of the same device. */
+/* Rebind the context to another stream of the same device.  Work queued on
+ * the new stream after this call waits (through an event) for the work the
+ * context queued on the old one, which may still be using the context's
+ * workspace. */
 int tdg_set_stream(tdg_ctx ctx, void* hip_stream);
 /* Message describing the last failed call on ctx ("" if none); owned by ctx,
  * valid until the next call on ctx.  ctx may be NULL for tdg_create failures. */
@@ -295,7 +302,11 @@ typedef struct {
  * t_n, t_n + dt/2 twice, t_n + dt; t_n = n dt), each for its own nsteps.
  * rho: device c128 [batch][nk][nb][nb], row n column m; on entry rho(0)
  * (ignored and replaced by rho_eq when init_eq != 0), on exit rho(T_b).
- * Every step of the path runs on the device; nothing is copied back. */
+ * Every step of the path runs on the device; nothing is copied back.
+ * With init_eq == 0, rho(0) is checked on the device first: if any
+ * |rho_nm - conj rho_mn| exceeds 1e-12 (or is NaN) the call fails with
+ * TDG_E_INVAL before anything is integrated; this check waits for its
+ * one-number result. */
 int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
                   const tdg_field* fields, int32_t batch, double dt, void* rho,
                   int32_t init_eq, const tdg_obs* obs);

@@ -155,6 +155,12 @@ class Context:
         self._check(self._lib.tdg_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)), None)
         self.h = h
 
+    def set_stream(self, stream: torch.cuda.Stream) -> None:
+        """Queue later calls on `stream`; it first waits for the work already
+        queued on the previous one (tdg_set_stream)."""
+        self._check(self._lib.tdg_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
     def close(self):
         if getattr(self, "h", None):
             self._lib.tdg_destroy(self.h)

@@ -495,8 +495,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   double* part = (double*)(wb + o_part);
   double* dfacc = (double*)(wb + o_df);
   tdg_field* dfields = (tdg_field*)(wb + o_f);
-  TDG_TRY(hip_check(ctx, hipMemcpyAsync(dfields, fields, sizeof(tdg_field) * batch, hipMemcpyHostToDevice, ctx->stream),
-                    "field upload"));
+  TDG_TRY(args_upload(ctx, dfields, fields, sizeof(tdg_field) * batch));
 
   AdjArgs a;
   a.nk = nk;

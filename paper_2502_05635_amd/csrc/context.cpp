@@ -147,13 +147,23 @@ int tdg_destroy(tdg_ctx ctx) {
       hipEventDestroy(p.b);
     }
   release_blas(ctx);
+  if (ctx->order_ev) hipEventDestroy(ctx->order_ev);
   delete ctx;
   return TDG_OK;
 }
 
 int tdg_set_stream(tdg_ctx ctx, void* hip_stream) {
   if (!ctx) return TDG_E_INVAL;
-  ctx->stream = (hipStream_t)hip_stream;
+  const hipStream_t next = (hipStream_t)hip_stream;
+  if (next == ctx->stream) return TDG_OK;
+  // work queued on the old stream still reads and writes the context's
+  // workspace: the new stream waits for it before anything queued after
+  TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
+  if (!ctx->order_ev)
+    TDG_TRY(hip_check(ctx, hipEventCreateWithFlags(&ctx->order_ev, hipEventDisableTiming), "stream order event"));
+  TDG_TRY(hip_check(ctx, hipEventRecord(ctx->order_ev, ctx->stream), "stream order record"));
+  TDG_TRY(hip_check(ctx, hipStreamWaitEvent(next, ctx->order_ev, 0), "stream order wait"));
+  ctx->stream = next;
   return TDG_OK;
 }
 

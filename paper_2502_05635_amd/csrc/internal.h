@@ -76,6 +76,7 @@ struct tdg_ctx_s {
   bool graphs = false;   // batched path: replay captured RK4 steps (TDG_OPT_GRAPHS)
   int gemm_slices = 0;   // batched products: 0 = tuned split-K, else this many K slices (TDG_OPT_GEMM_SLICES)
   int adj_stash = 1;     // adjoint: keep a segment's stage data when it fits (TDG_OPT_ADJOINT_STASH)
+  hipEvent_t order_ev = nullptr;  // tdg_set_stream: orders the new stream after the old one's queued work
   std::vector<std::pair<std::string, int>> tuned;  // shape key -> variant index
   std::string last_variant;
 };
@@ -127,6 +128,10 @@ void covariant_derivative(hipStream_t stream, const tdg_model* model, const void
 // out = sum of `slices` complex64 arrays of `count` elements, `stride` apart
 // (count, stride even; in and out 16-byte aligned).
 void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stride, int64_t count, void* out);
+// Copy `bytes` (a multiple of 4) of host memory to device memory `dev`
+// (4-byte aligned) inside the arguments of kernels queued on the context
+// stream: the call does not wait, and the host array need not outlive it.
+int args_upload(tdg_ctx ctx, void* dev, const void* host, size_t bytes);
 
 }  // namespace tdg
 

@@ -5,9 +5,10 @@
 //
 // W is the 2D Rytova-Keldysh interaction 2pi / (q (1 + r0 q)); the divergent
 // q = 0 term is replaced by its average over the grid cell (paper Appendix B).
-// On a uniform grid q depends only on the index difference, so the host
-// tabulates W (with the -1/(nk a^2) prefactor) once per difference and the
-// device kernel combines it with band overlaps.
+// On a uniform grid q depends only on the index difference, so W (with the
+// -1/(nk a^2) prefactor) is tabulated once per difference on the device (the
+// q = 0 cell average, a single number, comes from the host) and the build
+// kernel combines it with band overlaps.
 #include <cmath>
 #include <vector>
 
@@ -111,6 +112,21 @@ __device__ inline void pair_bands(int block, int nb, int nv, int p, int& a, int&
   }
 }
 
+// wt[d1 nk2 + d2] = scale W(q) for the index difference (d1, d2), folded into
+// [-N/2, N/2) per direction; w0 replaces W at q = 0.
+__global__ void __launch_bounds__(256) wtable_kernel(double* __restrict__ wt, int nk1, int nk2, double a, double r0,
+                                                     double w0, double scale) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nk1 * nk2) return;
+  const int d1 = i / nk2, d2 = i % nk2;
+  const int m1 = (2 * d1 < nk1) ? d1 : d1 - nk1;
+  const int m2 = (2 * d2 < nk2) ? d2 : d2 - nk2;
+  const double qx = 2.0 * M_PI / (nk1 * a) * m1, qy = 2.0 * M_PI / (nk2 * a) * m2;
+  const double q = sqrt(qx * qx + qy * qy);
+  const double w = (m1 == 0 && m2 == 0) ? w0 : 2.0 * M_PI / (q * (1.0 + r0 * q));
+  wt[i] = scale * w;
+}
+
 // One thread per (k, k') block of P x P kernel elements; k' runs along x so
 // neighbouring threads write neighbouring column blocks of the same rows.
 template <typename T>
@@ -171,25 +187,14 @@ extern "C" int tdg_kernel_build(tdg_ctx ctx, const tdg_model* model, const tdg_c
   if (nquad > 4096) return fail(ctx, TDG_E_INVAL, "nquad = %d too large", nquad);
   TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
 
-  // W table by index difference, folded into [-N/2, N/2) per direction, with
-  // the -1/(nk a^2) prefactor folded in.
+  // W table by index difference, with the -1/(nk a^2) prefactor folded in
   const double a = model->a_bohr;
-  std::vector<double> wt((size_t)nk);
-  const double scale = -1.0 / ((double)nk * a * a);
-  for (int d1 = 0; d1 < model->nk1; ++d1)
-    for (int d2 = 0; d2 < model->nk2; ++d2) {
-      int m1 = (2 * d1 < model->nk1) ? d1 : d1 - model->nk1;
-      int m2 = (2 * d2 < model->nk2) ? d2 : d2 - model->nk2;
-      double qx = 2.0 * M_PI / (model->nk1 * a) * m1, qy = 2.0 * M_PI / (model->nk2 * a) * m2;
-      double q = std::sqrt(qx * qx + qy * qy);
-      double w = (m1 == 0 && m2 == 0) ? cell_average_w0(M_PI / (model->nk1 * a), coul->r0_bohr, nquad)
-                                      : 2.0 * M_PI / (q * (1.0 + coul->r0_bohr * q));
-      wt[(size_t)d1 * model->nk2 + d2] = scale * w;
-    }
   void* wdev = nullptr;
-  TDG_TRY(ws_reserve(ctx, WS_WTAB, wt.size() * sizeof(double), &wdev));
-  TDG_TRY(hip_check(ctx, hipMemcpyAsync(wdev, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
-                    "W table upload"));
+  TDG_TRY(ws_reserve(ctx, WS_WTAB, (size_t)nk * sizeof(double), &wdev));
+  hipLaunchKernelGGL(wtable_kernel, dim3((nk + 255) / 256), dim3(256), 0, ctx->stream, (double*)wdev, model->nk1,
+                     model->nk2, a, coul->r0_bohr, cell_average_w0(M_PI / (model->nk1 * a), coul->r0_bohr, nquad),
+                     -1.0 / ((double)nk * a * a));
+  TDG_TRY(launch_check(ctx, "W table launch"));
   dim3 grid((nk + 255) / 256, nk);
   if (dtype == TDG_BF16X2) {
     // build in complex64, then split into the hi / lo planes
@@ -201,8 +206,7 @@ extern "C" int tdg_kernel_build(tdg_ctx ctx, const tdg_model* model, const tdg_c
     TDG_TRY(launch_check(ctx, "build_kernel launch"));
     if (n > 65535) return fail(ctx, TDG_E_UNSUPPORTED, "N exceeds the conversion grid");
     split_bf16x2(ctx->stream, tmp, 0, n, n, n, K, ld);
-    TDG_TRY(launch_check(ctx, "bf16 split launch"));
-    return hip_check(ctx, hipStreamSynchronize(ctx->stream), "kernel build sync");
+    return launch_check(ctx, "bf16 split launch");
   }
   if (dtype == TDG_C128)
     hipLaunchKernelGGL(build_kernel_k<double>, grid, dim3(256), 0, ctx->stream, (const double*)wdev,
@@ -212,7 +216,5 @@ extern "C" int tdg_kernel_build(tdg_ctx ctx, const tdg_model* model, const tdg_c
     hipLaunchKernelGGL(build_kernel_k<float>, grid, dim3(256), 0, ctx->stream, (const double*)wdev,
                        (const double2*)model->evec, model->nk1, model->nk2, model->nb, model->nv, coul->block, npair,
                        (float2*)K, ld);
-  TDG_TRY(launch_check(ctx, "build_kernel launch"));
-  // the host table must outlive the asynchronous upload
-  return hip_check(ctx, hipStreamSynchronize(ctx->stream), "kernel build sync");
+  return launch_check(ctx, "build_kernel launch");
 }

@@ -23,6 +23,7 @@
 #include <functional>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -76,6 +77,17 @@ __global__ void field_table_kernel(const tdg_field* __restrict__ fields, int bat
   const int s = i & 3, b = (i >> 2) % batch, slot = (i >> 2) / batch;
   const double cs = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
   tab[i] = field_value(fields[b], (double)(step0 + slot) * dt + cs * dt);
+}
+
+// Host records copied to the device inside kernel arguments: the launch takes
+// its own copy of the arguments, so nothing waits for the copy and the host
+// array may go away as soon as the launch is queued.
+constexpr int ARG_WORDS = 512;  // 2 KiB of payload per launch
+struct ArgPayload {
+  uint32_t w[ARG_WORDS];
+};
+__global__ void __launch_bounds__(256) arg_copy_kernel(ArgPayload p, uint32_t* __restrict__ dst, int nwords) {
+  for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = p.w[i];
 }
 
 // Barrier for the per-k epilogue, which only the block's first wave runs
@@ -655,6 +667,48 @@ __global__ void finish_kernel(const double2* __restrict__ rho_n, const int* __re
   rho_out[((size_t)perm[b] * nk + k) * nb2 + t] = rho_n[((size_t)b * nk + k) * nb2 + t];
 }
 
+// Hermiticity residual of a caller's rho(0): thread i takes the (instance,
+// k) block i of nb x nb elements; part[blockIdx.x] = the block's largest
+// max_nm |rho_nm - conj rho_mn| (NaN counted as infinite).
+__global__ void __launch_bounds__(256) herm_check_kernel(const double2* __restrict__ rho, int64_t nblk, int nb,
+                                                         double* __restrict__ part) {
+  __shared__ double s[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double h = 0.0;
+  if (i < nblk) {
+    const double2* r = rho + i * nb * nb;
+    for (int n = 0; n < nb; ++n)
+      for (int m = n; m < nb; ++m) {
+        const double2 a = r[n * nb + m], c = r[m * nb + n];
+        const double dx = a.x - c.x, dy = a.y + c.y;
+        double v = sqrt(dx * dx + dy * dy);
+        if (v != v) v = INFINITY;
+        h = fmax(h, v);
+      }
+  }
+  s[threadIdx.x] = h;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// out[0] = max of part[0 .. count)
+__global__ void __launch_bounds__(256) max_reduce_kernel(const double* __restrict__ part, int64_t count, double* out) {
+  __shared__ double s[256];
+  double h = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) h = fmax(h, part[i]);
+  s[threadIdx.x] = h;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
 // ---- batched path: per-k stage after the matrix-core contraction -----------
 struct BatchParams {
   const float2* Y;    // contraction result, [slice][N][ldy] (instance fastest)
@@ -1065,13 +1119,43 @@ static int validate_fields(tdg_ctx ctx, const tdg_field* fields, int batch, int6
   return TDG_OK;
 }
 
-// Copy a host array into a workspace slot (synchronously: the host array
-// need not outlive the call).
-static int upload(tdg_ctx ctx, WsSlot slot, const void* src, size_t bytes, void** dev) {
-  TDG_TRY(ws_reserve(ctx, slot, bytes, dev));
-  TDG_TRY(hip_check(ctx, hipMemcpyAsync(*dev, src, bytes, hipMemcpyHostToDevice, ctx->stream), "upload"));
-  return hip_check(ctx, hipStreamSynchronize(ctx->stream), "upload sync");
+namespace tdg {
+
+int args_upload(tdg_ctx ctx, void* dev, const void* host, size_t bytes) {
+  if ((bytes & 3) || ((uintptr_t)dev & 3)) return fail(ctx, TDG_E_INVAL, "args_upload: unaligned copy");
+  const uint32_t* src = static_cast<const uint32_t*>(host);
+  uint32_t* dst = static_cast<uint32_t*>(dev);
+  const size_t words = bytes / 4;
+  for (size_t w0 = 0; w0 < words; w0 += ARG_WORDS) {
+    const int nw = (int)std::min<size_t>(ARG_WORDS, words - w0);
+    ArgPayload pl;
+    std::memcpy(pl.w, src + w0, (size_t)nw * 4);
+    hipLaunchKernelGGL(arg_copy_kernel, dim3(1), dim3(256), 0, ctx->stream, pl, dst + w0, nw);
+  }
+  return launch_check(ctx, "argument upload");
 }
+
+}  // namespace tdg
+
+// Device workspace of one propagation: the context's grow-only slots, or,
+// when `arena` is set, consecutive 256-byte aligned pieces of a fixed device
+// array of `cap` bytes (nothing is allocated then).
+struct Workspace {
+  tdg_ctx ctx;
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
+  int get(WsSlot slot, size_t bytes, void** out) {
+    if (!arena) return ws_reserve(ctx, slot, bytes, out);
+    const size_t want = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+    if (want > cap - used)
+      return fail(ctx, TDG_E_INVAL, "workspace of %zu bytes exceeds the %zu-byte scratch array (slot %d)", used + want,
+                  cap, (int)slot);
+    *out = arena + used;
+    used += want;
+    return TDG_OK;
+  }
+  size_t left() const { return arena ? cap - used : SIZE_MAX; }
+};
 
 // ---- stage-kernel variants -------------------------------------------------
 // Stage-kernel launch; with events (profiling) the dispatch itself is timed.
@@ -1145,14 +1229,21 @@ static void table(const Variant (&v)[N], const Variant*& out, int& count) {
   count = (int)N;
 }
 
-extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model, const tdg_field* fields,
-                             int32_t batch, double dt, void* rho, int32_t init_eq, const tdg_obs* obs) {
-  if (!ctx) return TDG_E_INVAL;
+// Largest Hermiticity residual accepted in a caller's rho(0).
+constexpr double RHO0_HERM_TOL = 1e-12;
+
+// tdg_propagate on the workspace W.  With a fixed arena (W.arena) every
+// instance takes the per-instance path and the stage-kernel choice comes from
+// the context's tuner cache (or variant 0): no timing, nothing allocated.
+static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model, const tdg_field* fields,
+                          int32_t batch, double dt, void* rho, int32_t init_eq, const tdg_obs* obs, Workspace& W) {
+  const bool fixed = W.arena != nullptr;
   TDG_TRY(validate_model(ctx, model));
   if (!op) return fail(ctx, TDG_E_INVAL, "operator is NULL");
   if (op->dtype != TDG_C128 && op->dtype != TDG_C64 && op->dtype != TDG_BF16X2)
     return fail(ctx, TDG_E_INVAL, "operator dtype %d", op->dtype);
   const bool bf16 = op->dtype == TDG_BF16X2;
+  if (fixed && bf16) return fail(ctx, TDG_E_UNSUPPORTED, "BF16X2 operators run on the batched path only");
   const int npair = pairs_per_k(model, op->block);
   if (npair <= 0) return fail(ctx, TDG_E_INVAL, "unknown block %d", op->block);
   const int nk = model->nk1 * model->nk2;
@@ -1221,7 +1312,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
 
   const int nb2 = model->nb * model->nb;
   // matrix-core path: complex64 operator and enough instances
-  const bool batched = !channel && (bf16 || (op->dtype == TDG_C64 && batch >= ctx->batched_min));
+  const bool batched = !fixed && !channel && (bf16 || (op->dtype == TDG_C64 && batch >= ctx->batched_min));
   if (batched && n > 2147483647 / 2) return fail(ctx, TDG_E_UNSUPPORTED, "batched path: N < 2^30 required");
   // batched rows hold an even number of instances (two per 16-byte load)
   const int64_t xstride = batched ? (((int64_t)batch + 1) & ~int64_t(1)) : ((n + 1) & ~int64_t(1));
@@ -1237,14 +1328,14 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   if (intra && (int64_t)nk * nb2 * batch > ((int64_t)1 << 38))
     return fail(ctx, TDG_E_UNSUPPORTED, "intraband term: nk * nb^2 * batch too large for one launch");
   void* rho_s2 = nullptr;
-  if (intra && batched) TDG_TRY(ws_reserve(ctx, WS_INTRA, state_bytes, &dintra));
-  if (intra && !batched) TDG_TRY(ws_reserve(ctx, WS_RHO_S2, state_bytes, &rho_s2));
-  TDG_TRY(ws_reserve(ctx, WS_RHO_N, state_bytes, &rho_n));
-  TDG_TRY(ws_reserve(ctx, WS_RHO_S, state_bytes, &rho_s));
-  TDG_TRY(ws_reserve(ctx, WS_ACC, state_bytes, &acc));
+  if (intra && batched) TDG_TRY(W.get(WS_INTRA, state_bytes, &dintra));
+  if (intra && !batched) TDG_TRY(W.get(WS_RHO_S2, state_bytes, &rho_s2));
+  TDG_TRY(W.get(WS_RHO_N, state_bytes, &rho_n));
+  TDG_TRY(W.get(WS_RHO_S, state_bytes, &rho_s));
+  TDG_TRY(W.get(WS_ACC, state_bytes, &acc));
   const size_t xbytes = batched ? (size_t)n * xstride * elt : (size_t)batch * xstride * elt;
-  TDG_TRY(ws_reserve(ctx, WS_X0, xbytes, &x0));
-  TDG_TRY(ws_reserve(ctx, WS_X1, xbytes, &x1));
+  TDG_TRY(W.get(WS_X0, xbytes, &x0));
+  TDG_TRY(W.get(WS_X1, xbytes, &x1));
   // low rank: the projection is split over zsplit column slices (at least
   // about 256 blocks per instance, at most ZSPLIT_MAX slices); the stage
   // kernel sums the slices it reads
@@ -1252,34 +1343,60 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   int64_t zslice = n;
   if (channel) {
     zslice = nk;
-    TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)batch * zstride * elt, &z));
+    TDG_TRY(W.get(WS_Z, (size_t)batch * zstride * elt, &z));
   } else if (lowrank && !batched) {
     const int64_t groups = (op->rank + ROWS - 1) / ROWS;
     zsplit = (int)std::min<int64_t>(ZSPLIT_MAX, std::max<int64_t>(1, (256 + groups - 1) / groups));
     zslice = ((n + zsplit - 1) / zsplit + 1) & ~int64_t(1);
     zsplit = (int)((n + zslice - 1) / zslice);
     // room for the tuner's largest split
-    TDG_TRY(ws_reserve(ctx, WS_Z, (size_t)ZSPLIT_MAX * batch * zstride * elt, &z));
+    TDG_TRY(W.get(WS_Z, (size_t)ZSPLIT_MAX * batch * zstride * elt, &z));
   }
   // a split of the projection's columns into `want` slices (at most ZSPLIT_MAX)
   auto set_split = [&](int want) {
     zslice = ((n + want - 1) / want + 1) & ~int64_t(1);
     zsplit = (int)((n + zslice - 1) / zslice);
   };
+  // field records, sorted order, and the sorted position -> caller's index map
+  TDG_TRY(W.get(WS_FIELDS, sizeof(tdg_field) * batch, &dfields));
+  TDG_TRY(W.get(WS_PERM, sizeof(int) * batch, &dperm));
+  void* dmisc = nullptr;
+  TDG_TRY(W.get(WS_MISC, 256, &dmisc));
+  // observable partials of `chunk` steps, and the field at their stage times
+  // (refilled at each chunk start); a fixed arena bounds the chunk
   const size_t part_per_step = (size_t)batch * nk * 5 * sizeof(double);
-  const int chunk = (int)std::min<size_t>(256, std::max<size_t>(1, OBS_PART_BUDGET / part_per_step));
-  TDG_TRY(ws_reserve(ctx, WS_OBS_PART, part_per_step * chunk, &part));
-  // field at the stage times of one chunk of steps (refilled at each chunk start)
+  const size_t per_slot = part_per_step + (size_t)batch * 4 * sizeof(double);
+  int chunk = (int)std::min<size_t>(256, std::max<size_t>(1, OBS_PART_BUDGET / part_per_step));
+  if (fixed) chunk = (int)std::min<size_t>(chunk, W.left() >= 512 ? (W.left() - 512) / per_slot : 0);
+  if (chunk < 1) return fail(ctx, TDG_E_INVAL, "the scratch array cannot hold one step of observable partials");
+  TDG_TRY(W.get(WS_OBS_PART, part_per_step * chunk, &part));
   void* ftab = nullptr;
-  TDG_TRY(ws_reserve(ctx, WS_FTAB, (size_t)chunk * batch * 4 * sizeof(double), &ftab));
+  TDG_TRY(W.get(WS_FTAB, (size_t)chunk * batch * 4 * sizeof(double), &ftab));
   auto field_table = [&](int64_t step0) {
     const int count = (int)std::min<int64_t>(chunk, max_steps - step0 + 1);
     const int total = count * batch * 4;
     hipLaunchKernelGGL(field_table_kernel, dim3((total + 255) / 256), dim3(256), 0, ctx->stream,
                        (const tdg_field*)dfields, batch, (int)step0, count, dt, (double*)ftab);
   };
-  TDG_TRY(upload(ctx, WS_FIELDS, sorted.data(), sizeof(tdg_field) * batch, &dfields));
-  TDG_TRY(upload(ctx, WS_PERM, perm.data(), sizeof(int) * batch, &dperm));
+  TDG_TRY(args_upload(ctx, dfields, sorted.data(), sizeof(tdg_field) * batch));
+  TDG_TRY(args_upload(ctx, dperm, perm.data(), sizeof(int) * batch));
+  if (!init_eq) {
+    // rho(0) must be Hermitian; the check waits for its one-value result
+    const int64_t nblk = (int64_t)batch * nk;
+    const int64_t nparts = (nblk + 255) / 256;
+    hipLaunchKernelGGL(herm_check_kernel, dim3((unsigned)nparts), dim3(256), 0, ctx->stream, (const double2*)rho, nblk,
+                       model->nb, (double*)part);
+    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, ctx->stream, (const double*)part, nparts,
+                       (double*)dmisc);
+    TDG_TRY(launch_check(ctx, "rho(0) check launch"));
+    double h = 0.0;
+    TDG_TRY(hip_check(ctx, hipMemcpyAsync(&h, dmisc, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+                      "rho(0) check copy"));
+    TDG_TRY(hip_check(ctx, hipStreamSynchronize(ctx->stream), "rho(0) check sync"));
+    if (!(h <= RHO0_HERM_TOL))
+      return fail(ctx, TDG_E_INVAL, "rho(0) is not Hermitian: max |rho_nm - conj rho_mn| = %.3g > %g", h,
+                  RHO0_HERM_TOL);
+  }
 
   const int init_threads = ((nb2 + 63) / 64) * 64;
   auto init = [&]() {
@@ -1745,7 +1862,7 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
     if (found >= 0) {
       var = found % 100;
       if (tune_split) set_split(splits[found / 100]);
-    } else {
+    } else if (!fixed) {
       // time each variant on stage 0 of step 0: it reads rho and writes only
       // the stage state, accumulator and next gather, which init restores
       TunerEvents te;
@@ -1866,6 +1983,13 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
   return launch_check(ctx, "propagation launch");
 }
 
+extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model, const tdg_field* fields,
+                             int32_t batch, double dt, void* rho, int32_t init_eq, const tdg_obs* obs) {
+  if (!ctx) return TDG_E_INVAL;
+  Workspace W{ctx};
+  return propagate_impl(ctx, op, model, fields, batch, dt, rho, init_eq, obs, W);
+}
+
 extern "C" int tdg_observables(tdg_ctx ctx, const tdg_model* model, const void* rho, int32_t batch,
                                const tdg_field* fields, double* out) {
   if (!ctx) return TDG_E_INVAL;
@@ -1877,7 +2001,8 @@ extern "C" int tdg_observables(tdg_ctx ctx, const tdg_model* model, const void* 
   const int nk = model->nk1 * model->nk2;
   void *part = nullptr, *dfields = nullptr;
   TDG_TRY(ws_reserve(ctx, WS_OBS_PART, (size_t)batch * nk * 5 * sizeof(double), &part));
-  TDG_TRY(upload(ctx, WS_FIELDS, fields, sizeof(tdg_field) * batch, &dfields));
+  TDG_TRY(ws_reserve(ctx, WS_FIELDS, sizeof(tdg_field) * batch, &dfields));
+  TDG_TRY(args_upload(ctx, dfields, fields, sizeof(tdg_field) * batch));
   StageParams sp = {};
   sp.rho_s = (double2*)rho;
   sp.dip = (const double2*)model->dip;
