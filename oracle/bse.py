@@ -63,6 +63,18 @@ def _response_integrals(lam, fields, b, dt, nsteps, nodes: int = 16):
     return g
 
 
+def sector_trace(drho: np.ndarray, a: np.ndarray, lab: np.ndarray, block: str) -> np.ndarray:
+    """Re Tr(a drho) per time from the sector rows: sum of a_mn drho_nm over the
+    rows (k, n, m); the conduction-valence block also carries the rows
+    drho_vc = conj(drho_cv), whose terms a_cv conj(drho_cv) are the complex
+    conjugates of the a_vc drho_cv terms (a Hermitian)."""
+    kn, n, m = lab[:, 0], lab[:, 1], lab[:, 2]
+    t = drho * a[kn, m, n][None, :]
+    if block == "eh":
+        t = t + t.conj()
+    return t.sum(1).real
+
+
 def linear_response(model, k: np.ndarray, block: str, fields, dt: float, nsteps: int,
                     instance: int = 0) -> dict:
     """First-order P(t), J(t) from the eigendecomposition of L; also its eigenvalues."""
@@ -78,17 +90,10 @@ def linear_response(model, k: np.ndarray, block: str, fields, dt: float, nsteps:
     coef = np.linalg.solve(rvec, src)
     g = _response_integrals(lam, fields, b, dt, nsteps)
     drho = -1j * (g * coef[None, :]) @ rvec.T          # [t][row]
-    # Tr(A drho) = sum over sector rows of A_mn drho_nm; the conduction-valence
-    # block carries drho_vc = conj(drho_cv) implicitly.
-    pd = drho * d[kn, m, n][None, :]
-    pj = drho * v[kn, m, n][None, :]
-    if block == "eh":
-        pd = pd + (drho * d[kn, m, n][None, :]).conj()
-        pj = pj + (drho * v[kn, m, n][None, :]).conj()
     j_eq = sum(v[:, i, i].sum() for i in range(model.nv)).real
     return {
-        "P": pd.sum(1).real / model.nk,
-        "J": (pj.sum(1).real + j_eq) / model.nk,
+        "P": sector_trace(drho, d, lab, block) / model.nk,
+        "J": (sector_trace(drho, v, lab, block) + j_eq) / model.nk,
         "eig": lam,
         "drho": drho,
         "labels": lab,

@@ -21,6 +21,7 @@ BSE = importlib.import_module("oracle.bse")
 ADJOINT = importlib.import_module("oracle.adjoint")
 INTRABAND = importlib.import_module("oracle.intraband")
 COMPRESS = importlib.import_module("oracle.compress")
+SPECTRA = importlib.import_module("oracle.spectra")
 
 
 @pytest.fixture(scope="module")
@@ -152,6 +153,38 @@ def _current_not_averaged(model, rho, ex, ey, grid_trace=False):
     return o
 
 
+def _sector_trace_partner_dropped(drho, a, lab, block):
+    kn, n, m = lab[:, 0], lab[:, 1], lab[:, 2]
+    return (drho * a[kn, m, n][None, :]).sum(1).real
+
+
+def _sector_trace_transposed(drho, a, lab, block):
+    kn, n, m = lab[:, 0], lab[:, 1], lab[:, 2]
+    t = drho * a[kn, n, m][None, :]
+    if block == "eh":
+        t = t + t.conj()
+    return t.sum(1).real
+
+
+def _absorption_no_frequency(p, e, dt, omegas, eta):
+    return SPECTRA._real_absorption(p, e, dt, omegas, eta) / omegas
+
+
+def _hhg_no_frequency(j, dt, omegas):
+    return SPECTRA._real_hhg(j, dt, omegas) / omegas ** 2
+
+
+def _hhg_no_dt(j, dt, omegas):
+    return SPECTRA._real_hhg(j, dt, omegas) / dt ** 2
+
+
+def _harmonic_loss_fundamental(j, omega, dt, order=3):
+    return ADJOINT._real_harmonic_loss(j, omega, dt, order=1)
+
+
+SPECTRA._real_absorption = SPECTRA.absorption
+SPECTRA._real_hhg = SPECTRA.hhg
+ADJOINT._real_harmonic_loss = ADJOINT.harmonic_loss
 INTRABAND._real_neighbour = INTRABAND._neighbour
 COMPRESS._real_svd_offdiag = COMPRESS.svd_offdiag
 COMPRESS._real_choose_rank = COMPRESS.choose_rank
@@ -210,6 +243,14 @@ CASES = {
     "intraband: polar factor conjugate-transposed": (INTRABAND, "polar_unitary",
                                                      lambda b: np.linalg.svd(b)[2].conj().T
                                                      @ np.linalg.svd(b)[0].conj().T, "intra_rotated"),
+    "linear response (e-h): the conjugate partner rows dropped": (BSE, "sector_trace",
+                                                                  _sector_trace_partner_dropped, "weak_tda"),
+    "linear response: trace operand transposed": (BSE, "sector_trace", _sector_trace_transposed, "weak_tda"),
+    "absorption: frequency prefactor dropped": (SPECTRA, "absorption", _absorption_no_frequency, "absorption"),
+    "hhg: frequency prefactor dropped": (SPECTRA, "hhg", _hhg_no_frequency, "hhg"),
+    "hhg: time step dropped": (SPECTRA, "hhg", _hhg_no_dt, "hhg"),
+    "harmonic loss taken at the fundamental": (ADJOINT, "harmonic_loss", _harmonic_loss_fundamental,
+                                               "harmonic_loss"),
 }
 
 
@@ -217,6 +258,14 @@ def _run_pin(name, small):
     d6, t4 = small
     if name == "weak_bse":
         pins.test_weak_pulse_matches_bse_linear_response(d6, O.build_kernel(d6, R0_STABLE, "all"))
+    elif name == "weak_tda":
+        pins.test_weak_pulse_matches_tamm_dancoff_linear_response(t4, O.build_kernel(t4, R0_STABLE, "eh"))
+    elif name == "absorption":
+        pins.test_absorption_matches_sum_over_states(t4, O.build_kernel(t4, R0_STABLE, "eh"))
+    elif name == "hhg":
+        pins.test_hhg_of_a_pure_harmonic_closed_form()
+    elif name == "harmonic_loss":
+        pins.test_harmonic_loss_closed_form()
     elif name == "two_level":
         pins.test_two_level_closed_form(d6)
     elif name == "hermitian":

@@ -392,25 +392,86 @@ def test_weak_pulse_matches_bse_linear_response(dirac6, k_dirac6):
     assert np.abs((out["J"] - out["J"][0]) - jd).max() < 2e-5 * np.abs(jd).max()
 
 
-def test_absorption_peak_at_lowest_bright_exciton(tb4_4, k_tb4_eh):
-    """A narrow kick excites every exciton; the absorption maximum near the
-    band edge sits at the lowest bright eigenvalue of A = dE + K_eh."""
+def test_weak_pulse_matches_tamm_dancoff_linear_response(tb4_4, k_tb4_eh):
+    """Conduction-valence block: a weak pulse's P(t), J(t) equal the linear
+    response of the Tamm-Dancoff problem A = dE + K_eh (the e-h branch of the
+    linear response), to O(E0^2) and the RK4 error."""
+    f = FieldTable.single(1e-7, 2.0 / HARTREE_EV, 3.0 * FS_AU, 8.0 * FS_AU, 800)
+    lr = O.linear_response(tb4_4, k_tb4_eh, "eh", f, DT / 2, 800)
+    out = O.propagate(tb4_4, O.DenseOp(k_tb4_eh), "eh", f, DT / 2, nsteps=800)
+    assert np.abs(lr["P"]).max() > 1e-9
+    assert np.abs(out["P"] - lr["P"]).max() < 2e-5 * np.abs(lr["P"]).max()
+    jd = lr["J"] - lr["J"][0]
+    assert np.abs((out["J"] - out["J"][0]) - jd).max() < 1e-4 * np.abs(jd).max()
+
+
+def test_absorption_matches_sum_over_states(tb4_4, k_tb4_eh):
+    """A narrow kick excites every exciton.  The absorption spectrum of the
+    time-domain run equals the textbook linear-response spectrum built from the
+    eigenpairs (W_S, A^S) of the Tamm-Dancoff A = dE + K_eh, with the same
+    damping eta:
+      A(w) = w Im chi(w),
+      chi(w) = (1/nk) sum_S |<A^S|d_cv>|^2 [1/(W_S - w - i eta) + 1/(W_S + w + i eta)],
+    over 0.2-1.2 eV to 2 % of its maximum (the rest: the finite window and the
+    kick's width).  Within 0.1 eV of the lowest bright exciton the spectrum's
+    maximum lies within the transform's resolution 2 pi/T of it."""
     m = tb4_4
-    kick = FieldTable.single(1e-6, 0.0, 0.125 * FS_AU, 0.5 * FS_AU, 3000)
+    nsteps = 3000
+    kick = FieldTable.single(1e-6, 0.0, 0.125 * FS_AU, 0.5 * FS_AU, nsteps)
     out = O.propagate(m, O.DenseOp(k_tb4_eh), "eh", kick, DT)
     amat, lab = O.linear_operator(m, k_tb4_eh, "eh")
     ev, vec = np.linalg.eigh(amat)
     kn, n, mm = lab[:, 0], lab[:, 1], lab[:, 2]
-    # the pulse drives drho_cv through d_cv: strength |<A^S | d_cv>|^2
     osc = np.abs(vec.conj().T @ m.dip[0][kn, n, mm]) ** 2
-    bright = ev[osc > 1e-2 * osc.max()]
-    target = bright[0]
     t = np.arange(out["P"].shape[0]) * DT
     efield = np.array([O.field_at(ti, kick, 0) for ti in t])
-    om = np.linspace(target - 0.3 / HARTREE_EV, target + 0.3 / HARTREE_EV, 601)
-    spec = O.absorption(out["P"], efield, DT, om, 0.02 / HARTREE_EV)
-    near = np.abs(ev - om[np.argmax(spec)]).min() * HARTREE_EV
-    assert near < 5e-3
+    eta = 0.02 / HARTREE_EV
+    om = np.linspace(0.2 / HARTREE_EV, 1.2 / HARTREE_EV, 1001)
+    spec = O.absorption(out["P"], efield, DT, om, eta)
+    chi = (osc[None, :] * (1.0 / (ev[None, :] - om[:, None] - 1j * eta)
+                           + 1.0 / (ev[None, :] + om[:, None] + 1j * eta))).sum(1) / m.nk
+    ref = om * chi.imag
+    assert np.abs(spec - ref).max() < 2e-2 * ref.max()
+    target = ev[osc > 1e-2 * osc.max()][0]
+    win = np.linspace(target - 0.1 / HARTREE_EV, target + 0.1 / HARTREE_EV, 401)
+    assert np.sum(np.abs(ev - target) < 0.1 / HARTREE_EV) == 1      # an isolated exciton
+    peak = win[np.argmax(O.absorption(out["P"], efield, DT, win, eta))]
+    assert abs(peak - target) < 2 * np.pi / (nsteps * DT)
+
+
+def _geometric(x, count):
+    """sum_{n < count} exp(i x n)"""
+    z = np.exp(1j * x)
+    return complex(count) if abs(1.0 - z) < 1e-14 else (1.0 - z ** count) / (1.0 - z)
+
+
+def test_hhg_of_a_pure_harmonic_closed_form():
+    """HHG(W) = |W dt sum_n J_n exp(-i W t_n)|^2 for J_n = cos(a t_n): the two
+    exponentials of the cosine sum as geometric series, at the harmonic
+    (where the sum grows as count/2) and away from it."""
+    dt, count, a = 0.37, 1500, 0.21
+    j = np.cos(a * np.arange(count) * dt)
+    om = np.array([a, 2 * a, 3 * a, 0.5 * a, 1.013 * a])
+    got = O.hhg(j, dt, om)
+    ref = np.array([abs(w * dt * 0.5 * (_geometric((a - w) * dt, count) + _geometric(-(a + w) * dt, count))) ** 2
+                    for w in om])
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-12 * ref.max())
+    assert abs(got[0] / (a * dt * count / 2) ** 2 - 1.0) < 1e-2
+    # the spectrum's maximum sits at the harmonic, within the resolution 2 pi / (count dt)
+    fine = np.linspace(0.5 * a, 1.5 * a, 2001)
+    assert abs(fine[np.argmax(O.hhg(j, dt, fine))] - a) < 2 * np.pi / (count * dt)
+
+
+def test_harmonic_loss_closed_form():
+    """The third-harmonic intensity of J_n = cos(3 w t_n) + cos(w t_n) is the
+    geometric-series value at 3w, and equals hhg at 3w."""
+    dt, count, w = 0.29, 1200, 0.11
+    t = np.arange(count) * dt
+    j = np.cos(3 * w * t) + np.cos(w * t)
+    loss, _, _ = O.harmonic_loss(j, w, dt, order=3)
+    s = sum(0.5 * (_geometric((c - 3 * w) * dt, count) + _geometric(-(c + 3 * w) * dt, count)) for c in (3 * w, w))
+    assert abs(loss - abs(3 * w * dt * s) ** 2) <= 1e-10 * loss
+    assert abs(loss - O.hhg(j, dt, np.array([3 * w]))[0]) <= 1e-12 * loss
 
 
 def test_linear_response_of_literal_r0_grows():
