@@ -311,6 +311,33 @@ int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
                   const tdg_field* fields, int32_t batch, double dt, void* rho,
                   int32_t init_eq, const tdg_obs* obs);
 
+/* Size in bytes of the per-device scratch array of tdg_propagate_noalloc. */
+#define TDG_NOALLOC_SCRATCH_BYTES 33554432 /* 32 MiB */
+
+/* tdg_propagate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, integration and results, with every workspace buffer
+ * (stage states, drho gathers, projections, observable partials, field
+ * table) carved from a fixed device array of TDG_NOALLOC_SCRATCH_BYTES that
+ * the library holds per GPU from tdg_create until the process ends.  It
+ * calls no hipMalloc, hipFree or allocating library routine and creates no
+ * events.  Differences from tdg_propagate:
+ *   - every instance takes the per-instance path (each streams the operator;
+ *     no matrix-core batching); BF16X2 operators fail with TDG_E_UNSUPPORTED;
+ *   - the stage kernel is the one tdg_propagate tuned for this shape on the
+ *     same context, else variant 0 (TDG_OPT_STAGE_VARIANT still forces one);
+ *     nothing is timed; variants differ only in summation order;
+ *   - a workspace larger than the array (it grows with batch * nk * nb^2 and
+ *     batch * N) fails with TDG_E_INVAL before any work is queued; the
+ *     observable partials are kept for fewer steps at a time to fit.
+ * All calls on one GPU share its array, which keeps the last call's contents
+ * (every byte a call reads it has written first): calls that may overlap on
+ * one GPU (other streams or contexts) race and must be serialised by the
+ * caller. */
+int tdg_propagate_noalloc(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
+                          const tdg_field* fields, int32_t batch, double dt, void* rho,
+                          int32_t init_eq, const tdg_obs* obs);
+
 /* Reverse-mode derivative of tdg_propagate (not in the paper, which
  * integrates forward only): the exact gradient of the discrete RK4 scheme
  * for a real loss L given by its cotangents on the observable series,

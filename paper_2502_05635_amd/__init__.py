@@ -307,7 +307,7 @@ class Context:
 
     def propagate(self, op, model: DeviceModel, block: str, fields, dt: float,
                   rho: torch.Tensor | None = None, init_eq: bool | None = None,
-                  diagnostics: bool = True) -> dict:
+                  diagnostics: bool = True, _entry: str = "tdg_propagate") -> dict:
         """Integrate every instance of `fields`; returns device tensors
         P, J, occ (and tr, herm) of shape [B][max nsteps + 1] and rho(T)."""
         fa = field_array(fields)
@@ -327,11 +327,20 @@ class Context:
         n = self.kernel_dim(model, block)
         opr = self._operator(op, block, n)
         ms = model.struct()
-        self._check(self._lib.tdg_propagate(self.h, C.byref(opr), C.byref(ms), fa, batch, float(dt), _ptr(rho),
-                                            int(init_eq), C.byref(obs)))
+        fn = getattr(self._lib, _entry)
+        self._check(fn(self.h, C.byref(opr), C.byref(ms), fa, batch, float(dt), _ptr(rho), int(init_eq),
+                       C.byref(obs)))
         arrs["rho"] = rho
         arrs["_obs_struct"] = obs
         return arrs
+
+    def propagate_noalloc(self, op, model: DeviceModel, block: str, fields, dt: float,
+                          rho: torch.Tensor | None = None, init_eq: bool | None = None,
+                          diagnostics: bool = True) -> dict:
+        """propagate() through tdg_propagate_noalloc: the library allocates
+        nothing (its workspace is the per-GPU scratch array); the result
+        tensors are still allocated here, by torch."""
+        return self.propagate(op, model, block, fields, dt, rho, init_eq, diagnostics, "tdg_propagate_noalloc")
 
     def propagate_adjoint(self, op, model: DeviceModel, block: str, fields, dt: float, gP=None, gJ=None,
                           gocc=None, rho0: torch.Tensor | None = None, checkpoint_every: int = 50,

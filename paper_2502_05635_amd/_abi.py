@@ -32,6 +32,7 @@ TDG_OPT_GEMM_VARIANT = 4
 TDG_OPT_GRAPHS = 5
 TDG_OPT_GEMM_SLICES = 6
 TDG_OPT_ADJOINT_STASH = 7
+TDG_NOALLOC_SCRATCH_BYTES = 33554432
 
 P = C.c_void_p
 
@@ -99,6 +100,8 @@ SIGNATURES = {
     "tdg_kernel_compress_channels": ([P, P, C.c_int64, C.c_int32, C.POINTER(Trunc), C.POINTER(Channels)], C.c_int),
     "tdg_propagate": ([P, C.POINTER(Operator), C.POINTER(Model), C.POINTER(Field), C.c_int32, C.c_double, P,
                        C.c_int32, C.POINTER(Obs)], C.c_int),
+    "tdg_propagate_noalloc": ([P, C.POINTER(Operator), C.POINTER(Model), C.POINTER(Field), C.c_int32, C.c_double, P,
+                               C.c_int32, C.POINTER(Obs)], C.c_int),
     "tdg_propagate_adjoint": ([P, C.POINTER(Operator), C.POINTER(Model), C.POINTER(Field), C.c_int32, C.c_double,
                                P, C.c_int32, C.POINTER(ObsGrad), C.POINTER(Grads)], C.c_int),
     "tdg_observables": ([P, C.POINTER(Model), P, C.c_int32, C.POINTER(Field), P], C.c_int),

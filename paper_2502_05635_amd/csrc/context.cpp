@@ -127,6 +127,7 @@ int tdg_create(tdg_ctx* out, int device, void* hip_stream) {
   if (device < 0 || device >= count) return fail(nullptr, TDG_E_INVAL, "device %d of %d", device, count);
   e = hipSetDevice(device);
   if (e != hipSuccess) return fail(nullptr, TDG_E_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+  TDG_TRY(scratch_init(device));
   tdg_ctx c = new (std::nothrow) tdg_ctx_s();
   if (!c) return fail(nullptr, TDG_E_NOMEM, "context allocation");
   c->device = device;

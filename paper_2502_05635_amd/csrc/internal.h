@@ -132,6 +132,9 @@ void sum_slices_c64(hipStream_t stream, const void* in, int slices, int64_t stri
 // (4-byte aligned) inside the arguments of kernels queued on the context
 // stream: the call does not wait, and the host array need not outlive it.
 int args_upload(tdg_ctx ctx, void* dev, const void* host, size_t bytes);
+// Look up, once per device (the device current), the device address of the
+// scratch array of tdg_propagate_noalloc (propagate.hip).
+int scratch_init(int device);
 
 }  // namespace tdg
 

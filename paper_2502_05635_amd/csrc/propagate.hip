@@ -21,6 +21,7 @@
 // and is scattered back to the caller's order at the end.
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1949,8 +1950,8 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       const int active = s == 0 ? n_obs : n_dyn;
       if (active == 0) break;
       if (projects && n_dyn > 0) {
-        hipEvent_t pa, pb;
-        prof_pair(ctx, TDG_KCLASS_PROJECT, &pa, &pb);
+        hipEvent_t pa = nullptr, pb = nullptr;
+        if (!fixed) prof_pair(ctx, TDG_KCLASS_PROJECT, &pa, &pb);
         project(xc, n_dyn, pa, pb);
       }
       sp.vec = projects ? z : xc;
@@ -1960,8 +1961,8 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       sp.step = (int)step;
       sp.stage = s;
       sp.obs_slot = slot;
-      hipEvent_t sa, sb;
-      prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
+      hipEvent_t sa = nullptr, sb = nullptr;
+      if (!fixed) prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
       stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
       std::swap(xc, xn);
       // with links the next stage reads the buffer this one wrote (four
@@ -1987,6 +1988,50 @@ extern "C" int tdg_propagate(tdg_ctx ctx, const tdg_operator* op, const tdg_mode
                              int32_t batch, double dt, void* rho, int32_t init_eq, const tdg_obs* obs) {
   if (!ctx) return TDG_E_INVAL;
   Workspace W{ctx};
+  return propagate_impl(ctx, op, model, fields, batch, dt, rho, init_eq, obs, W);
+}
+
+// ---- allocation-free propagation ---------------------------------------------
+// The workspace of tdg_propagate_noalloc.  Each device holds its own copy from
+// the load of the library's code object until the process ends.  Host code
+// never uses this name for the memory (on the host it is only a stand-in):
+// the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) char scratch[TDG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_DEVICES] = {};
+}  // namespace
+
+namespace tdg {
+
+int scratch_init(int device) {
+  if (device < 0 || device >= SCRATCH_DEVICES)
+    return fail(nullptr, TDG_E_UNSUPPORTED, "device %d: at most %d devices", device, SCRATCH_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return TDG_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(nullptr, TDG_E_HIP, "device %d: address of the scratch array: %s", device, hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return TDG_OK;
+}
+
+}  // namespace tdg
+
+extern "C" int tdg_propagate_noalloc(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
+                                     const tdg_field* fields, int32_t batch, double dt, void* rho, int32_t init_eq,
+                                     const tdg_obs* obs) {
+  if (!ctx) return TDG_E_INVAL;
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < SCRATCH_DEVICES) base = g_scratch_ptr[ctx->device];
+  }
+  if (!base) return fail(ctx, TDG_E_HIP, "no scratch array address for device %d", ctx->device);
+  Workspace W{ctx, (char*)base, (size_t)TDG_NOALLOC_SCRATCH_BYTES};
   return propagate_impl(ctx, op, model, fields, batch, dt, rho, init_eq, obs, W);
 }
 
