@@ -7,9 +7,12 @@ Workload: the seeded four-band lattice model on a 36x36 grid, conduction-valence
 kernel block N = 5184 (complex64), one field instance E0 = 5e-3 a.u.,
 omega = 1.5 eV, 4000 RK4 steps of 0.05 fs.  The low-rank operator keeps the
 fraction of singular values chosen by the fixed-error criterion (stored with
-the oracle results under tests/golden/).  One step = one full RK4 step of the
-hot path: field, drho gather, contraction, per-k commutator, RK4 combine and
-observables, all on the device.
+the oracle results under tests/golden/): the smallest kept fraction whose FP64
+compressed kernel moves the first bright exciton by at most 0.04 eV and keeps
+the relative L2 error of P(t) within 5e-2 over the first half of the run.  One
+step = one full RK4 step of the hot path: field, drho gather, contraction,
+per-k commutator, RK4 combine and observables, all on the device.  `value` is
+the median of the timed runs of that path.
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region.
 """
@@ -48,10 +51,13 @@ def parse():
                     help="npz file: load the compressed factors from it if present, else compute and save them "
                          "(lets a counter-collection run skip the eigensolver)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 60x60 sweep measurement")
-    ap.add_argument("--large-grid", action="store_true",
-                    help="also measure the 120x120 workload (N = 57600, 256 instances): randomized "
-                         "compression, then dense FP32, low-rank FP32 and low-rank BF16X2 throughput")
-    ap.add_argument("--large-grid-steps", type=int, default=40, help="RK4 steps per instance timed there")
+    ap.add_argument("--no-large-grid", action="store_true",
+                    help="skip the 120x120 workload (N = 57600, 256 instances): randomized compression, "
+                         "then dense FP32, low-rank FP32 and low-rank BF16X2 throughput")
+    ap.add_argument("--large-grid-steps", type=int, default=12, help="RK4 steps per instance timed there")
+    ap.add_argument("--no-dense-hbm", action="store_true",
+                    help="skip the single-instance dense leg on the 60x60 kernel (1.66 GB, outside the "
+                         "256 MB Infinity Cache)")
     ap.add_argument("--no-channelwise", action="store_true", help="skip the channel-wise compression leg")
     ap.add_argument("--no-intraband", action="store_true", help="skip the intraband field-coupling leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
@@ -130,6 +136,8 @@ def algorithmic_bytes(kind, n, r, nk, nb, elt=8):
         return n * n * elt + 2 * n * elt + state_bytes(nk, nb)
     if kind == "lowrank_stage":    # S rows, z, K_diag, drho in, drho out, state
         return n * r * elt + r * elt + 3 * n * elt + state_bytes(nk, nb)
+    if kind == "lowrank_fused_stage":  # S rows and V^H columns of k, z in and out, K_diag, drho in and out, state
+        return 2 * n * r * elt + 2 * r * elt + 3 * n * elt + state_bytes(nk, nb)
     if kind == "project":          # V^H rows, drho in, z out
         return r * n * elt + n * elt + r * elt
     raise ValueError(kind)
@@ -171,7 +179,9 @@ def main():
     model = cfg.model()
     f = cfg.fields
     golden = json.load(open(GOLDEN_JSON)) if os.path.exists(GOLDEN_JSON) else None
-    frac = args.fraction if args.fraction is not None else (golden["chosen"]["fraction"] if golden else 0.05)
+    frac = args.fraction if args.fraction is not None else (golden["chosen"]["fraction"] if golden else 0.075)
+    # the smallest fraction meeting the exciton-shift criterion alone (the paper's 5 % point)
+    shift_frac = golden["shift_only"]["fraction"] if golden and golden.get("shift_only") else 0.05
 
     def fields_for(nsteps):
         return FieldTable(f.e0, f.omega, f.tau, f.t0, f.ex, f.ey, np.array([nsteps], dtype=np.int64))
@@ -207,15 +217,26 @@ def main():
         ctx.profile_enable(False)
         return res, t_b - t_a, prof
 
+    fac_shift = None
+    if abs(shift_frac - frac) > 1e-12 and args.fraction is None:
+        cache = args.factors_cache + ".shift.npz" if args.factors_cache else None
+        if cache and os.path.exists(cache):
+            fac_shift = load_factors(P, cache, K.shape[0], shift_frac)
+        else:
+            fac_shift = ctx.kernel_compress(K, "fraction", shift_frac)
+            if cache:
+                save_factors(fac_shift, cache, shift_frac)
     out = {}
-    for name, op in (("dense", K), ("lowrank", fac)):
+    legs = [("dense", K), ("lowrank", fac)] + ([("lowrank_shift_only", fac_shift)] if fac_shift else [])
+    for name, op in legs:
         progress(f"{name} operator, {args.steps} steps")
         res, secs, _ = timed(op, args.steps, args.warmup, False)
         variant = ctx.last_variant()
-        # further runs of the same K steps, for the spread between runs
+        # further runs of the same K steps; the median of all runs is reported
         again = [timed(op, args.steps, args.warmup, False)[1] for _ in range(args.repeats)]
         _, _, prof = timed(op, args.steps, args.warmup, True)
-        out[name] = {"secs": secs, "res": res, "prof": prof, "variant": variant, "runs": [secs] + again}
+        runs = [secs] + again
+        out[name] = {"secs": float(np.median(runs)), "res": res, "prof": prof, "variant": variant, "runs": runs}
 
     # channel-wise compression (Eq. svd-channel-wise) at its own fixed-error fraction
     chan_golden = json.load(open(CHAN_JSON)) if os.path.exists(CHAN_JSON) else None
@@ -257,26 +278,51 @@ def main():
             "covariant_difference_extra_bytes_per_launch": 4 * nk * nb * nb * 16,
         }
 
-    # errors against the stored FP64 oracle series (same operator, same steps):
-    # over the first half of the run (t <= t0, before the post-pulse chaotic
-    # divergence; the parity window) and over the whole run
+    # errors against the stored FP64 oracle series (same operator, same steps),
+    # each labelled with the window of samples it covers: the first half of the
+    # run (t <= t0, the parity window before the post-pulse chaotic divergence)
+    # and the whole run when the timed run is that long, else the steps run
     errs = {}
+    total = int(cfg.fields.nsteps[0])
     if os.path.exists(GOLDEN_NPZ) and golden and abs(golden["chosen"]["fraction"] - frac) < 1e-12:
         g = np.load(GOLDEN_NPZ)
-        m_ = min(args.steps, int(cfg.fields.nsteps[0])) + 1
-        half = min(m_, int(cfg.fields.nsteps[0]) // 2 + 1)
-        for name, pre in (("dense", "dense"), ("lowrank", "low")):
+        m_ = min(args.steps, total) + 1
+        half = total // 2 + 1
+
+        def windows(got, ref):
+            e = {}
+            if m_ >= half:
+                e["first_half"] = err_rel(got[:half], ref[:half])
+            e["full_run" if m_ == total + 1 else f"steps_0_to_{m_ - 1}"] = err_rel(got[:m_], ref[:m_])
+            return e
+
+        pairs = [("dense", "dense"), ("lowrank", "low")]
+        if "lowrank_shift_only" in out and "paper_P" in g.files:
+            pairs.append(("lowrank_shift_only", "paper"))
+        for name, pre in pairs:
             res = out[name]["res"]
             errs[name] = {}
             for k in ("P", "J"):
                 got = res[k][0, :m_].cpu().numpy()
-                errs[name][f"{k}_first_half"] = err_rel(got[:half], g[f"{pre}_{k}"][:half])
-                errs[name][f"{k}_full"] = err_rel(got, g[f"{pre}_{k}"][:m_])
-        low = out["lowrank"]["res"]["P"][0, :m_].cpu().numpy()
-        errs["lowrank_fp32_vs_dense_fp64_P_l2_first_half"] = float(
-            np.linalg.norm(low[:half] - g["dense_P"][:half]) / np.linalg.norm(g["dense_P"][:half]))
-        errs["fixed_error_criterion"] = golden["criterion"]
-        errs["bright_exciton_shift_ev"] = golden["chosen"]["shift_ev"]
+                for w, v in windows(got, g[f"{pre}_{k}"]).items():
+                    errs[name][f"{k}_{w}"] = v
+                if name == "dense" and "pert_P" in g.files:
+                    # against the oracle run with K rounded to complex64: FP32 arithmetic alone
+                    for w, v in windows(got, g[f"pert_{k}"]).items():
+                        errs[name][f"{k}_{w}_vs_oracle_with_K_in_complex64"] = v
+        errs["samples_compared"] = m_
+        # the fixed-error points themselves, from the stored FP64 oracle table
+        # (compressed FP64 run against the dense FP64 run over all 4000 steps)
+        def point(row, meets):
+            return {"kept_fraction": row["fraction"], "rank": row["rank"],
+                    "bright_exciton_shift_ev": row["shift_ev"],
+                    "oracle_err_P_l2_first_half": row["err_P_l2_first_half"],
+                    "oracle_err_P_l2_full_run": row["err_P_l2_full"], "meets": meets}
+        errs["fixed_error_point"] = point(golden["chosen"], "bright-exciton shift <= 0.04 eV and first-half "
+                                                             "relative L2 error of P(t) <= 5e-2")
+        if golden.get("shift_only"):
+            errs["shift_only_point"] = point(golden["shift_only"], "bright-exciton shift <= 0.04 eV only "
+                                                                   "(the paper's 5 % criterion)")
 
     chan_errs = {}
     if chan is not None and os.path.exists(CHAN_NPZ) and chan_golden:
@@ -304,7 +350,8 @@ def main():
     # dominant kernel of the low-rank path and the dense stage kernel
     lp = out["lowrank"]["prof"]
     dom = "stage" if lp["stage"][0] >= lp["project"][0] else "project"
-    dom_kind = "lowrank_stage" if dom == "stage" else "project"
+    fused = "fused" in out["lowrank"]["variant"]
+    dom_kind = ("lowrank_fused_stage" if fused else "lowrank_stage") if dom == "stage" else "project"
     dom_avg_s = lp[dom][0] / lp[dom][1] * 1e-3
     dom_bytes = algorithmic_bytes(dom_kind, n, r, nk, nb)
     dense_avg_s = out["dense"]["prof"]["stage"][0] / out["dense"]["prof"]["stage"][1] * 1e-3
@@ -322,17 +369,29 @@ def main():
         intraband["cost_vs_k_local_lowrank"] = value / intraband["value"]
 
     rank_cut = int(np.count_nonzero(fac.sigma > 1e-3 * fac.sigma[0]))
+    shift_point = None
+    if "lowrank_shift_only" in out:
+        sv = args.steps / out["lowrank_shift_only"]["secs"]
+        shift_point = {"value": sv, "ms_per_step": 1e3 / sv, "kept_fraction": shift_frac, "rank": fac_shift.rank,
+                       "variant": out["lowrank_shift_only"]["variant"], "speedup_vs_dense": sv / dense_value}
+    for v in out.values():
+        v.pop("res", None)
+    del K, fac, fac_shift, res, chan
+    torch.cuda.empty_cache()
+    dense_hbm = None
+    if not args.no_dense_hbm:
+        progress("single-instance dense leg on the 60x60 kernel")
+        dense_hbm = dense_hbm_leg(P, abi, ctx, min(args.steps, 100))
     sweep = None
     if not args.no_sweep:
-        for v in out.values():
-            v.pop("res", None)
-        del K, fac, res, chan
-        torch.cuda.empty_cache()
         progress("60x60 batched sweep")
-        sweep = batched_sweep(P, abi, ctx, frac, bf16x2=not args.no_sweep_bf16x2)
-    if args.large_grid:
+        # the sweep keeps 5 % of the singular values (the paper's point; no
+        # stored oracle table exists for its grid)
+        sweep = batched_sweep(P, abi, ctx, 0.05, bf16x2=not args.no_sweep_bf16x2)
+    large = None
+    if not args.no_large_grid:
         progress("120x120 large grid")
-    large = large_grid(P, abi, args.large_grid_steps) if args.large_grid else None
+        large = large_grid(P, abi, args.large_grid_steps)
     if not args.no_adjoint:
         progress("adjoint")
     adjoint = None if args.no_adjoint else adjoint_leg(P, ctx)
@@ -360,8 +419,12 @@ def main():
                         f"N={n} complex64, 1 field instance, dt=0.05 fs; FP32 contraction, FP64 state",
             "operator": "low-rank K_diag + S V^H",
             "kept_fraction": frac, "rank": r, "rank_rel_cut_1e-3": rank_cut,
+            "fixed_error": "smallest kept fraction whose FP64 compressed kernel moves the first bright exciton "
+                           "by <= 0.04 eV and keeps the first-half relative L2 error of P(t) <= 5e-2",
             "batch": 1, "parallelism": "none",
         },
+        "lowrank_shift_only_point": shift_point,
+        "value_is": f"median of {1 + args.repeats} timed runs of {args.steps} steps",
         "dense": {"value": dense_value, "ms_per_step": 1e3 / dense_value, "variant": out["dense"]["variant"],
                   "stage_kernel_us": dense_avg_s * 1e6,
                   "stage_kernel_GBps": dense_bytes / dense_avg_s / 1e9,
@@ -369,15 +432,16 @@ def main():
         "speedup_lowrank_vs_dense": value / dense_value,
         "runs": {name: {"steps_per_s": [args.steps / t for t in out[name]["runs"]],
                         "median_steps_per_s": float(np.median([args.steps / t for t in out[name]["runs"]]))}
-                 for name in ("lowrank", "dense")},
+                 for name in out},
+        "dense_single_instance_60x60": dense_hbm,
         "channelwise": channelwise,
         "intraband": intraband,
         "errors_vs_fp64_oracle": errs or None,
         "compress_seconds": compress_s,
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"stage_kernel<float, 1, ...> ({out['lowrank']['variant']})" if dom == "stage"
-                       else "project_kernel<float>"),
+            "kernel": (f"stage_kernel<float, {3 if fused else 1}, ...> ({out['lowrank']['variant']})"
+                       if dom == "stage" else "project_kernel<float>"),
             "achieved": dom_bytes / dom_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom_bytes / dom_avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
             "avg_launch_us": dom_avg_s * 1e6, "bytes_per_launch": dom_bytes,
@@ -389,6 +453,44 @@ def main():
     }
     ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def dense_hbm_leg(P, abi, ctx, steps):
+    """One instance of the 60x60 workload's pulse with the dense FP32 kernel
+    (N = 14400, 1.66 GB complex64: far beyond the 256 MB Infinity Cache, so
+    every stage streams K from HBM), on the per-instance path: the stage
+    kernel's HBM bandwidth against the 8 TB/s peak."""
+    import numpy as np
+    import torch
+
+    from workloads import FieldTable, get_config
+    cfg = get_config(2)
+    model = cfg.model()
+    dm = P.DeviceModel.from_model(model)
+    K = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
+    f = cfg.fields
+    one = lambda ns: FieldTable(f.e0[:1], f.omega[:1], f.tau[:1], f.t0[:1], f.ex[:1], f.ey[:1],  # noqa: E731
+                                np.array([ns], dtype=np.int64))
+    ctx.propagate(K, dm, "eh", one(4), cfg.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.propagate(K, dm, "eh", one(steps), cfg.dt)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    ctx.profile_enable(True)
+    ctx.propagate(K, dm, "eh", one(steps), cfg.dt)
+    ms, cnt = ctx.profile_read(abi.TDG_KCLASS_STAGE)
+    ctx.profile_enable(False)
+    n, nk, nb = K.shape[0], model.nk, model.nb
+    avg = ms / cnt * 1e-3
+    nbytes = algorithmic_bytes("dense_stage", n, 0, nk, nb)
+    out = {"workload": f"{cfg.name}, instance 0 alone: N={n} complex64 kernel ({n * n * 8 / 1e9:.2f} GB), "
+                       f"{steps} RK4 steps", "value": steps / secs, "ms_per_step": 1e3 * secs / steps,
+           "variant": ctx.last_variant(), "stage_kernel_us": avg * 1e6, "bytes_per_launch": nbytes,
+           "stage_kernel_GBps": nbytes / avg / 1e9, "stage_kernel_hbm_frac": nbytes / avg / 1e9 / HBM_PEAK_GBS}
+    del K
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_sweep(P, abi, ctx, frac, steps=0, cache=None, bf16x2=True):
@@ -598,8 +700,12 @@ def cpu_baseline(cfg, frac, seconds):
     t0 = time.perf_counter()
     O.propagate(model, op, "eh", cfg.fields, cfg.dt, nsteps=nsamp)
     secs = time.perf_counter() - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    pools = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+    threads = max([p.get("num_threads", 1) for p in pools] or [1])
+    blas = ", ".join(f"{p.get('internal_api')} {p.get('version')} ({p.get('threading_layer', '')} threads)"
+                     for p in pools) or "unknown"
     return {"value": nsamp / secs, "unit": "instance·RK4 steps/sec", "cores": int(threads), "kind": "oracle",
+            "blas": blas,
             "sample": f"first {nsamp} of {int(cfg.fields.nsteps[0])} RK4 steps of the same workload, FP64 numpy "
                       f"oracle, low-rank operator at rank {fac['r']} (kernel build and SVD untimed)"}
 

@@ -319,8 +319,12 @@ class Context:
             init_eq = True if init_eq is None else init_eq
         init_eq = bool(init_eq)
         stride = maxn + 1
-        arrs = {k: torch.zeros((batch, stride), dtype=torch.float64, device=dev)
-                for k in (("P", "J", "occ", "tr", "herm") if diagnostics else ("P", "J", "occ"))}
+        names = ("P", "J", "occ", "tr", "herm") if diagnostics else ("P", "J", "occ")
+        # every entry up to an instance's own length is written; only shorter
+        # instances leave a tail, which is zeroed
+        even = all(int(f.nsteps) == maxn for f in fa)
+        buf = (torch.empty if even else torch.zeros)((len(names), batch, stride), dtype=torch.float64, device=dev)
+        arrs = {k: buf[i] for i, k in enumerate(names)}
         obs = abi.Obs(arrs["P"].data_ptr(), arrs["J"].data_ptr(), arrs["occ"].data_ptr(),
                       arrs["tr"].data_ptr() if diagnostics else None,
                       arrs["herm"].data_ptr() if diagnostics else None, stride)

@@ -20,14 +20,13 @@ enum WsSlot {
   WS_X1,         // drho gather, pong
   WS_Z,          // low-rank projection  [B][r]
   WS_OBS_PART,   // per-k observables    double [chunk][B][nk][5]
-  WS_FIELDS,     // field records        tdg_field [B]
+  WS_FIELDS,     // field records        tdg_field [B], then the sorted -> caller's instance map int [B]
   WS_WTAB,       // W(q) by index difference, double [nk1][nk2]
   WS_SOLVER_A,   // compression: K_off column-major, c128 [n][n]
   WS_SOLVER_D,   // eigenvalues / off-diagonal, double [2n]
   WS_SOLVER_I,   // info, permutation, kept eigenvalues
   WS_MISC,       // small scratch (row sums, flags)
   WS_RHO_N,      // rho(t_n) in sorted instance order, c128 [B][nk][nb][nb]
-  WS_PERM,       // sorted position -> caller's instance index, int [B]
   WS_Y,          // batched: contraction result / split-K partials, c64
   WS_ZSUM,       // batched low rank: projection summed over its split-K slices, c64
   WS_TMP1,       // conversion staging (complex64 copies before a BF16X2 split)
@@ -43,6 +42,11 @@ enum WsSlot {
   WS_INTRA,      // intraband term: covariant derivative of the stage state, c128 like the state
   WS_RHO_S2,     // intraband term, per-instance path: second stage-state buffer (stages alternate)
   WS_FTAB,       // field at the stage times of a chunk of steps, double [chunk][B][4]
+  WS_VT,         // fused projection: V^H transposed [N][rank]
+  WS_ZPART,      // fused projection: per-k partials [B][nk][rank]
+  WS_GSUM,       // fused projection: group sums, c128 [B][groups][rank]
+  WS_CNT,        // fused projection: arrival counters [B][groups + 1]
+  WS_ZF,         // fused projection: the projection of the current and next gather [2][B][rank]
   WS_COUNT
 };
 

@@ -45,6 +45,7 @@ constexpr int THREADS = 256;  // dense stage kernel and auxiliary kernels
 constexpr int NB2_MAX = TDG_NB_MAX * TDG_NB_MAX;
 constexpr int ROWS = 4;  // kernel rows contracted together (shared drho loads)
 constexpr int ZSPLIT_MAX = 4;  // low rank: largest number of projection column slices
+constexpr int FUSED_RMAX = 512;  // fused projection: largest rank (its V^H columns are held in LDS)
 constexpr int PROJ_THREADS = 256;
 constexpr size_t OBS_PART_BUDGET = size_t(64) << 20;
 
@@ -286,6 +287,16 @@ struct StageParams {
   double cov_c1, cov_c2;  // 1 / (2 |b_a|) per grid axis
   int tr_signed;          // per-k trace partial signed (summed over k) instead of |.| (maximised)
   const double* ftab;     // field at the stage times, [obs slot][B][4] (field_table_kernel)
+  // low rank with the projection fused into the stage kernel (MODE 3): z of
+  // the next stage from the gather this kernel writes, by per-k partials and
+  // a two-level fixed-order reduction done by the last block of each k group
+  // and then by the last group
+  const void* vt;         // V^H transposed, [N][ncols] (rows k P .. k P + P - 1 contiguous)
+  void* zpart;            // per-k partials [B][nk][ncols]
+  double2* gsum;          // group sums [B][ngroups][ncols]
+  unsigned* cnt;          // arrival counters [B][ngroups + 1], zero between launches
+  void* znext;            // projection of the next gather [B][vstride]
+  int kgroup, ngroups;    // k points per group, number of groups
 };
 
 // Per-k observables of s_rho (LDS) into obs_part; de, ve are this thread's
@@ -337,7 +348,7 @@ template <typename T, int MODE, int NT, int U, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 stage_kernel(StageParams sp) {
   using C = typename Cx<T>::type;
-  constexpr bool LOWRANK = MODE == 1, CHANNEL = MODE == 2;
+  constexpr bool FUSED = MODE == 3, LOWRANK = MODE == 1 || FUSED, CHANNEL = MODE == 2;
   constexpr int WAVES = NT / 64;
   const int k = blockIdx.x, b = blockIdx.y;
   const bool dyn = b < sp.n_dyn;
@@ -354,6 +365,24 @@ stage_kernel(StageParams sp) {
   // intraband term: entry (4 a + w) nb^2 + e holds element e of, for axis a,
   // w = 0: y(k + b_a), 1: y(k - b_a), 2: L_a(k), 3: L_a(k - b_a)
   __shared__ __align__(16) double2 s_cov[8 * NB2_MAX];
+  // fused projection: this k point's V^H columns, [p][j] = V^H[j][k P + p],
+  // and the next gather of its pairs
+  __shared__ __align__(16) C s_vt[FUSED ? ROWS * FUSED_RMAX : 1];
+  __shared__ C s_xn[ROWS];
+  __shared__ int s_last;
+  if (FUSED && dyn) {
+    // the P rows of V^H transposed are one contiguous run of P ncols elements:
+    // 16-byte direct-to-LDS copies issued now, waited for after the epilogue
+    const int pieces = (int)((size_t)P * sp.ncols * sizeof(C) / 16);
+    const char* src = reinterpret_cast<const char*>(sp.vt) + (size_t)k * P * sp.ncols * sizeof(C);
+    const int wave = t >> 6, lane = t & 63;
+    for (int c0 = wave * 64; c0 < pieces; c0 += NT) {
+      const int i = c0 + lane;
+      if (i < pieces)
+        __builtin_amdgcn_global_load_lds((lds_dma_src*)(src + (size_t)i * 16),
+                                         (lds_dma_dst*)(reinterpret_cast<char*>(s_vt) + (size_t)c0 * 16), 16, 0, 0);
+    }
+  }
 
   // ---- loads: the low-rank kernel issues every load of the block before any
   // use (its lifetime is latency-bound); the dense kernel loads the per-k
@@ -493,8 +522,11 @@ stage_kernel(StageParams sp) {
     load_state();
     load_field();
   }
-  // the per-k epilogue runs in the first wave (nb^2 <= 64 elements, P <= 64 pairs)
-  if (t >= 64) return;
+  // the per-k epilogue runs in the first wave (nb^2 <= 64 elements, P <= 64 pairs);
+  // with the fused projection the other waves of an integrating block wait
+  // for it below (dyn is uniform over the block)
+  if (t >= 64 && (!FUSED || !dyn)) return;
+  if (t < 64) {
   // the direct-to-LDS copies of the intraband neighbours have landed once
   // this wave's vector memory counter is zero
   if (sp.links && dyn) __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
@@ -587,8 +619,75 @@ stage_kernel(StageParams sp) {
       xv.y = (T)next.y;
       reinterpret_cast<C*>(sp.xnext)[(size_t)b * sp.xstride + (CHANNEL ? (size_t)p * sp.nk + k : (size_t)k * P + p)] =
           xv;
+      if (FUSED) s_xn[p] = xv;
     }
   }
+  }  // first wave
+  if (!FUSED) return;
+
+  // ---- fused projection of the next gather: z_j = sum_i V^H[j][i] x_i -------
+  __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);  // this wave's V^H copies have landed
+  __syncthreads();
+  const int nc = sp.ncols;
+  C* zp = reinterpret_cast<C*>(sp.zpart) + ((size_t)b * sp.nk + k) * nc;
+  for (int j = t; j < nc; j += NT) {
+    T pr = (T)0, pi = (T)0;
+    for (int p = 0; p < P; ++p) {
+      const C w = s_vt[p * nc + j], x = s_xn[p];
+      pr += w.x * x.x - w.y * x.y;
+      pi += w.x * x.y + w.y * x.x;
+    }
+    C v;
+    v.x = pr;
+    v.y = pi;
+    zp[j] = v;
+  }
+  // the last block of a group of kgroup k points sums the group's partials in
+  // k order; the last group sums the group sums in group order
+  unsigned* cnt = sp.cnt + (size_t)b * (sp.ngroups + 1);
+  const int g = k / sp.kgroup, g0 = g * sp.kgroup, gn = min(sp.kgroup, sp.nk - g0);
+  __syncthreads();
+  if (t == 0) {
+    __threadfence();
+    s_last = atomicAdd(cnt + g, 1u) == (unsigned)(gn - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const C* zg = reinterpret_cast<const C*>(sp.zpart) + ((size_t)b * sp.nk + g0) * nc;
+  double2* gs = sp.gsum + (size_t)b * sp.ngroups * nc;
+  for (int j = t; j < nc; j += NT) {
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < gn; ++q) {
+      const C v = zg[(size_t)q * nc + j];
+      sr += (double)v.x;
+      si += (double)v.y;
+    }
+    gs[(size_t)g * nc + j] = make_double2(sr, si);
+  }
+  __syncthreads();
+  if (t == 0) {
+    __threadfence();
+    s_last = atomicAdd(cnt + sp.ngroups, 1u) == (unsigned)(sp.ngroups - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  C* zn = reinterpret_cast<C*>(sp.znext) + (size_t)b * sp.vstride;
+  for (int j = t; j < nc; j += NT) {
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < sp.ngroups; ++q) {
+      const double2 v = gs[(size_t)q * nc + j];
+      sr += v.x;
+      si += v.y;
+    }
+    C v;
+    v.x = (T)sr;
+    v.y = (T)si;
+    zn[j] = v;
+  }
+  // every block of this instance has arrived: the counters start at zero again
+  for (int i = t; i <= sp.ngroups; i += NT) cnt[i] = 0u;
 }
 
 // Low-rank projection z_j = sum_i W[j][i] x_i (W = V^H): block (g, q, b) takes
@@ -666,6 +765,36 @@ __global__ void finish_kernel(const double2* __restrict__ rho_n, const int* __re
   const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
   if (t >= nb2) return;
   rho_out[((size_t)perm[b] * nk + k) * nb2 + t] = rho_n[((size_t)b * nk + k) * nb2 + t];
+}
+
+// vt = transpose of V^H (rank rows of n) for the fused projection: 32 x 32
+// tiles through LDS, both sides coalesced.
+template <typename T>
+__global__ void __launch_bounds__(256) transpose_vh_kernel(const void* __restrict__ w, int64_t n, int rank,
+                                                           void* __restrict__ vt) {
+  using C = typename Cx<T>::type;
+  __shared__ C tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32;
+  const int j0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const C* src = reinterpret_cast<const C*>(w);
+  C* dst = reinterpret_cast<C*>(vt);
+  for (int r = ty; r < 32; r += 8) {
+    const int j = j0 + r;
+    const int64_t i = i0 + tx;
+    if (j < rank && i < n) tile[r][tx] = src[(size_t)j * n + i];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r;
+    const int j = j0 + tx;
+    if (i < n && j < rank) dst[(size_t)i * rank + j] = tile[tx][r];
+  }
+}
+
+__global__ void __launch_bounds__(256) zero_u32_kernel(unsigned* p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = 0u;
 }
 
 // Hermiticity residual of a caller's rho(0): thread i takes the (instance,
@@ -1174,6 +1303,7 @@ static void launch_stage(dim3 grid, size_t lds, hipStream_t stream, const StageP
 struct Variant {
   const char* name;
   StageLaunch fn;
+  bool fused = false;  // low rank with the projection fused into the stage kernel
 };
 
 static const Variant kDenseF32[] = {
@@ -1194,6 +1324,9 @@ static const Variant kLowF32[] = {
     {"lowrank_f32_nt256", launch_stage<float, 1, 256, 1, 2>},
     {"lowrank_f32_nt128_c4", launch_stage<float, 1, 128, 2, 2>},
     {"lowrank_f32_nt64_c6", launch_stage<float, 1, 64, 3, 2>},
+    {"lowrank_fused_f32_nt128", launch_stage<float, 3, 128, 1, 2>, true},
+    {"lowrank_fused_f32_nt128_c4", launch_stage<float, 3, 128, 2, 2>, true},
+    {"lowrank_fused_f32_nt256", launch_stage<float, 3, 256, 1, 2>, true},
 };
 static const Variant kChanF32[] = {
     {"channel_f32_nt256_u2_w6", launch_stage<float, 2, 256, 2, 6>},
@@ -1208,6 +1341,8 @@ static const Variant kLowF64[] = {
     {"lowrank_f64_nt64", launch_stage<double, 1, 64, 1, 2>},
     {"lowrank_f64_nt128", launch_stage<double, 1, 128, 1, 2>},
     {"lowrank_f64_nt256", launch_stage<double, 1, 256, 1, 2>},
+    {"lowrank_fused_f64_nt128", launch_stage<double, 3, 128, 1, 2>, true},
+    {"lowrank_fused_f64_nt256", launch_stage<double, 3, 256, 1, 2>, true},
 };
 
 // Timing events of a tuner, destroyed on every exit path.
@@ -1358,9 +1493,11 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     zslice = ((n + want - 1) / want + 1) & ~int64_t(1);
     zsplit = (int)((n + zslice - 1) / zslice);
   };
-  // field records, sorted order, and the sorted position -> caller's index map
-  TDG_TRY(W.get(WS_FIELDS, sizeof(tdg_field) * batch, &dfields));
-  TDG_TRY(W.get(WS_PERM, sizeof(int) * batch, &dperm));
+  // field records in sorted order, followed by the sorted position -> caller's
+  // index map (one upload)
+  const size_t fbytes = sizeof(tdg_field) * batch, pbytes = (sizeof(int) * batch + 3) & ~size_t(3);
+  TDG_TRY(W.get(WS_FIELDS, fbytes + pbytes, &dfields));
+  dperm = (char*)dfields + fbytes;
   void* dmisc = nullptr;
   TDG_TRY(W.get(WS_MISC, 256, &dmisc));
   // observable partials of `chunk` steps, and the field at their stage times
@@ -1379,8 +1516,12 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     hipLaunchKernelGGL(field_table_kernel, dim3((total + 255) / 256), dim3(256), 0, ctx->stream,
                        (const tdg_field*)dfields, batch, (int)step0, count, dt, (double*)ftab);
   };
-  TDG_TRY(args_upload(ctx, dfields, sorted.data(), sizeof(tdg_field) * batch));
-  TDG_TRY(args_upload(ctx, dperm, perm.data(), sizeof(int) * batch));
+  {
+    std::vector<char> rec(fbytes + pbytes);
+    std::memcpy(rec.data(), sorted.data(), fbytes);
+    std::memcpy(rec.data() + fbytes, perm.data(), sizeof(int) * batch);
+    TDG_TRY(args_upload(ctx, dfields, rec.data(), rec.size()));
+  }
   if (!init_eq) {
     // rho(0) must be Hermitian; the check waits for its one-value result
     const int64_t nblk = (int64_t)batch * nk;
@@ -1849,10 +1990,64 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
   // low rank: the tuner also picks the projection's column split
   const bool tune_split = lowrank && !batched;
   const int splits[3] = {1, 2, ZSPLIT_MAX};
+
+  // Fused projection (low-rank variants marked fused): the stage kernel also
+  // forms z of the gather it writes, so no projection launch is needed per
+  // stage.  It holds a k point's V^H columns in LDS (P <= ROWS pairs, rank <=
+  // FUSED_RMAX) and reads V^H transposed, written once per call.
+  const bool fuse_ok = lowrank && !batched && !fixed && npair <= ROWS && op->rank <= FUSED_RMAX &&
+                       ((size_t)npair * op->rank * elt) % 16 == 0;
+  void* zf = nullptr;
+  bool fused_ready = false;
+  auto fused_setup = [&]() -> int {
+    if (fused_ready) return TDG_OK;
+    void *vtb = nullptr, *zpb = nullptr, *gsb = nullptr, *cnb = nullptr;
+    sp.kgroup = std::max(1, (int)std::lround(std::sqrt((double)nk)));
+    sp.ngroups = (nk + sp.kgroup - 1) / sp.kgroup;
+    TDG_TRY(W.get(WS_VT, (size_t)n * op->rank * elt, &vtb));
+    TDG_TRY(W.get(WS_ZPART, (size_t)batch * nk * op->rank * elt, &zpb));
+    TDG_TRY(W.get(WS_GSUM, (size_t)batch * sp.ngroups * op->rank * sizeof(double2), &gsb));
+    TDG_TRY(W.get(WS_CNT, (size_t)batch * (sp.ngroups + 1) * sizeof(unsigned), &cnb));
+    TDG_TRY(W.get(WS_ZF, (size_t)2 * batch * zstride * elt, &zf));
+    const dim3 tg((unsigned)((n + 31) / 32), (unsigned)((op->rank + 31) / 32));
+    if (op->dtype == TDG_C128)
+      hipLaunchKernelGGL(transpose_vh_kernel<double>, tg, dim3(256), 0, ctx->stream, op->w, n, (int)op->rank, vtb);
+    else
+      hipLaunchKernelGGL(transpose_vh_kernel<float>, tg, dim3(256), 0, ctx->stream, op->w, n, (int)op->rank, vtb);
+    const int64_t ncnt = (int64_t)batch * (sp.ngroups + 1);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((ncnt + 255) / 256)), dim3(256), 0, ctx->stream, (unsigned*)cnb,
+                       ncnt);
+    sp.vt = vtb;
+    sp.zpart = zpb;
+    sp.gsum = (double2*)gsb;
+    sp.cnt = (unsigned*)cnb;
+    fused_ready = true;
+    return launch_check(ctx, "fused projection setup");
+  };
+  // z of a gather in one piece into half h of zf (the fused variants' input)
+  auto project_full = [&](const void* xin, int active, int h) {
+    void* dst = (char*)zf + (size_t)h * batch * zstride * elt;
+    const dim3 g(groups, 1, active);
+    if (op->dtype == TDG_C128)
+      hipLaunchKernelGGL(project_kernel<double>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
+                         xstride, dst, zstride, pcols, (int64_t)0, 0, 0);
+    else
+      hipLaunchKernelGGL(project_kernel<float>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
+                         xstride, dst, zstride, pcols, (int64_t)0, 0, 0);
+  };
+  auto fused_params = [&](int h) {
+    sp.vec = (char*)zf + (size_t)h * batch * zstride * elt;
+    sp.znext = (char*)zf + (size_t)(1 - h) * batch * zstride * elt;
+    sp.vstride = zstride;
+    sp.zsplit = 1;
+  };
+
   if (ctx->forced_variant >= 0) {
     if (ctx->forced_variant >= nvar)
       return fail(ctx, TDG_E_INVAL, "variant %d of %d for this operator", ctx->forced_variant, nvar);
     var = ctx->forced_variant;
+    if (vt[var].fused && !fuse_ok)
+      return fail(ctx, TDG_E_INVAL, "variant %d (fused projection) does not apply to this operator or call", var);
   } else if (ctx->autotune && max_steps > 0) {
     char key[160];
     snprintf(key, sizeof(key), "%d/%d/%lld/%d/%d/%lld/%d", op->kind, op->dtype, (long long)n, nk, batch,
@@ -1863,6 +2058,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     if (found >= 0) {
       var = found % 100;
       if (tune_split) set_split(splits[found / 100]);
+      if (vt[var].fused && !fuse_ok) var = 0;  // the allocation-free call uses no fused variant
     } else if (!fixed) {
       // time each variant on stage 0 of step 0: it reads rho and writes only
       // the stage state, accumulator and next gather, which init restores
@@ -1880,6 +2076,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       sp.vec = projects ? z : x0;
       sp.vstride = projects ? zstride : xstride;
       const dim3 g(nk, dyn0);
+      if (fuse_ok) TDG_TRY(fused_setup());
       // three interleaved rounds of 8 repetitions per (split, variant); the
       // fastest round counts (single short timings vary by tens of per cent)
       float tmin[3][8];
@@ -1890,12 +2087,22 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
         for (int si = 0; si < nsplit; ++si) {
           if (tune_split) set_split(splits[si]);
           // with the split tuned, each timed repetition includes the projection
+          // (a fused variant forms it itself: timed alone, with the first split)
           auto run = [&](int v) {
-            if (projects && (tune_split || si == 0)) project(x0, dyn0);
+            if (projects && !vt[v].fused && (tune_split || si == 0)) project(x0, dyn0);
             vt[v].fn(g, 0, ctx->stream, sp, nullptr, nullptr);
           };
           if (projects && !tune_split) project(x0, dyn0);
           for (int v = 0; v < nvar; ++v) {
+            if (vt[v].fused && (!fuse_ok || si > 0)) continue;
+            if (vt[v].fused) {
+              project_full(x0, dyn0, 0);
+              fused_params(0);
+            } else {
+              sp.vec = projects ? z : x0;
+              sp.vstride = projects ? zstride : xstride;
+              sp.zsplit = zsplit;
+            }
             run(v);  // warm-up
             (void)hipEventRecord(ea, ctx->stream);
             for (int rep = 0; rep < 8; ++rep) {
@@ -1932,10 +2139,16 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       TDG_TRY(init());  // the caller's rho was only read
     }
   }
+  const bool fused = vt[var].fused;
   ctx->last_variant = vt[var].name;
-  if (tune_split) ctx->last_variant += "_z" + std::to_string(zsplit);
+  if (tune_split && !fused) ctx->last_variant += "_z" + std::to_string(zsplit);
   sp.zsplit = zsplit;
   const StageLaunch stage_fn = vt[var].fn;
+  int zhalf = 0;
+  if (fused) {
+    TDG_TRY(fused_setup());
+    if (count_gt(0) > 0) project_full(x0, count_gt(0), 0);
+  }
 
   tdg_obs ob = *obs;
   void* xc = x0;
@@ -1949,13 +2162,17 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     for (int s = 0; s < 4; ++s) {
       const int active = s == 0 ? n_obs : n_dyn;
       if (active == 0) break;
-      if (projects && n_dyn > 0) {
+      if (projects && n_dyn > 0 && !fused) {
         hipEvent_t pa = nullptr, pb = nullptr;
         if (!fixed) prof_pair(ctx, TDG_KCLASS_PROJECT, &pa, &pb);
         project(xc, n_dyn, pa, pb);
       }
-      sp.vec = projects ? z : xc;
-      sp.vstride = projects ? zstride : xstride;
+      if (fused) {
+        fused_params(zhalf);
+      } else {
+        sp.vec = projects ? z : xc;
+        sp.vstride = projects ? zstride : xstride;
+      }
       sp.xcur = xc;
       sp.xnext = xn;
       sp.step = (int)step;
@@ -1965,6 +2182,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       if (!fixed) prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
       stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
       std::swap(xc, xn);
+      if (fused && n_dyn > 0) zhalf = 1 - zhalf;  // the projection of the new gather
       // with links the next stage reads the buffer this one wrote (four
       // stages per step: every step starts from the first buffer)
       if (sp.links) std::swap(sp.rho_s, sp.rho_s_out);
