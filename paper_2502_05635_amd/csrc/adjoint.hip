@@ -24,11 +24,11 @@
 // Memory: rho is stored every M steps on the forward sweep; the backward
 // sweep recomputes a segment's states from its checkpoint, then each step's
 // four stages (states, dSigma pairs, x, z) before pulling the step back.
-// Products with K, S and V run as plain complex FP64 GEMMs (rocBLAS); the
-// per-k commutator pullbacks run in the kernels below.  The factor gradients
-// are accumulated once per segment with two GEMMs over its stage columns.
-#include <rocblas/rocblas.h>
-
+// Products with K, S and V (and their transposes, from copies transposed once
+// per call) run as fixed-order FP64 row products, one block per row or four;
+// the per-k commutator pullbacks run in the kernels below.  The factor
+// gradients are accumulated once per segment as sums of outer products over
+// its stage columns, in column order.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -379,21 +379,111 @@ __global__ void fill_zero_kernel(double* p, int64_t count) {
     p[i] = 0.0;
 }
 
-// out[j][i] = in[i][j] for in [rows][cols] row-major (32 x 32 tiles through LDS).
+// out[j][i] = in[i][j] for in [rows][cols] row-major with row stride ld
+// (32 x 32 tiles through LDS); out is [cols][rows].
 __global__ void __launch_bounds__(256) transpose_kernel(const double2* __restrict__ in, int64_t rows, int64_t cols,
-                                                        double2* __restrict__ out) {
+                                                        int64_t ld, double2* __restrict__ out) {
   __shared__ double2 tile[32][33];
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int q = ty; q < 32; q += 8) {
     const int64_t r = r0 + q, c = c0 + tx;
-    if (r < rows && c < cols) tile[q][tx] = in[r * cols + c];
+    if (r < rows && c < cols) tile[q][tx] = in[r * ld + c];
   }
   __syncthreads();
   for (int q = ty; q < 32; q += 8) {
     const int64_t c = c0 + q, r = r0 + tx;
     if (r < rows && c < cols) out[c * rows + r] = tile[tx][q];
   }
+}
+
+// C[b][i] = sum_j A[i][j] B[b][j], i < m, for every instance b: A row-major
+// [m][lda] complex128, B[b] at B + b k, C[b] at C + b m.  Block (g, b): R
+// consecutive rows, the 256 threads striding over the k columns; each row's
+// sum is reduced in a fixed order (wave sums, then the four waves in order).
+template <int R>
+__global__ void __launch_bounds__(256) rowdot_kernel(const double2* __restrict__ A, int64_t lda, int64_t m, int64_t k,
+                                                     const double2* __restrict__ B, double2* __restrict__ C) {
+  const int64_t i0 = (int64_t)blockIdx.x * R;
+  const int b = blockIdx.y, t = threadIdx.x;
+  const double2* x = B + (size_t)b * k;
+  double ar[R], ai[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ar[r] = ai[r] = 0.0;
+  for (int64_t j = t; j < k; j += 256) {
+    const double2 xv = x[j];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (i0 + r < m) {
+        const double2 a = A[(i0 + r) * lda + j];
+        ar[r] += a.x * xv.x - a.y * xv.y;
+        ai[r] += a.x * xv.y + a.y * xv.x;
+      }
+    }
+  }
+  __shared__ double red[4][2 * R];
+  const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    for (int off = 32; off > 0; off >>= 1) {
+      ar[r] += __shfl_down(ar[r], off, 64);
+      ai[r] += __shfl_down(ai[r], off, 64);
+    }
+    if (lane == 0) {
+      red[wave][2 * r] = ar[r];
+      red[wave][2 * r + 1] = ai[r];
+    }
+  }
+  __syncthreads();
+  if (t < R && i0 + t < m) {
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      sr += red[w][2 * t];
+      si += red[w][2 * t + 1];
+    }
+    C[(size_t)b * m + i0 + t] = make_double2(sr, si);
+  }
+}
+
+// out[i][j] += sum_{c < cols} a[c sa + i] b[c sb + j], i < mi, j < mj (complex
+// products, not conjugated; out row-major with row stride ldo).  A block owns a
+// 32 x 32 tile of out, each thread 2 x 2 of it, with 16 of the c at a time in
+// LDS; every element is summed over c in order.
+__global__ void __launch_bounds__(256) outer_acc_kernel(const double2* __restrict__ a, int64_t sa, int64_t mi,
+                                                        const double2* __restrict__ b, int64_t sb, int64_t mj,
+                                                        int64_t cols, double2* __restrict__ out, int64_t ldo) {
+  __shared__ double2 as[16][32], bs[16][32];
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  const int t = threadIdx.x, ti = t >> 4, tj = t & 15;
+  double2 acc[2][2];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) acc[u][v] = make_double2(0.0, 0.0);
+  for (int64_t c0 = 0; c0 < cols; c0 += 16) {
+    for (int q = t; q < 16 * 32; q += 256) {
+      const int cc = q >> 5, e = q & 31;
+      const int64_t c = c0 + cc;
+      as[cc][e] = (c < cols && i0 + e < mi) ? a[c * sa + i0 + e] : make_double2(0.0, 0.0);
+      bs[cc][e] = (c < cols && j0 + e < mj) ? b[c * sb + j0 + e] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int cc = 0; cc < 16; ++cc)
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          const double2 x = as[cc][ti + 16 * u], y = bs[cc][tj + 16 * v];
+          acc[u][v].x += x.x * y.x - x.y * y.y;
+          acc[u][v].y += x.x * y.y + x.y * y.x;
+        }
+    __syncthreads();
+  }
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      const int64_t i = i0 + ti + 16 * u, j = j0 + tj + 16 * v;
+      if (i < mi && j < mj) {
+        double2& o = out[i * ldo + j];
+        o.x += acc[u][v].x;
+        o.y += acc[u][v].y;
+      }
+    }
 }
 
 __global__ void conj_kernel(double2* p, int64_t count) {
@@ -476,10 +566,11 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
                o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
                o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)4 * batch * nk * sizeof(double)),
                o_df = cv.take((size_t)batch * 4 * sizeof(double)), o_f = cv.take((size_t)batch * sizeof(tdg_field));
-  // low rank, few instances: S transposed ([rank][n]) so that S^T conj(sbar) is a
-  // transposed matrix-vector product (rank output rows are too few to spread)
-  const bool use_ust = lowrank && batch <= 8;
-  const size_t o_ust = cv.take(use_ust ? (size_t)n * rank * sizeof(double2) : 0);
+  // transposed copies, so that every product is a row-major row product: S^T
+  // ([rank][n]) and V^H transposed ([n][rank]) for low rank, K^T for dense
+  const size_t o_ust = cv.take(lowrank ? (size_t)n * rank * sizeof(double2) : 0);
+  const size_t o_wt = cv.take(lowrank ? (size_t)n * rank * sizeof(double2) : 0);
+  const size_t o_kt = cv.take(lowrank ? 0 : (size_t)n * n * sizeof(double2));
   // intraband term: D of a stage state, of abar and of ybar
   const bool intra = model->links != nullptr;
   const size_t o_dy = cv.take(intra ? st_b : 0), o_da = cv.take(intra ? st_b : 0), o_dyb = cv.take(intra ? st_b : 0);
@@ -491,7 +582,9 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
           *YBAR = P2(o_ybar), *YD = P2(o_yd), *ACCA = P2(o_acca), *SS = P2(o_s), *XS = P2(o_x), *SBC = P2(o_sbc),
           *TT = P2(o_t), *ZS = P2(o_z), *UC = P2(o_uc);
   double2 *DY = intra ? P2(o_dy) : nullptr, *DA = intra ? P2(o_da) : nullptr, *DYB = intra ? P2(o_dyb) : nullptr;
-  double2* UST = use_ust ? P2(o_ust) : nullptr;
+  double2* UST = lowrank ? P2(o_ust) : nullptr;
+  double2* WT = lowrank ? P2(o_wt) : nullptr;
+  double2* KT = lowrank ? nullptr : P2(o_kt);
   double* part = (double*)(wb + o_part);
   double* dfacc = (double*)(wb + o_df);
   tdg_field* dfields = (tdg_field*)(wb + o_f);
@@ -513,52 +606,45 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   a.fields = dfields;
   a.kdiag = lowrank ? (const double2*)op->kdiag : nullptr;
 
-  rocblas_handle h = nullptr;
-  TDG_TRY(blas_handle(ctx, (void**)&h));
-  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-  auto gemm = [&](rocblas_operation ta, rocblas_operation tb, int64_t m_, int64_t n_, int64_t k_, const void* A,
-                  int64_t lda, const void* B, int64_t ldb, const rocblas_double_complex* beta, void* C,
-                  int64_t ldc) -> int {
-    const rocblas_status st =
-        rocblas_zgemm_64(h, ta, tb, m_, n_, k_, &one, (const rocblas_double_complex*)A, lda,
-                         (const rocblas_double_complex*)B, ldb, beta, (rocblas_double_complex*)C, ldc);
-    if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_zgemm status %d", (int)st);
-    return TDG_OK;
+  // C[b] = A B[b] for every instance (A row-major [m_][lda], B[b] of k_
+  // values, C[b] of m_): one fixed-order row product per row (four rows per
+  // block when there are many rows)
+  auto prod = [&](const double2* A, int64_t lda, int64_t m_, int64_t k_, const double2* B, double2* C) -> int {
+    if (m_ >= 1024)
+      hipLaunchKernelGGL(rowdot_kernel<4>, dim3((unsigned)((m_ + 3) / 4), (unsigned)batch), dim3(256), 0, ctx->stream,
+                         A, lda, m_, k_, B, C);
+    else
+      hipLaunchKernelGGL(rowdot_kernel<1>, dim3((unsigned)m_, (unsigned)batch), dim3(256), 0, ctx->stream, A, lda, m_,
+                         k_, B, C);
+    return launch_check(ctx, "adjoint product");
   };
-  const rocblas_operation NN = rocblas_operation_none, TR = rocblas_operation_transpose;
-  // C[:, b] = op(A) B[:, b] for every instance b (A column-major m_ x k_ with
-  // op = N, or k_ x m_ with op = T).  With few instances the product is a
-  // matrix-vector product per instance: one strided-batched GEMV sharing A
-  // (a GEMM tile of 64 columns would hold one useful column and stream all
-  // of K through two work-groups).
-  auto prod = [&](rocblas_operation ta, int64_t m_, int64_t k_, const void* A, int64_t lda, const void* B,
-                  void* C) -> int {
-    if (batch > 8) return gemm(ta, NN, m_, batch, k_, A, lda, B, k_, &zero, C, m_);
-    const bool tr = ta == TR;
-    const rocblas_status st = rocblas_zgemv_strided_batched_64(
-        h, ta, tr ? k_ : m_, tr ? m_ : k_, &one, (const rocblas_double_complex*)A, lda, 0,
-        (const rocblas_double_complex*)B, 1, k_, &zero, (rocblas_double_complex*)C, 1, m_, batch);
-    if (st != rocblas_status_success) return fail(ctx, TDG_E_SOLVER, "rocblas_zgemv status %d", (int)st);
-    return TDG_OK;
-  };
+  const double2* Kd = (const double2*)op->K;
+  const double2* USd = (const double2*)op->us;
+  const double2* Wd = (const double2*)op->w;
   // S = K X (dense) or Z = W X, S = US Z (low rank); K, W, US row-major
   auto apply_k = [&](const double2* X, double2* S, double2* Z) -> int {
-    if (!lowrank) return prod(TR, n, n, op->K, op->ld, X, S);
-    TDG_TRY(prod(TR, rank, n, op->w, n, X, Z));
-    return prod(TR, n, rank, op->us, rank, Z, S);
+    if (!lowrank) return prod(Kd, op->ld, n, n, X, S);
+    TDG_TRY(prod(Wd, n, rank, n, X, Z));
+    return prod(USd, rank, n, rank, Z, S);
   };
   // T with K^H sbar = conj(T) (+ K_diag term in the kernel): T = K^T conj(sbar), or
   // Uc = US^T conj(sbar) = conj(US^H sbar), T = W^T Uc
   auto apply_kh = [&](const double2* Sbc, double2* Uc) -> int {
-    if (!lowrank) return prod(NN, n, n, op->K, op->ld, Sbc, TT);
-    TDG_TRY(use_ust ? prod(TR, rank, n, UST, n, Sbc, Uc) : prod(NN, rank, n, op->us, rank, Sbc, Uc));
-    return prod(NN, n, rank, op->w, n, Uc, TT);
+    if (!lowrank) return prod(KT, n, n, n, Sbc, TT);
+    TDG_TRY(prod(UST, n, rank, n, Sbc, Uc));
+    return prod(WT, rank, n, rank, Uc, TT);
   };
-  if (use_ust) {
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((rank + 31) / 32), (unsigned)((n + 31) / 32)), dim3(256), 0,
-                       ctx->stream, (const double2*)op->us, n, rank, UST);
-    TDG_TRY(launch_check(ctx, "transpose launch"));
+  auto transpose = [&](const double2* in, int64_t rows, int64_t cols, int64_t ld, double2* o) {
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)), dim3(256), 0,
+                       ctx->stream, in, rows, cols, ld, o);
+  };
+  if (lowrank) {
+    transpose(USd, n, rank, rank, UST);
+    transpose(Wd, rank, n, n, WT);
+  } else {
+    transpose(Kd, n, n, op->ld, KT);
   }
+  TDG_TRY(launch_check(ctx, "transpose launch"));
 
   const int kpb = AT / nb2;
   const dim3 grid((unsigned)((nk + kpb - 1) / kpb), (unsigned)batch);
@@ -646,10 +732,18 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
       TDG_TRY(launch_check(ctx, "adjoint backward step"));
     }
     if (lowrank && (out->dus || out->dw)) {
-      // conj(dL/dS)^T += Z Sbc^T and conj(dL/dV^H)^T += X Uc^T over the segment's stage columns
+      // conj(dL/dS)[i][j] += sum_c Sbc_c[i] Z_c[j] and conj(dL/dV^H)[j][i] += sum_c Uc_c[j] X_c[i]
+      // over the segment's stage columns c
       const int64_t cols = (int64_t)(end - start) * 4 * batch;
-      if (out->dus) TDG_TRY(gemm(NN, TR, rank, n, cols, ZS, rank, SBC, n, &one, out->dus, rank));
-      if (out->dw) TDG_TRY(gemm(NN, TR, n, rank, cols, XS, n, UC, rank, &one, out->dw, n));
+      if (out->dus)
+        hipLaunchKernelGGL(outer_acc_kernel, dim3((unsigned)((rank + 31) / 32), (unsigned)((n + 31) / 32)),
+                           dim3(256), 0, ctx->stream, (const double2*)SBC, n, n, (const double2*)ZS, rank, rank, cols,
+                           (double2*)out->dus, rank);
+      if (out->dw)
+        hipLaunchKernelGGL(outer_acc_kernel, dim3((unsigned)((n + 31) / 32), (unsigned)((rank + 31) / 32)),
+                           dim3(256), 0, ctx->stream, (const double2*)UC, rank, rank, (const double2*)XS, n, n, cols,
+                           (double2*)out->dw, n);
+      TDG_TRY(launch_check(ctx, "factor gradient launch"));
     }
   }
 
