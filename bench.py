@@ -136,8 +136,6 @@ def algorithmic_bytes(kind, n, r, nk, nb, elt=8):
         return n * n * elt + 2 * n * elt + state_bytes(nk, nb)
     if kind == "lowrank_stage":    # S rows, z, K_diag, drho in, drho out, state
         return n * r * elt + r * elt + 3 * n * elt + state_bytes(nk, nb)
-    if kind == "lowrank_fused_stage":  # S rows and V^H columns of k, z in and out, K_diag, drho in and out, state
-        return 2 * n * r * elt + 2 * r * elt + 3 * n * elt + state_bytes(nk, nb)
     if kind == "project":          # V^H rows, drho in, z out
         return r * n * elt + n * elt + r * elt
     raise ValueError(kind)
@@ -350,8 +348,7 @@ def main():
     # dominant kernel of the low-rank path and the dense stage kernel
     lp = out["lowrank"]["prof"]
     dom = "stage" if lp["stage"][0] >= lp["project"][0] else "project"
-    fused = "fused" in out["lowrank"]["variant"]
-    dom_kind = ("lowrank_fused_stage" if fused else "lowrank_stage") if dom == "stage" else "project"
+    dom_kind = "lowrank_stage" if dom == "stage" else "project"
     dom_avg_s = lp[dom][0] / lp[dom][1] * 1e-3
     dom_bytes = algorithmic_bytes(dom_kind, n, r, nk, nb)
     dense_avg_s = out["dense"]["prof"]["stage"][0] / out["dense"]["prof"]["stage"][1] * 1e-3
@@ -432,7 +429,7 @@ def main():
         "speedup_lowrank_vs_dense": value / dense_value,
         "runs": {name: {"steps_per_s": [args.steps / t for t in out[name]["runs"]],
                         "median_steps_per_s": float(np.median([args.steps / t for t in out[name]["runs"]]))}
-                 for name in out},
+                 for name in out if "runs" in out[name]},
         "dense_single_instance_60x60": dense_hbm,
         "channelwise": channelwise,
         "intraband": intraband,
@@ -440,8 +437,8 @@ def main():
         "compress_seconds": compress_s,
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"stage_kernel<float, {3 if fused else 1}, ...> ({out['lowrank']['variant']})"
-                       if dom == "stage" else "project_kernel<float>"),
+            "kernel": (f"stage_kernel<float, 1, ...> ({out['lowrank']['variant']})" if dom == "stage"
+                       else "project_kernel<float>"),
             "achieved": dom_bytes / dom_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom_bytes / dom_avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
             "avg_launch_us": dom_avg_s * 1e6, "bytes_per_launch": dom_bytes,
@@ -524,6 +521,12 @@ def batched_sweep(P, abi, ctx, frac, steps=0, cache=None, bf16x2=True):
     def bf16x2_factors():
         # split-precision factors of the same rank from the randomized range
         # finder (l = r + 128 test vectors, 2 power iterations)
+        bcache = cache + ".bf16x2.npz" if cache else None
+        if bcache and os.path.exists(bcache):
+            z = np.load(bcache)
+            t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+            return P.LowRankFactors(t(z["kdiag"]), t(z["us"]), t(z["w"]), z["sigma"], int(z["rank"]), 0.0, 0.0,
+                                    "bf16x2")
         g = torch.Generator(device=f"cuda:{ctx.device}")
         g.manual_seed(2027)
         om = (torch.randn(r + 128, n, dtype=torch.float64, device=K.device, generator=g)
@@ -531,6 +534,9 @@ def batched_sweep(P, abi, ctx, frac, steps=0, cache=None, bf16x2=True):
         out = ctx.kernel_compress_randomized(K, om, "rank", r, power_iters=2, out_dtype="bf16x2")
         del om
         torch.cuda.empty_cache()
+        if bcache:
+            np.savez(bcache, kdiag=out.kdiag.cpu().numpy(), us=out.us.cpu().numpy(), w=out.w.cpu().numpy(),
+                     sigma=out.sigma, rank=out.rank)
         return out
 
     legs = [("dense", lambda: K), ("lowrank", lambda: fac)]

@@ -375,8 +375,9 @@ typedef struct {
  * intraband term is differentiated too (its covariant difference is
  * anti-self-adjoint).  Device workspace about (nsteps / M + 4 M + 12) states
  * plus 12 M x n x batch complex128 values (without the stash: nsteps / M +
- * M + 15 states plus 4 (M for low rank) x 2 x n x batch values), held by the
- * context.  Synchronises the stream. */
+ * M + 15 states plus 4 (M for low rank) x 2 x n x batch values), and a
+ * transposed copy of the operator (n x n dense, 2 x n x rank low rank), held
+ * by the context.  Synchronises the stream. */
 int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
                           const tdg_field* fields, int32_t batch, double dt, const void* rho0,
                           int32_t checkpoint_every, const tdg_obs_grad* g, tdg_grads* out);
@@ -426,7 +427,9 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * keeps for the context the first pair (default split first) within 2 % of the
  * fastest.  FP32 tilings: 0 = 64-row tiles, 1 = 64-row tiles with the next K
  * tile prefetched into registers and two LDS buffers, 2 = 128-row tiles;
- * BF16X2 tilings 0 and 1 (see TDG_BF16X2).  A value >= 0 forces that tiling
+ * BF16X2 tilings 0 = 64-row tiles splitting X while staged, 1 = 128-row
+ * tiles on X split once per product, 2 = 256-row tiles on X split once, both
+ * operands copied straight to LDS three stages deep.  A value >= 0 forces that tiling
  * with the default split (or the one TDG_OPT_GEMM_SLICES gives).  Tilings and
  * splits differ only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects
  * 0 / 2. */

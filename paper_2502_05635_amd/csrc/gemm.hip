@@ -748,6 +748,138 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
     }
 }
 
+// ---- BF16 split-precision product, third tiling ----------------------------
+// 256 rows x 64 instances per block; wave w owns rows 64 w .. +63 and all 128
+// real columns as 2 x 4 MFMA accumulators, so a fragment read from LDS feeds
+// two (X) or four (A) products.  A (both planes) and the expanded X (as for
+// the second tiling) are copied straight into LDS by 16-byte direct-to-LDS
+// loads, into a ring of three stages of 16 complex K: the loads of the next
+// two stages are in flight while one is multiplied, with no registers held.
+// In a stage, row r of a plane is 4 chunks of 8 bf16 (64 bytes); chunk c sits
+// at slot c ^ ((r / 2) % 4), so the 32 rows of a fragment read spread over
+// all banks.  Rows past M read row M - 1 and K past the product reads chunk
+// 0 of the row: both multiply zeros of X or land in outputs never stored
+// (X is zero from K = Kc on, and the row's own columns Kc .. lda - 1 are).
+constexpr int BM4 = 256;
+constexpr int KR4 = 32;                          // real K per stage
+constexpr int ST4 = 3;                           // stages in the ring
+constexpr int A4_BYTES = 2 * BM4 * KR4 * 2;      // both planes of a stage
+constexpr int X4_BYTES = 2 * XB_ROWS * KR4 * 2;
+// s_waitcnt immediate with vmcnt = n (gfx9 encoding: bits 3:0 and 15:14),
+// expcnt and lgkmcnt at their maxima (no wait)
+constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
+
+typedef __attribute__((address_space(1))) void gsrc_t;
+typedef __attribute__((address_space(3))) void ldst_t;
+
+__device__ inline int swz(int row, int c) { return c ^ ((row >> 1) & 3); }
+
+__global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, const unsigned short* __restrict__ XB,
+                                                             int64_t ldxb) {
+  __shared__ __align__(16) unsigned char lds[ST4 * (A4_BYTES + X4_BYTES)];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.x * BM4, ct = blockIdx.y, b0 = ct * BNI, s = blockIdx.z;
+  const int kc_begin = s * g.kslice;
+  const int kc_end = min(g.Kc, kc_begin + g.kslice);
+  const int nst = (kc_end - kc_begin + KR4 / 2 - 1) / (KR4 / 2);
+  const int64_t row_bf = 2 * g.lda;  // bf16 per row of a plane (columns Kc .. lda - 1 hold zeros)
+
+  // issue the direct-to-LDS copies of stage `st` (K from kc0) into ring slot q:
+  // wave w copies A rows 16 (8 w + j) .. +15 of plane (8 w + j) / 16 ... (8 per
+  // wave) and X rows (4 per wave); lane l fills slot l % 4 of row l / 4
+  auto issue = [&](int st, int q) {
+    const int kr0 = 2 * (kc_begin + st * (KR4 / 2));
+    unsigned char* abase = lds + q * (A4_BYTES + X4_BYTES);
+    unsigned char* xbase = abase + A4_BYTES;
+    const int rl = lane >> 2, sl = lane & 3;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int ins = w * 8 + j, p = ins >> 4, row = 16 * (ins & 15) + rl;
+      const int gi = min(m0 + row, g.M - 1);
+      int kr = kr0 + 8 * swz(row, sl);
+      if (kr + 8 > row_bf) kr = 0;  // past the row: any finite chunk (X is zero there)
+      const unsigned short* src = (p ? g.Alo : g.Ahi) + (int64_t)gi * row_bf + kr;
+      __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(abase + (p * BM4 + 16 * (ins & 15)) * 64), 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int ins = w * 4 + j, p = ins >> 3, row = 16 * (ins & 7) + rl;
+      const unsigned short* src =
+          XB + ((int64_t)(ct * 2 + p) * XB_ROWS + row) * ldxb + kr0 + 8 * swz(row, sl);
+      __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(xbase + (p * XB_ROWS + 16 * (ins & 7)) * 64), 16, 0, 0);
+    }
+  };
+
+  floatx16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  if (nst > 0) issue(0, 0);
+  if (nst > 1) issue(1, 1);
+  for (int st = 0; st < nst; ++st) {
+    // this wave's copies of stage st have landed (those of st + 1 may not);
+    // the barrier makes every wave's copies visible and frees slot (st + 2) % 3
+    if (st + 1 < nst)
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(12));
+    else
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    // a plain barrier: the waits above are the only ones the copies need (a
+    // __syncthreads fence would also wait for the next stage's copies)
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(63) & ~0x0F00);  // lgkmcnt(0): this wave's LDS reads are done
+    __builtin_amdgcn_s_barrier();
+    if (st + 2 < nst) issue(st + 2, (st + 2) % ST4);
+    const unsigned char* abase = lds + (st % ST4) * (A4_BYTES + X4_BYTES);
+    const unsigned char* xbase = abase + A4_BYTES;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int c = 2 * ks + (lane >> 5);
+      bf16x8 ah[2], al[2], xh[4], xl[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = 64 * w + 32 * i + (lane & 31);
+        const int off = (row * 4 + swz(row, c)) * 16;
+        ah[i] = *reinterpret_cast<const bf16x8*>(abase + off);
+        al[i] = *reinterpret_cast<const bf16x8*>(abase + BM4 * 64 + off);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 32 * j + (lane & 31);
+        const int off = (row * 4 + swz(row, c)) * 16;
+        xh[j] = *reinterpret_cast<const bf16x8*>(xbase + off);
+        xl[j] = *reinterpret_cast<const bf16x8*>(xbase + XB_ROWS * 64 + off);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], xh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], xl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], xh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+
+  // real column 32 j + lane % 32: instance 32 (j % 2) + lane % 32, part j / 2
+  float* Yf = reinterpret_cast<float*>(g.Y + s * g.y_slice_stride);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = m0 + 64 * w + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (row >= g.M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int b = b0 + 32 * (j & 1) + (lane & 31);
+        if (b < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b) + (j >> 1)] = acc[i][j][r];
+      }
+    }
+}
+
 // dst (TDG_BF16X2, [rows][ld_dst]) <- src complex (float or double, [rows][ld_src]);
 // columns cols .. ld_dst-1 of dst are zero-filled.
 template <typename S>
@@ -797,11 +929,16 @@ void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc,
   g.ncols = ncols;
   g.kslice = kslice;
   const int splits = (Kc + kslice - 1) / kslice;
-  if (variant == 1 && work) {
+  if ((variant == 1 || variant == 2) && work) {
     const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
     const int tiles = (ncols + BNI - 1) / BNI;
     hipLaunchKernelGGL(expand_bf16x2_kernel, dim3((unsigned)(ldxb / 64), (unsigned)tiles), dim3(256), 0, stream,
                        (const float2*)X, ldx, Kc, ncols, (unsigned short*)work, ldxb);
+    if (variant == 2) {
+      const dim3 grid((M + BM4 - 1) / BM4, tiles, splits);
+      hipLaunchKernelGGL(cgemm_bf16x2_mfma_v3, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
+      return;
+    }
     const dim3 grid((M + BM3 - 1) / BM3, tiles, splits);
     hipLaunchKernelGGL(cgemm_bf16x2_mfma_v2, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
     return;

@@ -42,11 +42,6 @@ enum WsSlot {
   WS_INTRA,      // intraband term: covariant derivative of the stage state, c128 like the state
   WS_RHO_S2,     // intraband term, per-instance path: second stage-state buffer (stages alternate)
   WS_FTAB,       // field at the stage times of a chunk of steps, double [chunk][B][4]
-  WS_VT,         // fused projection: V^H transposed [N][rank]
-  WS_ZPART,      // fused projection: per-k partials [B][nk][rank]
-  WS_GSUM,       // fused projection: group sums, c128 [B][groups][rank]
-  WS_CNT,        // fused projection: arrival counters [B][groups + 1]
-  WS_ZF,         // fused projection: the projection of the current and next gather [2][B][rank]
   WS_COUNT
 };
 

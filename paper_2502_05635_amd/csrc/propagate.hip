@@ -45,7 +45,6 @@ constexpr int THREADS = 256;  // dense stage kernel and auxiliary kernels
 constexpr int NB2_MAX = TDG_NB_MAX * TDG_NB_MAX;
 constexpr int ROWS = 4;  // kernel rows contracted together (shared drho loads)
 constexpr int ZSPLIT_MAX = 4;  // low rank: largest number of projection column slices
-constexpr int FUSED_RMAX = 512;  // fused projection: largest rank (its V^H columns are held in LDS)
 constexpr int PROJ_THREADS = 256;
 constexpr size_t OBS_PART_BUDGET = size_t(64) << 20;
 
@@ -287,16 +286,6 @@ struct StageParams {
   double cov_c1, cov_c2;  // 1 / (2 |b_a|) per grid axis
   int tr_signed;          // per-k trace partial signed (summed over k) instead of |.| (maximised)
   const double* ftab;     // field at the stage times, [obs slot][B][4] (field_table_kernel)
-  // low rank with the projection fused into the stage kernel (MODE 3): z of
-  // the next stage from the gather this kernel writes, by per-k partials and
-  // a two-level fixed-order reduction done by the last block of each k group
-  // and then by the last group
-  const void* vt;         // V^H transposed, [N][ncols] (rows k P .. k P + P - 1 contiguous)
-  void* zpart;            // per-k partials [B][nk][ncols]
-  double2* gsum;          // group sums [B][ngroups][ncols]
-  unsigned* cnt;          // arrival counters [B][ngroups + 1], zero between launches
-  void* znext;            // projection of the next gather [B][vstride]
-  int kgroup, ngroups;    // k points per group, number of groups
 };
 
 // Per-k observables of s_rho (LDS) into obs_part; de, ve are this thread's
@@ -348,7 +337,7 @@ template <typename T, int MODE, int NT, int U, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 stage_kernel(StageParams sp) {
   using C = typename Cx<T>::type;
-  constexpr bool FUSED = MODE == 3, LOWRANK = MODE == 1 || FUSED, CHANNEL = MODE == 2;
+  constexpr bool LOWRANK = MODE == 1, CHANNEL = MODE == 2;
   constexpr int WAVES = NT / 64;
   const int k = blockIdx.x, b = blockIdx.y;
   const bool dyn = b < sp.n_dyn;
@@ -365,24 +354,6 @@ stage_kernel(StageParams sp) {
   // intraband term: entry (4 a + w) nb^2 + e holds element e of, for axis a,
   // w = 0: y(k + b_a), 1: y(k - b_a), 2: L_a(k), 3: L_a(k - b_a)
   __shared__ __align__(16) double2 s_cov[8 * NB2_MAX];
-  // fused projection: this k point's V^H columns, [p][j] = V^H[j][k P + p],
-  // and the next gather of its pairs
-  __shared__ __align__(16) C s_vt[FUSED ? ROWS * FUSED_RMAX : 1];
-  __shared__ C s_xn[ROWS];
-  __shared__ int s_last;
-  if (FUSED && dyn) {
-    // the P rows of V^H transposed are one contiguous run of P ncols elements:
-    // 16-byte direct-to-LDS copies issued now, waited for after the epilogue
-    const int pieces = (int)((size_t)P * sp.ncols * sizeof(C) / 16);
-    const char* src = reinterpret_cast<const char*>(sp.vt) + (size_t)k * P * sp.ncols * sizeof(C);
-    const int wave = t >> 6, lane = t & 63;
-    for (int c0 = wave * 64; c0 < pieces; c0 += NT) {
-      const int i = c0 + lane;
-      if (i < pieces)
-        __builtin_amdgcn_global_load_lds((lds_dma_src*)(src + (size_t)i * 16),
-                                         (lds_dma_dst*)(reinterpret_cast<char*>(s_vt) + (size_t)c0 * 16), 16, 0, 0);
-    }
-  }
 
   // ---- loads: the low-rank kernel issues every load of the block before any
   // use (its lifetime is latency-bound); the dense kernel loads the per-k
@@ -522,11 +493,8 @@ stage_kernel(StageParams sp) {
     load_state();
     load_field();
   }
-  // the per-k epilogue runs in the first wave (nb^2 <= 64 elements, P <= 64 pairs);
-  // with the fused projection the other waves of an integrating block wait
-  // for it below (dyn is uniform over the block)
-  if (t >= 64 && (!FUSED || !dyn)) return;
-  if (t < 64) {
+  // the per-k epilogue runs in the first wave (nb^2 <= 64 elements, P <= 64 pairs)
+  if (t >= 64) return;
   // the direct-to-LDS copies of the intraband neighbours have landed once
   // this wave's vector memory counter is zero
   if (sp.links && dyn) __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
@@ -619,75 +587,8 @@ stage_kernel(StageParams sp) {
       xv.y = (T)next.y;
       reinterpret_cast<C*>(sp.xnext)[(size_t)b * sp.xstride + (CHANNEL ? (size_t)p * sp.nk + k : (size_t)k * P + p)] =
           xv;
-      if (FUSED) s_xn[p] = xv;
     }
   }
-  }  // first wave
-  if (!FUSED) return;
-
-  // ---- fused projection of the next gather: z_j = sum_i V^H[j][i] x_i -------
-  __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);  // this wave's V^H copies have landed
-  __syncthreads();
-  const int nc = sp.ncols;
-  C* zp = reinterpret_cast<C*>(sp.zpart) + ((size_t)b * sp.nk + k) * nc;
-  for (int j = t; j < nc; j += NT) {
-    T pr = (T)0, pi = (T)0;
-    for (int p = 0; p < P; ++p) {
-      const C w = s_vt[p * nc + j], x = s_xn[p];
-      pr += w.x * x.x - w.y * x.y;
-      pi += w.x * x.y + w.y * x.x;
-    }
-    C v;
-    v.x = pr;
-    v.y = pi;
-    zp[j] = v;
-  }
-  // the last block of a group of kgroup k points sums the group's partials in
-  // k order; the last group sums the group sums in group order
-  unsigned* cnt = sp.cnt + (size_t)b * (sp.ngroups + 1);
-  const int g = k / sp.kgroup, g0 = g * sp.kgroup, gn = min(sp.kgroup, sp.nk - g0);
-  __syncthreads();
-  if (t == 0) {
-    __threadfence();
-    s_last = atomicAdd(cnt + g, 1u) == (unsigned)(gn - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const C* zg = reinterpret_cast<const C*>(sp.zpart) + ((size_t)b * sp.nk + g0) * nc;
-  double2* gs = sp.gsum + (size_t)b * sp.ngroups * nc;
-  for (int j = t; j < nc; j += NT) {
-    double sr = 0.0, si = 0.0;
-    for (int q = 0; q < gn; ++q) {
-      const C v = zg[(size_t)q * nc + j];
-      sr += (double)v.x;
-      si += (double)v.y;
-    }
-    gs[(size_t)g * nc + j] = make_double2(sr, si);
-  }
-  __syncthreads();
-  if (t == 0) {
-    __threadfence();
-    s_last = atomicAdd(cnt + sp.ngroups, 1u) == (unsigned)(sp.ngroups - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  C* zn = reinterpret_cast<C*>(sp.znext) + (size_t)b * sp.vstride;
-  for (int j = t; j < nc; j += NT) {
-    double sr = 0.0, si = 0.0;
-    for (int q = 0; q < sp.ngroups; ++q) {
-      const double2 v = gs[(size_t)q * nc + j];
-      sr += v.x;
-      si += v.y;
-    }
-    C v;
-    v.x = (T)sr;
-    v.y = (T)si;
-    zn[j] = v;
-  }
-  // every block of this instance has arrived: the counters start at zero again
-  for (int i = t; i <= sp.ngroups; i += NT) cnt[i] = 0u;
 }
 
 // Low-rank projection z_j = sum_i W[j][i] x_i (W = V^H): block (g, q, b) takes
@@ -765,36 +666,6 @@ __global__ void finish_kernel(const double2* __restrict__ rho_n, const int* __re
   const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
   if (t >= nb2) return;
   rho_out[((size_t)perm[b] * nk + k) * nb2 + t] = rho_n[((size_t)b * nk + k) * nb2 + t];
-}
-
-// vt = transpose of V^H (rank rows of n) for the fused projection: 32 x 32
-// tiles through LDS, both sides coalesced.
-template <typename T>
-__global__ void __launch_bounds__(256) transpose_vh_kernel(const void* __restrict__ w, int64_t n, int rank,
-                                                           void* __restrict__ vt) {
-  using C = typename Cx<T>::type;
-  __shared__ C tile[32][33];
-  const int64_t i0 = (int64_t)blockIdx.x * 32;
-  const int j0 = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const C* src = reinterpret_cast<const C*>(w);
-  C* dst = reinterpret_cast<C*>(vt);
-  for (int r = ty; r < 32; r += 8) {
-    const int j = j0 + r;
-    const int64_t i = i0 + tx;
-    if (j < rank && i < n) tile[r][tx] = src[(size_t)j * n + i];
-  }
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t i = i0 + r;
-    const int j = j0 + tx;
-    if (i < n && j < rank) dst[(size_t)i * rank + j] = tile[tx][r];
-  }
-}
-
-__global__ void __launch_bounds__(256) zero_u32_kernel(unsigned* p, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < count) p[i] = 0u;
 }
 
 // Hermiticity residual of a caller's rho(0): thread i takes the (instance,
@@ -901,6 +772,27 @@ __device__ inline size_t bidx(const BatchParams& bp, int k, int e, int b) {
   return ((size_t)k * bp.nb * bp.nb + e) * bp.ldx + b;
 }
 
+// Packed Hermitian state (batched path without the intraband term): rho(t_n),
+// the stage state and the RK4 sum of stage derivatives are Hermitian, so only
+// the nb (nb - 1) / 2 elements above the diagonal are kept, as double2
+// [k][u][ldx] with u the row-major index of (n, m), n < m, followed (after nk
+// U ldx double2) by the nb real diagonal elements as double [k][n][ldx]: half
+// the bytes of the full matrices.
+__device__ inline int upper_slot(int n, int m, int nb) { return n * nb - n * (n + 1) / 2 + (m - n - 1); }
+__device__ inline double2 pk_get(const double2* A, int nk, int nb, int64_t ldx, int k, int n, int m, int b) {
+  const int U = nb * (nb - 1) / 2;
+  if (m == n)
+    return make_double2(reinterpret_cast<const double*>(A + (size_t)nk * U * ldx)[((size_t)k * nb + n) * ldx + b], 0.0);
+  return A[((size_t)k * U + upper_slot(n, m, nb)) * ldx + b];
+}
+__device__ inline void pk_put(double2* A, int nk, int nb, int64_t ldx, int k, int n, int m, int b, double2 v) {
+  const int U = nb * (nb - 1) / 2;
+  if (m == n)
+    reinterpret_cast<double*>(A + (size_t)nk * U * ldx)[((size_t)k * nb + n) * ldx + b] = v.x;
+  else
+    A[((size_t)k * U + upper_slot(n, m, nb)) * ldx + b] = v;
+}
+
 // One block per (k point, group of IB instances): thread t has lane i = t % IB
 // (instance group * IB + i) and row n = t / IB, and owns the row's elements
 // (n, m), m = 0 .. nb-1.  The instances' H and rho blocks are staged in LDS as
@@ -909,7 +801,7 @@ __device__ inline size_t bidx(const BatchParams& bp, int k, int e, int b) {
 // NBT: a bound on nb (4 or TDG_NB_MAX) sizing the per-thread row arrays.  The
 // observable sums [5][nb][IB] share the H blocks' LDS when they fit (nb >= 3):
 // they are consumed before H is built; otherwise they follow the H blocks.
-template <int NBT>
+template <int NBT, bool PACK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBT <= 4 ? 3 : 1, 8)))
 batched_stage_kernel(BatchParams bp) {
   extern __shared__ double2 dyn_lds[];
@@ -955,12 +847,13 @@ batched_stage_kernel(BatchParams bp) {
     prow[m] = -1;
     partner[m] = false;
     if (m >= nb || !act) continue;
+    if (PACK && m < n) continue;  // elements below the diagonal: conjugates of those above
     const size_t g = bidx(bp, k, n * nb + m, b);
-    rs[m] = bp.rho_s[g];
+    rs[m] = PACK ? pk_get(bp.rho_s, bp.nk, nb, bp.ldx, k, n, m, b) : bp.rho_s[g];
     if (!dyn) continue;
-    r_n[m] = bp.rho_n[g];
-    if (bp.stage != 0) r_acc[m] = bp.acc[g];
-    if (bp.intra) dv[m] = bp.intra[g];
+    r_n[m] = PACK ? pk_get(bp.rho_n, bp.nk, nb, bp.ldx, k, n, m, b) : bp.rho_n[g];
+    if (bp.stage != 0) r_acc[m] = PACK ? pk_get(bp.acc, bp.nk, nb, bp.ldx, k, n, m, b) : bp.acc[g];
+    if (!PACK && bp.intra) dv[m] = bp.intra[g];
     int p = -1;
     if (bp.block == TDG_BLOCK_ALL) {
       p = n * nb + m;
@@ -1012,7 +905,10 @@ batched_stage_kernel(BatchParams bp) {
       }
       ds[m] = make_double2((double)zr, partner[m] ? -(double)zi : (double)zi);
     }
-    if (m < nb) s_rho[(n * nb + m) * IB + i] = rs[m];
+    if (m < nb && (!PACK || m >= n)) {
+      s_rho[(n * nb + m) * IB + i] = rs[m];
+      if (PACK && m > n) s_rho[(m * nb + n) * IB + i] = make_double2(rs[m].x, -rs[m].y);
+    }
   }
   __syncthreads();
 
@@ -1063,11 +959,14 @@ batched_stage_kernel(BatchParams bp) {
 #pragma unroll
     for (int m = 0; m < NBT; ++m) {
       if (m >= nb) break;
+      if (PACK && m < n) continue;
       const int e = n * nb + m;
       const double2 de = proj_e(F, s_d[e], s_d[nb2 + e]);
       double2 h = make_double2(ds[m].x - ef * de.x, ds[m].y - ef * de.y);
       if (n == m) h.x += s_eps[n];
+      if (PACK && n == m) h.y = 0.0;  // Hermitian: a real diagonal
       s_h[e * IB + i] = h;
+      if (PACK && m > n) s_h[(m * nb + n) * IB + i] = make_double2(h.x, -h.y);
     }
   }
   __syncthreads();
@@ -1077,6 +976,7 @@ batched_stage_kernel(BatchParams bp) {
 #pragma unroll
   for (int m = 0; m < NBT; ++m) {
     if (m >= nb) break;
+    if (PACK && m < n) continue;
     const int e = n * nb + m;
     double2 c = make_double2(0.0, 0.0);
     for (int l = 0; l < nb; ++l) {
@@ -1086,36 +986,45 @@ batched_stage_kernel(BatchParams bp) {
       c.y += hr.y - rh.y;
     }
     double2 f = make_double2(c.y, -c.x);
+    if (PACK && n == m) f.y = 0.0;  // the derivative of a Hermitian state is Hermitian
     const size_t g = bidx(bp, k, e, b);
-    if (bp.intra) {
+    if (!PACK && bp.intra) {
       // intraband part of the field term: -E(t) e.(rho)_{;k}
       f.x -= ef * dv[m].x;
       f.y -= ef * dv[m].y;
     }
-    double2 next;
+    double2 next, accv = f;
     if (bp.stage == 0) {
-      bp.acc[g] = f;
       next = make_double2(r_n[m].x + 0.5 * bp.dt * f.x, r_n[m].y + 0.5 * bp.dt * f.y);
     } else if (bp.stage == 1) {
-      bp.acc[g] = make_double2(r_acc[m].x + 2.0 * f.x, r_acc[m].y + 2.0 * f.y);
+      accv = make_double2(r_acc[m].x + 2.0 * f.x, r_acc[m].y + 2.0 * f.y);
       next = make_double2(r_n[m].x + 0.5 * bp.dt * f.x, r_n[m].y + 0.5 * bp.dt * f.y);
     } else if (bp.stage == 2) {
-      bp.acc[g] = make_double2(r_acc[m].x + 2.0 * f.x, r_acc[m].y + 2.0 * f.y);
+      accv = make_double2(r_acc[m].x + 2.0 * f.x, r_acc[m].y + 2.0 * f.y);
       next = make_double2(r_n[m].x + bp.dt * f.x, r_n[m].y + bp.dt * f.y);
     } else {
       const double w = bp.dt / 6.0;
       next = make_double2(r_n[m].x + w * (r_acc[m].x + f.x), r_n[m].y + w * (r_acc[m].y + f.y));
-      bp.rho_n[g] = next;
     }
-    bp.rho_s[g] = next;
-    int p = -1;
-    if (bp.block == TDG_BLOCK_ALL)
-      p = e;
-    else if (n >= bp.nv && m < bp.nv)
-      p = (n - bp.nv) * bp.nv + m;
-    if (p >= 0) {
-      const double dre = next.x - ((n == m && n < bp.nv) ? 1.0 : 0.0);
-      bp.xnext[((size_t)k * P + p) * bp.ldx + b] = make_float2((float)dre, (float)next.y);
+    if (PACK) {
+      if (bp.stage < 3) pk_put(bp.acc, bp.nk, nb, bp.ldx, k, n, m, b, accv);
+      if (bp.stage == 3) pk_put(bp.rho_n, bp.nk, nb, bp.ldx, k, n, m, b, next);
+      pk_put(bp.rho_s, bp.nk, nb, bp.ldx, k, n, m, b, next);
+    } else {
+      if (bp.stage < 3) bp.acc[g] = accv;
+      if (bp.stage == 3) bp.rho_n[g] = next;
+      bp.rho_s[g] = next;
+    }
+    const double dre = next.x - ((n == m && n < bp.nv) ? 1.0 : 0.0);
+    if (bp.block == TDG_BLOCK_ALL) {
+      bp.xnext[((size_t)k * P + e) * bp.ldx + b] = make_float2((float)dre, (float)next.y);
+      if (PACK && m > n)  // the pair below the diagonal: conj of this one
+        bp.xnext[((size_t)k * P + m * nb + n) * bp.ldx + b] = make_float2((float)dre, -(float)next.y);
+    } else if (!PACK && n >= bp.nv && m < bp.nv) {
+      bp.xnext[((size_t)k * P + (n - bp.nv) * bp.nv + m) * bp.ldx + b] = make_float2((float)dre, (float)next.y);
+    } else if (PACK && n < bp.nv && m >= bp.nv) {
+      // conduction-valence pair (m, n) from its partner above the diagonal
+      bp.xnext[((size_t)k * P + (m - bp.nv) * bp.nv + n) * bp.ldx + b] = make_float2((float)dre, -(float)next.y);
     }
   }
 }
@@ -1124,15 +1033,28 @@ batched_stage_kernel(BatchParams bp) {
 // position) at k to [(k nb^2 + e) ldx + b]; drho gather [N][ldx].  One block per k.
 __global__ void init_batched_kernel(const double2* __restrict__ rho_in, const int* __restrict__ perm, double2* rho_n,
                                     double2* rho_s, float2* x, int64_t ldx, int nk, int nb, int nv, int npair,
-                                    int block, int init_eq, int batch) {
+                                    int block, int init_eq, int batch, int pack) {
   const int k = blockIdx.x, nb2 = nb * nb;
   for (int idx = threadIdx.x; idx < nb2 * batch; idx += blockDim.x) {
     const int e = idx / batch, b = idx % batch, n = e / nb, m = e % nb;
     const double occ = (n == m && n < nv) ? 1.0 : 0.0;
-    const double2 r = init_eq ? make_double2(occ, 0.0) : rho_in[((size_t)perm[b] * nk + k) * nb2 + e];
-    const size_t g = ((size_t)k * nb2 + e) * ldx + b;
-    rho_n[g] = r;
-    rho_s[g] = r;
+    double2 r = init_eq ? make_double2(occ, 0.0) : rho_in[((size_t)perm[b] * nk + k) * nb2 + e];
+    if (pack) {
+      // the Hermitian part: below the diagonal, the conjugate of the element above
+      if (n > m && !init_eq) {
+        const double2 u = rho_in[((size_t)perm[b] * nk + k) * nb2 + m * nb + n];
+        r = make_double2(u.x, -u.y);
+      }
+      if (n == m) r.y = 0.0;
+      if (m >= n) {
+        pk_put(rho_n, nk, nb, ldx, k, n, m, b, r);
+        pk_put(rho_s, nk, nb, ldx, k, n, m, b, r);
+      }
+    } else {
+      const size_t g = ((size_t)k * nb2 + e) * ldx + b;
+      rho_n[g] = r;
+      rho_s[g] = r;
+    }
     int p = -1;
     if (block == TDG_BLOCK_ALL)
       p = e;
@@ -1144,11 +1066,18 @@ __global__ void init_batched_kernel(const double2* __restrict__ rho_in, const in
 
 // rho[perm[b]] <- batched rho_n.  One block per k.
 __global__ void finish_batched_kernel(const double2* __restrict__ rho_n, const int* __restrict__ perm,
-                                      double2* rho_out, int64_t ldx, int nk, int nb2, int batch) {
-  const int k = blockIdx.x;
+                                      double2* rho_out, int64_t ldx, int nk, int nb, int batch, int pack) {
+  const int k = blockIdx.x, nb2 = nb * nb;
   for (int idx = threadIdx.x; idx < nb2 * batch; idx += blockDim.x) {
-    const int e = idx / batch, b = idx % batch;
-    rho_out[((size_t)perm[b] * nk + k) * nb2 + e] = rho_n[((size_t)k * nb2 + e) * ldx + b];
+    const int e = idx / batch, b = idx % batch, n = e / nb, m = e % nb;
+    double2 v;
+    if (pack) {
+      v = pk_get(rho_n, nk, nb, ldx, k, min(n, m), max(n, m), b);
+      if (n > m) v.y = -v.y;
+    } else {
+      v = rho_n[((size_t)k * nb2 + e) * ldx + b];
+    }
+    rho_out[((size_t)perm[b] * nk + k) * nb2 + e] = v;
   }
 }
 
@@ -1303,7 +1232,6 @@ static void launch_stage(dim3 grid, size_t lds, hipStream_t stream, const StageP
 struct Variant {
   const char* name;
   StageLaunch fn;
-  bool fused = false;  // low rank with the projection fused into the stage kernel
 };
 
 static const Variant kDenseF32[] = {
@@ -1324,9 +1252,6 @@ static const Variant kLowF32[] = {
     {"lowrank_f32_nt256", launch_stage<float, 1, 256, 1, 2>},
     {"lowrank_f32_nt128_c4", launch_stage<float, 1, 128, 2, 2>},
     {"lowrank_f32_nt64_c6", launch_stage<float, 1, 64, 3, 2>},
-    {"lowrank_fused_f32_nt128", launch_stage<float, 3, 128, 1, 2>, true},
-    {"lowrank_fused_f32_nt128_c4", launch_stage<float, 3, 128, 2, 2>, true},
-    {"lowrank_fused_f32_nt256", launch_stage<float, 3, 256, 1, 2>, true},
 };
 static const Variant kChanF32[] = {
     {"channel_f32_nt256_u2_w6", launch_stage<float, 2, 256, 2, 6>},
@@ -1341,8 +1266,6 @@ static const Variant kLowF64[] = {
     {"lowrank_f64_nt64", launch_stage<double, 1, 64, 1, 2>},
     {"lowrank_f64_nt128", launch_stage<double, 1, 128, 1, 2>},
     {"lowrank_f64_nt256", launch_stage<double, 1, 256, 1, 2>},
-    {"lowrank_fused_f64_nt128", launch_stage<double, 3, 128, 1, 2>, true},
-    {"lowrank_fused_f64_nt256", launch_stage<double, 3, 256, 1, 2>, true},
 };
 
 // Timing events of a tuner, destroyed on every exit path.
@@ -1545,7 +1468,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     if (batched) {
       hipLaunchKernelGGL(init_batched_kernel, dim3(nk), dim3(256), 0, ctx->stream, (const double2*)rho,
                          (const int*)dperm, (double2*)rho_n, (double2*)rho_s, (float2*)x0, xstride, nk, model->nb,
-                         model->nv, npair, op->block, init_eq, batch);
+                         model->nv, npair, op->block, init_eq, batch, (int)!intra);
       return launch_check(ctx, "init launch");
     }
     if (op->dtype == TDG_C128)
@@ -1698,7 +1621,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     // BF16X2: the second tiling needs X split once into a bf16 work array
     void* xbw = nullptr;
     if (bf16) TDG_TRY(ws_reserve(ctx, WS_XB, cgemm_bf16x2_work_bytes((int)n, batch), &xbw));
-    const int ntilings = bf16 ? 2 : 3;
+    const int ntilings = 3;  // FP32: 64-row, prefetching 64-row, 128-row; BF16X2: 64-row, 128-row, 256-row
     if (n_dyn0 > 0) {
       // Split-K candidates: the default (about 1024 blocks), no split, twice
       // the default, and slice counts that put about 256 j blocks (j = 1..4)
@@ -1894,12 +1817,17 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
           covariant_derivative(st, model, rho_s, 1, (int64_t)nb2 * xstride, xstride, (const tdg_field*)dfields, n_dyn,
                                dintra);
         if (prof) prof_begin(ctx, TDG_KCLASS_STAGE);
-        if (model->nb <= 4)
-          hipLaunchKernelGGL(batched_stage_kernel<4>, dim3(nk, (active + IB - 1) / IB), dim3(IB * model->nb),
-                             stage_lds, st, bp);
+        // Hermitian-packed state unless the intraband term (which reads the
+        // full stage state) is on
+        const dim3 sg(nk, (active + IB - 1) / IB), sb(IB * model->nb);
+        if (model->nb <= 4 && !intra)
+          hipLaunchKernelGGL((batched_stage_kernel<4, true>), sg, sb, stage_lds, st, bp);
+        else if (model->nb <= 4)
+          hipLaunchKernelGGL((batched_stage_kernel<4, false>), sg, sb, stage_lds, st, bp);
+        else if (!intra)
+          hipLaunchKernelGGL((batched_stage_kernel<TDG_NB_MAX, true>), sg, sb, stage_lds, st, bp);
         else
-          hipLaunchKernelGGL(batched_stage_kernel<TDG_NB_MAX>, dim3(nk, (active + IB - 1) / IB),
-                             dim3(IB * model->nb), stage_lds, st, bp);
+          hipLaunchKernelGGL((batched_stage_kernel<TDG_NB_MAX, false>), sg, sb, stage_lds, st, bp);
         if (prof) prof_end(ctx, TDG_KCLASS_STAGE);
         std::swap(xc, xn);
       }
@@ -1974,7 +1902,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     release();
     TDG_TRY(rc);
     hipLaunchKernelGGL(finish_batched_kernel, dim3(nk), dim3(256), 0, ctx->stream, (const double2*)rho_n,
-                       (const int*)dperm, (double2*)rho, xstride, nk, nb2, batch);
+                       (const int*)dperm, (double2*)rho, xstride, nk, model->nb, batch, (int)!intra);
     return launch_check(ctx, "batched propagation launch");
   }
 
@@ -1991,63 +1919,10 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
   const bool tune_split = lowrank && !batched;
   const int splits[3] = {1, 2, ZSPLIT_MAX};
 
-  // Fused projection (low-rank variants marked fused): the stage kernel also
-  // forms z of the gather it writes, so no projection launch is needed per
-  // stage.  It holds a k point's V^H columns in LDS (P <= ROWS pairs, rank <=
-  // FUSED_RMAX) and reads V^H transposed, written once per call.
-  const bool fuse_ok = lowrank && !batched && !fixed && npair <= ROWS && op->rank <= FUSED_RMAX &&
-                       ((size_t)npair * op->rank * elt) % 16 == 0;
-  void* zf = nullptr;
-  bool fused_ready = false;
-  auto fused_setup = [&]() -> int {
-    if (fused_ready) return TDG_OK;
-    void *vtb = nullptr, *zpb = nullptr, *gsb = nullptr, *cnb = nullptr;
-    sp.kgroup = std::max(1, (int)std::lround(std::sqrt((double)nk)));
-    sp.ngroups = (nk + sp.kgroup - 1) / sp.kgroup;
-    TDG_TRY(W.get(WS_VT, (size_t)n * op->rank * elt, &vtb));
-    TDG_TRY(W.get(WS_ZPART, (size_t)batch * nk * op->rank * elt, &zpb));
-    TDG_TRY(W.get(WS_GSUM, (size_t)batch * sp.ngroups * op->rank * sizeof(double2), &gsb));
-    TDG_TRY(W.get(WS_CNT, (size_t)batch * (sp.ngroups + 1) * sizeof(unsigned), &cnb));
-    TDG_TRY(W.get(WS_ZF, (size_t)2 * batch * zstride * elt, &zf));
-    const dim3 tg((unsigned)((n + 31) / 32), (unsigned)((op->rank + 31) / 32));
-    if (op->dtype == TDG_C128)
-      hipLaunchKernelGGL(transpose_vh_kernel<double>, tg, dim3(256), 0, ctx->stream, op->w, n, (int)op->rank, vtb);
-    else
-      hipLaunchKernelGGL(transpose_vh_kernel<float>, tg, dim3(256), 0, ctx->stream, op->w, n, (int)op->rank, vtb);
-    const int64_t ncnt = (int64_t)batch * (sp.ngroups + 1);
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((ncnt + 255) / 256)), dim3(256), 0, ctx->stream, (unsigned*)cnb,
-                       ncnt);
-    sp.vt = vtb;
-    sp.zpart = zpb;
-    sp.gsum = (double2*)gsb;
-    sp.cnt = (unsigned*)cnb;
-    fused_ready = true;
-    return launch_check(ctx, "fused projection setup");
-  };
-  // z of a gather in one piece into half h of zf (the fused variants' input)
-  auto project_full = [&](const void* xin, int active, int h) {
-    void* dst = (char*)zf + (size_t)h * batch * zstride * elt;
-    const dim3 g(groups, 1, active);
-    if (op->dtype == TDG_C128)
-      hipLaunchKernelGGL(project_kernel<double>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
-                         xstride, dst, zstride, pcols, (int64_t)0, 0, 0);
-    else
-      hipLaunchKernelGGL(project_kernel<float>, g, dim3(PROJ_THREADS), 0, ctx->stream, op->w, pcols, prows, xin,
-                         xstride, dst, zstride, pcols, (int64_t)0, 0, 0);
-  };
-  auto fused_params = [&](int h) {
-    sp.vec = (char*)zf + (size_t)h * batch * zstride * elt;
-    sp.znext = (char*)zf + (size_t)(1 - h) * batch * zstride * elt;
-    sp.vstride = zstride;
-    sp.zsplit = 1;
-  };
-
   if (ctx->forced_variant >= 0) {
     if (ctx->forced_variant >= nvar)
       return fail(ctx, TDG_E_INVAL, "variant %d of %d for this operator", ctx->forced_variant, nvar);
     var = ctx->forced_variant;
-    if (vt[var].fused && !fuse_ok)
-      return fail(ctx, TDG_E_INVAL, "variant %d (fused projection) does not apply to this operator or call", var);
   } else if (ctx->autotune && max_steps > 0) {
     char key[160];
     snprintf(key, sizeof(key), "%d/%d/%lld/%d/%d/%lld/%d", op->kind, op->dtype, (long long)n, nk, batch,
@@ -2058,7 +1933,6 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     if (found >= 0) {
       var = found % 100;
       if (tune_split) set_split(splits[found / 100]);
-      if (vt[var].fused && !fuse_ok) var = 0;  // the allocation-free call uses no fused variant
     } else if (!fixed) {
       // time each variant on stage 0 of step 0: it reads rho and writes only
       // the stage state, accumulator and next gather, which init restores
@@ -2076,7 +1950,6 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       sp.vec = projects ? z : x0;
       sp.vstride = projects ? zstride : xstride;
       const dim3 g(nk, dyn0);
-      if (fuse_ok) TDG_TRY(fused_setup());
       // three interleaved rounds of 8 repetitions per (split, variant); the
       // fastest round counts (single short timings vary by tens of per cent)
       float tmin[3][8];
@@ -2087,22 +1960,12 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
         for (int si = 0; si < nsplit; ++si) {
           if (tune_split) set_split(splits[si]);
           // with the split tuned, each timed repetition includes the projection
-          // (a fused variant forms it itself: timed alone, with the first split)
           auto run = [&](int v) {
-            if (projects && !vt[v].fused && (tune_split || si == 0)) project(x0, dyn0);
+            if (projects && (tune_split || si == 0)) project(x0, dyn0);
             vt[v].fn(g, 0, ctx->stream, sp, nullptr, nullptr);
           };
           if (projects && !tune_split) project(x0, dyn0);
           for (int v = 0; v < nvar; ++v) {
-            if (vt[v].fused && (!fuse_ok || si > 0)) continue;
-            if (vt[v].fused) {
-              project_full(x0, dyn0, 0);
-              fused_params(0);
-            } else {
-              sp.vec = projects ? z : x0;
-              sp.vstride = projects ? zstride : xstride;
-              sp.zsplit = zsplit;
-            }
             run(v);  // warm-up
             (void)hipEventRecord(ea, ctx->stream);
             for (int rep = 0; rep < 8; ++rep) {
@@ -2139,16 +2002,10 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       TDG_TRY(init());  // the caller's rho was only read
     }
   }
-  const bool fused = vt[var].fused;
   ctx->last_variant = vt[var].name;
-  if (tune_split && !fused) ctx->last_variant += "_z" + std::to_string(zsplit);
+  if (tune_split) ctx->last_variant += "_z" + std::to_string(zsplit);
   sp.zsplit = zsplit;
   const StageLaunch stage_fn = vt[var].fn;
-  int zhalf = 0;
-  if (fused) {
-    TDG_TRY(fused_setup());
-    if (count_gt(0) > 0) project_full(x0, count_gt(0), 0);
-  }
 
   tdg_obs ob = *obs;
   void* xc = x0;
@@ -2162,17 +2019,13 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     for (int s = 0; s < 4; ++s) {
       const int active = s == 0 ? n_obs : n_dyn;
       if (active == 0) break;
-      if (projects && n_dyn > 0 && !fused) {
+      if (projects && n_dyn > 0) {
         hipEvent_t pa = nullptr, pb = nullptr;
         if (!fixed) prof_pair(ctx, TDG_KCLASS_PROJECT, &pa, &pb);
         project(xc, n_dyn, pa, pb);
       }
-      if (fused) {
-        fused_params(zhalf);
-      } else {
-        sp.vec = projects ? z : xc;
-        sp.vstride = projects ? zstride : xstride;
-      }
+      sp.vec = projects ? z : xc;
+      sp.vstride = projects ? zstride : xstride;
       sp.xcur = xc;
       sp.xnext = xn;
       sp.step = (int)step;
@@ -2182,7 +2035,6 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       if (!fixed) prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
       stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
       std::swap(xc, xn);
-      if (fused && n_dyn > 0) zhalf = 1 - zhalf;  // the projection of the new gather
       // with links the next stage reads the buffer this one wrote (four
       // stages per step: every step starts from the first buffer)
       if (sp.links) std::swap(sp.rho_s, sp.rho_s_out);

@@ -186,8 +186,7 @@ def test_lowrank_fp32_every_stage_variant(P, ctx):
     """Each low-rank FP32 stage-kernel variant, forced in turn, against the
     FP64 oracle.  Rank 401 on a 12x12 grid (N = 576) gives every variant a
     ragged last pass: 4 passes of 128 columns, 2 of 256, and single passes of
-    512 and of 384 + 17 columns.  Variants 5-7 form the next projection
-    themselves (fused); 12 groups of 12 k points in their reduction."""
+    512 and of 384 + 17 columns."""
     from paper_2502_05635_amd import _abi as abi
     m = tb4_model(12, A, 0.5)
     dm = _dev(P, m)
@@ -200,7 +199,7 @@ def test_lowrank_fp32_every_stage_variant(P, ctx):
     assert fac.rank == r
     names = []
     try:
-        for v in range(8):
+        for v in range(5):
             ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, v)
             res = ctx.propagate(fac, dm, "eh", f, DT)
             names.append(ctx.last_variant())
@@ -210,41 +209,7 @@ def test_lowrank_fp32_every_stage_variant(P, ctx):
                 assert e <= 1e-4, (names[-1], key)
     finally:
         ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, -1)
-    assert len(set(n.split("_z")[0] for n in names)) == 8, names
-    assert sum("fused" in n for n in names) == 3, names
-
-
-@pytest.mark.parametrize("variant", [3, 4])
-def test_lowrank_fp64_fused_projection(P, ctx, tb4_6, variant):
-    """FP64 low rank with the projection fused into the stage kernel (the
-    last block of each k group and the last group reduce it in fixed order):
-    three instances of uneven length (one of zero steps) against the oracle
-    at 1e-10, and bitwise the same series on a second run."""
-    from paper_2502_05635_amd import _abi as abi
-    dm = _dev(P, tb4_6)
-    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c128")
-    fac = ctx.kernel_compress(kg, "rank", 37)
-    oop = O.LowRankOp.from_factors(O.compress(kg.cpu().numpy(), "rank", 37))
-    fields = FieldTable.stack([strong(150), FieldTable.single(5e-3, 1.5 / HARTREE_EV, 10.0, 20.0, 0),
-                             strong(90, e0=8e-3, omega_ev=2.2)])
-    ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, variant)
-    try:
-        res = ctx.propagate(fac, dm, "eh", fields, DT)
-        name = ctx.last_variant()
-        again = ctx.propagate(fac, dm, "eh", fields, DT)
-    finally:
-        ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, -1)
-    _log(f"  {name}")
-    assert "fused" in name
-    for b in range(3):
-        ref = O.propagate(tb4_6, oop, "eh", fields, DT, instance=b)
-        nsb = int(fields.nsteps[b])
-        for key in ("P", "J", "occ"):
-            got = res[key][b, : nsb + 1].cpu().numpy()
-            assert np.abs(got - ref[key]).max() <= 1e-10 * max(np.abs(ref[key]).max(), 1e-300), (b, key)
-        np.testing.assert_allclose(res["rho"][b].cpu().numpy(), ref["rho"], rtol=0, atol=1e-12)
-    for key in ("P", "J", "occ"):
-        assert torch.equal(res[key], again[key]), key
+    assert len(set(n.split("_z")[0] for n in names)) == 5, names
 
 
 def test_batched_uneven_instances(P, ctx):
@@ -449,6 +414,41 @@ def test_batched_mfma_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, slices):
         np.testing.assert_allclose(res["rho"][b].cpu().numpy(), ref["rho"], rtol=0, atol=1e-5)
 
 
+@pytest.mark.parametrize("block", ["eh", "all"])
+def test_batched_from_given_rho0(P, ctx, tb4_6, block):
+    """The batched path keeps its state Hermitian-packed (upper triangle and a
+    real diagonal): started from a caller's non-equilibrium Hermitian rho(0),
+    five instances of uneven length against the oracle from the same state,
+    for the conduction-valence block and for all band pairs."""
+    from paper_2502_05635_amd import _abi as abi
+    m = tb4_6
+    dm = _dev(P, m)
+    kg = ctx.kernel_build(dm, R0_STABLE, block, "c64")
+    ko = O.build_kernel(m, R0_STABLE, block)
+    rng = np.random.default_rng(11)
+    z = rng.standard_normal((m.nk, m.nb, m.nb)) + 1j * rng.standard_normal((m.nk, m.nb, m.nb))
+    rho0 = O.rho_equilibrium(m) + 1e-3 * (z + z.conj().transpose(0, 2, 1))
+    fields = FieldTable.stack([strong(n, e0=4e-3 * (1 + 0.2 * i)) for i, n in enumerate([90, 40, 130, 7, 60])])
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 2)
+    try:
+        rho = torch.from_numpy(np.stack([rho0] * fields.batch)).cuda()
+        res = ctx.propagate(kg, dm, block, fields, DT, rho=rho, init_eq=False)
+        variant = ctx.last_variant()
+    finally:
+        ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 4)
+    _log(f"  {variant}")
+    assert variant.startswith("batched_mfma_dense")
+    for b in range(fields.batch):
+        ref = O.propagate(m, O.DenseOp(ko), block, fields, DT, instance=b, rho0=rho0)
+        nsb = int(fields.nsteps[b])
+        for key in ("P", "J", "occ"):
+            got = res[key][b, : nsb + 1].cpu().numpy()
+            assert np.abs(got - ref[key]).max() <= 1e-4 * np.abs(ref[key]).max(), (b, key)
+        r = res["rho"][b].cpu().numpy()
+        np.testing.assert_allclose(r, ref["rho"], rtol=0, atol=1e-6)
+        assert np.abs(r - r.conj().transpose(0, 2, 1)).max() == 0.0      # returned exactly Hermitian
+
+
 @pytest.mark.parametrize("kind", ["dense", "lowrank"])
 def test_batched_mfma_matches_per_instance_path(P, ctx, kind):
     """70 instances (two instance tiles of the matrix-core product) agree with
@@ -539,6 +539,22 @@ def test_bf16x2_batched_forced_split_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, sli
     finally:
         ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
         ctx.set_option(abi.TDG_OPT_GEMM_SLICES, 0)
+
+
+@pytest.mark.parametrize("kind,tiling", [("dense", 0), ("lowrank", 0), ("dense", 1), ("lowrank", 1),
+                                         ("dense", 2), ("lowrank", 2)])
+def test_bf16x2_batched_each_tiling_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, tiling):
+    """Every BF16X2 tiling forced in turn, against the FP64 oracle: N = 144
+    rows (within one 256-row tile of the third tiling) and rank 37 (a ragged
+    last K stage)."""
+    from paper_2502_05635_amd import _abi as abi
+    ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, tiling)
+    try:
+        _bf16x2_batched_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind)
+        _log(f"  {ctx.last_variant()}")
+        assert f"tiling {tiling}" in ctx.last_variant() or f"tilings {tiling}/{tiling}" in ctx.last_variant()
+    finally:
+        ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
 
 
 def _bf16x2_batched_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind):
