@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--sweep-only", type=int, default=0, metavar="STEPS",
                     help="only run the batched 60x60 sweep, every instance for STEPS steps (for counter runs; "
                          "with --factors-cache the sweep's factors are cached as well)")
+    ap.add_argument("--stage-variant", type=int, default=-1,
+                    help="force this single-instance stage-kernel variant for the low-rank legs (profiling runs: "
+                         "a tracer can move the tuner's pick); -1 = tuned")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -228,6 +231,7 @@ def main():
     legs = [("dense", K), ("lowrank", fac)] + ([("lowrank_shift_only", fac_shift)] if fac_shift else [])
     for name, op in legs:
         progress(f"{name} operator, {args.steps} steps")
+        ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, args.stage_variant if name != "dense" else -1)
         res, secs, _ = timed(op, args.steps, args.warmup, False)
         variant = ctx.last_variant()
         # further runs of the same K steps; the median of all runs is reported
@@ -235,6 +239,7 @@ def main():
         _, _, prof = timed(op, args.steps, args.warmup, True)
         runs = [secs] + again
         out[name] = {"secs": float(np.median(runs)), "res": res, "prof": prof, "variant": variant, "runs": runs}
+    ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, -1)
 
     # channel-wise compression (Eq. svd-channel-wise) at its own fixed-error fraction
     chan_golden = json.load(open(CHAN_JSON)) if os.path.exists(CHAN_JSON) else None

@@ -880,6 +880,56 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
     }
 }
 
+// The expanded X of the second and third tilings (layout as for
+// expand_bf16x2_kernel) straight from split-K slices of a product: x[k][b] =
+// sum over slices s in order of in[s stride + k ldx + b], for k < Kc and b <
+// ncols, zero elsewhere in [Kc rounded][tiles x 64].  Thread (pair o, slice
+// group g) of a block sums slices g, g + 4, ... of two instances; the four
+// group sums are added in order and written as bf16 hi / lo words.
+__global__ void __launch_bounds__(256) sum_expand_bf16x2_kernel(const float4* __restrict__ in, int slices,
+                                                                int64_t stride2, int Kc, int64_t ldx2, int ncols,
+                                                                int tiles, unsigned short* __restrict__ XB,
+                                                                int64_t ldxb) {
+  __shared__ float4 red[4][64];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + o;  // pair index over (k, instance pair)
+  const int pairs_per_k = tiles * (BNI / 2);
+  const int64_t npairs = (ldxb / 2) * (int64_t)pairs_per_k;
+  const int k = (int)(i / pairs_per_k), bp = (int)(i % pairs_per_k), b = 2 * bp;
+  const bool live = i < npairs && k < Kc && b < ncols;
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (live) {
+    const int64_t e = (int64_t)k * ldx2 + bp;
+    for (int sl = g; sl < slices; sl += 4) {
+      const float4 a = in[sl * stride2 + e];
+      v.x += a.x; v.y += a.y; v.z += a.z; v.w += a.w;
+    }
+  }
+  red[g][o] = v;
+  __syncthreads();
+  if (g != 0 || i >= npairs) return;
+  float4 r = red[0][o];
+  for (int q = 1; q < 4; ++q) {
+    const float4 a = red[q][o];
+    r.x += a.x; r.y += a.y; r.z += a.z; r.w += a.w;
+  }
+  for (int h = 0; h < 2; ++h) {
+    const int bb = b + h, ct = bb / BNI, c = bb % BNI;
+    const float re = (live && bb < ncols) ? (h ? r.z : r.x) : 0.f, im = (live && bb < ncols) ? (h ? r.w : r.y) : 0.f;
+    const unsigned short rh = f2bf(re), ih = f2bf(im);
+    const unsigned short rl = f2bf(re - bf2f(rh)), il = f2bf(im - bf2f(ih));
+    const unsigned short hv[2][2] = {{rh, ih}, {rl, il}};
+    for (int p = 0; p < 2; ++p) {
+      const unsigned short rv = hv[p][0], iv = hv[p][1];
+      // rows c (real parts of the outputs): (re, -im); rows 64 + c: (im, re)
+      *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + c) * ldxb + 2 * k]) =
+          (unsigned int)rv | ((unsigned int)(iv ^ 0x8000u) << 16);
+      *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + BNI + c) * ldxb + 2 * k]) =
+          (unsigned int)iv | ((unsigned int)rv << 16);
+    }
+  }
+}
+
 // dst (TDG_BF16X2, [rows][ld_dst]) <- src complex (float or double, [rows][ld_src]);
 // columns cols .. ld_dst-1 of dst are zero-filled.
 template <typename S>
@@ -911,10 +961,23 @@ size_t cgemm_bf16x2_work_bytes(int Kc, int ncols) {
   return (size_t)((ncols + BNI - 1) / BNI) * 2 * XB_ROWS * ldxb * sizeof(unsigned short);
 }
 
-// variant 0: 64-row tiles, X split while staged; variant 1: X split and
-// expanded once into `work` (cgemm_bf16x2_work_bytes), 128-row tiles.
+void sum_expand_bf16x2(hipStream_t stream, const void* in, int slices, int64_t stride, int Kc, int64_t ldx, int ncols,
+                       void* work) {
+  const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
+  const int tiles = (ncols + BNI - 1) / BNI;
+  const int64_t npairs = (ldxb / 2) * (int64_t)tiles * (BNI / 2);
+  hipLaunchKernelGGL(sum_expand_bf16x2_kernel, dim3((unsigned)((npairs + 63) / 64)), dim3(256), 0, stream,
+                     (const float4*)in, slices, stride / 2, Kc, ldx / 2, ncols, tiles, (unsigned short*)work, ldxb);
+}
+
+// variant 0: 64-row tiles, X split while staged; variants 1 and 2: X split and
+// expanded once into `work` (cgemm_bf16x2_work_bytes), then 128-row tiles
+// (variant 1) or 256-row tiles staged by direct-to-LDS loads (variant 2).
+// With x_expanded, `work` already holds that expansion (sum_expand_bf16x2)
+// and X is not read.
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
-                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant, void* work) {
+                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant, void* work,
+                  bool x_expanded) {
   GemmBf16Args g;
   g.Ahi = (const unsigned short*)A;
   g.Alo = (const unsigned short*)A + (int64_t)M * lda * 2;
@@ -932,8 +995,9 @@ void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc,
   if ((variant == 1 || variant == 2) && work) {
     const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
     const int tiles = (ncols + BNI - 1) / BNI;
-    hipLaunchKernelGGL(expand_bf16x2_kernel, dim3((unsigned)(ldxb / 64), (unsigned)tiles), dim3(256), 0, stream,
-                       (const float2*)X, ldx, Kc, ncols, (unsigned short*)work, ldxb);
+    if (!x_expanded)
+      hipLaunchKernelGGL(expand_bf16x2_kernel, dim3((unsigned)(ldxb / 64), (unsigned)tiles), dim3(256), 0, stream,
+                         (const float2*)X, ldx, Kc, ncols, (unsigned short*)work, ldxb);
     if (variant == 2) {
       const dim3 grid((M + BM4 - 1) / BM4, tiles, splits);
       hipLaunchKernelGGL(cgemm_bf16x2_mfma_v3, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);

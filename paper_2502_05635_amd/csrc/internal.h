@@ -107,10 +107,18 @@ void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, co
                int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant);
 // BF16 split-precision product: A in TDG_BF16X2 storage (hi plane, then lo
 // plane, [M][lda], lda % 4 == 0), X complex64 [Kc][ldx] (gemm.hip).
-// variant 0: 64-row tiles splitting X while staged; 1: X split once into
-// `work` (cgemm_bf16x2_work_bytes bytes), 128-row tiles.
+// variant 0: 64-row tiles splitting X while staged; 1 and 2: X split once
+// into `work` (cgemm_bf16x2_work_bytes bytes), then 128-row tiles (1) or
+// 256-row tiles staged by direct-to-LDS loads (2).
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
-                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant, void* work);
+                  void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant, void* work,
+                  bool x_expanded = false);
+// The split X of BF16X2 tilings 1 and 2 written into `work` straight from
+// `slices` split-K partial products (complex64 [Kc][ldx] each, `stride`
+// apart; ldx and stride even), summed in slice order: then call cgemm_bf16x2
+// with x_expanded (X unused).
+void sum_expand_bf16x2(hipStream_t stream, const void* in, int slices, int64_t stride, int Kc, int64_t ldx, int ncols,
+                       void* work);
 size_t cgemm_bf16x2_work_bytes(int Kc, int ncols);
 // dst (TDG_BF16X2 [rows][ld_dst]) <- complex src [rows][ld_src]; columns >= cols zero.
 void split_bf16x2(hipStream_t stream, const void* src, int src_is_double, int64_t ld_src, int64_t rows, int64_t cols,

@@ -1743,11 +1743,19 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
         }, &gv_proj, &ks_proj));
         z_slices = (int)((n + ks_proj - 1) / ks_proj);
         // Zsum now holds the step-0 projection (the expansion's timing input)
+        // BF16X2 tilings 1 and 2 take the split projection straight from its
+        // slices (one kernel instead of the slice sum and the split); tiling
+        // 0 reads the summed projection, so its timing includes the sum
         TDG_TRY(pick("expand", n, op->rank, ks_main, [&](int v, int64_t ks) {
-          if (bf16)
+          if (bf16 && v > 0) {
+            sum_expand_bf16x2(ctx->stream, Zbuf, z_slices, op->rank * ldy, (int)op->rank, ldy, n_dyn0, xbw);
+            cgemm_bf16x2(ctx->stream, op->us, ld_us0, (int)n, (int)op->rank, nullptr, ldy, Ybuf, ldy, n * ldy,
+                         n_dyn0, (int)ks, v, xbw, true);
+          } else if (bf16) {
+            sum_slices_c64(ctx->stream, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
             cgemm_bf16x2(ctx->stream, op->us, ld_us0, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn0,
                          (int)ks, v, xbw);
-          else
+          } else
             cgemm_f32(ctx->stream, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy,
                       n_dyn0, (int)ks, v);
           slice_read((int)((op->rank + ks - 1) / ks));
@@ -1796,13 +1804,19 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
             else
               cgemm_f32(st, op->w, n, (int)op->rank, (int)n, xc, xstride, Zbuf, ldy, op->rank * ldy, n_dyn,
                         (int)ks_proj, gv_proj);
-            sum_slices_c64(st, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
-            if (bf16)
-              cgemm_bf16x2(st, op->us, ld_us, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
-                           (int)ks_main, gv_main, xbw);
-            else
-              cgemm_f32(st, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
-                        (int)ks_main, gv_main);
+            if (bf16 && gv_main > 0) {
+              sum_expand_bf16x2(st, Zbuf, z_slices, op->rank * ldy, (int)op->rank, ldy, n_dyn, xbw);
+              cgemm_bf16x2(st, op->us, ld_us, (int)n, (int)op->rank, nullptr, ldy, Ybuf, ldy, n * ldy, n_dyn,
+                           (int)ks_main, gv_main, xbw, true);
+            } else {
+              sum_slices_c64(st, Zbuf, z_slices, op->rank * ldy, op->rank * ldy, Zsum);
+              if (bf16)
+                cgemm_bf16x2(st, op->us, ld_us, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
+                             (int)ks_main, gv_main, xbw);
+              else
+                cgemm_f32(st, op->us, op->rank, (int)n, (int)op->rank, Zsum, ldy, Ybuf, ldy, n * ldy, n_dyn,
+                          (int)ks_main, gv_main);
+            }
           }
           if (prof) prof_end(ctx, TDG_KCLASS_GEMM);
         }
