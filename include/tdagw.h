@@ -435,11 +435,16 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * 0 / 2. */
 #define TDG_OPT_GEMM_TILE 3
 #define TDG_OPT_GEMM_VARIANT 4
-/* Batched path: 1 captures one RK4 step (products, stage kernels) per running
- * instance count into a HIP graph on a private stream and replays it on the
- * context stream for every step in which no instance reaches its final time
- * (the stage kernels then read the step index from device memory); 0
- * (default) launches every kernel directly.  Results are identical. */
+/* 1 replays captured HIP graphs; 0 (default) launches every kernel directly.
+ * Results are identical.  Batched path: one RK4 step (products, stage
+ * kernels) per running instance count is captured on a private stream and
+ * replayed on the context stream for every step in which no instance reaches
+ * its final time (the stage kernels then read the step index from device
+ * memory).  Per-instance path: every full observable chunk (up to 256 steps,
+ * with its field table and observable reduction) in which no instance
+ * reaches its final time is captured and replayed once; the host captures
+ * the next chunk while the GPU runs the previous one.  tdg_propagate_noalloc
+ * and profiled runs always launch directly. */
 #define TDG_OPT_GRAPHS 5
 /* Batched path: a value in [1, 4096] splits every matrix-core product's K
  * range into that many slices (clamped to twice the default count, the size of

@@ -2024,45 +2024,88 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
   tdg_obs ob = *obs;
   void* xc = x0;
   void* xn = x1;
-  int slot = 0;
-  int64_t chunk_start = 0;
-  for (int64_t step = 0; step <= max_steps; ++step) {
-    const int n_obs = count_ge(step), n_dyn = count_gt(step);
-    if (slot == 0) field_table(step);
-    sp.n_dyn = n_dyn;
-    for (int s = 0; s < 4; ++s) {
-      const int active = s == 0 ? n_obs : n_dyn;
-      if (active == 0) break;
-      if (projects && n_dyn > 0) {
-        hipEvent_t pa = nullptr, pb = nullptr;
-        if (!fixed) prof_pair(ctx, TDG_KCLASS_PROJECT, &pa, &pb);
-        project(xc, n_dyn, pa, pb);
+  // one observable chunk: the field table, steps c0 .. c1 - 1, the reduction
+  auto issue_chunk = [&](int64_t c0, int64_t c1) {
+    field_table(c0);
+    for (int64_t step = c0; step < c1; ++step) {
+      const int n_obs = count_ge(step), n_dyn = count_gt(step);
+      sp.n_dyn = n_dyn;
+      for (int s = 0; s < 4; ++s) {
+        const int active = s == 0 ? n_obs : n_dyn;
+        if (active == 0) break;
+        if (projects && n_dyn > 0) {
+          hipEvent_t pa = nullptr, pb = nullptr;
+          if (!fixed) prof_pair(ctx, TDG_KCLASS_PROJECT, &pa, &pb);
+          project(xc, n_dyn, pa, pb);
+        }
+        sp.vec = projects ? z : xc;
+        sp.vstride = projects ? zstride : xstride;
+        sp.xcur = xc;
+        sp.xnext = xn;
+        sp.step = (int)step;
+        sp.stage = s;
+        sp.obs_slot = (int)(step - c0);
+        hipEvent_t sa = nullptr, sb = nullptr;
+        if (!fixed) prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
+        stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
+        std::swap(xc, xn);
+        // with links the next stage reads the buffer this one wrote (four
+        // stages per step: every step starts from the first buffer)
+        if (sp.links) std::swap(sp.rho_s, sp.rho_s_out);
       }
-      sp.vec = projects ? z : xc;
-      sp.vstride = projects ? zstride : xstride;
-      sp.xcur = xc;
-      sp.xnext = xn;
-      sp.step = (int)step;
-      sp.stage = s;
-      sp.obs_slot = slot;
-      hipEvent_t sa = nullptr, sb = nullptr;
-      if (!fixed) prof_pair(ctx, TDG_KCLASS_STAGE, &sa, &sb);
-      stage_fn(dim3(nk, active), 0, ctx->stream, sp, sa, sb);
-      std::swap(xc, xn);
-      // with links the next stage reads the buffer this one wrote (four
-      // stages per step: every step starts from the first buffer)
-      if (sp.links) std::swap(sp.rho_s, sp.rho_s_out);
     }
-    ++slot;
-    if (slot == chunk || step == max_steps) {
-      hipLaunchKernelGGL(obs_reduce_kernel, dim3(slot, batch), dim3(THREADS), 0, ctx->stream, (const double*)part, nk,
-                         batch, (int)chunk_start, (const tdg_field*)dfields, (const int*)dperm, ob, (double*)nullptr,
-                         (int)intra);
-      chunk_start += slot;
-      slot = 0;
+    hipLaunchKernelGGL(obs_reduce_kernel, dim3((unsigned)(c1 - c0), batch), dim3(THREADS), 0, ctx->stream,
+                       (const double*)part, nk, batch, (int)c0, (const tdg_field*)dfields, (const int*)dperm, ob,
+                       (double*)nullptr, (int)intra);
+  };
+  // Graph replays (TDG_OPT_GRAPHS): a full chunk in which every running
+  // instance runs through is captured on a private stream (its launches
+  // read ctx->stream) and replayed once on the context stream; the host
+  // captures the next chunk while the GPU runs this one.  Profiled and
+  // allocation-free runs launch directly.
+  const bool use_graphs = ctx->graphs && !ctx->prof && !fixed;
+  std::vector<hipGraphExec_t> execs;
+  hipStream_t cap = nullptr;
+  if (use_graphs && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+    return fail(ctx, TDG_E_HIP, "capture stream");
+  int rc = TDG_OK;
+  for (int64_t c0 = 0; c0 <= max_steps && rc == TDG_OK; c0 += chunk) {
+    const int64_t c1 = std::min<int64_t>(c0 + chunk, max_steps + 1);
+    const bool uniform = c1 - c0 == chunk && c1 - 1 < max_steps && count_gt(c1 - 1) == count_ge(c0);
+    if (use_graphs && uniform) {
+      hipStream_t own = ctx->stream;
+      if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = fail(ctx, TDG_E_HIP, "graph capture begin");
+        break;
+      }
+      ctx->stream = cap;
+      issue_chunk(c0, c1);
+      ctx->stream = own;
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e1 = hipStreamEndCapture(cap, &g);
+      const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) : e1;
+      if (g) (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess) {
+        rc = fail(ctx, TDG_E_HIP, "graph capture: %s", hipGetErrorString(e2));
+        break;
+      }
+      execs.push_back(ex);
+      if (hipGraphLaunch(ex, ctx->stream) != hipSuccess) rc = fail(ctx, TDG_E_HIP, "graph launch");
+    } else {
+      issue_chunk(c0, c1);
+      rc = launch_check(ctx, "propagation launch");
     }
-    if ((step & 63) == 0) TDG_TRY(launch_check(ctx, "propagation launch"));
   }
+  // the graph executables are destroyed only after their replays finished
+  if (use_graphs) {
+    const hipError_t es = hipStreamSynchronize(ctx->stream);
+    if (es != hipSuccess && rc == TDG_OK) rc = fail(ctx, TDG_E_HIP, "graph replay: %s", hipGetErrorString(es));
+    for (hipGraphExec_t e : execs) (void)hipGraphExecDestroy(e);
+    (void)hipStreamDestroy(cap);
+    if (!execs.empty()) ctx->last_variant += " graphs";
+  }
+  TDG_TRY(rc);
   hipLaunchKernelGGL(finish_kernel, dim3(nk, batch), dim3(init_threads), 0, ctx->stream, (const double2*)rho_n,
                      (const int*)dperm, (double2*)rho, nk, nb2);
   return launch_check(ctx, "propagation launch");
