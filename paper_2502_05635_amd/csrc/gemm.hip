@@ -20,9 +20,14 @@
 // D[8*(r/4) + 4*(l/32) + r%4][l%32].
 #include <algorithm>
 
+#include "bf16x2.h"
 #include "internal.h"
 
 namespace {
+
+using tdg::bf2f;
+using tdg::f2bf;
+using tdg::xb_word;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -478,12 +483,6 @@ constexpr int BKC2 = 32;                 // complex K columns per stage
 constexpr int KR = 2 * BKC2;             // real K per stage
 constexpr int LPAD = 8;                  // bf16 padding per LDS row
 
-__device__ inline unsigned short f2bf(float f) {
-  unsigned int u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);       // round to nearest even
-  return (unsigned short)(u >> 16);
-}
-__device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
 struct GemmBf16Args {
   const unsigned short* Ahi;  // bf16 bits, [M][2*lda]
@@ -599,14 +598,11 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma(GemmBf16Args g) {
 }
 
 // ---- BF16 split-precision product, second tiling ---------------------------
-// X is split and expanded once per product into XB (bf16 bits): for column
-// tile ct of 64 instances, plane p (0 = hi, 1 = lo), row c < 128 and real K
-// index kr, XB[((ct * 2 + p) * 128 + c) * ldxb + kr] holds the real expansion
-// of x[k][64 ct + (c % 64)]: rows c < 64 (real parts of the outputs) carry
-// (re, -im) at kr = (2k, 2k + 1), rows c >= 64 (imaginary parts) carry (im, re).
-// Rows are K-contiguous, so a lane's 8 consecutive K are one 16-byte read,
-// and zero from 2 Kc up to ldxb = 2 Kc rounded up to 64.
-constexpr int XB_ROWS = 2 * BNI;
+// X is split and expanded once per product into XB (bf16 bits, the layout of
+// bf16x2.h).  Rows are K-contiguous, so a lane's 8 consecutive K are one
+// 16-byte read.
+using tdg::XB_ROWS;
+static_assert(tdg::XB_TILE == BNI, "split operand tiles hold one block's instances");
 
 __global__ void __launch_bounds__(256) expand_bf16x2_kernel(const float2* __restrict__ X, int64_t ldx, int Kc,
                                                             int ncols, unsigned short* __restrict__ XB,
@@ -623,11 +619,8 @@ __global__ void __launch_bounds__(256) expand_bf16x2_kernel(const float2* __rest
   for (int i = t; i < 2 * XB_ROWS * 32; i += 256) {
     const int kk = i % 32, c = (i / 32) % XB_ROWS, p = i / (32 * XB_ROWS);
     const float2 v = tile[kk][c % BNI];
-    const unsigned short rh = f2bf(v.x), ih = f2bf(v.y);
-    const unsigned short re = p ? f2bf(v.x - bf2f(rh)) : rh, im = p ? f2bf(v.y - bf2f(ih)) : ih;
-    const unsigned int word = c < BNI ? ((unsigned int)re | ((unsigned int)(im ^ 0x8000u) << 16))
-                                      : ((unsigned int)im | ((unsigned int)re << 16));
-    *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + c) * ldxb + 2 * (k0 + kk)]) = word;
+    *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + c) * ldxb + 2 * (k0 + kk)]) =
+        xb_word(v.x, v.y, p, c >= BNI);
   }
 }
 
@@ -916,16 +909,11 @@ __global__ void __launch_bounds__(256) sum_expand_bf16x2_kernel(const float4* __
   for (int h = 0; h < 2; ++h) {
     const int bb = b + h, ct = bb / BNI, c = bb % BNI;
     const float re = (live && bb < ncols) ? (h ? r.z : r.x) : 0.f, im = (live && bb < ncols) ? (h ? r.w : r.y) : 0.f;
-    const unsigned short rh = f2bf(re), ih = f2bf(im);
-    const unsigned short rl = f2bf(re - bf2f(rh)), il = f2bf(im - bf2f(ih));
-    const unsigned short hv[2][2] = {{rh, ih}, {rl, il}};
     for (int p = 0; p < 2; ++p) {
-      const unsigned short rv = hv[p][0], iv = hv[p][1];
-      // rows c (real parts of the outputs): (re, -im); rows 64 + c: (im, re)
       *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + c) * ldxb + 2 * k]) =
-          (unsigned int)rv | ((unsigned int)(iv ^ 0x8000u) << 16);
+          xb_word(re, im, p, false);
       *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + BNI + c) * ldxb + 2 * k]) =
-          (unsigned int)iv | ((unsigned int)rv << 16);
+          xb_word(re, im, p, true);
     }
   }
 }
@@ -959,6 +947,13 @@ namespace tdg {
 size_t cgemm_bf16x2_work_bytes(int Kc, int ncols) {
   const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
   return (size_t)((ncols + BNI - 1) / BNI) * 2 * XB_ROWS * ldxb * sizeof(unsigned short);
+}
+
+void expand_bf16x2(hipStream_t stream, const void* X, int64_t ldx, int Kc, int ncols, void* work) {
+  const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
+  const int tiles = (ncols + BNI - 1) / BNI;
+  hipLaunchKernelGGL(expand_bf16x2_kernel, dim3((unsigned)(ldxb / 64), (unsigned)tiles), dim3(256), 0, stream,
+                     (const float2*)X, ldx, Kc, ncols, (unsigned short*)work, ldxb);
 }
 
 void sum_expand_bf16x2(hipStream_t stream, const void* in, int slices, int64_t stride, int Kc, int64_t ldx, int ncols,
@@ -995,9 +990,7 @@ void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc,
   if ((variant == 1 || variant == 2) && work) {
     const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
     const int tiles = (ncols + BNI - 1) / BNI;
-    if (!x_expanded)
-      hipLaunchKernelGGL(expand_bf16x2_kernel, dim3((unsigned)(ldxb / 64), (unsigned)tiles), dim3(256), 0, stream,
-                         (const float2*)X, ldx, Kc, ncols, (unsigned short*)work, ldxb);
+    if (!x_expanded) expand_bf16x2(stream, X, ldx, Kc, ncols, work);
     if (variant == 2) {
       const dim3 grid((M + BM4 - 1) / BM4, tiles, splits);
       hipLaunchKernelGGL(cgemm_bf16x2_mfma_v3, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);

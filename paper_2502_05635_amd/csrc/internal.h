@@ -42,6 +42,7 @@ enum WsSlot {
   WS_INTRA,      // intraband term: covariant derivative of the stage state, c128 like the state
   WS_RHO_S2,     // intraband term, per-instance path: second stage-state buffer (stages alternate)
   WS_FTAB,       // field at the stage times of a chunk of steps, double [chunk][B][4]
+  WS_XE,         // batched BF16X2 path: the gather split by the stage kernel for the next product
   WS_COUNT
 };
 
@@ -113,6 +114,9 @@ void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, co
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
                   void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant, void* work,
                   bool x_expanded = false);
+// The split X of BF16X2 tilings 1 and 2 (complex64 [Kc][ldx], first ncols
+// instances; the rest of the last tile zero) written into `work`.
+void expand_bf16x2(hipStream_t stream, const void* X, int64_t ldx, int Kc, int ncols, void* work);
 // The split X of BF16X2 tilings 1 and 2 written into `work` straight from
 // `slices` split-K partial products (complex64 [Kc][ldx] each, `stride`
 // apart; ldx and stride even), summed in slice order: then call cgemm_bf16x2

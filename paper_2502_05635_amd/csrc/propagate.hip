@@ -29,6 +29,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "bf16x2.h"
 #include "covariant.h"
 #include "internal.h"
 
@@ -739,6 +740,17 @@ struct BatchParams {
   const double2* intra;  // intraband term e.(rho_s)_{;k} of this stage, laid out as rho_s; NULL = none
   int tr_signed;         // per-k trace partial signed (summed over k) instead of |.| (maximised)
   const double* ftab;    // field at the stage times, [obs slot][B][4] (field_table_kernel)
+  // the elements (n nb + m) the stage kernel updates: the upper triangle and
+  // diagonal when the state is Hermitian-packed, else all nb^2; pair elements
+  // (those that read the product) first.  Thread group g of a block takes
+  // entries g, g + nb, g + 2 nb, ...
+  int nelem;
+  int elist[TDG_NB_MAX * TDG_NB_MAX];
+  // the next gather also split for a BF16X2 product of the second or third
+  // tiling (bf16x2.h layout, Kc = N); NULL = not written.  Used with 64
+  // instances per block and a multiple of 4 pairs per k only.
+  unsigned short* xexp;
+  int64_t ldxb;
 };
 
 // The step counter of graph replays (vector stores: the address depends on the lane).
@@ -785,6 +797,21 @@ __device__ inline double2 pk_get(const double2* A, int nk, int nb, int64_t ldx, 
     return make_double2(reinterpret_cast<const double*>(A + (size_t)nk * U * ldx)[((size_t)k * nb + n) * ldx + b], 0.0);
   return A[((size_t)k * U + upper_slot(n, m, nb)) * ldx + b];
 }
+// The stage kernel's form of pk_get: one aligned 16-byte load and no branch.
+// Above the diagonal it is the element; on the diagonal it is the pair of
+// instances (b & ~1, b | 1) holding b's real value (ldx is even, so the pair
+// stays in its row), which pk_fix resolves at the first use.  A branch
+// between an 8- and a 16-byte load made the compiler wait for every load in
+// flight on the diagonal's path.
+__device__ inline double2 pk_load(const double2* A, int nk, int nb, int64_t ldx, int k, int n, int m, int b) {
+  const int U = nb * (nb - 1) / 2;
+  const double* dg = reinterpret_cast<const double*>(A + (size_t)nk * U * ldx) + ((size_t)k * nb + n) * ldx + (b & ~1);
+  const double2* p = m == n ? reinterpret_cast<const double2*>(dg) : A + ((size_t)k * U + upper_slot(n, m, nb)) * ldx + b;
+  return *p;
+}
+__device__ inline double2 pk_fix(double2 v, bool diag, int b) {
+  return diag ? make_double2((b & 1) ? v.y : v.x, 0.0) : v;
+}
 __device__ inline void pk_put(double2* A, int nk, int nb, int64_t ldx, int k, int n, int m, int b, double2 v) {
   const int U = nb * (nb - 1) / 2;
   if (m == n)
@@ -794,24 +821,43 @@ __device__ inline void pk_put(double2* A, int nk, int nb, int64_t ldx, int k, in
 }
 
 // One block per (k point, group of IB instances): thread t has lane i = t % IB
-// (instance group * IB + i) and row n = t / IB, and owns the row's elements
-// (n, m), m = 0 .. nb-1.  The instances' H and rho blocks are staged in LDS as
+// (instance group * IB + i) and group n = t / IB, and owns elements n, n + nb,
+// n + 2 nb, ... of bp.elist; the list puts the elements that read the product
+// first, so each group has about the same loads.  For the observables, group
+// n sums row n.  The instances' H and rho blocks are staged in LDS as
 // [element][lane] (dynamic LDS: 2 nb^2 IB double2), followed by the k point's
 // dipole and velocity planes and band energies (4 nb^2 double2 + nb double).
 // NBT: a bound on nb (4 or TDG_NB_MAX) sizing the per-thread row arrays.  The
 // observable sums [5][nb][IB] share the H blocks' LDS when they fit (nb >= 3):
 // they are consumed before H is built; otherwise they follow the H blocks.
-template <int NBT, bool PACK>
+// With bp.xexp, the next gather's P values per instance follow (P IB float2):
+// the block then writes its k point's 16-byte pieces of the split operand,
+// one per (plane, row, 4 pairs).
+// Workgroups are handed to the 8 XCDs in turn (block i to XCD i % 8), each
+// with its own L2.  This maps block i to k so that each XCD takes a
+// contiguous range of k points: the 16-byte pieces that neighbouring k points
+// write into one cache line of the split operand then meet in one L2.  A
+// bijection on [0, count).
+__device__ inline int xcd_block(int i, int count) {
+  const int q = count / 8, r = count % 8, x = i % 8, l = i / 8;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// WG: IB is one wave (64), so a wave's threads share their group and every
+// choice that depends on the group (which element, diagonal or not) is
+// uniform across the wave; the element list is then read by scalar loads and
+// no load waits at a divergent branch.
+template <int NBT, bool PACK, bool WG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBT <= 4 ? 3 : 1, 8)))
 batched_stage_kernel(BatchParams bp) {
   extern __shared__ double2 dyn_lds[];
-  const int nb = bp.nb, nb2 = nb * nb, IB = blockDim.x / nb;
+  const int nb = bp.nb, nb2 = nb * nb, IB = WG ? 64 : blockDim.x / nb;
   double2* s_rho = dyn_lds;
   double2* s_h = dyn_lds + nb2 * IB;
   const bool o_shared = nb >= 3;
   double* s_o = reinterpret_cast<double*>(o_shared ? s_h : dyn_lds + 2 * nb2 * IB);  // [5][nb][IB]
-  const int i = threadIdx.x % IB, n = threadIdx.x / IB;
-  const int k = blockIdx.x, b = blockIdx.y * IB + i;
+  const int i = threadIdx.x % IB, n = WG ? __builtin_amdgcn_readfirstlane(threadIdx.x / 64) : threadIdx.x / IB;
+  const int k = xcd_block(blockIdx.x, gridDim.x), b = blockIdx.y * IB + i;
   const bool act = b < bp.n_active, dyn = act && b < bp.n_dyn;
   const int step = bp.step_dev ? bp.step_dev[0] : bp.step;
   const int obs_slot = bp.step_dev ? step % bp.chunk : bp.obs_slot;
@@ -821,15 +867,26 @@ batched_stage_kernel(BatchParams bp) {
   // shared by the block's instances: [dx][dy][vx][vy] blocks, then eps
   double2* s_d = dyn_lds + 2 * nb2 * IB + (o_shared ? 0 : (5 * nb * IB + 1) / 2);
   double* s_eps = reinterpret_cast<double*>(s_d + 4 * nb2);
+  float2* s_x = reinterpret_cast<float2*>(s_eps + nb);  // [P][IB], with bp.xexp
   const bool want_obs = bp.stage == 0 && bp.obs_part;
-  for (int q = threadIdx.x; q < 4 * nb2; q += blockDim.x) {
-    const int pl = q / nb2, e = q - pl * nb2;
-    if (pl < 2)
-      s_d[q] = bp.dip[pl * plane + (size_t)k * nb2 + e];
-    else if (want_obs)
-      s_d[q] = bp.vel[(pl - 2) * plane + (size_t)k * nb2 + e];
+  // this k point's dipole / velocity planes and band energies go to LDS just
+  // before the first barrier; loaded here, their values are not waited for
+  // ahead of the state loads (at most two entries per thread: 4 nb^2 <= 2
+  // blockDim for every nb and IB the host uses)
+  double2 d_val[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  double e_val = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = threadIdx.x + h * blockDim.x;
+    if (q < 4 * nb2) {
+      const int pl = q / nb2, e = q - pl * nb2;
+      if (pl < 2)
+        d_val[h] = bp.dip[pl * plane + (size_t)k * nb2 + e];
+      else if (want_obs)
+        d_val[h] = bp.vel[(pl - 2) * plane + (size_t)k * nb2 + e];
+    }
   }
-  if (threadIdx.x < nb) s_eps[threadIdx.x] = bp.eps[(size_t)k * nb + threadIdx.x];
+  if (threadIdx.x < nb) e_val = bp.eps[(size_t)k * nb + threadIdx.x];
 
   tdg_field F = {};
   if (act) F = bp.fields[b];
@@ -839,31 +896,36 @@ batched_stage_kernel(BatchParams bp) {
   // product's slices for the row's pair elements, SG slices at a time (sums
   // in slice order).
   double2 rs[NBT], r_n[NBT], r_acc[NBT], ds[NBT], dv[NBT];
-  int prow[NBT];       // product row (k P + p) of element m, -1 = none
-  bool partner[NBT];   // element (v, c) of the conduction-valence block: conj of (c, v)
+  int ee[NBT];           // element n nb + m of slot q; -1: none
+  int prow[NBT];         // product row (k P + p) of slot q, -1 = none
+  bool partner[NBT];     // element (v, c) of the conduction-valence block: conj of (c, v)
 #pragma unroll
-  for (int m = 0; m < NBT; ++m) {
-    rs[m] = r_n[m] = r_acc[m] = ds[m] = dv[m] = make_double2(0.0, 0.0);
-    prow[m] = -1;
-    partner[m] = false;
-    if (m >= nb || !act) continue;
-    if (PACK && m < n) continue;  // elements below the diagonal: conjugates of those above
-    const size_t g = bidx(bp, k, n * nb + m, b);
-    rs[m] = PACK ? pk_get(bp.rho_s, bp.nk, nb, bp.ldx, k, n, m, b) : bp.rho_s[g];
+  for (int q = 0; q < NBT; ++q) {
+    rs[q] = r_n[q] = r_acc[q] = ds[q] = dv[q] = make_double2(0.0, 0.0);
+    prow[q] = -1;
+    partner[q] = false;
+    const int j = n + q * nb;
+    ee[q] = j < bp.nelem ? bp.elist[j] : -1;
+    if (WG) ee[q] = __builtin_amdgcn_readfirstlane(ee[q]);
+    if (ee[q] < 0 || !act) continue;
+    const int r = ee[q] / nb, c = ee[q] - r * nb;
+    const size_t g = bidx(bp, k, ee[q], b);
+    // packed: raw 16-byte loads, resolved by pk_fix at the first use
+    rs[q] = PACK ? pk_load(bp.rho_s, bp.nk, nb, bp.ldx, k, r, c, b) : bp.rho_s[g];
     if (!dyn) continue;
-    r_n[m] = PACK ? pk_get(bp.rho_n, bp.nk, nb, bp.ldx, k, n, m, b) : bp.rho_n[g];
-    if (bp.stage != 0) r_acc[m] = PACK ? pk_get(bp.acc, bp.nk, nb, bp.ldx, k, n, m, b) : bp.acc[g];
-    if (!PACK && bp.intra) dv[m] = bp.intra[g];
+    r_n[q] = PACK ? pk_load(bp.rho_n, bp.nk, nb, bp.ldx, k, r, c, b) : bp.rho_n[g];
+    if (bp.stage != 0) r_acc[q] = PACK ? pk_load(bp.acc, bp.nk, nb, bp.ldx, k, r, c, b) : bp.acc[g];
+    if (!PACK && bp.intra) dv[q] = bp.intra[g];
     int p = -1;
     if (bp.block == TDG_BLOCK_ALL) {
-      p = n * nb + m;
-    } else if (n >= bp.nv && m < bp.nv) {
-      p = (n - bp.nv) * bp.nv + m;
-    } else if (n < bp.nv && m >= bp.nv) {
-      p = (m - bp.nv) * bp.nv + n;
-      partner[m] = true;
+      p = r * nb + c;
+    } else if (r >= bp.nv && c < bp.nv) {
+      p = (r - bp.nv) * bp.nv + c;
+    } else if (r < bp.nv && c >= bp.nv) {
+      p = (c - bp.nv) * bp.nv + r;
+      partner[q] = true;
     }
-    if (p >= 0) prow[m] = k * P + p;
+    if (p >= 0) prow[q] = k * P + p;
   }
   float2 kd[NBT], xk[NBT];
   float yr[NBT], yi[NBT];
@@ -896,20 +958,26 @@ batched_stage_kernel(BatchParams bp) {
         }
   }
 #pragma unroll
-  for (int m = 0; m < NBT; ++m) {
-    if (prow[m] >= 0) {
-      float zr = yr[m], zi = yi[m];
+  for (int q = 0; q < NBT; ++q) {
+    if (prow[q] >= 0) {
+      float zr = yr[q], zi = yi[q];
       if (bp.kdiag) {
-        zr += kd[m].x * xk[m].x - kd[m].y * xk[m].y;
-        zi += kd[m].x * xk[m].y + kd[m].y * xk[m].x;
+        zr += kd[q].x * xk[q].x - kd[q].y * xk[q].y;
+        zi += kd[q].x * xk[q].y + kd[q].y * xk[q].x;
       }
-      ds[m] = make_double2((double)zr, partner[m] ? -(double)zi : (double)zi);
+      ds[q] = make_double2((double)zr, partner[q] ? -(double)zi : (double)zi);
     }
-    if (m < nb && (!PACK || m >= n)) {
-      s_rho[(n * nb + m) * IB + i] = rs[m];
-      if (PACK && m > n) s_rho[(m * nb + n) * IB + i] = make_double2(rs[m].x, -rs[m].y);
+    if (ee[q] >= 0) {
+      const int r = ee[q] / nb, c = ee[q] - r * nb;
+      if (PACK) rs[q] = pk_fix(rs[q], r == c, b);
+      s_rho[ee[q] * IB + i] = rs[q];
+      if (PACK && c > r) s_rho[(c * nb + r) * IB + i] = make_double2(rs[q].x, -rs[q].y);
     }
   }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (threadIdx.x + h * blockDim.x < 4 * nb2) s_d[threadIdx.x + h * blockDim.x] = d_val[h];
+  if (threadIdx.x < nb) s_eps[threadIdx.x] = e_val;
   __syncthreads();
 
   // observables of rho(t_n), per (k, instance): row sums, then a fixed-order sum over rows
@@ -957,27 +1025,28 @@ batched_stage_kernel(BatchParams bp) {
   const double ef = ef_stage;
   if (dyn) {
 #pragma unroll
-    for (int m = 0; m < NBT; ++m) {
-      if (m >= nb) break;
-      if (PACK && m < n) continue;
-      const int e = n * nb + m;
+    for (int q = 0; q < NBT; ++q) {
+      if (ee[q] < 0) continue;
+      const int e = ee[q], r = e / nb, c = e - r * nb;
       const double2 de = proj_e(F, s_d[e], s_d[nb2 + e]);
-      double2 h = make_double2(ds[m].x - ef * de.x, ds[m].y - ef * de.y);
-      if (n == m) h.x += s_eps[n];
-      if (PACK && n == m) h.y = 0.0;  // Hermitian: a real diagonal
+      double2 h = make_double2(ds[q].x - ef * de.x, ds[q].y - ef * de.y);
+      if (r == c) h.x += s_eps[r];
+      if (PACK && r == c) h.y = 0.0;  // Hermitian: a real diagonal
       s_h[e * IB + i] = h;
-      if (PACK && m > n) s_h[(m * nb + n) * IB + i] = make_double2(h.x, -h.y);
+      if (PACK && c > r) s_h[(c * nb + r) * IB + i] = make_double2(h.x, -h.y);
     }
   }
   __syncthreads();
-  if (!dyn) return;
 
   // f = -i [H, rho], RK4 stage, next drho gather
 #pragma unroll
-  for (int m = 0; m < NBT; ++m) {
-    if (m >= nb) break;
-    if (PACK && m < n) continue;
-    const int e = n * nb + m;
+  for (int q = 0; q < NBT; ++q) {
+    if (!dyn || ee[q] < 0) continue;
+    const int e = ee[q], n = e / nb, m = e - n * nb;
+    if (PACK) {
+      r_n[q] = pk_fix(r_n[q], n == m, b);
+      r_acc[q] = pk_fix(r_acc[q], n == m, b);
+    }
     double2 c = make_double2(0.0, 0.0);
     for (int l = 0; l < nb; ++l) {
       const double2 hr = cmul(s_h[(n * nb + l) * IB + i], s_rho[(l * nb + m) * IB + i]);
@@ -990,21 +1059,21 @@ batched_stage_kernel(BatchParams bp) {
     const size_t g = bidx(bp, k, e, b);
     if (!PACK && bp.intra) {
       // intraband part of the field term: -E(t) e.(rho)_{;k}
-      f.x -= ef * dv[m].x;
-      f.y -= ef * dv[m].y;
+      f.x -= ef * dv[q].x;
+      f.y -= ef * dv[q].y;
     }
     double2 next, accv = f;
     if (bp.stage == 0) {
-      next = make_double2(r_n[m].x + 0.5 * bp.dt * f.x, r_n[m].y + 0.5 * bp.dt * f.y);
+      next = make_double2(r_n[q].x + 0.5 * bp.dt * f.x, r_n[q].y + 0.5 * bp.dt * f.y);
     } else if (bp.stage == 1) {
-      accv = make_double2(r_acc[m].x + 2.0 * f.x, r_acc[m].y + 2.0 * f.y);
-      next = make_double2(r_n[m].x + 0.5 * bp.dt * f.x, r_n[m].y + 0.5 * bp.dt * f.y);
+      accv = make_double2(r_acc[q].x + 2.0 * f.x, r_acc[q].y + 2.0 * f.y);
+      next = make_double2(r_n[q].x + 0.5 * bp.dt * f.x, r_n[q].y + 0.5 * bp.dt * f.y);
     } else if (bp.stage == 2) {
-      accv = make_double2(r_acc[m].x + 2.0 * f.x, r_acc[m].y + 2.0 * f.y);
-      next = make_double2(r_n[m].x + bp.dt * f.x, r_n[m].y + bp.dt * f.y);
+      accv = make_double2(r_acc[q].x + 2.0 * f.x, r_acc[q].y + 2.0 * f.y);
+      next = make_double2(r_n[q].x + bp.dt * f.x, r_n[q].y + bp.dt * f.y);
     } else {
       const double w = bp.dt / 6.0;
-      next = make_double2(r_n[m].x + w * (r_acc[m].x + f.x), r_n[m].y + w * (r_acc[m].y + f.y));
+      next = make_double2(r_n[q].x + w * (r_acc[q].x + f.x), r_n[q].y + w * (r_acc[q].y + f.y));
     }
     if (PACK) {
       if (bp.stage < 3) pk_put(bp.acc, bp.nk, nb, bp.ldx, k, n, m, b, accv);
@@ -1016,16 +1085,47 @@ batched_stage_kernel(BatchParams bp) {
       bp.rho_s[g] = next;
     }
     const double dre = next.x - ((n == m && n < bp.nv) ? 1.0 : 0.0);
+    // pair p of this element (and, packed, pair pm of its mirror) gets x
+    int p = -1, pm = -1;
+    float xi = (float)next.y;
     if (bp.block == TDG_BLOCK_ALL) {
-      bp.xnext[((size_t)k * P + e) * bp.ldx + b] = make_float2((float)dre, (float)next.y);
-      if (PACK && m > n)  // the pair below the diagonal: conj of this one
-        bp.xnext[((size_t)k * P + m * nb + n) * bp.ldx + b] = make_float2((float)dre, -(float)next.y);
+      p = e;
+      if (PACK && m > n) pm = m * nb + n;  // the pair below the diagonal: conj of this one
     } else if (!PACK && n >= bp.nv && m < bp.nv) {
-      bp.xnext[((size_t)k * P + (n - bp.nv) * bp.nv + m) * bp.ldx + b] = make_float2((float)dre, (float)next.y);
+      p = (n - bp.nv) * bp.nv + m;
     } else if (PACK && n < bp.nv && m >= bp.nv) {
       // conduction-valence pair (m, n) from its partner above the diagonal
-      bp.xnext[((size_t)k * P + (m - bp.nv) * bp.nv + n) * bp.ldx + b] = make_float2((float)dre, -(float)next.y);
+      p = (m - bp.nv) * bp.nv + n;
+      xi = -xi;
     }
+    if (p >= 0) {
+      bp.xnext[((size_t)k * P + p) * bp.ldx + b] = make_float2((float)dre, xi);
+      if (bp.xexp) s_x[p * IB + i] = make_float2((float)dre, xi);
+    }
+    if (pm >= 0) {
+      bp.xnext[((size_t)k * P + pm) * bp.ldx + b] = make_float2((float)dre, -xi);
+      if (bp.xexp) s_x[pm * IB + i] = make_float2((float)dre, -xi);
+    }
+  }
+  if (!bp.xexp) return;
+  // the split operand of this k point: piece (plane, row c, pairs 4 g4 ..
+  // 4 g4 + 3) is 16 contiguous bytes of row c; rows of instances that no
+  // longer integrate are left as they are (their product columns are unused)
+  __syncthreads();
+  const int nch = P / 4, ct = blockIdx.y;
+  for (int q = threadIdx.x; q < 2 * tdg::XB_ROWS * nch; q += blockDim.x) {
+    const int plane = q / (tdg::XB_ROWS * nch), rem = q - plane * tdg::XB_ROWS * nch;
+    const int c = rem / nch, g4 = rem - c * nch, lane = c % tdg::XB_TILE;
+    if (blockIdx.y * IB + lane >= bp.n_dyn) continue;
+    uint4 w;
+    unsigned int* wp = reinterpret_cast<unsigned int*>(&w);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float2 v = s_x[(4 * g4 + u) * IB + lane];
+      wp[u] = tdg::xb_word(v.x, v.y, plane, c >= tdg::XB_TILE);
+    }
+    *reinterpret_cast<uint4*>(bp.xexp + ((size_t)(ct * 2 + plane) * tdg::XB_ROWS + c) * bp.ldxb +
+                              2 * ((size_t)k * P + 4 * g4)) = w;
   }
 }
 
@@ -1605,6 +1705,16 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     bp.dt = dt;
     bp.tr_signed = intra;
     bp.ftab = (const double*)ftab;
+    // the elements the stage kernel updates (Hermitian-packed unless the
+    // intraband term is on), the ones that read the product first
+    bp.nelem = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int r = 0; r < model->nb; ++r)
+        for (int c = 0; c < model->nb; ++c) {
+          if (!intra && c < r) continue;
+          const bool pair = op->block == TDG_BLOCK_ALL || (r >= model->nv) != (c >= model->nv);
+          if (pair == (pass == 0)) bp.elist[bp.nelem++] = r * model->nb + c;
+        }
     // stage kernel blocks: IB instances x nb rows, LDS for their H and rho blocks and row sums
     int IB = 16;  // instances per block: up to 64 for nb <= 4, matched to the batch
     while (model->nb <= 4 && IB < 64 && IB < batch) IB *= 2;
@@ -1621,6 +1731,17 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     // BF16X2: the second tiling needs X split once into a bf16 work array
     void* xbw = nullptr;
     if (bf16) TDG_TRY(ws_reserve(ctx, WS_XB, cgemm_bf16x2_work_bytes((int)n, batch), &xbw));
+    // With those tilings the stage kernel can write the next gather split as
+    // well, which saves the product's own split of X (64 instances per stage
+    // block and whole 16-byte pieces of 4 pairs).  The array is cleared once:
+    // its padding past 2N stays zero.
+    void* xe = nullptr;
+    const bool fuse_ok = bf16 && IB == tdg::XB_TILE && npair % 4 == 0;
+    if (fuse_ok) {
+      const size_t xe_bytes = cgemm_bf16x2_work_bytes((int)n, batch);
+      TDG_TRY(ws_reserve(ctx, WS_XE, xe_bytes, &xe));
+      TDG_TRY(hip_check(ctx, hipMemsetAsync(xe, 0, xe_bytes, ctx->stream), "split gather clear"));
+    }
     const int ntilings = 3;  // FP32: 64-row, prefetching 64-row, 128-row; BF16X2: 64-row, 128-row, 256-row
     if (n_dyn0 > 0) {
       // Split-K candidates: the default (about 1024 blocks), no split, twice
@@ -1719,12 +1840,20 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       void* xt = x1;
       hipLaunchKernelGGL(pattern_fill_kernel, dim3(1024), dim3(256), 0, ctx->stream, (float2*)xt,
                          (int64_t)n * xstride);
+      // tilings 1 and 2 then read X split by the stage kernel: timed without their own split
+      if (fuse_ok) expand_bf16x2(ctx->stream, xt, xstride, (int)n, n_dyn0, xe);
+      auto gemm_x = [&](hipStream_t st, const void* A, int64_t lda, int M, const void* X, void* Y, int64_t ystride,
+                        int ks, int v) {
+        if (fuse_ok && v > 0)
+          cgemm_bf16x2(st, A, lda, M, (int)n, nullptr, xstride, Y, ldy, ystride, n_dyn0, ks, v, xe, true);
+        else
+          cgemm_bf16x2(st, A, lda, M, (int)n, X, xstride, Y, ldy, ystride, n_dyn0, ks, v, xbw);
+      };
       const int64_t ld_us0 = bf16 ? (op->rank + 3) / 4 * 4 : op->rank;
       if (!lowrank) {
         TDG_TRY(pick("dense", n, n, ks_main, [&](int v, int64_t ks) {
           if (bf16)
-            cgemm_bf16x2(ctx->stream, op->K, op->ld, (int)n, (int)n, xt, xstride, Ybuf, ldy, n * ldy, n_dyn0,
-                         (int)ks, v, xbw);
+            gemm_x(ctx->stream, op->K, op->ld, (int)n, xt, Ybuf, n * ldy, (int)ks, v);
           else
             cgemm_f32(ctx->stream, op->K, op->ld, (int)n, (int)n, xt, xstride, Ybuf, ldy, n * ldy, n_dyn0,
                       (int)ks, v);
@@ -1734,8 +1863,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       } else {
         TDG_TRY(pick("project", op->rank, n, ks_proj, [&](int v, int64_t ks) {
           if (bf16)
-            cgemm_bf16x2(ctx->stream, op->w, n, (int)op->rank, (int)n, xt, xstride, Zbuf, ldy, op->rank * ldy,
-                         n_dyn0, (int)ks, v, xbw);
+            gemm_x(ctx->stream, op->w, n, (int)op->rank, xt, Zbuf, op->rank * ldy, (int)ks, v);
           else
             cgemm_f32(ctx->stream, op->w, n, (int)op->rank, (int)n, xt, xstride, Zbuf, ldy, op->rank * ldy,
                       n_dyn0, (int)ks, v);
@@ -1764,6 +1892,14 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       }
       bp.y_slices = y_slices;
     }
+    // the stage kernel writes the next gather split when the product that
+    // reads the gather (the projection, or the dense product) uses tiling 1
+    // or 2; the first stage's gather is split here
+    const bool fuse_x = fuse_ok && (lowrank ? gv_proj : gv_main) > 0;
+    bp.xexp = fuse_x ? (unsigned short*)xe : nullptr;
+    bp.ldxb = 2 * ((n + 31) / 32 * 32);
+    if (fuse_x) expand_bf16x2(ctx->stream, x0, xstride, (int)n, n_dyn0, xe);
+    const size_t stage_lds_run = stage_lds + (fuse_x ? (size_t)npair * IB * sizeof(float2) : 0);
     ctx->last_variant = std::string(lowrank ? "batched_mfma_lowrank_" : "batched_mfma_dense_") +
                         (bf16 ? "bf16x2" : "f32");
     ctx->last_variant += lowrank ? " (tilings " + std::to_string(gv_proj) + "/" + std::to_string(gv_main) +
@@ -1790,7 +1926,10 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
           if (prof) prof_begin(ctx, TDG_KCLASS_GEMM);
           const int64_t ld_us = bf16 ? (op->rank + 3) / 4 * 4 : op->rank;
           if (!lowrank) {
-            if (bf16)
+            if (fuse_x)
+              cgemm_bf16x2(st, op->K, op->ld, (int)n, (int)n, nullptr, xstride, Ybuf, ldy, n * ldy, n_dyn,
+                           (int)ks_main, gv_main, xe, true);
+            else if (bf16)
               cgemm_bf16x2(st, op->K, op->ld, (int)n, (int)n, xc, xstride, Ybuf, ldy, n * ldy, n_dyn, (int)ks_main,
                            gv_main, xbw);
             else
@@ -1798,7 +1937,10 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
                         (int)ks_main, gv_main);
           } else {
             // projection split over K, summed once in fixed order, then expansion
-            if (bf16)
+            if (fuse_x)
+              cgemm_bf16x2(st, op->w, n, (int)op->rank, (int)n, nullptr, xstride, Zbuf, ldy, op->rank * ldy, n_dyn,
+                           (int)ks_proj, gv_proj, xe, true);
+            else if (bf16)
               cgemm_bf16x2(st, op->w, n, (int)op->rank, (int)n, xc, xstride, Zbuf, ldy, op->rank * ldy, n_dyn,
                            (int)ks_proj, gv_proj, xbw);
             else
@@ -1834,14 +1976,18 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
         // Hermitian-packed state unless the intraband term (which reads the
         // full stage state) is on
         const dim3 sg(nk, (active + IB - 1) / IB), sb(IB * model->nb);
-        if (model->nb <= 4 && !intra)
-          hipLaunchKernelGGL((batched_stage_kernel<4, true>), sg, sb, stage_lds, st, bp);
+        if (model->nb <= 4 && !intra && IB == 64)
+          hipLaunchKernelGGL((batched_stage_kernel<4, true, true>), sg, sb, stage_lds_run, st, bp);
+        else if (model->nb <= 4 && IB == 64)
+          hipLaunchKernelGGL((batched_stage_kernel<4, false, true>), sg, sb, stage_lds_run, st, bp);
+        else if (model->nb <= 4 && !intra)
+          hipLaunchKernelGGL((batched_stage_kernel<4, true, false>), sg, sb, stage_lds_run, st, bp);
         else if (model->nb <= 4)
-          hipLaunchKernelGGL((batched_stage_kernel<4, false>), sg, sb, stage_lds, st, bp);
+          hipLaunchKernelGGL((batched_stage_kernel<4, false, false>), sg, sb, stage_lds_run, st, bp);
         else if (!intra)
-          hipLaunchKernelGGL((batched_stage_kernel<TDG_NB_MAX, true>), sg, sb, stage_lds, st, bp);
+          hipLaunchKernelGGL((batched_stage_kernel<TDG_NB_MAX, true, false>), sg, sb, stage_lds_run, st, bp);
         else
-          hipLaunchKernelGGL((batched_stage_kernel<TDG_NB_MAX, false>), sg, sb, stage_lds, st, bp);
+          hipLaunchKernelGGL((batched_stage_kernel<TDG_NB_MAX, false, false>), sg, sb, stage_lds_run, st, bp);
         if (prof) prof_end(ctx, TDG_KCLASS_STAGE);
         std::swap(xc, xn);
       }
