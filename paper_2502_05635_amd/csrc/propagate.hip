@@ -1747,15 +1747,20 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       // Split-K candidates: the default (about 1024 blocks), no split, twice
       // the default, and slice counts that put about 256 j blocks (j = 1..4)
       // on the 256 CUs; at most twice the default (the buffers' size).
+      // Slice widths are multiples of 16 complex columns (one LDS stage of
+      // every tiling); the counts aim at about 256 j blocks for 64-row tiles
+      // (j = 1..4) and for the 128- and 256-row tiles (j = 1, 2).
       auto split_options = [&](int64_t M, int64_t Kc, int64_t ks_def) {
-        const int64_t tiles = ((M + tile - 1) / tile) * ((n_dyn0 + 63) / 64);
+        const int64_t ctiles = (n_dyn0 + 63) / 64;
         const int64_t s_def = (Kc + ks_def - 1) / ks_def;
         std::vector<int64_t> out{ks_def};
         std::vector<int64_t> counts{1, 2 * s_def};
-        for (int j = 1; j <= 4; ++j) counts.push_back((256 * j) / tiles);
+        for (int j = 1; j <= 4; ++j) counts.push_back((256 * j) / (((M + tile - 1) / tile) * ctiles));
+        for (int64_t rows : {128, 256})
+          for (int j = 1; j <= 2; ++j) counts.push_back((256 * j) / (((M + rows - 1) / rows) * ctiles));
         for (int64_t sc : counts) {
           if (sc < 1 || sc > 2 * s_def) continue;
-          const int64_t ks = std::max<int64_t>(32, ((Kc + sc - 1) / sc + 31) / 32 * 32);
+          const int64_t ks = std::max<int64_t>(16, ((Kc + sc - 1) / sc + 15) / 16 * 16);
           if (std::find(out.begin(), out.end(), ks) == out.end()) out.push_back(ks);
         }
         return out;
