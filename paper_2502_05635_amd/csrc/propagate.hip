@@ -869,10 +869,11 @@ batched_stage_kernel(BatchParams bp) {
   double* s_eps = reinterpret_cast<double*>(s_d + 4 * nb2);
   float2* s_x = reinterpret_cast<float2*>(s_eps + nb);  // [P][IB], with bp.xexp
   const bool want_obs = bp.stage == 0 && bp.obs_part;
-  // this k point's dipole / velocity planes and band energies go to LDS just
-  // before the first barrier; loaded here, their values are not waited for
-  // ahead of the state loads (at most two entries per thread: 4 nb^2 <= 2
-  // blockDim for every nb and IB the host uses)
+  // this k point's dipole / velocity planes and band energies: with WG they
+  // go to LDS just before the first barrier, so their loads are not waited
+  // for ahead of the state loads (at most two entries per thread: 4 nb^2 <=
+  // 2 blockDim for every nb and IB the host uses); otherwise they are stored
+  // at once, which holds fewer registers
   double2 d_val[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
   double e_val = 0.0;
 #pragma unroll
@@ -884,9 +885,11 @@ batched_stage_kernel(BatchParams bp) {
         d_val[h] = bp.dip[pl * plane + (size_t)k * nb2 + e];
       else if (want_obs)
         d_val[h] = bp.vel[(pl - 2) * plane + (size_t)k * nb2 + e];
+      if (!WG) s_d[q] = d_val[h];
     }
   }
   if (threadIdx.x < nb) e_val = bp.eps[(size_t)k * nb + threadIdx.x];
+  if (!WG && threadIdx.x < nb) s_eps[threadIdx.x] = e_val;
 
   tdg_field F = {};
   if (act) F = bp.fields[b];
@@ -974,10 +977,12 @@ batched_stage_kernel(BatchParams bp) {
       if (PACK && c > r) s_rho[(c * nb + r) * IB + i] = make_double2(rs[q].x, -rs[q].y);
     }
   }
+  if (WG) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-    if (threadIdx.x + h * blockDim.x < 4 * nb2) s_d[threadIdx.x + h * blockDim.x] = d_val[h];
-  if (threadIdx.x < nb) s_eps[threadIdx.x] = e_val;
+    for (int h = 0; h < 2; ++h)
+      if (threadIdx.x + h * blockDim.x < 4 * nb2) s_d[threadIdx.x + h * blockDim.x] = d_val[h];
+    if (threadIdx.x < nb) s_eps[threadIdx.x] = e_val;
+  }
   __syncthreads();
 
   // observables of rho(t_n), per (k, instance): row sums, then a fixed-order sum over rows
