@@ -423,16 +423,18 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * TDG_OPT_GEMM_VARIANT -1 (default) times, on the first use of each product
  * shape (M, K, instances), every tiling with each of a few split-K widths (the
  * default of about 1024 blocks, no split, twice the default, and about 256 j
- * blocks for j = 1..4), each followed by one pass over the slices it wrote, and
- * keeps for the context the first pair (default split first) within 2 % of the
- * fastest.  FP32 tilings: 0 = 64-row tiles, 1 = 64-row tiles with the next K
- * tile prefetched into registers and two LDS buffers, 2 = 128-row tiles;
- * BF16X2 tilings 0 = 64-row tiles splitting X while staged, 1 = 128-row
+ * blocks for 64-row tiles (j = 1..4) and for 128- and 256-row tiles (j = 1, 2),
+ * in steps of 16 complex columns), each followed by one pass over the slices it
+ * wrote, and keeps for the context the first pair (default split first) within
+ * 2 % of the fastest.  FP32 tilings: 0 = 64-row tiles, 1 = 64-row tiles with
+ * the next K tile prefetched into registers and two LDS buffers, 2 = 128-row
+ * tiles; BF16X2 tilings 0 = 64-row tiles splitting X while staged, 1 = 128-row
  * tiles on X split once per product, 2 = 256-row tiles on X split once, both
- * operands copied straight to LDS three stages deep.  A value >= 0 forces that tiling
- * with the default split (or the one TDG_OPT_GEMM_SLICES gives).  Tilings and
- * splits differ only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects
- * 0 / 2. */
+ * operands copied straight to LDS three stages deep, 3 = 128-row tiles on X
+ * split once with loads two stages ahead (two register sets, two LDS buffers).
+ * A value >= 0 forces that tiling (clamped to the last one) with the default
+ * split (or the one TDG_OPT_GEMM_SLICES gives).  Tilings and splits differ
+ * only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects 0 / 2. */
 #define TDG_OPT_GEMM_TILE 3
 #define TDG_OPT_GEMM_VARIANT 4
 /* 1 replays captured HIP graphs; 0 (default) launches every kernel directly.

@@ -639,10 +639,17 @@ constexpr int BKC3 = 16;
 constexpr int KR3 = 2 * BKC3;
 constexpr int LPAD3 = 8;
 
+// KR: real K per LDS stage, 32 (second tiling) or 64 (fourth tiling: rows
+// are read in 128-byte pieces per plane instead of 64-byte ones, two blocks
+// per CU by LDS).
+template <int KR>
 __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, const unsigned short* __restrict__ XB,
                                                              int64_t ldxb) {
-  __shared__ __align__(16) unsigned short As[2][BM3][KR3 + LPAD3];
-  __shared__ __align__(16) unsigned short Xs[2][XB_ROWS][KR3 + LPAD3];
+  constexpr int CH = KR / 8;       // 16-byte chunks per row and plane
+  constexpr int RPI = 256 / CH;    // rows one pass of the block's threads covers
+  constexpr int IT = 2 * BM3 / RPI;  // passes over both planes
+  __shared__ __align__(16) unsigned short As[2][BM3][KR + LPAD3];
+  __shared__ __align__(16) unsigned short Xs[2][XB_ROWS][KR + LPAD3];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.x * BM3, ct = blockIdx.y, b0 = ct * BNI, s = blockIdx.z;
   const int kc_begin = s * g.kslice;
@@ -656,28 +663,30 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
   // Tile loads go into registers (the next stage's while the current one is
   // multiplied); bf16 past the slice's K are zeroed when the tile is written to
   // LDS.  A chunk of 8 bf16 (4 complex) never crosses a split-K boundary
-  // (slices are multiples of 32 complex) and stays inside its row (ld % 4 == 0).
+  // (slices are multiples of 16 complex) and stays inside its row (ld % 4 == 0).
   const int kr_end = 2 * kc_end;
-  u32x4 ra[4], rx[4];
+  u32x4 ra[IT], rx[IT];
   auto load_tile = [&](int kc0) {
     const int kr0 = 2 * kc0;
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      // chunk q of row `row` in plane p (it = 0, 1: hi plane; 2, 3: lo plane)
-      const int q = t & 3, row = ((t >> 2) + 64 * it) & (BM3 - 1), p = it >> 1;
+    for (int it = 0; it < IT; ++it) {
+      // chunk q of row `row` in plane p (the first IT / 2 passes: hi plane)
+      const int q = t % CH, row = ((t / CH) + RPI * it) & (BM3 - 1), p = it / (IT / 2);
       const int kr = kr0 + 8 * q, gi = m0 + row;
       ra[it] = u32x4{0u, 0u, 0u, 0u};
       if (gi < g.M && kr < kr_end)
         ra[it] = *reinterpret_cast<const u32x4*>((p ? g.Alo : g.Ahi) + (int64_t)gi * 2 * g.lda + kr);
-      // X: the padded rows of XB cover every stage
-      rx[it] = *reinterpret_cast<const u32x4*>(XB + ((int64_t)(ct * 2 + p) * XB_ROWS + row) * ldxb + kr);
+      // X: zero past the padded row (a 64-K stage that starts 16 columns past
+      // a multiple of 32 can reach beyond ldxb; the padding itself is zero)
+      rx[it] = u32x4{0u, 0u, 0u, 0u};
+      if (kr < ldxb) rx[it] = *reinterpret_cast<const u32x4*>(XB + ((int64_t)(ct * 2 + p) * XB_ROWS + row) * ldxb + kr);
     }
   };
   auto store_tile = [&](int kc0) {
     const int kr0 = 2 * kc0;
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int q = t & 3, row = ((t >> 2) + 64 * it) & (BM3 - 1), p = it >> 1;
+    for (int it = 0; it < IT; ++it) {
+      const int q = t % CH, row = ((t / CH) + RPI * it) & (BM3 - 1), p = it / (IT / 2);
       const int kr = kr0 + 8 * q;
       u32x4 v = ra[it];
       // keep bf16 e of the chunk only while kr + e < kr_end (two per 32-bit word)
@@ -695,11 +704,11 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
     store_tile(kc_begin);
   }
   __syncthreads();
-  for (int kc0 = kc_begin; kc0 < kc_end; kc0 += BKC3) {
-    const bool more = kc0 + BKC3 < kc_end;
-    if (more) load_tile(kc0 + BKC3);
+  for (int kc0 = kc_begin; kc0 < kc_end; kc0 += KR / 2) {
+    const bool more = kc0 + KR / 2 < kc_end;
+    if (more) load_tile(kc0 + KR / 2);
 #pragma unroll
-    for (int ks = 0; ks < KR3; ks += 16) {
+    for (int ks = 0; ks < KR; ks += 16) {
       const int kb = ks + 8 * (lane >> 5);
       bf16x8 ah[2], al[2], xh[2], xl[2];
 #pragma unroll
@@ -720,7 +729,7 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
         }
     }
     __syncthreads();
-    if (more) store_tile(kc0 + BKC3);
+    if (more) store_tile(kc0 + KR / 2);
     __syncthreads();
   }
 
@@ -965,9 +974,10 @@ void sum_expand_bf16x2(hipStream_t stream, const void* in, int slices, int64_t s
                      (const float4*)in, slices, stride / 2, Kc, ldx / 2, ncols, tiles, (unsigned short*)work, ldxb);
 }
 
-// variant 0: 64-row tiles, X split while staged; variants 1 and 2: X split and
+// variant 0: 64-row tiles, X split while staged; variants 1 to 3: X split and
 // expanded once into `work` (cgemm_bf16x2_work_bytes), then 128-row tiles
-// (variant 1) or 256-row tiles staged by direct-to-LDS loads (variant 2).
+// (variant 1), 256-row tiles staged by direct-to-LDS loads (variant 2), or
+// 128-row tiles of 64 real K per stage (variant 3).
 // With x_expanded, `work` already holds that expansion (sum_expand_bf16x2)
 // and X is not read.
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
@@ -987,17 +997,22 @@ void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc,
   g.ncols = ncols;
   g.kslice = kslice;
   const int splits = (Kc + kslice - 1) / kslice;
-  if ((variant == 1 || variant == 2) && work) {
+  if (variant >= 1 && variant <= 3 && work) {
     const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
     const int tiles = (ncols + BNI - 1) / BNI;
     if (!x_expanded) expand_bf16x2(stream, X, ldx, Kc, ncols, work);
+    if (variant == 3) {
+      const dim3 grid((M + BM3 - 1) / BM3, tiles, splits);
+      hipLaunchKernelGGL(cgemm_bf16x2_mfma_v2<64>, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
+      return;
+    }
     if (variant == 2) {
       const dim3 grid((M + BM4 - 1) / BM4, tiles, splits);
       hipLaunchKernelGGL(cgemm_bf16x2_mfma_v3, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
       return;
     }
     const dim3 grid((M + BM3 - 1) / BM3, tiles, splits);
-    hipLaunchKernelGGL(cgemm_bf16x2_mfma_v2, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
+    hipLaunchKernelGGL(cgemm_bf16x2_mfma_v2<32>, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
     return;
   }
   const dim3 grid((M + BM - 1) / BM, (ncols + BNI - 1) / BNI, splits);

@@ -1747,7 +1747,9 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       TDG_TRY(ws_reserve(ctx, WS_XE, xe_bytes, &xe));
       TDG_TRY(hip_check(ctx, hipMemsetAsync(xe, 0, xe_bytes, ctx->stream), "split gather clear"));
     }
-    const int ntilings = 3;  // FP32: 64-row, prefetching 64-row, 128-row; BF16X2: 64-row, 128-row, 256-row
+    // FP32: 64-row, prefetching 64-row, 128-row; BF16X2: 64-row, 128-row,
+    // 256-row, 128-row loading two stages ahead
+    const int ntilings = bf16 ? 4 : 3;
     if (n_dyn0 > 0) {
       // Split-K candidates: the default (about 1024 blocks), no split, twice
       // the default, and slice counts that put about 256 j blocks (j = 1..4)
@@ -1850,7 +1852,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       void* xt = x1;
       hipLaunchKernelGGL(pattern_fill_kernel, dim3(1024), dim3(256), 0, ctx->stream, (float2*)xt,
                          (int64_t)n * xstride);
-      // tilings 1 and 2 then read X split by the stage kernel: timed without their own split
+      // tilings 1 to 3 then read X split by the stage kernel: timed without their own split
       if (fuse_ok) expand_bf16x2(ctx->stream, xt, xstride, (int)n, n_dyn0, xe);
       auto gemm_x = [&](hipStream_t st, const void* A, int64_t lda, int M, const void* X, void* Y, int64_t ystride,
                         int ks, int v) {
@@ -1881,7 +1883,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
         }, &gv_proj, &ks_proj));
         z_slices = (int)((n + ks_proj - 1) / ks_proj);
         // Zsum now holds the step-0 projection (the expansion's timing input)
-        // BF16X2 tilings 1 and 2 take the split projection straight from its
+        // BF16X2 tilings 1 to 3 take the split projection straight from its
         // slices (one kernel instead of the slice sum and the split); tiling
         // 0 reads the summed projection, so its timing includes the sum
         TDG_TRY(pick("expand", n, op->rank, ks_main, [&](int v, int64_t ks) {
