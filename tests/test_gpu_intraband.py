@@ -233,6 +233,48 @@ def test_tb4_intraband_batched_path(P, ctx, tb4_6, k_tb4_6, kind):
     _compare(res, refs, tol, 1e-4)
 
 
+@pytest.mark.parametrize("links", [False, True])
+@pytest.mark.parametrize("tiling", [1, 3])
+def test_bf16x2_split_gather_written_by_stage_kernel(P, ctx, tb4_6, k_tb4_6, links, tiling):
+    """40 uneven instances (64 per stage-kernel block): with BF16X2 tiling 1
+    or 3 the batched stage kernel writes the next projection's split operand
+    itself, Hermitian-packed state without the intraband term, full state
+    with it.  Four instances against the FP64 oracle; all of them against the
+    same run on tiling 0, which splits X in the product (the tilings differ
+    only in summation order)."""
+    from paper_2502_05635_amd import _abi as abi
+    dm = _with_links(P, ctx, tb4_6) if links else P.DeviceModel.from_model(tb4_6)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c64")
+    op = ctx.kernel_compress(kg, "rank", 37, out_dtype="bf16x2")
+    rng = np.random.default_rng(33)
+    tabs = []
+    for i in range(40):
+        ns = int(rng.integers(20, 90))
+        t = ns * DT
+        tabs.append(FieldTable.single(10 ** rng.uniform(-3, -2), rng.uniform(0.5, 3.0) / HARTREE_EV,
+                                      max(t / 10.0, 0.5 * FS_AU), t / 2.0, ns, ex=np.cos(0.3 * i),
+                                      ey=np.sin(0.3 * i)))
+    fields = FieldTable.stack(tabs)
+    try:
+        ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, tiling)
+        res = ctx.propagate(op, dm, "eh", fields, DT)
+        assert f"tilings {tiling}/{tiling}" in ctx.last_variant()
+        ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, 0)
+        ref0 = ctx.propagate(op, dm, "eh", fields, DT)
+        assert "tilings 0/0" in ctx.last_variant()
+    finally:
+        ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
+    for key in ("P", "J", "occ"):
+        a, b = res[key].cpu().numpy(), ref0[key].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max(), key
+    oop = O.LowRankOp.from_factors(O.compress(k_tb4_6, "rank", 37))
+    lk = O.transport_links(tb4_6) if links else None
+    idx = [0, 13, 27, 39]
+    refs = [O.propagate(tb4_6, oop, "eh", fields, DT, instance=b, links=lk) for b in idx]
+    sub = {k: res[k][idx] for k in ("P", "J", "occ", "tr", "rho")}
+    _compare(sub, refs, 2e-3, 1e-4)
+
+
 def test_intraband_graph_replay_matches_direct(P, ctx, tb4_6):
     from paper_2502_05635_amd import _abi as abi
     dm = _with_links(P, ctx, tb4_6)
