@@ -746,8 +746,8 @@ struct BatchParams {
   // entries g, g + nb, g + 2 nb, ...
   int nelem;
   int elist[TDG_NB_MAX * TDG_NB_MAX];
-  // the next gather also split for a BF16X2 product of the second or third
-  // tiling (bf16x2.h layout, Kc = N); NULL = not written.  Used with 64
+  // the next gather also split for a BF16X2 product of tiling 1, 2 or 3
+  // (bf16x2.h layout, Kc = N); NULL = not written.  Used with 64
   // instances per block and a multiple of 4 pairs per k only.
   unsigned short* xexp;
   int64_t ldxb;
@@ -1654,7 +1654,8 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
 
   if (batched) {
     // split-K so that each product launches about 1024 blocks of 64 rows;
-    // slices are multiples of 32 complex columns (whole LDS stages)
+    // the default slices are multiples of 32 complex columns (whole LDS
+    // stages of every tiling: 16 columns, or 32 for BF16X2 tiling 3)
     const int tile = 64;
     auto kslice_for = [&](int64_t M, int64_t Kc) {
       const int64_t tiles = ((M + tile - 1) / tile) * ((batch + 63) / 64);
