@@ -4,13 +4,15 @@
 // kernels and by the batched stage kernel, which writes the split operand of
 // the next product directly.
 //
-// Split operand layout (the second and third product tilings): for tile ct of
-// XB_TILE instances, plane p (0 = hi, 1 = lo), row c < XB_ROWS and real K
-// index kr, XB[((ct * 2 + p) * XB_ROWS + c) * ldxb + kr] holds the real
-// expansion of x[k][XB_TILE ct + (c % XB_TILE)]: rows c < XB_TILE (real parts
-// of the outputs) carry (re, -im) at kr = (2k, 2k + 1), rows c >= XB_TILE
-// (imaginary parts) carry (im, re).  ldxb is 2 Kc rounded up to 64, and the
-// entries from 2 Kc up to ldxb are zero.
+// Split operand layout (product tilings 1 to 3): for tile ct of XB_TILE
+// instances, plane p (0 = hi, 1 = lo), instance c < XB_TILE and real K index
+// kr, XB[((ct * 2 + p) * XB_TILE + c) * ldxb + kr] holds (re, -im) of
+// x[k][XB_TILE ct + c] at kr = (2k, 2k + 1).  These are the rows of X's real
+// expansion that give the real parts of the outputs; the rows that give the
+// imaginary parts, (im, re), are the same words with their halves swapped
+// and one sign flipped (xb_imag), formed by the product kernels, so the
+// array holds half of the expansion.  ldxb is 2 Kc rounded up to 64, and the
+// entries from 2 Kc up to ldxb are zeros (of either sign).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,7 +20,7 @@
 namespace tdg {
 
 constexpr int XB_TILE = 64;            // instances per tile
-constexpr int XB_ROWS = 2 * XB_TILE;   // rows per tile and plane
+constexpr int XB_ROWS = 2 * XB_TILE;   // rows of the real expansion per tile and plane
 
 __device__ inline unsigned short f2bf(float f) {
   unsigned int u = __float_as_uint(f);
@@ -27,12 +29,17 @@ __device__ inline unsigned short f2bf(float f) {
 }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
-// The word (two bf16) of x = re + i im at K pair (2k, 2k + 1) of plane p, in a
-// row of real parts (imag_row false: (re, -im)) or of imaginary parts (im, re).
-__device__ inline unsigned int xb_word(float re, float im, int p, bool imag_row) {
+// The stored word (two bf16) of x = re + i im at K pair (2k, 2k + 1) of plane
+// p: (re, -im), the part's bf16 hi (p = 0) or the bf16 of its remainder (p = 1).
+__device__ inline unsigned int xb_word(float re, float im, int p) {
   const unsigned short rh = f2bf(re), ih = f2bf(im);
   const unsigned short r = p ? f2bf(re - bf2f(rh)) : rh, i = p ? f2bf(im - bf2f(ih)) : ih;
-  return imag_row ? ((unsigned int)i | ((unsigned int)r << 16)) : ((unsigned int)r | ((unsigned int)(i ^ 0x8000u) << 16));
+  return (unsigned int)r | ((unsigned int)(i ^ 0x8000u) << 16);
 }
+
+// The word of the imaginary-part row, (im, re), from a stored word (re, -im):
+// halves swapped, then the sign of the new low half flipped.  The split is
+// symmetric under negation, so this is exact in both planes.
+__device__ inline unsigned int xb_imag(unsigned int w) { return ((w >> 16) | (w << 16)) ^ 0x8000u; }
 
 }  // namespace tdg

@@ -27,6 +27,7 @@ namespace {
 
 using tdg::bf2f;
 using tdg::f2bf;
+using tdg::xb_imag;
 using tdg::xb_word;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -598,9 +599,9 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma(GemmBf16Args g) {
 }
 
 // ---- BF16 split-precision product, second tiling ---------------------------
-// X is split and expanded once per product into XB (bf16 bits, the layout of
-// bf16x2.h).  Rows are K-contiguous, so a lane's 8 consecutive K are one
-// 16-byte read.
+// X is split once per product into XB (bf16 bits, the layout of bf16x2.h:
+// the real-part rows of its expansion).  Rows are K-contiguous, so a lane's 8
+// consecutive K are one 16-byte read.
 using tdg::XB_ROWS;
 static_assert(tdg::XB_TILE == BNI, "split operand tiles hold one block's instances");
 
@@ -616,11 +617,11 @@ __global__ void __launch_bounds__(256) expand_bf16x2_kernel(const float2* __rest
     tile[r][b] = (k < Kc && bb < ncols) ? X[(int64_t)k * ldx + bb] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  for (int i = t; i < 2 * XB_ROWS * 32; i += 256) {
-    const int kk = i % 32, c = (i / 32) % XB_ROWS, p = i / (32 * XB_ROWS);
-    const float2 v = tile[kk][c % BNI];
-    *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + c) * ldxb + 2 * (k0 + kk)]) =
-        xb_word(v.x, v.y, p, c >= BNI);
+  for (int i = t; i < 2 * BNI * 32; i += 256) {
+    const int kk = i % 32, c = (i / 32) % BNI, p = i / (32 * BNI);
+    const float2 v = tile[kk][c];
+    *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * BNI + c) * ldxb + 2 * (k0 + kk)]) =
+        xb_word(v.x, v.y, p);
   }
 }
 
@@ -647,7 +648,8 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
                                                              int64_t ldxb) {
   constexpr int CH = KR / 8;       // 16-byte chunks per row and plane
   constexpr int RPI = 256 / CH;    // rows one pass of the block's threads covers
-  constexpr int IT = 2 * BM3 / RPI;  // passes over both planes
+  constexpr int IT = 2 * BM3 / RPI;  // passes over both planes of A
+  constexpr int ITX = IT / 2;        // of the stored (real-part) rows of X
   __shared__ __align__(16) unsigned short As[2][BM3][KR + LPAD3];
   __shared__ __align__(16) unsigned short Xs[2][XB_ROWS][KR + LPAD3];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -665,7 +667,7 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
   // LDS.  A chunk of 8 bf16 (4 complex) never crosses a split-K boundary
   // (slices are multiples of 16 complex) and stays inside its row (ld % 4 == 0).
   const int kr_end = 2 * kc_end;
-  u32x4 ra[IT], rx[IT];
+  u32x4 ra[IT], rx[ITX];
   auto load_tile = [&](int kc0) {
     const int kr0 = 2 * kc0;
 #pragma unroll
@@ -676,10 +678,16 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
       ra[it] = u32x4{0u, 0u, 0u, 0u};
       if (gi < g.M && kr < kr_end)
         ra[it] = *reinterpret_cast<const u32x4*>((p ? g.Alo : g.Ahi) + (int64_t)gi * 2 * g.lda + kr);
-      // X: zero past the padded row (a 64-K stage that starts 16 columns past
-      // a multiple of 32 can reach beyond ldxb; the padding itself is zero)
+    }
+#pragma unroll
+    for (int it = 0; it < ITX; ++it) {
+      // X: chunk q of stored row `row` in plane p; zero past the padded row (a
+      // 64-K stage that starts 16 columns past a multiple of 32 can reach
+      // beyond ldxb; the padding itself is zero)
+      const int q = t % CH, row = ((t / CH) + RPI * it) & (BNI - 1), p = it / (ITX / 2);
+      const int kr = kr0 + 8 * q;
       rx[it] = u32x4{0u, 0u, 0u, 0u};
-      if (kr < ldxb) rx[it] = *reinterpret_cast<const u32x4*>(XB + ((int64_t)(ct * 2 + p) * XB_ROWS + row) * ldxb + kr);
+      if (kr < ldxb) rx[it] = *reinterpret_cast<const u32x4*>(XB + ((int64_t)(ct * 2 + p) * BNI + row) * ldxb + kr);
     }
   };
   auto store_tile = [&](int kc0) {
@@ -695,7 +703,14 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
       v.z = bf16_pair_mask(v.z, kr + 4, kr_end);
       v.w = bf16_pair_mask(v.w, kr + 6, kr_end);
       *reinterpret_cast<u32x4*>(&As[p][row][8 * q]) = v;
-      *reinterpret_cast<u32x4*>(&Xs[p][row][8 * q]) = rx[it];
+    }
+#pragma unroll
+    for (int it = 0; it < ITX; ++it) {
+      // the stored row and the imaginary-part row it gives
+      const int q = t % CH, row = ((t / CH) + RPI * it) & (BNI - 1), p = it / (ITX / 2);
+      const u32x4 v = rx[it];
+      *reinterpret_cast<u32x4*>(&Xs[p][row][8 * q]) = v;
+      *reinterpret_cast<u32x4*>(&Xs[p][BNI + row][8 * q]) = u32x4{xb_imag(v.x), xb_imag(v.y), xb_imag(v.z), xb_imag(v.w)};
     }
   };
 
@@ -753,10 +768,12 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
 // ---- BF16 split-precision product, third tiling ----------------------------
 // 256 rows x 64 instances per block; wave w owns rows 64 w .. +63 and all 128
 // real columns as 2 x 4 MFMA accumulators, so a fragment read from LDS feeds
-// two (X) or four (A) products.  A (both planes) and the expanded X (as for
-// the second tiling) are copied straight into LDS by 16-byte direct-to-LDS
-// loads, into a ring of three stages of 16 complex K: the loads of the next
-// two stages are in flight while one is multiplied, with no registers held.
+// two (X) or four (A) products.  A (both planes) and the stored rows of the
+// split X (as for the second tiling) are copied straight into LDS by 16-byte
+// direct-to-LDS loads, into a ring of three stages of 16 complex K: the loads
+// of the next two stages are in flight while one is multiplied, with no
+// registers held.  The imaginary-part columns' X fragments are formed from
+// the real-part ones after they are read (xb_imag).
 // In a stage, row r of a plane is 4 chunks of 8 bf16 (64 bytes); chunk c sits
 // at slot c ^ ((r / 2) % 4), so the 32 rows of a fragment read spread over
 // all banks.  Rows past M read row M - 1 and K past the product reads chunk
@@ -766,7 +783,10 @@ constexpr int BM4 = 256;
 constexpr int KR4 = 32;                          // real K per stage
 constexpr int ST4 = 3;                           // stages in the ring
 constexpr int A4_BYTES = 2 * BM4 * KR4 * 2;      // both planes of a stage
-constexpr int X4_BYTES = 2 * XB_ROWS * KR4 * 2;
+constexpr int X4_BYTES = 2 * BNI * KR4 * 2;      // the stored X rows of a stage
+constexpr int A4_COPIES = 8;                     // 16-byte copies per lane and stage
+constexpr int X4_COPIES = 2;
+static_assert(A4_COPIES * 256 * 16 == A4_BYTES && X4_COPIES * 256 * 16 == X4_BYTES, "copies cover a stage");
 // s_waitcnt immediate with vmcnt = n (gfx9 encoding: bits 3:0 and 15:14),
 // expcnt and lgkmcnt at their maxima (no wait)
 constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
@@ -775,6 +795,13 @@ typedef __attribute__((address_space(1))) void gsrc_t;
 typedef __attribute__((address_space(3))) void ldst_t;
 
 __device__ inline int swz(int row, int c) { return c ^ ((row >> 1) & 3); }
+
+// xb_imag on each word of an X fragment
+__device__ inline bf16x8 imag_fragment(bf16x8 f) {
+  u32x4 v = __builtin_bit_cast(u32x4, f);
+  v = u32x4{xb_imag(v.x), xb_imag(v.y), xb_imag(v.z), xb_imag(v.w)};
+  return __builtin_bit_cast(bf16x8, v);
+}
 
 __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, const unsigned short* __restrict__ XB,
                                                              int64_t ldxb) {
@@ -788,14 +815,14 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
 
   // issue the direct-to-LDS copies of stage `st` (K from kc0) into ring slot q:
   // wave w copies A rows 16 (8 w + j) .. +15 of plane (8 w + j) / 16 ... (8 per
-  // wave) and X rows (4 per wave); lane l fills slot l % 4 of row l / 4
+  // wave) and X rows (2 per wave); lane l fills slot l % 4 of row l / 4
   auto issue = [&](int st, int q) {
     const int kr0 = 2 * (kc_begin + st * (KR4 / 2));
     unsigned char* abase = lds + q * (A4_BYTES + X4_BYTES);
     unsigned char* xbase = abase + A4_BYTES;
     const int rl = lane >> 2, sl = lane & 3;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < A4_COPIES; ++j) {
       const int ins = w * 8 + j, p = ins >> 4, row = 16 * (ins & 15) + rl;
       const int gi = min(m0 + row, g.M - 1);
       int kr = kr0 + 8 * swz(row, sl);
@@ -804,11 +831,10 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
       __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(abase + (p * BM4 + 16 * (ins & 15)) * 64), 16, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int ins = w * 4 + j, p = ins >> 3, row = 16 * (ins & 7) + rl;
-      const unsigned short* src =
-          XB + ((int64_t)(ct * 2 + p) * XB_ROWS + row) * ldxb + kr0 + 8 * swz(row, sl);
-      __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(xbase + (p * XB_ROWS + 16 * (ins & 7)) * 64), 16, 0, 0);
+    for (int j = 0; j < X4_COPIES; ++j) {
+      const int ins = w * X4_COPIES + j, p = ins >> 2, row = 16 * (ins & 3) + rl;
+      const unsigned short* src = XB + ((int64_t)(ct * 2 + p) * BNI + row) * ldxb + kr0 + 8 * swz(row, sl);
+      __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(xbase + (p * BNI + 16 * (ins & 3)) * 64), 16, 0, 0);
     }
   };
 
@@ -826,7 +852,7 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
     // this wave's copies of stage st have landed (those of st + 1 may not);
     // the barrier makes every wave's copies visible and frees slot (st + 2) % 3
     if (st + 1 < nst)
-      __builtin_amdgcn_s_waitcnt(waitcnt_vm(12));
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(A4_COPIES + X4_COPIES));
     else
       __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
     // a plain barrier: the waits above are the only ones the copies need (a
@@ -848,13 +874,19 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
         al[i] = *reinterpret_cast<const bf16x8*>(abase + BM4 * 64 + off);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 2; ++j) {
         const int row = 32 * j + (lane & 31);
         const int off = (row * 4 + swz(row, c)) * 16;
         xh[j] = *reinterpret_cast<const bf16x8*>(xbase + off);
-        xl[j] = *reinterpret_cast<const bf16x8*>(xbase + XB_ROWS * 64 + off);
+        xl[j] = *reinterpret_cast<const bf16x8*>(xbase + BNI * 64 + off);
       }
       __builtin_amdgcn_sched_barrier(0);
+      // the imaginary-part columns (fragments 2 and 3) from the real-part ones
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        xh[j + 2] = imag_fragment(xh[j]);
+        xl[j + 2] = imag_fragment(xl[j]);
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -882,7 +914,7 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
     }
 }
 
-// The expanded X of the second and third tilings (layout as for
+// The split X of tilings 1 to 3 (the layout of bf16x2.h, as written by
 // expand_bf16x2_kernel) straight from split-K slices of a product: x[k][b] =
 // sum over slices s in order of in[s stride + k ldx + b], for k < Kc and b <
 // ncols, zero elsewhere in [Kc rounded][tiles x 64].  Thread (pair o, slice
@@ -918,12 +950,8 @@ __global__ void __launch_bounds__(256) sum_expand_bf16x2_kernel(const float4* __
   for (int h = 0; h < 2; ++h) {
     const int bb = b + h, ct = bb / BNI, c = bb % BNI;
     const float re = (live && bb < ncols) ? (h ? r.z : r.x) : 0.f, im = (live && bb < ncols) ? (h ? r.w : r.y) : 0.f;
-    for (int p = 0; p < 2; ++p) {
-      *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + c) * ldxb + 2 * k]) =
-          xb_word(re, im, p, false);
-      *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * XB_ROWS + BNI + c) * ldxb + 2 * k]) =
-          xb_word(re, im, p, true);
-    }
+    for (int p = 0; p < 2; ++p)
+      *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * BNI + c) * ldxb + 2 * k]) = xb_word(re, im, p);
   }
 }
 
@@ -955,7 +983,7 @@ namespace tdg {
 
 size_t cgemm_bf16x2_work_bytes(int Kc, int ncols) {
   const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
-  return (size_t)((ncols + BNI - 1) / BNI) * 2 * XB_ROWS * ldxb * sizeof(unsigned short);
+  return (size_t)((ncols + BNI - 1) / BNI) * 2 * BNI * ldxb * sizeof(unsigned short);
 }
 
 void expand_bf16x2(hipStream_t stream, const void* X, int64_t ldx, int Kc, int ncols, void* work) {

@@ -1113,23 +1113,23 @@ batched_stage_kernel(BatchParams bp) {
     }
   }
   if (!bp.xexp) return;
-  // the split operand of this k point: piece (plane, row c, pairs 4 g4 ..
-  // 4 g4 + 3) is 16 contiguous bytes of row c; rows of instances that no
+  // the split operand of this k point: piece (plane, instance c, pairs 4 g4
+  // .. 4 g4 + 3) is 16 contiguous bytes of row c; rows of instances that no
   // longer integrate are left as they are (their product columns are unused)
   __syncthreads();
   const int nch = P / 4, ct = blockIdx.y;
-  for (int q = threadIdx.x; q < 2 * tdg::XB_ROWS * nch; q += blockDim.x) {
-    const int plane = q / (tdg::XB_ROWS * nch), rem = q - plane * tdg::XB_ROWS * nch;
-    const int c = rem / nch, g4 = rem - c * nch, lane = c % tdg::XB_TILE;
-    if (blockIdx.y * IB + lane >= bp.n_dyn) continue;
+  for (int q = threadIdx.x; q < 2 * tdg::XB_TILE * nch; q += blockDim.x) {
+    const int plane = q / (tdg::XB_TILE * nch), rem = q - plane * tdg::XB_TILE * nch;
+    const int c = rem / nch, g4 = rem - c * nch;
+    if (blockIdx.y * IB + c >= bp.n_dyn) continue;
     uint4 w;
     unsigned int* wp = reinterpret_cast<unsigned int*>(&w);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const float2 v = s_x[(4 * g4 + u) * IB + lane];
-      wp[u] = tdg::xb_word(v.x, v.y, plane, c >= tdg::XB_TILE);
+      const float2 v = s_x[(4 * g4 + u) * IB + c];
+      wp[u] = tdg::xb_word(v.x, v.y, plane);
     }
-    *reinterpret_cast<uint4*>(bp.xexp + ((size_t)(ct * 2 + plane) * tdg::XB_ROWS + c) * bp.ldxb +
+    *reinterpret_cast<uint4*>(bp.xexp + ((size_t)(ct * 2 + plane) * tdg::XB_TILE + c) * bp.ldxb +
                               2 * ((size_t)k * P + 4 * g4)) = w;
   }
 }
@@ -1749,7 +1749,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       TDG_TRY(hip_check(ctx, hipMemsetAsync(xe, 0, xe_bytes, ctx->stream), "split gather clear"));
     }
     // FP32: 64-row, prefetching 64-row, 128-row; BF16X2: 64-row, 128-row,
-    // 256-row, 128-row loading two stages ahead
+    // 256-row, 128-row with 64 real K per stage
     const int ntilings = bf16 ? 4 : 3;
     if (n_dyn0 > 0) {
       // Split-K candidates: the default (about 1024 blocks), no split, twice
