@@ -22,6 +22,7 @@
 
 #include "bf16x2.h"
 #include "internal.h"
+#include "xcd.h"
 
 namespace {
 
@@ -625,6 +626,10 @@ __global__ void __launch_bounds__(256) expand_bf16x2_kernel(const float2* __rest
   }
 }
 
+// Blocks take their (row tile, instance tile, K slice) XCD-aware: the row
+// tiles of one slice, which read the same slice of X, run on one XCD and
+// share its L2, so X is fetched about once per product.
+//
 // 128 rows x 64 instances per block, 16 complex K columns per LDS stage; wave
 // w owns rows 64*(w/2) .. +63 and real columns 64*(w%2) .. +63 as 2 x 2 MFMA
 // accumulators, so each 16-byte fragment read from LDS feeds six products.
@@ -653,7 +658,9 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
   __shared__ __align__(16) unsigned short As[2][BM3][KR + LPAD3];
   __shared__ __align__(16) unsigned short Xs[2][XB_ROWS][KR + LPAD3];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int m0 = blockIdx.x * BM3, ct = blockIdx.y, b0 = ct * BNI, s = blockIdx.z;
+  int bx, ct, s;
+  tdg::xcd_block3(bx, ct, s);
+  const int m0 = bx * BM3, b0 = ct * BNI;
   const int kc_begin = s * g.kslice;
   const int kc_end = min(g.Kc, kc_begin + g.kslice);
   const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
@@ -773,7 +780,8 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
 // direct-to-LDS loads, into a ring of three stages of 16 complex K: the loads
 // of the next two stages are in flight while one is multiplied, with no
 // registers held.  The imaginary-part columns' X fragments are formed from
-// the real-part ones after they are read (xb_imag).
+// the real-part ones after they are read (xb_imag).  Blocks are placed on the
+// XCDs as for the second tiling.
 // In a stage, row r of a plane is 4 chunks of 8 bf16 (64 bytes); chunk c sits
 // at slot c ^ ((r / 2) % 4), so the 32 rows of a fragment read spread over
 // all banks.  Rows past M read row M - 1 and K past the product reads chunk
@@ -807,7 +815,9 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
                                                              int64_t ldxb) {
   __shared__ __align__(16) unsigned char lds[ST4 * (A4_BYTES + X4_BYTES)];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int m0 = blockIdx.x * BM4, ct = blockIdx.y, b0 = ct * BNI, s = blockIdx.z;
+  int bx, ct, s;
+  tdg::xcd_block3(bx, ct, s);
+  const int m0 = bx * BM4, b0 = ct * BNI;
   const int kc_begin = s * g.kslice;
   const int kc_end = min(g.Kc, kc_begin + g.kslice);
   const int nst = (kc_end - kc_begin + KR4 / 2 - 1) / (KR4 / 2);

@@ -30,6 +30,7 @@
 #include <hip/hip_ext.h>
 
 #include "bf16x2.h"
+#include "xcd.h"
 #include "covariant.h"
 #include "internal.h"
 
@@ -833,15 +834,9 @@ __device__ inline void pk_put(double2* A, int nk, int nb, int64_t ldx, int k, in
 // With bp.xexp, the next gather's P values per instance follow (P IB float2):
 // the block then writes its k point's 16-byte pieces of the split operand,
 // one per (plane, row, 4 pairs).
-// Workgroups are handed to the 8 XCDs in turn (block i to XCD i % 8), each
-// with its own L2.  This maps block i to k so that each XCD takes a
-// contiguous range of k points: the 16-byte pieces that neighbouring k points
-// write into one cache line of the split operand then meet in one L2.  A
-// bijection on [0, count).
-__device__ inline int xcd_block(int i, int count) {
-  const int q = count / 8, r = count % 8, x = i % 8, l = i / 8;
-  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
+// Blocks map to k XCD-aware (xcd_block): each XCD takes a contiguous range of
+// k points, so the 16-byte pieces that neighbouring k points write into one
+// cache line of the split operand meet in one L2.
 
 // WG: IB is one wave (64), so a wave's threads share their group and every
 // choice that depends on the group (which element, diagonal or not) is
@@ -857,7 +852,7 @@ batched_stage_kernel(BatchParams bp) {
   const bool o_shared = nb >= 3;
   double* s_o = reinterpret_cast<double*>(o_shared ? s_h : dyn_lds + 2 * nb2 * IB);  // [5][nb][IB]
   const int i = threadIdx.x % IB, n = WG ? __builtin_amdgcn_readfirstlane(threadIdx.x / 64) : threadIdx.x / IB;
-  const int k = xcd_block(blockIdx.x, gridDim.x), b = blockIdx.y * IB + i;
+  const int k = tdg::xcd_block(blockIdx.x, gridDim.x), b = blockIdx.y * IB + i;
   const bool act = b < bp.n_active, dyn = act && b < bp.n_dyn;
   const int step = bp.step_dev ? bp.step_dev[0] : bp.step;
   const int obs_slot = bp.step_dev ? step % bp.chunk : bp.obs_slot;
