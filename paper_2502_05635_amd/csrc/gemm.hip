@@ -374,31 +374,40 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_pf(GemmArgs g) {
   }
 }
 
+// Thread group g of a slice sum adds slices g, g + 4, g + 8, ... of element
+// pair i in that order; the loads of up to SUM_PASS slices are issued before
+// the first add (the sums run to 80 slices and more).
+constexpr int SUM_PASS = 16;
+__device__ inline float4 group_slice_sum(const float4* __restrict__ in, int slices, int64_t stride2, int64_t i,
+                                         int g) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int s0 = g; s0 < slices; s0 += 4 * SUM_PASS) {
+    float4 a[SUM_PASS];
+#pragma unroll
+    for (int q = 0; q < SUM_PASS; ++q) {
+      a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (s0 + 4 * q < slices) a[q] = in[(int64_t)(s0 + 4 * q) * stride2 + i];
+    }
+#pragma unroll
+    for (int q = 0; q < SUM_PASS; ++q)
+      if (s0 + 4 * q < slices) {
+        v.x += a[q].x; v.y += a[q].y; v.z += a[q].z; v.w += a[q].w;
+      }
+  }
+  return v;
+}
+
 // out[i] = sum_s in[s * stride + i] for i < count (complex), fixed order.
 // Blocks of 64 outputs x 4 slice groups: thread (o, g) sums slices g, g + 4,
-// ... of its output pair (16-byte loads, four in flight), then the four group
-// sums are added in order.  count and stride are even (pairs of complex).
+// ... of its output pair (16-byte loads), then the four group sums are added
+// in order.  count and stride are even (pairs of complex).
 __global__ void __launch_bounds__(256) sum_slices_kernel(const float4* __restrict__ in, int slices, int64_t stride2,
                                                         int64_t count2, float4* __restrict__ out) {
   __shared__ float4 red[4][64];
   const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + o;
   float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (i < count2) {
-    int sl = g;
-    for (; sl + 12 < slices; sl += 16) {
-      const float4 a = in[sl * stride2 + i], b = in[(sl + 4) * stride2 + i], c = in[(sl + 8) * stride2 + i],
-                   d = in[(sl + 12) * stride2 + i];
-      v.x += a.x; v.y += a.y; v.z += a.z; v.w += a.w;
-      v.x += b.x; v.y += b.y; v.z += b.z; v.w += b.w;
-      v.x += c.x; v.y += c.y; v.z += c.z; v.w += c.w;
-      v.x += d.x; v.y += d.y; v.z += d.z; v.w += d.w;
-    }
-    for (; sl < slices; sl += 4) {
-      const float4 a = in[sl * stride2 + i];
-      v.x += a.x; v.y += a.y; v.z += a.z; v.w += a.w;
-    }
-  }
+  if (i < count2) v = group_slice_sum(in, slices, stride2, i, g);
   red[g][o] = v;
   __syncthreads();
   if (g == 0 && i < count2) {
@@ -942,13 +951,7 @@ __global__ void __launch_bounds__(256) sum_expand_bf16x2_kernel(const float4* __
   const int k = (int)(i / pairs_per_k), bp = (int)(i % pairs_per_k), b = 2 * bp;
   const bool live = i < npairs && k < Kc && b < ncols;
   float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (live) {
-    const int64_t e = (int64_t)k * ldx2 + bp;
-    for (int sl = g; sl < slices; sl += 4) {
-      const float4 a = in[sl * stride2 + e];
-      v.x += a.x; v.y += a.y; v.z += a.z; v.w += a.w;
-    }
-  }
+  if (live) v = group_slice_sum(in, slices, stride2, (int64_t)k * ldx2 + bp, g);
   red[g][o] = v;
   __syncthreads();
   if (g != 0 || i >= npairs) return;
