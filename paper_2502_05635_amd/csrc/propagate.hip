@@ -841,8 +841,11 @@ __device__ inline void pk_put(double2* A, int nk, int nb, int64_t ldx, int k, in
 // WG: IB is one wave (64), so a wave's threads share their group and every
 // choice that depends on the group (which element, diagonal or not) is
 // uniform across the wave; the element list is then read by scalar loads and
-// no load waits at a divergent branch.
-template <int NBT, bool PACK, bool WG>
+// no load waits at a divergent branch.  WIDE: every pair element is the first
+// entry of its group (at most nb of them), and only that slot's product
+// slices are loaded, SG0 at a time; without the other slots' slice registers
+// the kernel fits 4 waves per SIMD.
+template <int NBT, bool PACK, bool WG, bool WIDE = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBT <= 4 ? 3 : 1, 8)))
 batched_stage_kernel(BatchParams bp) {
   extern __shared__ double2 dyn_lds[];
@@ -891,8 +894,8 @@ batched_stage_kernel(BatchParams bp) {
   const double ef_stage = dyn ? bp.ftab[((size_t)obs_slot * bp.batch + b) * 4 + bp.stage] : 0.0;
   // Every global load of the thread's row is issued before its first use:
   // the state elements (and the intraband term), K_diag o x, then the
-  // product's slices for the row's pair elements, SG slices at a time (sums
-  // in slice order).
+  // product's slices for the row's pair elements, SG slices at a time, or
+  // SG0 when only the first slot holds pair elements (sums in slice order).
   double2 rs[NBT], r_n[NBT], r_acc[NBT], ds[NBT], dv[NBT];
   int ee[NBT];           // element n nb + m of slot q; -1: none
   int prow[NBT];         // product row (k P + p) of slot q, -1 = none
@@ -936,8 +939,26 @@ batched_stage_kernel(BatchParams bp) {
       xk[m] = bp.xcur[(size_t)prow[m] * bp.ldx + b];
     }
   }
+  if (WIDE) {
+    // only slot 0 reads the product: up to SG0 of its slices in flight at once
+    constexpr int SG0 = 16;
+    for (int s0 = 0; s0 < bp.y_slices; s0 += SG0) {
+      float2 yv[SG0];
+#pragma unroll
+      for (int q = 0; q < SG0; ++q)
+        yv[q] = (prow[0] >= 0 && s0 + q < bp.y_slices)
+                    ? bp.Y[(size_t)(s0 + q) * bp.y_slice_stride + (size_t)prow[0] * bp.ldy + b]
+                    : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int q = 0; q < SG0; ++q)
+        if (prow[0] >= 0 && s0 + q < bp.y_slices) {
+          yr[0] += yv[q].x;
+          yi[0] += yv[q].y;
+        }
+    }
+  }
   constexpr int SG = NBT <= 4 ? 4 : 2;  // slices per group
-  for (int s0 = 0; s0 < bp.y_slices; s0 += SG) {
+  for (int s0 = 0; s0 < (WIDE ? 0 : bp.y_slices); s0 += SG) {
     float2 yv[NBT][SG];
 #pragma unroll
     for (int m = 0; m < NBT; ++m)
@@ -1709,13 +1730,16 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     // the elements the stage kernel updates (Hermitian-packed unless the
     // intraband term is on), the ones that read the product first
     bp.nelem = 0;
+    int npe = 0;  // pair elements
     for (int pass = 0; pass < 2; ++pass)
       for (int r = 0; r < model->nb; ++r)
         for (int c = 0; c < model->nb; ++c) {
           if (!intra && c < r) continue;
           const bool pair = op->block == TDG_BLOCK_ALL || (r >= model->nv) != (c >= model->nv);
           if (pair == (pass == 0)) bp.elist[bp.nelem++] = r * model->nb + c;
+          if (pair && pass == 0) ++npe;
         }
+    const bool pair_slot0 = npe <= model->nb;
     // stage kernel blocks: IB instances x nb rows, LDS for their H and rho blocks and row sums
     int IB = 16;  // instances per block: up to 64 for nb <= 4, matched to the batch
     while (model->nb <= 4 && IB < 64 && IB < batch) IB *= 2;
@@ -1984,7 +2008,9 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
         // Hermitian-packed state unless the intraband term (which reads the
         // full stage state) is on
         const dim3 sg(nk, (active + IB - 1) / IB), sb(IB * model->nb);
-        if (model->nb <= 4 && !intra && IB == 64)
+        if (model->nb <= 4 && !intra && IB == 64 && pair_slot0)
+          hipLaunchKernelGGL((batched_stage_kernel<4, true, true, true>), sg, sb, stage_lds_run, st, bp);
+        else if (model->nb <= 4 && !intra && IB == 64)
           hipLaunchKernelGGL((batched_stage_kernel<4, true, true>), sg, sb, stage_lds_run, st, bp);
         else if (model->nb <= 4 && IB == 64)
           hipLaunchKernelGGL((batched_stage_kernel<4, false, true>), sg, sb, stage_lds_run, st, bp);
