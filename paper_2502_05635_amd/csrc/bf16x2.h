@@ -4,15 +4,17 @@
 // kernels and by the batched stage kernel, which writes the split operand of
 // the next product directly.
 //
-// Split operand layout (product tilings 1 to 3): for tile ct of XB_TILE
-// instances, plane p (0 = hi, 1 = lo), instance c < XB_TILE and real K index
-// kr, XB[((ct * 2 + p) * XB_TILE + c) * ldxb + kr] holds (re, -im) of
-// x[k][XB_TILE ct + c] at kr = (2k, 2k + 1).  These are the rows of X's real
-// expansion that give the real parts of the outputs; the rows that give the
-// imaginary parts, (im, re), are the same words with their halves swapped
-// and one sign flipped (xb_imag), formed by the product kernels, so the
-// array holds half of the expansion.  ldxb is 2 Kc rounded up to 64, and the
-// entries from 2 Kc up to ldxb are zeros (of either sign).
+// Split operand layout (product tilings 1 to 3): the stored part of X's real
+// expansion is the rows that give the real parts of the outputs, holding
+// (re, -im) of x[k][XB_TILE ct + c] at real K index kr = (2k, 2k + 1), for
+// tile ct of XB_TILE instances, plane p (0 = hi, 1 = lo) and instance c <
+// XB_TILE.  The rows that give the imaginary parts, (im, re), are the same
+// words with their halves swapped and one sign flipped (xb_imag), formed by
+// the product kernels.  The array is K-blocked: chunk j = kr / 8 of instance
+// c is 8 bf16 (16 bytes) at xb_index(ct, p, c, 8 j, ldxb), and the chunks of
+// the tile's 64 instances for one (p, j) are contiguous (1 KB).  ldxb is 2 Kc
+// rounded up to 64, and the entries from 2 Kc up to ldxb are zeros (of either
+// sign).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,6 +30,11 @@ __device__ inline unsigned short f2bf(float f) {
   return (unsigned short)(u >> 16);
 }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+// Element offset of real K index kr of instance c (tile ct, plane p).
+__host__ __device__ inline int64_t xb_index(int ct, int p, int c, int64_t kr, int64_t ldxb) {
+  return (((int64_t)(ct * 2 + p) * (ldxb / 8) + kr / 8) * XB_TILE + c) * 8 + kr % 8;
+}
 
 // The stored word (two bf16) of x = re + i im at K pair (2k, 2k + 1) of plane
 // p: (re, -im), the part's bf16 hi (p = 0) or the bf16 of its remainder (p = 1).

@@ -29,6 +29,7 @@ namespace {
 using tdg::bf2f;
 using tdg::f2bf;
 using tdg::xb_imag;
+using tdg::xb_index;
 using tdg::xb_word;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -627,11 +628,16 @@ __global__ void __launch_bounds__(256) expand_bf16x2_kernel(const float2* __rest
     tile[r][b] = (k < Kc && bb < ncols) ? X[(int64_t)k * ldx + bb] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  for (int i = t; i < 2 * BNI * 32; i += 256) {
-    const int kk = i % 32, c = (i / 32) % BNI, p = i / (32 * BNI);
-    const float2 v = tile[kk][c];
-    *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * BNI + c) * ldxb + 2 * (k0 + kk)]) =
-        xb_word(v.x, v.y, p);
+  // one 16-byte chunk (4 complex K of one instance) per thread and pass;
+  // consecutive threads write consecutive instances' chunks
+  for (int i = t; i < 2 * 8 * BNI; i += 256) {
+    const int c = i % BNI, j = (i / BNI) % 8, p = i / (8 * BNI);
+    uint4 w;
+    w.x = xb_word(tile[4 * j][c].x, tile[4 * j][c].y, p);
+    w.y = xb_word(tile[4 * j + 1][c].x, tile[4 * j + 1][c].y, p);
+    w.z = xb_word(tile[4 * j + 2][c].x, tile[4 * j + 2][c].y, p);
+    w.w = xb_word(tile[4 * j + 3][c].x, tile[4 * j + 3][c].y, p);
+    *reinterpret_cast<uint4*>(&XB[xb_index(ct, p, c, 2 * (k0 + 4 * j), ldxb)]) = w;
   }
 }
 
@@ -697,13 +703,14 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
     }
 #pragma unroll
     for (int it = 0; it < ITX; ++it) {
-      // X: chunk q of stored row `row` in plane p; zero past the padded row (a
-      // 64-K stage that starts 16 columns past a multiple of 32 can reach
-      // beyond ldxb; the padding itself is zero)
-      const int q = t % CH, row = ((t / CH) + RPI * it) & (BNI - 1), p = it / (ITX / 2);
+      // X: chunk q of stored row `row` in plane p, a wave taking one chunk of
+      // all 64 rows (1 KB contiguous); zero past the padded row (a 64-K stage
+      // that starts 16 columns past a multiple of 32 can reach beyond ldxb;
+      // the padding itself is zero)
+      const int u = t / BNI + 4 * it, row = t % BNI, q = u % CH, p = u / CH;
       const int kr = kr0 + 8 * q;
       rx[it] = u32x4{0u, 0u, 0u, 0u};
-      if (kr < ldxb) rx[it] = *reinterpret_cast<const u32x4*>(XB + ((int64_t)(ct * 2 + p) * BNI + row) * ldxb + kr);
+      if (kr < ldxb) rx[it] = *reinterpret_cast<const u32x4*>(XB + xb_index(ct, p, row, kr, ldxb));
     }
   };
   auto store_tile = [&](int kc0) {
@@ -723,7 +730,7 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
 #pragma unroll
     for (int it = 0; it < ITX; ++it) {
       // the stored row and the imaginary-part row it gives
-      const int q = t % CH, row = ((t / CH) + RPI * it) & (BNI - 1), p = it / (ITX / 2);
+      const int u = t / BNI + 4 * it, row = t % BNI, q = u % CH, p = u / CH;
       const u32x4 v = rx[it];
       *reinterpret_cast<u32x4*>(&Xs[p][row][8 * q]) = v;
       *reinterpret_cast<u32x4*>(&Xs[p][BNI + row][8 * q]) = u32x4{xb_imag(v.x), xb_imag(v.y), xb_imag(v.z), xb_imag(v.w)};
@@ -791,9 +798,10 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
 // registers held.  The imaginary-part columns' X fragments are formed from
 // the real-part ones after they are read (xb_imag).  Blocks are placed on the
 // XCDs as for the second tiling.
-// In a stage, row r of a plane is 4 chunks of 8 bf16 (64 bytes); chunk c sits
-// at slot c ^ ((r / 2) % 4), so the 32 rows of a fragment read spread over
-// all banks.  Rows past M read row M - 1 and K past the product reads chunk
+// In a stage, row r of a plane of A is 4 chunks of 8 bf16 (64 bytes); chunk c
+// sits at slot c ^ ((r / 2) % 4), so the 32 rows of a fragment read spread
+// over all banks.  X is kept as in memory, [plane][chunk][64 rows] (16 bytes
+// each): one copy instruction moves one chunk of all rows.  Rows past M read row M - 1 and K past the product reads chunk
 // 0 of the row: both multiply zeros of X or land in outputs never stored
 // (X is zero from K = Kc on, and the row's own columns Kc .. lda - 1 are).
 constexpr int BM4 = 256;
@@ -834,7 +842,8 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
 
   // issue the direct-to-LDS copies of stage `st` (K from kc0) into ring slot q:
   // wave w copies A rows 16 (8 w + j) .. +15 of plane (8 w + j) / 16 ... (8 per
-  // wave) and X rows (2 per wave); lane l fills slot l % 4 of row l / 4
+  // wave; lane l fills slot l % 4 of row l / 4) and two chunks of X (lane l:
+  // row l)
   auto issue = [&](int st, int q) {
     const int kr0 = 2 * (kc_begin + st * (KR4 / 2));
     unsigned char* abase = lds + q * (A4_BYTES + X4_BYTES);
@@ -851,9 +860,9 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
     }
 #pragma unroll
     for (int j = 0; j < X4_COPIES; ++j) {
-      const int ins = w * X4_COPIES + j, p = ins >> 2, row = 16 * (ins & 3) + rl;
-      const unsigned short* src = XB + ((int64_t)(ct * 2 + p) * BNI + row) * ldxb + kr0 + 8 * swz(row, sl);
-      __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(xbase + (p * BNI + 16 * (ins & 3)) * 64), 16, 0, 0);
+      const int ins = w * X4_COPIES + j, p = ins >> 2, c = ins & 3;
+      const unsigned short* src = XB + xb_index(ct, p, lane, kr0 + 8 * c, ldxb);
+      __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(xbase + (p * 4 + c) * BNI * 16), 16, 0, 0);
     }
   };
 
@@ -894,10 +903,9 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int row = 32 * j + (lane & 31);
-        const int off = (row * 4 + swz(row, c)) * 16;
+        const int off = (c * BNI + 32 * j + (lane & 31)) * 16;
         xh[j] = *reinterpret_cast<const bf16x8*>(xbase + off);
-        xl[j] = *reinterpret_cast<const bf16x8*>(xbase + BNI * 64 + off);
+        xl[j] = *reinterpret_cast<const bf16x8*>(xbase + 4 * BNI * 16 + off);
       }
       __builtin_amdgcn_sched_barrier(0);
       // the imaginary-part columns (fragments 2 and 3) from the real-part ones
@@ -964,7 +972,7 @@ __global__ void __launch_bounds__(256) sum_expand_bf16x2_kernel(const float4* __
     const int bb = b + h, ct = bb / BNI, c = bb % BNI;
     const float re = (live && bb < ncols) ? (h ? r.z : r.x) : 0.f, im = (live && bb < ncols) ? (h ? r.w : r.y) : 0.f;
     for (int p = 0; p < 2; ++p)
-      *reinterpret_cast<unsigned int*>(&XB[((int64_t)(ct * 2 + p) * BNI + c) * ldxb + 2 * k]) = xb_word(re, im, p);
+      *reinterpret_cast<unsigned int*>(&XB[xb_index(ct, p, c, 2 * k, ldxb)]) = xb_word(re, im, p);
   }
 }
 

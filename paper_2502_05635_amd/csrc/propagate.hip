@@ -828,15 +828,15 @@ __device__ inline void pk_put(double2* A, int nk, int nb, int64_t ldx, int k, in
 // n sums row n.  The instances' H and rho blocks are staged in LDS as
 // [element][lane] (dynamic LDS: 2 nb^2 IB double2), followed by the k point's
 // dipole and velocity planes and band energies (4 nb^2 double2 + nb double).
-// NBT: a bound on nb (4 or TDG_NB_MAX) sizing the per-thread row arrays.  The
+// NBT: a bound on nb (4 or TDG_NB_MAX); a thread holds NS element slots (3
+// for a packed block at nb <= 4, else NBT), at least its group's entries.  The
 // observable sums [5][nb][IB] share the H blocks' LDS when they fit (nb >= 3):
 // they are consumed before H is built; otherwise they follow the H blocks.
 // With bp.xexp, the next gather's P values per instance follow (P IB float2):
 // the block then writes its k point's 16-byte pieces of the split operand,
 // one per (plane, row, 4 pairs).
 // Blocks map to k XCD-aware (xcd_block): each XCD takes a contiguous range of
-// k points, so the 16-byte pieces that neighbouring k points write into one
-// cache line of the split operand meet in one L2.
+// k points.
 
 // WG: IB is one wave (64), so a wave's threads share their group and every
 // choice that depends on the group (which element, diagonal or not) is
@@ -896,12 +896,14 @@ batched_stage_kernel(BatchParams bp) {
   // the state elements (and the intraband term), K_diag o x, then the
   // product's slices for the row's pair elements, SG slices at a time, or
   // SG0 when only the first slot holds pair elements (sums in slice order).
-  double2 rs[NBT], r_n[NBT], r_acc[NBT], ds[NBT], dv[NBT];
-  int ee[NBT];           // element n nb + m of slot q; -1: none
-  int prow[NBT];         // product row (k P + p) of slot q, -1 = none
-  bool partner[NBT];     // element (v, c) of the conduction-valence block: conj of (c, v)
+  // element slots per thread: a packed block at nb <= 4 has at most 3 per group
+  constexpr int NS = (PACK && NBT <= 4) ? 3 : NBT;
+  double2 rs[NS], r_n[NS], r_acc[NS], ds[NS], dv[NS];
+  int ee[NS];           // element n nb + m of slot q; -1: none
+  int prow[NS];         // product row (k P + p) of slot q, -1 = none
+  bool partner[NS];     // element (v, c) of the conduction-valence block: conj of (c, v)
 #pragma unroll
-  for (int q = 0; q < NBT; ++q) {
+  for (int q = 0; q < NS; ++q) {
     rs[q] = r_n[q] = r_acc[q] = ds[q] = dv[q] = make_double2(0.0, 0.0);
     prow[q] = -1;
     partner[q] = false;
@@ -926,12 +928,12 @@ batched_stage_kernel(BatchParams bp) {
       p = (c - bp.nv) * bp.nv + r;
       partner[q] = true;
     }
-    if (p >= 0) prow[q] = k * P + p;
+    if (p >= 0 && (!WIDE || q == 0)) prow[q] = k * P + p;
   }
-  float2 kd[NBT], xk[NBT];
-  float yr[NBT], yi[NBT];
+  float2 kd[NS], xk[NS];
+  float yr[NS], yi[NS];
 #pragma unroll
-  for (int m = 0; m < NBT; ++m) {
+  for (int m = 0; m < NS; ++m) {
     yr[m] = yi[m] = 0.f;
     kd[m] = xk[m] = make_float2(0.f, 0.f);
     if (bp.kdiag && prow[m] >= 0) {
@@ -959,16 +961,16 @@ batched_stage_kernel(BatchParams bp) {
   }
   constexpr int SG = NBT <= 4 ? 4 : 2;  // slices per group
   for (int s0 = 0; s0 < (WIDE ? 0 : bp.y_slices); s0 += SG) {
-    float2 yv[NBT][SG];
+    float2 yv[NS][SG];
 #pragma unroll
-    for (int m = 0; m < NBT; ++m)
+    for (int m = 0; m < NS; ++m)
 #pragma unroll
       for (int q = 0; q < SG; ++q)
         yv[m][q] = (prow[m] >= 0 && s0 + q < bp.y_slices)
                        ? bp.Y[(size_t)(s0 + q) * bp.y_slice_stride + (size_t)prow[m] * bp.ldy + b]
                        : make_float2(0.f, 0.f);
 #pragma unroll
-    for (int m = 0; m < NBT; ++m)
+    for (int m = 0; m < NS; ++m)
 #pragma unroll
       for (int q = 0; q < SG; ++q)
         if (prow[m] >= 0 && s0 + q < bp.y_slices) {
@@ -977,7 +979,7 @@ batched_stage_kernel(BatchParams bp) {
         }
   }
 #pragma unroll
-  for (int q = 0; q < NBT; ++q) {
+  for (int q = 0; q < NS; ++q) {
     if (prow[q] >= 0) {
       float zr = yr[q], zi = yi[q];
       if (bp.kdiag) {
@@ -1046,7 +1048,7 @@ batched_stage_kernel(BatchParams bp) {
   const double ef = ef_stage;
   if (dyn) {
 #pragma unroll
-    for (int q = 0; q < NBT; ++q) {
+    for (int q = 0; q < NS; ++q) {
       if (ee[q] < 0) continue;
       const int e = ee[q], r = e / nb, c = e - r * nb;
       const double2 de = proj_e(F, s_d[e], s_d[nb2 + e]);
@@ -1061,7 +1063,7 @@ batched_stage_kernel(BatchParams bp) {
 
   // f = -i [H, rho], RK4 stage, next drho gather
 #pragma unroll
-  for (int q = 0; q < NBT; ++q) {
+  for (int q = 0; q < NS; ++q) {
     if (!dyn || ee[q] < 0) continue;
     const int e = ee[q], n = e / nb, m = e - n * nb;
     if (PACK) {
@@ -1129,14 +1131,14 @@ batched_stage_kernel(BatchParams bp) {
     }
   }
   if (!bp.xexp) return;
-  // the split operand of this k point: piece (plane, instance c, pairs 4 g4
-  // .. 4 g4 + 3) is 16 contiguous bytes of row c; rows of instances that no
-  // longer integrate are left as they are (their product columns are unused)
+  // the split operand of this k point: chunk g4 of instance c (pairs 4 g4 ..
+  // 4 g4 + 3) in plane p is 16 bytes, and the 64 instances' chunks are
+  // contiguous; rows of instances that no longer integrate are left as they
+  // are (their product columns are unused)
   __syncthreads();
   const int nch = P / 4, ct = blockIdx.y;
-  for (int q = threadIdx.x; q < 2 * tdg::XB_TILE * nch; q += blockDim.x) {
-    const int plane = q / (tdg::XB_TILE * nch), rem = q - plane * tdg::XB_TILE * nch;
-    const int c = rem / nch, g4 = rem - c * nch;
+  for (int q = threadIdx.x; q < 2 * nch * tdg::XB_TILE; q += blockDim.x) {
+    const int c = q % tdg::XB_TILE, g4 = (q / tdg::XB_TILE) % nch, plane = q / (tdg::XB_TILE * nch);
     if (blockIdx.y * IB + c >= bp.n_dyn) continue;
     uint4 w;
     unsigned int* wp = reinterpret_cast<unsigned int*>(&w);
@@ -1145,8 +1147,7 @@ batched_stage_kernel(BatchParams bp) {
       const float2 v = s_x[(4 * g4 + u) * IB + c];
       wp[u] = tdg::xb_word(v.x, v.y, plane);
     }
-    *reinterpret_cast<uint4*>(bp.xexp + ((size_t)(ct * 2 + plane) * tdg::XB_TILE + c) * bp.ldxb +
-                              2 * ((size_t)k * P + 4 * g4)) = w;
+    *reinterpret_cast<uint4*>(bp.xexp + tdg::xb_index(ct, plane, c, 2 * ((int64_t)k * P + 4 * g4), bp.ldxb)) = w;
   }
 }
 
