@@ -431,7 +431,7 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * tiles; BF16X2 tilings 0 = 64-row tiles splitting X while staged, 1 = 128-row
  * tiles on X split once per product, 2 = 256-row tiles on X split once, both
  * operands copied straight to LDS three stages deep, 3 = 128-row tiles on X
- * split once with loads two stages ahead (two register sets, two LDS buffers).
+ * split once with 64 real K per LDS stage, 4 = tiling 2 with 128-row tiles.
  * A value >= 0 forces that tiling (clamped to the last one) with the default
  * split (or the one TDG_OPT_GEMM_SLICES gives).  Tilings and splits differ
  * only in summation order.  TDG_OPT_GEMM_TILE 64 / 128 selects 0 / 2. */

@@ -4,7 +4,7 @@
 // kernels and by the batched stage kernel, which writes the split operand of
 // the next product directly.
 //
-// Split operand layout (product tilings 1 to 3): the stored part of X's real
+// Split operand layout (product tilings 1 to 4): the stored part of X's real
 // expansion is the rows that give the real parts of the outputs, holding
 // (re, -im) of x[k][XB_TILE ct + c] at real K index kr = (2k, 2k + 1), for
 // tile ct of XB_TILE instances, plane p (0 = hi, 1 = lo) and instance c <

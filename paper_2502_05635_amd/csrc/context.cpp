@@ -201,7 +201,7 @@ int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value) {
     return TDG_OK;
   }
   if (option == TDG_OPT_GEMM_VARIANT) {
-    if (value < -1 || value > 3) return fail(ctx, TDG_E_INVAL, "GEMM variant %lld outside [-1, 3]", (long long)value);
+    if (value < -1 || value > 4) return fail(ctx, TDG_E_INVAL, "GEMM variant %lld outside [-1, 4]", (long long)value);
     ctx->gemm_variant = (int)value;
     return TDG_OK;
   }

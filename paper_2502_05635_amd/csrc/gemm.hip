@@ -788,30 +788,31 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
     }
 }
 
-// ---- BF16 split-precision product, third tiling ----------------------------
-// 256 rows x 64 instances per block; wave w owns rows 64 w .. +63 and all 128
-// real columns as 2 x 4 MFMA accumulators, so a fragment read from LDS feeds
-// two (X) or four (A) products.  A (both planes) and the stored rows of the
-// split X (as for the second tiling) are copied straight into LDS by 16-byte
-// direct-to-LDS loads, into a ring of three stages of 16 complex K: the loads
-// of the next two stages are in flight while one is multiplied, with no
-// registers held.  The imaginary-part columns' X fragments are formed from
-// the real-part ones after they are read (xb_imag).  Blocks are placed on the
-// XCDs as for the second tiling.
+// ---- BF16 split-precision product, third and fifth tilings ----------------
+// BMT rows x 64 instances per block.  BMT = 256 (third tiling): wave w owns
+// rows 64 w .. +63 and all 128 real columns as 2 x 4 MFMA accumulators, so a
+// fragment read from LDS feeds two (X) or four (A) products.  BMT = 128
+// (fifth tiling): wave w owns rows 64 (w / 2) .. +63 and the real (w even) or
+// imaginary (w odd) output parts of the 64 instances as 2 x 2 accumulators.
+// A (both planes) and the stored rows of the split X are copied straight into
+// LDS by 16-byte direct-to-LDS loads, into a ring of three stages of 16
+// complex K: the loads of the next two stages are in flight while one is
+// multiplied, with no registers held.  The imaginary-part columns' X
+// fragments are formed from the real-part ones after they are read
+// (xb_imag).  Blocks are placed on the XCDs as for the second tiling.  The
+// ring takes 120 KB of LDS at BMT = 256 (one block per CU) and 72 KB at 128
+// (two).
 // In a stage, row r of a plane of A is 4 chunks of 8 bf16 (64 bytes); chunk c
 // sits at slot c ^ ((r / 2) % 4), so the 32 rows of a fragment read spread
 // over all banks.  X is kept as in memory, [plane][chunk][64 rows] (16 bytes
-// each): one copy instruction moves one chunk of all rows.  Rows past M read row M - 1 and K past the product reads chunk
-// 0 of the row: both multiply zeros of X or land in outputs never stored
-// (X is zero from K = Kc on, and the row's own columns Kc .. lda - 1 are).
-constexpr int BM4 = 256;
+// each): one copy instruction moves one chunk of all rows.  Rows past M read
+// row M - 1 and K past the product reads chunk 0 of the row: both multiply
+// zeros of X or land in outputs never stored (X is zero from K = Kc on, and
+// the row's own columns Kc .. lda - 1 are).
 constexpr int KR4 = 32;                          // real K per stage
 constexpr int ST4 = 3;                           // stages in the ring
-constexpr int A4_BYTES = 2 * BM4 * KR4 * 2;      // both planes of a stage
 constexpr int X4_BYTES = 2 * BNI * KR4 * 2;      // the stored X rows of a stage
-constexpr int A4_COPIES = 8;                     // 16-byte copies per lane and stage
-constexpr int X4_COPIES = 2;
-static_assert(A4_COPIES * 256 * 16 == A4_BYTES && X4_COPIES * 256 * 16 == X4_BYTES, "copies cover a stage");
+constexpr int X4_COPIES = X4_BYTES / (256 * 16);  // 16-byte copies per lane and stage
 // s_waitcnt immediate with vmcnt = n (gfx9 encoding: bits 3:0 and 15:14),
 // expcnt and lgkmcnt at their maxima (no wait)
 constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
@@ -828,35 +829,44 @@ __device__ inline bf16x8 imag_fragment(bf16x8 f) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+template <int BMT>
 __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, const unsigned short* __restrict__ XB,
                                                              int64_t ldxb) {
-  __shared__ __align__(16) unsigned char lds[ST4 * (A4_BYTES + X4_BYTES)];
+  static_assert(BMT == 256 || BMT == 128, "tile rows");
+  constexpr int A_BYTES = 2 * BMT * KR4 * 2;       // both planes of a stage
+  constexpr int A_COPIES = A_BYTES / (256 * 16);   // 16-byte copies per lane and stage
+  constexpr int A_INS = BMT / 16;                  // copy instructions per plane (16 rows each)
+  constexpr int NJ = BMT == 256 ? 4 : 2;           // column fragments per wave
+  __shared__ __align__(16) unsigned char lds[ST4 * (A_BYTES + X4_BYTES)];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int bx, ct, s;
   tdg::xcd_block3(bx, ct, s);
-  const int m0 = bx * BM4, b0 = ct * BNI;
+  const int m0 = bx * BMT, b0 = ct * BNI;
+  const int wr = BMT == 256 ? 64 * w : 64 * (w >> 1);  // the wave's first row
+  const int half = BMT == 256 ? 0 : (w & 1);            // BMT = 128: imaginary output parts
   const int kc_begin = s * g.kslice;
   const int kc_end = min(g.Kc, kc_begin + g.kslice);
   const int nst = (kc_end - kc_begin + KR4 / 2 - 1) / (KR4 / 2);
   const int64_t row_bf = 2 * g.lda;  // bf16 per row of a plane (columns Kc .. lda - 1 hold zeros)
 
   // issue the direct-to-LDS copies of stage `st` (K from kc0) into ring slot q:
-  // wave w copies A rows 16 (8 w + j) .. +15 of plane (8 w + j) / 16 ... (8 per
-  // wave; lane l fills slot l % 4 of row l / 4) and two chunks of X (lane l:
-  // row l)
+  // instruction ins copies A rows 16 (ins % A_INS) .. +15 of plane ins / A_INS
+  // (A_COPIES per wave; lane l fills slot l % 4 of row l / 4), and each wave
+  // two chunks of X (lane l: row l)
   auto issue = [&](int st, int q) {
     const int kr0 = 2 * (kc_begin + st * (KR4 / 2));
-    unsigned char* abase = lds + q * (A4_BYTES + X4_BYTES);
-    unsigned char* xbase = abase + A4_BYTES;
+    unsigned char* abase = lds + q * (A_BYTES + X4_BYTES);
+    unsigned char* xbase = abase + A_BYTES;
     const int rl = lane >> 2, sl = lane & 3;
 #pragma unroll
-    for (int j = 0; j < A4_COPIES; ++j) {
-      const int ins = w * 8 + j, p = ins >> 4, row = 16 * (ins & 15) + rl;
+    for (int j = 0; j < A_COPIES; ++j) {
+      const int ins = w * A_COPIES + j, p = ins / A_INS, row = 16 * (ins % A_INS) + rl;
       const int gi = min(m0 + row, g.M - 1);
       int kr = kr0 + 8 * swz(row, sl);
       if (kr + 8 > row_bf) kr = 0;  // past the row: any finite chunk (X is zero there)
       const unsigned short* src = (p ? g.Alo : g.Ahi) + (int64_t)gi * row_bf + kr;
-      __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(abase + (p * BM4 + 16 * (ins & 15)) * 64), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gsrc_t*)src, (ldst_t*)(abase + (p * BMT + 16 * (ins % A_INS)) * 64), 16, 0,
+                                       0);
     }
 #pragma unroll
     for (int j = 0; j < X4_COPIES; ++j) {
@@ -866,11 +876,11 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
     }
   };
 
-  floatx16 acc[2][4];
+  floatx16 acc[2][NJ];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
@@ -880,7 +890,7 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
     // this wave's copies of stage st have landed (those of st + 1 may not);
     // the barrier makes every wave's copies visible and frees slot (st + 2) % 3
     if (st + 1 < nst)
-      __builtin_amdgcn_s_waitcnt(waitcnt_vm(A4_COPIES + X4_COPIES));
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(A_COPIES + X4_COPIES));
     else
       __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
     // a plain barrier: the waits above are the only ones the copies need (a
@@ -888,18 +898,18 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(63) & ~0x0F00);  // lgkmcnt(0): this wave's LDS reads are done
     __builtin_amdgcn_s_barrier();
     if (st + 2 < nst) issue(st + 2, (st + 2) % ST4);
-    const unsigned char* abase = lds + (st % ST4) * (A4_BYTES + X4_BYTES);
-    const unsigned char* xbase = abase + A4_BYTES;
+    const unsigned char* abase = lds + (st % ST4) * (A_BYTES + X4_BYTES);
+    const unsigned char* xbase = abase + A_BYTES;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const int c = 2 * ks + (lane >> 5);
-      bf16x8 ah[2], al[2], xh[4], xl[4];
+      bf16x8 ah[2], al[2], xh[NJ], xl[NJ];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const int row = 64 * w + 32 * i + (lane & 31);
+        const int row = wr + 32 * i + (lane & 31);
         const int off = (row * 4 + swz(row, c)) * 16;
         ah[i] = *reinterpret_cast<const bf16x8*>(abase + off);
-        al[i] = *reinterpret_cast<const bf16x8*>(abase + BM4 * 64 + off);
+        al[i] = *reinterpret_cast<const bf16x8*>(abase + BMT * 64 + off);
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
@@ -908,16 +918,22 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
         xl[j] = *reinterpret_cast<const bf16x8*>(xbase + 4 * BNI * 16 + off);
       }
       __builtin_amdgcn_sched_barrier(0);
-      // the imaginary-part columns (fragments 2 and 3) from the real-part ones
+      // the imaginary-part columns from the real-part ones: fragments 2 and 3
+      // (BMT = 256), or the wave's two fragments (BMT = 128, odd waves)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        xh[j + 2] = imag_fragment(xh[j]);
-        xl[j + 2] = imag_fragment(xl[j]);
+        if (BMT == 256) {
+          xh[j + 2] = imag_fragment(xh[j]);
+          xl[j + 2] = imag_fragment(xl[j]);
+        } else if (half) {
+          xh[j] = imag_fragment(xh[j]);
+          xl[j] = imag_fragment(xl[j]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NJ; ++j) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], xh[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], xl[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], xh[j], acc[i][j], 0, 0, 0);
@@ -925,23 +941,25 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
     }
   }
 
-  // real column 32 j + lane % 32: instance 32 (j % 2) + lane % 32, part j / 2
+  // fragment j: instance 32 (j % 2) + lane % 32 of the tile; output part j / 2
+  // (BMT = 256) or the wave's half (BMT = 128)
   float* Yf = reinterpret_cast<float*>(g.Y + s * g.y_slice_stride);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = m0 + 64 * w + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int row = m0 + wr + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       if (row >= g.M) continue;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         const int b = b0 + 32 * (j & 1) + (lane & 31);
-        if (b < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b) + (j >> 1)] = acc[i][j][r];
+        const int part = BMT == 256 ? (j >> 1) : half;
+        if (b < g.ncols) Yf[2 * ((int64_t)row * g.ldy + b) + part] = acc[i][j][r];
       }
     }
 }
 
-// The split X of tilings 1 to 3 (the layout of bf16x2.h, as written by
+// The split X of tilings 1 to 4 (the layout of bf16x2.h, as written by
 // expand_bf16x2_kernel) straight from split-K slices of a product: x[k][b] =
 // sum over slices s in order of in[s stride + k ldx + b], for k < Kc and b <
 // ncols, zero elsewhere in [Kc rounded][tiles x 64].  Thread (pair o, slice
@@ -1023,10 +1041,11 @@ void sum_expand_bf16x2(hipStream_t stream, const void* in, int slices, int64_t s
                      (const float4*)in, slices, stride / 2, Kc, ldx / 2, ncols, tiles, (unsigned short*)work, ldxb);
 }
 
-// variant 0: 64-row tiles, X split while staged; variants 1 to 3: X split and
-// expanded once into `work` (cgemm_bf16x2_work_bytes), then 128-row tiles
-// (variant 1), 256-row tiles staged by direct-to-LDS loads (variant 2), or
-// 128-row tiles of 64 real K per stage (variant 3).
+// variant 0: 64-row tiles, X split while staged; variants 1 to 4: X split
+// once into `work` (cgemm_bf16x2_work_bytes), then 128-row tiles (variant 1),
+// 256-row tiles staged by direct-to-LDS loads (variant 2), 128-row tiles of
+// 64 real K per stage (variant 3), or 128-row tiles staged by direct-to-LDS
+// loads (variant 4).
 // With x_expanded, `work` already holds that expansion (sum_expand_bf16x2)
 // and X is not read.
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
@@ -1046,7 +1065,7 @@ void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc,
   g.ncols = ncols;
   g.kslice = kslice;
   const int splits = (Kc + kslice - 1) / kslice;
-  if (variant >= 1 && variant <= 3 && work) {
+  if (variant >= 1 && variant <= 4 && work) {
     const int64_t ldxb = 2 * (((int64_t)Kc + 31) / 32 * 32);
     const int tiles = (ncols + BNI - 1) / BNI;
     if (!x_expanded) expand_bf16x2(stream, X, ldx, Kc, ncols, work);
@@ -1056,8 +1075,13 @@ void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc,
       return;
     }
     if (variant == 2) {
-      const dim3 grid((M + BM4 - 1) / BM4, tiles, splits);
-      hipLaunchKernelGGL(cgemm_bf16x2_mfma_v3, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
+      const dim3 grid((M + 255) / 256, tiles, splits);
+      hipLaunchKernelGGL(cgemm_bf16x2_mfma_v3<256>, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
+      return;
+    }
+    if (variant == 4) {
+      const dim3 grid((M + 127) / 128, tiles, splits);
+      hipLaunchKernelGGL(cgemm_bf16x2_mfma_v3<128>, grid, dim3(256), 0, stream, g, (const unsigned short*)work, ldxb);
       return;
     }
     const dim3 grid((M + BM3 - 1) / BM3, tiles, splits);

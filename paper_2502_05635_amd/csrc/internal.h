@@ -108,17 +108,17 @@ void cgemm_f32(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, co
                int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant);
 // BF16 split-precision product: A in TDG_BF16X2 storage (hi plane, then lo
 // plane, [M][lda], lda % 4 == 0), X complex64 [Kc][ldx] (gemm.hip).
-// variant 0: 64-row tiles splitting X while staged; 1 to 3: X split once
+// variant 0: 64-row tiles splitting X while staged; 1 to 4: X split once
 // into `work` (cgemm_bf16x2_work_bytes bytes), then 128-row tiles (1),
-// 256-row tiles staged by direct-to-LDS loads (2), or 128-row tiles with
-// loads two stages ahead (3).
+// 256-row tiles staged by direct-to-LDS loads (2), 128-row tiles of 64 real
+// K per stage (3), or 128-row tiles staged by direct-to-LDS loads (4).
 void cgemm_bf16x2(hipStream_t stream, const void* A, int64_t lda, int M, int Kc, const void* X, int64_t ldx,
                   void* Y, int64_t ldy, int64_t y_slice_stride, int ncols, int kslice, int variant, void* work,
                   bool x_expanded = false);
-// The split X of BF16X2 tilings 1 to 3 (complex64 [Kc][ldx], first ncols
+// The split X of BF16X2 tilings 1 to 4 (complex64 [Kc][ldx], first ncols
 // instances; the rest of the last tile zero) written into `work`.
 void expand_bf16x2(hipStream_t stream, const void* X, int64_t ldx, int Kc, int ncols, void* work);
-// The split X of BF16X2 tilings 1 to 3 written into `work` straight from
+// The split X of BF16X2 tilings 1 to 4 written into `work` straight from
 // `slices` split-K partial products (complex64 [Kc][ldx] each, `stride`
 // apart; ldx and stride even), summed in slice order: then call cgemm_bf16x2
 // with x_expanded (X unused).

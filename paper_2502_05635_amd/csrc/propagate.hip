@@ -747,7 +747,7 @@ struct BatchParams {
   // entries g, g + nb, g + 2 nb, ...
   int nelem;
   int elist[TDG_NB_MAX * TDG_NB_MAX];
-  // the next gather also split for a BF16X2 product of tiling 1, 2 or 3
+  // the next gather also split for a BF16X2 product of tilings 1 to 4
   // (bf16x2.h layout, Kc = N); NULL = not written.  Used with 64
   // instances per block and a multiple of 4 pairs per k only.
   unsigned short* xexp;
@@ -1769,8 +1769,8 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       TDG_TRY(hip_check(ctx, hipMemsetAsync(xe, 0, xe_bytes, ctx->stream), "split gather clear"));
     }
     // FP32: 64-row, prefetching 64-row, 128-row; BF16X2: 64-row, 128-row,
-    // 256-row, 128-row with 64 real K per stage
-    const int ntilings = bf16 ? 4 : 3;
+    // 256-row, 128-row with 64 real K per stage, 128-row direct-to-LDS
+    const int ntilings = bf16 ? 5 : 3;
     if (n_dyn0 > 0) {
       // Split-K candidates: the default (about 1024 blocks), no split, twice
       // the default, and slice counts that put about 256 j blocks (j = 1..4)
@@ -1815,8 +1815,8 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
                  (long long)Kc, n_dyn0, (long long)ks_def, (long long)ks_forced);
         for (auto& kv : ctx->tuned)
           if (kv.first == key) {
-            *out_v = kv.second % 4;
-            *out_ks = kv.second / 4;
+            *out_v = kv.second % 8;
+            *out_ks = kv.second / 8;
             return TDG_OK;
           }
         const std::vector<int64_t> opts =
@@ -1856,7 +1856,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
               break;
             }
         TDG_TRY(launch_check(ctx, "GEMM tuning"));
-        ctx->tuned.emplace_back(key, (int)(bestks * 4 + bestv));
+        ctx->tuned.emplace_back(key, (int)(bestks * 8 + bestv));
         *out_v = bestv;
         *out_ks = bestks;
         return TDG_OK;
@@ -1873,7 +1873,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
       void* xt = x1;
       hipLaunchKernelGGL(pattern_fill_kernel, dim3(1024), dim3(256), 0, ctx->stream, (float2*)xt,
                          (int64_t)n * xstride);
-      // tilings 1 to 3 then read X split by the stage kernel: timed without their own split
+      // tilings 1 to 4 then read X split by the stage kernel: timed without their own split
       if (fuse_ok) expand_bf16x2(ctx->stream, xt, xstride, (int)n, n_dyn0, xe);
       auto gemm_x = [&](hipStream_t st, const void* A, int64_t lda, int M, const void* X, void* Y, int64_t ystride,
                         int ks, int v) {
@@ -1904,7 +1904,7 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
         }, &gv_proj, &ks_proj));
         z_slices = (int)((n + ks_proj - 1) / ks_proj);
         // Zsum now holds the step-0 projection (the expansion's timing input)
-        // BF16X2 tilings 1 to 3 take the split projection straight from its
+        // BF16X2 tilings 1 to 4 take the split projection straight from its
         // slices (one kernel instead of the slice sum and the split); tiling
         // 0 reads the summed projection, so its timing includes the sum
         TDG_TRY(pick("expand", n, op->rank, ks_main, [&](int v, int64_t ks) {

@@ -234,10 +234,10 @@ def test_tb4_intraband_batched_path(P, ctx, tb4_6, k_tb4_6, kind):
 
 
 @pytest.mark.parametrize("links", [False, True])
-@pytest.mark.parametrize("tiling", [1, 3])
+@pytest.mark.parametrize("tiling", [1, 3, 4])
 def test_bf16x2_split_gather_written_by_stage_kernel(P, ctx, tb4_6, k_tb4_6, links, tiling):
-    """40 uneven instances (64 per stage-kernel block): with BF16X2 tiling 1
-    or 3 the batched stage kernel writes the next projection's split operand
+    """40 uneven instances (64 per stage-kernel block): with BF16X2 tiling 1,
+    3 or 4 the batched stage kernel writes the next projection's split operand
     itself, Hermitian-packed state without the intraband term, full state
     with it.  Four instances against the FP64 oracle; all of them against the
     same run on tiling 0, which splits X in the product (the tilings differ

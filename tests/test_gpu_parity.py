@@ -267,7 +267,7 @@ def test_invalid_arguments_rejected(P, ctx, tb4_6):
         ctx.kernel_compress(kg, "rank", 50, max_rank=10)       # rank above capacity
     from paper_2502_05635_amd import _abi as abi
     for option, bad in ((abi.TDG_OPT_GEMM_SLICES, -1), (abi.TDG_OPT_GEMM_SLICES, 4097),
-                        (abi.TDG_OPT_GEMM_VARIANT, 4), (abi.TDG_OPT_GEMM_VARIANT, -2)):
+                        (abi.TDG_OPT_GEMM_VARIANT, 5), (abi.TDG_OPT_GEMM_VARIANT, -2)):
         with pytest.raises(P.TdgError) as e:
             ctx.set_option(option, bad)
         assert e.value.code == -1, (option, bad)
@@ -524,12 +524,13 @@ def test_bf16x2_batched_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, tiling):
         ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
 
 
-@pytest.mark.parametrize("tiling", [1, 3])
+@pytest.mark.parametrize("tiling", [1, 3, 4])
 @pytest.mark.parametrize("kind,slices", [("dense", 1), ("lowrank", 4096)])
 def test_bf16x2_batched_forced_split_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, slices, tiling):
     """The BF16X2 products with the split-K forced to one slice and to the
     most slices allowed (16-column slices: half a K stage of the fourth
-    tiling), for the second and fourth tilings, against the FP64 oracle."""
+    tiling), for the second, fourth and fifth tilings, against the FP64
+    oracle."""
     from paper_2502_05635_amd import _abi as abi
     ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, tiling)
     ctx.set_option(abi.TDG_OPT_GEMM_SLICES, slices)
@@ -544,12 +545,13 @@ def test_bf16x2_batched_forced_split_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, sli
 
 
 @pytest.mark.parametrize("kind,tiling", [("dense", 0), ("lowrank", 0), ("dense", 1), ("lowrank", 1),
-                                         ("dense", 2), ("lowrank", 2), ("dense", 3), ("lowrank", 3)])
+                                         ("dense", 2), ("lowrank", 2), ("dense", 3), ("lowrank", 3),
+                                         ("dense", 4), ("lowrank", 4)])
 def test_bf16x2_batched_each_tiling_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, tiling):
     """Every BF16X2 tiling forced in turn, against the FP64 oracle: N = 144
     rows (within one 256-row tile of the third tiling, two 128-row tiles of
-    the second and fourth, the second tile ragged) and rank 37 (a ragged last
-    K stage)."""
+    the second, fourth and fifth, the second tile ragged) and rank 37 (a
+    ragged last K stage)."""
     from paper_2502_05635_amd import _abi as abi
     ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, tiling)
     try:
