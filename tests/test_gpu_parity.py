@@ -414,6 +414,44 @@ def test_batched_mfma_vs_oracle(P, ctx, tb4_6, k_tb4_6, kind, slices):
         np.testing.assert_allclose(res["rho"][b].cpu().numpy(), ref["rho"], rtol=0, atol=1e-5)
 
 
+@pytest.mark.parametrize("tiling", [0, 1, 2])
+@pytest.mark.parametrize("kind", ["dense", "lowrank"])
+def test_batched_mfma_each_fp32_tiling_vs_oracle(P, ctx, kind, tiling):
+    """Every FP32 tiling of the batched products forced in turn, against the
+    FP64 oracle, on a 5x5 grid: N = 100 (a ragged last K stage of 16 complex
+    for the dense product and the projection, and a ragged row tile) and rank
+    38 (a ragged last K stage of the expansion, 16-byte rows).  Six uneven
+    instances."""
+    from paper_2502_05635_amd import _abi as abi
+    m = tb4_model(5, A, 0.5)
+    ko = O.build_kernel(m, R0_STABLE, "eh")
+    fields = _uneven_fields(6, seed=9)
+    dm = _dev(P, m)
+    kg = ctx.kernel_build(dm, R0_STABLE, "eh", "c64")
+    op, oracle_op = kg, O.DenseOp(ko)
+    if kind == "lowrank":
+        op = ctx.kernel_compress(kg, "rank", 38)
+        oracle_op = O.LowRankOp.from_factors(O.compress(ko, "rank", 38))
+    ctx.set_option(abi.TDG_OPT_BATCHED_MIN, 2)
+    ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, tiling)
+    _log(f"batched {kind} FP32, tiling {tiling}, 6 instances, N = 100")
+    try:
+        res = ctx.propagate(op, dm, "eh", fields, DT)
+        variant = ctx.last_variant()
+    finally:
+        ctx.set_option(abi.TDG_OPT_GEMM_VARIANT, -1)
+    _log(f"  {variant}")
+    assert f"tiling {tiling}" in variant or f"tilings {tiling}/{tiling}" in variant
+    for b in range(fields.batch):
+        ref = O.propagate(m, oracle_op, "eh", fields, DT, instance=b)
+        nsb = int(fields.nsteps[b])
+        for key in ("P", "J"):
+            got = res[key][b, : nsb + 1].cpu().numpy()
+            scale = max(np.abs(ref[key]).max(), 1e-300)
+            assert np.abs(got - ref[key]).max() <= 1e-4 * scale, (b, key)
+        np.testing.assert_allclose(res["rho"][b].cpu().numpy(), ref["rho"], rtol=0, atol=1e-5)
+
+
 @pytest.mark.parametrize("block", ["eh", "all"])
 def test_batched_from_given_rho0(P, ctx, tb4_6, block):
     """The batched path keeps its state Hermitian-packed (upper triangle and a
