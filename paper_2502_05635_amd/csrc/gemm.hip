@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma(GemmArgs g) {
   }
 }
 
-// Second tiling: 128 rows x 64 instances per block; wave w owns rows
+// FP32 tiling 2: 128 rows x 64 instances per block; wave w owns rows
 // 64*(w/2) .. +63 and real columns 64*(w%2) .. +63 as 2 x 2 MFMA accumulators,
 // so each fragment read from LDS feeds two products.  The next K tile is
 // loaded into registers while the current one is multiplied (one LDS buffer,
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(256) cgemm_f32_mfma_128(GemmArgs g) {
     }
 }
 
-// Third tiling: the first one's 64 rows x 64 instances and wave layout, with
+// FP32 tiling 1: tiling 0's 64 rows x 64 instances and wave layout, with
 // the next K tile loaded into registers while the current one is multiplied
 // and two LDS buffers, so one barrier per tile separates the writers of one
 // buffer from the readers of the other.  AVEC as above.
@@ -609,10 +609,10 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma(GemmBf16Args g) {
   }
 }
 
-// ---- BF16 split-precision product, second tiling ---------------------------
+// ---- BF16 split-precision product, tiling 1 ---------------------------------
 // X is split once per product into XB (bf16 bits, the layout of bf16x2.h:
-// the real-part rows of its expansion).  Rows are K-contiguous, so a lane's 8
-// consecutive K are one 16-byte read.
+// the real-part rows of its expansion, K-blocked), so 8 consecutive K of one
+// instance are one 16-byte read and 64 instances' chunks are contiguous.
 using tdg::XB_ROWS;
 static_assert(tdg::XB_TILE == BNI, "split operand tiles hold one block's instances");
 
@@ -660,7 +660,7 @@ constexpr int BKC3 = 16;
 constexpr int KR3 = 2 * BKC3;
 constexpr int LPAD3 = 8;
 
-// KR: real K per LDS stage, 32 (second tiling) or 64 (fourth tiling: rows
+// KR: real K per LDS stage, 32 (tiling 1) or 64 (tiling 3: rows
 // are read in 128-byte pieces per plane instead of 64-byte ones, two blocks
 // per CU by LDS).
 template <int KR>
@@ -788,18 +788,18 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
     }
 }
 
-// ---- BF16 split-precision product, third and fifth tilings ----------------
-// BMT rows x 64 instances per block.  BMT = 256 (third tiling): wave w owns
+// ---- BF16 split-precision product, tilings 2 and 4 -------------------------
+// BMT rows x 64 instances per block.  BMT = 256 (tiling 2): wave w owns
 // rows 64 w .. +63 and all 128 real columns as 2 x 4 MFMA accumulators, so a
 // fragment read from LDS feeds two (X) or four (A) products.  BMT = 128
-// (fifth tiling): wave w owns rows 64 (w / 2) .. +63 and the real (w even) or
+// (tiling 4): wave w owns rows 64 (w / 2) .. +63 and the real (w even) or
 // imaginary (w odd) output parts of the 64 instances as 2 x 2 accumulators.
 // A (both planes) and the stored rows of the split X are copied straight into
 // LDS by 16-byte direct-to-LDS loads, into a ring of three stages of 16
 // complex K: the loads of the next two stages are in flight while one is
 // multiplied, with no registers held.  The imaginary-part columns' X
 // fragments are formed from the real-part ones after they are read
-// (xb_imag).  Blocks are placed on the XCDs as for the second tiling.  The
+// (xb_imag).  Blocks are placed on the XCDs as for tiling 1.  The
 // ring takes 120 KB of LDS at BMT = 256 (one block per CU) and 72 KB at 128
 // (two).
 // In a stage, row r of a plane of A is 4 chunks of 8 bf16 (64 bytes); chunk c

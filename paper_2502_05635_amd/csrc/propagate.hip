@@ -833,8 +833,8 @@ __device__ inline void pk_put(double2* A, int nk, int nb, int64_t ldx, int k, in
 // observable sums [5][nb][IB] share the H blocks' LDS when they fit (nb >= 3):
 // they are consumed before H is built; otherwise they follow the H blocks.
 // With bp.xexp, the next gather's P values per instance follow (P IB float2):
-// the block then writes its k point's 16-byte pieces of the split operand,
-// one per (plane, row, 4 pairs).
+// the block then writes its k point's 16-byte chunks of the split operand,
+// one per (plane, instance, 4 pairs).
 // Blocks map to k XCD-aware (xcd_block): each XCD takes a contiguous range of
 // k points.
 
@@ -1754,12 +1754,12 @@ static int propagate_impl(tdg_ctx ctx, const tdg_operator* op, const tdg_model* 
     // below recomputes
     int gv_main = 0, gv_proj = 0;
     const int n_dyn0 = count_gt(0);
-    // BF16X2: the second tiling needs X split once into a bf16 work array
+    // BF16X2: tilings 1 to 4 need X split once into a bf16 work array
     void* xbw = nullptr;
     if (bf16) TDG_TRY(ws_reserve(ctx, WS_XB, cgemm_bf16x2_work_bytes((int)n, batch), &xbw));
     // With those tilings the stage kernel can write the next gather split as
     // well, which saves the product's own split of X (64 instances per stage
-    // block and whole 16-byte pieces of 4 pairs).  The array is cleared once:
+    // block and whole 16-byte chunks of 4 pairs).  The array is cleared once:
     // its padding past 2N stays zero.
     void* xe = nullptr;
     const bool fuse_ok = bf16 && IB == tdg::XB_TILE && npair % 4 == 0;
