@@ -53,6 +53,12 @@ def _host_factors(fac) -> dict:
 
 
 def test_sweep_lowrank_batched_full_shape_vs_oracle(P):
+    """The 60x60 sweep shape (N = 14400, rank 720, 64 instances of 14-24
+    steps, retiring unevenly) on the batched path, FP32 and then BF16X2 from
+    the same K, each against the FP64 oracle with the FP32 factors on eight
+    instances.  BF16X2 runs the tuner's tilings with the split gather written
+    by the stage kernel; its factors differ from the FP32 ones only by their
+    rounding."""
     cfg = get_config(2)
     m = cfg.model()
     n = cfg.n
@@ -66,8 +72,6 @@ def test_sweep_lowrank_batched_full_shape_vs_oracle(P):
         K = ctx.kernel_build(dm, cfg.r0, "eh", "c64")
         fac = ctx.kernel_compress(K, "fraction", 0.05)
         assert fac.rank == 720
-        del K
-        torch.cuda.empty_cache()
         _log(f"  batched low rank FP32, B={B}, {lengths.min()}-{lengths.max()} steps, tuner on")
         res = ctx.propagate(fac, dm, "eh", fields, cfg.dt)
         torch.cuda.synchronize()
@@ -76,13 +80,31 @@ def test_sweep_lowrank_batched_full_shape_vs_oracle(P):
         assert variant.startswith("batched_mfma_lowrank_f32")
         op = O.LowRankOp.from_factors(_host_factors(fac))
         checked = [0, 9, 18, 27, 36, 45, 54, 63]
+        refs = {}
         for b in checked:
-            ref = O.propagate(m, op, "eh", fields, cfg.dt, instance=b)
+            refs[b] = ref = O.propagate(m, op, "eh", fields, cfg.dt, instance=b)
             nsb = int(lengths[b])
             errs = {key: _err(res[key][b, : nsb + 1].cpu().numpy(), ref[key]) for key in ("P", "J", "occ")}
             _log(f"  instance {b} (E0 {fields.e0[b]:.1e}, {nsb} steps): "
                  + ", ".join(f"err_{k} {v:.2e}" for k, v in errs.items()))
             assert abs(ref["occ"][-1]) > 1e-14                      # the pulse does excite
+            assert errs["P"] <= TOL and errs["J"] <= TOL, b
+        assert torch.isfinite(res["P"]).all()
+        del res, fac
+        fbf = ctx.kernel_compress(K, "fraction", 0.05, out_dtype="bf16x2")
+        assert fbf.rank == 720
+        del K
+        torch.cuda.empty_cache()
+        _log("  batched low rank BF16X2, same instances, tuner on")
+        res = ctx.propagate(fbf, dm, "eh", fields, cfg.dt)
+        torch.cuda.synchronize()
+        variant = ctx.last_variant()
+        _log(f"  {variant}")
+        assert variant.startswith("batched_mfma_lowrank_bf16x2")
+        for b in checked:
+            nsb = int(lengths[b])
+            errs = {key: _err(res[key][b, : nsb + 1].cpu().numpy(), refs[b][key]) for key in ("P", "J", "occ")}
+            _log(f"  instance {b}: " + ", ".join(f"err_{k} {v:.2e}" for k, v in errs.items()))
             assert errs["P"] <= TOL and errs["J"] <= TOL, b
         assert torch.isfinite(res["P"]).all()
     finally:
