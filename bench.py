@@ -685,10 +685,19 @@ def adjoint_leg(P, ctx):
     ctx.propagate_adjoint(fac, dm, "eh", fl, cfg.dt, gJ=gj[None], checkpoint_every=50)
     torch.cuda.synchronize()
     adj_s = time.perf_counter() - t0
+    # Bytes a gradient step must move at minimum: both factors (complex128, r N
+    # each) read in every stage of the checkpointing forward sweep, of the
+    # segment recompute and of the backward step (S^H and V products), 3 x 4 x
+    # 2 r N x 16 bytes; the factor gradients and the per-k state are smaller.
+    n, r = cfg.n, fac.rank
+    step_bytes = 3 * 4 * 2 * r * n * 16
+    achieved = step_bytes * nsteps / adj_s / 1e9
     return {"workload": f"{cfg.name}: 24x24 k-grid, N={cfg.n}, complex128 low-rank factors rank {fac.rank}, "
                         f"{nsteps} steps, checkpoints every 50; loss = third-harmonic intensity of J",
             "forward_steps_per_s": nsteps / fwd_s, "gradient_steps_per_s": nsteps / adj_s,
-            "gradient_vs_forward_time": adj_s / fwd_s, "loss": float(abs(a) ** 2)}
+            "gradient_vs_forward_time": adj_s / fwd_s, "loss": float(abs(a) ** 2),
+            "roofline": {"bound": "hbm", "bytes_per_gradient_step": step_bytes, "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}}
 
 
 def cpu_baseline(cfg, frac, seconds):
