@@ -856,6 +856,10 @@ batched_stage_kernel(BatchParams bp) {
   double* s_o = reinterpret_cast<double*>(o_shared ? s_h : dyn_lds + 2 * nb2 * IB);  // [5][nb][IB]
   const int i = threadIdx.x % IB, n = WG ? __builtin_amdgcn_readfirstlane(threadIdx.x / 64) : threadIdx.x / IB;
   const int k = tdg::xcd_block(blockIdx.x, gridDim.x), b = blockIdx.y * IB + i;
+  // WG: the wave takes the list entries of group (n + rot) % nb, rotating
+  // with k, so the waves that own one more element (10 packed elements over
+  // 4 groups) do not all sit on the same SIMDs of a CU
+  const int rot = WG ? k % nb : 0;
   const bool act = b < bp.n_active, dyn = act && b < bp.n_dyn;
   const int step = bp.step_dev ? bp.step_dev[0] : bp.step;
   const int obs_slot = bp.step_dev ? step % bp.chunk : bp.obs_slot;
@@ -907,7 +911,7 @@ batched_stage_kernel(BatchParams bp) {
     rs[q] = r_n[q] = r_acc[q] = ds[q] = dv[q] = make_double2(0.0, 0.0);
     prow[q] = -1;
     partner[q] = false;
-    const int j = n + q * nb;
+    const int j = (WG ? (n + rot) % nb : n) + q * nb;
     ee[q] = j < bp.nelem ? bp.elist[j] : -1;
     if (WG) ee[q] = __builtin_amdgcn_readfirstlane(ee[q]);
     if (ee[q] < 0 || !act) continue;
