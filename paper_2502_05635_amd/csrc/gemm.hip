@@ -792,8 +792,9 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v2(GemmBf16Args g, cons
 // BMT rows x 64 instances per block.  BMT = 256 (tiling 2): wave w owns
 // rows 64 w .. +63 and all 128 real columns as 2 x 4 MFMA accumulators, so a
 // fragment read from LDS feeds two (X) or four (A) products.  BMT = 128
-// (tiling 4): wave w owns rows 64 (w / 2) .. +63 and the real (w even) or
-// imaginary (w odd) output parts of the 64 instances as 2 x 2 accumulators.
+// (tiling 4): wave w owns rows 64 (w / 2) .. +63 and the real or the
+// imaginary output parts of the 64 instances (alternating between blocks) as
+// 2 x 2 accumulators.
 // A (both planes) and the stored rows of the split X are copied straight into
 // LDS by 16-byte direct-to-LDS loads, into a ring of three stages of 16
 // complex K: the loads of the next two stages are in flight while one is
@@ -843,7 +844,10 @@ __global__ void __launch_bounds__(256) cgemm_bf16x2_mfma_v3(GemmBf16Args g, cons
   tdg::xcd_block3(bx, ct, s);
   const int m0 = bx * BMT, b0 = ct * BNI;
   const int wr = BMT == 256 ? 64 * w : 64 * (w >> 1);  // the wave's first row
-  const int half = BMT == 256 ? 0 : (w & 1);            // BMT = 128: imaginary output parts
+  // BMT = 128: imaginary output parts; which waves form the imaginary-part
+  // fragments alternates with the block, so that work is not always on the
+  // same SIMDs of a CU
+  const int half = BMT == 256 ? 0 : ((w ^ bx ^ s) & 1);
   const int kc_begin = s * g.kslice;
   const int kc_end = min(g.Kc, kc_begin + g.kslice);
   const int nst = (kc_end - kc_begin + KR4 / 2 - 1) / (KR4 / 2);
