@@ -98,23 +98,26 @@ __device__ inline double2 proj_e(const tdg_field& F, const AdjArgs& a, const dou
   return make_double2(F.ex * u.x + F.ey * v.x, F.ex * u.y + F.ey * v.y);
 }
 
-// dSigma pair value: S (from the GEMM) plus K_diag o x for the low-rank form.
-__device__ inline double2 sigma_pair(const AdjArgs& a, const double2* S, const double2* X, int b, int k, int p) {
+// dSigma pair value: S (from the products) plus K_diag o x for the low-rank
+// form.  S is the product for every pair [B][n], or with sl the block's own
+// rows in LDS (local k point lk: sl[lk P + p]).
+__device__ inline double2 sigma_pair(const AdjArgs& a, const double2* S, const double2* sl, const double2* X, int b,
+                                     int k, int lk, int p) {
   const size_t i = (size_t)b * a.n + (size_t)k * a.npair + p;
-  double2 v = S[i];
+  double2 v = sl ? sl[lk * a.npair + p] : S[i];
   if (a.kdiag) v = cadd(v, cmul(a.kdiag[(size_t)k * a.npair + p], X[i]));
   return v;
 }
 
 // Element (n, m) of H_k = diag(eps) + dSigma - E e.d (e-h block: dSigma_vc = conj(dSigma_cv)).
-__device__ inline double2 ham_element(const AdjArgs& a, const double2* S, const double2* X, const Slot& s, double ef,
-                                      double2 de) {
+__device__ inline double2 ham_element(const AdjArgs& a, const double2* S, const double2* sl, const double2* X,
+                                      const Slot& s, double ef, double2 de) {
   double2 ds = make_double2(0.0, 0.0);
   const int p = pair_of(a, s.nn, s.m);
   if (p >= 0) {
-    ds = sigma_pair(a, S, X, s.b, s.k, p);
+    ds = sigma_pair(a, S, sl, X, s.b, s.k, s.lk, p);
   } else if (a.block == TDG_BLOCK_EH && s.nn < a.nv && s.m >= a.nv) {
-    ds = cconj(sigma_pair(a, S, X, s.b, s.k, (s.m - a.nv) * a.nv + s.nn));
+    ds = cconj(sigma_pair(a, S, sl, X, s.b, s.k, s.lk, (s.m - a.nv) * a.nv + s.nn));
   }
   double2 h = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
   if (s.nn == s.m) h.x += a.eps[(size_t)s.k * a.nb + s.nn];
@@ -164,22 +167,83 @@ __global__ void __launch_bounds__(AT) adj_gather_kernel(AdjArgs a, const double2
       make_double2(v.x - ((s.nn == s.m && s.nn < a.nv) ? 1.0 : 0.0), v.y);
 }
 
+// The block's rows of a factor product, low rank: out[lk P + p] = sum_j
+// M[(k P + p) ldm + j] vec[b r + j] for the block's k points k = k0 + lk and
+// pairs p (kpb P <= AT rows).  tpr consecutive lanes share a row, each
+// summing every tpr-th column in order, eight columns' loads issued together;
+// the lanes' sums are then combined by a butterfly, whose partners add the
+// same two values, so every lane of the row holds the same sum.  The block is
+// one wave.
+__device__ inline void block_rows_dot(const AdjArgs& a, const double2* __restrict__ M, int64_t ldm,
+                                      const double2* __restrict__ vec, int r, double2* out) {
+  const int kpb = AT / (a.nb * a.nb), P = a.npair, rows = kpb * P;
+  int tpr = 1;
+  while (2 * tpr * rows <= AT) tpr *= 2;
+  const int t = threadIdx.x, row = t / tpr, part = t % tpr;
+  const int k = blockIdx.x * kpb + row / P;
+  double sr = 0.0, si = 0.0;
+  if (row < rows && k < a.nk) {
+    const double2* mr = M + ((size_t)k * P + row % P) * ldm;
+    const double2* v = vec + (size_t)blockIdx.y * r;
+    constexpr int U = 8;
+    for (int j0 = part; j0 < r; j0 += U * tpr) {
+      double2 m[U], x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // past the last column: load column j0 (in range) and use zero
+        const int j = j0 + u * tpr, jc = j < r ? j : j0;
+        m[u] = mr[jc];
+        x[u] = v[jc];
+        if (j >= r) m[u] = make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        sr += m[u].x * x[u].x - m[u].y * x[u].y;
+        si += m[u].x * x[u].y + m[u].y * x[u].x;
+      }
+    }
+  }
+  for (int off = 1; off < tpr; off <<= 1) {
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
+  }
+  if (part == 0 && row < rows) out[row] = make_double2(sr, si);
+}
+
 // Forward stage s of step `step` at the state y: f = -i [H, y]; RK4
 // accumulation; the next stage's state (or rho_{n+1} after the fourth stage)
-// into y_next and its gather into x_next (if not NULL).
+// into y_next and its gather into x_next (if not NULL).  Dense: S is K x.
+// Low rank (M not NULL): the block forms its rows of S = M vec itself (M = S~,
+// vec = z = V^H x) and stores them into S for the backward sweep.
 __global__ void __launch_bounds__(AT) adj_fwd_stage_kernel(AdjArgs a, int step, int st, const double2* rho_n,
-                                                           const double2* y, const double2* S, const double2* X,
+                                                           const double2* y, double2* S, const double2* X,
+                                                           const double2* M, int64_t ldm, const double2* vec, int r,
                                                            const double2* dy, double2* acc, double2* y_next,
                                                            double2* x_next) {
-  __shared__ double2 sh_y[AT], sh_h[AT];
+  __shared__ double2 sh_y[AT], sh_h[AT], sh_s[AT];
   const Slot s = slot_of(a);
   const int t = threadIdx.x, nb = a.nb, o = s.lk * nb * nb;
+  // the slot's own inputs, read before the product so that their latency
+  // overlaps it
+  double2 yv = make_double2(0.0, 0.0), rn = yv, ac = yv, dv = yv;
+  if (s.active) {
+    yv = y[s.g];
+    rn = rho_n[s.g];
+    if (st > 0) ac = acc[s.g];
+    if (dy) dv = dy[s.g];
+  }
+  if (M) {
+    block_rows_dot(a, M, ldm, vec, r, sh_s);
+    __syncthreads();
+    const int kpb = AT / (nb * nb), P = a.npair, k = blockIdx.x * kpb + t / P;
+    if (t < kpb * P && k < a.nk) S[(size_t)blockIdx.y * a.n + (size_t)k * P + t % P] = sh_s[t];
+  }
   double ef = 0.0;
   if (s.active) {
     const tdg_field F = a.fields[s.b];
     ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
-    sh_y[t] = y[s.g];
-    sh_h[t] = ham_element(a, S, X, s, ef, proj_e(F, a, a.dip, s.k, s.e));
+    sh_y[t] = yv;
+    sh_h[t] = ham_element(a, S, M ? sh_s : nullptr, X, s, ef, proj_e(F, a, a.dip, s.k, s.e));
   }
   __syncthreads();
   if (!s.active) return;
@@ -193,26 +257,21 @@ __global__ void __launch_bounds__(AT) adj_fwd_stage_kernel(AdjArgs a, int step, 
   double2 f = make_double2(c.y, -c.x);  // -i c
   if (dy) {
     // intraband term -E(t) D(y)
-    const double2 d = dy[s.g];
-    f.x -= ef * d.x;
-    f.y -= ef * d.y;
+    f.x -= ef * dv.x;
+    f.y -= ef * dv.y;
   }
-  const double2 rn = rho_n[s.g];
   const double dt = a.dt;
   double2 next;
   if (st == 0) {
     acc[s.g] = f;
     next = make_double2(rn.x + 0.5 * dt * f.x, rn.y + 0.5 * dt * f.y);
   } else if (st == 1) {
-    const double2 ac = acc[s.g];
     acc[s.g] = make_double2(ac.x + 2.0 * f.x, ac.y + 2.0 * f.y);
     next = make_double2(rn.x + 0.5 * dt * f.x, rn.y + 0.5 * dt * f.y);
   } else if (st == 2) {
-    const double2 ac = acc[s.g];
     acc[s.g] = make_double2(ac.x + 2.0 * f.x, ac.y + 2.0 * f.y);
     next = make_double2(rn.x + dt * f.x, rn.y + dt * f.y);
   } else {
-    const double2 ac = acc[s.g];
     const double w = dt / 6.0;
     next = make_double2(rn.x + w * (ac.x + f.x), rn.y + w * (ac.y + f.y));
   }
@@ -228,11 +287,10 @@ __global__ void __launch_bounds__(AT) adj_fwd_stage_kernel(AdjArgs a, int step, 
 // part[s][b][k] = Re sum conj(g) i [e.d, y] over the k point's elements.
 // Intraband term (dy = D(y) not NULL; da = D(abar), dyb = D(ybar_next)):
 // ydirect += E D(g), part -= Re sum conj(g) D(y).
-__global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int st, const double2* y, const double2* S,
-                                                       const double2* X, const double2* abar, double coef,
-                                                       const double2* ybar_next, double cnext, const double2* dy,
-                                                       const double2* da, const double2* dyb, double2* ydirect,
-                                                       double2* sbc, double* part) {
+__device__ inline void adj_bwd_a(const AdjArgs& a, int step, int st, const double2* y, const double2* S,
+                                  const double2* X, const double2* abar, double coef, const double2* ybar_next,
+                                  double cnext, const double2* dy, const double2* da, const double2* dyb,
+                                  double2* ydirect, double2* sbc, double* part) {
   __shared__ double2 sh_y[AT], sh_h[AT], sh_g[AT], sh_d[AT], sh_sig[AT];
   __shared__ double sh_de[AT];
   const Slot s = slot_of(a);
@@ -250,7 +308,7 @@ __global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int 
       g.y += cnext * yb.y;
     }
     sh_y[t] = y[s.g];
-    sh_h[t] = ham_element(a, S, X, s, ef, de);
+    sh_h[t] = ham_element(a, S, nullptr, X, s, ef, de);
     sh_g[t] = g;
     sh_d[t] = de;
   }
@@ -313,17 +371,24 @@ __global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int 
 
 // Pullback, second half, for stage s: ybar = ydirect + scatter(conj(T + K_diag o sbc));
 // acca accumulates dL/drho_n; after the first stage abar <- acca + ybar + observable cotangent.
-__global__ void __launch_bounds__(AT) adj_bwd_b_kernel(AdjArgs a, int step, int st, const double2* ydirect,
-                                                       const double2* T, const double2* sbc, double2* ybar,
-                                                       double2* acca, double2* abar, const double* gP,
-                                                       const double* gJ, const double* gocc, int64_t gstride) {
+// Dense: T = K^T conj(sbar) is given.  Low rank (M not NULL): the block forms
+// its rows of T = M vec itself (M = V^H transposed, vec = S~^T conj(sbar)).
+__device__ inline void adj_bwd_b(const AdjArgs& a, int step, int st, const double2* ydirect, const double2* T,
+                                  const double2* M, int64_t ldm, const double2* vec, int r, const double2* sbc,
+                                  double2* ybar, double2* acca, double2* abar, const double* gP, const double* gJ,
+                                  const double* gocc, int64_t gstride) {
+  __shared__ double2 sh_t[AT];
+  if (M) {
+    block_rows_dot(a, M, ldm, vec, r, sh_t);
+    __syncthreads();
+  }
   const Slot s = slot_of(a);
   if (!s.active) return;
   double2 yb = ydirect[s.g];
   const int p = pair_of(a, s.nn, s.m);
   if (p >= 0) {
     const size_t i = (size_t)s.b * a.n + (size_t)s.k * a.npair + p;
-    double2 v = T[i];
+    double2 v = M ? sh_t[s.lk * a.npair + p] : T[i];
     if (a.kdiag) v = cadd(v, cmul(a.kdiag[(size_t)s.k * a.npair + p], sbc[i]));
     yb.x += v.x;
     yb.y -= v.y;
@@ -342,35 +407,79 @@ __global__ void __launch_bounds__(AT) adj_bwd_b_kernel(AdjArgs a, int step, int 
   }
 }
 
+__global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int st, const double2* y, const double2* S,
+                                                       const double2* X, const double2* abar, double coef,
+                                                       const double2* ybar_next, double cnext, const double2* dy,
+                                                       const double2* da, const double2* dyb, double2* ydirect,
+                                                       double2* sbc, double* part) {
+  adj_bwd_a(a, step, st, y, S, X, abar, coef, ybar_next, cnext, dy, da, dyb, ydirect, sbc, part);
+}
+
+__global__ void __launch_bounds__(AT) adj_bwd_b_kernel(AdjArgs a, int step, int st, const double2* ydirect,
+                                                       const double2* T, const double2* M, int64_t ldm,
+                                                       const double2* vec, int r, const double2* sbc, double2* ybar,
+                                                       double2* acca, double2* abar, const double* gP,
+                                                       const double* gJ, const double* gocc, int64_t gstride) {
+  adj_bwd_b(a, step, st, ydirect, T, M, ldm, vec, r, sbc, ybar, acca, abar, gP, gJ, gocc, gstride);
+}
+
+// The second half of stage st's pullback, then the first half of stage
+// st - 1's (no intraband term): both are local to a k point, and the first
+// half reads only the thread's own elements of ybar and abar, which the
+// second half has just written, so one launch does both.
+__global__ void __launch_bounds__(AT) adj_bwd_ba_kernel(AdjArgs a, int step, int st, const double2* M, int64_t ldm,
+                                                        const double2* vec, int r, const double2* T,
+                                                        const double2* sbc_in, double2* ybar, double2* acca,
+                                                        double2* abar, const double2* y, const double2* S,
+                                                        const double2* X, double coef, double cnext,
+                                                        double2* ydirect, double2* sbc_out, double* part) {
+  adj_bwd_b(a, step, st, ydirect, T, M, ldm, vec, r, sbc_in, ybar, acca, abar, nullptr, nullptr, nullptr, 0);
+  adj_bwd_a(a, step, st - 1, y, S, X, abar, coef, ybar, cnext, nullptr, nullptr, nullptr, ydirect, sbc_out, part);
+}
+
 // dL/dE at the four stage times of `step` (sum over k in fixed order) and
-// its contribution to dL/d(e0, omega, tau, t0).  One block per instance.
+// its contribution to dL/d(e0, omega, tau, t0).  One block per instance, one
+// wave per stage: each lane sums every 64th k in order (sixteen loads issued
+// together), a butterfly combines the lanes, and the four stages' terms are
+// added to dfield in stage order.
 __global__ void __launch_bounds__(256) adj_de_kernel(AdjArgs a, int step, const double* part, double* dE,
                                                      double* dfield) {
-  __shared__ double red[256];
-  const int b = blockIdx.x, t = threadIdx.x;
+  __shared__ double terms[4][4];
+  const int b = blockIdx.x, t = threadIdx.x, st = t >> 6, lane = t & 63;
   const tdg_field F = a.fields[b];
-  for (int st = 0; st < 4; ++st) {
-    double v = 0.0;
-    for (int k = t; k < a.nk; k += 256) v += part[((size_t)st * a.batch + b) * a.nk + k];
-    red[t] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (t < w) red[t] += red[t + w];
-      __syncthreads();
+  const double* ps = part + ((size_t)st * a.batch + b) * a.nk;
+  constexpr int U = 16;
+  double v = 0.0;
+  for (int k0 = lane; k0 < a.nk; k0 += 64 * U) {
+    double q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // past the last k: load k0 (in range) and use zero
+      const int k = k0 + 64 * u;
+      q[u] = ps[k < a.nk ? k : k0];
+      if (k >= a.nk) q[u] = 0.0;
     }
-    if (t == 0) {
-      const double d = red[0];
-      if (dE) dE[((size_t)b * a.nsteps + step) * 4 + st] = d;
-      const double tt = ((double)step + stage_offset(st)) * a.dt;
-      const double dd = tt - F.t0, g = exp(-dd * dd / (2.0 * F.tau * F.tau));
-      const double c = cos(F.omega * tt), sn = sin(F.omega * tt);
-      double* df = dfield + (size_t)b * 4;
-      df[0] += d * (g * c);
-      df[1] += d * (-F.e0 * g * tt * sn);
-      df[2] += d * (F.e0 * g * c * dd * dd / (F.tau * F.tau * F.tau));
-      df[3] += d * (F.e0 * g * c * dd / (F.tau * F.tau));
-    }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) v += q[u];
+  }
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) {
+    const double d = v;
+    if (dE) dE[((size_t)b * a.nsteps + step) * 4 + st] = d;
+    const double tt = ((double)step + stage_offset(st)) * a.dt;
+    const double dd = tt - F.t0, g = exp(-dd * dd / (2.0 * F.tau * F.tau));
+    const double c = cos(F.omega * tt), sn = sin(F.omega * tt);
+    terms[st][0] = d * (g * c);
+    terms[st][1] = d * (-F.e0 * g * tt * sn);
+    terms[st][2] = d * (F.e0 * g * c * dd * dd / (F.tau * F.tau * F.tau));
+    terms[st][3] = d * (F.e0 * g * c * dd / (F.tau * F.tau));
+  }
+  __syncthreads();
+  if (t < 4) {
+    double* df = dfield + (size_t)b * 4;
+    double acc = df[t];
+    for (int i = 0; i < 4; ++i) acc += terms[i][t];
+    df[t] = acc;
   }
 }
 
@@ -399,8 +508,10 @@ __global__ void __launch_bounds__(256) transpose_kernel(const double2* __restric
 
 // C[b][i] = sum_j A[i][j] B[b][j], i < m, for every instance b: A row-major
 // [m][lda] complex128, B[b] at B + b k, C[b] at C + b m.  Block (g, b): R
-// consecutive rows, the 256 threads striding over the k columns; each row's
-// sum is reduced in a fixed order (wave sums, then the four waves in order).
+// consecutive rows, the 256 threads striding over the k columns, U columns'
+// loads issued together (the products are latency bound: a few thousand
+// columns); each row's sum is reduced in a fixed order (wave sums, then the
+// four waves in order).
 template <int R>
 __global__ void __launch_bounds__(256) rowdot_kernel(const double2* __restrict__ A, int64_t lda, int64_t m, int64_t k,
                                                      const double2* __restrict__ B, double2* __restrict__ C) {
@@ -410,14 +521,29 @@ __global__ void __launch_bounds__(256) rowdot_kernel(const double2* __restrict__
   double ar[R], ai[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) ar[r] = ai[r] = 0.0;
-  for (int64_t j = t; j < k; j += 256) {
-    const double2 xv = x[j];
+  constexpr int U = R == 1 ? 8 : 2;
+  const double2 zero = make_double2(0.0, 0.0);
+  for (int64_t j0 = t; j0 < k; j0 += 256 * U) {
+    double2 xv[U], av[U][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (i0 + r < m) {
-        const double2 a = A[(i0 + r) * lda + j];
-        ar[r] += a.x * xv.x - a.y * xv.y;
-        ai[r] += a.x * xv.y + a.y * xv.x;
+    for (int u = 0; u < U; ++u) {
+      // past the last column or row: load an in-range element and use zero
+      const int64_t j = j0 + (int64_t)u * 256, jc = j < k ? j : j0;
+      xv[u] = x[jc];
+      if (j >= k) xv[u] = zero;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t i = i0 + r < m ? i0 + r : i0;
+        av[u][r] = A[i * lda + jc];
+        if (i0 + r >= m) av[u][r] = zero;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        ar[r] += av[u][r].x * xv[u].x - av[u][r].y * xv[u].y;
+        ai[r] += av[u][r].x * xv[u].y + av[u][r].y * xv[u].x;
       }
     }
   }
@@ -563,7 +689,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
                o_out = cv.take(st_b), o_acc = cv.take(st_b), o_abar = cv.take(st_b), o_ybar = cv.take(st_b),
                o_yd = cv.take(st_b), o_acca = cv.take(st_b), o_s = cv.take(xn_b * 4 * per_step),
                o_x = cv.take(xn_b * cblocks),
-               o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
+               o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(lowrank ? 0 : xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
                o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)4 * batch * nk * sizeof(double)),
                o_df = cv.take((size_t)batch * 4 * sizeof(double)), o_f = cv.take((size_t)batch * sizeof(tdg_field));
   // transposed copies, so that every product is a row-major row product: S^T
@@ -580,7 +706,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   auto P2 = [&](size_t o) { return (double2*)(wb + o); };
   double2 *CK = P2(o_ck), *SEG = P2(o_seg), *YS = P2(o_ys), *OUT = P2(o_out), *ACC = P2(o_acc), *ABAR = P2(o_abar),
           *YBAR = P2(o_ybar), *YD = P2(o_yd), *ACCA = P2(o_acca), *SS = P2(o_s), *XS = P2(o_x), *SBC = P2(o_sbc),
-          *TT = P2(o_t), *ZS = P2(o_z), *UC = P2(o_uc);
+          *TT = lowrank ? nullptr : P2(o_t), *ZS = P2(o_z), *UC = P2(o_uc);
   double2 *DY = intra ? P2(o_dy) : nullptr, *DA = intra ? P2(o_da) : nullptr, *DYB = intra ? P2(o_dyb) : nullptr;
   double2* UST = lowrank ? P2(o_ust) : nullptr;
   double2* WT = lowrank ? P2(o_wt) : nullptr;
@@ -621,18 +747,18 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   const double2* Kd = (const double2*)op->K;
   const double2* USd = (const double2*)op->us;
   const double2* Wd = (const double2*)op->w;
-  // S = K X (dense) or Z = W X, S = US Z (low rank); K, W, US row-major
+  // S = K X (dense) or Z = W X (low rank: the forward stage kernel forms
+  // S = US Z itself); K, W, US row-major
   auto apply_k = [&](const double2* X, double2* S, double2* Z) -> int {
     if (!lowrank) return prod(Kd, op->ld, n, n, X, S);
-    TDG_TRY(prod(Wd, n, rank, n, X, Z));
-    return prod(USd, rank, n, rank, Z, S);
+    return prod(Wd, n, rank, n, X, Z);
   };
-  // T with K^H sbar = conj(T) (+ K_diag term in the kernel): T = K^T conj(sbar), or
-  // Uc = US^T conj(sbar) = conj(US^H sbar), T = W^T Uc
+  // T with K^H sbar = conj(T) (+ K_diag term in the kernel): T = K^T conj(sbar),
+  // or Uc = US^T conj(sbar) = conj(US^H sbar) (low rank: the backward kernel
+  // forms T = W^T Uc itself)
   auto apply_kh = [&](const double2* Sbc, double2* Uc) -> int {
     if (!lowrank) return prod(KT, n, n, n, Sbc, TT);
-    TDG_TRY(prod(UST, n, rank, n, Sbc, Uc));
-    return prod(WT, rank, n, rank, Uc, TT);
+    return prod(UST, n, rank, n, Sbc, Uc);
   };
   auto transpose = [&](const double2* in, int64_t rows, int64_t cols, int64_t ld, double2* o) {
     hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)), dim3(256), 0,
@@ -661,16 +787,20 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     covariant_derivative(ctx->stream, model, v, (int64_t)nk * nb2, nb2, 1, dfields, batch, o);
   };
   // One forward step from rho_in to rho_out, keeping X_s, Z_s of its stages
-  // in the column block group j and y_s, S_s in stash slot js.
-  auto run_step = [&](int step, const double2* rho_in, double2* rho_out, int j, int js) -> int {
-    hipLaunchKernelGGL(adj_gather_kernel, grid, dim3(AT), 0, ctx->stream, a, rho_in, xblk(j * 4));
+  // in the column block group j and y_s, S_s in stash slot js.  gathered:
+  // X_0 of rho_in is already in block group j (the previous step's last stage
+  // wrote it); x_out (or NULL): where the last stage gathers rho_out.
+  auto run_step = [&](int step, const double2* rho_in, double2* rho_out, int j, int js, bool gathered,
+                      double2* x_out) -> int {
+    if (!gathered) hipLaunchKernelGGL(adj_gather_kernel, grid, dim3(AT), 0, ctx->stream, a, rho_in, xblk(j * 4));
     for (int s = 0; s < 4; ++s) {
       const double2* y = s == 0 ? rho_in : ys(s, js);
       TDG_TRY(apply_k(xblk(j * 4 + s), sst(s, js), lowrank ? zblk(j * 4 + s) : nullptr));
       if (intra) covd(y, DY);
       hipLaunchKernelGGL(adj_fwd_stage_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, rho_in, y, sst(s, js),
-                         xblk(j * 4 + s), (const double2*)DY, ACC, s < 3 ? ys(s + 1, js) : rho_out,
-                         s < 3 ? xblk(j * 4 + s + 1) : nullptr);
+                         xblk(j * 4 + s), lowrank ? USd : nullptr, (int64_t)rank,
+                         lowrank ? (const double2*)zblk(j * 4 + s) : nullptr, (int)rank, (const double2*)DY, ACC,
+                         s < 3 ? ys(s + 1, js) : rho_out, s < 3 ? xblk(j * 4 + s + 1) : x_out);
     }
     return launch_check(ctx, "adjoint forward step");
   };
@@ -686,11 +816,13 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   TDG_TRY(launch_check(ctx, "adjoint init"));
   for (int c = 0; c + 1 < nck; ++c) {
     // steps c M .. (c + 1) M - 1, the last landing on checkpoint c + 1; the
-    // states between alternate over SEG's first slot and OUT (both idle here)
+    // states between alternate over SEG's first slot and OUT (both idle here);
+    // each step gathers the next one's X_0 into block group 0
     const double2* rin = CK + (size_t)c * st_el;
     for (int i = 0; i < M; ++i) {
       double2* rout = (i == M - 1) ? CK + (size_t)(c + 1) * st_el : ((i & 1) ? OUT : SEG);
-      TDG_TRY(run_step(c * M + i, rin, rout, 0, 0));
+      const bool last = c + 2 == nck && i == M - 1;
+      TDG_TRY(run_step(c * M + i, rin, rout, 0, 0, c > 0 || i > 0, last ? nullptr : xblk(0)));
       rin = rout;
     }
   }
@@ -702,31 +834,48 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     auto seg = [&](int i) { return i == 0 ? CK + (size_t)c * st_el : SEG + (size_t)i * st_el; };
     if (stash) {
       // every step of the segment once, each keeping its stages in slot i
-      for (int i = 0; i < end - start; ++i)
-        TDG_TRY(run_step(start + i, seg(i), i + 1 < end - start ? seg(i + 1) : OUT, i, i));
+      for (int i = 0; i < end - start; ++i) {
+        const bool more = i + 1 < end - start;
+        TDG_TRY(run_step(start + i, seg(i), more ? seg(i + 1) : OUT, i, i, i > 0, more ? xblk((i + 1) * 4) : nullptr));
+      }
     } else {
-      for (int i = 0; i + 1 < end - start; ++i) TDG_TRY(run_step(start + i, seg(i), seg(i + 1), 0, 0));
+      for (int i = 0; i + 1 < end - start; ++i)
+        TDG_TRY(run_step(start + i, seg(i), seg(i + 1), 0, 0, false, nullptr));
     }
     for (int step = end - 1; step >= start; --step) {
       const int j = lowrank || stash ? step - start : 0;
       const int js = stash ? step - start : 0;
-      if (!stash) TDG_TRY(run_step(step, seg(step - start), OUT, j, 0));
+      if (!stash) TDG_TRY(run_step(step, seg(step - start), OUT, j, 0, false, nullptr));
       static const double coef[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
       static const double cnext[4] = {0.5, 0.5, 1.0, 0.0};
       if (intra) covd(ABAR, DA);
       for (int s = 3; s >= 0; --s) {
         const double2* y = s == 0 ? seg(step - start) : ys(s, js);
         const int cb = j * 4 + s;
-        if (intra) {
-          covd(y, DY);
-          if (s < 3) covd(YBAR, DYB);
+        // without the intraband term, stage s's first half ran in stage
+        // s + 1's last launch
+        if (s == 3 || intra) {
+          if (intra) {
+            covd(y, DY);
+            if (s < 3) covd(YBAR, DYB);
+          }
+          hipLaunchKernelGGL(adj_bwd_a_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, y, sst(s, js), xblk(cb),
+                             ABAR, coef[s] * dt, s == 3 ? (const double2*)nullptr : YBAR, cnext[s] * dt,
+                             (const double2*)DY, (const double2*)DA, (const double2*)DYB, YD, sbcblk(cb), part);
         }
-        hipLaunchKernelGGL(adj_bwd_a_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, y, sst(s, js), xblk(cb), ABAR,
-                           coef[s] * dt, s == 3 ? (const double2*)nullptr : YBAR, cnext[s] * dt, (const double2*)DY,
-                           (const double2*)DA, (const double2*)DYB, YD, sbcblk(cb), part);
         TDG_TRY(apply_kh(sbcblk(cb), lowrank ? ucblk(cb) : nullptr));
-        hipLaunchKernelGGL(adj_bwd_b_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, YD, TT, sbcblk(cb), YBAR,
-                           ACCA, ABAR, gobs->gP, gobs->gJ, gobs->gocc, gobs->stride);
+        const double2* Mt = lowrank ? (const double2*)WT : nullptr;
+        const double2* vt = lowrank ? (const double2*)ucblk(cb) : nullptr;
+        if (s > 0 && !intra)
+          hipLaunchKernelGGL(adj_bwd_ba_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, Mt, (int64_t)rank, vt,
+                             (int)rank, (const double2*)TT, (const double2*)sbcblk(cb), YBAR, ACCA, ABAR,
+                             s - 1 == 0 ? seg(step - start) : ys(s - 1, js), (const double2*)sst(s - 1, js),
+                             (const double2*)xblk(cb - 1), coef[s - 1] * dt, cnext[s - 1] * dt, YD, sbcblk(cb - 1),
+                             part);
+        else
+          hipLaunchKernelGGL(adj_bwd_b_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, YD, TT, Mt, (int64_t)rank,
+                             vt, (int)rank, sbcblk(cb), YBAR, ACCA, ABAR, gobs->gP, gobs->gJ, gobs->gocc,
+                             gobs->stride);
       }
       hipLaunchKernelGGL(adj_de_kernel, dim3(batch), dim3(256), 0, ctx->stream, a, step, part, out->dE, dfacc);
       TDG_TRY(launch_check(ctx, "adjoint backward step"));
