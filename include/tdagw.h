@@ -366,7 +366,8 @@ typedef struct {
 } tdg_grads;
 
 /* Integrates forward from rho0 (device c128 [batch][nk][nb][nb]; NULL =
- * rho_eq) keeping rho every checkpoint_every (M) steps, then pulls the loss
+ * rho_eq) keeping rho every checkpoint_every (M) steps (M = nsteps under
+ * TDG_OPT_ADJOINT_STASH 2 when the run fits; see there), then pulls the loss
  * back step by step, recomputing each segment from its checkpoint once and
  * keeping every step's stage states, products and gathers of the segment
  * (when those take at most 8 GiB; beyond that each backward step recomputes
@@ -454,10 +455,13 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
  * 0 (default) lets the tuner choose.  Other values: TDG_E_INVAL.  Results
  * differ only in summation order. */
 #define TDG_OPT_GEMM_SLICES 6
-/* tdg_propagate_adjoint: 1 (default) keeps each segment's stage data when it
+/* tdg_propagate_adjoint: 2 (default) makes one segment of the whole run when
+ * every step's stage data fits in 8 GiB (no checkpoint sweep; checkpoint_every
+ * is then unused), else acts as 1; 1 keeps each segment's stage data when it
  * fits (see there); 0 always recomputes each backward step's forward step,
- * for the smaller workspace.  Results are identical.  Other values:
- * TDG_E_INVAL. */
+ * for the smaller workspace.  0 and 1 give identical results; 2 differs from
+ * them only in the summation order of the factor gradients over segments.
+ * Other values: TDG_E_INVAL. */
 #define TDG_OPT_ADJOINT_STASH 7
 int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
 /* Name of the stage-kernel variant the last tdg_propagate used ("" before any). */

@@ -668,8 +668,6 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   if (checkpoint_every < 1) return fail(ctx, TDG_E_INVAL, "checkpoint_every must be >= 1");
   if (model->links && (int64_t)nk * nb2 * batch > ((int64_t)1 << 38))
     return fail(ctx, TDG_E_UNSUPPORTED, "intraband term: nk * nb^2 * batch too large for one launch");
-  const int M = std::min(checkpoint_every, nsteps);
-  const int nck = (nsteps + M - 1) / M;
   TDG_TRY(hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice"));
 
   // ---- workspace ---------------------------------------------------------
@@ -677,6 +675,15 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   const size_t st_b = st_el * sizeof(double2);
   const size_t xn_b = (size_t)n * batch * sizeof(double2);
   const size_t zr_b = (size_t)std::max<int64_t>(rank, 1) * batch * sizeof(double2);
+  // Whole run (stash mode 2): when every step's segment data (segment state,
+  // stage states, products, gathers, their cotangents and the factor-space
+  // columns) fits in ADJ_STASH_BYTES, one segment spans the run, so the
+  // checkpoint sweep, one of the two forward passes, is skipped.
+  int M = std::min(checkpoint_every, nsteps);
+  if (ctx->adj_stash == 2 &&
+      (double)nsteps * (4.0 * st_b + 12.0 * xn_b + (lowrank ? 8.0 * zr_b : 0.0)) <= ADJ_STASH_BYTES)
+    M = nsteps;
+  const int nck = (nsteps + M - 1) / M;
   // Stage stash: when a segment's stage states, products and gathers fit in
   // ADJ_STASH_BYTES, the segment's recompute keeps them for every step and the
   // backward steps read them; otherwise each backward step reruns its forward

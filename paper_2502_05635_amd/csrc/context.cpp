@@ -191,7 +191,7 @@ int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value) {
     return TDG_OK;
   }
   if (option == TDG_OPT_ADJOINT_STASH) {
-    if (value != 0 && value != 1) return fail(ctx, TDG_E_INVAL, "adjoint stash %lld is not 0 or 1", (long long)value);
+    if (value < 0 || value > 2) return fail(ctx, TDG_E_INVAL, "adjoint stash %lld is not 0, 1 or 2", (long long)value);
     ctx->adj_stash = (int)value;
     return TDG_OK;
   }

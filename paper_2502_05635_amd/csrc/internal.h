@@ -75,7 +75,7 @@ struct tdg_ctx_s {
   int gemm_variant = -1; // tiling of the matrix-core product: -1 tuned per shape, else 0..2 (cgemm_f32)
   bool graphs = false;   // replay captured steps or chunks (TDG_OPT_GRAPHS)
   int gemm_slices = 0;   // batched products: 0 = tuned split-K, else this many K slices (TDG_OPT_GEMM_SLICES)
-  int adj_stash = 1;     // adjoint: keep a segment's stage data when it fits (TDG_OPT_ADJOINT_STASH)
+  int adj_stash = 2;     // adjoint: keep the whole run's or a segment's stage data when it fits (TDG_OPT_ADJOINT_STASH)
   hipEvent_t order_ev = nullptr;  // tdg_set_stream: orders the new stream after the old one's queued work
   std::vector<std::pair<std::string, int>> tuned;  // shape key -> variant index
   std::string last_variant;

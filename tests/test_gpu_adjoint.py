@@ -2,6 +2,8 @@
 derivative (same inputs) and against central finite differences of the
 device's own forward propagation (GPU only)."""
 
+import contextlib
+
 import numpy as np
 import pytest
 import torch
@@ -49,26 +51,39 @@ def _weights(batch, seed):
     return [rng.standard_normal((batch, NSTEPS + 1)) for _ in range(3)]
 
 
+@contextlib.contextmanager
+def _stash(ctx, mode):
+    """TDG_OPT_ADJOINT_STASH set to mode for the block, then the default (2)."""
+    from paper_2502_05635_amd import _abi as abi
+    ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, mode)
+    try:
+        yield
+    finally:
+        ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, 2)
+
+
 def _rel(a, b):
     a, b = np.asarray(a), np.asarray(b)
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("every", [1, 7, 64])
-def test_adjoint_lowrank_matches_oracle(P, ctx, every):
+@pytest.mark.parametrize("every,stash", [(1, 1), (7, 1), (64, 1), (7, 2)])
+def test_adjoint_lowrank_matches_oracle(P, ctx, every, stash):
     """Seeded Hermitian factors (rank 12) on the 4x4 four-band model, two
-    instances, loss weights on P, J and occupation; checkpoint spacing 1,
-    7 (ragged last segment) and beyond the run length."""
+    instances, loss weights on P, J and occupation; segments of checkpoint
+    spacing 1, 7 (ragged last segment) and beyond the run length, and the
+    whole run as one segment (stash mode 2, the default)."""
     m = tb4_model(4, A, 0.5)
     dm = P.DeviceModel.from_model(m)
     n = ctx.kernel_dim(dm, "eh")
     kd, us, vh = hermitian_lowrank_factors(n, 12, 0.03, -0.01, 31)
     f = _fields()
     w = _weights(2, 32)
-    _log(f"adjoint low-rank tb4 4x4 N={n} rank 12, checkpoint every {every}")
+    _log(f"adjoint low-rank tb4 4x4 N={n} rank 12, checkpoint every {every}, stash mode {stash}")
     fac = P.LowRankFactors(torch.from_numpy(kd).cuda(), torch.from_numpy(us).cuda(), torch.from_numpy(vh).cuda(),
                            None, 12, 0.0, 0.0, "c128")
-    g = ctx.propagate_adjoint(fac, dm, "eh", f, DT, gP=w[0], gJ=w[1], gocc=w[2], checkpoint_every=every)
+    with _stash(ctx, stash):
+        g = ctx.propagate_adjoint(fac, dm, "eh", f, DT, gP=w[0], gJ=w[1], gocc=w[2], checkpoint_every=every)
     op = O.LowRankOp(kd, us, vh)
     for b in range(2):
         ref = O.propagate_adjoint(m, op, "eh", f, DT, w[0][b], w[1][b], w[2][b], instance=b)
@@ -106,9 +121,11 @@ def test_adjoint_dense_matches_oracle(P, ctx, block):
 
 @pytest.mark.parametrize("kind", ["dense", "lowrank"])
 def test_adjoint_stash_matches_recompute(P, ctx, kind):
-    """Keeping each segment's stage data (default) and rerunning every
-    backward step's forward step (TDG_OPT_ADJOINT_STASH 0) are the same
-    arithmetic: every gradient agrees bitwise, with a ragged last segment."""
+    """Keeping each segment's stage data (TDG_OPT_ADJOINT_STASH 1) and
+    rerunning every backward step's forward step (0) are the same arithmetic:
+    every gradient agrees bitwise, with a ragged last segment.  The whole run
+    as one segment (2, the default) differs only in the order in which the
+    factor gradients add up the segments' columns."""
     from paper_2502_05635_amd import _abi as abi
     m = tb4_model(4, A, 0.5)
     dm = P.DeviceModel.from_model(m)
@@ -122,18 +139,20 @@ def test_adjoint_stash_matches_recompute(P, ctx, kind):
     f = _fields()
     w = _weights(2, 34)
     out = []
-    try:
-        for stash in (1, 0):
-            ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, stash)
+    for stash in (1, 0, 2):
+        with _stash(ctx, stash):
             out.append(ctx.propagate_adjoint(op, dm, "eh", f, DT, gP=w[0], gJ=w[1], gocc=w[2], checkpoint_every=7))
-    finally:
-        ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, 1)
     for key, v in out[0].items():
         if v is None:
             continue
         assert torch.equal(v, out[1][key]), key
-    with pytest.raises(P.TdgError):
-        ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, 2)
+        if key in ("dus", "dw"):
+            assert _rel(out[2][key].cpu().numpy(), v.cpu().numpy()) <= 1e-13, key
+        else:
+            assert torch.equal(out[2][key], v), key
+    for bad in (-1, 3):
+        with pytest.raises(P.TdgError):
+            ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, bad)
 
 
 def test_adjoint_rejects_unsupported(P, ctx):
