@@ -719,8 +719,8 @@ struct BatchParams {
   int y_slices;
   int64_t y_slice_stride;
   const float2* kdiag;  // low rank: K_diag [N]; dense: NULL
-  const float2* xcur;   // drho gather of this stage, [N][ldx]
-  float2* xnext;
+  const float2* xcur;   // drho gather of this stage, [N][ldx] (read by the unpacked kernel)
+  float2* xnext;        // not written by the packed kernel when it writes the split (xexp)
   int64_t ldx;
   double2* rho_n;
   double2* rho_s;
@@ -900,6 +900,9 @@ batched_stage_kernel(BatchParams bp) {
   // the state elements (and the intraband term), K_diag o x, then the
   // product's slices for the row's pair elements, SG slices at a time, or
   // SG0 when only the first slot holds pair elements (sums in slice order).
+  // Packed, x of a pair element is formed from the element's own state (the
+  // stage state less rho_eq, rounded to FP32 as the gather was), so the
+  // gather is not read.
   // element slots per thread: a packed block at nb <= 4 has at most 3 per group
   constexpr int NS = (PACK && NBT <= 4) ? 3 : NBT;
   double2 rs[NS], r_n[NS], r_acc[NS], ds[NS], dv[NS];
@@ -942,7 +945,7 @@ batched_stage_kernel(BatchParams bp) {
     kd[m] = xk[m] = make_float2(0.f, 0.f);
     if (bp.kdiag && prow[m] >= 0) {
       kd[m] = bp.kdiag[prow[m]];
-      xk[m] = bp.xcur[(size_t)prow[m] * bp.ldx + b];
+      if (!PACK) xk[m] = bp.xcur[(size_t)prow[m] * bp.ldx + b];
     }
   }
   if (WIDE) {
@@ -984,17 +987,23 @@ batched_stage_kernel(BatchParams bp) {
   }
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
+    const int r = ee[q] / nb, c = ee[q] - r * nb;
+    if (PACK && ee[q] >= 0) rs[q] = pk_fix(rs[q], r == c, b);
     if (prow[q] >= 0) {
       float zr = yr[q], zi = yi[q];
       if (bp.kdiag) {
-        zr += kd[q].x * xk[q].x - kd[q].y * xk[q].y;
-        zi += kd[q].x * xk[q].y + kd[q].y * xk[q].x;
+        float2 x = xk[q];
+        if (PACK) {
+          // pair p of this element, or of its mirror below the diagonal (partner)
+          const float xi = (float)rs[q].y;
+          x = make_float2((float)(rs[q].x - ((r == c && r < bp.nv) ? 1.0 : 0.0)), partner[q] ? -xi : xi);
+        }
+        zr += kd[q].x * x.x - kd[q].y * x.y;
+        zi += kd[q].x * x.y + kd[q].y * x.x;
       }
       ds[q] = make_double2((double)zr, partner[q] ? -(double)zi : (double)zi);
     }
     if (ee[q] >= 0) {
-      const int r = ee[q] / nb, c = ee[q] - r * nb;
-      if (PACK) rs[q] = pk_fix(rs[q], r == c, b);
       s_rho[ee[q] * IB + i] = rs[q];
       if (PACK && c > r) s_rho[(c * nb + r) * IB + i] = make_double2(rs[q].x, -rs[q].y);
     }
@@ -1125,12 +1134,15 @@ batched_stage_kernel(BatchParams bp) {
       p = (m - bp.nv) * bp.nv + n;
       xi = -xi;
     }
+    // packed with the split operand, nothing reads the FP32 gather: the
+    // products read the split, and the next stage forms x from its state
+    const bool x32 = !PACK || !bp.xexp;
     if (p >= 0) {
-      bp.xnext[((size_t)k * P + p) * bp.ldx + b] = make_float2((float)dre, xi);
+      if (x32) bp.xnext[((size_t)k * P + p) * bp.ldx + b] = make_float2((float)dre, xi);
       if (bp.xexp) s_x[p * IB + i] = make_float2((float)dre, xi);
     }
     if (pm >= 0) {
-      bp.xnext[((size_t)k * P + pm) * bp.ldx + b] = make_float2((float)dre, -xi);
+      if (x32) bp.xnext[((size_t)k * P + pm) * bp.ldx + b] = make_float2((float)dre, -xi);
       if (bp.xexp) s_x[pm * IB + i] = make_float2((float)dre, -xi);
     }
   }
