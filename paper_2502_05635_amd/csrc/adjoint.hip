@@ -38,6 +38,10 @@
 namespace {
 
 constexpr int AT = 64;  // threads per block of the per-k kernels (a block holds 64 / nb^2 k points)
+// Threads per block of the per-k kernels that also form their rows of a
+// low-rank factor product: all of them share the product, the first AT do
+// the k-local work and the rest stay idle there.
+constexpr int ATW = 4 * AT;
 // Largest per-segment stage stash (bytes) kept instead of rerunning each
 // forward step in the backward sweep.
 constexpr double ADJ_STASH_BYTES = 8.0 * (1 << 30);
@@ -169,16 +173,16 @@ __global__ void __launch_bounds__(AT) adj_gather_kernel(AdjArgs a, const double2
 
 // The block's rows of a factor product, low rank: out[lk P + p] = sum_j
 // M[(k P + p) ldm + j] vec[b r + j] for the block's k points k = k0 + lk and
-// pairs p (kpb P <= AT rows).  tpr consecutive lanes share a row, each
-// summing every tpr-th column in order, eight columns' loads issued together;
-// the lanes' sums are then combined by a butterfly, whose partners add the
-// same two values, so every lane of the row holds the same sum.  The block is
-// one wave.
+// pairs p (kpb P <= AT rows), over all the block's threads.  tpr consecutive
+// lanes (a power of two, within one wave) share a row, each summing every
+// tpr-th column in order, eight columns' loads issued together; the lanes'
+// sums are then combined by a butterfly, whose partners add the same two
+// values, so every lane of the row holds the same sum.
 __device__ inline void block_rows_dot(const AdjArgs& a, const double2* __restrict__ M, int64_t ldm,
                                       const double2* __restrict__ vec, int r, double2* out) {
-  const int kpb = AT / (a.nb * a.nb), P = a.npair, rows = kpb * P;
+  const int kpb = AT / (a.nb * a.nb), P = a.npair, rows = kpb * P, nt = blockDim.x;
   int tpr = 1;
-  while (2 * tpr * rows <= AT) tpr *= 2;
+  while (2 * tpr * rows <= nt && 2 * tpr <= 64) tpr *= 2;
   const int t = threadIdx.x, row = t / tpr, part = t % tpr;
   const int k = blockIdx.x * kpb + row / P;
   double sr = 0.0, si = 0.0;
@@ -215,7 +219,7 @@ __device__ inline void block_rows_dot(const AdjArgs& a, const double2* __restric
 // into y_next and its gather into x_next (if not NULL).  Dense: S is K x.
 // Low rank (M not NULL): the block forms its rows of S = M vec itself (M = S~,
 // vec = z = V^H x) and stores them into S for the backward sweep.
-__global__ void __launch_bounds__(AT) adj_fwd_stage_kernel(AdjArgs a, int step, int st, const double2* rho_n,
+__global__ void __launch_bounds__(ATW) adj_fwd_stage_kernel(AdjArgs a, int step, int st, const double2* rho_n,
                                                            const double2* y, double2* S, const double2* X,
                                                            const double2* M, int64_t ldm, const double2* vec, int r,
                                                            const double2* dy, double2* acc, double2* y_next,
@@ -415,7 +419,7 @@ __global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int 
   adj_bwd_a(a, step, st, y, S, X, abar, coef, ybar_next, cnext, dy, da, dyb, ydirect, sbc, part);
 }
 
-__global__ void __launch_bounds__(AT) adj_bwd_b_kernel(AdjArgs a, int step, int st, const double2* ydirect,
+__global__ void __launch_bounds__(ATW) adj_bwd_b_kernel(AdjArgs a, int step, int st, const double2* ydirect,
                                                        const double2* T, const double2* M, int64_t ldm,
                                                        const double2* vec, int r, const double2* sbc, double2* ybar,
                                                        double2* acca, double2* abar, const double* gP,
@@ -427,7 +431,7 @@ __global__ void __launch_bounds__(AT) adj_bwd_b_kernel(AdjArgs a, int step, int 
 // st - 1's (no intraband term): both are local to a k point, and the first
 // half reads only the thread's own elements of ybar and abar, which the
 // second half has just written, so one launch does both.
-__global__ void __launch_bounds__(AT) adj_bwd_ba_kernel(AdjArgs a, int step, int st, const double2* M, int64_t ldm,
+__global__ void __launch_bounds__(ATW) adj_bwd_ba_kernel(AdjArgs a, int step, int st, const double2* M, int64_t ldm,
                                                         const double2* vec, int r, const double2* T,
                                                         const double2* sbc_in, double2* ybar, double2* acca,
                                                         double2* abar, const double2* y, const double2* S,
@@ -781,6 +785,8 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
 
   const int kpb = AT / nb2;
   const dim3 grid((unsigned)((nk + kpb - 1) / kpb), (unsigned)batch);
+  // threads of the kernels that form their rows of a factor product
+  const int pt = lowrank ? ATW : AT;
   auto xblk = [&](int cb) { return XS + (size_t)cb * n * batch; };
   auto sbcblk = [&](int cb) { return SBC + (size_t)cb * n * batch; };
   auto zblk = [&](int cb) { return ZS + (size_t)cb * rank * batch; };
@@ -804,7 +810,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
       const double2* y = s == 0 ? rho_in : ys(s, js);
       TDG_TRY(apply_k(xblk(j * 4 + s), sst(s, js), lowrank ? zblk(j * 4 + s) : nullptr));
       if (intra) covd(y, DY);
-      hipLaunchKernelGGL(adj_fwd_stage_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, rho_in, y, sst(s, js),
+      hipLaunchKernelGGL(adj_fwd_stage_kernel, grid, dim3(pt), 0, ctx->stream, a, step, s, rho_in, y, sst(s, js),
                          xblk(j * 4 + s), lowrank ? USd : nullptr, (int64_t)rank,
                          lowrank ? (const double2*)zblk(j * 4 + s) : nullptr, (int)rank, (const double2*)DY, ACC,
                          s < 3 ? ys(s + 1, js) : rho_out, s < 3 ? xblk(j * 4 + s + 1) : x_out);
@@ -874,13 +880,13 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
         const double2* Mt = lowrank ? (const double2*)WT : nullptr;
         const double2* vt = lowrank ? (const double2*)ucblk(cb) : nullptr;
         if (s > 0 && !intra)
-          hipLaunchKernelGGL(adj_bwd_ba_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, Mt, (int64_t)rank, vt,
+          hipLaunchKernelGGL(adj_bwd_ba_kernel, grid, dim3(pt), 0, ctx->stream, a, step, s, Mt, (int64_t)rank, vt,
                              (int)rank, (const double2*)TT, (const double2*)sbcblk(cb), YBAR, ACCA, ABAR,
                              s - 1 == 0 ? seg(step - start) : ys(s - 1, js), (const double2*)sst(s - 1, js),
                              (const double2*)xblk(cb - 1), coef[s - 1] * dt, cnext[s - 1] * dt, YD, sbcblk(cb - 1),
                              part);
         else
-          hipLaunchKernelGGL(adj_bwd_b_kernel, grid, dim3(AT), 0, ctx->stream, a, step, s, YD, TT, Mt, (int64_t)rank,
+          hipLaunchKernelGGL(adj_bwd_b_kernel, grid, dim3(pt), 0, ctx->stream, a, step, s, YD, TT, Mt, (int64_t)rank,
                              vt, (int)rank, sbcblk(cb), YBAR, ACCA, ABAR, gobs->gP, gobs->gJ, gobs->gocc,
                              gobs->stride);
       }
