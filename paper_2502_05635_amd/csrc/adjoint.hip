@@ -512,13 +512,14 @@ __global__ void __launch_bounds__(256) transpose_kernel(const double2* __restric
 
 // C[b][i] = sum_j A[i][j] B[b][j], i < m, for every instance b: A row-major
 // [m][lda] complex128, B[b] at B + b k, C[b] at C + b m.  Block (g, b): R
-// consecutive rows, the 256 threads striding over the k columns, U columns'
+// consecutive rows, the NT threads striding over the k columns, U columns'
 // loads issued together (the products are latency bound: a few thousand
 // columns); each row's sum is reduced in a fixed order (wave sums, then the
-// four waves in order).
-template <int R>
-__global__ void __launch_bounds__(256) rowdot_kernel(const double2* __restrict__ A, int64_t lda, int64_t m, int64_t k,
-                                                     const double2* __restrict__ B, double2* __restrict__ C) {
+// waves in order).
+template <int R, int NT>
+__global__ void __launch_bounds__(NT) rowdot_kernel(const double2* __restrict__ A, int64_t lda, int64_t m, int64_t k,
+                                                    const double2* __restrict__ B, double2* __restrict__ C) {
+  constexpr int NW = NT / 64;
   const int64_t i0 = (int64_t)blockIdx.x * R;
   const int b = blockIdx.y, t = threadIdx.x;
   const double2* x = B + (size_t)b * k;
@@ -527,12 +528,12 @@ __global__ void __launch_bounds__(256) rowdot_kernel(const double2* __restrict__
   for (int r = 0; r < R; ++r) ar[r] = ai[r] = 0.0;
   constexpr int U = R == 1 ? 8 : 2;
   const double2 zero = make_double2(0.0, 0.0);
-  for (int64_t j0 = t; j0 < k; j0 += 256 * U) {
+  for (int64_t j0 = t; j0 < k; j0 += NT * U) {
     double2 xv[U], av[U][R];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       // past the last column or row: load an in-range element and use zero
-      const int64_t j = j0 + (int64_t)u * 256, jc = j < k ? j : j0;
+      const int64_t j = j0 + (int64_t)u * NT, jc = j < k ? j : j0;
       xv[u] = x[jc];
       if (j >= k) xv[u] = zero;
 #pragma unroll
@@ -551,7 +552,7 @@ __global__ void __launch_bounds__(256) rowdot_kernel(const double2* __restrict__
       }
     }
   }
-  __shared__ double red[4][2 * R];
+  __shared__ double red[NW][2 * R];
   const int lane = t & 63, wave = t >> 6;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -567,7 +568,7 @@ __global__ void __launch_bounds__(256) rowdot_kernel(const double2* __restrict__
   __syncthreads();
   if (t < R && i0 + t < m) {
     double sr = 0.0, si = 0.0;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < NW; ++w) {
       sr += red[w][2 * t];
       si += red[w][2 * t + 1];
     }
@@ -745,14 +746,15 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
 
   // C[b] = A B[b] for every instance (A row-major [m_][lda], B[b] of k_
   // values, C[b] of m_): one fixed-order row product per row (four rows per
-  // block when there are many rows)
+  // block when there are many rows; one row over 512 threads otherwise, so
+  // that a row of a few thousand columns takes one batch of loads)
   auto prod = [&](const double2* A, int64_t lda, int64_t m_, int64_t k_, const double2* B, double2* C) -> int {
     if (m_ >= 1024)
-      hipLaunchKernelGGL(rowdot_kernel<4>, dim3((unsigned)((m_ + 3) / 4), (unsigned)batch), dim3(256), 0, ctx->stream,
-                         A, lda, m_, k_, B, C);
+      hipLaunchKernelGGL((rowdot_kernel<4, 256>), dim3((unsigned)((m_ + 3) / 4), (unsigned)batch), dim3(256), 0,
+                         ctx->stream, A, lda, m_, k_, B, C);
     else
-      hipLaunchKernelGGL(rowdot_kernel<1>, dim3((unsigned)m_, (unsigned)batch), dim3(256), 0, ctx->stream, A, lda, m_,
-                         k_, B, C);
+      hipLaunchKernelGGL((rowdot_kernel<1, 512>), dim3((unsigned)m_, (unsigned)batch), dim3(512), 0, ctx->stream, A,
+                         lda, m_, k_, B, C);
     return launch_check(ctx, "adjoint product");
   };
   const double2* Kd = (const double2*)op->K;
