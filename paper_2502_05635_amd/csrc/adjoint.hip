@@ -427,18 +427,24 @@ __global__ void __launch_bounds__(ATW) adj_bwd_b_kernel(AdjArgs a, int step, int
   adj_bwd_b(a, step, st, ydirect, T, M, ldm, vec, r, sbc, ybar, acca, abar, gP, gJ, gocc, gstride);
 }
 
-// The second half of stage st's pullback, then the first half of stage
-// st - 1's (no intraband term): both are local to a k point, and the first
-// half reads only the thread's own elements of ybar and abar, which the
-// second half has just written, so one launch does both.
+// The second half of stage st's pullback, then the first half of the stage
+// before it (no intraband term): stage st - 1 of the same step, or, after
+// stage 0, stage 3 of step - 1 (its stage data stashed).  Both halves are
+// local to a k point, and the first reads only the thread's own elements of
+// ybar and abar, which the second has just written, so one launch does both.
+// step_a, st_a, ybar_next, part: the first half's step, stage, ybar of the
+// stage after it (NULL for stage 3) and dE partials.
 __global__ void __launch_bounds__(ATW) adj_bwd_ba_kernel(AdjArgs a, int step, int st, const double2* M, int64_t ldm,
                                                         const double2* vec, int r, const double2* T,
                                                         const double2* sbc_in, double2* ybar, double2* acca,
-                                                        double2* abar, const double2* y, const double2* S,
-                                                        const double2* X, double coef, double cnext,
+                                                        double2* abar, const double* gP, const double* gJ,
+                                                        const double* gocc, int64_t gstride, int step_a, int st_a,
+                                                        const double2* y, const double2* S, const double2* X,
+                                                        double coef, const double2* ybar_next, double cnext,
                                                         double2* ydirect, double2* sbc_out, double* part) {
-  adj_bwd_b(a, step, st, ydirect, T, M, ldm, vec, r, sbc_in, ybar, acca, abar, nullptr, nullptr, nullptr, 0);
-  adj_bwd_a(a, step, st - 1, y, S, X, abar, coef, ybar, cnext, nullptr, nullptr, nullptr, ydirect, sbc_out, part);
+  adj_bwd_b(a, step, st, ydirect, T, M, ldm, vec, r, sbc_in, ybar, acca, abar, gP, gJ, gocc, gstride);
+  adj_bwd_a(a, step_a, st_a, y, S, X, abar, coef, ybar_next, cnext, nullptr, nullptr, nullptr, ydirect, sbc_out,
+            part);
 }
 
 // dL/dE at the four stage times of `step` (sum over k in fixed order) and
@@ -702,7 +708,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
                o_yd = cv.take(st_b), o_acca = cv.take(st_b), o_s = cv.take(xn_b * 4 * per_step),
                o_x = cv.take(xn_b * cblocks),
                o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(lowrank ? 0 : xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
-               o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)4 * batch * nk * sizeof(double)),
+               o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)2 * 4 * batch * nk * sizeof(double)),
                o_df = cv.take((size_t)batch * 4 * sizeof(double)), o_f = cv.take((size_t)batch * sizeof(tdg_field));
   // transposed copies, so that every product is a row-major row product: S^T
   // ([rank][n]) and V^H transposed ([n][rank]) for low rank, K^T for dense
@@ -723,7 +729,10 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   double2* UST = lowrank ? P2(o_ust) : nullptr;
   double2* WT = lowrank ? P2(o_wt) : nullptr;
   double2* KT = lowrank ? nullptr : P2(o_kt);
-  double* part = (double*)(wb + o_part);
+  // dE partials of a step, two buffers by step parity: the next step's
+  // first stage writes its own while this step's are still to be reduced
+  double* part_base = (double*)(wb + o_part);
+  auto partof = [&](int step) { return part_base + (size_t)(step & 1) * 4 * batch * nk; };
   double* dfacc = (double*)(wb + o_df);
   tdg_field* dfields = (tdg_field*)(wb + o_f);
   TDG_TRY(args_upload(ctx, dfields, fields, sizeof(tdg_field) * batch));
@@ -857,10 +866,16 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
       for (int i = 0; i + 1 < end - start; ++i)
         TDG_TRY(run_step(start + i, seg(i), seg(i + 1), 0, 0, false, nullptr));
     }
+    // a3_done: stage 3's first half of `step` ran in the previous step's last launch
+    bool a3_done = false;
     for (int step = end - 1; step >= start; --step) {
       const int j = lowrank || stash ? step - start : 0;
       const int js = stash ? step - start : 0;
       if (!stash) TDG_TRY(run_step(step, seg(step - start), OUT, j, 0, false, nullptr));
+      double* part = partof(step);
+      // stage 0's second half also does step - 1's stage 3 first half when
+      // that step's stage data is stashed
+      const bool a3_next = stash && !intra && step > start;
       static const double coef[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
       static const double cnext[4] = {0.5, 0.5, 1.0, 0.0};
       if (intra) covd(ABAR, DA);
@@ -869,7 +884,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
         const int cb = j * 4 + s;
         // without the intraband term, stage s's first half ran in stage
         // s + 1's last launch
-        if (s == 3 || intra) {
+        if ((s == 3 && !a3_done) || intra) {
           if (intra) {
             covd(y, DY);
             if (s < 3) covd(YBAR, DYB);
@@ -884,9 +899,16 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
         if (s > 0 && !intra)
           hipLaunchKernelGGL(adj_bwd_ba_kernel, grid, dim3(pt), 0, ctx->stream, a, step, s, Mt, (int64_t)rank, vt,
                              (int)rank, (const double2*)TT, (const double2*)sbcblk(cb), YBAR, ACCA, ABAR,
-                             s - 1 == 0 ? seg(step - start) : ys(s - 1, js), (const double2*)sst(s - 1, js),
-                             (const double2*)xblk(cb - 1), coef[s - 1] * dt, cnext[s - 1] * dt, YD, sbcblk(cb - 1),
-                             part);
+                             (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, (int64_t)0, step,
+                             s - 1, s - 1 == 0 ? seg(step - start) : ys(s - 1, js), (const double2*)sst(s - 1, js),
+                             (const double2*)xblk(cb - 1), coef[s - 1] * dt, (const double2*)YBAR, cnext[s - 1] * dt,
+                             YD, sbcblk(cb - 1), part);
+        else if (s == 0 && a3_next)
+          hipLaunchKernelGGL(adj_bwd_ba_kernel, grid, dim3(pt), 0, ctx->stream, a, step, 0, Mt, (int64_t)rank, vt,
+                             (int)rank, (const double2*)TT, (const double2*)sbcblk(cb), YBAR, ACCA, ABAR, gobs->gP,
+                             gobs->gJ, gobs->gocc, gobs->stride, step - 1, 3, (const double2*)ys(3, js - 1),
+                             (const double2*)sst(3, js - 1), (const double2*)xblk((j - 1) * 4 + 3), coef[3] * dt,
+                             (const double2*)nullptr, cnext[3] * dt, YD, sbcblk((j - 1) * 4 + 3), partof(step - 1));
         else
           hipLaunchKernelGGL(adj_bwd_b_kernel, grid, dim3(pt), 0, ctx->stream, a, step, s, YD, TT, Mt, (int64_t)rank,
                              vt, (int)rank, sbcblk(cb), YBAR, ACCA, ABAR, gobs->gP, gobs->gJ, gobs->gocc,
@@ -894,6 +916,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
       }
       hipLaunchKernelGGL(adj_de_kernel, dim3(batch), dim3(256), 0, ctx->stream, a, step, part, out->dE, dfacc);
       TDG_TRY(launch_check(ctx, "adjoint backward step"));
+      a3_done = a3_next;
     }
     if (lowrank && (out->dus || out->dw)) {
       // conj(dL/dS)[i][j] += sum_c Sbc_c[i] Z_c[j] and conj(dL/dV^H)[j][i] += sum_c Uc_c[j] X_c[i]
