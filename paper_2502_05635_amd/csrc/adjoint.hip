@@ -689,52 +689,93 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   // Whole run (stash mode 2): when every step's segment data (segment state,
   // stage states, products, gathers, their cotangents and the factor-space
   // columns) fits in ADJ_STASH_BYTES, one segment spans the run, so the
-  // checkpoint sweep, one of the two forward passes, is skipped.
-  int M = std::min(checkpoint_every, nsteps);
-  if (ctx->adj_stash == 2 &&
-      (double)nsteps * (4.0 * st_b + 12.0 * xn_b + (lowrank ? 8.0 * zr_b : 0.0)) <= ADJ_STASH_BYTES)
-    M = nsteps;
-  const int nck = (nsteps + M - 1) / M;
-  // Stage stash: when a segment's stage states, products and gathers fit in
-  // ADJ_STASH_BYTES, the segment's recompute keeps them for every step and the
-  // backward steps read them; otherwise each backward step reruns its forward
-  // step (one more forward pass).
-  const bool stash = ctx->adj_stash && (double)M * (3.0 * st_b + 8.0 * xn_b) <= ADJ_STASH_BYTES;
-  const int per_step = stash ? M : 1;
-  const int cblocks = (lowrank || stash ? M : 1) * 4;
-  Carver cv;
-  const size_t o_ck = cv.take(st_b * nck), o_seg = cv.take(st_b * M), o_ys = cv.take(st_b * 3 * per_step),
-               o_out = cv.take(st_b), o_acc = cv.take(st_b), o_abar = cv.take(st_b), o_ybar = cv.take(st_b),
-               o_yd = cv.take(st_b), o_acca = cv.take(st_b), o_s = cv.take(xn_b * 4 * per_step),
-               o_x = cv.take(xn_b * cblocks),
-               o_sbc = cv.take(xn_b * cblocks), o_t = cv.take(lowrank ? 0 : xn_b), o_z = cv.take(lowrank ? zr_b * cblocks : 0),
-               o_uc = cv.take(lowrank ? zr_b * cblocks : 0), o_part = cv.take((size_t)2 * 4 * batch * nk * sizeof(double)),
-               o_df = cv.take((size_t)batch * 4 * sizeof(double)), o_f = cv.take((size_t)batch * sizeof(tdg_field));
-  // transposed copies, so that every product is a row-major row product: S^T
-  // ([rank][n]) and V^H transposed ([n][rank]) for low rank, K^T for dense
-  const size_t o_ust = cv.take(lowrank ? (size_t)n * rank * sizeof(double2) : 0);
-  const size_t o_wt = cv.take(lowrank ? (size_t)n * rank * sizeof(double2) : 0);
-  const size_t o_kt = cv.take(lowrank ? 0 : (size_t)n * n * sizeof(double2));
-  // intraband term: D of a stage state, of abar and of ybar
+  // checkpoint sweep, one of the two forward passes, is skipped.  If the
+  // device cannot hold that workspace, the run falls back to checkpoint_every
+  // segments.
+  const int M0 = std::min(checkpoint_every, nsteps);
+  const bool whole = ctx->adj_stash == 2 && M0 < nsteps &&
+                     (double)nsteps * (4.0 * st_b + 12.0 * xn_b + (lowrank ? 8.0 * zr_b : 0.0)) <= ADJ_STASH_BYTES;
   const bool intra = model->links != nullptr;
-  const size_t o_dy = cv.take(intra ? st_b : 0), o_da = cv.take(intra ? st_b : 0), o_dyb = cv.take(intra ? st_b : 0);
+  // workspace layout for segments of Ms steps
+  struct Layout {
+    int M, nck, per_step, cblocks;
+    bool stash;
+    size_t o_ck, o_seg, o_ys, o_out, o_acc, o_abar, o_ybar, o_yd, o_acca, o_s, o_x, o_sbc, o_t, o_z, o_uc, o_part,
+        o_df, o_f, o_ust, o_wt, o_kt, o_dy, o_da, o_dyb, total;
+  };
+  auto layout = [&](int Ms) {
+    Layout L;
+    L.M = Ms;
+    L.nck = (nsteps + Ms - 1) / Ms;
+    // Stage stash: when a segment's stage states, products and gathers fit in
+    // ADJ_STASH_BYTES, the segment's recompute keeps them for every step and
+    // the backward steps read them; otherwise each backward step reruns its
+    // forward step (one more forward pass).
+    L.stash = ctx->adj_stash && (double)Ms * (3.0 * st_b + 8.0 * xn_b) <= ADJ_STASH_BYTES;
+    L.per_step = L.stash ? Ms : 1;
+    L.cblocks = (lowrank || L.stash ? Ms : 1) * 4;
+    Carver cv;
+    L.o_ck = cv.take(st_b * L.nck);
+    L.o_seg = cv.take(st_b * Ms);
+    L.o_ys = cv.take(st_b * 3 * L.per_step);
+    L.o_out = cv.take(st_b);
+    L.o_acc = cv.take(st_b);
+    L.o_abar = cv.take(st_b);
+    L.o_ybar = cv.take(st_b);
+    L.o_yd = cv.take(st_b);
+    L.o_acca = cv.take(st_b);
+    L.o_s = cv.take(xn_b * 4 * L.per_step);
+    L.o_x = cv.take(xn_b * L.cblocks);
+    L.o_sbc = cv.take(xn_b * L.cblocks);
+    L.o_t = cv.take(lowrank ? 0 : xn_b);
+    L.o_z = cv.take(lowrank ? zr_b * L.cblocks : 0);
+    L.o_uc = cv.take(lowrank ? zr_b * L.cblocks : 0);
+    L.o_part = cv.take((size_t)2 * 4 * batch * nk * sizeof(double));
+    L.o_df = cv.take((size_t)batch * 4 * sizeof(double));
+    L.o_f = cv.take((size_t)batch * sizeof(tdg_field));
+    // transposed copies, so that every product is a row-major row product:
+    // S^T ([rank][n]) and V^H transposed ([n][rank]) for low rank, K^T for dense
+    L.o_ust = cv.take(lowrank ? (size_t)n * rank * sizeof(double2) : 0);
+    L.o_wt = cv.take(lowrank ? (size_t)n * rank * sizeof(double2) : 0);
+    L.o_kt = cv.take(lowrank ? 0 : (size_t)n * n * sizeof(double2));
+    // intraband term: D of a stage state, of abar and of ybar
+    L.o_dy = cv.take(intra ? st_b : 0);
+    L.o_da = cv.take(intra ? st_b : 0);
+    L.o_dyb = cv.take(intra ? st_b : 0);
+    L.total = cv.off;
+    return L;
+  };
+  Layout L = layout(whole ? nsteps : M0);
   void* base = nullptr;
-  TDG_TRY(ws_reserve(ctx, WS_ADJ, cv.off, &base));
+  int rc_ws = ws_reserve(ctx, WS_ADJ, L.total, &base);
+  if (rc_ws == TDG_E_NOMEM && whole) {
+    (void)hipGetLastError();  // the failed allocation's error is not this call's
+    L = layout(M0);
+    rc_ws = ws_reserve(ctx, WS_ADJ, L.total, &base);
+  }
+  if (rc_ws != TDG_OK) return rc_ws;
+  const int M = L.M, nck = L.nck;
+  const bool stash = L.stash;
+  ctx->last_variant = std::string("adjoint: ") +
+                      (nck == 1 ? std::string("one segment")
+                                : std::to_string(nck) + " segments of " + std::to_string(M) + " steps") +
+                      (stash ? ", stage data stashed" : ", forward steps recomputed");
   char* wb = (char*)base;
   auto P2 = [&](size_t o) { return (double2*)(wb + o); };
-  double2 *CK = P2(o_ck), *SEG = P2(o_seg), *YS = P2(o_ys), *OUT = P2(o_out), *ACC = P2(o_acc), *ABAR = P2(o_abar),
-          *YBAR = P2(o_ybar), *YD = P2(o_yd), *ACCA = P2(o_acca), *SS = P2(o_s), *XS = P2(o_x), *SBC = P2(o_sbc),
-          *TT = lowrank ? nullptr : P2(o_t), *ZS = P2(o_z), *UC = P2(o_uc);
-  double2 *DY = intra ? P2(o_dy) : nullptr, *DA = intra ? P2(o_da) : nullptr, *DYB = intra ? P2(o_dyb) : nullptr;
-  double2* UST = lowrank ? P2(o_ust) : nullptr;
-  double2* WT = lowrank ? P2(o_wt) : nullptr;
-  double2* KT = lowrank ? nullptr : P2(o_kt);
+  double2 *CK = P2(L.o_ck), *SEG = P2(L.o_seg), *YS = P2(L.o_ys), *OUT = P2(L.o_out), *ACC = P2(L.o_acc),
+          *ABAR = P2(L.o_abar), *YBAR = P2(L.o_ybar), *YD = P2(L.o_yd), *ACCA = P2(L.o_acca), *SS = P2(L.o_s),
+          *XS = P2(L.o_x), *SBC = P2(L.o_sbc), *TT = lowrank ? nullptr : P2(L.o_t), *ZS = P2(L.o_z), *UC = P2(L.o_uc);
+  double2 *DY = intra ? P2(L.o_dy) : nullptr, *DA = intra ? P2(L.o_da) : nullptr,
+          *DYB = intra ? P2(L.o_dyb) : nullptr;
+  double2* UST = lowrank ? P2(L.o_ust) : nullptr;
+  double2* WT = lowrank ? P2(L.o_wt) : nullptr;
+  double2* KT = lowrank ? nullptr : P2(L.o_kt);
   // dE partials of a step, two buffers by step parity: the next step's
   // first stage writes its own while this step's are still to be reduced
-  double* part_base = (double*)(wb + o_part);
+  double* part_base = (double*)(wb + L.o_part);
   auto partof = [&](int step) { return part_base + (size_t)(step & 1) * 4 * batch * nk; };
-  double* dfacc = (double*)(wb + o_df);
-  tdg_field* dfields = (tdg_field*)(wb + o_f);
+  double* dfacc = (double*)(wb + L.o_df);
+  tdg_field* dfields = (tdg_field*)(wb + L.o_f);
   TDG_TRY(args_upload(ctx, dfields, fields, sizeof(tdg_field) * batch));
 
   AdjArgs a;

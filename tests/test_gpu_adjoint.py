@@ -155,6 +155,56 @@ def test_adjoint_stash_matches_recompute(P, ctx, kind):
             ctx.set_option(abi.TDG_OPT_ADJOINT_STASH, bad)
 
 
+def test_adjoint_whole_run_falls_back_to_segments_when_memory_is_short(P):
+    """The default stash mode keeps the whole run's stage data (3.1 GB for the
+    24x24, 3000-step workload).  With the device filled to within 1.5 GiB that
+    workspace cannot be allocated: the call runs checkpoint segments instead
+    and returns exactly the gradients of stash mode 1 (factor gradients
+    included, whose summation order differs for one segment).  With the
+    memory back it runs as one segment again."""
+    from paper_2502_05635_amd import _abi as abi
+    cfg = get_config(3)
+    dm = P.DeviceModel.from_model(cfg.model())
+    fl = cfg.fields
+    nsteps = int(fl.nsteps[0])
+    gj = np.random.default_rng(5).standard_normal((1, nsteps + 1))
+    c = P.Context(0)
+    hog = []
+    try:
+        fac = c.kernel_compress(c.kernel_build(dm, cfg.r0, "eh", "c128"), "fraction", 0.05)
+        with _stash(c, 1):
+            ref = c.propagate_adjoint(fac, dm, "eh", fl, cfg.dt, gJ=gj, checkpoint_every=50)
+        _log(f"  stash mode 1: {c.last_variant()}")
+        c.close()
+        c = P.Context(0)                               # no workspace held yet
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        # hold all but 1.5 GiB of the device, in pieces of at most 16 GiB
+        while True:
+            free, _ = torch.cuda.mem_get_info()
+            extra = free - (3 << 29)
+            if extra <= 0:
+                break
+            hog.append(torch.empty(min(extra, 16 << 30), dtype=torch.uint8, device="cuda"))
+        _log(f"  {sum(h.numel() for h in hog) / 2**30:.1f} GiB held, "
+             f"{torch.cuda.mem_get_info()[0] / 2**30:.2f} GiB left free")
+        g = c.propagate_adjoint(fac, dm, "eh", fl, cfg.dt, gJ=gj, checkpoint_every=50)
+        plan = c.last_variant()
+        hog.clear()
+        torch.cuda.empty_cache()
+        _log(f"  short of memory: {plan}")
+        assert "60 segments of 50 steps" in plan and "stashed" in plan
+        for key, v in ref.items():
+            assert torch.equal(g[key], v), key
+        c.propagate_adjoint(fac, dm, "eh", fl, cfg.dt, gJ=gj, checkpoint_every=50)
+        _log(f"  memory back: {c.last_variant()}")
+        assert "one segment" in c.last_variant()
+    finally:
+        hog.clear()
+        torch.cuda.empty_cache()
+        c.close()
+
+
 def test_adjoint_rejects_unsupported(P, ctx):
     m = tb4_model(4, A, 0.5)
     dm = P.DeviceModel.from_model(m)
