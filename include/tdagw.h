@@ -376,9 +376,9 @@ typedef struct {
  * intraband term is differentiated too (its covariant difference is
  * anti-self-adjoint).  Device workspace about (nsteps / M + 4 M + 12) states
  * plus 12 M x n x batch complex128 values (without the stash: nsteps / M +
- * M + 15 states plus 4 (M for low rank) x 2 x n x batch values), and a
- * transposed copy of the operator (n x n dense, 2 x n x rank low rank), held
- * by the context.  Synchronises the stream. */
+ * M + 15 states plus 4 (M for low rank) x 2 x n x batch values), 4 M x nk x
+ * batch doubles of dE partials, and a transposed copy of the operator (n x n
+ * dense, 2 x n x rank low rank), held by the context.  Synchronises the stream. */
 int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const tdg_model* model,
                           const tdg_field* fields, int32_t batch, double dt, const void* rho0,
                           int32_t checkpoint_every, const tdg_obs_grad* g, tdg_grads* out);

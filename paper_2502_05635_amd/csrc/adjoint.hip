@@ -447,17 +447,17 @@ __global__ void __launch_bounds__(ATW) adj_bwd_ba_kernel(AdjArgs a, int step, in
             part);
 }
 
-// dL/dE at the four stage times of `step` (sum over k in fixed order) and
-// its contribution to dL/d(e0, omega, tau, t0).  One block per instance, one
-// wave per stage: each lane sums every 64th k in order (sixteen loads issued
-// together), a butterfly combines the lanes, and the four stages' terms are
-// added to dfield in stage order.
-__global__ void __launch_bounds__(256) adj_de_kernel(AdjArgs a, int step, const double* part, double* dE,
-                                                     double* dfield) {
-  __shared__ double terms[4][4];
-  const int b = blockIdx.x, t = threadIdx.x, st = t >> 6, lane = t & 63;
+// dL/dE at the four stage times of each of a segment's steps start + i (sum
+// over k in fixed order), and each stage's contribution to dL/d(e0, omega,
+// tau, t0) into terms[i][b][stage][4].  Block (i, b), one wave per stage:
+// each lane sums every 64th k in order (sixteen loads issued together), a
+// butterfly combines the lanes.  part[i] holds step start + i's partials.
+__global__ void __launch_bounds__(256) adj_de_kernel(AdjArgs a, int start, const double* part, double* dE,
+                                                     double* terms) {
+  const int i = blockIdx.x, b = blockIdx.y, t = threadIdx.x, st = t >> 6, lane = t & 63;
+  const int step = start + i;
   const tdg_field F = a.fields[b];
-  const double* ps = part + ((size_t)st * a.batch + b) * a.nk;
+  const double* ps = part + (((size_t)i * 4 + st) * a.batch + b) * a.nk;
   constexpr int U = 16;
   double v = 0.0;
   for (int k0 = lane; k0 < a.nk; k0 += 64 * U) {
@@ -479,18 +479,25 @@ __global__ void __launch_bounds__(256) adj_de_kernel(AdjArgs a, int step, const 
     const double tt = ((double)step + stage_offset(st)) * a.dt;
     const double dd = tt - F.t0, g = exp(-dd * dd / (2.0 * F.tau * F.tau));
     const double c = cos(F.omega * tt), sn = sin(F.omega * tt);
-    terms[st][0] = d * (g * c);
-    terms[st][1] = d * (-F.e0 * g * tt * sn);
-    terms[st][2] = d * (F.e0 * g * c * dd * dd / (F.tau * F.tau * F.tau));
-    terms[st][3] = d * (F.e0 * g * c * dd / (F.tau * F.tau));
+    double* tm = terms + (((size_t)i * a.batch + b) * 4 + st) * 4;
+    tm[0] = d * (g * c);
+    tm[1] = d * (-F.e0 * g * tt * sn);
+    tm[2] = d * (F.e0 * g * c * dd * dd / (F.tau * F.tau * F.tau));
+    tm[3] = d * (F.e0 * g * c * dd / (F.tau * F.tau));
   }
-  __syncthreads();
-  if (t < 4) {
-    double* df = dfield + (size_t)b * 4;
-    double acc = df[t];
-    for (int i = 0; i < 4; ++i) acc += terms[i][t];
-    df[t] = acc;
-  }
+}
+
+// dfield[b] += the terms of a segment's count steps, the last step first and
+// the stages in order within a step (the order of the backward sweep).  One
+// thread per (instance, parameter).
+__global__ void adj_dfield_kernel(AdjArgs a, int count, const double* terms, double* dfield) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)a.batch * 4) return;
+  const int b = (int)(idx / 4), c = (int)(idx % 4);
+  double acc = dfield[idx];
+  for (int i = count - 1; i >= 0; --i)
+    for (int st = 0; st < 4; ++st) acc += terms[(((size_t)i * a.batch + b) * 4 + st) * 4 + c];
+  dfield[idx] = acc;
 }
 
 __global__ void fill_zero_kernel(double* p, int64_t count) {
@@ -694,14 +701,15 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   // segments.
   const int M0 = std::min(checkpoint_every, nsteps);
   const bool whole = ctx->adj_stash == 2 && M0 < nsteps &&
-                     (double)nsteps * (4.0 * st_b + 12.0 * xn_b + (lowrank ? 8.0 * zr_b : 0.0)) <= ADJ_STASH_BYTES;
+                     (double)nsteps * (4.0 * st_b + 12.0 * xn_b + (lowrank ? 8.0 * zr_b : 0.0) +
+                                       32.0 * batch * nk + 128.0 * batch) <= ADJ_STASH_BYTES;
   const bool intra = model->links != nullptr;
   // workspace layout for segments of Ms steps
   struct Layout {
     int M, nck, per_step, cblocks;
     bool stash;
     size_t o_ck, o_seg, o_ys, o_out, o_acc, o_abar, o_ybar, o_yd, o_acca, o_s, o_x, o_sbc, o_t, o_z, o_uc, o_part,
-        o_df, o_f, o_ust, o_wt, o_kt, o_dy, o_da, o_dyb, total;
+        o_terms, o_df, o_f, o_ust, o_wt, o_kt, o_dy, o_da, o_dyb, total;
   };
   auto layout = [&](int Ms) {
     Layout L;
@@ -730,7 +738,9 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     L.o_t = cv.take(lowrank ? 0 : xn_b);
     L.o_z = cv.take(lowrank ? zr_b * L.cblocks : 0);
     L.o_uc = cv.take(lowrank ? zr_b * L.cblocks : 0);
-    L.o_part = cv.take((size_t)2 * 4 * batch * nk * sizeof(double));
+    // dE partials of every step of a segment, and each step's dfield terms
+    L.o_part = cv.take((size_t)Ms * 4 * batch * nk * sizeof(double));
+    L.o_terms = cv.take((size_t)Ms * batch * 16 * sizeof(double));
     L.o_df = cv.take((size_t)batch * 4 * sizeof(double));
     L.o_f = cv.take((size_t)batch * sizeof(tdg_field));
     // transposed copies, so that every product is a row-major row product:
@@ -770,10 +780,12 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
   double2* UST = lowrank ? P2(L.o_ust) : nullptr;
   double2* WT = lowrank ? P2(L.o_wt) : nullptr;
   double2* KT = lowrank ? nullptr : P2(L.o_kt);
-  // dE partials of a step, two buffers by step parity: the next step's
-  // first stage writes its own while this step's are still to be reduced
+  // dE partials of a segment's steps (reduced once per segment) and their
+  // dfield terms; the step's index within its segment is set per segment
   double* part_base = (double*)(wb + L.o_part);
-  auto partof = [&](int step) { return part_base + (size_t)(step & 1) * 4 * batch * nk; };
+  double* terms = (double*)(wb + L.o_terms);
+  int seg_start = 0;
+  auto partof = [&](int step) { return part_base + (size_t)(step - seg_start) * 4 * batch * nk; };
   double* dfacc = (double*)(wb + L.o_df);
   tdg_field* dfields = (tdg_field*)(wb + L.o_f);
   TDG_TRY(args_upload(ctx, dfields, fields, sizeof(tdg_field) * batch));
@@ -909,6 +921,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     }
     // a3_done: stage 3's first half of `step` ran in the previous step's last launch
     bool a3_done = false;
+    seg_start = start;
     for (int step = end - 1; step >= start; --step) {
       const int j = lowrank || stash ? step - start : 0;
       const int js = stash ? step - start : 0;
@@ -955,10 +968,15 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
                              vt, (int)rank, sbcblk(cb), YBAR, ACCA, ABAR, gobs->gP, gobs->gJ, gobs->gocc,
                              gobs->stride);
       }
-      hipLaunchKernelGGL(adj_de_kernel, dim3(batch), dim3(256), 0, ctx->stream, a, step, part, out->dE, dfacc);
       TDG_TRY(launch_check(ctx, "adjoint backward step"));
       a3_done = a3_next;
     }
+    // dE of the segment's steps and their dfield terms, added in sweep order
+    hipLaunchKernelGGL(adj_de_kernel, dim3((unsigned)(end - start), (unsigned)batch), dim3(256), 0, ctx->stream, a,
+                       start, (const double*)part_base, out->dE, terms);
+    hipLaunchKernelGGL(adj_dfield_kernel, dim3((unsigned)((batch * 4 + 255) / 256)), dim3(256), 0, ctx->stream, a,
+                       end - start, (const double*)terms, dfacc);
+    TDG_TRY(launch_check(ctx, "adjoint dE launch"));
     if (lowrank && (out->dus || out->dw)) {
       // conj(dL/dS)[i][j] += sum_c Sbc_c[i] Z_c[j] and conj(dL/dV^H)[j][i] += sum_c Uc_c[j] X_c[i]
       // over the segment's stage columns c
