@@ -291,19 +291,40 @@ __global__ void __launch_bounds__(ATW) adj_fwd_stage_kernel(AdjArgs a, int step,
 // part[s][b][k] = Re sum conj(g) i [e.d, y] over the k point's elements.
 // Intraband term (dy = D(y) not NULL; da = D(abar), dyb = D(ybar_next)):
 // ydirect += E D(g), part -= Re sum conj(g) D(y).
-__device__ inline void adj_bwd_a(const AdjArgs& a, int step, int st, const double2* y, const double2* S,
-                                  const double2* X, const double2* abar, double coef, const double2* ybar_next,
-                                  double cnext, const double2* dy, const double2* da, const double2* dyb,
-                                  double2* ydirect, double2* sbc, double* part) {
+// The first half's inputs that nothing in the backward sweep writes while it
+// runs (stage state, H, the field term): read ahead of any other work of the
+// launch, so that their latency overlaps it.
+struct BwdAIn {
+  double ef;
+  double2 de, yv, hv;
+};
+__device__ inline BwdAIn adj_bwd_a_inputs(const AdjArgs& a, int step, int st, const double2* y, const double2* S,
+                                          const double2* X) {
+  BwdAIn in;
+  in.ef = 0.0;
+  in.de = in.yv = in.hv = make_double2(0.0, 0.0);
+  const Slot s = slot_of(a);
+  if (s.active) {
+    const tdg_field F = a.fields[s.b];
+    in.ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
+    in.de = proj_e(F, a, a.dip, s.k, s.e);
+    in.yv = y[s.g];
+    in.hv = ham_element(a, S, nullptr, X, s, in.ef, in.de);
+  }
+  return in;
+}
+
+__device__ inline void adj_bwd_a(const AdjArgs& a, int st, const BwdAIn& in, const double2* abar,
+                                  double coef, const double2* ybar_next, double cnext, const double2* dy,
+                                  const double2* da, const double2* dyb, double2* ydirect, double2* sbc,
+                                  double* part) {
   __shared__ double2 sh_y[AT], sh_h[AT], sh_g[AT], sh_d[AT], sh_sig[AT];
   __shared__ double sh_de[AT];
   const Slot s = slot_of(a);
   const int t = threadIdx.x, nb = a.nb, nb2 = nb * nb, o = s.lk * nb2;
-  double ef = 0.0;
+  const double ef = in.ef;
   if (s.active) {
-    const tdg_field F = a.fields[s.b];
-    ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
-    const double2 de = proj_e(F, a, a.dip, s.k, s.e);
+    const double2 de = in.de;
     const double2 ab = abar[s.g];
     double2 g = make_double2(coef * ab.x, coef * ab.y);
     if (ybar_next) {
@@ -311,8 +332,8 @@ __device__ inline void adj_bwd_a(const AdjArgs& a, int step, int st, const doubl
       g.x += cnext * yb.x;
       g.y += cnext * yb.y;
     }
-    sh_y[t] = y[s.g];
-    sh_h[t] = ham_element(a, S, nullptr, X, s, ef, de);
+    sh_y[t] = in.yv;
+    sh_h[t] = in.hv;
     sh_g[t] = g;
     sh_d[t] = de;
   }
@@ -416,7 +437,8 @@ __global__ void __launch_bounds__(AT) adj_bwd_a_kernel(AdjArgs a, int step, int 
                                                        const double2* ybar_next, double cnext, const double2* dy,
                                                        const double2* da, const double2* dyb, double2* ydirect,
                                                        double2* sbc, double* part) {
-  adj_bwd_a(a, step, st, y, S, X, abar, coef, ybar_next, cnext, dy, da, dyb, ydirect, sbc, part);
+  const BwdAIn in = adj_bwd_a_inputs(a, step, st, y, S, X);
+  adj_bwd_a(a, st, in, abar, coef, ybar_next, cnext, dy, da, dyb, ydirect, sbc, part);
 }
 
 __global__ void __launch_bounds__(ATW) adj_bwd_b_kernel(AdjArgs a, int step, int st, const double2* ydirect,
@@ -442,9 +464,9 @@ __global__ void __launch_bounds__(ATW) adj_bwd_ba_kernel(AdjArgs a, int step, in
                                                         const double2* y, const double2* S, const double2* X,
                                                         double coef, const double2* ybar_next, double cnext,
                                                         double2* ydirect, double2* sbc_out, double* part) {
+  const BwdAIn in = adj_bwd_a_inputs(a, step_a, st_a, y, S, X);
   adj_bwd_b(a, step, st, ydirect, T, M, ldm, vec, r, sbc_in, ybar, acca, abar, gP, gJ, gocc, gstride);
-  adj_bwd_a(a, step_a, st_a, y, S, X, abar, coef, ybar_next, cnext, nullptr, nullptr, nullptr, ydirect, sbc_out,
-            part);
+  adj_bwd_a(a, st_a, in, abar, coef, ybar_next, cnext, nullptr, nullptr, nullptr, ydirect, sbc_out, part);
 }
 
 // dL/dE at the four stage times of each of a segment's steps start + i (sum
