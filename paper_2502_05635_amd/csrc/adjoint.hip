@@ -103,25 +103,23 @@ __device__ inline double2 proj_e(const tdg_field& F, const AdjArgs& a, const dou
 }
 
 // dSigma pair value: S (from the products) plus K_diag o x for the low-rank
-// form.  S is the product for every pair [B][n], or with sl the block's own
-// rows in LDS (local k point lk: sl[lk P + p]).
-__device__ inline double2 sigma_pair(const AdjArgs& a, const double2* S, const double2* sl, const double2* X, int b,
-                                     int k, int lk, int p) {
+// form; S is [B][n].
+__device__ inline double2 sigma_pair(const AdjArgs& a, const double2* S, const double2* X, int b, int k, int p) {
   const size_t i = (size_t)b * a.n + (size_t)k * a.npair + p;
-  double2 v = sl ? sl[lk * a.npair + p] : S[i];
+  double2 v = S[i];
   if (a.kdiag) v = cadd(v, cmul(a.kdiag[(size_t)k * a.npair + p], X[i]));
   return v;
 }
 
 // Element (n, m) of H_k = diag(eps) + dSigma - E e.d (e-h block: dSigma_vc = conj(dSigma_cv)).
-__device__ inline double2 ham_element(const AdjArgs& a, const double2* S, const double2* sl, const double2* X,
-                                      const Slot& s, double ef, double2 de) {
+__device__ inline double2 ham_element(const AdjArgs& a, const double2* S, const double2* X, const Slot& s, double ef,
+                                      double2 de) {
   double2 ds = make_double2(0.0, 0.0);
   const int p = pair_of(a, s.nn, s.m);
   if (p >= 0) {
-    ds = sigma_pair(a, S, sl, X, s.b, s.k, s.lk, p);
+    ds = sigma_pair(a, S, X, s.b, s.k, p);
   } else if (a.block == TDG_BLOCK_EH && s.nn < a.nv && s.m >= a.nv) {
-    ds = cconj(sigma_pair(a, S, sl, X, s.b, s.k, s.lk, (s.m - a.nv) * a.nv + s.nn));
+    ds = cconj(sigma_pair(a, S, X, s.b, s.k, (s.m - a.nv) * a.nv + s.nn));
   }
   double2 h = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
   if (s.nn == s.m) h.x += a.eps[(size_t)s.k * a.nb + s.nn];
@@ -228,13 +226,34 @@ __global__ void __launch_bounds__(ATW) adj_fwd_stage_kernel(AdjArgs a, int step,
   const Slot s = slot_of(a);
   const int t = threadIdx.x, nb = a.nb, o = s.lk * nb * nb;
   // the slot's own inputs, read before the product so that their latency
-  // overlaps it
-  double2 yv = make_double2(0.0, 0.0), rn = yv, ac = yv, dv = yv;
+  // overlaps it: the state, and H but for the product's own term (dense: all
+  // of H; low rank: its pair, K_diag o x, the field term and the band energy,
+  // added to the product's row below in the order of ham_element)
+  const double2 zero = make_double2(0.0, 0.0);
+  double2 yv = zero, rn = zero, ac = zero, dv = zero, hv = zero, kx = zero, de = zero;
+  double ef = 0.0, eps = 0.0;
+  int hp = -1;
+  bool hcj = false;
   if (s.active) {
     yv = y[s.g];
     rn = rho_n[s.g];
     if (st > 0) ac = acc[s.g];
     if (dy) dv = dy[s.g];
+    const tdg_field F = a.fields[s.b];
+    ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
+    de = proj_e(F, a, a.dip, s.k, s.e);
+    if (!M) {
+      hv = ham_element(a, S, X, s, ef, de);
+    } else {
+      hp = pair_of(a, s.nn, s.m);
+      if (hp < 0 && a.block == TDG_BLOCK_EH && s.nn < a.nv && s.m >= a.nv) {
+        hp = (s.m - a.nv) * a.nv + s.nn;
+        hcj = true;
+      }
+      if (hp >= 0 && a.kdiag)
+        kx = cmul(a.kdiag[(size_t)s.k * a.npair + hp], X[(size_t)s.b * a.n + (size_t)s.k * a.npair + hp]);
+      if (s.nn == s.m) eps = a.eps[(size_t)s.k * a.nb + s.nn];
+    }
   }
   if (M) {
     block_rows_dot(a, M, ldm, vec, r, sh_s);
@@ -242,12 +261,19 @@ __global__ void __launch_bounds__(ATW) adj_fwd_stage_kernel(AdjArgs a, int step,
     const int kpb = AT / (nb * nb), P = a.npair, k = blockIdx.x * kpb + t / P;
     if (t < kpb * P && k < a.nk) S[(size_t)blockIdx.y * a.n + (size_t)k * P + t % P] = sh_s[t];
   }
-  double ef = 0.0;
   if (s.active) {
-    const tdg_field F = a.fields[s.b];
-    ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
     sh_y[t] = yv;
-    sh_h[t] = ham_element(a, S, M ? sh_s : nullptr, X, s, ef, proj_e(F, a, a.dip, s.k, s.e));
+    if (M) {
+      double2 ds = zero;
+      if (hp >= 0) {
+        double2 v = sh_s[s.lk * a.npair + hp];
+        if (a.kdiag) v = cadd(v, kx);
+        ds = hcj ? cconj(v) : v;
+      }
+      hv = make_double2(ds.x - ef * de.x, ds.y - ef * de.y);
+      if (s.nn == s.m) hv.x += eps;
+    }
+    sh_h[t] = hv;
   }
   __syncthreads();
   if (!s.active) return;
@@ -309,7 +335,7 @@ __device__ inline BwdAIn adj_bwd_a_inputs(const AdjArgs& a, int step, int st, co
     in.ef = field_value(F, ((double)step + stage_offset(st)) * a.dt);
     in.de = proj_e(F, a, a.dip, s.k, s.e);
     in.yv = y[s.g];
-    in.hv = ham_element(a, S, nullptr, X, s, in.ef, in.de);
+    in.hv = ham_element(a, S, X, s, in.ef, in.de);
   }
   return in;
 }
