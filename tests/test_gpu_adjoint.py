@@ -180,12 +180,17 @@ def test_adjoint_whole_run_falls_back_to_segments_when_memory_is_short(P):
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         # hold all but 1.5 GiB of the device, in pieces of at most 16 GiB
-        while True:
+        # (halved whenever one cannot be allocated)
+        chunk = 16 << 30
+        while chunk >= (64 << 20):
             free, _ = torch.cuda.mem_get_info()
             extra = free - (3 << 29)
-            if extra <= 0:
+            if extra <= (64 << 20):
                 break
-            hog.append(torch.empty(min(extra, 16 << 30), dtype=torch.uint8, device="cuda"))
+            try:
+                hog.append(torch.empty(min(extra, chunk), dtype=torch.uint8, device="cuda"))
+            except torch.cuda.OutOfMemoryError:
+                chunk //= 2
         _log(f"  {sum(h.numel() for h in hog) / 2**30:.1f} GiB held, "
              f"{torch.cuda.mem_get_info()[0] / 2**30:.2f} GiB left free")
         g = c.propagate_adjoint(fac, dm, "eh", fl, cfg.dt, gJ=gj, checkpoint_every=50)
