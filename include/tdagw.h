@@ -457,11 +457,12 @@ int tdg_profile_read(tdg_ctx ctx, int32_t kclass, double* total_ms, int64_t* lau
 #define TDG_OPT_GEMM_SLICES 6
 /* tdg_propagate_adjoint: 2 (default) makes one segment of the whole run when
  * every step's stage data fits in 8 GiB and the device can hold it (no
- * checkpoint sweep; checkpoint_every is then unused), else acts as 1; 1 keeps each segment's stage data when it
- * fits (see there); 0 always recomputes each backward step's forward step,
- * for the smaller workspace.  0 and 1 give identical results; 2 differs from
- * them only in the summation order of the factor gradients over segments.
- * Other values: TDG_E_INVAL. */
+ * checkpoint sweep; checkpoint_every is then unused), else acts as 1; 1 keeps
+ * each segment's stage data when it fits (see there); 0 always recomputes
+ * each backward step's forward step, for the smaller workspace.  0 and 1 give
+ * identical results; 2 differs from them only in the summation order of the
+ * factor gradients over segments.  tdg_last_variant names the plan a call
+ * used.  Other values: TDG_E_INVAL. */
 #define TDG_OPT_ADJOINT_STASH 7
 int tdg_set_option(tdg_ctx ctx, int32_t option, int64_t value);
 /* Name of the stage-kernel variant the last tdg_propagate used, or the
