@@ -156,7 +156,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(field instances, or blocks of k rows, would shard across GPUs).", file=sys.stderr)
         sys.exit(2)
     if args.sweep_only:

@@ -45,7 +45,7 @@ extern "C" {
 #define TDG_E_INVAL (-1)       /* bad argument: null pointer, shape, dtype, alignment */
 #define TDG_E_HIP (-2)         /* a HIP runtime call or kernel launch failed */
 #define TDG_E_NOMEM (-3)       /* workspace allocation failed */
-#define TDG_E_UNSUPPORTED (-4) /* valid request this build does not implement */
+#define TDG_E_UNSUPPORTED (-4) /* valid request the library does not implement */
 #define TDG_E_NUMERIC (-5)     /* NaN / trace / Hermiticity drift found by tdg_check_numeric */
 #define TDG_E_SOLVER (-6)      /* the eigensolver used by compression reported failure */
 
