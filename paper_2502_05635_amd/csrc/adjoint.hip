@@ -639,48 +639,97 @@ __global__ void __launch_bounds__(NT) rowdot_kernel(const double2* __restrict__ 
 
 // out[i][j] += sum_{c < cols} a[c sa + i] b[c sb + j], i < mi, j < mj (complex
 // products, not conjugated; out row-major with row stride ldo).  A block owns a
-// 32 x 32 tile of out, each thread 2 x 2 of it, with 16 of the c at a time in
-// LDS; every element is summed over c in order.
+// 64 x 64 tile of out and the columns [z cs, (z + 1) cs) of split z =
+// blockIdx.z; each thread owns 4 x 4 elements of the tile, with 16 of the c
+// at a time in LDS, and sums each element over its columns in order.  One
+// split adds into out; with several, split z stores its partial tile into
+// part[z] and outer_sum_kernel adds the splits to out in order.
 __global__ void __launch_bounds__(256) outer_acc_kernel(const double2* __restrict__ a, int64_t sa, int64_t mi,
                                                         const double2* __restrict__ b, int64_t sb, int64_t mj,
-                                                        int64_t cols, double2* __restrict__ out, int64_t ldo) {
-  __shared__ double2 as[16][32], bs[16][32];
-  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+                                                        int64_t cols, int64_t cs, double2* __restrict__ out,
+                                                        int64_t ldo, double2* __restrict__ part) {
+  __shared__ double2 as[16][64], bs[16][64];
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  const int64_t c_begin = (int64_t)blockIdx.z * cs, c_end = min(cols, c_begin + cs);
   const int t = threadIdx.x, ti = t >> 4, tj = t & 15;
-  double2 acc[2][2];
-  for (int u = 0; u < 2; ++u)
-    for (int v = 0; v < 2; ++v) acc[u][v] = make_double2(0.0, 0.0);
-  for (int64_t c0 = 0; c0 < cols; c0 += 16) {
-    for (int q = t; q < 16 * 32; q += 256) {
-      const int cc = q >> 5, e = q & 31;
+  const double2 zero = make_double2(0.0, 0.0);
+  double2 acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = zero;
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += 16) {
+    for (int q = t; q < 16 * 64; q += 256) {
+      const int cc = q >> 6, e = q & 63;
       const int64_t c = c0 + cc;
-      as[cc][e] = (c < cols && i0 + e < mi) ? a[c * sa + i0 + e] : make_double2(0.0, 0.0);
-      bs[cc][e] = (c < cols && j0 + e < mj) ? b[c * sb + j0 + e] : make_double2(0.0, 0.0);
+      as[cc][e] = (c < c_end && i0 + e < mi) ? a[c * sa + i0 + e] : zero;
+      bs[cc][e] = (c < c_end && j0 + e < mj) ? b[c * sb + j0 + e] : zero;
     }
     __syncthreads();
-    for (int cc = 0; cc < 16; ++cc)
-      for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) {
-          const double2 x = as[cc][ti + 16 * u], y = bs[cc][tj + 16 * v];
-          acc[u][v].x += x.x * y.x - x.y * y.y;
-          acc[u][v].y += x.x * y.y + x.y * y.x;
+    for (int cc = 0; cc < 16; ++cc) {
+      double2 x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = as[cc][ti + 16 * u];
+        y[u] = bs[cc][tj + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          acc[u][v].x += x[u].x * y[v].x - x[u].y * y[v].y;
+          acc[u][v].y += x[u].x * y[v].y + x[u].y * y[v].x;
         }
+    }
     __syncthreads();
   }
-  for (int u = 0; u < 2; ++u)
-    for (int v = 0; v < 2; ++v) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
       const int64_t i = i0 + ti + 16 * u, j = j0 + tj + 16 * v;
       if (i < mi && j < mj) {
-        double2& o = out[i * ldo + j];
-        o.x += acc[u][v].x;
-        o.y += acc[u][v].y;
+        if (gridDim.z == 1) {
+          double2& o = out[i * ldo + j];
+          o.x += acc[u][v].x;
+          o.y += acc[u][v].y;
+        } else {
+          part[((size_t)blockIdx.z * mi + i) * mj + j] = acc[u][v];
+        }
       }
     }
+}
+
+// out[i][j] += sum over splits z in order of part[z][i][j] (outer_acc_kernel's
+// partial tiles), one thread per element.
+__global__ void outer_sum_kernel(const double2* __restrict__ part, int splits, int64_t mi, int64_t mj, double2* out,
+                                 int64_t ldo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mi * mj) return;
+  const int64_t i = idx / mj, j = idx % mj;
+  double2 o = out[i * ldo + j];
+  for (int z = 0; z < splits; ++z) {
+    const double2 v = part[(size_t)z * mi * mj + idx];
+    o.x += v.x;
+    o.y += v.y;
+  }
+  out[i * ldo + j] = o;
 }
 
 __global__ void conj_kernel(double2* p, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i].y = -p[i].y;
+}
+
+// Column splits of a factor-gradient product out[mi][mj] over cols columns:
+// about 512 blocks of 64 x 64 tiles, each split at least 16 columns, at most
+// 64 splits; 1 when the tiles alone fill the device.
+int64_t outer_splits(int64_t mi, int64_t mj, int64_t cols) {
+  const int64_t tiles = ((mi + 63) / 64) * ((mj + 63) / 64);
+  int64_t splits = std::max<int64_t>(1, std::min<int64_t>(64, 512 / tiles));
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, cols / 16));
+  const int64_t cs = (cols + splits - 1) / splits;
+  return (cols + cs - 1) / cs;
 }
 
 // Carves 256-byte-aligned pieces out of one workspace block.
@@ -757,7 +806,7 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     int M, nck, per_step, cblocks;
     bool stash;
     size_t o_ck, o_seg, o_ys, o_out, o_acc, o_abar, o_ybar, o_yd, o_acca, o_s, o_x, o_sbc, o_t, o_z, o_uc, o_part,
-        o_terms, o_df, o_f, o_ust, o_wt, o_kt, o_dy, o_da, o_dyb, total;
+        o_terms, o_df, o_f, o_ust, o_wt, o_kt, o_dy, o_da, o_dyb, o_fg, total;
   };
   auto layout = [&](int Ms) {
     Layout L;
@@ -800,6 +849,13 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
     L.o_dy = cv.take(intra ? st_b : 0);
     L.o_da = cv.take(intra ? st_b : 0);
     L.o_dyb = cv.take(intra ? st_b : 0);
+    // partial tiles of the factor gradients when their columns are split
+    int64_t fg = 0;
+    if (lowrank && (out->dus || out->dw)) {
+      const int64_t cols = (int64_t)Ms * 4 * batch;
+      fg = std::max(outer_splits(n, rank, cols), outer_splits(rank, n, cols)) * n * rank;
+    }
+    L.o_fg = cv.take((fg > n * rank ? fg : 0) * sizeof(double2));
     L.total = cv.off;
     return L;
   };
@@ -1029,14 +1085,20 @@ extern "C" int tdg_propagate_adjoint(tdg_ctx ctx, const tdg_operator* op, const 
       // conj(dL/dS)[i][j] += sum_c Sbc_c[i] Z_c[j] and conj(dL/dV^H)[j][i] += sum_c Uc_c[j] X_c[i]
       // over the segment's stage columns c
       const int64_t cols = (int64_t)(end - start) * 4 * batch;
-      if (out->dus)
-        hipLaunchKernelGGL(outer_acc_kernel, dim3((unsigned)((rank + 31) / 32), (unsigned)((n + 31) / 32)),
-                           dim3(256), 0, ctx->stream, (const double2*)SBC, n, n, (const double2*)ZS, rank, rank, cols,
-                           (double2*)out->dus, rank);
-      if (out->dw)
-        hipLaunchKernelGGL(outer_acc_kernel, dim3((unsigned)((n + 31) / 32), (unsigned)((rank + 31) / 32)),
-                           dim3(256), 0, ctx->stream, (const double2*)UC, rank, rank, (const double2*)XS, n, n, cols,
-                           (double2*)out->dw, n);
+      double2* fgp = (double2*)(wb + L.o_fg);
+      // out[mi][mj] += sum_c a[c][i] b[c][j], its columns split over blocks when
+      // the tiles alone would leave the device idle
+      auto outer = [&](const double2* av, int64_t mi, const double2* bv, int64_t mj, double2* o) {
+        const int64_t splits = outer_splits(mi, mj, cols);
+        const int64_t cs = (cols + splits - 1) / splits;
+        hipLaunchKernelGGL(outer_acc_kernel, dim3((unsigned)((mj + 63) / 64), (unsigned)((mi + 63) / 64), (unsigned)splits),
+                           dim3(256), 0, ctx->stream, av, mi, mi, bv, mj, mj, cols, cs, o, mj, fgp);
+        if (splits > 1)
+          hipLaunchKernelGGL(outer_sum_kernel, dim3((unsigned)((mi * mj + 255) / 256)), dim3(256), 0, ctx->stream,
+                             (const double2*)fgp, (int)splits, mi, mj, o, mj);
+      };
+      if (out->dus) outer((const double2*)SBC, n, (const double2*)ZS, rank, (double2*)out->dus);
+      if (out->dw) outer((const double2*)UC, rank, (const double2*)XS, n, (double2*)out->dw);
       TDG_TRY(launch_check(ctx, "factor gradient launch"));
     }
   }
