@@ -236,7 +236,14 @@ def main():
         variant = ctx.last_variant()
         # further runs of the same K steps; the median of all runs is reported
         again = [timed(op, args.steps, args.warmup, False)[1] for _ in range(args.repeats)]
-        _, _, prof = timed(op, args.steps, args.warmup, True)
+        # per-launch kernel times: the median over three profiled runs of the
+        # same K steps, per kernel class (one run's clocks can sit apart)
+        profs = [timed(op, args.steps, args.warmup, True)[2] for _ in range(3)]
+        prof = {}
+        for cls in profs[0]:
+            cnt = profs[0][cls][1]
+            avgs = sorted(p_[cls][0] / p_[cls][1] if p_[cls][1] else 0.0 for p_ in profs)
+            prof[cls] = (avgs[1] * cnt, cnt)
         runs = [secs] + again
         out[name] = {"secs": float(np.median(runs)), "res": res, "prof": prof, "variant": variant, "runs": runs}
     ctx.set_option(abi.TDG_OPT_STAGE_VARIANT, -1)
